@@ -1,0 +1,265 @@
+"""Birkhoff-Chebyshev operators on the CGL grid, written out from their definitions.
+
+Test infrastructure only (see the package docstring).  Float64 throughout.
+
+Paper references are to arXiv 2509.01855 ("A Million-Point Fast Trajectory
+Optimization Solver"):
+
+* eq:CGLpts            CGL nodes tau_j = -cos(j pi / N), j = 0..N.
+* eq:birk-conditions   B_j^a(-1) = 0 and dB_j^a/dtau(tau_i) = delta_ij, so B_j^a is
+                       the antiderivative from -1 of the Lagrange basis l_j.
+* eq:manyDefs          [B^a]_ij = B_j^a(tau_i); w_B = Clenshaw-Curtis weights.
+* eq:Tkj=coskj         T_k(tau_j) = cos(k (N - j) pi / N).
+* eq:intChebPoly=      closed-form antiderivatives of T_k from -1.
+* App. B, eq:ak=3      modal coefficients from nodal values (discrete orthogonality).
+* Sec. "Development of a Special Birkhoff-Centric Preconditioner"
+                       last row of B^a = CC weights; the lower-triangular B~^a.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import scipy.fft
+
+__all__ = [
+    "cgl_nodes",
+    "cheb_T_at_nodes",
+    "T_matrix",
+    "T_inverse_closed_form",
+    "cheb_antiderivative_at_nodes",
+    "lagrange_basis",
+    "dense_Ba_quadrature",
+    "dense_Ba_modal",
+    "dense_Ba",
+    "weights",
+    "cc_weights_closed_form",
+    "btilde_dense",
+    "btilde_apply",
+    "ba_row",
+    "sparse_mode_exact",
+    "sparse_mode_values",
+]
+
+
+def cgl_nodes(N: int) -> np.ndarray:
+    """CGL nodes tau_j = -cos(j pi / N), j = 0..N (eq:CGLpts).
+
+    Evaluated as sin(pi (2j - N) / (2N)), the same number, so that tau_{N-j} = -tau_j
+    holds exactly in floating point and the ends are exactly -1 and +1.
+    """
+    j = np.arange(N + 1, dtype=np.float64)
+    return np.sin(np.pi * (2.0 * j - N) / (2.0 * N))
+
+
+def cheb_T_at_nodes(N: int, k: int) -> np.ndarray:
+    """T_k(tau_j) for j = 0..N via eq:Tkj=coskj, cos(pi * (k (N - j) mod 2N) / N).
+
+    The integer argument is reduced exactly before the cosine; valid for any k >= 0,
+    including k = N + 1 (evaluated directly, without the aliasing identity).
+    """
+    j = np.arange(N + 1, dtype=np.int64)
+    m = (np.int64(k) * (N - j)) % (2 * N)
+    return np.cos(np.pi * m.astype(np.float64) / N)
+
+
+def T_matrix(N: int) -> np.ndarray:
+    """Modal-to-nodal matrix of eq:V=Ta: T[j, k] = T_k(tau_j), (N+1) x (N+1)."""
+    j = np.arange(N + 1, dtype=np.int64)[:, None]
+    k = np.arange(N + 1, dtype=np.int64)[None, :]
+    m = (k * (N - j)) % (2 * N)
+    return np.cos(np.pi * m.astype(np.float64) / N)
+
+
+def T_inverse_closed_form(N: int) -> np.ndarray:
+    """Inverse of T from App. B (eq:ak=3): a_k = 2/(N c_k) sum_j e_j T_k(tau_j) v_j.
+
+    c_0 = c_N = 2, otherwise 1; e_0 = e_N = 1/2, otherwise 1 (CGL quadrature end weights).
+    """
+    T = T_matrix(N)
+    c = np.ones(N + 1)
+    c[0] = c[N] = 2.0
+    e = np.ones(N + 1)
+    e[0] = e[N] = 0.5
+    return (2.0 / N) * (T.T / c[:, None]) * e[None, :]
+
+
+def cheb_antiderivative_at_nodes(N: int, k: int) -> np.ndarray:
+    """I_k(tau_j) = integral_{-1}^{tau_j} T_k, j = 0..N, by eq:intChebPoly=.
+
+    k >= 2:  T_{k+1}/(2(k+1)) - T_{k-1}/(2(k-1)) - (-1)^k/(k^2 - 1)
+    k == 1:  T_2/4 - 1/4
+    k == 0:  T_1 + 1
+    T_{k+1} is evaluated directly at the nodes (no aliasing), so this is exact for
+    every k, including k = N.
+    """
+    if k == 0:
+        return cheb_T_at_nodes(N, 1) + 1.0
+    if k == 1:
+        return cheb_T_at_nodes(N, 2) / 4.0 - 0.25
+    sgn = 1.0 if k % 2 == 0 else -1.0
+    return (cheb_T_at_nodes(N, k + 1) / (2.0 * (k + 1))
+            - cheb_T_at_nodes(N, k - 1) / (2.0 * (k - 1))
+            - sgn / (k * k - 1.0))
+
+
+def lagrange_basis(N: int, x: np.ndarray) -> np.ndarray:
+    """Values l_j(x) of the degree-N Lagrange basis on the CGL nodes; shape (len(x), N+1).
+
+    Barycentric form with the CGL weights (-1)^j e_j (e_0 = e_N = 1/2, otherwise 1).
+    A point that coincides with a node gets the Kronecker row.
+    """
+    tau = cgl_nodes(N)
+    lam = np.ones(N + 1)
+    lam[1::2] = -1.0
+    lam[0] *= 0.5
+    lam[N] *= 0.5
+    x = np.asarray(x, dtype=np.float64)
+    diff = x[:, None] - tau[None, :]
+    hit = diff == 0.0
+    diff[hit] = 1.0
+    q = lam[None, :] / diff
+    L = q / q.sum(axis=1, keepdims=True)
+    rows = hit.any(axis=1)
+    if rows.any():
+        L[rows] = hit[rows].astype(np.float64)
+    return L
+
+
+def dense_Ba_quadrature(N: int) -> np.ndarray:
+    """Construction 1 of B^a: [B^a]_ij = integral_{-1}^{tau_i} l_j (eq:birk-conditions).
+
+    Each integral is taken by Gauss-Legendre quadrature on [-1, tau_i] with
+    N//2 + 2 points, which integrates the degree-N integrand exactly.
+    Cost O(N^3); for N up to a few hundred.
+    """
+    tau = cgl_nodes(N)
+    nq = N // 2 + 2
+    t, wq = np.polynomial.legendre.leggauss(nq)
+    B = np.zeros((N + 1, N + 1))
+    for i in range(1, N + 1):
+        half = 0.5 * (tau[i] + 1.0)
+        x = -1.0 + half * (t + 1.0)
+        L = lagrange_basis(N, x)
+        B[i] = half * (wq @ L)
+    return B
+
+
+def dense_Ba_modal(N: int) -> np.ndarray:
+    """Construction 2 of B^a: nodal -> modal (inverse of T), integrate, evaluate.
+
+    B^a = I T^{-1} with I[i, k] = integral_{-1}^{tau_i} T_k (eq:V=Ta, eq:BVt-1,
+    eq:intChebPoly=).  T^{-1} is taken from a LAPACK solve, not from the closed form,
+    so this construction does not lean on App. B.  Cost O(N^3) in BLAS/LAPACK.
+    """
+    T = T_matrix(N)
+    Int = np.empty((N + 1, N + 1))
+    for k in range(N + 1):
+        Int[:, k] = cheb_antiderivative_at_nodes(N, k)
+    Tinv = np.linalg.solve(T, np.eye(N + 1))
+    return Int @ Tinv
+
+
+def dense_Ba(N: int) -> np.ndarray:
+    """Dense B^a (construction 2; the two constructions agree to ~1e-14)."""
+    return dense_Ba_modal(N)
+
+
+def weights(N: int) -> np.ndarray:
+    """w_B: the last row of B^a, which equals the CC weights (Sec. on B~^a)."""
+    return ba_row(N, N)
+
+
+def cc_weights_closed_form(N: int) -> np.ndarray:
+    """Textbook Clenshaw-Curtis weights on the CGL nodes, independent of B^a.
+
+    w_j = integral_{-1}^{1} l_j, with l_j expanded by discrete orthogonality,
+    l_j = 2 e_j / N * sum_k T_k(tau_j) T_k / c_k, and integral_{-1}^{1} T_k =
+    2 / (1 - k^2) for even k, 0 for odd k.
+    """
+    T = T_matrix(N)
+    k = np.arange(N + 1)
+    c = np.ones(N + 1)
+    c[0] = c[N] = 2.0
+    e = np.ones(N + 1)
+    e[0] = e[N] = 0.5
+    kf = k.astype(np.float64)
+    even = k % 2 == 0
+    mom = np.zeros(N + 1)
+    mom[even] = 2.0 / (1.0 - kf[even] ** 2)
+    return (2.0 / N) * e * (T @ (mom / c))
+
+
+def btilde_dense(w: np.ndarray) -> np.ndarray:
+    """Dense B~^a: 0 above the diagonal, w_j/2 on it, w_j below it (Sec. on B~^a)."""
+    n = w.shape[0]
+    B = np.tril(np.ones((n, n)), -1) * w[None, :]
+    B[np.diag_indices(n)] = 0.5 * w
+    return B
+
+
+def btilde_apply(w: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """B~^a V along the last axis: (B~ V)_k = sum_{j<k} w_j v_j + w_k v_k / 2.
+
+    This is the row-by-row definition of B~^a with the exclusive prefix sum taken by
+    numpy's cumsum; the recursion in FastBccV reaches the same numbers.
+    """
+    wv = w * V
+    excl = np.cumsum(wv, axis=-1) - wv
+    return excl + 0.5 * wv
+
+
+def ba_row(N: int, i: int) -> np.ndarray:
+    """Row i of B^a, (B^a)_{ij} for j = 0..N, in O(N log N).
+
+    (B^a)_{ij} = sum_k I_k(tau_i) (T^{-1})_{kj} with I_k from eq:intChebPoly= and
+    T^{-1} from App. B, so (B^a)_{ij} = e_j sum_k u_k T_k(tau_j), u_k = 2 I_k(tau_i)/(N c_k).
+    The cosine sum over k is one type-I DCT (scipy), used here as a library step.
+    Lets the tests check single outputs at sizes where the dense matrix cannot exist.
+    """
+    k = np.arange(N + 1, dtype=np.int64)
+    # I_k(tau_i) for all k at one node: theta_i = (N - i) pi / N, T_m(tau_i) = cos(m theta_i)
+    def Tm(m):
+        mm = (m.astype(np.int64) * (N - i)) % (2 * N)
+        return np.cos(np.pi * mm.astype(np.float64) / N)
+    Ik = np.empty(N + 1)
+    Ik[0] = Tm(np.array([1]))[0] + 1.0
+    Ik[1] = Tm(np.array([2]))[0] / 4.0 - 0.25
+    kk = k[2:]
+    sgn = np.where(kk % 2 == 0, 1.0, -1.0)
+    Ik[2:] = (Tm(kk + 1) / (2.0 * (kk + 1)) - Tm(kk - 1) / (2.0 * (kk - 1))
+              - sgn / (kk.astype(np.float64) ** 2 - 1.0))
+    c = np.ones(N + 1)
+    c[0] = c[N] = 2.0
+    u = 2.0 * Ik / (N * c)
+    # S_m = sum_k u_k cos(pi k m / N); scipy's unnormalised DCT-I doubles interior terms
+    x = u.copy()
+    x[1:N] *= 0.5
+    S = scipy.fft.dct(x, type=1)
+    e = np.ones(N + 1)
+    e[0] = e[N] = 0.5
+    # T_k(tau_j) = cos(pi k (N - j) / N)  ->  S evaluated at m = N - j
+    return e * S[::-1]
+
+
+def sparse_mode_values(N: int, modes, alphas) -> np.ndarray:
+    """Nodal values v_j = sum_s alpha_s T_{k_s}(tau_j) of a sparse Chebyshev series."""
+    v = np.zeros(N + 1)
+    for k, a in zip(modes, alphas):
+        v += a * cheb_T_at_nodes(N, int(k))
+    return v
+
+
+def sparse_mode_exact(N: int, modes, alphas) -> np.ndarray:
+    """Exact B^a v for v = sum_s alpha_s T_{k_s} sampled at the nodes (k_s <= N).
+
+    B^a reproduces the antiderivative from -1 of any polynomial of degree <= N at the
+    nodes (its rows are integrals of the interpolant), so the exact result is
+    sum_s alpha_s integral_{-1}^{tau_j} T_{k_s}, taken from eq:intChebPoly=.
+    Cost O(len(modes) * N); usable at N = 2^20.
+    """
+    out = np.zeros(N + 1)
+    for k, a in zip(modes, alphas):
+        if not 0 <= int(k) <= N:
+            raise ValueError("mode index must lie in [0, N]")
+        out += a * cheb_antiderivative_at_nodes(N, int(k))
+    return out
