@@ -1,0 +1,181 @@
+/*
+ * birk.h -- fast Birkhoff-Chebyshev products and the Birkhoff-preconditioned Krylov
+ * solve on AMD Instinct MI355X (gfx950).  C ABI; no C++ or framework types cross it.
+ *
+ * Method: arXiv 2509.01855, "A Million-Point Fast Trajectory Optimization Solver".
+ *
+ *   CGL grid        tau_j = -cos(j pi / N), j = 0..N, N_n = N + 1 nodes   (eq:CGLpts)
+ *   B^a             [B^a]_ij = B_j^a(tau_i), B_j^a(-1) = 0, dB_j^a/dtau(tau_i) = delta_ij
+ *                   (eq:birk-conditions, eq:manyDefs)
+ *   FastBV          B^a V = Fasta2v(c^(Fastv2a(V))): DCT-I, coefficient-space
+ *                   integration recurrence with the T_{N+1} alias, inverse DCT-I
+ *                   (Sec. "An FFT Algorithm for Computing B^a V", eq:c_k=bydef,
+ *                   eq:chatk=, App. B, App. C)
+ *   FastAX          A chi = chi - B^a (J chi), J = blockdiag_k(J_k)  (eq:Achibetadef)
+ *   Preconditioner  P = I - B~^a J, B~^a lower triangular from the CC weights
+ *                   (Sec. "Development of a Special Birkhoff-Centric Preconditioner")
+ *   FastLinSol      right-preconditioned GMRES on A P^{-1} Upsilon = beta,
+ *                   chi = P^{-1} Upsilon (eq:rightPx2, FastLinSol box)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Plan.     A plan fixes a batch of independent instances i = 0..batch-1, each with its
+ *           own node count N_n[i] >= 3 and state count n_x[i] >= 1, the storage
+ *           precision, and a HIP stream.  It owns every scratch buffer (allocated at
+ *           creation); the product and preconditioner calls allocate nothing.
+ * Layout.   Component-major and contiguous: instance i, component r, node k lives at
+ *           offset(i) + r * N_n[i] + k, where offset(i) is the prefix sum of
+ *           n_x * N_n over earlier instances.  Per-node Jacobians are stored
+ *           J[r][c][k] (entry (r, c) contiguous over nodes), i.e. at
+ *           joff(i) + (r * n_x[i] + c) * N_n[i] + k with joff the prefix sum of
+ *           n_x^2 * N_n; constant Jacobians are J[r][c] at the prefix sum of n_x^2.
+ * Memory.   Every array argument is a caller-owned DEVICE pointer on the plan's device,
+ *           except where a parameter name ends in _host.  The library never frees or
+ *           retains caller memory.
+ * Types.    BIRK_F64: vectors are double.  BIRK_F32 and BIRK_F32_REFINE_F64: vectors
+ *           passed to birk_apply / birk_apply_T / birk_precond are float.  BIRK_DF32:
+ *           vectors are double-float pairs stored as two float planes, hi then lo, of
+ *           the full batch length each (value = hi + lo).  Jacobians, beta and chi are
+ *           always double.
+ * Streams.  Work is enqueued on the plan's stream in call order.  birk_apply,
+ *           birk_apply_T and birk_precond are asynchronous; birk_krylov_solve
+ *           synchronises the stream before it returns.
+ * Errors.   Functions return a birk_status.  Argument, size and precision errors are
+ *           found on the host before anything is enqueued, and leave outputs
+ *           untouched.  A plan must not be used from two host threads at once.
+ */
+#ifndef BIRK_H
+#define BIRK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BIRK_OK = 0,
+  BIRK_ERR_ARG = -1,         /* null pointer, bad enum, inconsistent arguments          */
+  BIRK_ERR_SIZE = -2,        /* batch < 1, N_n < 3, n_x < 1, or a size beyond limits    */
+  BIRK_ERR_DEVICE = -3,      /* a HIP runtime call failed                               */
+  BIRK_ERR_NOMEM = -4,       /* device allocation failed at plan creation               */
+  BIRK_ERR_SINGULAR = -5,    /* I - w_k J_k / 2 is singular at some node                */
+  BIRK_ERR_NOCONV = -6,      /* the solve hit max_iter before rtol                      */
+  BIRK_ERR_BREAKDOWN = -7,   /* Krylov breakdown without convergence                    */
+  BIRK_ERR_NONFINITE = -8,   /* NaN or Inf met in a norm during the solve               */
+  BIRK_ERR_UNSUPPORTED = -9  /* valid request this build does not implement             */
+} birk_status;
+
+typedef enum {
+  BIRK_F64 = 0,              /* everything in double                                    */
+  BIRK_F32 = 1,              /* float storage and arithmetic                            */
+  BIRK_F32_REFINE_F64 = 2,   /* float products; solve = float GMRES inside double
+                                iterative refinement on the true residual               */
+  BIRK_DF32 = 3              /* double-float (hi + lo float pairs) compensated products */
+} birk_precision;
+
+typedef enum {
+  BIRK_J_CONSTANT = 0,       /* one n_x x n_x Jacobian per instance (LTI)               */
+  BIRK_J_PER_NODE = 1        /* one n_x x n_x Jacobian per node                         */
+} birk_jac_kind;
+
+typedef struct birk_plan birk_plan;
+
+/* Create a plan.  n_nodes_host[i] = N_n of instance i (N = N_n - 1), n_x_host[i] = its
+ * state count; both host arrays of length batch, read during the call only.
+ * hip_stream is a hipStream_t (NULL = the device's null stream); the plan is bound to
+ * the device current at creation.  Allocates all scratch, the CGL weights and the
+ * transform tables (CC weights computed on the device through B^aT e_N).
+ * Errors: BIRK_ERR_ARG (out/arrays NULL, bad precision), BIRK_ERR_SIZE (batch < 1,
+ * N_n < 3, n_x < 1, N_n > 2^26 + 1, total length > 2^31), BIRK_ERR_NOMEM, BIRK_ERR_DEVICE. */
+birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_nodes_host,
+                             const int32_t* n_x_host, birk_precision prec, void* hip_stream);
+
+/* Release a plan and all memory it owns.  NULL is accepted and ignored. */
+birk_status birk_plan_destroy(birk_plan* plan);
+
+/* Total vector length sum_i n_x[i] * N_n[i] of the plan (elements, not bytes). */
+int64_t birk_plan_length(const birk_plan* plan);
+
+/* Copy the Clenshaw-Curtis weights w_B (the last row of B^a, eq:manyDefs and the
+ * B~^a section) of instance inst into w_host[0 .. N_n-1] (host memory, double).
+ * Synchronises the plan's stream.  Errors: BIRK_ERR_ARG (NULL), BIRK_ERR_SIZE (inst
+ * out of range), BIRK_ERR_DEVICE. */
+birk_status birk_weights(birk_plan* plan, int32_t inst, double* w_host);
+
+/* out = (I_{n_x} (x) B^a) v for every instance: FastBV on each component
+ * (FastBV box; Fastv2a / Fasta2v boxes; eq:c_k=bydef; eq:chatk=).
+ * v and out: device arrays of birk_plan_length elements in the plan's storage type;
+ * out must not overlap v.  Errors: BIRK_ERR_ARG (NULL or v == out). */
+birk_status birk_apply(birk_plan* plan, const void* v, void* out);
+
+/* out = (I_{n_x} (x) B^aT) g: the exact transpose of FastBV.  The paper does not give
+ * it; it is derived from the same factorisation, B^aT = (2/N) E C (S M^T S) C E^{-1}
+ * with C the DCT-I of eq:vm=DCT-1, E = diag(1/2, 1, ..., 1, 1/2), S = diag((-1)^k)
+ * and M the integration recurrence.  Same arguments and errors as birk_apply. */
+birk_status birk_apply_T(birk_plan* plan, const void* g, void* out);
+
+/* Birkhoff preconditioner P = I - (I (x) B~^a) J (B~^a section).
+ * inverse = 0: out = P y  (FastBccV applied to J y; an exclusive prefix sum).
+ * inverse = 1: out = P^{-1} y by exact block forward substitution,
+ *              xi_k = (I - w_k J_k/2)^{-1} (y_k + S_k), S_{k+1} = S_k + w_k J_k xi_k
+ *              (FastPinvY box; its printed running-sum update is read as exact
+ *              forward substitution), evaluated as a parallel scan of affine maps.
+ * J: device, double, laid out per jac_kind (see Layout).  y, out: plan storage type
+ * (BIRK_DF32 plans: not supported, BIRK_ERR_UNSUPPORTED).  out must not overlap y.
+ * Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED (n_x > 12 or BIRK_DF32).  A singular
+ * pivot is not reported by this call (it yields non-finite values); birk_krylov_solve
+ * checks pivots and returns BIRK_ERR_SINGULAR. */
+birk_status birk_precond(birk_plan* plan, birk_jac_kind jac_kind, const double* J,
+                         const void* y, void* out, int32_t inverse);
+
+/* out = A x = x - (I (x) B^a)(J x)  (FastAX box, eq:Achibetadef), double in and out
+ * regardless of the plan precision (the product runs in double).  Errors as above. */
+birk_status birk_fast_ax(birk_plan* plan, birk_jac_kind jac_kind, const double* J,
+                         const double* x, double* out);
+
+typedef struct {
+  int32_t method;       /* 0 = GMRES; 1 = MINRES (reserved: BIRK_ERR_UNSUPPORTED)     */
+  int32_t restart;      /* GMRES restart length m, 1..128 (default 30)                */
+  int32_t max_iter;     /* total inner iterations allowed (default 300)               */
+  double rtol;          /* target ||beta - A chi||_2 / ||beta||_2, true residual in
+                           double (default 1e-10)                                     */
+  int32_t use_precond;  /* 1 = right-precondition with P (default), 0 = none          */
+  int32_t use_x0;       /* 1 = start from chi as passed in, 0 = start from zero       */
+  int32_t max_refine;   /* BIRK_F32_REFINE_F64: outer refinement steps (default 8)    */
+  double inner_rtol;    /* BIRK_F32_REFINE_F64: inner float GMRES tolerance (1e-5)    */
+} birk_solve_opts;
+
+/* Fill opts with the defaults listed above. */
+void birk_solve_opts_default(birk_solve_opts* opts);
+
+typedef struct {
+  int32_t* status;          /* per instance birk_status (host array [batch]) or NULL   */
+  int32_t* inner_iters;     /* per instance Krylov iterations, or NULL                 */
+  int32_t* outer_iters;     /* per instance refinement steps (1 for plain), or NULL    */
+  double* rel_resid_fp64;   /* per instance final ||beta - A chi|| / ||beta||, or NULL */
+} birk_solve_info;
+
+/* Solve [I - (I (x) B^a) J] chi = beta for every instance (eq:Newton-ivp) by
+ * right-preconditioned, matrix-free GMRES (FastLinSol box), stopping on the true
+ * relative residual in double.  BIRK_F64 plans run the Krylov process in double;
+ * BIRK_F32_REFINE_F64 plans run float GMRES on A d = r inside double refinement
+ * chi += d, r = beta - A chi.  beta, chi: device, double, birk_plan_length elements;
+ * chi holds x0 on entry when opts->use_x0, and the best iterate on return, also when
+ * the status is an error.  opts may be NULL (defaults); info may be NULL.
+ * Returns BIRK_OK when every instance converged, else the first failing instance's
+ * status.  Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED (MINRES, BIRK_F32 or BIRK_DF32
+ * plans, n_x > 12), BIRK_ERR_SINGULAR, BIRK_ERR_NOCONV, BIRK_ERR_BREAKDOWN,
+ * BIRK_ERR_NONFINITE, BIRK_ERR_DEVICE. */
+birk_status birk_krylov_solve(birk_plan* plan, birk_jac_kind jac_kind, const double* J,
+                              const double* beta, double* chi, const birk_solve_opts* opts,
+                              birk_solve_info* info);
+
+/* Static, NUL-terminated description of a status code (never NULL). */
+const char* birk_status_string(birk_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BIRK_H */

@@ -1,0 +1,212 @@
+"""Python binding of libbirk (the C ABI declared in include/birk.h).
+
+Argument marshalling only: every computation runs in the HIP library.  The functions
+keep the C names (birk_plan_create, birk_apply, ...).  Vectors are torch tensors on the
+plan's GPU (contiguous, in the plan's storage dtype); PyTorch supplies device memory and
+the stream, nothing else.  If the shared library has not been built, importing this
+module raises ImportError: there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbirk.so")
+
+BIRK_OK = 0
+BIRK_ERR_ARG = -1
+BIRK_ERR_SIZE = -2
+BIRK_ERR_DEVICE = -3
+BIRK_ERR_NOMEM = -4
+BIRK_ERR_SINGULAR = -5
+BIRK_ERR_NOCONV = -6
+BIRK_ERR_BREAKDOWN = -7
+BIRK_ERR_NONFINITE = -8
+BIRK_ERR_UNSUPPORTED = -9
+
+BIRK_F64 = 0
+BIRK_F32 = 1
+BIRK_F32_REFINE_F64 = 2
+BIRK_DF32 = 3
+
+BIRK_J_CONSTANT = 0
+BIRK_J_PER_NODE = 1
+
+EXPORTED = [
+    "birk_plan_create", "birk_plan_destroy", "birk_plan_length", "birk_weights",
+    "birk_apply", "birk_apply_T", "birk_precond", "birk_fast_ax",
+    "birk_solve_opts_default", "birk_krylov_solve", "birk_status_string",
+]
+
+
+class birk_solve_opts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("use_precond", ctypes.c_int32), ("use_x0", ctypes.c_int32),
+                ("max_refine", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
+
+
+class birk_solve_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.POINTER(ctypes.c_int32)),
+                ("inner_iters", ctypes.POINTER(ctypes.c_int32)),
+                ("outer_iters", ctypes.POINTER(ctypes.c_int32)),
+                ("rel_resid_fp64", ctypes.POINTER(ctypes.c_double))]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2509_01855_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.birk_plan_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i64), ctypes.POINTER(i32), i32, vp]
+    lib.birk_plan_destroy.argtypes = [vp]
+    lib.birk_plan_length.argtypes = [vp]
+    lib.birk_plan_length.restype = i64
+    lib.birk_weights.argtypes = [vp, i32, ctypes.POINTER(dbl)]
+    lib.birk_apply.argtypes = [vp, vp, vp]
+    lib.birk_apply_T.argtypes = [vp, vp, vp]
+    lib.birk_precond.argtypes = [vp, i32, vp, vp, vp, i32]
+    lib.birk_fast_ax.argtypes = [vp, i32, vp, vp, vp]
+    lib.birk_solve_opts_default.argtypes = [ctypes.POINTER(birk_solve_opts)]
+    lib.birk_solve_opts_default.restype = None
+    lib.birk_krylov_solve.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(birk_solve_opts),
+                                      ctypes.POINTER(birk_solve_info)]
+    lib.birk_status_string.argtypes = [i32]
+    lib.birk_status_string.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("birk_plan_length", "birk_solve_opts_default", "birk_status_string"):
+            getattr(lib, name).restype = i32
+    return lib
+
+
+_lib = _load()
+
+
+class BirkError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = int(status)
+        super().__init__(f"{where}: {birk_status_string(status)}")
+
+
+def birk_status_string(status: int) -> str:
+    return _lib.birk_status_string(int(status)).decode()
+
+
+def _check(st: int, where: str) -> None:
+    if st != BIRK_OK:
+        raise BirkError(st, where)
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+@dataclass
+class Plan:
+    """Owning handle of a birk_plan."""
+    handle: int
+    n_nodes: tuple
+    n_x: tuple
+    prec: int
+
+    @property
+    def length(self) -> int:
+        return int(_lib.birk_plan_length(self.handle))
+
+    def destroy(self) -> None:
+        if self.handle:
+            _lib.birk_plan_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def birk_plan_create(n_nodes, n_x, prec: int = BIRK_F64, stream=None) -> Plan:
+    n_nodes = [int(v) for v in n_nodes]
+    n_x = [int(v) for v in n_x]
+    if len(n_nodes) != len(n_x):
+        raise ValueError("n_nodes and n_x must have the same length")
+    b = len(n_nodes)
+    nn = (ctypes.c_int64 * max(b, 1))(*n_nodes)
+    nx = (ctypes.c_int32 * max(b, 1))(*n_x)
+    h = ctypes.c_void_p()
+    st = _lib.birk_plan_create(ctypes.byref(h), b, nn, nx, int(prec), _stream_handle(stream))
+    _check(st, "birk_plan_create")
+    return Plan(h.value, tuple(n_nodes), tuple(n_x), int(prec))
+
+
+def birk_plan_destroy(plan: Plan) -> None:
+    plan.destroy()
+
+
+def birk_plan_length(plan: Plan) -> int:
+    return plan.length
+
+
+def birk_weights(plan: Plan, inst: int = 0):
+    import numpy as np
+    w = np.empty(plan.n_nodes[inst], dtype=np.float64)
+    _check(_lib.birk_weights(plan.handle, int(inst), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "birk_weights")
+    return w
+
+
+def birk_apply(plan: Plan, v, out) -> None:
+    _check(_lib.birk_apply(plan.handle, _ptr(v), _ptr(out)), "birk_apply")
+
+
+def birk_apply_T(plan: Plan, g, out) -> None:
+    _check(_lib.birk_apply_T(plan.handle, _ptr(g), _ptr(out)), "birk_apply_T")
+
+
+def birk_precond(plan: Plan, J, y, out, inverse: bool, jac_kind: int = BIRK_J_PER_NODE) -> None:
+    _check(_lib.birk_precond(plan.handle, int(jac_kind), _ptr(J), _ptr(y), _ptr(out), int(bool(inverse))),
+           "birk_precond")
+
+
+def birk_fast_ax(plan: Plan, J, x, out, jac_kind: int = BIRK_J_PER_NODE) -> None:
+    _check(_lib.birk_fast_ax(plan.handle, int(jac_kind), _ptr(J), _ptr(x), _ptr(out)), "birk_fast_ax")
+
+
+def birk_solve_opts_default() -> birk_solve_opts:
+    o = birk_solve_opts()
+    _lib.birk_solve_opts_default(ctypes.byref(o))
+    return o
+
+
+def birk_krylov_solve(plan: Plan, J, beta, chi, jac_kind: int = BIRK_J_PER_NODE, raise_on_error: bool = True,
+                      **opts):
+    """Solve [I - B^a J] chi = beta; returns a dict with per-instance status, iteration counts
+    and final double-precision relative residuals."""
+    o = birk_solve_opts_default()
+    for k, v in opts.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown solve option {k}")
+        setattr(o, k, v)
+    b = len(plan.n_nodes)
+    stv = (ctypes.c_int32 * b)()
+    inner = (ctypes.c_int32 * b)()
+    outer = (ctypes.c_int32 * b)()
+    res = (ctypes.c_double * b)()
+    info = birk_solve_info(stv, inner, outer, res)
+    st = _lib.birk_krylov_solve(plan.handle, int(jac_kind), _ptr(J), _ptr(beta), _ptr(chi), ctypes.byref(o),
+                                ctypes.byref(info))
+    out = {"status": int(st), "inst_status": list(stv), "inner_iters": list(inner),
+           "outer_iters": list(outer), "rel_resid": list(res)}
+    if raise_on_error and st != BIRK_OK:
+        raise BirkError(st, "birk_krylov_solve")
+    return out

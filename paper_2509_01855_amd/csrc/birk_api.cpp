@@ -1,0 +1,611 @@
+// C-ABI entry points of libbirk: plan management, products, preconditioner, FastAX and
+// the right-preconditioned GMRES solve with double-precision iterative refinement.
+//
+// Solve (arXiv 2509.01855, eq:Newton-ivp, eq:rightPx2, Algorithm 2, FastLinSol box):
+// every outer step forms the true residual r = beta - A chi in double (FastAX in
+// double), stops when ||r|| <= rtol ||beta|| per instance, and otherwise runs one
+// right-preconditioned GMRES cycle on A d = r / ||r|| in the Krylov precision
+// (double for BIRK_F64 plans, float for BIRK_F32_REFINE_F64 plans), then chi += ||r|| d.
+// With a double Krylov precision this is restarted GMRES whose restarts use the true
+// residual; with float it is mixed-precision iterative refinement.  The Arnoldi
+// process uses classical Gram-Schmidt with one re-orthogonalisation (CGS2); dot
+// products and norms accumulate in double; the Hessenberg least-squares problem is
+// solved with Givens rotations on the host, one small device-to-host copy per
+// iteration.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "birk_internal.h"
+
+using namespace birk;
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+inline bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+inline int ilog2(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+
+constexpr int64_t kMaxN = int64_t(1) << 22;       // any N
+constexpr int64_t kMaxNPow2 = int64_t(1) << 23;   // N a power of two
+constexpr int64_t kMaxTotal = int64_t(1) << 31;
+constexpr int kMaxPrecondNx = 12;
+
+void free_plan(birk_plan* p) {
+  if (!p) return;
+  for (auto& in : p->inst) {
+    for (int pi = 0; pi < 2; ++pi) {
+      if (in.tab[pi].chirp) (void)hipFree(in.tab[pi].chirp);
+      if (in.tab[pi].filt) (void)hipFree(in.tab[pi].filt);
+      if (in.tab[pi].tw4_hi) (void)hipFree(in.tab[pi].tw4_hi);
+      if (in.tab[pi].tw4_lo) (void)hipFree(in.tab[pi].tw4_lo);
+    }
+    if (in.w) (void)hipFree(in.w);
+  }
+  for (void* q : p->work) if (q) (void)hipFree(q);
+  for (void* q : p->tmp_vec) if (q) (void)hipFree(q);
+  for (void* q : p->lds_tw) if (q) (void)hipFree(q);
+  if (p->partials) (void)hipFree(p->partials);
+  if (p->scan) (void)hipFree(p->scan);
+  if (p->krylov_Q) (void)hipFree(p->krylov_Q);
+  if (p->krylov_vec) (void)hipFree(p->krylov_vec);
+  if (p->krylov_dots) (void)hipFree(p->krylov_dots);
+  if (p->krylov_part) (void)hipFree(p->krylov_part);
+  if (p->flag) (void)hipFree(p->flag);
+  delete p;
+}
+
+birk_status dev_err(hipError_t e) { return e == hipErrorOutOfMemory ? BIRK_ERR_NOMEM : BIRK_ERR_DEVICE; }
+
+__global__ void k_extract_weights(const double* __restrict__ v, double* __restrict__ w, int64_t Nn) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < Nn) w[k] = v[k];
+}
+
+__global__ void k_set_unit(double* __restrict__ v, int64_t idx) { v[idx] = 1.0; }
+
+}  // namespace
+
+extern "C" {
+
+const char* birk_status_string(birk_status s) {
+  switch (s) {
+    case BIRK_OK: return "BIRK_OK: success";
+    case BIRK_ERR_ARG: return "BIRK_ERR_ARG: invalid argument (null pointer, bad enum or overlap)";
+    case BIRK_ERR_SIZE: return "BIRK_ERR_SIZE: size out of range (batch < 1, N_n < 3, n_x < 1 or too large)";
+    case BIRK_ERR_DEVICE: return "BIRK_ERR_DEVICE: a HIP runtime call failed";
+    case BIRK_ERR_NOMEM: return "BIRK_ERR_NOMEM: device allocation failed";
+    case BIRK_ERR_SINGULAR: return "BIRK_ERR_SINGULAR: I - w_k J_k / 2 is singular at some node";
+    case BIRK_ERR_NOCONV: return "BIRK_ERR_NOCONV: iteration limit reached before the tolerance";
+    case BIRK_ERR_BREAKDOWN: return "BIRK_ERR_BREAKDOWN: Krylov breakdown without convergence";
+    case BIRK_ERR_NONFINITE: return "BIRK_ERR_NONFINITE: NaN or Inf met during the solve";
+    case BIRK_ERR_UNSUPPORTED: return "BIRK_ERR_UNSUPPORTED: request not implemented by this build";
+  }
+  return "unknown birk_status";
+}
+
+void birk_solve_opts_default(birk_solve_opts* o) {
+  if (!o) return;
+  o->method = 0;
+  o->restart = 30;
+  o->max_iter = 300;
+  o->rtol = 1e-10;
+  o->use_precond = 1;
+  o->use_x0 = 0;
+  o->max_refine = 8;
+  o->inner_rtol = 1e-5;
+}
+
+int64_t birk_plan_length(const birk_plan* p) { return p ? p->total_len : 0; }
+
+birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_nodes_host,
+                             const int32_t* n_x_host, birk_precision prec, void* hip_stream) {
+  if (!out) return BIRK_ERR_ARG;
+  *out = nullptr;
+  if (!n_nodes_host || !n_x_host) return BIRK_ERR_ARG;
+  if (prec != BIRK_F64 && prec != BIRK_F32 && prec != BIRK_F32_REFINE_F64 && prec != BIRK_DF32)
+    return BIRK_ERR_ARG;
+  if (batch < 1) return BIRK_ERR_SIZE;
+  int64_t total = 0;
+  for (int i = 0; i < batch; ++i) {
+    const int64_t Nn = n_nodes_host[i];
+    const int nx = n_x_host[i];
+    if (Nn < 3 || nx < 1) return BIRK_ERR_SIZE;
+    const int64_t N = Nn - 1;
+    if (N > (is_pow2(N) ? kMaxNPow2 : kMaxN)) return BIRK_ERR_SIZE;
+    total += Nn * nx;
+    if (total > kMaxTotal) return BIRK_ERR_SIZE;
+  }
+  birk_plan* p = new (std::nothrow) birk_plan();
+  if (!p) return BIRK_ERR_NOMEM;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return BIRK_ERR_DEVICE;
+  }
+  p->stream = (hipStream_t)hip_stream;
+  p->prec = prec;
+  p->inst.resize(batch);
+  int64_t off = 0, joff = 0, jcoff = 0, woff = 0, poff = 0, soff = 0;
+  for (int i = 0; i < batch; ++i) {
+    Instance& in = p->inst[i];
+    in.Nn = n_nodes_host[i];
+    in.N = in.Nn - 1;
+    in.nx = n_x_host[i];
+    in.npairs = (in.nx + 1) / 2;
+    in.off = off;
+    in.joff = joff;
+    in.jcoff = jcoff;
+    in.L = 2 * in.N;
+    if (is_pow2(in.L)) {
+      in.method = DCT_POW2;
+      in.M = in.L;
+    } else {
+      in.method = DCT_BLUESTEIN;
+      in.M = int64_t(1) << ilog2(2 * in.L - 1);
+    }
+    in.logM = ilog2(in.M);
+    if (in.logM > kLdsMaxLog) {
+      in.logM1 = (in.logM + 1) / 2;
+      in.logM2 = in.logM - in.logM1;
+    }
+    in.tw4_shift = (in.logM + 1) / 2;
+    in.work_off = woff;
+    in.nblk_mid = (int)((in.Nn + 255) / 256);
+    in.part_off = poff;
+    in.scan_off = soff;
+    off += in.Nn * in.nx;
+    joff += in.Nn * in.nx * in.nx;
+    jcoff += (int64_t)in.nx * in.nx;
+    woff += in.M * in.npairs;
+    poff += (int64_t)in.npairs * in.nblk_mid * 2;
+    soff += pinv_scratch(in.Nn, in.nx) + (int64_t)in.nx * ((in.Nn + 1023) / 1024) + 64;
+  }
+  p->total_len = off;
+  p->total_jnode = joff;
+  p->total_jconst = jcoff;
+  p->total_work = woff;
+  p->total_part = poff;
+  p->total_scan = soff;
+
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < 3 && e == hipSuccess; ++b) e = hipMalloc(&p->work[b], woff * sizeof(double2));
+  for (int b = 0; b < 4 && e == hipSuccess; ++b) e = hipMalloc(&p->tmp_vec[b], off * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&p->partials, std::max<int64_t>(poff, 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&p->scan, std::max<int64_t>(soff, 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&p->flag, sizeof(int));
+  for (int i = 0; i < batch && e == hipSuccess; ++i) e = hipMalloc(&p->inst[i].w, p->inst[i].Nn * sizeof(double));
+  if (e == hipSuccess) e = build_tables(p);
+  // CC weights: w = B^aT e_N (the last row of B^a), instance by instance on component 0
+  if (e == hipSuccess) {
+    double* v = (double*)p->tmp_vec[0];
+    double* o = (double*)p->tmp_vec[1];
+    e = hipMemsetAsync(v, 0, off * sizeof(double), p->stream);
+    for (int i = 0; i < batch && e == hipSuccess; ++i) {
+      hipLaunchKernelGGL(k_set_unit, dim3(1), dim3(1), 0, p->stream, v, p->inst[i].off + p->inst[i].N);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = apply_product<double>(p, v, o, 1, p->stream);
+    for (int i = 0; i < batch && e == hipSuccess; ++i) {
+      const Instance& in = p->inst[i];
+      hipLaunchKernelGGL(k_extract_weights, dim3((unsigned)((in.Nn + 255) / 256)), dim3(256), 0, p->stream,
+                         o + in.off, in.w, in.Nn);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  }
+  if (e != hipSuccess) {
+    free_plan(p);
+    return dev_err(e);
+  }
+  *out = p;
+  return BIRK_OK;
+}
+
+birk_status birk_plan_destroy(birk_plan* p) {
+  if (!p) return BIRK_OK;
+  DeviceGuard g(p->device);
+  (void)hipStreamSynchronize(p->stream);
+  free_plan(p);
+  return BIRK_OK;
+}
+
+birk_status birk_weights(birk_plan* p, int32_t inst, double* w_host) {
+  if (!p || !w_host) return BIRK_ERR_ARG;
+  if (inst < 0 || inst >= (int32_t)p->inst.size()) return BIRK_ERR_SIZE;
+  DeviceGuard g(p->device);
+  const Instance& in = p->inst[inst];
+  hipError_t e = hipMemcpyAsync(w_host, in.w, in.Nn * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+}
+
+static birk_status product(birk_plan* p, const void* v, void* out, int transpose) {
+  if (!p || !v || !out || v == out) return BIRK_ERR_ARG;
+  DeviceGuard g(p->device);
+  hipError_t e;
+  switch (p->prec) {
+    case BIRK_F64:
+      e = apply_product<double>(p, (const double*)v, (double*)out, transpose, p->stream);
+      break;
+    case BIRK_F32:
+    case BIRK_F32_REFINE_F64:
+      e = apply_product<float>(p, (const float*)v, (float*)out, transpose, p->stream);
+      break;
+    default:
+      return BIRK_ERR_UNSUPPORTED;
+  }
+  return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+}
+
+birk_status birk_apply(birk_plan* p, const void* v, void* out) { return product(p, v, out, 0); }
+birk_status birk_apply_T(birk_plan* p, const void* g, void* out) { return product(p, g, out, 1); }
+
+static bool nx_ok_for_precond(const birk_plan* p) {
+  for (const auto& in : p->inst)
+    if (in.nx > kMaxPrecondNx) return false;
+  return true;
+}
+
+birk_status birk_precond(birk_plan* p, birk_jac_kind jk, const double* J, const void* y, void* out,
+                         int32_t inverse) {
+  if (!p || !J || !y || !out || y == out) return BIRK_ERR_ARG;
+  if (jk != BIRK_J_CONSTANT && jk != BIRK_J_PER_NODE) return BIRK_ERR_ARG;
+  if (inverse != 0 && inverse != 1) return BIRK_ERR_ARG;
+  if (p->prec == BIRK_DF32) return BIRK_ERR_UNSUPPORTED;
+  if (inverse && !nx_ok_for_precond(p)) return BIRK_ERR_UNSUPPORTED;
+  DeviceGuard g(p->device);
+  hipError_t e;
+  if (p->prec == BIRK_F64) {
+    e = inverse ? precond_inverse<double>(p, jk, J, (const double*)y, (double*)out, nullptr, p->stream, nullptr)
+                : precond_forward<double>(p, jk, J, (const double*)y, (double*)out, p->stream);
+  } else {
+    e = inverse ? precond_inverse<float>(p, jk, J, (const float*)y, (float*)out, nullptr, p->stream, nullptr)
+                : precond_forward<float>(p, jk, J, (const float*)y, (float*)out, p->stream);
+  }
+  return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+}
+
+// A x = x - B^a (J x) in double; uses tmp_vec[2], tmp_vec[3].
+static hipError_t fast_ax_f64(birk_plan* p, int jk, const double* J, const double* x, double* t_out) {
+  double* y = (double*)p->tmp_vec[2];
+  hipError_t e = jac_times<double>(p, jk, J, x, y, p->stream);
+  if (e == hipSuccess) e = apply_product<double>(p, y, t_out, 0, p->stream);
+  return e;
+}
+
+birk_status birk_fast_ax(birk_plan* p, birk_jac_kind jk, const double* J, const double* x, double* out) {
+  if (!p || !J || !x || !out || x == out) return BIRK_ERR_ARG;
+  if (jk != BIRK_J_CONSTANT && jk != BIRK_J_PER_NODE) return BIRK_ERR_ARG;
+  DeviceGuard g(p->device);
+  double* t = (double*)p->tmp_vec[3];
+  hipError_t e = fast_ax_f64(p, jk, J, x, t);
+  if (e == hipSuccess) kry::sub<double>(x, t, out, p->total_len, p->stream);
+  e = (e == hipSuccess) ? hipGetLastError() : e;
+  return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ GMRES
+namespace {
+
+constexpr int kDotsStride = kKryMaxDots + 1;
+
+struct InstState {
+  double bnorm = 0.0;
+  double rnorm = 0.0;
+  int status = BIRK_OK;
+  int inner = 0;
+  int outer = 0;
+  bool done = false;
+  bool breakdown_last = false;
+};
+
+hipError_t ensure_krylov(birk_plan* p, int m, size_t esize) {
+  if (p->krylov_Q && p->krylov_m >= m) return hipSuccess;
+  if (p->krylov_Q) (void)hipFree(p->krylov_Q);
+  if (p->krylov_vec) (void)hipFree(p->krylov_vec);
+  p->krylov_Q = p->krylov_vec = nullptr;
+  // sized for double so that one allocation serves either Krylov precision
+  (void)esize;
+  hipError_t e = hipMalloc(&p->krylov_Q, (size_t)(m + 1) * p->total_len * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&p->krylov_vec, (size_t)4 * p->total_len * sizeof(double));
+  if (e == hipSuccess && !p->krylov_dots)
+    e = hipMalloc(&p->krylov_dots, (size_t)p->inst.size() * 2 * kDotsStride * sizeof(double));
+  if (e == hipSuccess && !p->krylov_part) e = hipMalloc(&p->krylov_part, (size_t)2048 * kDotsStride * sizeof(double));
+  if (e == hipSuccess) p->krylov_m = m;
+  return e;
+}
+
+// Per-instance ||v_i||^2 for a double vector; results into host array.
+hipError_t seg_norms(birk_plan* p, const double* v, std::vector<double>& out) {
+  const int B = (int)p->inst.size();
+  for (int i = 0; i < B; ++i) {
+    const Instance& in = p->inst[i];
+    kry::dots<double>(nullptr, 0, 0, v + in.off, in.Nn * in.nx, p->krylov_part,
+                      p->krylov_dots + (size_t)i * 2 * kDotsStride, p->stream);
+  }
+  std::vector<double> h((size_t)B * 2 * kDotsStride);
+  hipError_t e = hipMemcpyAsync(h.data(), p->krylov_dots, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  out.resize(B);
+  for (int i = 0; i < B; ++i) out[i] = std::sqrt(std::max(0.0, h[(size_t)i * 2 * kDotsStride + kKryMaxDots]));
+  return e;
+}
+
+// One right-preconditioned GMRES cycle in precision TK on A d = r / ||r||, for every
+// instance not yet done; chi += ||r|| d.  r lives in tmp_vec[0] (double).
+template <typename TK>
+birk_status gmres_cycle(birk_plan* p, int jk, const double* J, double* chi, std::vector<InstState>& st,
+                        const std::vector<double>& tol_inner, int m, int use_precond, int& budget) {
+  const int B = (int)p->inst.size();
+  const int64_t n = p->total_len;
+  hipStream_t s = p->stream;
+  TK* Q = (TK*)p->krylov_Q;
+  TK* u = (TK*)p->krylov_vec;
+  TK* z = u + n;
+  TK* y = z + n;
+  TK* t = y + n;
+  const double* r = (const double*)p->tmp_vec[0];
+  const int64_t ld = n;
+  hipError_t e = hipSuccess;
+
+  std::vector<char> active(B, 0);
+  for (int i = 0; i < B; ++i) active[i] = !st[i].done;
+  // q_0 = r / ||r|| (zero for inactive instances)
+  for (int i = 0; i < B; ++i) {
+    const Instance& in = p->inst[i];
+    const double sc = active[i] && st[i].rnorm > 0 ? 1.0 / st[i].rnorm : 0.0;
+    kry::scale_conv<double, TK>(r + in.off, Q + in.off, sc, in.Nn * in.nx, s);
+  }
+  std::vector<std::vector<double>> H(B, std::vector<double>((size_t)(m + 1) * m, 0.0));
+  std::vector<std::vector<double>> cs(B, std::vector<double>(m, 0.0)), sn(B, std::vector<double>(m, 0.0));
+  std::vector<std::vector<double>> gv(B, std::vector<double>(m + 1, 0.0));
+  std::vector<int> jend(B, 0);
+  std::vector<char> running(active);
+  for (int i = 0; i < B; ++i) gv[i][0] = 1.0;
+  std::vector<double> hbuf((size_t)B * 2 * kDotsStride);
+  int flag_checked = 0;
+
+  for (int j = 0; j < m && budget > 0; ++j) {
+    bool any = false;
+    for (int i = 0; i < B; ++i) any = any || running[i];
+    if (!any) break;
+    const TK* qj = Q + (size_t)j * ld;
+    // z = P^{-1} q_j, y = J z; t = B^a y; u = z - t
+    if (use_precond) {
+      e = precond_inverse<TK>(p, jk, J, qj, z, y, s, p->flag);
+      if (e != hipSuccess) return BIRK_ERR_DEVICE;
+      e = apply_product<TK>(p, y, t, 0, s);
+      if (e != hipSuccess) return BIRK_ERR_DEVICE;
+      kry::sub<TK>(z, t, u, n, s);
+    } else {
+      e = jac_times<TK>(p, jk, J, qj, y, s);
+      if (e != hipSuccess) return BIRK_ERR_DEVICE;
+      e = apply_product<TK>(p, y, t, 0, s);
+      if (e != hipSuccess) return BIRK_ERR_DEVICE;
+      kry::sub<TK>(qj, t, u, n, s);
+    }
+    // CGS2 per running instance
+    for (int i = 0; i < B; ++i) {
+      if (!running[i]) continue;
+      const Instance& in = p->inst[i];
+      const int64_t ni = in.Nn * in.nx;
+      double* d1 = p->krylov_dots + (size_t)i * 2 * kDotsStride;
+      double* d2 = d1 + kDotsStride;
+      kry::dots<TK>(Q + in.off, ld, j + 1, u + in.off, ni, p->krylov_part, d1, s);
+      kry::axpys<TK>(Q + in.off, ld, j + 1, d1, u + in.off, ni, nullptr, nullptr, s);
+      kry::dots<TK>(Q + in.off, ld, j + 1, u + in.off, ni, p->krylov_part, d2, s);
+      kry::axpys<TK>(Q + in.off, ld, j + 1, d2, u + in.off, ni, p->krylov_part, d2, s);
+      kry::normalize<TK>(u + in.off, d2 + kKryMaxDots, Q + (size_t)(j + 1) * ld + in.off, ni, s);
+    }
+    e = hipMemcpyAsync(hbuf.data(), p->krylov_dots, hbuf.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return BIRK_ERR_DEVICE;
+    if (use_precond && !flag_checked) {
+      int f = 0;
+      if (hipMemcpy(&f, p->flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return BIRK_ERR_DEVICE;
+      flag_checked = 1;
+      if (f) {
+        for (int i = 0; i < B; ++i) st[i].status = BIRK_ERR_SINGULAR;
+        return BIRK_ERR_SINGULAR;
+      }
+    }
+    --budget;
+    for (int i = 0; i < B; ++i) {
+      if (!running[i]) continue;
+      st[i].inner += 1;
+      const double* d1 = hbuf.data() + (size_t)i * 2 * kDotsStride;
+      const double* d2 = d1 + kDotsStride;
+      double* Hc = H[i].data() + (size_t)j * (m + 1);  // column j, rows 0..j+1
+      for (int k = 0; k <= j; ++k) Hc[k] = d1[k] + d2[k];
+      double hn = std::sqrt(std::max(0.0, d2[kKryMaxDots]));
+      Hc[j + 1] = hn;
+      bool finite = std::isfinite(hn);
+      for (int k = 0; k <= j; ++k) finite = finite && std::isfinite(Hc[k]);
+      if (!finite) {
+        st[i].status = BIRK_ERR_NONFINITE;
+        running[i] = 0;
+        jend[i] = j;  // discard this column
+        continue;
+      }
+      for (int k = 0; k < j; ++k) {
+        const double a = cs[i][k] * Hc[k] + sn[i][k] * Hc[k + 1];
+        Hc[k + 1] = -sn[i][k] * Hc[k] + cs[i][k] * Hc[k + 1];
+        Hc[k] = a;
+      }
+      const double den = std::hypot(Hc[j], Hc[j + 1]);
+      if (den == 0.0) {
+        st[i].status = BIRK_ERR_BREAKDOWN;
+        running[i] = 0;
+        jend[i] = j;
+        continue;
+      }
+      cs[i][j] = Hc[j] / den;
+      sn[i][j] = Hc[j + 1] / den;
+      Hc[j] = den;
+      Hc[j + 1] = 0.0;
+      gv[i][j + 1] = -sn[i][j] * gv[i][j];
+      gv[i][j] = cs[i][j] * gv[i][j];
+      jend[i] = j + 1;
+      const bool lucky = hn <= 1e-14 * den;
+      if (std::fabs(gv[i][j + 1]) <= tol_inner[i] || lucky) running[i] = 0;
+    }
+  }
+  // back substitution and chi += ||r|| P^{-1} (Q y)
+  std::vector<double> coef((size_t)B * kDotsStride, 0.0);
+  for (int i = 0; i < B; ++i) {
+    if (!active[i]) continue;
+    const int k = jend[i];
+    std::vector<double> yv(k, 0.0);
+    for (int a = k - 1; a >= 0; --a) {
+      double sacc = gv[i][a];
+      for (int b = a + 1; b < k; ++b) sacc -= H[i][(size_t)b * (m + 1) + a] * yv[b];
+      yv[a] = sacc / H[i][(size_t)a * (m + 1) + a];
+    }
+    for (int a = 0; a < k; ++a) coef[(size_t)i * kDotsStride + a] = yv[a] * st[i].rnorm;
+  }
+  e = hipMemcpyAsync(p->krylov_dots, coef.data(), std::min(coef.size(), (size_t)B * 2 * kDotsStride) * sizeof(double),
+                     hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return BIRK_ERR_DEVICE;
+  for (int i = 0; i < B; ++i) {
+    const Instance& in = p->inst[i];
+    const int k = active[i] ? jend[i] : 0;
+    kry::combine<TK>(Q + in.off, ld, k, p->krylov_dots + (size_t)i * kDotsStride, t + in.off, in.Nn * in.nx, s);
+  }
+  if (use_precond) {
+    e = precond_inverse<TK>(p, jk, J, t, z, nullptr, s, nullptr);
+    if (e != hipSuccess) return BIRK_ERR_DEVICE;
+    kry::add_to<TK>(chi, z, n, s);
+  } else {
+    kry::add_to<TK>(chi, t, n, s);
+  }
+  e = hipStreamSynchronize(s);
+  return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+}
+
+}  // namespace
+
+extern "C" birk_status birk_krylov_solve(birk_plan* p, birk_jac_kind jk, const double* J, const double* beta, double* chi,
+                              const birk_solve_opts* opts_in, birk_solve_info* info) {
+  if (!p || !J || !beta || !chi || beta == chi) return BIRK_ERR_ARG;
+  if (jk != BIRK_J_CONSTANT && jk != BIRK_J_PER_NODE) return BIRK_ERR_ARG;
+  birk_solve_opts o;
+  birk_solve_opts_default(&o);
+  if (opts_in) o = *opts_in;
+  if (o.method == 1) return BIRK_ERR_UNSUPPORTED;
+  if (o.method != 0) return BIRK_ERR_ARG;
+  if (o.restart < 1 || o.restart > kKryMaxDots - 1 || o.max_iter < 1 || !(o.rtol > 0.0)) return BIRK_ERR_ARG;
+  if (p->prec == BIRK_F32 || p->prec == BIRK_DF32) return BIRK_ERR_UNSUPPORTED;
+  if (o.use_precond && !nx_ok_for_precond(p)) return BIRK_ERR_UNSUPPORTED;
+  const bool mixed = p->prec == BIRK_F32_REFINE_F64;
+  if (mixed && (!(o.inner_rtol > 0.0) || o.max_refine < 1)) return BIRK_ERR_ARG;
+  DeviceGuard g(p->device);
+  const int B = (int)p->inst.size();
+  const int64_t n = p->total_len;
+  hipStream_t s = p->stream;
+  hipError_t e = ensure_krylov(p, o.restart, mixed ? sizeof(float) : sizeof(double));
+  if (e != hipSuccess) return dev_err(e);
+  if (hipMemsetAsync(p->flag, 0, sizeof(int), s) != hipSuccess) return BIRK_ERR_DEVICE;
+  if (!o.use_x0 && hipMemsetAsync(chi, 0, n * sizeof(double), s) != hipSuccess) return BIRK_ERR_DEVICE;
+
+  std::vector<InstState> st(B);
+  std::vector<double> nb;
+  if (seg_norms(p, beta, nb) != hipSuccess) return BIRK_ERR_DEVICE;
+  for (int i = 0; i < B; ++i) st[i].bnorm = nb[i];
+
+  int budget = o.max_iter;
+  const int max_outer = mixed ? o.max_refine + 1 : o.max_iter + 1;
+  birk_status result = BIRK_OK;
+  double* r = (double*)p->tmp_vec[0];
+  double* t = (double*)p->tmp_vec[1];
+  for (int outer = 0;; ++outer) {
+    // true residual r = beta - A chi in double
+    e = fast_ax_f64(p, jk, J, chi, t);
+    if (e != hipSuccess) return BIRK_ERR_DEVICE;
+    kry::residual(beta, chi, t, r, n, s);
+    std::vector<double> rn;
+    if (seg_norms(p, r, rn) != hipSuccess) return BIRK_ERR_DEVICE;
+    bool all_done = true;
+    for (int i = 0; i < B; ++i) {
+      st[i].rnorm = rn[i];
+      if (st[i].done) continue;
+      if (!std::isfinite(rn[i])) {
+        st[i].status = BIRK_ERR_NONFINITE;
+        st[i].done = true;
+        continue;
+      }
+      if (rn[i] <= o.rtol * st[i].bnorm) {
+        st[i].status = BIRK_OK;
+        st[i].done = true;
+        continue;
+      }
+      if (st[i].status == BIRK_ERR_BREAKDOWN && st[i].breakdown_last) {
+        st[i].done = true;
+        continue;
+      }
+      all_done = false;
+    }
+    if (all_done) break;
+    if (outer >= max_outer || budget <= 0) {
+      for (int i = 0; i < B; ++i)
+        if (!st[i].done) {
+          st[i].status = BIRK_ERR_NOCONV;
+          st[i].done = true;
+        }
+      break;
+    }
+    std::vector<double> tol(B, 0.0);
+    for (int i = 0; i < B; ++i) {
+      if (st[i].done) continue;
+      const double need = 0.5 * o.rtol * st[i].bnorm / st[i].rnorm;
+      tol[i] = mixed ? std::max(o.inner_rtol, need) : need;
+      st[i].outer += 1;
+      st[i].breakdown_last = st[i].status == BIRK_ERR_BREAKDOWN;
+      if (st[i].status == BIRK_ERR_BREAKDOWN) st[i].status = BIRK_OK;
+    }
+    birk_status cs = mixed ? gmres_cycle<float>(p, jk, J, chi, st, tol, o.restart, o.use_precond, budget)
+                           : gmres_cycle<double>(p, jk, J, chi, st, tol, o.restart, o.use_precond, budget);
+    if (cs == BIRK_ERR_SINGULAR || cs == BIRK_ERR_DEVICE) {
+      result = cs;
+      for (int i = 0; i < B; ++i) st[i].done = true;
+      break;
+    }
+    for (int i = 0; i < B; ++i)
+      if (st[i].status == BIRK_ERR_NONFINITE) st[i].done = true;
+  }
+  for (int i = 0; i < B; ++i) {
+    if (result == BIRK_OK && st[i].status != BIRK_OK) result = (birk_status)st[i].status;
+    if (info) {
+      if (info->status) info->status[i] = st[i].status;
+      if (info->inner_iters) info->inner_iters[i] = st[i].inner;
+      if (info->outer_iters) info->outer_iters[i] = st[i].outer;
+      if (info->rel_resid_fp64) info->rel_resid_fp64[i] = st[i].bnorm > 0 ? st[i].rnorm / st[i].bnorm : st[i].rnorm;
+    }
+  }
+  if (result == BIRK_ERR_SINGULAR && info && info->status)
+    for (int i = 0; i < B; ++i) info->status[i] = BIRK_ERR_SINGULAR;
+  return result;
+}

@@ -1,0 +1,91 @@
+"""Host-only checks of the C-ABI library: it loads, exports every symbol that
+include/birk.h declares, and rejects bad arguments on the host before any device work.
+No compute call is made (no GPU is needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "birk.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(birk_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def birk():
+    from paper_2509_01855_amd import birk as b
+    return b
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("birk_apply", "birk_apply_T", "birk_precond", "birk_krylov_solve",
+                     "birk_plan_create", "birk_plan_destroy", "birk_status_string"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(birk):
+    lib = ctypes.CDLL(birk.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(birk.EXPORTED) == _declared_functions()
+
+
+def test_status_strings_cover_every_code(birk):
+    seen = set()
+    for code in range(0, -10, -1):
+        s = birk.birk_status_string(code)
+        assert s.startswith("BIRK_") and s not in seen
+        seen.add(s)
+    assert birk.birk_status_string(12345) == "unknown birk_status"
+
+
+def test_solve_opts_defaults(birk):
+    o = birk.birk_solve_opts_default()
+    assert (o.method, o.restart, o.max_iter, o.use_precond, o.use_x0) == (0, 30, 300, 1, 0)
+    assert o.rtol == 1e-10 and o.inner_rtol == 1e-5 and o.max_refine == 8
+
+
+def test_struct_layouts(birk):
+    assert ctypes.sizeof(birk.birk_solve_opts) == 48
+    assert ctypes.sizeof(birk.birk_solve_info) == 32
+
+
+@pytest.mark.parametrize("n_nodes,n_x,prec,expect", [
+    ([2], [6], 0, -2),          # N_n < 3
+    ([256], [0], 0, -2),        # n_x < 1
+    ([256], [6], 7, -1),        # bad precision
+    ([(1 << 23) + 2], [1], 0, -2),   # N = 2^23 + 1 is not a power of two and exceeds 2^22
+    ([(1 << 24) + 1], [1], 0, -2),   # power of two beyond the limit
+])
+def test_plan_create_rejects_on_host(birk, n_nodes, n_x, prec, expect):
+    h = ctypes.c_void_p()
+    nn = (ctypes.c_int64 * 1)(*n_nodes)
+    nx = (ctypes.c_int32 * 1)(*n_x)
+    assert birk._lib.birk_plan_create(ctypes.byref(h), 1, nn, nx, prec, None) == expect
+    assert h.value is None
+
+
+def test_null_arguments_are_rejected(birk):
+    lib = birk._lib
+    h = ctypes.c_void_p()
+    nn = (ctypes.c_int64 * 1)(256)
+    nx = (ctypes.c_int32 * 1)(6)
+    assert lib.birk_plan_create(None, 1, nn, nx, 0, None) == birk.BIRK_ERR_ARG
+    assert lib.birk_plan_create(ctypes.byref(h), 1, None, nx, 0, None) == birk.BIRK_ERR_ARG
+    assert lib.birk_plan_create(ctypes.byref(h), 0, nn, nx, 0, None) == birk.BIRK_ERR_SIZE
+    assert lib.birk_apply(None, None, None) == birk.BIRK_ERR_ARG
+    assert lib.birk_apply_T(None, None, None) == birk.BIRK_ERR_ARG
+    assert lib.birk_precond(None, 0, None, None, None, 1) == birk.BIRK_ERR_ARG
+    assert lib.birk_fast_ax(None, 0, None, None, None) == birk.BIRK_ERR_ARG
+    assert lib.birk_krylov_solve(None, 0, None, None, None, None, None) == birk.BIRK_ERR_ARG
+    assert lib.birk_weights(None, 0, None) == birk.BIRK_ERR_ARG
+    assert lib.birk_plan_destroy(None) == birk.BIRK_OK
+    assert lib.birk_plan_length(None) == 0

@@ -1,0 +1,137 @@
+"""GPU parity of birk_apply / birk_apply_T (FastBV and its transpose) against the FP64
+oracle, through the C ABI.
+
+Tolerances (relative to max |reference|):
+* double: 1e-12, the accuracy target for the FP64 path.  Two FFT-based DCT-I of
+  length <= 2^21 accumulate roughly 2 * c * log2(M) * eps64 ~ 1e-14; 1e-12 leaves room.
+* float:  2e-5.  The same bound with eps32 = 6e-8 and log2(M) <= 22 gives
+  ~2 * 22 * 6e-8 ~ 3e-6 for power-of-two transforms; Bluestein's chirp products add
+  a few ulps more per output.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import birkhoff as bk
+from paper_2509_01855_amd import workloads as wl
+from tests.gpu_util import announce, dense_Ba, dev, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 2e-5}
+
+SIZES = [3, 4, 5, 6, 9, 10, 17, 33, 100, 256, 257, 1000, 1025, 2049, 3000, 4097]
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU parity tests need a GPU"
+    from paper_2509_01855_amd import birk
+    return birk
+
+
+def _run(B, Nn_list, nx_list, prec, X, transpose):
+    import torch
+    plan = B.birk_plan_create(Nn_list, nx_list, prec)
+    dt = torch.float64 if prec == B.BIRK_F64 else torch.float32
+    v = dev(X, dt)
+    out = torch.empty_like(v)
+    (B.birk_apply_T if transpose else B.birk_apply)(plan, v, out)
+    torch.cuda.synchronize()
+    r = host(out).astype(np.float64)
+    plan.destroy()
+    return r
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("transpose", [0, 1])
+@pytest.mark.parametrize("Nn", SIZES)
+def test_product_dense(B, Nn, transpose, prec):
+    nx = 3 if Nn > 1000 else 7
+    announce(f"product Nn={Nn} nx={nx} transpose={transpose} prec={prec}")
+    N = Nn - 1
+    X = wl.random_vectors([1, Nn], (nx, Nn))[0]
+    p = B.BIRK_F64 if prec == "f64" else B.BIRK_F32
+    got = _run(B, [Nn], [nx], p, X.ravel(), transpose).reshape(nx, Nn)
+    Ba = dense_Ba(N)
+    ref = X @ (Ba if transpose else Ba.T)
+    assert rel_err(got, ref) <= TOL[prec]
+
+
+def test_product_batched_instances(B):
+    Nn_list = [3, 256, 257, 1000, 4097, 65]
+    nx_list = [1, 6, 4, 5, 2, 12]
+    announce(f"batched plan {Nn_list} {nx_list}")
+    Xs = [wl.random_vectors([2, i], (nx, Nn))[0] for i, (Nn, nx) in enumerate(zip(Nn_list, nx_list))]
+    flat = np.concatenate([x.ravel() for x in Xs])
+    for transpose in (0, 1):
+        got = _run(B, Nn_list, nx_list, B.BIRK_F64, flat, transpose)
+        o = 0
+        for X, Nn, nx in zip(Xs, Nn_list, nx_list):
+            Ba = dense_Ba(Nn - 1)
+            ref = X @ (Ba if transpose else Ba.T)
+            assert rel_err(got[o:o + nx * Nn].reshape(nx, Nn), ref) <= TOL["f64"]
+            o += nx * Nn
+
+
+@pytest.mark.parametrize("Nn", [(1 << 16) + 1, (1 << 20) + 1, 65521, 100003])
+def test_apply_exact_sparse_modes_large(B, Nn):
+    """At sizes without a dense matrix: v = sum of 64 Chebyshev modes, exact B^a v from the
+    closed-form antiderivatives (B^a is exact for polynomials of degree <= N)."""
+    N = Nn - 1
+    nx = 2
+    announce(f"sparse-mode apply Nn={Nn}")
+    rows, refs = [], []
+    for c in range(nx):
+        modes, alphas = wl.sparse_modes([7, c, Nn], N, count=64)
+        rows.append(bk.sparse_mode_values(N, modes, alphas))
+        refs.append(bk.sparse_mode_exact(N, modes, alphas))
+    X = np.stack(rows)
+    got = _run(B, [Nn], [nx], B.BIRK_F64, X.ravel(), 0).reshape(nx, Nn)
+    assert rel_err(got, np.stack(refs)) <= TOL["f64"]
+    got32 = _run(B, [Nn], [nx], B.BIRK_F32, X.ravel(), 0).reshape(nx, Nn)
+    assert rel_err(got32, np.stack(refs)) <= TOL["f32"]
+
+
+@pytest.mark.parametrize("Nn", [(1 << 16) + 1, (1 << 20) + 1, 100003])
+def test_apply_T_sparse_rhs_large(B, Nn):
+    """B^aT g for g supported on a few nodes is a combination of rows of B^a, each of
+    which the oracle computes in O(N log N); compared at every output."""
+    N = Nn - 1
+    rng = np.random.default_rng(Nn)
+    idx = sorted(set([0, 1, N // 2, N - 1, N] + list(rng.integers(0, Nn, 5))))
+    g = np.zeros(Nn)
+    g[idx] = rng.standard_normal(len(idx))
+    announce(f"sparse-g apply_T Nn={Nn}")
+    ref = sum(g[i] * bk.ba_row(N, i) for i in idx)
+    got = _run(B, [Nn], [1], B.BIRK_F64, g, 1)
+    assert rel_err(got, ref) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("Nn", [(1 << 18) + 1, 12345])
+def test_transpose_is_adjoint_large(B, Nn):
+    """<B^a v, g> = <v, B^aT g> with random v, g (both products from the GPU), and the
+    B^a v side pinned exactly through sparse modes."""
+    N = Nn - 1
+    modes, alphas = wl.sparse_modes([9, Nn], N, count=32)
+    v = bk.sparse_mode_values(N, modes, alphas)
+    Bv = bk.sparse_mode_exact(N, modes, alphas)
+    g = np.random.default_rng(3).standard_normal(Nn)
+    announce(f"adjoint Nn={Nn}")
+    BTg = _run(B, [Nn], [1], B.BIRK_F64, g, 1)
+    lhs = float(Bv @ g)
+    rhs = float(v @ BTg)
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(Bv) * np.linalg.norm(g) * 10
+
+
+@pytest.mark.parametrize("Nn", [3, 10, 257, 4097, (1 << 20) + 1])
+def test_weights(B, Nn):
+    announce(f"weights Nn={Nn}")
+    plan = B.birk_plan_create([Nn], [1], B.BIRK_F64)
+    w = B.birk_weights(plan, 0)
+    plan.destroy()
+    N = Nn - 1
+    ref = bk.cc_weights_closed_form(N) if Nn <= 4097 else bk.ba_row(N, N)
+    assert np.max(np.abs(w - ref)) <= 1e-15 * 50 + 1e-12 * np.max(np.abs(ref))
+    assert abs(w.sum() - 2.0) <= 1e-12
