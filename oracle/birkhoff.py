@@ -18,6 +18,8 @@ Optimization Solver"):
 
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 import scipy.fft
 
@@ -38,6 +40,7 @@ __all__ = [
     "ba_row",
     "sparse_mode_exact",
     "sparse_mode_values",
+    "apply_Ba_extended",
 ]
 
 
@@ -160,8 +163,15 @@ def dense_Ba_modal(N: int) -> np.ndarray:
 
 
 def dense_Ba(N: int) -> np.ndarray:
-    """Dense B^a (construction 2; the two constructions agree to ~1e-14)."""
-    return dense_Ba_modal(N)
+    """Dense B^a = I T^{-1} with the closed-form inverse of App. B (eq:ak=3).
+
+    Same definition as construction 2; the closed-form inverse keeps entries accurate
+    to a few ulps at N in the thousands, where the LAPACK inverse loses ~3 digits.
+    """
+    Int = np.empty((N + 1, N + 1))
+    for k in range(N + 1):
+        Int[:, k] = cheb_antiderivative_at_nodes(N, k)
+    return Int @ T_inverse_closed_form(N)
 
 
 def weights(N: int) -> np.ndarray:
@@ -263,3 +273,45 @@ def sparse_mode_exact(N: int, modes, alphas) -> np.ndarray:
             raise ValueError("mode index must lie in [0, N]")
         out += a * cheb_antiderivative_at_nodes(N, int(k))
     return out
+
+
+def apply_Ba_extended(N: int, X: np.ndarray, transpose: bool = False) -> np.ndarray:
+    """Rows of X times B^a^T (transpose=False: each row x -> B^a x) or times B^a
+    (transpose=True: x -> B^aT x), evaluated in x87 extended precision (np.longdouble).
+
+    Same definition as construction 2, B^a = I T^{-1}, with T^{-1} from App. B
+    (eq:ak=3) and I from eq:intChebPoly=; the factors are applied one after the other
+    (X T^{-T} I^T, or X I T^{-1}) so the dense B^a is never rounded to double.  Used as
+    the product reference where the double-precision dense matrix is itself only good
+    to ~1e-12 relative (N in the thousands).  Cost O(N^2) per row plus O(N^2) set-up.
+    """
+    ld = np.longdouble
+    X = np.atleast_2d(np.asarray(X, dtype=np.float64)).astype(ld)
+    Tinv, Int = _extended_factors(N)
+    if transpose:
+        return ((X @ Int) @ Tinv).astype(np.float64)
+    return ((X @ Tinv.T) @ Int.T).astype(np.float64)
+
+
+@functools.lru_cache(maxsize=1)
+def _extended_factors(N: int):
+    ld = np.longdouble
+    pi = ld(4) * np.arctan(ld(1))
+    j = np.arange(N + 1, dtype=np.int64)
+    k = np.arange(N + 2, dtype=np.int64)
+    # T_m(tau_j) for m = 0..N+1 (column N+1 feeds the antiderivative of T_N)
+    Tm = np.cos(pi * ((k[None, :] * (N - j[:, None])) % (2 * N)).astype(ld) / ld(N))
+    c = np.ones(N + 1, dtype=ld)
+    c[0] = c[N] = ld(2)
+    e = np.ones(N + 1, dtype=ld)
+    e[0] = e[N] = ld(0.5)
+    Tinv = (ld(2) / ld(N)) * (Tm[:, :N + 1].T / c[:, None]) * e[None, :]   # [k, j]
+    Int = np.empty((N + 1, N + 1), dtype=ld)                              # [i, k]
+    Int[:, 0] = Tm[:, 1] + ld(1)
+    Int[:, 1] = Tm[:, 2] / ld(4) - ld(0.25)
+    kk = np.arange(2, N + 1)
+    sgn = np.where(kk % 2 == 0, ld(1), ld(-1))
+    Int[:, 2:] = (Tm[:, 3:N + 2] / (ld(2) * (kk + 1).astype(ld))
+                  - Tm[:, 1:N] / (ld(2) * (kk - 1).astype(ld))
+                  - sgn / (kk.astype(ld) ** 2 - ld(1)))
+    return Tinv, Int

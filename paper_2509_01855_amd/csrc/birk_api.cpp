@@ -18,7 +18,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <vector>
 
@@ -145,6 +147,21 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
   }
   p->stream = (hipStream_t)hip_stream;
   p->prec = prec;
+  {
+    // BIRK_FAST=0 routes power-of-two sizes through the general FFT path (testing aid)
+    const char* f = std::getenv("BIRK_FAST");
+    p->use_fast = (f && f[0] == '0') ? 0 : 1;
+    // tuning of the three-pass kernels: LDS budget per workgroup (KB) for double and
+    // float, and which side of 2N = L1 L2 is the longer one
+    const char* l64 = std::getenv("BIRK_FAST_LDS_KB_F64");
+    const char* l32 = std::getenv("BIRK_FAST_LDS_KB_F32");
+    const char* sp = std::getenv("BIRK_FAST_SPLIT");
+    if (l64) p->fast_lds_kb[0] = std::max(16, std::min(160, std::atoi(l64)));
+    if (l32) p->fast_lds_kb[1] = std::max(16, std::min(160, std::atoi(l32)));
+    if (sp) p->fast_split = std::atoi(sp) ? 1 : 0;
+    const char* pp = std::getenv("BIRK_FAST_PPT");
+    if (pp) p->fast_ppt = std::atoi(pp) == 16 ? 16 : 8;
+  }
   p->inst.resize(batch);
   int64_t off = 0, joff = 0, jcoff = 0, woff = 0, poff = 0, soff = 0;
   for (int i = 0; i < batch; ++i) {
@@ -174,11 +191,18 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     in.nblk_mid = (int)((in.Nn + 255) / 256);
     in.part_off = poff;
     in.scan_off = soff;
+    int64_t wneed = in.M * in.npairs, pneed = (int64_t)in.npairs * in.nblk_mid * 2;
+    if (fast_eligible(in)) {
+      int64_t fw = 0, fp = 0;
+      fast_sizes(p, in, &fw, &fp);
+      wneed = std::max(wneed, fw);
+      pneed = std::max(pneed, fp);
+    }
     off += in.Nn * in.nx;
     joff += in.Nn * in.nx * in.nx;
     jcoff += (int64_t)in.nx * in.nx;
-    woff += in.M * in.npairs;
-    poff += (int64_t)in.npairs * in.nblk_mid * 2;
+    woff += wneed;
+    poff += pneed;
     soff += pinv_scratch(in.Nn, in.nx) + (int64_t)in.nx * ((in.Nn + 1023) / 1024) + 64;
   }
   p->total_len = off;
@@ -351,7 +375,11 @@ hipError_t seg_norms(birk_plan* p, const double* v, std::vector<double>& out) {
                                 p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   out.resize(B);
-  for (int i = 0; i < B; ++i) out[i] = std::sqrt(std::max(0.0, h[(size_t)i * 2 * kDotsStride + kKryMaxDots]));
+  for (int i = 0; i < B; ++i) {
+    const double v = h[(size_t)i * 2 * kDotsStride + kKryMaxDots];
+    // NaN must survive: std::max(0.0, NaN) would return 0
+    out[i] = std::isfinite(v) ? std::sqrt(v > 0.0 ? v : 0.0) : std::numeric_limits<double>::quiet_NaN();
+  }
   return e;
 }
 
@@ -441,7 +469,8 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, double* chi, std:
       const double* d2 = d1 + kDotsStride;
       double* Hc = H[i].data() + (size_t)j * (m + 1);  // column j, rows 0..j+1
       for (int k = 0; k <= j; ++k) Hc[k] = d1[k] + d2[k];
-      double hn = std::sqrt(std::max(0.0, d2[kKryMaxDots]));
+      const double hn2 = d2[kKryMaxDots];
+      double hn = std::isfinite(hn2) ? std::sqrt(hn2 > 0.0 ? hn2 : 0.0) : std::numeric_limits<double>::quiet_NaN();
       Hc[j + 1] = hn;
       bool finite = std::isfinite(hn);
       for (int k = 0; k <= j; ++k) finite = finite && std::isfinite(Hc[k]);

@@ -358,19 +358,31 @@ __global__ void k_mid_fwd(const cplx<T>* __restrict__ z, cplx<T>* __restrict__ z
   }
 }
 
-// d_0 = 2 c^_0 from the partials (fixed summation order), written at position 0.
+// d_0 = 2 c^_0 from the partials: one block per pair, fixed-order tree reduction.
 template <typename T>
-__global__ void k_c0(const double* __restrict__ part, int nblk, cplx<T>* __restrict__ z2, int64_t N,
-                     int64_t M, int npairs) {
-  const int pidx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (pidx >= npairs) return;
+__global__ __launch_bounds__(256) void k_c0(const double* __restrict__ part, int nblk, cplx<T>* __restrict__ z2,
+                                            int64_t N, int64_t M) {
+  const int pidx = blockIdx.x;
   double a = 0.0, b = 0.0;
-  for (int i = 0; i < nblk; ++i) {
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
     a += part[((int64_t)pidx * nblk + i) * 2 + 0];
     b += part[((int64_t)pidx * nblk + i) * 2 + 1];
   }
-  const double s = 2.0 / (double)N;
-  z2[(int64_t)pidx * M] = mk<T>((T)(a * s), (T)(b * s));
+  __shared__ double ra[256], rb[256];
+  ra[threadIdx.x] = a;
+  rb[threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      ra[threadIdx.x] += ra[threadIdx.x + st];
+      rb[threadIdx.x] += rb[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double s = 2.0 / (double)N;
+    z2[(int64_t)pidx * M] = mk<T>((T)(ra[0] * s), (T)(rb[0] * s));
+  }
 }
 
 // Transpose mid stage.  p = C E^{-1} g = Y / 2; q = S M^T S p, i.e.
@@ -453,6 +465,11 @@ template <typename T>
 hipError_t apply_product(birk_plan* p, const T* v, T* out, int transpose, hipStream_t s) {
   const int pi = std::is_same<T, double>::value ? 0 : 1;
   for (const Instance& in : p->inst) {
+    if (p->use_fast && fast_eligible(in)) {
+      hipError_t e = fast_product<T>(p, in, v, out, transpose, s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     cplx<T>* z = (cplx<T>*)p->work[0] + in.work_off;
     cplx<T>* z2 = (cplx<T>*)p->work[1] + in.work_off;
     cplx<T>* tmp = (cplx<T>*)p->work[2] + in.work_off;
@@ -469,8 +486,7 @@ hipError_t apply_product(birk_plan* p, const T* v, T* out, int transpose, hipStr
       double* part = p->partials + in.part_off;
       hipLaunchKernelGGL(k_mid_fwd<T>, dim3(nblk, in.npairs), dim3(256), 0, s, z, z2, in.N, in.L, M,
                          chirp, part);
-      hipLaunchKernelGGL(k_c0<T>, dim3((in.npairs + 63) / 64), dim3(64), 0, s, part, nblk, z2, in.N, M,
-                         in.npairs);
+      hipLaunchKernelGGL(k_c0<T>, dim3(in.npairs), dim3(256), 0, s, part, nblk, z2, in.N, M);
     } else {
       hipLaunchKernelGGL(k_mid_tr<T>, dim3(nblk, in.npairs), dim3(256), 0, s, z, z2, in.N, in.L, M,
                          chirp);
@@ -576,7 +592,7 @@ hipError_t build_tables(birk_plan* p) {
     }
   }
   for (Instance& in : p->inst) {
-    if (in.logM > kLdsMaxLog) {
+    if (in.logM > kLdsMaxLog || fast_eligible(in)) {
       const int sh = in.tw4_shift;
       const int64_t nlo = (int64_t)1 << sh, nhi = in.M >> sh;
       std::vector<double> re(nlo), im(nlo);

@@ -1,0 +1,719 @@
+// Three-pass fused Birkhoff products for N a power of two (gfx950).
+//
+// A DCT-I of length N + 1 (eq:vm=DCT-1) is half the length-2N DFT of the even extension
+// z of its input.  With 2N = L1 L2, the four-step factorisation n = L2 n1 + n2,
+// k = k1 + L1 k2 of that DFT inherits the symmetry of z:
+//   * every column n2 (z[L2 n1 + n2] over n1) is real, and column L2 - n2 is column n2
+//     reversed, so only columns 0..L2/2 are transformed -- two real columns per complex
+//     FFT of length L1 -- and only outputs k1 = 0..L1/2 are kept;
+//   * after the twiddle W_2N^(n2 k1), each row k1 is Hermitian in n2 (the output is
+//     real), so a row is rebuilt from its half and two rows share one complex FFT of
+//     length L2; rows L1 - k1 are mirror images and are never formed.
+// Both DCT-I of FastBV (B^a = (2/N) C [E^{-1} S M S E] C, see birk_dct.hip) use this
+// scheme, the second with the transposed factorisation (stride L1 first), so that the
+// rows produced by the first DCT are exactly the columns the second one needs:
+//
+//   pass A: columns of DCT 1                       x        -> G  [k1][n2]
+//   pass B: rows of DCT 1, the coefficient stencil          G -> G2 [q1][r]
+//           (eq:c_k=bydef with the alias of eq:chatk=), columns of DCT 2
+//   pass C: rows of DCT 2, plus the constant c^_0 term      G2 -> out
+//
+// The stencil couples coefficient k with k +- 1, i.e. row k1 with rows k1 +- 1, so a
+// pass-B workgroup that owns rows [t0, t0 + TB) also transforms the two neighbouring
+// rows (halo).  c^_0 (a reduction over all coefficients) only adds a constant to every
+// output (T_0 = 1), so pass B emits partial sums and pass C adds the total.  Three
+// round trips through memory per product: read x, write G, read G, write G2, read G2,
+// write out.  FFTs are radix-4/2 Stockham in LDS on split real/imaginary rows.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "birk_internal.h"
+
+namespace birk {
+
+namespace fast {
+
+template <typename T>
+__device__ __forceinline__ cplx<T> mk(T x, T y) {
+  cplx<T> r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> conjg(cplx<T> a) {
+  return mk<T>(a.x, -a.y);
+}
+
+// W_2N^t from the two-level table, t in [0, 2N)
+template <typename T>
+__device__ __forceinline__ cplx<T> tw2n(const cplx<T>* __restrict__ hi, const cplx<T>* __restrict__ lo, int sh,
+                                        int64_t t) {
+  return cmul<T>(hi[t >> sh], lo[t & ((int64_t(1) << sh) - 1)]);
+}
+
+// ---- in-register DFTs of length 2, 4, 8, 16 (forward, W_R = exp(-2 pi i / R)) ----
+// vr/vi hold the R inputs in natural order and receive the R outputs in natural order.
+template <typename T>
+__device__ __forceinline__ void dft4(T& ar, T& ai, T& br, T& bi, T& cr, T& ci, T& dr, T& di) {
+  const T t0r = ar + cr, t0i = ai + ci, t1r = ar - cr, t1i = ai - ci;
+  const T t2r = br + dr, t2i = bi + di, ur = br - dr, ui = bi - di;
+  // (b - d) * (-i) = (ui, -ur)
+  ar = t0r + t2r;
+  ai = t0i + t2i;
+  cr = t0r - t2r;
+  ci = t0i - t2i;
+  br = t1r + ui;
+  bi = t1i - ur;
+  dr = t1r - ui;
+  di = t1i + ur;
+}
+
+template <typename T>
+__device__ __forceinline__ void cmul_inplace(T& r, T& i, T wr, T wi) {
+  const T a = r * wr - i * wi;
+  i = r * wi + i * wr;
+  r = a;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_reg(T (&vr)[R], T (&vi)[R]) {
+  if constexpr (R == 2) {
+    const T ar = vr[0], ai = vi[0];
+    vr[0] = ar + vr[1];
+    vi[0] = ai + vi[1];
+    vr[1] = ar - vr[1];
+    vi[1] = ai - vi[1];
+  } else if constexpr (R == 4) {
+    dft4<T>(vr[0], vi[0], vr[1], vi[1], vr[2], vi[2], vr[3], vi[3]);
+  } else if constexpr (R == 8) {
+    // n = q + 2p, k = s + 4t: two DFT4 over p, twiddle W8^(q s), DFT2 over q
+    dft4<T>(vr[0], vi[0], vr[2], vi[2], vr[4], vi[4], vr[6], vi[6]);
+    dft4<T>(vr[1], vi[1], vr[3], vi[3], vr[5], vi[5], vr[7], vi[7]);
+    const T h = T(0.70710678118654752440);  // sqrt(1/2)
+    // q = 1 row, s = 1..3: W8^1 = (h, -h), W8^2 = (0, -1), W8^3 = (-h, -h)
+    cmul_inplace<T>(vr[3], vi[3], h, -h);
+    { const T a = vr[5]; vr[5] = vi[5]; vi[5] = -a; }
+    cmul_inplace<T>(vr[7], vi[7], -h, -h);
+    T outr[8], outi[8];
+#pragma unroll
+    for (int sI = 0; sI < 4; ++sI) {
+      const T a0r = vr[2 * sI], a0i = vi[2 * sI], a1r = vr[2 * sI + 1], a1i = vi[2 * sI + 1];
+      outr[sI] = a0r + a1r;
+      outi[sI] = a0i + a1i;
+      outr[sI + 4] = a0r - a1r;
+      outi[sI + 4] = a0i - a1i;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      vr[i] = outr[i];
+      vi[i] = outi[i];
+    }
+  } else {
+    // R == 16: n = q + 4p, k = s + 4t: four DFT4 over p, twiddle W16^(q s), four DFT4 over q
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dft4<T>(vr[q], vi[q], vr[q + 4], vi[q + 4], vr[q + 8], vi[q + 8], vr[q + 12], vi[q + 12]);
+    // element (q, s) now sits at index q + 4 s
+    const T c1 = T(0.92387953251128675613);  // cos(pi/8)
+    const T s1 = T(0.38268343236508977173);  // sin(pi/8)
+    const T h = T(0.70710678118654752440);
+    // W16^m = (cos(2 pi m/16), -sin(2 pi m/16)), m = q s
+    cmul_inplace<T>(vr[1 + 4], vi[1 + 4], c1, -s1);    // q1 s1: m1
+    cmul_inplace<T>(vr[1 + 8], vi[1 + 8], h, -h);      // q1 s2: m2
+    cmul_inplace<T>(vr[1 + 12], vi[1 + 12], s1, -c1);  // q1 s3: m3
+    cmul_inplace<T>(vr[2 + 4], vi[2 + 4], h, -h);      // q2 s1: m2
+    { const T a = vr[2 + 8]; vr[2 + 8] = vi[2 + 8]; vi[2 + 8] = -a; }  // q2 s2: m4 = -i
+    cmul_inplace<T>(vr[2 + 12], vi[2 + 12], -h, -h);   // q2 s3: m6
+    cmul_inplace<T>(vr[3 + 4], vi[3 + 4], s1, -c1);    // q3 s1: m3
+    cmul_inplace<T>(vr[3 + 8], vi[3 + 8], -h, -h);     // q3 s2: m6
+    cmul_inplace<T>(vr[3 + 12], vi[3 + 12], -c1, s1);  // q3 s3: m9
+#pragma unroll
+    for (int sI = 0; sI < 4; ++sI)
+      dft4<T>(vr[4 * sI], vi[4 * sI], vr[4 * sI + 1], vi[4 * sI + 1], vr[4 * sI + 2], vi[4 * sI + 2],
+              vr[4 * sI + 3], vi[4 * sI + 3]);
+    // element (s, t) now sits at index 4 s + t; output k = s + 4 t
+    T outr[16], outi[16];
+#pragma unroll
+    for (int sI = 0; sI < 4; ++sI)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        outr[sI + 4 * t] = vr[4 * sI + t];
+        outi[sI + 4 * t] = vi[4 * sI + t];
+      }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      vr[i] = outr[i];
+      vi[i] = outi[i];
+    }
+  }
+}
+
+// LDS rows are padded with one element after every 16 (and rows are an odd number of
+// elements apart) so that the strided accesses of the early Stockham stages and the
+// column-tile loads spread over the 64 LDS banks.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int padded_ld(int L) { return L + (L >> 4) + 1; }
+
+// One radix-R Stockham stage on `count` split-complex transforms: transform t has its
+// real part in row (first + 2t) and imaginary part in row (first + 2t + 1) of a
+// row-major array with `ld` reals per (padded) row.  Each thread owns PPT / R
+// butterflies, i.e. PPT complex values; all reads of the stage precede all writes.
+// Twiddles W_(Ns R)^(jm r) come from the table (powers 1, 2, 4, 8) and products of at
+// most three of them.
+template <typename T, int R, int PPT>
+__device__ __forceinline__ void split_stage(T* buf, int first, int ld, int logL, int count, int logNs,
+                                            const cplx<T>* __restrict__ tw) {
+  constexpr int logR = (R == 16) ? 4 : (R == 8) ? 3 : (R == 4) ? 2 : 1;
+  constexpr int NB = PPT / R;
+  const int logNb = logL - logR;
+  const int nb = 1 << logNb;
+  const int total = count << logNb;
+  const int Ns = 1 << logNs;
+  const int tshift = kLdsMaxLog - (logNs + logR);
+  T vr[NB][R], vi[NB][R];
+  int dst[NB], tt[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = threadIdx.x + i * blockDim.x;
+    dst[i] = -1;
+    tt[i] = 0;
+    if (b < total) {
+      const int t = b >> logNb;
+      const int j = b & (nb - 1);
+      const T* re = buf + (first + 2 * t) * ld;
+      const T* im = re + ld;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        vr[i][r] = re[pad(j + r * nb)];
+        vi[i][r] = im[pad(j + r * nb)];
+      }
+      const int jm = j & (Ns - 1);
+      if (jm != 0) {
+        // powers 1, 2, 4, 8 from the table; the others as products of at most three
+        const cplx<T> w1 = tw[jm << tshift];
+        cmul_inplace<T>(vr[i][1], vi[i][1], w1.x, w1.y);
+        if constexpr (R > 2) {
+          const cplx<T> w2 = tw[(2 * jm) << tshift];
+          const cplx<T> w3 = cmul<T>(w2, w1);
+          cmul_inplace<T>(vr[i][2], vi[i][2], w2.x, w2.y);
+          cmul_inplace<T>(vr[i][3], vi[i][3], w3.x, w3.y);
+          if constexpr (R > 4) {
+            const cplx<T> w4 = tw[(4 * jm) << tshift];
+            const cplx<T> w5 = cmul<T>(w4, w1), w6 = cmul<T>(w4, w2), w7 = cmul<T>(w4, w3);
+            cmul_inplace<T>(vr[i][4], vi[i][4], w4.x, w4.y);
+            cmul_inplace<T>(vr[i][5], vi[i][5], w5.x, w5.y);
+            cmul_inplace<T>(vr[i][6], vi[i][6], w6.x, w6.y);
+            cmul_inplace<T>(vr[i][7], vi[i][7], w7.x, w7.y);
+            if constexpr (R > 8) {
+              const cplx<T> w8 = tw[(8 * jm) << tshift];
+              const cplx<T> wa[8] = {w8, cmul<T>(w8, w1), cmul<T>(w8, w2), cmul<T>(w8, w3),
+                                     cmul<T>(w8, w4), cmul<T>(w8, w5), cmul<T>(w8, w6), cmul<T>(w8, w7)};
+#pragma unroll
+              for (int r = 0; r < 8; ++r) cmul_inplace<T>(vr[i][8 + r], vi[i][8 + r], wa[r].x, wa[r].y);
+            }
+          }
+        }
+      }
+      dft_reg<T, R>(vr[i], vi[i]);
+      dst[i] = ((j >> logNs) << (logNs + logR)) + jm;
+      tt[i] = t;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    if (dst[i] >= 0) {
+      T* re = buf + (first + 2 * tt[i]) * ld;
+      T* im = re + ld;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        re[pad(dst[i] + r * Ns)] = vr[i][r];
+        im[pad(dst[i] + r * Ns)] = vi[i][r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// count << logL <= PPT * blockDim.x complex points.  PPT = 16: radix-16 stages and one
+// radix-2/4/8 stage for the remainder of log2 L; PPT = 8: radix-8 stages and one
+// radix-2/4 stage.
+template <typename T, int PPT>
+__device__ void split_fft(T* buf, int first, int ld, int logL, int count, const cplx<T>* __restrict__ tw) {
+  int logNs = 0;
+  if constexpr (PPT == 16) {
+    const int rem = logL & 3;
+    if (rem == 1) {
+      split_stage<T, 2, PPT>(buf, first, ld, logL, count, 0, tw);
+      logNs = 1;
+    } else if (rem == 2) {
+      split_stage<T, 4, PPT>(buf, first, ld, logL, count, 0, tw);
+      logNs = 2;
+    } else if (rem == 3) {
+      split_stage<T, 8, PPT>(buf, first, ld, logL, count, 0, tw);
+      logNs = 3;
+    }
+    for (; logNs < logL; logNs += 4) split_stage<T, 16, PPT>(buf, first, ld, logL, count, logNs, tw);
+  } else {
+    const int rem = logL % 3;
+    if (rem == 1) {
+      split_stage<T, 2, PPT>(buf, first, ld, logL, count, 0, tw);
+      logNs = 1;
+    } else if (rem == 2) {
+      split_stage<T, 4, PPT>(buf, first, ld, logL, count, 0, tw);
+      logNs = 2;
+    }
+    for (; logNs < logL; logNs += 3) split_stage<T, 8, PPT>(buf, first, ld, logL, count, logNs, tw);
+  }
+}
+
+// Separate the DFTs of two real sequences a, b from F = DFT(a + i b):
+//   Fa[k] = (F[k] + conj F[-k]) / 2,  Fb[k] = (F[k] - conj F[-k]) / (2i)
+template <typename T>
+__device__ __forceinline__ cplx<T> separate(T fr, T fi, T mr, T mi, int second) {
+  const T h = T(0.5);
+  return second ? mk<T>(h * (fi + mi), h * (mr - fr)) : mk<T>(h * (fr + mr), h * (fi - mi));
+}
+
+// Sum over the block for any blockDim.x that is a multiple of 64 (<= 1024): wavefront
+// butterfly with shuffles, then the per-wave sums in a fixed order.  Every thread gets
+// the total.  `red` needs blockDim.x / 64 doubles.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int nw = (int)(blockDim.x >> 6);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < nw; ++i) r += red[i];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------- pass A
+// Columns n2 in [c0, c0 + W) of the even extension of x (optionally with both end
+// points doubled: the E^{-1} pre-factor of the transpose), FFT over n1, keep k1 <= L1/2,
+// twiddle W_2N^(n2 k1), store G[k1][n2] for n2 <= L2/2.
+template <typename T, int PPT>
+__global__ __launch_bounds__(512) void k_fastA(const T* __restrict__ x, int64_t Nn, int logL1, int logL2, int W,
+                        cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg, const cplx<T>* __restrict__ tw,
+                        const cplx<T>* __restrict__ thi, const cplx<T>* __restrict__ tlo, int tsh, int ends2) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* A = reinterpret_cast<T*>(smem_raw);
+  const int comp = blockIdx.y;
+  const T* xc = x + (int64_t)comp * Nn;
+  const int64_t N = Nn - 1, N2 = 2 * N;
+  const int L1 = 1 << logL1, L2 = 1 << logL2;
+  const int c0 = blockIdx.x * W;
+  const int ld1 = padded_ld(L1);
+  const int n = W << logL1;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int w = e % W, n1 = e / W;
+    const int64_t m = ((int64_t)n1 << logL2) + c0 + w;
+    const int64_t idx = m <= N ? m : N2 - m;
+    T v = xc[idx];
+    if (ends2 && (idx == 0 || idx == N)) v *= T(2);
+    A[w * ld1 + pad(n1)] = v;
+  }
+  __syncthreads();
+  split_fft<T, PPT>(A, 0, ld1, logL1, W / 2, tw);
+  const int half1 = L1 / 2;
+  cplx<T>* Gc = G + (int64_t)comp * gcomp;
+  const int nout = (half1 + 1) * W;
+  for (int e = threadIdx.x; e < nout; e += blockDim.x) {
+    const int w = e % W, k1 = e / W;
+    const int n2 = c0 + w;
+    if (n2 > L2 / 2) continue;
+    const T* re = A + (w & ~1) * ld1;
+    const T* im = re + ld1;
+    const int km = (L1 - k1) & (L1 - 1);
+    const cplx<T> v = separate<T>(re[pad(k1)], im[pad(k1)], re[pad(km)], im[pad(km)], w & 1);
+    Gc[(int64_t)k1 * sg + n2] = cmul<T>(v, tw2n<T>(thi, tlo, tsh, (int64_t)n2 * k1));
+  }
+}
+
+// ---------------------------------------------------------------- pass B
+// Value at n2 <= L2/2 of the Hermitian row that reproduces Y_ext[k1 + L1 m] (m in
+// [0, L2)) for any k1 in [-1, L1): rows 0..L1/2 are stored; row -1 is row 1 read
+// backwards (conjugate input); rows above L1/2 are mirrors of row L1 - k1 read
+// backwards with a shift of one (conjugate input times W_L2^n2).
+template <typename T>
+__device__ __forceinline__ cplx<T> hrow(const cplx<T>* __restrict__ Gc, int64_t sg, int k1, int L1, int n2,
+                                        int logL2, const cplx<T>* __restrict__ tw) {
+  if (k1 < 0) return conjg<T>(Gc[sg + n2]);
+  if (k1 <= L1 / 2) return Gc[(int64_t)k1 * sg + n2];
+  const cplx<T> v = conjg<T>(Gc[(int64_t)(L1 - k1) * sg + n2]);
+  return cmul<T>(v, tw[n2 << (kLdsMaxLog - logL2)]);
+}
+
+// Forward stencil (FastBV step 2 with the reversals folded into signs):
+//   d_k = (-1)^k c^_k / e_k with c^ from eq:c_k=bydef and eq:chatk= applied to the
+//   Chebyshev coefficients a_k = (-1)^k e_k Y_k / N; d_0 is deferred (c^_0 term).
+template <typename T>
+__device__ __forceinline__ T stencil_fwd(int64_t k, int64_t N, T Ym, T Yp) {
+  if (k == 0) return T(0);
+  const T invN = T(1) / T(N);
+  const T lo = (k == 1) ? T(1) : T(1) / (T(2) * T(k));
+  const T em1 = (k == 1) ? T(0.5) : T(1);
+  T r = -lo * em1 * Ym;
+  if (k < N) {
+    const T ep1 = (k + 1 == N) ? T(0.5) : T(1);
+    r += ep1 * Yp / (T(2) * T(k));
+  }
+  if (k == N - 1) r -= Yp / (T(4) * T(N + 1));
+  const T ek = (k == N) ? T(0.5) : T(1);
+  return r * invN / ek;
+}
+
+// Transpose stencil: q = S M^T S p with p = Y / 2 (see birk_dct.hip, k_mid_tr).
+template <typename T>
+__device__ __forceinline__ T stencil_tr(int64_t j, int64_t N, T Y0, T Ym, T Yp, T p0) {
+  const T h = T(0.5);
+  if (j == 0) return p0 - h * Yp;
+  if (j == 1) return T(0.25) * (p0 - h * Yp);
+  const T jj = T(j);
+  T cm = T(1) / (T(2) * (jj - T(1)));
+  if (j == N) cm -= T(1) / (T(2) * T(N + 1));
+  T q = -p0 / (jj * jj - T(1)) + cm * h * Ym;
+  if (j < N) q -= h * Yp / (T(2) * (jj + T(1)));
+  (void)Y0;
+  return q;
+}
+
+// c^_0 = (1/N) [ e_0 Y_0 + Y_1 / 4 - sum_{k >= 2} e_k Y_k / (k^2 - 1) ]
+__device__ __forceinline__ double c0_coef(int64_t k, int64_t N) {
+  if (k == 0) return 0.5;
+  if (k == 1) return 0.25;
+  const double ek = (k == N) ? 0.5 : 1.0;
+  return -ek / ((double)k * (double)k - 1.0);
+}
+
+template <typename T, int TB, int TRANS, int PPT>
+__global__ __launch_bounds__(512) void k_fastB(const cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg, cplx<T>* __restrict__ G2,
+                        int64_t g2comp, int64_t sg2, int64_t N, int logL1, int logL2,
+                        const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ thi,
+                        const cplx<T>* __restrict__ tlo, int tsh, double* __restrict__ part) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Y = reinterpret_cast<T*>(smem_raw);  // (TB + 2) real rows of L2
+  __shared__ double red[16];
+  const int comp = blockIdx.y;
+  const int L1 = 1 << logL1, L2 = 1 << logL2;
+  const int half2 = L2 / 2;
+  const int t0 = blockIdx.x * TB;
+  const int ld2 = padded_ld(L2);
+  const cplx<T>* Gc = G + (int64_t)comp * gcomp;
+  constexpr int NR = TB + 2;
+  // rows rho = 0..TB+1 <-> k1 = t0 - 1 + rho; pairs (2i, 2i+1) share one complex FFT
+  const int nin = (NR / 2) * (half2 + 1);
+  for (int e = threadIdx.x; e < nin; e += blockDim.x) {
+    const int pr = e / (half2 + 1), n2 = e % (half2 + 1);
+    const cplx<T> ra = hrow<T>(Gc, sg, t0 - 1 + 2 * pr, L1, n2, logL2, tw);
+    const cplx<T> rb = hrow<T>(Gc, sg, t0 + 2 * pr, L1, n2, logL2, tw);
+    T* re = Y + (2 * pr) * ld2;
+    T* im = re + ld2;
+    re[pad(n2)] = ra.x - rb.y;
+    im[pad(n2)] = ra.y + rb.x;
+    if (n2 > 0 && n2 < half2) {
+      re[pad(L2 - n2)] = ra.x + rb.y;
+      im[pad(L2 - n2)] = rb.x - ra.y;
+    }
+  }
+  T p0 = T(0);
+  if (TRANS) {
+    // Y_0 of the first DCT is the sum of row 0 of the Hermitian G: p_0 = Y_0 / 2
+    double acc = 0.0;
+    for (int n2 = threadIdx.x; n2 <= half2; n2 += blockDim.x)
+      acc += (double)Gc[n2].x * ((n2 == 0 || n2 == half2) ? 1.0 : 2.0);
+    p0 = (T)(0.5 * block_sum(acc, red));
+  }
+  __syncthreads();
+  split_fft<T, PPT>(Y, 0, ld2, logL2, NR / 2, tw);
+  // stencil, one thread per m (owns column m of the tile: no cross-thread hazard)
+  double c0acc = 0.0;
+  const int64_t N2 = 2 * N;
+  for (int m = threadIdx.x; m < L2; m += blockDim.x) {
+    T yv[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) yv[r] = Y[r * ld2 + pad(m)];
+#pragma unroll
+    for (int r = 1; r <= TB; ++r) {
+      const int k1 = t0 - 1 + r;
+      const int64_t K = (int64_t)k1 + (int64_t)L1 * m;
+      const bool lowhalf = K <= N;
+      const int64_t k = lowhalf ? K : N2 - K;
+      const T Ym = lowhalf ? yv[r - 1] : yv[r + 1];
+      const T Yp = lowhalf ? yv[r + 1] : yv[r - 1];
+      T d;
+      if (TRANS) {
+        d = stencil_tr<T>(k, N, yv[r], Ym, Yp, p0);
+      } else {
+        d = stencil_fwd<T>(k, N, Ym, Yp);
+        if (k1 <= L1 / 2 && ((k1 != 0 && k1 != L1 / 2) || lowhalf)) c0acc += c0_coef(k, N) * (double)yv[r];
+      }
+      Y[r * ld2 + pad(m)] = d;
+    }
+  }
+  if (!TRANS) {
+    const double tot = block_sum(c0acc, red);
+    if (threadIdx.x == 0) part[(int64_t)comp * gridDim.x + blockIdx.x] = tot;
+  }
+  __syncthreads();
+  // columns of the second DCT: d rows (1 + 2i, 2 + 2i) as one complex FFT each
+  split_fft<T, PPT>(Y, 1, ld2, logL2, TB / 2, tw);
+  cplx<T>* G2c = G2 + (int64_t)comp * g2comp;
+  const int nout = (half2 + 1) * TB;
+  for (int e = threadIdx.x; e < nout; e += blockDim.x) {
+    const int rl = e % TB, q = e / TB;
+    const int r = t0 + rl;
+    if (r > L1 / 2) continue;
+    const T* re = Y + (1 + (rl & ~1)) * ld2;
+    const T* im = re + ld2;
+    const int qm = (L2 - q) & (L2 - 1);
+    const cplx<T> v = separate<T>(re[pad(q)], im[pad(q)], re[pad(qm)], im[pad(qm)], rl & 1);
+    G2c[(int64_t)q * sg2 + r] = cmul<T>(v, tw2n<T>(thi, tlo, tsh, (int64_t)r * q));
+  }
+}
+
+// ---------------------------------------------------------------- pass C
+// Rows q1 in [c0, c0 + W) of the second DCT (Hermitian in r, rebuilt from r <= L1/2),
+// two per complex FFT of length L1, written to the natural output positions
+// j = q1 + L2 q2 and, for 0 < q1 < L2/2, the mirrored j = (L2 - q1) + L2 q2.
+template <typename T, int TRANS, int PPT>
+__global__ __launch_bounds__(512) void k_fastC(const cplx<T>* __restrict__ G2, int64_t g2comp, int64_t sg2, T* __restrict__ out,
+                        int64_t Nn, int logL1, int logL2, int W, const cplx<T>* __restrict__ tw,
+                        const double* __restrict__ part, int ntB) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* U = reinterpret_cast<T*>(smem_raw);  // W real rows of L1
+  __shared__ double red[16];
+  const int comp = blockIdx.y;
+  const int L1 = 1 << logL1, L2 = 1 << logL2;
+  const int half1 = L1 / 2, half2 = L2 / 2;
+  const int64_t N = Nn - 1;
+  const int c0 = blockIdx.x * W;
+  const int ld1 = padded_ld(L1);
+  T c0hat = T(0);
+  if (!TRANS) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < ntB; i += blockDim.x) acc += part[(int64_t)comp * ntB + i];
+    c0hat = (T)(block_sum(acc, red) / (double)N);
+  }
+  const cplx<T>* G2c = G2 + (int64_t)comp * g2comp;
+  const int nin = (W / 2) * (half1 + 1);
+  for (int e = threadIdx.x; e < nin; e += blockDim.x) {
+    const int pr = e / (half1 + 1), r = e % (half1 + 1);
+    const int qa = c0 + 2 * pr, qb = qa + 1;
+    const cplx<T> ra = qa <= half2 ? G2c[(int64_t)qa * sg2 + r] : mk<T>(T(0), T(0));
+    const cplx<T> rb = qb <= half2 ? G2c[(int64_t)qb * sg2 + r] : mk<T>(T(0), T(0));
+    T* re = U + (2 * pr) * ld1;
+    T* im = re + ld1;
+    re[pad(r)] = ra.x - rb.y;
+    im[pad(r)] = ra.y + rb.x;
+    if (r > 0 && r < half1) {
+      re[pad(L1 - r)] = ra.x + rb.y;
+      im[pad(L1 - r)] = rb.x - ra.y;
+    }
+  }
+  __syncthreads();
+  split_fft<T, PPT>(U, 0, ld1, logL1, W / 2, tw);
+  T* oc = out + (int64_t)comp * Nn;
+  const T invN = T(1) / T(N);
+  const int nout = W * (half1 + 1);
+  for (int e = threadIdx.x; e < nout; e += blockDim.x) {
+    const int w = e % W, q2 = e / W;
+    const int q1 = c0 + w;
+    if (q1 > half2) continue;
+    const T* row = U + w * ld1;
+    if (q2 < half1 || (q1 == 0 && q2 == half1)) {
+      const int64_t j = (int64_t)q1 + (int64_t)L2 * q2;
+      const T u = row[pad(q2)];
+      T o;
+      if (TRANS) o = ((j == 0 || j == N) ? T(0.5) : T(1)) * u * invN;
+      else o = T(0.5) * u + c0hat;
+      oc[j] = o;
+    }
+    if (q1 > 0 && q1 < half2 && q2 < half1) {
+      const int64_t j = (int64_t)(L2 - q1) + (int64_t)L2 * q2;
+      const T u = row[pad(L1 - 1 - q2)];
+      T o;
+      if (TRANS) o = u * invN;
+      else o = T(0.5) * u + c0hat;
+      oc[j] = o;
+    }
+  }
+}
+
+}  // namespace fast
+
+// ---------------------------------------------------------------- host side
+
+// Shape of the fast path for one instance and precision (chosen at plan creation).
+bool fast_eligible(const Instance& in) {
+  const int64_t N = in.N;
+  if (N < 512 || (N & (N - 1)) != 0) return false;
+  int s = 0;
+  while ((int64_t(1) << s) < 2 * N) ++s;
+  return s <= 2 * kLdsMaxLog;
+}
+
+template <typename T>
+static void fast_shape(const birk_plan* p, const Instance& in, int& logL1, int& logL2, int& WA, int& TB, int& WC) {
+  int s = 0;
+  while ((int64_t(1) << s) < 2 * in.N) ++s;
+  if (p->fast_split == 0) {
+    logL2 = (s + 1) / 2;  // rows of the first DCT (pass B) are the longer side
+    logL1 = s - logL2;
+  } else {
+    logL1 = (s + 1) / 2;
+    logL2 = s - logL1;
+  }
+  const int kb = p->fast_lds_kb[std::is_same<T, double>::value ? 0 : 1];
+  const int budget = (int)((int64_t)kb * 1024 / sizeof(T));  // reals of LDS per workgroup
+  const int L1 = 1 << logL1, L2 = 1 << logL2;
+  WA = std::max(2, std::min(16, budget / fast::padded_ld(L1))) & ~1;
+  WC = WA;
+  const int rows = std::max(4, std::min(16, budget / fast::padded_ld(L2)));
+  TB = std::max(2, (rows - 2) & ~1);
+  // the halo rows of a pass-B tile must stay inside [-1, L1)
+  while (TB > 2 && TB > L1 / 2 - 2) TB -= 2;
+  // at most PPT complex points per thread of a 512-thread workgroup
+  const int maxpts = 512 * p->fast_ppt;
+  while (WA > 2 && WA * L1 / 2 > maxpts) WA -= 2;
+  while (WC > 2 && WC * L1 / 2 > maxpts) WC -= 2;
+  while (TB > 2 && (TB + 2) * L2 / 2 > maxpts) TB -= 2;
+}
+
+// Threads per workgroup: one per PPT complex points of the largest split_fft call.
+static int threads_for(int complex_points, int ppt) {
+  int t = (complex_points + ppt - 1) / ppt;
+  t = (t + 63) / 64 * 64;
+  return std::max(64, std::min(512, t));
+}
+
+template <typename F>
+static void lds_attr(F f, int bytes) {
+  (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <typename T, int PPT>
+static void launch_A(dim3 grid, int thr, int lds, hipStream_t s, const T* x, int64_t Nn, int logL1, int logL2, int W,
+                     cplx<T>* G, int64_t gcomp, int64_t sg, const cplx<T>* tw, const cplx<T>* thi,
+                     const cplx<T>* tlo, int tsh, int ends2) {
+  auto f = fast::k_fastA<T, PPT>;
+  lds_attr(f, lds);
+  hipLaunchKernelGGL(f, grid, dim3(thr), lds, s, x, Nn, logL1, logL2, W, G, gcomp, sg, tw, thi, tlo, tsh, ends2);
+}
+
+template <typename T, int TB, int TRANS, int PPT>
+static void launch_B(dim3 grid, int thr, int lds, hipStream_t s, const cplx<T>* G, int64_t gcomp, int64_t sg,
+                     cplx<T>* G2, int64_t g2comp, int64_t sg2, int64_t N, int logL1, int logL2, const cplx<T>* tw,
+                     const cplx<T>* thi, const cplx<T>* tlo, int tsh, double* part) {
+  auto f = fast::k_fastB<T, TB, TRANS, PPT>;
+  lds_attr(f, lds);
+  hipLaunchKernelGGL(f, grid, dim3(thr), lds, s, G, gcomp, sg, G2, g2comp, sg2, N, logL1, logL2, tw, thi, tlo, tsh,
+                     part);
+}
+
+template <typename T, int TRANS, int PPT>
+static void launch_C(dim3 grid, int thr, int lds, hipStream_t s, const cplx<T>* G2, int64_t g2comp, int64_t sg2,
+                     T* out, int64_t Nn, int logL1, int logL2, int W, const cplx<T>* tw, const double* part,
+                     int ntB) {
+  auto f = fast::k_fastC<T, TRANS, PPT>;
+  lds_attr(f, lds);
+  hipLaunchKernelGGL(f, grid, dim3(thr), lds, s, G2, g2comp, sg2, out, Nn, logL1, logL2, W, tw, part, ntB);
+}
+
+template <typename T, int PPT>
+static hipError_t fast_product_ppt(birk_plan* p, const Instance& in, const T* v, T* out, int transpose,
+                                   hipStream_t s) {
+  const int pi = std::is_same<T, double>::value ? 0 : 1;
+  int logL1, logL2, WA, TB, WC;
+  fast_shape<T>(p, in, logL1, logL2, WA, TB, WC);
+  const int L1 = 1 << logL1, L2 = 1 << logL2;
+  const int ld1 = fast::padded_ld(L1), ld2 = fast::padded_ld(L2);
+  const int64_t sg = L2 / 2 + 1, sg2 = L1 / 2 + 1;
+  const int64_t gcomp = (int64_t)(L1 / 2 + 1) * sg, g2comp = (int64_t)(L2 / 2 + 1) * sg2;
+  cplx<T>* G = (cplx<T>*)p->work[0] + in.work_off;
+  cplx<T>* G2 = (cplx<T>*)p->work[1] + in.work_off;
+  double* part = p->partials + in.part_off;
+  const cplx<T>* tw = (const cplx<T>*)p->lds_tw[pi];
+  const cplx<T>* thi = (const cplx<T>*)in.tab[pi].tw4_hi;
+  const cplx<T>* tlo = (const cplx<T>*)in.tab[pi].tw4_lo;
+  const int tsh = in.tw4_shift;
+  const int nc = in.nx;
+  {
+    const int ntA = (L2 / 2 + 1 + WA - 1) / WA;
+    const int lds = WA * ld1 * (int)sizeof(T);
+    launch_A<T, PPT>(dim3(ntA, nc), threads_for(WA * L1 / 2, PPT), lds, s, v + in.off, in.Nn, logL1, logL2, WA, G,
+                     gcomp, sg, tw, thi, tlo, tsh, transpose ? 1 : 0);
+  }
+  const int ntB = (L1 / 2 + 1 + TB - 1) / TB;
+  {
+    const int lds = (TB + 2) * ld2 * (int)sizeof(T);
+    const int thr = threads_for((TB + 2) * L2 / 2, PPT);
+    const dim3 grid(ntB, nc);
+#define BIRK_LB(tb)                                                                                                \
+  case tb:                                                                                                         \
+    if (transpose)                                                                                                 \
+      launch_B<T, tb, 1, PPT>(grid, thr, lds, s, G, gcomp, sg, G2, g2comp, sg2, in.N, logL1, logL2, tw, thi, tlo,  \
+                              tsh, part);                                                                          \
+    else                                                                                                           \
+      launch_B<T, tb, 0, PPT>(grid, thr, lds, s, G, gcomp, sg, G2, g2comp, sg2, in.N, logL1, logL2, tw, thi, tlo,  \
+                              tsh, part);                                                                          \
+    break;
+    switch (TB) {
+      BIRK_LB(2)
+      BIRK_LB(4)
+      BIRK_LB(6)
+      BIRK_LB(8)
+      BIRK_LB(10)
+      BIRK_LB(12)
+      BIRK_LB(14)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef BIRK_LB
+  }
+  {
+    const int ntC = (L2 / 2 + 1 + WC - 1) / WC;
+    const int lds = WC * ld1 * (int)sizeof(T);
+    const int thr = threads_for(WC * L1 / 2, PPT);
+    T* o = out + in.off;
+    if (transpose)
+      launch_C<T, 1, PPT>(dim3(ntC, nc), thr, lds, s, G2, g2comp, sg2, o, in.Nn, logL1, logL2, WC, tw, part, ntB);
+    else
+      launch_C<T, 0, PPT>(dim3(ntC, nc), thr, lds, s, G2, g2comp, sg2, o, in.Nn, logL1, logL2, WC, tw, part, ntB);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fast_product(birk_plan* p, const Instance& in, const T* v, T* out, int transpose, hipStream_t s) {
+  return p->fast_ppt == 8 ? fast_product_ppt<T, 8>(p, in, v, out, transpose, s)
+                          : fast_product_ppt<T, 16>(p, in, v, out, transpose, s);
+}
+
+// Work (complex elements per buffer) and partials (doubles) the fast path needs.
+void fast_sizes(const birk_plan* p, const Instance& in, int64_t* work, int64_t* part) {
+  int l1f, l2f, waf, tbf, wcf, l1d, l2d, wad, tbd, wcd;
+  fast_shape<float>(p, in, l1f, l2f, waf, tbf, wcf);
+  fast_shape<double>(p, in, l1d, l2d, wad, tbd, wcd);
+  const int64_t L1 = int64_t(1) << l1f, L2 = int64_t(1) << l2f;
+  *work = (int64_t)in.nx * (L1 / 2 + 1) * (L2 / 2 + 1);
+  const int64_t ntB = std::max((L1 / 2 + 1 + tbf - 1) / tbf, ((int64_t(1) << l1d) / 2 + 1 + tbd - 1) / tbd);
+  *part = (int64_t)in.nx * ntB;
+}
+
+template hipError_t fast_product<double>(birk_plan*, const Instance&, const double*, double*, int, hipStream_t);
+template hipError_t fast_product<float>(birk_plan*, const Instance&, const float*, float*, int, hipStream_t);
+
+}  // namespace birk

@@ -79,6 +79,10 @@ struct birk_plan {
   double* krylov_dots = nullptr;  // [batch][2][kKryMaxDots + 1]
   double* krylov_part = nullptr;  // reduction partials
   int* flag = nullptr;            // device flag: singular pivot seen
+  int use_fast = 1;               // power-of-two N takes the three-pass path
+  int fast_lds_kb[2] = {128, 64};  // LDS budget per workgroup of the three-pass kernels [double, float]
+  int fast_ppt = 8;               // complex points per thread in the three-pass FFTs (8 or 16)
+  int fast_split = 0;             // 0: rows of the first DCT are the longer side (L2 >= L1); 1: L1 >= L2
 };
 
 namespace birk {
@@ -92,6 +96,12 @@ template <typename T>
 hipError_t apply_product(birk_plan* p, const T* v, T* out, int transpose, hipStream_t s);
 
 hipError_t build_tables(birk_plan* p);
+
+// ---- power-of-two three-pass path (birk_fast.hip) ----
+bool fast_eligible(const Instance& in);
+template <typename T>
+hipError_t fast_product(birk_plan* p, const Instance& in, const T* v, T* out, int transpose, hipStream_t s);
+void fast_sizes(const birk_plan* p, const Instance& in, int64_t* work, int64_t* part);
 
 // ---- preconditioner, Jacobian products and Krylov kernels (birk_solve.hip) ----
 template <typename T>

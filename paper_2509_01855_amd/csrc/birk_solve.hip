@@ -167,16 +167,15 @@ hipError_t precond_forward(birk_plan* p, int jac_kind, const double* J, const T*
 // ------------------------------------------------------------------ P^{-1} y (inverse)
 
 // Unpivoted LU of K = I - (w/2) Jk in place, with reciprocal pivots.  K is strongly
-// diagonally dominant on the configurations of interest (w_k <= ~pi/N).  A zero or
-// non-finite pivot sets *flag.
+// diagonally dominant on the configurations of interest (w_k <= ~pi/N).  A pivot that
+// is non-finite, or not above 1e-13 times the scale 1 + |w/2| max|J_k| of K, marks K as
+// numerically singular in *flag.
 template <int NX>
-__device__ __forceinline__ void lu_kmat(double (&K)[NX][NX], double (&rp)[NX], int* flag) {
+__device__ __forceinline__ void lu_kmat(double (&K)[NX][NX], double (&rp)[NX], int* flag, double scale) {
 #pragma unroll
   for (int p = 0; p < NX; ++p) {
     const double piv = K[p][p];
-    if (!(fabs(piv) > 1e-300) || !isfinite(piv)) {
-      if (flag) atomicOr(flag, 1);
-    }
+    if (flag && (!(fabs(piv) > 1e-13 * scale) || !isfinite(piv))) atomicOr(flag, 1);
     rp[p] = 1.0 / piv;
 #pragma unroll
     for (int i = p + 1; i < NX; ++i) {
@@ -241,7 +240,12 @@ __global__ __launch_bounds__(256) void k_pinv_up0(const double* __restrict__ J, 
     load_jk<NX>(J, per_node, Nn, k, Jk);
     const double wk = w[k];
     form_k<NX>(Jk, wk, K);
-    lu_kmat<NX>(K, rp, flag);
+    double jmax = 0.0;
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int q = 0; q < NX; ++q) jmax = fmax(jmax, fabs(Jk[r][q]));
+    lu_kmat<NX>(K, rp, flag, 1.0 + 0.5 * fabs(wk) * jmax);
     // b <- b + wk Jk K^{-1} (b + y_k)
     double x[NX];
 #pragma unroll
@@ -402,7 +406,7 @@ __global__ __launch_bounds__(256) void k_pinv_final(const double* __restrict__ J
     load_jk<NX>(J, per_node, Nn, k, Jk);
     const double wk = w[k];
     form_k<NX>(Jk, wk, K);
-    lu_kmat<NX>(K, rp, nullptr);
+    lu_kmat<NX>(K, rp, nullptr, 1.0);
     double x[NX];
 #pragma unroll
     for (int r = 0; r < NX; ++r) x[r] = s[r] + (double)y[(int64_t)r * Nn + k];

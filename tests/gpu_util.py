@@ -23,9 +23,13 @@ def dense_Ba(N):
 
 
 def rel_err(got, ref):
+    """max |got - ref| / max |ref| (also printed with the normwise error for the log)."""
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
-    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+    e = float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+    e2 = float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+    print(f"  max-rel {e:.3e}  norm-rel {e2:.3e}", flush=True)
+    return e
 
 
 def announce(msg):

@@ -1,6 +1,10 @@
 """GPU parity of birk_apply / birk_apply_T (FastBV and its transpose) against the FP64
 oracle, through the C ABI.
 
+References: the extended-precision (80-bit) evaluation of the oracle's modal
+definition at N <= 4096, exact sparse-mode antiderivatives and O(N log N) rows at
+larger N.
+
 Tolerances (relative to max |reference|):
 * double: 1e-12, the accuracy target for the FP64 path.  Two FFT-based DCT-I of
   length <= 2^21 accumulate roughly 2 * c * log2(M) * eps64 ~ 1e-14; 1e-12 leaves room.
@@ -54,8 +58,7 @@ def test_product_dense(B, Nn, transpose, prec):
     X = wl.random_vectors([1, Nn], (nx, Nn))[0]
     p = B.BIRK_F64 if prec == "f64" else B.BIRK_F32
     got = _run(B, [Nn], [nx], p, X.ravel(), transpose).reshape(nx, Nn)
-    Ba = dense_Ba(N)
-    ref = X @ (Ba if transpose else Ba.T)
+    ref = bk.apply_Ba_extended(N, X, transpose=bool(transpose))
     assert rel_err(got, ref) <= TOL[prec]
 
 
@@ -69,8 +72,7 @@ def test_product_batched_instances(B):
         got = _run(B, Nn_list, nx_list, B.BIRK_F64, flat, transpose)
         o = 0
         for X, Nn, nx in zip(Xs, Nn_list, nx_list):
-            Ba = dense_Ba(Nn - 1)
-            ref = X @ (Ba if transpose else Ba.T)
+            ref = bk.apply_Ba_extended(Nn - 1, X, transpose=bool(transpose))
             assert rel_err(got[o:o + nx * Nn].reshape(nx, Nn), ref) <= TOL["f64"]
             o += nx * Nn
 
@@ -135,3 +137,22 @@ def test_weights(B, Nn):
     ref = bk.cc_weights_closed_form(N) if Nn <= 4097 else bk.ba_row(N, N)
     assert np.max(np.abs(w - ref)) <= 1e-15 * 50 + 1e-12 * np.max(np.abs(ref))
     assert abs(w.sum() - 2.0) <= 1e-12
+
+
+@pytest.mark.parametrize("Nn", [513, 1025, 4097, (1 << 16) + 1])
+def test_general_path_matches_fast_path(B, Nn, monkeypatch):
+    """Power-of-two N normally takes the three-pass path; BIRK_FAST=0 at plan creation
+    routes it through the general FFT path.  Both must agree with the oracle."""
+    nx = 3
+    X = wl.random_vectors([3, Nn], (nx, Nn))[0]
+    announce(f"general vs fast Nn={Nn}")
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BIRK_FAST", flag)
+        outs.append([_run(B, [Nn], [nx], B.BIRK_F64, X.ravel(), t) for t in (0, 1)])
+    for t in (0, 1):
+        assert rel_err(outs[0][t], outs[1][t]) <= 1e-12
+    if Nn <= 4097:
+        ref = bk.apply_Ba_extended(Nn - 1, X)
+        assert rel_err(outs[1][0].reshape(nx, Nn), ref) <= TOL["f64"]
+        assert rel_err(outs[0][0].reshape(nx, Nn), ref) <= TOL["f64"]

@@ -305,3 +305,30 @@ def test_condition_number_is_order_one():
         inst = wl.lti_instance(0, N_n)
         ks.append(np.linalg.cond(sy.dense_A(N_n - 1, inst.J)))
     assert max(ks) < 20.0 and max(ks) / min(ks) < 1.5, ks
+
+
+# ---------------------------------------------------------------- extended-precision products
+@pytest.mark.parametrize("N", [2, 9, 64, 255])
+def test_extended_products_match_quadrature_construction(N):
+    X = np.random.default_rng(N).standard_normal((3, N + 1))
+    B1 = bk.dense_Ba_quadrature(N)
+    assert np.max(np.abs(bk.apply_Ba_extended(N, X) - X @ B1.T)) <= 1e-13
+    assert np.max(np.abs(bk.apply_Ba_extended(N, X, transpose=True) - X @ B1)) <= 1e-13
+
+
+def test_extended_products_match_rows_at_3000():
+    """At N = 2999 the extended evaluation and the O(N log N) row route agree to ~1e-15,
+    which the double dense matrix (LAPACK inverse + O(N^3) product) does not reach."""
+    N = 2999
+    X = np.random.default_rng(1).standard_normal((2, N + 1))
+    R = np.array([bk.ba_row(N, i) for i in range(N + 1)])
+    for tr, ref in ((False, X @ R.T), (True, X @ R)):
+        e = bk.apply_Ba_extended(N, X, transpose=tr)
+        assert np.max(np.abs(e - ref)) / np.max(np.abs(e)) <= 1e-14
+
+
+def test_extended_products_exact_on_modes():
+    N = 200
+    modes, alphas = wl.sparse_modes(3, N, count=20)
+    v = bk.sparse_mode_values(N, modes, alphas)
+    assert np.max(np.abs(bk.apply_Ba_extended(N, v)[0] - bk.sparse_mode_exact(N, modes, alphas))) <= 1e-15
