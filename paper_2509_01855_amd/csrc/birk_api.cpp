@@ -70,6 +70,7 @@ void free_plan(birk_plan* p) {
   for (void* q : p->lds_tw) if (q) (void)hipFree(q);
   if (p->partials) (void)hipFree(p->partials);
   if (p->scan) (void)hipFree(p->scan);
+  if (p->jsw) (void)hipFree(p->jsw);
   if (p->krylov_Q) (void)hipFree(p->krylov_Q);
   if (p->krylov_vec) (void)hipFree(p->krylov_vec);
   if (p->krylov_dots) (void)hipFree(p->krylov_dots);
@@ -163,7 +164,7 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     if (pp) p->fast_ppt = std::atoi(pp) == 16 ? 16 : 8;
   }
   p->inst.resize(batch);
-  int64_t off = 0, joff = 0, jcoff = 0, woff = 0, poff = 0, soff = 0;
+  int64_t off = 0, joff = 0, jcoff = 0, woff = 0, poff = 0, soff = 0, jswoff = 0;
   for (int i = 0; i < batch; ++i) {
     Instance& in = p->inst[i];
     in.Nn = n_nodes_host[i];
@@ -204,6 +205,8 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     woff += wneed;
     poff += pneed;
     soff += pinv_scratch(in.Nn, in.nx) + (int64_t)in.nx * ((in.Nn + 1023) / 1024) + 64;
+    in.jsw_off = jswoff;
+    jswoff += pinv_jsw_size(in.Nn, in.nx);
   }
   p->total_len = off;
   p->total_jnode = joff;
@@ -211,12 +214,14 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
   p->total_work = woff;
   p->total_part = poff;
   p->total_scan = soff;
+  p->total_jsw = jswoff;
 
   hipError_t e = hipSuccess;
   for (int b = 0; b < 3 && e == hipSuccess; ++b) e = hipMalloc(&p->work[b], woff * sizeof(double2));
   for (int b = 0; b < 4 && e == hipSuccess; ++b) e = hipMalloc(&p->tmp_vec[b], off * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&p->partials, std::max<int64_t>(poff, 1) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&p->scan, std::max<int64_t>(soff, 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&p->jsw, std::max<int64_t>(jswoff, 1) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&p->flag, sizeof(int));
   for (int i = 0; i < batch && e == hipSuccess; ++i) e = hipMalloc(&p->inst[i].w, p->inst[i].Nn * sizeof(double));
   if (e == hipSuccess) e = build_tables(p);
@@ -300,6 +305,10 @@ birk_status birk_precond(birk_plan* p, birk_jac_kind jk, const double* J, const 
   if (inverse && !nx_ok_for_precond(p)) return BIRK_ERR_UNSUPPORTED;
   DeviceGuard g(p->device);
   hipError_t e;
+  if (inverse) {
+    e = precond_prepare(p, jk, J, p->prec == BIRK_F64 ? 0 : 1, p->stream);
+    if (e != hipSuccess) return BIRK_ERR_DEVICE;
+  }
   if (p->prec == BIRK_F64) {
     e = inverse ? precond_inverse<double>(p, jk, J, (const double*)y, (double*)out, nullptr, p->stream, nullptr)
                 : precond_forward<double>(p, jk, J, (const double*)y, (double*)out, p->stream);
@@ -558,6 +567,7 @@ extern "C" birk_status birk_krylov_solve(birk_plan* p, birk_jac_kind jk, const d
   hipError_t e = ensure_krylov(p, o.restart, mixed ? sizeof(float) : sizeof(double));
   if (e != hipSuccess) return dev_err(e);
   if (hipMemsetAsync(p->flag, 0, sizeof(int), s) != hipSuccess) return BIRK_ERR_DEVICE;
+  if (o.use_precond && precond_prepare(p, jk, J, mixed ? 1 : 0, s) != hipSuccess) return BIRK_ERR_DEVICE;
   if (!o.use_x0 && hipMemsetAsync(chi, 0, n * sizeof(double), s) != hipSuccess) return BIRK_ERR_DEVICE;
 
   std::vector<InstState> st(B);
@@ -571,10 +581,15 @@ extern "C" birk_status birk_krylov_solve(birk_plan* p, birk_jac_kind jk, const d
   double* r = (double*)p->tmp_vec[0];
   double* t = (double*)p->tmp_vec[1];
   for (int outer = 0;; ++outer) {
-    // true residual r = beta - A chi in double
-    e = fast_ax_f64(p, jk, J, chi, t);
-    if (e != hipSuccess) return BIRK_ERR_DEVICE;
-    kry::residual(beta, chi, t, r, n, s);
+    // true residual r = beta - A chi in double (chi = 0 on the first step without x0: r = beta)
+    if (outer == 0 && !o.use_x0) {
+      if (hipMemcpyAsync(r, beta, n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return BIRK_ERR_DEVICE;
+    } else {
+      e = fast_ax_f64(p, jk, J, chi, t);
+      if (e != hipSuccess) return BIRK_ERR_DEVICE;
+      kry::residual(beta, chi, t, r, n, s);
+    }
     std::vector<double> rn;
     if (seg_norms(p, r, rn) != hipSuccess) return BIRK_ERR_DEVICE;
     bool all_done = true;

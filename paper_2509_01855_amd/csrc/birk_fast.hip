@@ -245,11 +245,12 @@ __device__ __forceinline__ void split_stage(T* buf, int first, int ld, int logL,
   __syncthreads();
 }
 
-// count << logL <= PPT * blockDim.x complex points.  PPT = 16: radix-16 stages and one
-// radix-2/4/8 stage for the remainder of log2 L; PPT = 8: radix-8 stages and one
-// radix-2/4 stage.
+// `count` transforms of length 2^logL, processed in chunks of whole transforms that fit
+// PPT * blockDim.x complex points (2^logL itself must fit).  PPT = 16: radix-16 stages
+// and one radix-2/4/8 stage for the remainder of log2 L; PPT = 8: radix-8 stages and
+// one radix-2/4 stage.
 template <typename T, int PPT>
-__device__ void split_fft(T* buf, int first, int ld, int logL, int count, const cplx<T>* __restrict__ tw) {
+__device__ void split_fft_chunk(T* buf, int first, int ld, int logL, int count, const cplx<T>* __restrict__ tw) {
   int logNs = 0;
   if constexpr (PPT == 16) {
     const int rem = logL & 3;
@@ -277,6 +278,14 @@ __device__ void split_fft(T* buf, int first, int ld, int logL, int count, const 
   }
 }
 
+template <typename T, int PPT>
+__device__ void split_fft(T* buf, int first, int ld, int logL, int count, const cplx<T>* __restrict__ tw) {
+  const int per = max(1, (PPT * (int)blockDim.x) >> logL);
+#pragma nounroll
+  for (int t0 = 0; t0 < count; t0 += per)
+    split_fft_chunk<T, PPT>(buf, first + 2 * t0, ld, logL, min(per, count - t0), tw);
+}
+
 // Separate the DFTs of two real sequences a, b from F = DFT(a + i b):
 //   Fa[k] = (F[k] + conj F[-k]) / 2,  Fb[k] = (F[k] - conj F[-k]) / (2i)
 template <typename T>
@@ -300,132 +309,201 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return r;
 }
 
+// Global-memory phases process kUnroll elements per thread per batch: all loads of a
+// batch are issued before any of them is consumed, so each thread keeps several
+// requests in flight instead of one.
+constexpr int kUnroll = 8;
+
 // ---------------------------------------------------------------- pass A
 // Columns n2 in [c0, c0 + W) of the even extension of x (optionally with both end
 // points doubled: the E^{-1} pre-factor of the transpose), FFT over n1, keep k1 <= L1/2,
-// twiddle W_2N^(n2 k1), store G[k1][n2] for n2 <= L2/2.
+// twiddle W_2N^(n2 k1), store G[k1][n2] for n2 <= L2/2.  W is a power of two.
 template <typename T, int PPT>
-__global__ __launch_bounds__(512) void k_fastA(const T* __restrict__ x, int64_t Nn, int logL1, int logL2, int W,
-                        cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg, const cplx<T>* __restrict__ tw,
-                        const cplx<T>* __restrict__ thi, const cplx<T>* __restrict__ tlo, int tsh, int ends2) {
+__global__ __launch_bounds__(512) void k_fastA(const T* __restrict__ x, int64_t Nn, int logL1, int logL2, int logW,
+                                               cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg,
+                                               const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ thi,
+                                               const cplx<T>* __restrict__ tlo, int tsh, int ends2) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* A = reinterpret_cast<T*>(smem_raw);
   const int comp = blockIdx.y;
   const T* xc = x + (int64_t)comp * Nn;
-  const int64_t N = Nn - 1, N2 = 2 * N;
+  const int N = (int)(Nn - 1), N2 = 2 * N;
   const int L1 = 1 << logL1, L2 = 1 << logL2;
+  const int W = 1 << logW;
   const int c0 = blockIdx.x * W;
   const int ld1 = padded_ld(L1);
   const int n = W << logL1;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int w = e % W, n1 = e / W;
-    const int64_t m = ((int64_t)n1 << logL2) + c0 + w;
-    const int64_t idx = m <= N ? m : N2 - m;
-    T v = xc[idx];
-    if (ends2 && (idx == 0 || idx == N)) v *= T(2);
-    A[w * ld1 + pad(n1)] = v;
+  for (int base = threadIdx.x; base < n; base += kUnroll * blockDim.x) {
+    T val[kUnroll];
+    int dst[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int e = base + u * blockDim.x;
+      dst[u] = -1;
+      if (e < n) {
+        const int w = e & (W - 1), n1 = e >> logW;
+        const int m = (n1 << logL2) + c0 + w;
+        const int idx = m <= N ? m : N2 - m;
+        val[u] = xc[idx];
+        if (ends2 && (idx == 0 || idx == N)) val[u] *= T(2);
+        dst[u] = w * ld1 + pad(n1);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (dst[u] >= 0) A[dst[u]] = val[u];
   }
   __syncthreads();
-  split_fft<T, PPT>(A, 0, ld1, logL1, W / 2, tw);
+  split_fft_chunk<T, PPT>(A, 0, ld1, logL1, W / 2, tw);
   const int half1 = L1 / 2;
   cplx<T>* Gc = G + (int64_t)comp * gcomp;
-  const int nout = (half1 + 1) * W;
-  for (int e = threadIdx.x; e < nout; e += blockDim.x) {
-    const int w = e % W, k1 = e / W;
-    const int n2 = c0 + w;
-    if (n2 > L2 / 2) continue;
-    const T* re = A + (w & ~1) * ld1;
-    const T* im = re + ld1;
-    const int km = (L1 - k1) & (L1 - 1);
-    const cplx<T> v = separate<T>(re[pad(k1)], im[pad(k1)], re[pad(km)], im[pad(km)], w & 1);
-    Gc[(int64_t)k1 * sg + n2] = cmul<T>(v, tw2n<T>(thi, tlo, tsh, (int64_t)n2 * k1));
+  const int nout = (half1 + 1) << logW;
+  const int tmask = (1 << tsh) - 1;
+  for (int base = threadIdx.x; base < nout; base += kUnroll * blockDim.x) {
+    cplx<T> wh[kUnroll], wl[kUnroll], v[kUnroll];
+    int gi[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int e = base + u * blockDim.x;
+      gi[u] = -1;
+      const int w = e & (W - 1), k1 = e >> logW;
+      const int n2 = c0 + w;
+      if (e < nout && n2 <= L2 / 2) {
+        const int t = n2 * k1;
+        wh[u] = thi[t >> tsh];
+        wl[u] = tlo[t & tmask];
+        const T* re = A + (w & ~1) * ld1;
+        const T* im = re + ld1;
+        const int km = (L1 - k1) & (L1 - 1);
+        v[u] = separate<T>(re[pad(k1)], im[pad(k1)], re[pad(km)], im[pad(km)], w & 1);
+        gi[u] = k1 * (int)sg + n2;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (gi[u] >= 0) Gc[gi[u]] = cmul<T>(v[u], cmul<T>(wh[u], wl[u]));
   }
 }
 
 // ---------------------------------------------------------------- pass B
-// Value at n2 <= L2/2 of the Hermitian row that reproduces Y_ext[k1 + L1 m] (m in
-// [0, L2)) for any k1 in [-1, L1): rows 0..L1/2 are stored; row -1 is row 1 read
-// backwards (conjugate input); rows above L1/2 are mirrors of row L1 - k1 read
-// backwards with a shift of one (conjugate input times W_L2^n2).
-template <typename T>
-__device__ __forceinline__ cplx<T> hrow(const cplx<T>* __restrict__ Gc, int64_t sg, int k1, int L1, int n2,
-                                        int logL2, const cplx<T>* __restrict__ tw) {
-  if (k1 < 0) return conjg<T>(Gc[sg + n2]);
-  if (k1 <= L1 / 2) return Gc[(int64_t)k1 * sg + n2];
-  const cplx<T> v = conjg<T>(Gc[(int64_t)(L1 - k1) * sg + n2]);
-  return cmul<T>(v, tw[n2 << (kLdsMaxLog - logL2)]);
+// Source of the Hermitian row that reproduces Y_ext[k1 + L1 m] (m in [0, L2)) for any
+// k1 in [-1, L1): rows 0..L1/2 are stored; row -1 is row 1 read backwards (conjugate
+// input); rows above L1/2 are mirrors of row L1 - k1 read backwards with a shift of one
+// (conjugate input times W_L2^n2).  mode: 0 plain, 1 conjugate, 2 conjugate + twiddle.
+__device__ __forceinline__ int hrow_src(int k1, int L1, int* mode) {
+  if (k1 < 0) {
+    *mode = 1;
+    return 1;
+  }
+  if (k1 <= L1 / 2) {
+    *mode = 0;
+    return k1;
+  }
+  *mode = 2;
+  return L1 - k1;
 }
 
 // Forward stencil (FastBV step 2 with the reversals folded into signs):
 //   d_k = (-1)^k c^_k / e_k with c^ from eq:c_k=bydef and eq:chatk= applied to the
 //   Chebyshev coefficients a_k = (-1)^k e_k Y_k / N; d_0 is deferred (c^_0 term).
+//   invN = 1/N, inv4N1 = 1/(4 (N + 1)).
 template <typename T>
-__device__ __forceinline__ T stencil_fwd(int64_t k, int64_t N, T Ym, T Yp) {
+__device__ __forceinline__ T stencil_fwd(int k, int N, T Ym, T Yp, T invN, T inv4N1) {
   if (k == 0) return T(0);
-  const T invN = T(1) / T(N);
-  const T lo = (k == 1) ? T(1) : T(1) / (T(2) * T(k));
+  const T i2k = T(1) / T(2 * k);
+  const T lo = (k == 1) ? T(1) : i2k;
   const T em1 = (k == 1) ? T(0.5) : T(1);
   T r = -lo * em1 * Ym;
   if (k < N) {
     const T ep1 = (k + 1 == N) ? T(0.5) : T(1);
-    r += ep1 * Yp / (T(2) * T(k));
+    r += ep1 * Yp * i2k;
   }
-  if (k == N - 1) r -= Yp / (T(4) * T(N + 1));
-  const T ek = (k == N) ? T(0.5) : T(1);
-  return r * invN / ek;
+  if (k == N - 1) r -= Yp * inv4N1;
+  const T sc = (k == N) ? T(2) : T(1);
+  return r * invN * sc;
 }
 
 // Transpose stencil: q = S M^T S p with p = Y / 2 (see birk_dct.hip, k_mid_tr).
+//   inv2N1 = 1/(2 (N + 1)).
 template <typename T>
-__device__ __forceinline__ T stencil_tr(int64_t j, int64_t N, T Y0, T Ym, T Yp, T p0) {
+__device__ __forceinline__ T stencil_tr(int j, int N, T Ym, T Yp, T p0, T inv2N1) {
   const T h = T(0.5);
   if (j == 0) return p0 - h * Yp;
   if (j == 1) return T(0.25) * (p0 - h * Yp);
   const T jj = T(j);
   T cm = T(1) / (T(2) * (jj - T(1)));
-  if (j == N) cm -= T(1) / (T(2) * T(N + 1));
-  T q = -p0 / (jj * jj - T(1)) + cm * h * Ym;
+  if (j == N) cm -= inv2N1;
+  T q = -p0 / ((jj - T(1)) * (jj + T(1))) + cm * h * Ym;
   if (j < N) q -= h * Yp / (T(2) * (jj + T(1)));
-  (void)Y0;
   return q;
 }
 
 // c^_0 = (1/N) [ e_0 Y_0 + Y_1 / 4 - sum_{k >= 2} e_k Y_k / (k^2 - 1) ]
-__device__ __forceinline__ double c0_coef(int64_t k, int64_t N) {
+__device__ __forceinline__ double c0_coef(int k, int N) {
   if (k == 0) return 0.5;
   if (k == 1) return 0.25;
   const double ek = (k == N) ? 0.5 : 1.0;
-  return -ek / ((double)k * (double)k - 1.0);
+  return -ek / (((double)k - 1.0) * ((double)k + 1.0));
 }
 
 template <typename T, int TB, int TRANS, int PPT>
-__global__ __launch_bounds__(512) void k_fastB(const cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg, cplx<T>* __restrict__ G2,
-                        int64_t g2comp, int64_t sg2, int64_t N, int logL1, int logL2,
-                        const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ thi,
-                        const cplx<T>* __restrict__ tlo, int tsh, double* __restrict__ part) {
+__global__ __launch_bounds__(512) void k_fastB(const cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg,
+                                               cplx<T>* __restrict__ G2, int64_t g2comp, int64_t sg2, int64_t N64,
+                                               int logL1, int logL2, const cplx<T>* __restrict__ tw,
+                                               const cplx<T>* __restrict__ thi, const cplx<T>* __restrict__ tlo,
+                                               int tsh, double* __restrict__ part) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Y = reinterpret_cast<T*>(smem_raw);  // (TB + 2) real rows of L2
   __shared__ double red[16];
   const int comp = blockIdx.y;
+  const int N = (int)N64;
   const int L1 = 1 << logL1, L2 = 1 << logL2;
   const int half2 = L2 / 2;
   const int t0 = blockIdx.x * TB;
   const int ld2 = padded_ld(L2);
+  const int sgi = (int)sg;
   const cplx<T>* Gc = G + (int64_t)comp * gcomp;
   constexpr int NR = TB + 2;
   // rows rho = 0..TB+1 <-> k1 = t0 - 1 + rho; pairs (2i, 2i+1) share one complex FFT
-  const int nin = (NR / 2) * (half2 + 1);
-  for (int e = threadIdx.x; e < nin; e += blockDim.x) {
-    const int pr = e / (half2 + 1), n2 = e % (half2 + 1);
-    const cplx<T> ra = hrow<T>(Gc, sg, t0 - 1 + 2 * pr, L1, n2, logL2, tw);
-    const cplx<T> rb = hrow<T>(Gc, sg, t0 + 2 * pr, L1, n2, logL2, tw);
-    T* re = Y + (2 * pr) * ld2;
-    T* im = re + ld2;
-    re[pad(n2)] = ra.x - rb.y;
-    im[pad(n2)] = ra.y + rb.x;
-    if (n2 > 0 && n2 < half2) {
-      re[pad(L2 - n2)] = ra.x + rb.y;
-      im[pad(L2 - n2)] = rb.x - ra.y;
+  const int hp1 = half2 + 1;
+  const int nin = (NR / 2) * hp1;
+  const int twsh = kLdsMaxLog - logL2;
+  for (int base = threadIdx.x; base < nin; base += kUnroll * blockDim.x) {
+    cplx<T> ra[kUnroll], rb[kUnroll], wa[kUnroll], wb[kUnroll];
+    int ma[kUnroll], mb[kUnroll], pr_[kUnroll], n2_[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int e = base + u * blockDim.x;
+      pr_[u] = -1;
+      if (e < nin) {
+        const int pr = e / hp1, n2 = e - pr * hp1;
+        const int sa = hrow_src(t0 - 1 + 2 * pr, L1, &ma[u]);
+        const int sb = hrow_src(t0 + 2 * pr, L1, &mb[u]);
+        ra[u] = Gc[sa * sgi + n2];
+        rb[u] = Gc[sb * sgi + n2];
+        wa[u] = tw[(ma[u] == 2 ? n2 : 0) << twsh];
+        wb[u] = tw[(mb[u] == 2 ? n2 : 0) << twsh];
+        pr_[u] = pr;
+        n2_[u] = n2;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (pr_[u] < 0) continue;
+      cplx<T> a = ra[u], b = rb[u];
+      if (ma[u]) a = conjg<T>(a);
+      if (ma[u] == 2) a = cmul<T>(a, wa[u]);
+      if (mb[u]) b = conjg<T>(b);
+      if (mb[u] == 2) b = cmul<T>(b, wb[u]);
+      const int n2 = n2_[u];
+      T* re = Y + (2 * pr_[u]) * ld2;
+      T* im = re + ld2;
+      re[pad(n2)] = a.x - b.y;
+      im[pad(n2)] = a.y + b.x;
+      if (n2 > 0 && n2 < half2) {
+        re[pad(L2 - n2)] = a.x + b.y;
+        im[pad(L2 - n2)] = b.x - a.y;
+      }
     }
   }
   T p0 = T(0);
@@ -440,7 +518,8 @@ __global__ __launch_bounds__(512) void k_fastB(const cplx<T>* __restrict__ G, in
   split_fft<T, PPT>(Y, 0, ld2, logL2, NR / 2, tw);
   // stencil, one thread per m (owns column m of the tile: no cross-thread hazard)
   double c0acc = 0.0;
-  const int64_t N2 = 2 * N;
+  const int N2 = 2 * N;
+  const T invN = T(1) / T(N), inv4N1 = T(1) / T(4 * (int64_t)N + 4), inv2N1 = T(1) / T(2 * (int64_t)N + 2);
   for (int m = threadIdx.x; m < L2; m += blockDim.x) {
     T yv[NR];
 #pragma unroll
@@ -448,16 +527,16 @@ __global__ __launch_bounds__(512) void k_fastB(const cplx<T>* __restrict__ G, in
 #pragma unroll
     for (int r = 1; r <= TB; ++r) {
       const int k1 = t0 - 1 + r;
-      const int64_t K = (int64_t)k1 + (int64_t)L1 * m;
+      const int K = k1 + L1 * m;
       const bool lowhalf = K <= N;
-      const int64_t k = lowhalf ? K : N2 - K;
+      const int k = lowhalf ? K : N2 - K;
       const T Ym = lowhalf ? yv[r - 1] : yv[r + 1];
       const T Yp = lowhalf ? yv[r + 1] : yv[r - 1];
       T d;
       if (TRANS) {
-        d = stencil_tr<T>(k, N, yv[r], Ym, Yp, p0);
+        d = stencil_tr<T>(k, N, Ym, Yp, p0, inv2N1);
       } else {
-        d = stencil_fwd<T>(k, N, Ym, Yp);
+        d = stencil_fwd<T>(k, N, Ym, Yp, invN, inv4N1);
         if (k1 <= L1 / 2 && ((k1 != 0 && k1 != L1 / 2) || lowhalf)) c0acc += c0_coef(k, N) * (double)yv[r];
       }
       Y[r * ld2 + pad(m)] = d;
@@ -471,16 +550,32 @@ __global__ __launch_bounds__(512) void k_fastB(const cplx<T>* __restrict__ G, in
   // columns of the second DCT: d rows (1 + 2i, 2 + 2i) as one complex FFT each
   split_fft<T, PPT>(Y, 1, ld2, logL2, TB / 2, tw);
   cplx<T>* G2c = G2 + (int64_t)comp * g2comp;
-  const int nout = (half2 + 1) * TB;
-  for (int e = threadIdx.x; e < nout; e += blockDim.x) {
-    const int rl = e % TB, q = e / TB;
-    const int r = t0 + rl;
-    if (r > L1 / 2) continue;
-    const T* re = Y + (1 + (rl & ~1)) * ld2;
-    const T* im = re + ld2;
-    const int qm = (L2 - q) & (L2 - 1);
-    const cplx<T> v = separate<T>(re[pad(q)], im[pad(q)], re[pad(qm)], im[pad(qm)], rl & 1);
-    G2c[(int64_t)q * sg2 + r] = cmul<T>(v, tw2n<T>(thi, tlo, tsh, (int64_t)r * q));
+  const int nout = hp1 * TB;
+  const int tmask = (1 << tsh) - 1;
+  const int sg2i = (int)sg2;
+  for (int base = threadIdx.x; base < nout; base += kUnroll * blockDim.x) {
+    cplx<T> wh[kUnroll], wl[kUnroll], v[kUnroll];
+    int gi[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int e = base + u * blockDim.x;
+      gi[u] = -1;
+      const int q = e / TB, rl = e - q * TB;
+      const int r = t0 + rl;
+      if (e < nout && r <= L1 / 2) {
+        const int t = r * q;
+        wh[u] = thi[t >> tsh];
+        wl[u] = tlo[t & tmask];
+        const T* re = Y + (1 + (rl & ~1)) * ld2;
+        const T* im = re + ld2;
+        const int qm = (L2 - q) & (L2 - 1);
+        v[u] = separate<T>(re[pad(q)], im[pad(q)], re[pad(qm)], im[pad(qm)], rl & 1);
+        gi[u] = q * sg2i + r;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (gi[u] >= 0) G2c[gi[u]] = cmul<T>(v[u], cmul<T>(wh[u], wl[u]));
   }
 }
 
@@ -489,18 +584,21 @@ __global__ __launch_bounds__(512) void k_fastB(const cplx<T>* __restrict__ G, in
 // two per complex FFT of length L1, written to the natural output positions
 // j = q1 + L2 q2 and, for 0 < q1 < L2/2, the mirrored j = (L2 - q1) + L2 q2.
 template <typename T, int TRANS, int PPT>
-__global__ __launch_bounds__(512) void k_fastC(const cplx<T>* __restrict__ G2, int64_t g2comp, int64_t sg2, T* __restrict__ out,
-                        int64_t Nn, int logL1, int logL2, int W, const cplx<T>* __restrict__ tw,
-                        const double* __restrict__ part, int ntB) {
+__global__ __launch_bounds__(512) void k_fastC(const cplx<T>* __restrict__ G2, int64_t g2comp, int64_t sg2,
+                                               T* __restrict__ out, int64_t Nn, int logL1, int logL2, int logW,
+                                               const cplx<T>* __restrict__ tw, const double* __restrict__ part,
+                                               int ntB) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* U = reinterpret_cast<T*>(smem_raw);  // W real rows of L1
   __shared__ double red[16];
   const int comp = blockIdx.y;
   const int L1 = 1 << logL1, L2 = 1 << logL2;
   const int half1 = L1 / 2, half2 = L2 / 2;
-  const int64_t N = Nn - 1;
+  const int N = (int)(Nn - 1);
+  const int W = 1 << logW;
   const int c0 = blockIdx.x * W;
   const int ld1 = padded_ld(L1);
+  const int sg2i = (int)sg2;
   T c0hat = T(0);
   if (!TRANS) {
     double acc = 0.0;
@@ -508,33 +606,50 @@ __global__ __launch_bounds__(512) void k_fastC(const cplx<T>* __restrict__ G2, i
     c0hat = (T)(block_sum(acc, red) / (double)N);
   }
   const cplx<T>* G2c = G2 + (int64_t)comp * g2comp;
-  const int nin = (W / 2) * (half1 + 1);
-  for (int e = threadIdx.x; e < nin; e += blockDim.x) {
-    const int pr = e / (half1 + 1), r = e % (half1 + 1);
-    const int qa = c0 + 2 * pr, qb = qa + 1;
-    const cplx<T> ra = qa <= half2 ? G2c[(int64_t)qa * sg2 + r] : mk<T>(T(0), T(0));
-    const cplx<T> rb = qb <= half2 ? G2c[(int64_t)qb * sg2 + r] : mk<T>(T(0), T(0));
-    T* re = U + (2 * pr) * ld1;
-    T* im = re + ld1;
-    re[pad(r)] = ra.x - rb.y;
-    im[pad(r)] = ra.y + rb.x;
-    if (r > 0 && r < half1) {
-      re[pad(L1 - r)] = ra.x + rb.y;
-      im[pad(L1 - r)] = rb.x - ra.y;
+  const int hp1 = half1 + 1;
+  const int nin = (W / 2) * hp1;
+  for (int base = threadIdx.x; base < nin; base += kUnroll * blockDim.x) {
+    cplx<T> ra[kUnroll], rb[kUnroll];
+    int pr_[kUnroll], r_[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int e = base + u * blockDim.x;
+      pr_[u] = -1;
+      if (e < nin) {
+        const int pr = e / hp1, r = e - pr * hp1;
+        const int qa = c0 + 2 * pr, qb = qa + 1;
+        ra[u] = qa <= half2 ? G2c[qa * sg2i + r] : mk<T>(T(0), T(0));
+        rb[u] = qb <= half2 ? G2c[qb * sg2i + r] : mk<T>(T(0), T(0));
+        pr_[u] = pr;
+        r_[u] = r;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (pr_[u] < 0) continue;
+      const int r = r_[u];
+      T* re = U + (2 * pr_[u]) * ld1;
+      T* im = re + ld1;
+      re[pad(r)] = ra[u].x - rb[u].y;
+      im[pad(r)] = ra[u].y + rb[u].x;
+      if (r > 0 && r < half1) {
+        re[pad(L1 - r)] = ra[u].x + rb[u].y;
+        im[pad(L1 - r)] = rb[u].x - ra[u].y;
+      }
     }
   }
   __syncthreads();
-  split_fft<T, PPT>(U, 0, ld1, logL1, W / 2, tw);
+  split_fft_chunk<T, PPT>(U, 0, ld1, logL1, W / 2, tw);
   T* oc = out + (int64_t)comp * Nn;
   const T invN = T(1) / T(N);
-  const int nout = W * (half1 + 1);
+  const int nout = W * hp1;
   for (int e = threadIdx.x; e < nout; e += blockDim.x) {
-    const int w = e % W, q2 = e / W;
+    const int w = e & (W - 1), q2 = e >> logW;
     const int q1 = c0 + w;
     if (q1 > half2) continue;
     const T* row = U + w * ld1;
     if (q2 < half1 || (q1 == 0 && q2 == half1)) {
-      const int64_t j = (int64_t)q1 + (int64_t)L2 * q2;
+      const int j = q1 + L2 * q2;
       const T u = row[pad(q2)];
       T o;
       if (TRANS) o = ((j == 0 || j == N) ? T(0.5) : T(1)) * u * invN;
@@ -542,7 +657,7 @@ __global__ __launch_bounds__(512) void k_fastC(const cplx<T>* __restrict__ G2, i
       oc[j] = o;
     }
     if (q1 > 0 && q1 < half2 && q2 < half1) {
-      const int64_t j = (int64_t)(L2 - q1) + (int64_t)L2 * q2;
+      const int j = (L2 - q1) + L2 * q2;
       const T u = row[pad(L1 - 1 - q2)];
       T o;
       if (TRANS) o = u * invN;
@@ -579,17 +694,25 @@ static void fast_shape(const birk_plan* p, const Instance& in, int& logL1, int& 
   const int kb = p->fast_lds_kb[std::is_same<T, double>::value ? 0 : 1];
   const int budget = (int)((int64_t)kb * 1024 / sizeof(T));  // reals of LDS per workgroup
   const int L1 = 1 << logL1, L2 = 1 << logL2;
-  WA = std::max(2, std::min(16, budget / fast::padded_ld(L1))) & ~1;
+  WA = std::max(2, std::min(16, budget / fast::padded_ld(L1)));
+  while (WA & (WA - 1)) WA &= WA - 1;  // power of two
   WC = WA;
   const int rows = std::max(4, std::min(16, budget / fast::padded_ld(L2)));
   TB = std::max(2, (rows - 2) & ~1);
   // the halo rows of a pass-B tile must stay inside [-1, L1)
   while (TB > 2 && TB > L1 / 2 - 2) TB -= 2;
-  // at most PPT complex points per thread of a 512-thread workgroup
+  // Passes A and C: one split_fft chunk per workgroup (W L1 / 2 <= 512 PPT points), which
+  // keeps tiles small and workgroups many.  Pass B: larger tiles amortise the two halo
+  // rows; its split_fft works through the rows in chunks.
   const int maxpts = 512 * p->fast_ppt;
-  while (WA > 2 && WA * L1 / 2 > maxpts) WA -= 2;
-  while (WC > 2 && WC * L1 / 2 > maxpts) WC -= 2;
-  while (TB > 2 && (TB + 2) * L2 / 2 > maxpts) TB -= 2;
+  while (WA > 2 && WA * L1 / 2 > maxpts) WA /= 2;
+  while (WC > 2 && WC * L1 / 2 > maxpts) WC /= 2;
+}
+
+static int ilog2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
 }
 
 // Threads per workgroup: one per PPT complex points of the largest split_fft call.
@@ -605,12 +728,12 @@ static void lds_attr(F f, int bytes) {
 }
 
 template <typename T, int PPT>
-static void launch_A(dim3 grid, int thr, int lds, hipStream_t s, const T* x, int64_t Nn, int logL1, int logL2, int W,
+static void launch_A(dim3 grid, int thr, int lds, hipStream_t s, const T* x, int64_t Nn, int logL1, int logL2, int logW,
                      cplx<T>* G, int64_t gcomp, int64_t sg, const cplx<T>* tw, const cplx<T>* thi,
                      const cplx<T>* tlo, int tsh, int ends2) {
   auto f = fast::k_fastA<T, PPT>;
   lds_attr(f, lds);
-  hipLaunchKernelGGL(f, grid, dim3(thr), lds, s, x, Nn, logL1, logL2, W, G, gcomp, sg, tw, thi, tlo, tsh, ends2);
+  hipLaunchKernelGGL(f, grid, dim3(thr), lds, s, x, Nn, logL1, logL2, logW, G, gcomp, sg, tw, thi, tlo, tsh, ends2);
 }
 
 template <typename T, int TB, int TRANS, int PPT>
@@ -625,11 +748,11 @@ static void launch_B(dim3 grid, int thr, int lds, hipStream_t s, const cplx<T>* 
 
 template <typename T, int TRANS, int PPT>
 static void launch_C(dim3 grid, int thr, int lds, hipStream_t s, const cplx<T>* G2, int64_t g2comp, int64_t sg2,
-                     T* out, int64_t Nn, int logL1, int logL2, int W, const cplx<T>* tw, const double* part,
+                     T* out, int64_t Nn, int logL1, int logL2, int logW, const cplx<T>* tw, const double* part,
                      int ntB) {
   auto f = fast::k_fastC<T, TRANS, PPT>;
   lds_attr(f, lds);
-  hipLaunchKernelGGL(f, grid, dim3(thr), lds, s, G2, g2comp, sg2, out, Nn, logL1, logL2, W, tw, part, ntB);
+  hipLaunchKernelGGL(f, grid, dim3(thr), lds, s, G2, g2comp, sg2, out, Nn, logL1, logL2, logW, tw, part, ntB);
 }
 
 template <typename T, int PPT>
@@ -653,8 +776,8 @@ static hipError_t fast_product_ppt(birk_plan* p, const Instance& in, const T* v,
   {
     const int ntA = (L2 / 2 + 1 + WA - 1) / WA;
     const int lds = WA * ld1 * (int)sizeof(T);
-    launch_A<T, PPT>(dim3(ntA, nc), threads_for(WA * L1 / 2, PPT), lds, s, v + in.off, in.Nn, logL1, logL2, WA, G,
-                     gcomp, sg, tw, thi, tlo, tsh, transpose ? 1 : 0);
+    launch_A<T, PPT>(dim3(ntA, nc), threads_for(WA * L1 / 2, PPT), lds, s, v + in.off, in.Nn, logL1, logL2,
+                     ilog2i(WA), G, gcomp, sg, tw, thi, tlo, tsh, transpose ? 1 : 0);
   }
   const int ntB = (L1 / 2 + 1 + TB - 1) / TB;
   {
@@ -689,9 +812,11 @@ static hipError_t fast_product_ppt(birk_plan* p, const Instance& in, const T* v,
     const int thr = threads_for(WC * L1 / 2, PPT);
     T* o = out + in.off;
     if (transpose)
-      launch_C<T, 1, PPT>(dim3(ntC, nc), thr, lds, s, G2, g2comp, sg2, o, in.Nn, logL1, logL2, WC, tw, part, ntB);
+      launch_C<T, 1, PPT>(dim3(ntC, nc), thr, lds, s, G2, g2comp, sg2, o, in.Nn, logL1, logL2, ilog2i(WC), tw, part,
+                          ntB);
     else
-      launch_C<T, 0, PPT>(dim3(ntC, nc), thr, lds, s, G2, g2comp, sg2, o, in.Nn, logL1, logL2, WC, tw, part, ntB);
+      launch_C<T, 0, PPT>(dim3(ntC, nc), thr, lds, s, G2, g2comp, sg2, o, in.Nn, logL1, logL2, ilog2i(WC), tw, part,
+                          ntB);
   }
   return hipGetLastError();
 }

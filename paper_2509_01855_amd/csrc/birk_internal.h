@@ -46,6 +46,7 @@ struct Instance {
   int64_t part_off = 0; // offset into the reduction partials (doubles)
   int nblk_mid = 0;     // blocks of the mid kernel per pair
   int64_t scan_off = 0; // offset into the preconditioner scan scratch (doubles)
+  int64_t jsw_off = 0;  // offset into the swizzled per-node Jacobian buffer (doubles)
   double* w = nullptr;  // CC weights on the device [Nn]
   DctTables tab[2];     // [0] double, [1] float
 };
@@ -70,6 +71,8 @@ struct birk_plan {
   void* work[3] = {nullptr, nullptr, nullptr};   // complex work buffers sized for double
   double* partials = nullptr;
   double* scan = nullptr;     // preconditioner scan scratch
+  double* jsw = nullptr;      // per-node Jacobians and weights in the scan's thread layout
+  int64_t total_jsw = 0;
   void* lds_tw[2] = {nullptr, nullptr};          // exp(-2 pi i t / kLdsMax), t < kLdsMax
   void* tmp_vec[4] = {nullptr, nullptr, nullptr, nullptr};  // vectors of total_len doubles
   // Krylov workspace, allocated by the first solve that needs it.
@@ -114,6 +117,11 @@ template <typename T>
 hipError_t precond_inverse(birk_plan* p, int jac_kind, const double* J, const T* y, T* out,
                            T* jout, hipStream_t s, int* flag);
 int64_t pinv_scratch(int64_t Nn, int nx);
+int64_t pinv_jsw_size(int64_t Nn, int nx);
+// Lay out per-node J (or, for constant J, the weights) for the inverse scan; must precede
+// precond_inverse whenever J changes.
+// single = 1 lays the data out in float (for precond_inverse<float>), else in double.
+hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s);
 
 // Krylov BLAS-1 launchers (birk_solve.hip).  Reductions accumulate in double.
 constexpr int kKryMaxDots = 32;

@@ -219,13 +219,74 @@ __device__ __forceinline__ void form_k(const double (&Jk)[NX][NX], double wk, do
     for (int c = 0; c < NX; ++c) K[r][c] = (r == c ? 1.0 : 0.0) - 0.5 * wk * Jk[r][c];
 }
 
-// Level 0 up-sweep: thread per chunk of kChunk nodes -> aggregate (A, b).
+// ---- level-0 layout ----
+// Chunks of kChunk consecutive nodes are reduced by one thread each.  Chunk c is child
+// i = c % kFan of level-1 group g = c / kFan.  Level-0 threads are laid out so that the
+// 64 lanes of a wave hold 64 consecutive groups g and the wave index within a block of
+// kFan waves is the child index i:  thread tau -> block B = tau / (64 kFan),
+// i = (tau / 64) % kFan, lane l = tau % 64, g = 64 B + l, c = kFan g + i.
+// Every per-chunk array (swizzled Jacobians, aggregates, start states) is stored as
+// [B][i][field][l], so each access of a wave is 64 consecutive doubles.
+__device__ __forceinline__ int64_t swz(int64_t B, int i, int field, int nfield, int l) {
+  return (((B * kFan + i) * nfield) + field) * 64 + l;
+}
+
+// Swizzle per-node data for the level-0 kernels: field e < nx^2 is J entry e at the node
+// (per-node Jacobians only), the last field is w_k.  Node k -> chunk c = k / kChunk,
+// j = k % kChunk; g = c / kFan, i = c % kFan; B = g / 64, l = g % 64; stored at
+// jsw[(((B kFan + i) kChunk + j) E + e) 64 + l] with E = fields.  Nodes past N_n are zero
+// (identity maps).  One thread per (slot, field); reads J column e at 64 consecutive
+// groups' nodes.
+template <typename JT>
+__global__ void k_swizzle_nodes(const double* __restrict__ J, int per_node, const double* __restrict__ w,
+                                int nx, int64_t Nn, int64_t nslots, JT* __restrict__ jsw) {
+  const int E = per_node ? nx * nx + 1 : 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nslots * E) return;
+  // t enumerates the destination in order: l fastest, then e, then (B, i, j)
+  const int l = (int)(t & 63);
+  const int64_t r1 = t >> 6;
+  const int e = (int)(r1 % E);
+  const int64_t bij = r1 / E;
+  const int j = (int)(bij % kChunk);
+  const int64_t bi = bij / kChunk;
+  const int i = (int)(bi % kFan);
+  const int64_t B = bi / kFan;
+  const int64_t g = B * 64 + l;
+  const int64_t k = (g * kFan + i) * kChunk + j;
+  double v = 0.0;
+  if (k < Nn) v = (e == E - 1) ? w[k] : J[(int64_t)e * Nn + k];
+  jsw[t] = (JT)v;
+}
+
+template <int NX, typename JT>
+__device__ __forceinline__ void load_jk_sw(const JT* __restrict__ jsw, const double* __restrict__ Jc,
+                                           int per_node, int64_t slot, double (&Jk)[NX][NX], double& wk) {
+  // slot = ((B kFan + i) kChunk + j); per-node: fields 0..NX^2-1 then w; constant: w only
+  const int E = per_node ? NX * NX + 1 : 1;
+  const JT* base = jsw + slot * E * 64;
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int q = 0; q < NX; ++q) Jk[r][q] = per_node ? (double)base[(r * NX + q) * 64 + l] : Jc[r * NX + q];
+  wk = (double)base[(E - 1) * 64 + l];
+}
+
+// Level-0 up-sweep: each thread reduces one chunk of kChunk nodes to (A, b) with
+// S_out = A S_in + b.
 template <int NX, typename T>
-__global__ __launch_bounds__(256) void k_pinv_up0(const double* __restrict__ J, int per_node, int64_t Nn,
-                                                  const double* __restrict__ w, const T* __restrict__ y,
+__global__ __launch_bounds__(256) void k_pinv_up0(const T* __restrict__ jsw, const double* __restrict__ Jc,
+                                                  int per_node, int64_t Nn, const T* __restrict__ y,
                                                   int64_t nchunks, double* __restrict__ agg, int* flag) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tau = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t B = tau / (64 * kFan);
+  const int i = (int)((tau >> 6) % kFan);
+  const int l = (int)(tau & 63);
+  const int64_t g = B * 64 + l;
+  const int64_t c = g * kFan + i;
   if (c >= nchunks) return;
+  constexpr int F = NX * NX + NX;
   double A[NX][NX], b[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
@@ -234,11 +295,14 @@ __global__ __launch_bounds__(256) void k_pinv_up0(const double* __restrict__ J, 
     for (int q = 0; q < NX; ++q) A[r][q] = (r == q) ? 1.0 : 0.0;
   }
   const int64_t k0 = c * kChunk;
-  const int64_t k1 = min(k0 + (int64_t)kChunk, Nn);
-  for (int64_t k = k0; k < k1; ++k) {
-    double Jk[NX][NX], K[NX][NX], rp[NX];
-    load_jk<NX>(J, per_node, Nn, k, Jk);
-    const double wk = w[k];
+  const int jn = (int)min((int64_t)kChunk, Nn - k0);
+  for (int j = 0; j < jn; ++j) {
+    const int64_t k = k0 + j;
+    double Jk[NX][NX], K[NX][NX], rp[NX], wk;
+    load_jk_sw<NX, T>(jsw, Jc, per_node, (B * kFan + i) * kChunk + j, Jk, wk);
+    double x[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) x[r] = (double)y[(int64_t)r * Nn + k];
     form_k<NX>(Jk, wk, K);
     double jmax = 0.0;
 #pragma unroll
@@ -247,9 +311,8 @@ __global__ __launch_bounds__(256) void k_pinv_up0(const double* __restrict__ J, 
       for (int q = 0; q < NX; ++q) jmax = fmax(jmax, fabs(Jk[r][q]));
     lu_kmat<NX>(K, rp, flag, 1.0 + 0.5 * fabs(wk) * jmax);
     // b <- b + wk Jk K^{-1} (b + y_k)
-    double x[NX];
 #pragma unroll
-    for (int r = 0; r < NX; ++r) x[r] = b[r] + (double)y[(int64_t)r * Nn + k];
+    for (int r = 0; r < NX; ++r) x[r] += b[r];
     lu_solve<NX>(K, rp, x);
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
@@ -274,13 +337,98 @@ __global__ __launch_bounds__(256) void k_pinv_up0(const double* __restrict__ J, 
       }
     }
   }
-  double* o = agg + c * (NX * NX + NX);
+#pragma unroll
+  for (int r = 0; r < NX; ++r)
+#pragma unroll
+    for (int q = 0; q < NX; ++q) agg[swz(B, i, r * NX + q, F, l)] = A[r][q];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) agg[swz(B, i, NX * NX + r, F, l)] = b[r];
+}
+
+// Level 0 -> 1 up-sweep: thread per group g combines its kFan chunk aggregates, stored
+// swizzled, into a plain-layout level-1 aggregate.
+template <int NX>
+__global__ __launch_bounds__(256) void k_pinv_up_sw(const double* __restrict__ child, int64_t nchild,
+                                                    double* __restrict__ parent, int64_t nparent) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nparent) return;
+  constexpr int F = NX * NX + NX;
+  const int64_t B = g >> 6;
+  const int l = (int)(g & 63);
+  double A[NX][NX], b[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    b[r] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NX; ++q) A[r][q] = (r == q) ? 1.0 : 0.0;
+  }
+  const int nc = (int)min((int64_t)kFan, nchild - g * kFan);
+  for (int i = 0; i < nc; ++i) {
+    double a[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) a[f] = child[swz(B, i, f, F, l)];
+    double nb[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      double acc = a[NX * NX + r];
+#pragma unroll
+      for (int q = 0; q < NX; ++q) acc += a[r * NX + q] * b[q];
+      nb[r] = acc;
+    }
+#pragma unroll
+    for (int col = 0; col < NX; ++col) {
+      double ncol[NX];
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < NX; ++q) acc += a[r * NX + q] * A[q][col];
+        ncol[r] = acc;
+      }
+#pragma unroll
+      for (int r = 0; r < NX; ++r) A[r][col] = ncol[r];
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) b[r] = nb[r];
+  }
+  double* o = parent + g * F;
 #pragma unroll
   for (int r = 0; r < NX; ++r)
 #pragma unroll
     for (int q = 0; q < NX; ++q) o[r * NX + q] = A[r][q];
 #pragma unroll
   for (int r = 0; r < NX; ++r) o[NX * NX + r] = b[r];
+}
+
+// Level 1 -> 0 down-sweep: group g pushes its start state through its chunks, writing
+// swizzled chunk start states.
+template <int NX>
+__global__ __launch_bounds__(256) void k_pinv_down_sw(const double* __restrict__ child, int64_t nchild,
+                                                      const double* __restrict__ pstate, int64_t nparent,
+                                                      double* __restrict__ cstate) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nparent) return;
+  constexpr int F = NX * NX + NX;
+  const int64_t B = g >> 6;
+  const int l = (int)(g & 63);
+  double s[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) s[r] = pstate[g * NX + r];
+  const int nc = (int)min((int64_t)kFan, nchild - g * kFan);
+  for (int i = 0; i < nc; ++i) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) cstate[swz(B, i, r, NX, l)] = s[r];
+    double ns[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      double acc = child[swz(B, i, NX * NX + r, F, l)];
+#pragma unroll
+      for (int q = 0; q < NX; ++q) acc += child[swz(B, i, r * NX + q, F, l)] * s[q];
+      ns[r] = acc;
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) s[r] = ns[r];
+  }
 }
 
 // Up-sweep one level: thread per parent combines up to kFan child aggregates in order.
@@ -359,6 +507,31 @@ __global__ void k_pinv_top(const double* __restrict__ agg, int64_t n, double* __
   }
 }
 
+// Single group (at most kFan chunks): walk the swizzled level-0 aggregates of group 0
+// from S = 0 and write their swizzled start states.
+template <int NX>
+__global__ void k_pinv_top1(const double* __restrict__ agg, int64_t n, double* __restrict__ state) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  constexpr int F = NX * NX + NX;
+  double s[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) s[r] = 0.0;
+  for (int i = 0; i < (int)n; ++i) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) state[swz(0, i, r, NX, 0)] = s[r];
+    double ns[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      double acc = agg[swz(0, i, NX * NX + r, F, 0)];
+#pragma unroll
+      for (int q = 0; q < NX; ++q) acc += agg[swz(0, i, r * NX + q, F, 0)] * s[q];
+      ns[r] = acc;
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) s[r] = ns[r];
+  }
+}
+
 // Down-sweep one level: thread per parent pushes its start state through its children.
 template <int NX>
 __global__ __launch_bounds__(256) void k_pinv_down(const double* __restrict__ child, int64_t nchild,
@@ -388,28 +561,34 @@ __global__ __launch_bounds__(256) void k_pinv_down(const double* __restrict__ ch
   }
 }
 
-// Replay each chunk from its start state: xi_k and (J xi)_k.
+// Replay each chunk from its start state (same thread layout as k_pinv_up0): xi_k and
+// (J xi)_k.
 template <int NX, typename T>
-__global__ __launch_bounds__(256) void k_pinv_final(const double* __restrict__ J, int per_node, int64_t Nn,
-                                                    const double* __restrict__ w, const T* __restrict__ y,
+__global__ __launch_bounds__(256) void k_pinv_final(const T* __restrict__ jsw, const double* __restrict__ Jc,
+                                                    int per_node, int64_t Nn, const T* __restrict__ y,
                                                     int64_t nchunks, const double* __restrict__ state,
                                                     T* __restrict__ out, T* __restrict__ jout) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tau = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t B = tau / (64 * kFan);
+  const int i = (int)((tau >> 6) % kFan);
+  const int l = (int)(tau & 63);
+  const int64_t g = B * 64 + l;
+  const int64_t c = g * kFan + i;
   if (c >= nchunks) return;
   double s[NX];
 #pragma unroll
-  for (int r = 0; r < NX; ++r) s[r] = state[c * NX + r];
+  for (int r = 0; r < NX; ++r) s[r] = state[swz(B, i, r, NX, l)];
   const int64_t k0 = c * kChunk;
-  const int64_t k1 = min(k0 + (int64_t)kChunk, Nn);
-  for (int64_t k = k0; k < k1; ++k) {
-    double Jk[NX][NX], K[NX][NX], rp[NX];
-    load_jk<NX>(J, per_node, Nn, k, Jk);
-    const double wk = w[k];
-    form_k<NX>(Jk, wk, K);
-    lu_kmat<NX>(K, rp, nullptr, 1.0);
+  const int jn = (int)min((int64_t)kChunk, Nn - k0);
+  for (int j = 0; j < jn; ++j) {
+    const int64_t k = k0 + j;
+    double Jk[NX][NX], K[NX][NX], rp[NX], wk;
+    load_jk_sw<NX, T>(jsw, Jc, per_node, (B * kFan + i) * kChunk + j, Jk, wk);
     double x[NX];
 #pragma unroll
     for (int r = 0; r < NX; ++r) x[r] = s[r] + (double)y[(int64_t)r * Nn + k];
+    form_k<NX>(Jk, wk, K);
+    lu_kmat<NX>(K, rp, nullptr, 1.0);
     lu_solve<NX>(K, rp, x);
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
@@ -425,56 +604,104 @@ __global__ __launch_bounds__(256) void k_pinv_final(const double* __restrict__ J
 
 static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-template <int NX, typename T>
-static void pinv_instance(birk_plan* p, const Instance& in, const double* Ji, int pn, const T* y, T* out,
-                          T* jout, int* flag, hipStream_t s) {
-  constexpr int S = NX * NX + NX;
-  // level sizes
-  int64_t cnt[16];
+// Level sizes of the scan for one instance: cnt[0] chunks, then groups of kFan.
+static int pinv_levels(int64_t Nn, int64_t* cnt) {
   int L = 0;
-  cnt[0] = (in.Nn + kChunk - 1) / kChunk;
+  cnt[0] = (Nn + kChunk - 1) / kChunk;
   while (cnt[L] > kFan && L < 15) {
     cnt[L + 1] = (cnt[L] + kFan - 1) / kFan;
     ++L;
   }
-  // scratch layout: for each level l: agg[cnt[l] * S], then state[cnt[l] * NX]
+  return L;
+}
+
+// Level-0 threads (and swizzled slots) are allocated in blocks of 64 groups.
+static int64_t pinv_blocks0(int64_t nchunks) {
+  const int64_t groups = (nchunks + kFan - 1) / kFan;
+  return (groups + 63) / 64;
+}
+
+int64_t pinv_jsw_size(int64_t Nn, int nx) {
+  int64_t cnt[16];
+  pinv_levels(Nn, cnt);
+  return pinv_blocks0(cnt[0]) * 64 * kFan * kChunk * ((int64_t)nx * nx + 1);
+}
+
+hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s) {
+  const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
+  for (const Instance& in : p->inst) {
+    int64_t cnt[16];
+    pinv_levels(in.Nn, cnt);
+    const int64_t nslots = pinv_blocks0(cnt[0]) * kFan * kChunk;
+    const int E = pn ? in.nx * in.nx + 1 : 1;
+    const double* Ji = J + (pn ? in.joff : in.jcoff);
+    if (single)
+      hipLaunchKernelGGL(k_swizzle_nodes<float>, dim3(nblocks(nslots * E * 64, 256)), dim3(256), 0, s, Ji, pn, in.w,
+                         in.nx, in.Nn, nslots * 64, (float*)p->jsw + in.jsw_off);
+    else
+      hipLaunchKernelGGL(k_swizzle_nodes<double>, dim3(nblocks(nslots * E * 64, 256)), dim3(256), 0, s, Ji, pn,
+                         in.w, in.nx, in.Nn, nslots * 64, p->jsw + in.jsw_off);
+  }
+  return hipGetLastError();
+}
+
+template <int NX, typename T>
+static void pinv_instance(birk_plan* p, const Instance& in, const double* Ji, int pn, const T* y, T* out,
+                          T* jout, int* flag, hipStream_t s) {
+  constexpr int S = NX * NX + NX;
+  int64_t cnt[16];
+  const int L = pinv_levels(in.Nn, cnt);
+  // scratch: for each level l: agg[cnt[l] * S], then state[cnt[l] * NX]; level 0 swizzled
+  const int64_t nb0 = pinv_blocks0(cnt[0]);
   double* base = p->scan + in.scan_off;
   double* agg[16];
   double* st[16];
   for (int l = 0; l <= L; ++l) {
+    const int64_t slots = (l == 0) ? nb0 * 64 * kFan : cnt[l];
     agg[l] = base;
-    base += cnt[l] * S;
+    base += slots * S;
     st[l] = base;
-    base += cnt[l] * NX;
+    base += slots * NX;
   }
-  hipLaunchKernelGGL((k_pinv_up0<NX, T>), dim3(nblocks(cnt[0], 256)), dim3(256), 0, s, Ji, pn, in.Nn, in.w, y,
-                     cnt[0], agg[0], flag);
-  for (int l = 0; l < L; ++l)
-    hipLaunchKernelGGL((k_pinv_up<NX>), dim3(nblocks(cnt[l + 1], 256)), dim3(256), 0, s, agg[l], cnt[l],
-                       agg[l + 1], cnt[l + 1]);
-  hipLaunchKernelGGL((k_pinv_top<NX>), dim3(1), dim3(64), 0, s, agg[L], cnt[L], st[L]);
-  for (int l = L - 1; l >= 0; --l)
-    hipLaunchKernelGGL((k_pinv_down<NX>), dim3(nblocks(cnt[l + 1], 256)), dim3(256), 0, s, agg[l], cnt[l],
-                       st[l + 1], cnt[l + 1], st[l]);
-  hipLaunchKernelGGL((k_pinv_final<NX, T>), dim3(nblocks(cnt[0], 256)), dim3(256), 0, s, Ji, pn, in.Nn, in.w,
-                     y, cnt[0], st[0], out, jout);
+  // per-node data in the plan's storage type (float copies for float products)
+  const T* jsw = (const T*)p->jsw + in.jsw_off;
+  const int64_t thr0 = nb0 * 64 * kFan;
+  hipLaunchKernelGGL((k_pinv_up0<NX, T>), dim3(nblocks(thr0, 256)), dim3(256), 0, s, jsw, Ji, pn, in.Nn, y, cnt[0],
+                     agg[0], flag);
+  if (L == 0) {
+    // a single group of at most kFan chunks: walk it from zero in one thread
+    hipLaunchKernelGGL((k_pinv_top1<NX>), dim3(1), dim3(64), 0, s, agg[0], cnt[0], st[0]);
+  } else {
+    hipLaunchKernelGGL((k_pinv_up_sw<NX>), dim3(nblocks(cnt[1], 256)), dim3(256), 0, s, agg[0], cnt[0], agg[1],
+                       cnt[1]);
+    for (int l = 1; l < L; ++l)
+      hipLaunchKernelGGL((k_pinv_up<NX>), dim3(nblocks(cnt[l + 1], 256)), dim3(256), 0, s, agg[l], cnt[l],
+                         agg[l + 1], cnt[l + 1]);
+    hipLaunchKernelGGL((k_pinv_top<NX>), dim3(1), dim3(64), 0, s, agg[L], cnt[L], st[L]);
+    for (int l = L - 1; l >= 1; --l)
+      hipLaunchKernelGGL((k_pinv_down<NX>), dim3(nblocks(cnt[l + 1], 256)), dim3(256), 0, s, agg[l], cnt[l],
+                         st[l + 1], cnt[l + 1], st[l]);
+    hipLaunchKernelGGL((k_pinv_down_sw<NX>), dim3(nblocks(cnt[1], 256)), dim3(256), 0, s, agg[0], cnt[0], st[1],
+                       cnt[1], st[0]);
+  }
+  hipLaunchKernelGGL((k_pinv_final<NX, T>), dim3(nblocks(thr0, 256)), dim3(256), 0, s, jsw, Ji, pn, in.Nn, y,
+                     cnt[0], st[0], out, jout);
 }
 
-// Scratch (doubles) the inverse scan needs for one instance.
+// Scratch (doubles) the inverse scan needs for one instance (level 0 in whole blocks).
 int64_t pinv_scratch(int64_t Nn, int nx) {
   const int64_t S = (int64_t)nx * nx + 2 * nx;
-  int64_t c = (Nn + kChunk - 1) / kChunk, tot = 0;
-  while (true) {
-    tot += c * S;
-    if (c <= kFan) break;
-    c = (c + kFan - 1) / kFan;
-  }
+  int64_t cnt[16];
+  const int L = pinv_levels(Nn, cnt);
+  int64_t tot = pinv_blocks0(cnt[0]) * 64 * kFan * S;
+  for (int l = 1; l <= L; ++l) tot += cnt[l] * S;
   return tot;
 }
 
 template <typename T>
 hipError_t precond_inverse(birk_plan* p, int jac_kind, const double* J, const T* y, T* out, T* jout,
                            hipStream_t s, int* flag) {
+  // the per-node data must have been swizzled for this J by precond_prepare
   const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
   for (const Instance& in : p->inst) {
     const double* Ji = J + (pn ? in.joff : in.jcoff);
@@ -543,13 +770,16 @@ __global__ __launch_bounds__(256) void k_dots(const T* __restrict__ Q, int64_t l
   }
 }
 
-__global__ void k_reduce_parts(const double* __restrict__ part, int nblk, int nq, double* __restrict__ out) {
-  const int i = threadIdx.x;
-  if (i > kMaxDots) return;
-  if (!(i < nq || i == kMaxDots)) return;
+// One block per needed output (index blockIdx.x < nq, or the norm slot kMaxDots for the
+// last block): strided partial sums, then a fixed-order tree; deterministic.
+__global__ __launch_bounds__(256) void k_reduce_parts(const double* __restrict__ part, int nblk, int nq,
+                                                      double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int i = (blockIdx.x < (unsigned)nq) ? (int)blockIdx.x : kMaxDots;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * (kMaxDots + 1) + i];
-  out[i] = s;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(int64_t)b * (kMaxDots + 1) + i];
+  const double t = block_sum256(s, sh);
+  if (threadIdx.x == 0) out[i] = t;
 }
 
 // u -= sum_i h[i] Q_i ; optionally part <- block sums of ||u||^2
@@ -647,7 +877,7 @@ template <typename T>
 void dots(const T* Q, int64_t ld, int nq, const T* u, int64_t n, double* part, double* out, hipStream_t s) {
   const unsigned g = grid_for(n);
   hipLaunchKernelGGL(k_dots<T>, dim3(g), dim3(256), 0, s, Q, ld, nq, u, n, part);
-  hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(64), 0, s, part, (int)g, nq, out);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(nq + 1), dim3(256), 0, s, part, (int)g, nq, out);
 }
 
 template <typename T>
@@ -655,7 +885,7 @@ void axpys(const T* Q, int64_t ld, int nq, const double* h, T* u, int64_t n, dou
            hipStream_t s) {
   const unsigned g = grid_for(n);
   hipLaunchKernelGGL(k_axpys<T>, dim3(g), dim3(256), 0, s, Q, ld, nq, h, u, n, part);
-  if (part) hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(64), 0, s, part, (int)g, 0, nrm_out);
+  if (part) hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, part, (int)g, 0, nrm_out);
 }
 
 template <typename T>
