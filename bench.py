@@ -35,6 +35,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Birkhoff matvec Gpts/s at N=2^20; solve time mixed vs FP64 at 1e-10 resid"
+KERNEL_SOURCES = ["paper_2509_01855_amd/csrc/birk_fast.hip", "paper_2509_01855_amd/csrc/birk_dct.hip"]
 HBM_PEAK_GBS = 8000.0
 
 
@@ -48,7 +49,37 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--products-only", action="store_true", help="skip the solves (for profiling runs)")
     ap.add_argument("--cpu-sample", type=int, default=200, help="rows of B^a the oracle computes")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration under rocprofv3)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain 1 GiB device-to-device copy, three times, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = 1 << 27  # doubles: 1 GiB
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes_each": n * 8, "copies": 3}), flush=True)
+
+
+def traffic_record(kernel_sources):
+    """Measured HBM bytes per product from profiles/, if the kernels are unchanged since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "apply_f64_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in kernel_sources:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if rec.get("source_sha256") != h.hexdigest():
+        return None
+    return rec
 
 
 def cpu_baseline(N: int, sample_rows: int, v):
@@ -70,6 +101,9 @@ def cpu_baseline(N: int, sample_rows: int, v):
 
 def main():
     a = parse()
+    if a.calibrate_copy:
+        calibrate_copy()
+        return
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {a.gpus}); "
               "the multi-GPU sharding is a design note, not an implementation.", file=sys.stderr)
@@ -182,7 +216,7 @@ def main():
                    "N_n": Nn, "n_x": nx, "n": n, "rotation_buffers": R,
                    "products_per_step": {"apply_f64": R, "apply_T_f64": R, "apply_f32": 2, "precond_inverse": 1,
                                          "solves": 0 if a.products_only else 2}},
-        "roofline": {"bound": "hbm", "kernel": "birk_apply (FastBV pipeline, double)",
+        "roofline": {"bound": "hbm", "kernel": "birk_apply (FastBV, three-pass, double)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": bytes_alg, "avg_launch_us": round(t_apply * 1e6, 2)},
@@ -194,6 +228,10 @@ def main():
             "precond_inverse_f64_us": round(mean(rec["pinv"]) * 1e3, 2),
         },
     }
+    tr = traffic_record(KERNEL_SOURCES)
+    if tr is not None:
+        out["roofline"]["traffic"] = tr["bytes_per_product"]
+        out["roofline"]["traffic_source"] = "profiles/apply_f64_traffic.json"
     if not a.products_only:
         mx, f64 = mean(rec["mixed"]), mean(rec["fp64"])
         out["solve"] = {

@@ -362,7 +362,9 @@ hipError_t ensure_krylov(birk_plan* p, int m, size_t esize) {
   p->krylov_Q = p->krylov_vec = nullptr;
   // sized for double so that one allocation serves either Krylov precision
   (void)esize;
-  hipError_t e = hipMalloc(&p->krylov_Q, (size_t)(m + 1) * p->total_len * sizeof(double));
+  // Q: m + 1 basis vectors; Z: m preconditioned vectors z_j = P^{-1} q_j (kept so the
+  // update chi += P^{-1} Q y = Z y needs no further preconditioner application)
+  hipError_t e = hipMalloc(&p->krylov_Q, (size_t)(2 * m + 1) * p->total_len * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&p->krylov_vec, (size_t)4 * p->total_len * sizeof(double));
   if (e == hipSuccess && !p->krylov_dots)
     e = hipMalloc(&p->krylov_dots, (size_t)p->inst.size() * 2 * kDotsStride * sizeof(double));
@@ -401,9 +403,9 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, double* chi, std:
   const int64_t n = p->total_len;
   hipStream_t s = p->stream;
   TK* Q = (TK*)p->krylov_Q;
+  TK* Z = Q + (size_t)(m + 1) * n;
   TK* u = (TK*)p->krylov_vec;
-  TK* z = u + n;
-  TK* y = z + n;
+  TK* y = u + n;
   TK* t = y + n;
   const double* r = (const double*)p->tmp_vec[0];
   const int64_t ld = n;
@@ -431,6 +433,7 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, double* chi, std:
     for (int i = 0; i < B; ++i) any = any || running[i];
     if (!any) break;
     const TK* qj = Q + (size_t)j * ld;
+    TK* z = Z + (size_t)j * ld;
     // z = P^{-1} q_j, y = J z; t = B^a y; u = z - t
     if (use_precond) {
       e = precond_inverse<TK>(p, jk, J, qj, z, y, s, p->flag);
@@ -528,18 +531,14 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, double* chi, std:
   e = hipMemcpyAsync(p->krylov_dots, coef.data(), std::min(coef.size(), (size_t)B * 2 * kDotsStride) * sizeof(double),
                      hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return BIRK_ERR_DEVICE;
+  // chi += ||r|| P^{-1} Q y = ||r|| Z y (Z = Q without preconditioning)
+  const TK* basis = use_precond ? Z : Q;
   for (int i = 0; i < B; ++i) {
     const Instance& in = p->inst[i];
     const int k = active[i] ? jend[i] : 0;
-    kry::combine<TK>(Q + in.off, ld, k, p->krylov_dots + (size_t)i * kDotsStride, t + in.off, in.Nn * in.nx, s);
+    kry::combine<TK>(basis + in.off, ld, k, p->krylov_dots + (size_t)i * kDotsStride, t + in.off, in.Nn * in.nx, s);
   }
-  if (use_precond) {
-    e = precond_inverse<TK>(p, jk, J, t, z, nullptr, s, nullptr);
-    if (e != hipSuccess) return BIRK_ERR_DEVICE;
-    kry::add_to<TK>(chi, z, n, s);
-  } else {
-    kry::add_to<TK>(chi, t, n, s);
-  }
+  kry::add_to<TK>(chi, t, n, s);
   e = hipStreamSynchronize(s);
   return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
 }

@@ -235,28 +235,29 @@ __device__ __forceinline__ int64_t swz(int64_t B, int i, int field, int nfield, 
 // (per-node Jacobians only), the last field is w_k.  Node k -> chunk c = k / kChunk,
 // j = k % kChunk; g = c / kFan, i = c % kFan; B = g / 64, l = g % 64; stored at
 // jsw[(((B kFan + i) kChunk + j) E + e) 64 + l] with E = fields.  Nodes past N_n are zero
-// (identity maps).  One thread per (slot, field); reads J column e at 64 consecutive
-// groups' nodes.
+// (identity maps).  One workgroup per (B, i, e): for each of the 64 lanes l it reads the
+// kChunk consecutive nodes of chunk (64 B + l) kFan + i, and writes kChunk rows of 64
+// consecutive lanes, transposing through LDS.
 template <typename JT>
-__global__ void k_swizzle_nodes(const double* __restrict__ J, int per_node, const double* __restrict__ w,
-                                int nx, int64_t Nn, int64_t nslots, JT* __restrict__ jsw) {
+__global__ __launch_bounds__(256) void k_swizzle_nodes(const double* __restrict__ J, int per_node,
+                                                       const double* __restrict__ w, int nx, int64_t Nn,
+                                                       JT* __restrict__ jsw) {
+  __shared__ double tile[64][kChunk + 1];
   const int E = per_node ? nx * nx + 1 : 1;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nslots * E) return;
-  // t enumerates the destination in order: l fastest, then e, then (B, i, j)
-  const int l = (int)(t & 63);
-  const int64_t r1 = t >> 6;
-  const int e = (int)(r1 % E);
-  const int64_t bij = r1 / E;
-  const int j = (int)(bij % kChunk);
-  const int64_t bi = bij / kChunk;
-  const int i = (int)(bi % kFan);
-  const int64_t B = bi / kFan;
-  const int64_t g = B * 64 + l;
-  const int64_t k = (g * kFan + i) * kChunk + j;
-  double v = 0.0;
-  if (k < Nn) v = (e == E - 1) ? w[k] : J[(int64_t)e * Nn + k];
-  jsw[t] = (JT)v;
+  const int e = blockIdx.y;
+  const int i = blockIdx.x % kFan;
+  const int64_t B = blockIdx.x / kFan;
+  const double* src = (e == E - 1) ? w : J + (int64_t)e * Nn;
+  for (int t = threadIdx.x; t < 64 * kChunk; t += blockDim.x) {
+    const int l = t / kChunk, j = t % kChunk;
+    const int64_t k = (((B * 64 + l) * kFan + i) * kChunk) + j;
+    tile[l][j] = (k < Nn) ? src[k] : 0.0;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 64 * kChunk; t += blockDim.x) {
+    const int l = t & 63, j = t >> 6;
+    jsw[((((B * kFan + i) * kChunk) + j) * E + e) * 64 + l] = (JT)tile[l][j];
+  }
 }
 
 template <int NX, typename JT>
@@ -635,12 +636,14 @@ hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int sing
     const int64_t nslots = pinv_blocks0(cnt[0]) * kFan * kChunk;
     const int E = pn ? in.nx * in.nx + 1 : 1;
     const double* Ji = J + (pn ? in.joff : in.jcoff);
+    const dim3 grid((unsigned)(pinv_blocks0(cnt[0]) * kFan), E);
+    (void)nslots;
     if (single)
-      hipLaunchKernelGGL(k_swizzle_nodes<float>, dim3(nblocks(nslots * E * 64, 256)), dim3(256), 0, s, Ji, pn, in.w,
-                         in.nx, in.Nn, nslots * 64, (float*)p->jsw + in.jsw_off);
+      hipLaunchKernelGGL(k_swizzle_nodes<float>, grid, dim3(256), 0, s, Ji, pn, in.w, in.nx, in.Nn,
+                         (float*)p->jsw + in.jsw_off);
     else
-      hipLaunchKernelGGL(k_swizzle_nodes<double>, dim3(nblocks(nslots * E * 64, 256)), dim3(256), 0, s, Ji, pn,
-                         in.w, in.nx, in.Nn, nslots * 64, p->jsw + in.jsw_off);
+      hipLaunchKernelGGL(k_swizzle_nodes<double>, grid, dim3(256), 0, s, Ji, pn, in.w, in.nx, in.Nn,
+                         p->jsw + in.jsw_off);
   }
   return hipGetLastError();
 }

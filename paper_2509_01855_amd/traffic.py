@@ -1,0 +1,73 @@
+"""Turn rocprofv3 FETCH_SIZE / WRITE_SIZE runs into HBM bytes per B^a product.
+
+Usage (after the four counter runs described in profiles/README.md):
+    python -m paper_2509_01855_amd.traffic <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir> <out.json>
+
+Each counter is scaled by what it reads for a plain 1 GiB copy (bench.py --calibrate-copy):
+scale = known bytes / counter value, separately for FETCH_SIZE and WRITE_SIZE.  The
+product's bytes are the per-dispatch means of its three kernels (passes A, B, C of the
+double forward product) summed.
+"""
+
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SOURCES = ["paper_2509_01855_amd/csrc/birk_fast.hip", "paper_2509_01855_amd/csrc/birk_dct.hip"]
+PASSES = ("k_fastA<double", "k_fastB<double, ", "k_fastC<double, 0")
+
+
+def _rows(d):
+    f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    return list(csv.DictReader(open(f[0])))
+
+
+def _mean_by_kernel(d, counter):
+    acc = {}
+    for r in _rows(d):
+        if r["Counter_Name"] != counter:
+            continue
+        acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def _copy_value(d, counter):
+    vals = [v for k, v in _mean_by_kernel(d, counter).items() if "copy" in k.lower() or "elementwise" in k.lower()]
+    return max(vals)
+
+
+def main():
+    fetch_dir, write_dir, cf_dir, cw_dir, out = sys.argv[1:6]
+    copy_bytes = float(1 << 30)
+    sf = copy_bytes / _copy_value(cf_dir, "FETCH_SIZE")
+    sw = copy_bytes / _copy_value(cw_dir, "WRITE_SIZE")
+    fetch = _mean_by_kernel(fetch_dir, "FETCH_SIZE")
+    write = _mean_by_kernel(write_dir, "WRITE_SIZE")
+    per = {}
+    for key in PASSES:
+        names = [k for k in fetch if key in k and "TRANS" not in k]
+        # forward pass B/C instances carry TRANS = 0 as the second template argument
+        if key.startswith("k_fastB"):
+            names = [k for k in names if ", 0, " in k]
+        name = names[0]
+        per[name] = {"fetch_bytes": fetch[name] * sf, "write_bytes": write[name] * sw}
+    total = sum(v["fetch_bytes"] + v["write_bytes"] for v in per.values())
+    h = hashlib.sha256()
+    for f in SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    rec = {"bytes_per_product": total, "per_kernel": per, "fetch_scale": sf, "write_scale": sw,
+           "source_sha256": h.hexdigest()}
+    json.dump(rec, open(out, "w"), indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+if __name__ == "__main__":
+    main()
