@@ -34,8 +34,9 @@
  *           retains caller memory.
  * Types.    BIRK_F64: vectors are double.  BIRK_F32 and BIRK_F32_REFINE_F64: vectors
  *           passed to birk_apply / birk_apply_T / birk_precond are float.  BIRK_DF32:
- *           vectors are double-float pairs stored as two float planes, hi then lo, of
- *           the full batch length each (value = hi + lo).  Jacobians, beta and chi are
+ *           every vector element is a double-float pair of floats stored interleaved,
+ *           element k at floats 2k (hi) and 2k + 1 (lo), value = hi + lo (about 48
+ *           significant bits when |lo| <= ulp(hi) / 2).  Jacobians, beta and chi are
  *           always double.
  * Streams.  Work is enqueued on the plan's stream in call order.  birk_apply,
  *           birk_apply_T and birk_precond are asynchronous; birk_krylov_solve
@@ -86,8 +87,12 @@ typedef struct birk_plan birk_plan;
  * hip_stream is a hipStream_t (NULL = the device's null stream); the plan is bound to
  * the device current at creation.  Allocates all scratch, the CGL weights and the
  * transform tables (CC weights computed on the device through B^aT e_N).
+ * Consecutive instances with the same power-of-two N >= 512 share the launches of the
+ * three-pass product; all other instances, whatever their sizes, are covered by one
+ * fixed set of launches per product (work lists built here).
  * Errors: BIRK_ERR_ARG (out/arrays NULL, bad precision), BIRK_ERR_SIZE (batch < 1,
- * N_n < 3, n_x < 1, N_n > 2^26 + 1, total length > 2^31), BIRK_ERR_NOMEM, BIRK_ERR_DEVICE. */
+ * N_n < 3, n_x < 1, N_n - 1 > 2^22 (2^23 when N_n - 1 is a power of two), total length
+ * > 2^31), BIRK_ERR_NOMEM, BIRK_ERR_DEVICE. */
 birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_nodes_host,
                              const int32_t* n_x_host, birk_precision prec, void* hip_stream);
 
@@ -106,7 +111,9 @@ birk_status birk_weights(birk_plan* plan, int32_t inst, double* w_host);
 /* out = (I_{n_x} (x) B^a) v for every instance: FastBV on each component
  * (FastBV box; Fastv2a / Fasta2v boxes; eq:c_k=bydef; eq:chatk=).
  * v and out: device arrays of birk_plan_length elements in the plan's storage type;
- * out must not overlap v.  Errors: BIRK_ERR_ARG (NULL or v == out). */
+ * out must not overlap v.  BIRK_DF32 plans run every step (twiddles, butterflies,
+ * stencil) in compensated double-float arithmetic; the c^_0 reduction accumulates in
+ * double in all precisions.  Errors: BIRK_ERR_ARG (NULL or v == out). */
 birk_status birk_apply(birk_plan* plan, const void* v, void* out);
 
 /* out = (I_{n_x} (x) B^aT) g: the exact transpose of FastBV.  The paper does not give

@@ -56,18 +56,11 @@ constexpr int kMaxPrecondNx = 12;
 
 void free_plan(birk_plan* p) {
   if (!p) return;
-  for (auto& in : p->inst) {
-    for (int pi = 0; pi < 2; ++pi) {
-      if (in.tab[pi].chirp) (void)hipFree(in.tab[pi].chirp);
-      if (in.tab[pi].filt) (void)hipFree(in.tab[pi].filt);
-      if (in.tab[pi].tw4_hi) (void)hipFree(in.tab[pi].tw4_hi);
-      if (in.tab[pi].tw4_lo) (void)hipFree(in.tab[pi].tw4_lo);
-    }
+  for (auto& in : p->inst)
     if (in.w) (void)hipFree(in.w);
-  }
+  for (void* q : p->allocs) if (q) (void)hipFree(q);
   for (void* q : p->work) if (q) (void)hipFree(q);
   for (void* q : p->tmp_vec) if (q) (void)hipFree(q);
-  for (void* q : p->lds_tw) if (q) (void)hipFree(q);
   if (p->partials) (void)hipFree(p->partials);
   if (p->scan) (void)hipFree(p->scan);
   if (p->jsw) (void)hipFree(p->jsw);
@@ -164,46 +157,19 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     if (pp) p->fast_ppt = std::atoi(pp) == 16 ? 16 : 8;
   }
   p->inst.resize(batch);
-  int64_t off = 0, joff = 0, jcoff = 0, woff = 0, poff = 0, soff = 0, jswoff = 0;
+  int64_t off = 0, joff = 0, jcoff = 0, soff = 0, jswoff = 0;
   for (int i = 0; i < batch; ++i) {
     Instance& in = p->inst[i];
     in.Nn = n_nodes_host[i];
     in.N = in.Nn - 1;
     in.nx = n_x_host[i];
-    in.npairs = (in.nx + 1) / 2;
     in.off = off;
     in.joff = joff;
     in.jcoff = jcoff;
-    in.L = 2 * in.N;
-    if (is_pow2(in.L)) {
-      in.method = DCT_POW2;
-      in.M = in.L;
-    } else {
-      in.method = DCT_BLUESTEIN;
-      in.M = int64_t(1) << ilog2(2 * in.L - 1);
-    }
-    in.logM = ilog2(in.M);
-    if (in.logM > kLdsMaxLog) {
-      in.logM1 = (in.logM + 1) / 2;
-      in.logM2 = in.logM - in.logM1;
-    }
-    in.tw4_shift = (in.logM + 1) / 2;
-    in.work_off = woff;
-    in.nblk_mid = (int)((in.Nn + 255) / 256);
-    in.part_off = poff;
     in.scan_off = soff;
-    int64_t wneed = in.M * in.npairs, pneed = (int64_t)in.npairs * in.nblk_mid * 2;
-    if (fast_eligible(in)) {
-      int64_t fw = 0, fp = 0;
-      fast_sizes(p, in, &fw, &fp);
-      wneed = std::max(wneed, fw);
-      pneed = std::max(pneed, fp);
-    }
     off += in.Nn * in.nx;
     joff += in.Nn * in.nx * in.nx;
     jcoff += (int64_t)in.nx * in.nx;
-    woff += wneed;
-    poff += pneed;
     soff += pinv_scratch(in.Nn, in.nx) + (int64_t)in.nx * ((in.Nn + 1023) / 1024) + 64;
     in.jsw_off = jswoff;
     jswoff += pinv_jsw_size(in.Nn, in.nx);
@@ -211,10 +177,11 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
   p->total_len = off;
   p->total_jnode = joff;
   p->total_jconst = jcoff;
-  p->total_work = woff;
-  p->total_part = poff;
   p->total_scan = soff;
   p->total_jsw = jswoff;
+  // product schedule: three-pass groups and the general-path pair sets
+  plan_products(p);
+  const int64_t woff = std::max<int64_t>(p->total_work, 1), poff = p->total_part;
 
   hipError_t e = hipSuccess;
   for (int b = 0; b < 3 && e == hipSuccess; ++b) e = hipMalloc(&p->work[b], woff * sizeof(double2));
@@ -281,8 +248,11 @@ static birk_status product(birk_plan* p, const void* v, void* out, int transpose
     case BIRK_F32_REFINE_F64:
       e = apply_product<float>(p, (const float*)v, (float*)out, transpose, p->stream);
       break;
+    case BIRK_DF32:
+      e = apply_product<df32>(p, (const df32*)v, (df32*)out, transpose, p->stream);
+      break;
     default:
-      return BIRK_ERR_UNSUPPORTED;
+      return BIRK_ERR_ARG;
   }
   return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
 }

@@ -1,4 +1,5 @@
-// Fast Birkhoff products B^a v and B^aT g on the CGL grid (gfx950).
+// Fast Birkhoff products B^a v and B^aT g on the CGL grid (gfx950): the general path,
+// for any N, batched over every pair of components of every instance of a plan.
 //
 // FastBV (arXiv 2509.01855, FastBV box) applies Fastv2a, the integration recurrence
 // with the T_{N+1} alias (eq:c_k=bydef, eq:chatk=) and Fasta2v.  Writing C for the
@@ -16,12 +17,21 @@
 // real even sequence is real, so real and imaginary parts separate).  L a power of
 // two: radix-4/2 Stockham FFTs in LDS, four-step above the LDS limit.  Any other L:
 // Bluestein's chirp-z identity with a power-of-two FFT of length M >= 2L - 1.
+//
+// Batching: the pairs of all instances of one kind (plain power of two, or Bluestein)
+// form a PairSet.  Each phase of the product (pack, FFT passes, filter, stencil, c^_0,
+// unpack) is ONE launch over the whole set, whatever the mix of sizes: the grid is a
+// list of (pair, block) tiles built at plan creation, and every block reads its pair's
+// sizes, offsets and tables from a descriptor.  A product of a batch of uneven
+// instances is therefore a fixed number of launches (at most 14 per set).
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "birk_internal.h"
@@ -53,7 +63,7 @@ __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) {
 }
 
 template <typename T>
-__device__ __forceinline__ cplx<T> mk(T x, T y) {
+__host__ __device__ __forceinline__ cplx<T> mk(T x, T y) {
   cplx<T> r;
   r.x = x;
   r.y = y;
@@ -133,21 +143,22 @@ __device__ void lds_fft(cplx<T>* buf, int logL, int count, const cplx<T>* __rest
   for (; logNs < logL; logNs += 2) stockham_stage<T, 4, NB>(buf, logL, count, logNs, tw, inverse);
 }
 
-// Whole transforms of length M = 2^logM <= kLdsMax, several per block when short.
+
+// Whole transforms of length M = 2^logM <= kLdsMax: tile = (first pair, count); the
+// pairs of a tile have the same M and adjacent work slots.
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_fft_lds(cplx<T>* __restrict__ data, int logM,
-                                                        int count, const cplx<T>* __restrict__ tw,
-                                                        int inverse) {
+__global__ __launch_bounds__(kFftThreads) void k_fft_lds(cplx<T>* __restrict__ data, const PairDesc* __restrict__ pd,
+                                                        const int2* __restrict__ tiles,
+                                                        const cplx<T>* __restrict__ tw, int inverse) {
   __shared__ cplx<T> buf[kLdsMax];
-  const int per = kLdsMax >> logM;
-  const int t0 = blockIdx.x * per;
-  const int cnt = min(per, count - t0);
-  if (cnt <= 0) return;
-  const int n = cnt << logM;
-  cplx<T>* g = data + ((int64_t)t0 << logM);
+  const int2 tile = tiles[blockIdx.x];
+  const PairDesc& d = pd[tile.x];
+  const int logM = d.logM;
+  const int n = tile.y << logM;
+  cplx<T>* g = data + d.work;
   for (int e = threadIdx.x; e < n; e += blockDim.x) buf[e] = g[e];
   __syncthreads();
-  lds_fft<T, 4>(buf, logM, cnt, tw, inverse);
+  lds_fft<T, 4>(buf, logM, tile.y, tw, inverse);
   for (int e = threadIdx.x; e < n; e += blockDim.x) g[e] = buf[e];
 }
 
@@ -160,22 +171,25 @@ __device__ __forceinline__ cplx<T> tw4(const cplx<T>* __restrict__ hi, const cpl
 }
 
 // Four-step, pass 1: columns n2 of x[M2 n1 + n2], FFT over n1 (length M1), twiddle
-// W_M^(n2 k1), store tmp[k1 M2 + n2].  grid = (M2 / W, count).
+// W_M^(n2 k1), store tmp[k1 M2 + n2].  tile = (pair, column block of W).
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_fft4_cols(const cplx<T>* __restrict__ x,
-                                                          cplx<T>* __restrict__ tmp, int logM1,
-                                                          int logM2, const cplx<T>* __restrict__ tw,
-                                                          const cplx<T>* __restrict__ thi,
-                                                          const cplx<T>* __restrict__ tlo,
-                                                          int tshift, int inverse) {
+__global__ __launch_bounds__(kFftThreads) void k_fft4_cols(const cplx<T>* __restrict__ x, cplx<T>* __restrict__ tmp,
+                                                          const PairDesc* __restrict__ pd,
+                                                          const int2* __restrict__ tiles,
+                                                          const cplx<T>* __restrict__ tw, int inverse) {
   __shared__ cplx<T> buf[kLdsMax];
-  const int M1 = 1 << logM1, M2 = 1 << logM2;
+  constexpr int pi = prec_index<T>();
+  const int2 tile = tiles[blockIdx.x];
+  const PairDesc& d = pd[tile.x];
+  const int logM1 = d.logM1, logM2 = d.logM2;
+  const int M1 = 1 << logM1;
   const int logW = min(kLdsMaxLog - logM1, logM2);
   const int W = 1 << logW;
-  const int c0 = blockIdx.x << logW;
-  const int64_t M = (int64_t)M1 << logM2;
-  const cplx<T>* xs = x + (int64_t)blockIdx.y * M;
-  cplx<T>* ts = tmp + (int64_t)blockIdx.y * M;
+  const int c0 = tile.y << logW;
+  const cplx<T>* xs = x + d.work;
+  cplx<T>* ts = tmp + d.work;
+  const cplx<T>* thi = (const cplx<T>*)d.thi[pi];
+  const cplx<T>* tlo = (const cplx<T>*)d.tlo[pi];
   const int n = M1 << logW;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int w = e & (W - 1), n1 = e >> logW;
@@ -186,24 +200,27 @@ __global__ __launch_bounds__(kFftThreads) void k_fft4_cols(const cplx<T>* __rest
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int w = e & (W - 1), k1 = e >> logW;
     const int64_t t = (int64_t)(c0 + w) * k1;
-    ts[((int64_t)k1 << logM2) + c0 + w] = cmul<T>(buf[(w << logM1) + k1], tw4<T>(thi, tlo, tshift, t, inverse));
+    ts[((int64_t)k1 << logM2) + c0 + w] = cmul<T>(buf[(w << logM1) + k1], tw4<T>(thi, tlo, d.tw_shift, t, inverse));
   }
 }
 
 // Four-step, pass 2: rows k1 of tmp, FFT over n2 (length M2), store X[k1 + M1 k2].
+// tile = (pair, row block of W).
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_fft4_rows(const cplx<T>* __restrict__ tmp,
-                                                          cplx<T>* __restrict__ x, int logM1,
-                                                          int logM2, const cplx<T>* __restrict__ tw,
-                                                          int inverse) {
+__global__ __launch_bounds__(kFftThreads) void k_fft4_rows(const cplx<T>* __restrict__ tmp, cplx<T>* __restrict__ x,
+                                                          const PairDesc* __restrict__ pd,
+                                                          const int2* __restrict__ tiles,
+                                                          const cplx<T>* __restrict__ tw, int inverse) {
   __shared__ cplx<T> buf[kLdsMax];
+  const int2 tile = tiles[blockIdx.x];
+  const PairDesc& d = pd[tile.x];
+  const int logM1 = d.logM1, logM2 = d.logM2;
   const int M2 = 1 << logM2;
   const int logW = min(kLdsMaxLog - logM2, logM1);
   const int W = 1 << logW;
-  const int r0 = blockIdx.x << logW;
-  const int64_t M = (int64_t)M2 << logM1;
-  const cplx<T>* ts = tmp + (int64_t)blockIdx.y * M + ((int64_t)r0 << logM2);
-  cplx<T>* xs = x + (int64_t)blockIdx.y * M;
+  const int r0 = tile.y << logW;
+  const cplx<T>* ts = tmp + d.work + ((int64_t)r0 << logM2);
+  cplx<T>* xs = x + d.work;
   const int n = M2 << logW;
   for (int e = threadIdx.x; e < n; e += blockDim.x) buf[e] = ts[e];
   __syncthreads();
@@ -214,61 +231,67 @@ __global__ __launch_bounds__(kFftThreads) void k_fft4_rows(const cplx<T>* __rest
   }
 }
 
+// FFTs of length M over every pair of the set, in place in `data` (tmp: four-step
+// intermediate).
 template <typename T>
-hipError_t fft_batched(const birk_plan* p, const Instance& in, cplx<T>* data, cplx<T>* tmp,
-                       int count, int inverse, hipStream_t s) {
-  const int pi = std::is_same<T, double>::value ? 0 : 1;
-  const cplx<T>* tw = (const cplx<T>*)p->lds_tw[pi];
-  if (in.logM <= kLdsMaxLog) {
-    const int per = kLdsMax >> in.logM;
-    const int blocks = (count + per - 1) / per;
-    hipLaunchKernelGGL(k_fft_lds<T>, dim3(blocks), dim3(kFftThreads), 0, s, data, in.logM, count,
-                       tw, inverse);
-  } else {
-    const int logW1 = std::min(kLdsMaxLog - in.logM1, in.logM2);
-    const int logW2 = std::min(kLdsMaxLog - in.logM2, in.logM1);
-    hipLaunchKernelGGL(k_fft4_cols<T>, dim3(1 << (in.logM2 - logW1), count), dim3(kFftThreads), 0,
-                       s, data, tmp, in.logM1, in.logM2, tw, (const cplx<T>*)in.tab[pi].tw4_hi,
-                       (const cplx<T>*)in.tab[pi].tw4_lo, in.tw4_shift, inverse);
-    hipLaunchKernelGGL(k_fft4_rows<T>, dim3(1 << (in.logM1 - logW2), count), dim3(kFftThreads), 0,
-                       s, tmp, data, in.logM1, in.logM2, tw, inverse);
+static hipError_t fft_set(const birk_plan* p, const PairSet& ps, cplx<T>* data, cplx<T>* tmp, int inverse,
+                          hipStream_t s) {
+  const cplx<T>* tw = (const cplx<T>*)p->lds_tw[prec_index<T>()];
+  if (ps.n_lds > 0)
+    hipLaunchKernelGGL(k_fft_lds<T>, dim3(ps.n_lds), dim3(kFftThreads), 0, s, data, ps.dev, ps.tiles_lds, tw,
+                       inverse);
+  if (ps.n_c4 > 0) {
+    hipLaunchKernelGGL(k_fft4_cols<T>, dim3(ps.n_c4), dim3(kFftThreads), 0, s, data, tmp, ps.dev, ps.tiles_c4, tw,
+                       inverse);
+    hipLaunchKernelGGL(k_fft4_rows<T>, dim3(ps.n_r4), dim3(kFftThreads), 0, s, tmp, data, ps.dev, ps.tiles_r4, tw,
+                       inverse);
   }
   return hipGetLastError();
 }
 
 // ----------------------------------------------------------------- DCT-I plumbing
 
-// Pack pairs of real vectors (components 2p, 2p+1) into the even extension of length L,
-// optionally scaling the end points by `endscale` (2 for the E^{-1} pre-factor of the
-// transpose) and multiplying by the Bluestein chirp; zero-fill [L, M).
+// Pack components (2p, 2p+1) into the even extension of length L, optionally scaling
+// the end points by `endscale` (2 for the E^{-1} pre-factor of the transpose) and
+// multiplying by the Bluestein chirp; zero-fill [L, M).  tile = (pair, block over M).
 template <typename T>
-__global__ void k_pack(const T* __restrict__ x, int nx, int64_t Nn, cplx<T>* __restrict__ z,
-                       int64_t L, int64_t M, const cplx<T>* __restrict__ chirp, T endscale) {
-  const int pidx = blockIdx.y;
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= M) return;
+__global__ __launch_bounds__(256) void k_pack(const T* __restrict__ x, cplx<T>* __restrict__ z,
+                                              const PairDesc* __restrict__ pd, const int2* __restrict__ tiles,
+                                              int ends2) {
+  constexpr int pi = prec_index<T>();
+  const int2 tile = tiles[blockIdx.x];
+  const PairDesc& d = pd[tile.x];
+  const int64_t n = (int64_t)tile.y * blockDim.x + threadIdx.x;
+  if (n >= d.M) return;
+  const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
   cplx<T> val = mk<T>(T(0), T(0));
-  if (n < L) {
-    const int64_t N = Nn - 1;
-    const int64_t k = n <= N ? n : L - n;
-    const int c0 = 2 * pidx, c1 = 2 * pidx + 1;
-    T a = x[(int64_t)c0 * Nn + k];
-    T b = c1 < nx ? x[(int64_t)c1 * Nn + k] : T(0);
-    if (k == 0 || k == N) {
-      a *= endscale;
-      b *= endscale;
+  if (n < d.L) {
+    const int64_t N = d.N;
+    const int64_t k = n <= N ? n : d.L - n;
+    const T* xa = x + d.src;
+    T a = xa[k];
+    T b = d.has2 ? xa[d.Nn + k] : T(0);
+    if (ends2 && (k == 0 || k == N)) {
+      a = a + a;
+      b = b + b;
     }
     val = mk<T>(a, b);
     if (chirp) val = cmul<T>(val, chirp[n]);
   }
-  z[(int64_t)pidx * M + n] = val;
+  z[d.work + n] = val;
 }
 
+// Bluestein: multiply by the filter spectrum.  tile = (pair, block over M).
 template <typename T>
-__global__ void k_pointwise(cplx<T>* __restrict__ z, const cplx<T>* __restrict__ f, int64_t M) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= M) return;
-  cplx<T>* zz = z + (int64_t)blockIdx.y * M;
+__global__ __launch_bounds__(256) void k_pointwise(cplx<T>* __restrict__ z, const PairDesc* __restrict__ pd,
+                                                   const int2* __restrict__ tiles) {
+  constexpr int pi = prec_index<T>();
+  const int2 tile = tiles[blockIdx.x];
+  const PairDesc& d = pd[tile.x];
+  const int64_t n = (int64_t)tile.y * blockDim.x + threadIdx.x;
+  if (n >= d.M) return;
+  const cplx<T>* f = (const cplx<T>*)d.filt[pi];
+  cplx<T>* zz = z + d.work;
   zz[n] = cmul<T>(zz[n], f[n]);
 }
 
@@ -286,15 +309,19 @@ __device__ __forceinline__ cplx<T> dft_value(const cplx<T>* __restrict__ z, cons
 // Fasta2v's DCT.  Writes d into the packed even extension for the second transform,
 // except d_0, which needs c^_0, a reduction over all k; partial sums of
 //     c^_0 = (1/N) [ e_0 Y_0 + Y_1 / 4 - sum_{k>=2} e_k Y_k / (k^2 - 1) ]
-// go to `part` (double, per block, two per pair).
+// go to the pair's partials (double, two per block).  tile = (pair, block over N_n).
 template <typename T>
-__global__ void k_mid_fwd(const cplx<T>* __restrict__ z, cplx<T>* __restrict__ z2, int64_t N,
-                          int64_t L, int64_t M, const cplx<T>* __restrict__ chirp,
-                          double* __restrict__ part) {
-  const int pidx = blockIdx.y;
-  const cplx<T>* zz = z + (int64_t)pidx * M;
-  cplx<T>* z2p = z2 + (int64_t)pidx * M;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_mid_fwd(const cplx<T>* __restrict__ z, cplx<T>* __restrict__ z2,
+                                                 const PairDesc* __restrict__ pd, const int2* __restrict__ tiles,
+                                                 double* __restrict__ part) {
+  constexpr int pi = prec_index<T>();
+  const int2 tile = tiles[blockIdx.x];
+  const PairDesc& d = pd[tile.x];
+  const int64_t N = d.N, L = d.L, M = d.M;
+  const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
+  const cplx<T>* zz = z + d.work;
+  cplx<T>* z2p = z2 + d.work;
+  const int64_t k = (int64_t)tile.y * blockDim.x + threadIdx.x;
   double s0 = 0.0, s1 = 0.0;
   if (k <= N) {
     const T invN = T(1) / T(N);
@@ -329,17 +356,16 @@ __global__ void k_mid_fwd(const cplx<T>* __restrict__ z, cplx<T>* __restrict__ z
         ry -= f * YN.y;
       }
       const T sc = invN / ek;
-      cplx<T> d = mk<T>(rx * sc, ry * sc);
-      cplx<T> o = chirp ? cmul<T>(d, chirp[k]) : d;
-      z2p[k] = o;
+      cplx<T> dv = mk<T>(rx * sc, ry * sc);
+      z2p[k] = chirp ? cmul<T>(dv, chirp[k]) : dv;
       if (k < N) {
         const int64_t m = L - k;
-        z2p[m] = chirp ? cmul<T>(d, chirp[m]) : d;
+        z2p[m] = chirp ? cmul<T>(dv, chirp[m]) : dv;
       }
     }
   }
   // zero fill of the Bluestein padding [L, M)
-  for (int64_t m = L + k; m < M; m += (int64_t)gridDim.x * blockDim.x) z2p[m] = mk<T>(T(0), T(0));
+  for (int64_t m = L + k; m < M; m += (int64_t)d.nblk * blockDim.x) z2p[m] = mk<T>(T(0), T(0));
   // block reduction of the c^_0 partials, fixed order
   __shared__ double r0[256], r1[256];
   r0[threadIdx.x] = s0;
@@ -353,20 +379,20 @@ __global__ void k_mid_fwd(const cplx<T>* __restrict__ z, cplx<T>* __restrict__ z
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part[((int64_t)pidx * gridDim.x + blockIdx.x) * 2 + 0] = r0[0];
-    part[((int64_t)pidx * gridDim.x + blockIdx.x) * 2 + 1] = r1[0];
+    part[d.part + 2 * tile.y + 0] = r0[0];
+    part[d.part + 2 * tile.y + 1] = r1[0];
   }
 }
 
 // d_0 = 2 c^_0 from the partials: one block per pair, fixed-order tree reduction.
 template <typename T>
-__global__ __launch_bounds__(256) void k_c0(const double* __restrict__ part, int nblk, cplx<T>* __restrict__ z2,
-                                            int64_t N, int64_t M) {
-  const int pidx = blockIdx.x;
+__global__ __launch_bounds__(256) void k_c0(const double* __restrict__ part, cplx<T>* __restrict__ z2,
+                                            const PairDesc* __restrict__ pd) {
+  const PairDesc& d = pd[blockIdx.x];
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
-    a += part[((int64_t)pidx * nblk + i) * 2 + 0];
-    b += part[((int64_t)pidx * nblk + i) * 2 + 1];
+  for (int i = threadIdx.x; i < d.nblk; i += blockDim.x) {
+    a += part[d.part + 2 * i + 0];
+    b += part[d.part + 2 * i + 1];
   }
   __shared__ double ra[256], rb[256];
   ra[threadIdx.x] = a;
@@ -380,8 +406,9 @@ __global__ __launch_bounds__(256) void k_c0(const double* __restrict__ part, int
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double s = 2.0 / (double)N;
-    z2[(int64_t)pidx * M] = mk<T>((T)(ra[0] * s), (T)(rb[0] * s));
+    const double s = 2.0 / (double)d.N;
+    // the Bluestein chirp is 1 at index 0, so no pre-multiplication is needed here
+    z2[d.work] = mk<T>((T)(ra[0] * s), (T)(rb[0] * s));
   }
 }
 
@@ -389,12 +416,16 @@ __global__ __launch_bounds__(256) void k_c0(const double* __restrict__ part, int
 //   q_0 = p_0 - p_1,   q_1 = (p_0 - p_2) / 4,
 //   q_j = -p_0/(j^2-1) + p_{j-1} (1/(2(j-1)) - [j = N]/(2(N+1))) - [j < N] p_{j+1}/(2(j+1)).
 template <typename T>
-__global__ void k_mid_tr(const cplx<T>* __restrict__ z, cplx<T>* __restrict__ z2, int64_t N,
-                         int64_t L, int64_t M, const cplx<T>* __restrict__ chirp) {
-  const int pidx = blockIdx.y;
-  const cplx<T>* zz = z + (int64_t)pidx * M;
-  cplx<T>* z2p = z2 + (int64_t)pidx * M;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_mid_tr(const cplx<T>* __restrict__ z, cplx<T>* __restrict__ z2,
+                                                const PairDesc* __restrict__ pd, const int2* __restrict__ tiles) {
+  constexpr int pi = prec_index<T>();
+  const int2 tile = tiles[blockIdx.x];
+  const PairDesc& d = pd[tile.x];
+  const int64_t N = d.N, L = d.L, M = d.M;
+  const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
+  const cplx<T>* zz = z + d.work;
+  cplx<T>* z2p = z2 + d.work;
+  const int64_t j = (int64_t)tile.y * blockDim.x + threadIdx.x;
   if (j <= N) {
     cplx<T> p0 = dft_value<T>(zz, chirp, 0);
     p0.x *= T(0.5);
@@ -425,88 +456,75 @@ __global__ void k_mid_tr(const cplx<T>* __restrict__ z, cplx<T>* __restrict__ z2
     z2p[j] = chirp ? cmul<T>(q, chirp[j]) : q;
     if (j >= 1 && j < N) z2p[L - j] = chirp ? cmul<T>(q, chirp[L - j]) : q;
   }
-  for (int64_t m = L + j; m < M; m += (int64_t)gridDim.x * blockDim.x) z2p[m] = mk<T>(T(0), T(0));
+  for (int64_t m = L + j; m < M; m += (int64_t)d.nblk * blockDim.x) z2p[m] = mk<T>(T(0), T(0));
 }
 
 // Final stage: out_j = scale_j * Y_j for j in [0, N], unpacking the pair.
-// forward: scale = 1/2; transpose: scale = e_j / N.
+// forward: scale = 1/2; transpose: scale = e_j / N.  tile = (pair, block over N_n).
 template <typename T>
-__global__ void k_final(const cplx<T>* __restrict__ z, T* __restrict__ out, int nx, int64_t Nn,
-                        int64_t M, const cplx<T>* __restrict__ chirp, int transpose) {
-  const int pidx = blockIdx.y;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t N = Nn - 1;
+__global__ __launch_bounds__(256) void k_final(const cplx<T>* __restrict__ z, T* __restrict__ out,
+                                               const PairDesc* __restrict__ pd, const int2* __restrict__ tiles,
+                                               int transpose) {
+  constexpr int pi = prec_index<T>();
+  const int2 tile = tiles[blockIdx.x];
+  const PairDesc& d = pd[tile.x];
+  const int64_t N = d.N;
+  const int64_t j = (int64_t)tile.y * blockDim.x + threadIdx.x;
   if (j > N) return;
-  cplx<T> Y = dft_value<T>(z + (int64_t)pidx * M, chirp, j);
+  const cplx<T> Y = dft_value<T>(z + d.work, (const cplx<T>*)d.chirp[pi], j);
   T sc;
   if (transpose) sc = ((j == 0 || j == N) ? T(0.5) : T(1)) / T(N);
   else sc = T(0.5);
-  const int c0 = 2 * pidx, c1 = 2 * pidx + 1;
-  out[(int64_t)c0 * Nn + j] = Y.x * sc;
-  if (c1 < nx) out[(int64_t)c1 * Nn + j] = Y.y * sc;
+  T* o = out + d.src;
+  o[j] = Y.x * sc;
+  if (d.has2) o[d.Nn + j] = Y.y * sc;
+}
+
+// DCT-I (unnormalised, = 2 C) of every pair of the set, in place in z.
+template <typename T>
+static hipError_t dct_set(birk_plan* p, const PairSet& ps, int bluestein, cplx<T>* z, cplx<T>* tmp, hipStream_t s) {
+  hipError_t e = fft_set<T>(p, ps, z, tmp, 0, s);
+  if (e != hipSuccess || !bluestein) return e;
+  hipLaunchKernelGGL(k_pointwise<T>, dim3(ps.n_m), dim3(256), 0, s, z, ps.dev, ps.tiles_m);
+  return fft_set<T>(p, ps, z, tmp, 1, s);
 }
 
 template <typename T>
-static hipError_t dct_transform(birk_plan* p, const Instance& in, cplx<T>* z, cplx<T>* tmp,
-                                hipStream_t s) {
-  const int pi = std::is_same<T, double>::value ? 0 : 1;
-  hipError_t e = fft_batched<T>(p, in, z, tmp, in.npairs, 0, s);
+static hipError_t product_set(birk_plan* p, const PairSet& ps, int bluestein, const T* v, T* out, int transpose,
+                              hipStream_t s) {
+  if (ps.host.empty()) return hipSuccess;
+  cplx<T>* z = (cplx<T>*)p->work[0];
+  cplx<T>* z2 = (cplx<T>*)p->work[1];
+  cplx<T>* tmp = (cplx<T>*)p->work[2];
+  hipLaunchKernelGGL(k_pack<T>, dim3(ps.n_m), dim3(256), 0, s, v, z, ps.dev, ps.tiles_m, transpose);
+  hipError_t e = dct_set<T>(p, ps, bluestein, z, tmp, s);
   if (e != hipSuccess) return e;
-  if (in.method == DCT_BLUESTEIN) {
-    const int64_t M = in.M;
-    hipLaunchKernelGGL(k_pointwise<T>, dim3((unsigned)((M + 255) / 256), in.npairs), dim3(256), 0, s,
-                       z, (const cplx<T>*)in.tab[pi].filt, M);
-    e = fft_batched<T>(p, in, z, tmp, in.npairs, 1, s);
+  if (!transpose) {
+    hipLaunchKernelGGL(k_mid_fwd<T>, dim3(ps.n_n), dim3(256), 0, s, z, z2, ps.dev, ps.tiles_n, p->partials);
+    hipLaunchKernelGGL(k_c0<T>, dim3((unsigned)ps.host.size()), dim3(256), 0, s, p->partials, z2, ps.dev);
+  } else {
+    hipLaunchKernelGGL(k_mid_tr<T>, dim3(ps.n_n), dim3(256), 0, s, z, z2, ps.dev, ps.tiles_n);
   }
-  return e;
+  e = dct_set<T>(p, ps, bluestein, z2, tmp, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_final<T>, dim3(ps.n_n), dim3(256), 0, s, z2, out, ps.dev, ps.tiles_n, transpose);
+  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t apply_product(birk_plan* p, const T* v, T* out, int transpose, hipStream_t s) {
-  const int pi = std::is_same<T, double>::value ? 0 : 1;
-  for (const Instance& in : p->inst) {
-    if (p->use_fast && fast_eligible(in)) {
-      hipError_t e = fast_product<T>(p, in, v, out, transpose, s);
-      if (e != hipSuccess) return e;
-      continue;
-    }
-    cplx<T>* z = (cplx<T>*)p->work[0] + in.work_off;
-    cplx<T>* z2 = (cplx<T>*)p->work[1] + in.work_off;
-    cplx<T>* tmp = (cplx<T>*)p->work[2] + in.work_off;
-    const cplx<T>* chirp = in.method == DCT_BLUESTEIN ? (const cplx<T>*)in.tab[pi].chirp : nullptr;
-    const int64_t M = in.M;
-    const T* vi = v + in.off;
-    T* oi = out + in.off;
-    hipLaunchKernelGGL(k_pack<T>, dim3((unsigned)((M + 255) / 256), in.npairs), dim3(256), 0, s, vi,
-                       in.nx, in.Nn, z, in.L, M, chirp, transpose ? T(2) : T(1));
-    hipError_t e = dct_transform<T>(p, in, z, tmp, s);
-    if (e != hipSuccess) return e;
-    const int nblk = in.nblk_mid;
-    if (!transpose) {
-      double* part = p->partials + in.part_off;
-      hipLaunchKernelGGL(k_mid_fwd<T>, dim3(nblk, in.npairs), dim3(256), 0, s, z, z2, in.N, in.L, M,
-                         chirp, part);
-      hipLaunchKernelGGL(k_c0<T>, dim3(in.npairs), dim3(256), 0, s, part, nblk, z2, in.N, M);
-    } else {
-      hipLaunchKernelGGL(k_mid_tr<T>, dim3(nblk, in.npairs), dim3(256), 0, s, z, z2, in.N, in.L, M,
-                         chirp);
-    }
-    e = dct_transform<T>(p, in, z2, tmp, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_final<T>, dim3(nblk, in.npairs), dim3(256), 0, s, z2, oi, in.nx, in.Nn, M,
-                       chirp, transpose);
-    e = hipGetLastError();
+  for (const FastGroup& g : p->fgroups) {
+    hipError_t e = fast_product<T>(p, g, v, out, transpose, s);
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  hipError_t e = product_set<T>(p, p->gen[0], 0, v, out, transpose, s);
+  if (e == hipSuccess) e = product_set<T>(p, p->gen[1], 1, v, out, transpose, s);
+  return e;
 }
 
 template hipError_t apply_product<double>(birk_plan*, const double*, double*, int, hipStream_t);
 template hipError_t apply_product<float>(birk_plan*, const float*, float*, int, hipStream_t);
-template hipError_t fft_batched<double>(const birk_plan*, const Instance&, cplx<double>*, cplx<double>*,
-                                        int, int, hipStream_t);
-template hipError_t fft_batched<float>(const birk_plan*, const Instance&, cplx<float>*, cplx<float>*,
-                                       int, int, hipStream_t);
+template hipError_t apply_product<df32>(birk_plan*, const df32*, df32*, int, hipStream_t);
 
 // ----------------------------------------------------------------- tables
 
@@ -533,28 +551,33 @@ static void expi_pi(int64_t num, int64_t den, double* c, double* s) {
   *s = -(sgn_s * sn);
 }
 
-template <typename T>
-static hipError_t upload_cplx(const std::vector<double>& re, const std::vector<double>& im, void** dptr) {
-  const size_t n = re.size();
-  std::vector<T> h(2 * n);
-  for (size_t i = 0; i < n; ++i) {
-    h[2 * i] = (T)re[i];
-    h[2 * i + 1] = (T)im[i];
-  }
-  hipError_t e = hipMalloc(dptr, 2 * n * sizeof(T));
+static hipError_t upload_raw(birk_plan* p, const void* h, size_t bytes, void** d) {
+  *d = nullptr;
+  hipError_t e = hipMalloc(d, std::max<size_t>(bytes, 16));
   if (e != hipSuccess) return e;
-  return hipMemcpy(*dptr, h.data(), 2 * n * sizeof(T), hipMemcpyHostToDevice);
+  p->allocs.push_back(*d);
+  return hipMemcpy(*d, h, bytes, hipMemcpyHostToDevice);
 }
 
-static hipError_t upload_both(birk_plan* p, Instance* in, int which, const std::vector<double>& re,
-                              const std::vector<double>& im) {
-  // which: 0 chirp, 2 tw4_hi, 3 tw4_lo
-  for (int pi = 0; pi < 2; ++pi) {
-    void** dst = which == 0 ? &in->tab[pi].chirp : (which == 2 ? &in->tab[pi].tw4_hi : &in->tab[pi].tw4_lo);
-    hipError_t e = pi == 0 ? upload_cplx<double>(re, im, dst) : upload_cplx<float>(re, im, dst);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+template <typename T>
+static hipError_t upload_cplx(birk_plan* p, const std::vector<double>& re, const std::vector<double>& im,
+                              const void** dptr) {
+  const size_t n = re.size();
+  std::vector<cplx<T>> h(n);
+  for (size_t i = 0; i < n; ++i) h[i] = mk<T>((T)re[i], (T)im[i]);
+  void* d = nullptr;
+  hipError_t e = upload_raw(p, h.data(), n * sizeof(cplx<T>), &d);
+  *dptr = d;
+  return e;
+}
+
+// One table in all three precisions.
+static hipError_t upload_all(birk_plan* p, const std::vector<double>& re, const std::vector<double>& im,
+                             const void** dst) {
+  hipError_t e = upload_cplx<double>(p, re, im, &dst[0]);
+  if (e == hipSuccess) e = upload_cplx<float>(p, re, im, &dst[1]);
+  if (e == hipSuccess) e = upload_cplx<df32>(p, re, im, &dst[2]);
+  return e;
 }
 
 template <typename T>
@@ -581,52 +604,248 @@ __global__ void k_scale_to(const cplx<double>* __restrict__ src, cplx<T>* __rest
   dst[m] = mk<T>((T)(src[m].x * s), (T)(src[m].y * s));
 }
 
+static int ilog2_ceil(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+
+static PairDesc make_pair(int64_t src, int64_t Nn, int has2) {
+  PairDesc d;
+  d.src = src;
+  d.Nn = Nn;
+  d.N = Nn - 1;
+  d.L = 2 * d.N;
+  const bool pow2 = (d.L & (d.L - 1)) == 0;
+  d.M = pow2 ? d.L : (int64_t(1) << ilog2_ceil(2 * d.L - 1));
+  d.logM = ilog2_ceil(d.M);
+  if (d.logM > kLdsMaxLog) {
+    d.logM1 = (d.logM + 1) / 2;
+    d.logM2 = d.logM - d.logM1;
+  }
+  d.tw_shift = (d.logM + 1) / 2;
+  d.has2 = has2;
+  d.nblk = (int)((Nn + 255) / 256);
+  return d;
+}
+
+// Sort the pairs by M (so that pairs of one LDS-sized M are adjacent), then give each
+// its work slot and partials.
+static void layout_set(PairSet& ps, int64_t& woff, int64_t& poff) {
+  std::stable_sort(ps.host.begin(), ps.host.end(),
+                   [](const PairDesc& a, const PairDesc& b) { return a.M < b.M; });
+  ps.work = 0;
+  ps.parts = 0;
+  for (PairDesc& d : ps.host) {
+    d.work = woff;
+    woff += d.M;
+    ps.work += d.M;
+    d.part = poff;
+    poff += 2 * (int64_t)d.nblk;
+    ps.parts += 2 * (int64_t)d.nblk;
+  }
+}
+
+void plan_products(birk_plan* p) {
+  p->fgroups.clear();
+  p->gen[0] = PairSet();
+  p->gen[1] = PairSet();
+  int64_t woff = 0, poff = 0;
+  const int B = (int)p->inst.size();
+  for (int i = 0; i < B;) {
+    const Instance& in = p->inst[i];
+    if (p->use_fast && fast_eligible(in.N)) {
+      FastGroup g;
+      g.Nn = in.Nn;
+      g.N = in.N;
+      g.off = in.off;
+      int j = i;
+      while (j < B && p->inst[j].N == in.N) g.nc += p->inst[j++].nx;
+      int64_t fw = 0, fp = 0;
+      fast_sizes(p, g.N, g.nc, &fw, &fp);
+      g.work_off = woff;
+      g.part_off = poff;
+      woff += fw;
+      poff += fp;
+      p->fgroups.push_back(g);
+      i = j;
+      continue;
+    }
+    const int np = (in.nx + 1) / 2;
+    for (int q = 0; q < np; ++q) {
+      PairDesc d = make_pair(in.off + 2 * (int64_t)q * in.Nn, in.Nn, 2 * q + 1 < in.nx);
+      p->gen[(d.L == d.M) ? 0 : 1].host.push_back(d);
+    }
+    ++i;
+  }
+  layout_set(p->gen[0], woff, poff);
+  layout_set(p->gen[1], woff, poff);
+  p->total_work = woff;
+  p->total_part = poff;
+}
+
+// Tile lists of a set (see PairSet), uploaded with the descriptors.
+static hipError_t finalize_set(birk_plan* p, PairSet& ps) {
+  std::vector<int2> tm, tn, tl, tc, tr;
+  const int np = (int)ps.host.size();
+  for (int q = 0; q < np; ++q) {
+    const PairDesc& d = ps.host[q];
+    for (int64_t b = 0; b < (d.M + 255) / 256; ++b) tm.push_back(make_int2(q, (int)b));
+    for (int b = 0; b < d.nblk; ++b) tn.push_back(make_int2(q, b));
+    if (d.logM > kLdsMaxLog) {
+      const int logW1 = std::min(kLdsMaxLog - d.logM1, d.logM2);
+      const int logW2 = std::min(kLdsMaxLog - d.logM2, d.logM1);
+      for (int b = 0; b < (1 << (d.logM2 - logW1)); ++b) tc.push_back(make_int2(q, b));
+      for (int b = 0; b < (1 << (d.logM1 - logW2)); ++b) tr.push_back(make_int2(q, b));
+    }
+  }
+  for (int q = 0; q < np;) {
+    const PairDesc& d = ps.host[q];
+    if (d.logM > kLdsMaxLog) {
+      ++q;
+      continue;
+    }
+    const int per = kLdsMax >> d.logM;
+    int cnt = 1;
+    while (q + cnt < np && cnt < per && ps.host[q + cnt].M == d.M && ps.host[q + cnt].work == d.work + cnt * d.M)
+      ++cnt;
+    tl.push_back(make_int2(q, cnt));
+    q += cnt;
+  }
+  ps.n_m = (int)tm.size();
+  ps.n_n = (int)tn.size();
+  ps.n_lds = (int)tl.size();
+  ps.n_c4 = (int)tc.size();
+  ps.n_r4 = (int)tr.size();
+  void* d = nullptr;
+  hipError_t e = upload_raw(p, ps.host.data(), ps.host.size() * sizeof(PairDesc), &d);
+  ps.dev = (PairDesc*)d;
+  auto up = [&](const std::vector<int2>& v, int2** dst) {
+    void* x = nullptr;
+    if (e == hipSuccess) e = upload_raw(p, v.data(), v.size() * sizeof(int2), &x);
+    *dst = (int2*)x;
+  };
+  up(tm, &ps.tiles_m);
+  up(tn, &ps.tiles_n);
+  up(tl, &ps.tiles_lds);
+  up(tc, &ps.tiles_c4);
+  up(tr, &ps.tiles_r4);
+  return e;
+}
+
 hipError_t build_tables(birk_plan* p) {
   hipError_t e;
   {
     std::vector<double> re(kLdsMax), im(kLdsMax);
     for (int t = 0; t < kLdsMax; ++t) expi_pi(2 * (int64_t)t, kLdsMax, &re[t], &im[t]);
-    for (int pi = 0; pi < 2; ++pi) {
-      e = pi == 0 ? upload_cplx<double>(re, im, &p->lds_tw[0]) : upload_cplx<float>(re, im, &p->lds_tw[1]);
-      if (e != hipSuccess) return e;
-    }
+    if ((e = upload_all(p, re, im, p->lds_tw)) != hipSuccess) return e;
   }
-  for (Instance& in : p->inst) {
-    if (in.logM > kLdsMaxLog || fast_eligible(in)) {
-      const int sh = in.tw4_shift;
-      const int64_t nlo = (int64_t)1 << sh, nhi = in.M >> sh;
-      std::vector<double> re(nlo), im(nlo);
-      for (int64_t t = 0; t < nlo; ++t) expi_pi(2 * t, in.M, &re[t], &im[t]);
-      if ((e = upload_both(p, &in, 3, re, im)) != hipSuccess) return e;
-      re.assign(nhi, 0.0);
-      im.assign(nhi, 0.0);
-      for (int64_t t = 0; t < nhi; ++t) expi_pi(2 * (t << sh), in.M, &re[t], &im[t]);
-      if ((e = upload_both(p, &in, 2, re, im)) != hipSuccess) return e;
+  // four-step twiddles, one set per transform length
+  std::map<int64_t, TwiddleSet> twsets;
+  auto twiddles = [&](int64_t M, TwiddleSet* out) -> hipError_t {
+    auto it = twsets.find(M);
+    if (it != twsets.end()) {
+      *out = it->second;
+      return hipSuccess;
     }
-    if (in.method == DCT_BLUESTEIN) {
-      // chi_n = exp(-i pi n^2 / L), n in [0, L)
-      std::vector<double> re(in.L), im(in.L);
-      for (int64_t n = 0; n < in.L; ++n) {
-        const int64_t m = (int64_t)(((__int128)n * n) % (2 * in.L));
-        expi_pi(m, in.L, &re[n], &im[n]);
+    TwiddleSet ts;
+    const int logM = ilog2_ceil(M);
+    ts.shift = (logM + 1) / 2;
+    const int64_t nlo = (int64_t)1 << ts.shift, nhi = M >> ts.shift;
+    std::vector<double> re(nlo), im(nlo);
+    for (int64_t t = 0; t < nlo; ++t) expi_pi(2 * t, M, &re[t], &im[t]);
+    hipError_t err = upload_all(p, re, im, ts.lo);
+    re.assign(nhi, 0.0);
+    im.assign(nhi, 0.0);
+    for (int64_t t = 0; t < nhi; ++t) expi_pi(2 * (t << ts.shift), M, &re[t], &im[t]);
+    if (err == hipSuccess) err = upload_all(p, re, im, ts.hi);
+    twsets[M] = ts;
+    *out = ts;
+    return err;
+  };
+  for (FastGroup& g : p->fgroups)
+    if ((e = twiddles(2 * g.N, &g.tw)) != hipSuccess) return e;
+  for (int k = 0; k < 2; ++k)
+    for (PairDesc& d : p->gen[k].host)
+      if (d.logM > kLdsMaxLog) {
+        TwiddleSet ts;
+        if ((e = twiddles(d.M, &ts)) != hipSuccess) return e;
+        for (int pi = 0; pi < kNumPrec; ++pi) {
+          d.thi[pi] = ts.hi[pi];
+          d.tlo[pi] = ts.lo[pi];
+        }
       }
-      if ((e = upload_both(p, &in, 0, re, im)) != hipSuccess) return e;
-      // filter spectrum FFT_M(b) / M in double on the device, then rounded for float
-      cplx<double>* b = (cplx<double>*)p->work[0] + in.work_off;
-      cplx<double>* tmp = (cplx<double>*)p->work[2] + in.work_off;
-      hipLaunchKernelGGL(k_build_filter<double>, dim3((unsigned)((in.M + 255) / 256)), dim3(256), 0,
-                         p->stream, b, (const cplx<double>*)in.tab[0].chirp, in.L, in.M);
-      if ((e = fft_batched<double>(p, in, b, tmp, 1, 0, p->stream)) != hipSuccess) return e;
-      if ((e = hipMalloc(&in.tab[0].filt, in.M * sizeof(cplx<double>))) != hipSuccess) return e;
-      if ((e = hipMalloc(&in.tab[1].filt, in.M * sizeof(cplx<float>))) != hipSuccess) return e;
-      const double s = 1.0 / (double)in.M;
-      hipLaunchKernelGGL(k_scale_to<double>, dim3((unsigned)((in.M + 255) / 256)), dim3(256), 0,
-                         p->stream, b, (cplx<double>*)in.tab[0].filt, in.M, s);
-      hipLaunchKernelGGL(k_scale_to<float>, dim3((unsigned)((in.M + 255) / 256)), dim3(256), 0,
-                         p->stream, b, (cplx<float>*)in.tab[1].filt, in.M, s);
-      if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return e;
+  // Bluestein chirp and filter spectrum, one per distinct L
+  struct Blue {
+    const void* chirp[kNumPrec];
+    const void* filt[kNumPrec];
+  };
+  std::map<int64_t, Blue> blue;
+  PairSet fs;  // one pair per distinct L: the filter FFTs
+  for (const PairDesc& d : p->gen[1].host) {
+    if (blue.count(d.L)) continue;
+    Blue b{};
+    std::vector<double> re(d.L), im(d.L);
+    for (int64_t n = 0; n < d.L; ++n) {
+      const int64_t m = (int64_t)(((__int128)n * n) % (2 * d.L));
+      expi_pi(m, d.L, &re[n], &im[n]);
+    }
+    if ((e = upload_all(p, re, im, b.chirp)) != hipSuccess) return e;
+    blue[d.L] = b;
+    PairDesc f = d;
+    fs.host.push_back(f);
+  }
+  if (!fs.host.empty()) {
+    int64_t woff = 0, poff = 0;
+    layout_set(fs, woff, poff);  // filter slots from the start of work[0] / work[2]
+    for (PairDesc& f : fs.host) {
+      if (f.logM > kLdsMaxLog) {
+        TwiddleSet ts;
+        if ((e = twiddles(f.M, &ts)) != hipSuccess) return e;
+        for (int pi = 0; pi < kNumPrec; ++pi) {
+          f.thi[pi] = ts.hi[pi];
+          f.tlo[pi] = ts.lo[pi];
+        }
+      }
+      cplx<double>* bw = (cplx<double>*)p->work[0] + f.work;
+      hipLaunchKernelGGL(k_build_filter<double>, dim3((unsigned)((f.M + 255) / 256)), dim3(256), 0, p->stream, bw,
+                         (const cplx<double>*)blue[f.L].chirp[0], f.L, f.M);
+    }
+    if ((e = finalize_set(p, fs)) != hipSuccess) return e;
+    e = fft_set<double>(p, fs, (cplx<double>*)p->work[0], (cplx<double>*)p->work[2], 0, p->stream);
+    if (e != hipSuccess) return e;
+    for (const PairDesc& f : fs.host) {
+      Blue& b = blue[f.L];
+      const cplx<double>* bw = (const cplx<double>*)p->work[0] + f.work;
+      const double s = 1.0 / (double)f.M;
+      const dim3 grid((unsigned)((f.M + 255) / 256));
+      void* d0 = nullptr;
+      void* d1 = nullptr;
+      void* d2 = nullptr;
+      if ((e = hipMalloc(&d0, f.M * sizeof(cplx<double>))) != hipSuccess) return e;
+      p->allocs.push_back(d0);
+      if ((e = hipMalloc(&d1, f.M * sizeof(cplx<float>))) != hipSuccess) return e;
+      p->allocs.push_back(d1);
+      if ((e = hipMalloc(&d2, f.M * sizeof(cplx<df32>))) != hipSuccess) return e;
+      p->allocs.push_back(d2);
+      hipLaunchKernelGGL(k_scale_to<double>, grid, dim3(256), 0, p->stream, bw, (cplx<double>*)d0, f.M, s);
+      hipLaunchKernelGGL(k_scale_to<float>, grid, dim3(256), 0, p->stream, bw, (cplx<float>*)d1, f.M, s);
+      hipLaunchKernelGGL(k_scale_to<df32>, grid, dim3(256), 0, p->stream, bw, (cplx<df32>*)d2, f.M, s);
+      b.filt[0] = d0;
+      b.filt[1] = d1;
+      b.filt[2] = d2;
+    }
+    if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return e;
+    for (PairDesc& d : p->gen[1].host) {
+      const Blue& b = blue[d.L];
+      for (int pi = 0; pi < kNumPrec; ++pi) {
+        d.chirp[pi] = b.chirp[pi];
+        d.filt[pi] = b.filt[pi];
+      }
     }
   }
+  for (int k = 0; k < 2; ++k)
+    if (!p->gen[k].host.empty() && (e = finalize_set(p, p->gen[k])) != hipSuccess) return e;
   return hipGetLastError();
 }
 

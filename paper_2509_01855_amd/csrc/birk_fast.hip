@@ -671,9 +671,8 @@ __global__ __launch_bounds__(512) void k_fastC(const cplx<T>* __restrict__ G2, i
 
 // ---------------------------------------------------------------- host side
 
-// Shape of the fast path for one instance and precision (chosen at plan creation).
-bool fast_eligible(const Instance& in) {
-  const int64_t N = in.N;
+// Shape of the fast path for one transform size and precision (chosen at plan creation).
+bool fast_eligible(int64_t N) {
   if (N < 512 || (N & (N - 1)) != 0) return false;
   int s = 0;
   while ((int64_t(1) << s) < 2 * N) ++s;
@@ -681,9 +680,9 @@ bool fast_eligible(const Instance& in) {
 }
 
 template <typename T>
-static void fast_shape(const birk_plan* p, const Instance& in, int& logL1, int& logL2, int& WA, int& TB, int& WC) {
+static void fast_shape(const birk_plan* p, int64_t N, int& logL1, int& logL2, int& WA, int& TB, int& WC) {
   int s = 0;
-  while ((int64_t(1) << s) < 2 * in.N) ++s;
+  while ((int64_t(1) << s) < 2 * N) ++s;
   if (p->fast_split == 0) {
     logL2 = (s + 1) / 2;  // rows of the first DCT (pass B) are the longer side
     logL1 = s - logL2;
@@ -691,7 +690,7 @@ static void fast_shape(const birk_plan* p, const Instance& in, int& logL1, int& 
     logL1 = (s + 1) / 2;
     logL2 = s - logL1;
   }
-  const int kb = p->fast_lds_kb[std::is_same<T, double>::value ? 0 : 1];
+  const int kb = p->fast_lds_kb[sizeof(T) == 8 ? 0 : 1];
   const int budget = (int)((int64_t)kb * 1024 / sizeof(T));  // reals of LDS per workgroup
   const int L1 = 1 << logL1, L2 = 1 << logL2;
   WA = std::max(2, std::min(16, budget / fast::padded_ld(L1)));
@@ -756,27 +755,27 @@ static void launch_C(dim3 grid, int thr, int lds, hipStream_t s, const cplx<T>* 
 }
 
 template <typename T, int PPT>
-static hipError_t fast_product_ppt(birk_plan* p, const Instance& in, const T* v, T* out, int transpose,
+static hipError_t fast_product_ppt(birk_plan* p, const FastGroup& g, const T* v, T* out, int transpose,
                                    hipStream_t s) {
-  const int pi = std::is_same<T, double>::value ? 0 : 1;
+  constexpr int pi = prec_index<T>();
   int logL1, logL2, WA, TB, WC;
-  fast_shape<T>(p, in, logL1, logL2, WA, TB, WC);
+  fast_shape<T>(p, g.N, logL1, logL2, WA, TB, WC);
   const int L1 = 1 << logL1, L2 = 1 << logL2;
   const int ld1 = fast::padded_ld(L1), ld2 = fast::padded_ld(L2);
   const int64_t sg = L2 / 2 + 1, sg2 = L1 / 2 + 1;
   const int64_t gcomp = (int64_t)(L1 / 2 + 1) * sg, g2comp = (int64_t)(L2 / 2 + 1) * sg2;
-  cplx<T>* G = (cplx<T>*)p->work[0] + in.work_off;
-  cplx<T>* G2 = (cplx<T>*)p->work[1] + in.work_off;
-  double* part = p->partials + in.part_off;
+  cplx<T>* G = (cplx<T>*)p->work[0] + g.work_off;
+  cplx<T>* G2 = (cplx<T>*)p->work[1] + g.work_off;
+  double* part = p->partials + g.part_off;
   const cplx<T>* tw = (const cplx<T>*)p->lds_tw[pi];
-  const cplx<T>* thi = (const cplx<T>*)in.tab[pi].tw4_hi;
-  const cplx<T>* tlo = (const cplx<T>*)in.tab[pi].tw4_lo;
-  const int tsh = in.tw4_shift;
-  const int nc = in.nx;
+  const cplx<T>* thi = (const cplx<T>*)g.tw.hi[pi];
+  const cplx<T>* tlo = (const cplx<T>*)g.tw.lo[pi];
+  const int tsh = g.tw.shift;
+  const int nc = g.nc;
   {
     const int ntA = (L2 / 2 + 1 + WA - 1) / WA;
     const int lds = WA * ld1 * (int)sizeof(T);
-    launch_A<T, PPT>(dim3(ntA, nc), threads_for(WA * L1 / 2, PPT), lds, s, v + in.off, in.Nn, logL1, logL2,
+    launch_A<T, PPT>(dim3(ntA, nc), threads_for(WA * L1 / 2, PPT), lds, s, v + g.off, g.Nn, logL1, logL2,
                      ilog2i(WA), G, gcomp, sg, tw, thi, tlo, tsh, transpose ? 1 : 0);
   }
   const int ntB = (L1 / 2 + 1 + TB - 1) / TB;
@@ -787,10 +786,10 @@ static hipError_t fast_product_ppt(birk_plan* p, const Instance& in, const T* v,
 #define BIRK_LB(tb)                                                                                                \
   case tb:                                                                                                         \
     if (transpose)                                                                                                 \
-      launch_B<T, tb, 1, PPT>(grid, thr, lds, s, G, gcomp, sg, G2, g2comp, sg2, in.N, logL1, logL2, tw, thi, tlo,  \
+      launch_B<T, tb, 1, PPT>(grid, thr, lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, logL2, tw, thi, tlo,   \
                               tsh, part);                                                                          \
     else                                                                                                           \
-      launch_B<T, tb, 0, PPT>(grid, thr, lds, s, G, gcomp, sg, G2, g2comp, sg2, in.N, logL1, logL2, tw, thi, tlo,  \
+      launch_B<T, tb, 0, PPT>(grid, thr, lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, logL2, tw, thi, tlo,   \
                               tsh, part);                                                                          \
     break;
     switch (TB) {
@@ -810,35 +809,37 @@ static hipError_t fast_product_ppt(birk_plan* p, const Instance& in, const T* v,
     const int ntC = (L2 / 2 + 1 + WC - 1) / WC;
     const int lds = WC * ld1 * (int)sizeof(T);
     const int thr = threads_for(WC * L1 / 2, PPT);
-    T* o = out + in.off;
+    T* o = out + g.off;
     if (transpose)
-      launch_C<T, 1, PPT>(dim3(ntC, nc), thr, lds, s, G2, g2comp, sg2, o, in.Nn, logL1, logL2, ilog2i(WC), tw, part,
+      launch_C<T, 1, PPT>(dim3(ntC, nc), thr, lds, s, G2, g2comp, sg2, o, g.Nn, logL1, logL2, ilog2i(WC), tw, part,
                           ntB);
     else
-      launch_C<T, 0, PPT>(dim3(ntC, nc), thr, lds, s, G2, g2comp, sg2, o, in.Nn, logL1, logL2, ilog2i(WC), tw, part,
+      launch_C<T, 0, PPT>(dim3(ntC, nc), thr, lds, s, G2, g2comp, sg2, o, g.Nn, logL1, logL2, ilog2i(WC), tw, part,
                           ntB);
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t fast_product(birk_plan* p, const Instance& in, const T* v, T* out, int transpose, hipStream_t s) {
-  return p->fast_ppt == 8 ? fast_product_ppt<T, 8>(p, in, v, out, transpose, s)
-                          : fast_product_ppt<T, 16>(p, in, v, out, transpose, s);
+hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, int transpose, hipStream_t s) {
+  return p->fast_ppt == 8 ? fast_product_ppt<T, 8>(p, g, v, out, transpose, s)
+                          : fast_product_ppt<T, 16>(p, g, v, out, transpose, s);
 }
 
-// Work (complex elements per buffer) and partials (doubles) the fast path needs.
-void fast_sizes(const birk_plan* p, const Instance& in, int64_t* work, int64_t* part) {
+// Work (complex elements per buffer) and partials (doubles) of the fast path for nc
+// components of length N + 1, for any of the storage types.
+void fast_sizes(const birk_plan* p, int64_t N, int nc, int64_t* work, int64_t* part) {
   int l1f, l2f, waf, tbf, wcf, l1d, l2d, wad, tbd, wcd;
-  fast_shape<float>(p, in, l1f, l2f, waf, tbf, wcf);
-  fast_shape<double>(p, in, l1d, l2d, wad, tbd, wcd);
+  fast_shape<float>(p, N, l1f, l2f, waf, tbf, wcf);
+  fast_shape<double>(p, N, l1d, l2d, wad, tbd, wcd);
   const int64_t L1 = int64_t(1) << l1f, L2 = int64_t(1) << l2f;
-  *work = (int64_t)in.nx * (L1 / 2 + 1) * (L2 / 2 + 1);
+  *work = (int64_t)nc * (L1 / 2 + 1) * (L2 / 2 + 1);
   const int64_t ntB = std::max((L1 / 2 + 1 + tbf - 1) / tbf, ((int64_t(1) << l1d) / 2 + 1 + tbd - 1) / tbd);
-  *part = (int64_t)in.nx * ntB;
+  *part = (int64_t)nc * ntB;
 }
 
-template hipError_t fast_product<double>(birk_plan*, const Instance&, const double*, double*, int, hipStream_t);
-template hipError_t fast_product<float>(birk_plan*, const Instance&, const float*, float*, int, hipStream_t);
+template hipError_t fast_product<double>(birk_plan*, const FastGroup&, const double*, double*, int, hipStream_t);
+template hipError_t fast_product<float>(birk_plan*, const FastGroup&, const float*, float*, int, hipStream_t);
+template hipError_t fast_product<df32>(birk_plan*, const FastGroup&, const df32*, df32*, int, hipStream_t);
 
 }  // namespace birk

@@ -4,9 +4,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "birk.h"
+#include "birk_df32.h"
 
 namespace birk {
 
@@ -18,41 +20,77 @@ constexpr int kFftThreads = 256;
 template <typename T> struct C2;
 template <> struct C2<double> { using type = double2; };
 template <> struct C2<float> { using type = float2; };
+template <> struct C2<df32> { using type = df32c; };
 template <typename T> using cplx = typename C2<T>::type;
 
-enum DctMethod { DCT_POW2 = 0, DCT_BLUESTEIN = 1 };
+// Index of a storage type in the per-precision table arrays: 0 double, 1 float,
+// 2 double-float.
+template <typename T>
+constexpr int prec_index() {
+  return std::is_same<T, double>::value ? 0 : std::is_same<T, float>::value ? 1 : 2;
+}
+constexpr int kNumPrec = 3;
 
-// Device tables of one precision for one instance.
-struct DctTables {
-  void* chirp = nullptr;   // Bluestein: chi_n = exp(-i pi n^2 / L), n in [0, L)
-  void* filt = nullptr;    // Bluestein: FFT_M of conj(chi) wrapped, times 1/M
-  void* tw4_hi = nullptr;  // four-step twiddles W_M^(t) = hi[t >> s] * lo[t & (2^s - 1)]
-  void* tw4_lo = nullptr;
-};
-
+// Per-instance data of the preconditioner and the solve.
 struct Instance {
   int64_t Nn = 0, N = 0;
-  int nx = 0, npairs = 0;
+  int nx = 0;
   int64_t off = 0;      // vector offset (elements)
   int64_t joff = 0;     // per-node Jacobian offset (elements)
   int64_t jcoff = 0;    // constant Jacobian offset (elements)
-  int method = DCT_POW2;
-  int64_t L = 0;        // 2N: length of the even extension
-  int64_t M = 0;        // FFT length (L for pow2, pow2 >= 2L - 1 for Bluestein)
-  int logM = 0;
-  int logM1 = 0, logM2 = 0;  // four-step split (logM1 + logM2 = logM) when M > kLdsMax
-  int tw4_shift = 0;
-  int64_t work_off = 0; // offset into the complex work buffers (elements)
-  int64_t part_off = 0; // offset into the reduction partials (doubles)
-  int nblk_mid = 0;     // blocks of the mid kernel per pair
   int64_t scan_off = 0; // offset into the preconditioner scan scratch (doubles)
   int64_t jsw_off = 0;  // offset into the swizzled per-node Jacobian buffer (doubles)
   double* w = nullptr;  // CC weights on the device [Nn]
-  DctTables tab[2];     // [0] double, [1] float
 };
 
-struct ScanLevel {
-  int64_t items = 0;    // number of aggregates at this level (per instance)
+// Four-step twiddles W_M^t = hi[t >> shift] * lo[t & (2^shift - 1)], one array pair per
+// precision, shared by every transform of length M in the plan.
+struct TwiddleSet {
+  const void* hi[kNumPrec] = {nullptr, nullptr, nullptr};
+  const void* lo[kNumPrec] = {nullptr, nullptr, nullptr};
+  int shift = 0;
+};
+
+// Three-pass power-of-two product (birk_fast.hip): a run of consecutive instances with
+// the same N, whose nc components are then contiguous with stride N_n.
+struct FastGroup {
+  int64_t Nn = 0, N = 0;
+  int nc = 0;
+  int64_t off = 0;       // vector offset of the first component
+  int64_t work_off = 0;  // complex elements into work[0], work[1]
+  int64_t part_off = 0;  // doubles into partials
+  TwiddleSet tw;         // M = 2N
+};
+
+// General product path (birk_dct.hip): one pair of components (2p, 2p + 1) of one
+// instance.  Plain old data, copied to the device; kernels index it by pair.
+struct PairDesc {
+  int64_t src = 0;       // vector offset of component 2p
+  int64_t Nn = 0, N = 0, L = 0, M = 0;
+  int64_t work = 0;      // complex offset of this pair's M-long slot in work[0..2]
+  int64_t part = 0;      // offset of the pair's c^_0 partials (2 per block)
+  int logM = 0, logM1 = 0, logM2 = 0, tw_shift = 0;
+  int has2 = 0;          // component 2p + 1 exists
+  int nblk = 0;          // 256-wide blocks over [0, N_n)
+  const void* chirp[kNumPrec] = {nullptr, nullptr, nullptr};  // Bluestein chirp, or null (L = M)
+  const void* filt[kNumPrec] = {nullptr, nullptr, nullptr};   // Bluestein filter spectrum / M
+  const void* thi[kNumPrec] = {nullptr, nullptr, nullptr};    // four-step twiddles (M > kLdsMax)
+  const void* tlo[kNumPrec] = {nullptr, nullptr, nullptr};
+};
+
+// Work lists of the general path.  Each launch of a phase covers every pair of every
+// size: its grid is a list of tiles (pair, block) read from the device.
+struct PairSet {
+  std::vector<PairDesc> host;
+  PairDesc* dev = nullptr;
+  int2* tiles_m = nullptr;    // (pair, block of 256 over [0, M))
+  int2* tiles_n = nullptr;    // (pair, block of 256 over [0, N_n))
+  int2* tiles_lds = nullptr;  // (first pair, count): whole transforms of M <= kLdsMax
+  int2* tiles_c4 = nullptr;   // (pair, column block) of the four-step first pass
+  int2* tiles_r4 = nullptr;   // (pair, row block) of the four-step second pass
+  int n_m = 0, n_n = 0, n_lds = 0, n_c4 = 0, n_r4 = 0;
+  int64_t work = 0;           // complex elements needed per work buffer
+  int64_t parts = 0;          // doubles of partials needed
 };
 
 }  // namespace birk
@@ -62,6 +100,9 @@ struct birk_plan {
   hipStream_t stream = nullptr;
   birk_precision prec = BIRK_F64;
   std::vector<birk::Instance> inst;
+  std::vector<birk::FastGroup> fgroups;
+  birk::PairSet gen[2];           // general-path pairs: [0] 2N a power of two, [1] Bluestein
+  std::vector<void*> allocs;      // device tables owned by the plan
   int64_t total_len = 0;
   int64_t total_jnode = 0;
   int64_t total_jconst = 0;
@@ -73,38 +114,38 @@ struct birk_plan {
   double* scan = nullptr;     // preconditioner scan scratch
   double* jsw = nullptr;      // per-node Jacobians and weights in the scan's thread layout
   int64_t total_jsw = 0;
-  void* lds_tw[2] = {nullptr, nullptr};          // exp(-2 pi i t / kLdsMax), t < kLdsMax
+  const void* lds_tw[birk::kNumPrec] = {nullptr, nullptr, nullptr};  // exp(-2 pi i t / kLdsMax)
   void* tmp_vec[4] = {nullptr, nullptr, nullptr, nullptr};  // vectors of total_len doubles
   // Krylov workspace, allocated by the first solve that needs it.
   int krylov_m = 0;
-  void* krylov_Q = nullptr;   // (m + 1) vectors of the Krylov precision
+  void* krylov_Q = nullptr;   // (2m + 1) vectors of the Krylov precision (Q and Z)
   void* krylov_vec = nullptr; // 4 vectors of the Krylov precision
   double* krylov_dots = nullptr;  // [batch][2][kKryMaxDots + 1]
   double* krylov_part = nullptr;  // reduction partials
   int* flag = nullptr;            // device flag: singular pivot seen
   int use_fast = 1;               // power-of-two N takes the three-pass path
-  int fast_lds_kb[2] = {128, 64};  // LDS budget per workgroup of the three-pass kernels [double, float]
+  int fast_lds_kb[2] = {128, 64};  // LDS budget per workgroup of the three-pass kernels [8-byte, 4-byte reals]
   int fast_ppt = 8;               // complex points per thread in the three-pass FFTs (8 or 16)
   int fast_split = 0;             // 0: rows of the first DCT are the longer side (L2 >= L1); 1: L1 >= L2
 };
 
 namespace birk {
 
-// ---- transforms (birk_dct.hip) ----
-template <typename T>
-hipError_t fft_batched(const birk_plan* p, const Instance& in, cplx<T>* data, cplx<T>* tmp,
-                       int count, int inverse, hipStream_t s);
-
+// ---- products (birk_dct.hip) ----
 template <typename T>
 hipError_t apply_product(birk_plan* p, const T* v, T* out, int transpose, hipStream_t s);
 
+// Lay out the general-path pairs and the fast groups of a plan, with their table needs;
+// called once at plan creation, before any allocation of work buffers.
+void plan_products(birk_plan* p);
+// Allocate and fill every transform table and work list (after the work buffers exist).
 hipError_t build_tables(birk_plan* p);
 
 // ---- power-of-two three-pass path (birk_fast.hip) ----
-bool fast_eligible(const Instance& in);
+bool fast_eligible(int64_t N);
 template <typename T>
-hipError_t fast_product(birk_plan* p, const Instance& in, const T* v, T* out, int transpose, hipStream_t s);
-void fast_sizes(const birk_plan* p, const Instance& in, int64_t* work, int64_t* part);
+hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, int transpose, hipStream_t s);
+void fast_sizes(const birk_plan* p, int64_t N, int nc, int64_t* work, int64_t* part);
 
 // ---- preconditioner, Jacobian products and Krylov kernels (birk_solve.hip) ----
 template <typename T>

@@ -34,3 +34,19 @@ def rel_err(got, ref):
 
 def announce(msg):
     print(msg, flush=True)
+
+
+def to_df32(x):
+    """Double array -> interleaved double-float pairs (float32 [..., 2] flattened):
+    hi = rn32(x), lo = rn32(x - hi)."""
+    x = np.asarray(x, dtype=np.float64)
+    hi = x.astype(np.float32)
+    lo = (x - hi.astype(np.float64)).astype(np.float32)
+    return np.stack([hi, lo], axis=-1).reshape(*x.shape[:-1], 2 * x.shape[-1])
+
+
+def from_df32(a):
+    """Interleaved double-float pairs -> double (hi + lo)."""
+    a = np.asarray(a, dtype=np.float32)
+    pairs = a.reshape(*a.shape[:-1], a.shape[-1] // 2, 2)
+    return pairs[..., 0].astype(np.float64) + pairs[..., 1].astype(np.float64)
