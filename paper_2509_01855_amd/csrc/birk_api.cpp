@@ -68,6 +68,8 @@ void free_plan(birk_plan* p) {
   if (p->krylov_vec) (void)hipFree(p->krylov_vec);
   if (p->krylov_dots) (void)hipFree(p->krylov_dots);
   if (p->krylov_part) (void)hipFree(p->krylov_part);
+  if (p->krylov_coef) (void)hipFree(p->krylov_coef);
+  if (p->krylov_cnt) (void)hipFree(p->krylov_cnt);
   if (p->flag) (void)hipFree(p->flag);
   delete p;
 }
@@ -210,6 +212,7 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     }
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   }
+  if (e == hipSuccess) e = plan_solve(p);
   if (e != hipSuccess) {
     free_plan(p);
     return dev_err(e);
@@ -326,6 +329,14 @@ struct InstState {
 };
 
 hipError_t ensure_krylov(birk_plan* p, int m, size_t esize) {
+  hipError_t e = hipSuccess;
+  const size_t B = p->inst.size();
+  if (!p->krylov_dots) e = hipMalloc(&p->krylov_dots, B * 2 * kDotsStride * sizeof(double));
+  if (e == hipSuccess && !p->krylov_part)
+    e = hipMalloc(&p->krylov_part, (size_t)std::max(p->seg.ntiles, 1) * kDotsStride * sizeof(double));
+  if (e == hipSuccess && !p->krylov_coef) e = hipMalloc(&p->krylov_coef, B * kDotsStride * sizeof(double));
+  if (e == hipSuccess && !p->krylov_cnt) e = hipMalloc(&p->krylov_cnt, B * sizeof(int));
+  if (e != hipSuccess) return e;
   if (p->krylov_Q && p->krylov_m >= m) return hipSuccess;
   if (p->krylov_Q) (void)hipFree(p->krylov_Q);
   if (p->krylov_vec) (void)hipFree(p->krylov_vec);
@@ -334,23 +345,16 @@ hipError_t ensure_krylov(birk_plan* p, int m, size_t esize) {
   (void)esize;
   // Q: m + 1 basis vectors; Z: m preconditioned vectors z_j = P^{-1} q_j (kept so the
   // update chi += P^{-1} Q y = Z y needs no further preconditioner application)
-  hipError_t e = hipMalloc(&p->krylov_Q, (size_t)(2 * m + 1) * p->total_len * sizeof(double));
+  e = hipMalloc(&p->krylov_Q, (size_t)(2 * m + 1) * p->total_len * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&p->krylov_vec, (size_t)4 * p->total_len * sizeof(double));
-  if (e == hipSuccess && !p->krylov_dots)
-    e = hipMalloc(&p->krylov_dots, (size_t)p->inst.size() * 2 * kDotsStride * sizeof(double));
-  if (e == hipSuccess && !p->krylov_part) e = hipMalloc(&p->krylov_part, (size_t)2048 * kDotsStride * sizeof(double));
   if (e == hipSuccess) p->krylov_m = m;
   return e;
 }
 
-// Per-instance ||v_i||^2 for a double vector; results into host array.
+// Per-instance ||v_i||^2 for a double vector (one segmented launch); results into host array.
 hipError_t seg_norms(birk_plan* p, const double* v, std::vector<double>& out) {
   const int B = (int)p->inst.size();
-  for (int i = 0; i < B; ++i) {
-    const Instance& in = p->inst[i];
-    kry::dots<double>(nullptr, 0, 0, v + in.off, in.Nn * in.nx, p->krylov_part,
-                      p->krylov_dots + (size_t)i * 2 * kDotsStride, p->stream);
-  }
+  kry::sdots<double>(p, nullptr, 0, v, p->krylov_dots, 2 * kDotsStride, p->stream);
   std::vector<double> h((size_t)B * 2 * kDotsStride);
   hipError_t e = hipMemcpyAsync(h.data(), p->krylov_dots, h.size() * sizeof(double), hipMemcpyDeviceToHost,
                                 p->stream);
@@ -383,11 +387,14 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, double* chi, std:
 
   std::vector<char> active(B, 0);
   for (int i = 0; i < B; ++i) active[i] = !st[i].done;
-  // q_0 = r / ||r|| (zero for inactive instances)
-  for (int i = 0; i < B; ++i) {
-    const Instance& in = p->inst[i];
-    const double sc = active[i] && st[i].rnorm > 0 ? 1.0 / st[i].rnorm : 0.0;
-    kry::scale_conv<double, TK>(r + in.off, Q + in.off, sc, in.Nn * in.nx, s);
+  // q_0 = r / ||r|| (zero for inactive instances); host arrays handed to async copies
+  // live until the synchronisation at the end of the cycle
+  std::vector<double> sc(B, 0.0);
+  {
+    for (int i = 0; i < B; ++i) sc[i] = active[i] && st[i].rnorm > 0 ? 1.0 / st[i].rnorm : 0.0;
+    e = hipMemcpyAsync(p->krylov_coef, sc.data(), B * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return BIRK_ERR_DEVICE;
+    kry::sscale_conv<double, TK>(p, r, Q, p->krylov_coef, s);
   }
   std::vector<std::vector<double>> H(B, std::vector<double>((size_t)(m + 1) * m, 0.0));
   std::vector<std::vector<double>> cs(B, std::vector<double>(m, 0.0)), sn(B, std::vector<double>(m, 0.0));
@@ -418,18 +425,17 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, double* chi, std:
       if (e != hipSuccess) return BIRK_ERR_DEVICE;
       kry::sub<TK>(qj, t, u, n, s);
     }
-    // CGS2 per running instance
-    for (int i = 0; i < B; ++i) {
-      if (!running[i]) continue;
-      const Instance& in = p->inst[i];
-      const int64_t ni = in.Nn * in.nx;
-      double* d1 = p->krylov_dots + (size_t)i * 2 * kDotsStride;
+    // CGS2 on every instance at once (segmented launches; stopped instances are
+    // carried along and their results ignored)
+    {
+      double* d1 = p->krylov_dots;
       double* d2 = d1 + kDotsStride;
-      kry::dots<TK>(Q + in.off, ld, j + 1, u + in.off, ni, p->krylov_part, d1, s);
-      kry::axpys<TK>(Q + in.off, ld, j + 1, d1, u + in.off, ni, nullptr, nullptr, s);
-      kry::dots<TK>(Q + in.off, ld, j + 1, u + in.off, ni, p->krylov_part, d2, s);
-      kry::axpys<TK>(Q + in.off, ld, j + 1, d2, u + in.off, ni, p->krylov_part, d2, s);
-      kry::normalize<TK>(u + in.off, d2 + kKryMaxDots, Q + (size_t)(j + 1) * ld + in.off, ni, s);
+      const int64_t ds = 2 * kDotsStride;
+      kry::sdots<TK>(p, Q, j + 1, u, d1, ds, s);
+      kry::saxpys<TK>(p, Q, j + 1, d1, ds, u, nullptr, s);
+      kry::sdots<TK>(p, Q, j + 1, u, d2, ds, s);
+      kry::saxpys<TK>(p, Q, j + 1, d2, ds, u, d2, s);
+      kry::snormalize<TK>(p, u, d2 + kKryMaxDots, ds, Q + (size_t)(j + 1) * ld, s);
     }
     e = hipMemcpyAsync(hbuf.data(), p->krylov_dots, hbuf.size() * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -498,16 +504,14 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, double* chi, std:
     }
     for (int a = 0; a < k; ++a) coef[(size_t)i * kDotsStride + a] = yv[a] * st[i].rnorm;
   }
-  e = hipMemcpyAsync(p->krylov_dots, coef.data(), std::min(coef.size(), (size_t)B * 2 * kDotsStride) * sizeof(double),
-                     hipMemcpyHostToDevice, s);
+  std::vector<int> cnt(B, 0);
+  for (int i = 0; i < B; ++i) cnt[i] = active[i] ? jend[i] : 0;
+  e = hipMemcpyAsync(p->krylov_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->krylov_cnt, cnt.data(), B * sizeof(int), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return BIRK_ERR_DEVICE;
   // chi += ||r|| P^{-1} Q y = ||r|| Z y (Z = Q without preconditioning)
   const TK* basis = use_precond ? Z : Q;
-  for (int i = 0; i < B; ++i) {
-    const Instance& in = p->inst[i];
-    const int k = active[i] ? jend[i] : 0;
-    kry::combine<TK>(basis + in.off, ld, k, p->krylov_dots + (size_t)i * kDotsStride, t + in.off, in.Nn * in.nx, s);
-  }
+  kry::scombine<TK>(p, basis, p->krylov_coef, kDotsStride, p->krylov_cnt, t, s);
   kry::add_to<TK>(chi, t, n, s);
   e = hipStreamSynchronize(s);
   return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;

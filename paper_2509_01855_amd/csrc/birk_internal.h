@@ -93,6 +93,46 @@ struct PairSet {
   int64_t parts = 0;          // doubles of partials needed
 };
 
+// Inverse-preconditioner scan of one instance (birk_solve.hip): level sizes and the
+// offsets of its aggregates and start states in the plan's scan scratch.
+constexpr int kPinvMaxLevels = 8;
+struct PinvDesc {
+  int64_t Nn = 0, off = 0, joff = 0, jcoff = 0, jsw_off = 0;
+  const double* w = nullptr;            // CC weights
+  int64_t cnt[kPinvMaxLevels] = {};     // cnt[0] chunks of kChunk nodes, then groups of kFan
+  int64_t agg[kPinvMaxLevels] = {};     // aggregate offsets (doubles) per level
+  int64_t st[kPinvMaxLevels] = {};      // start-state offsets (doubles) per level
+  int L = 0;                            // top level
+  int nb0 = 0;                          // level-0 blocks of 64 groups
+};
+
+// Instances with one state count n_x: each scan phase is one launch over all of them.
+struct PinvClass {
+  int nx = 0;
+  int ninst = 0;
+  int Lmax = 0;
+  std::vector<PinvDesc> host;
+  PinvDesc* dev = nullptr;
+  int2* t_node0 = nullptr;                   // (k, block) over level-0 threads
+  int n_node0 = 0;
+  int2* t_up[kPinvMaxLevels] = {};           // (k, block) over cnt[l + 1] parents of level l
+  int n_up[kPinvMaxLevels] = {};
+  int2* t_swz[2] = {nullptr, nullptr};       // (k, block * E + field) of the layout pass [constant J, per node]
+  int n_swz[2] = {0, 0};
+  int2* t_nodes = nullptr;                   // (k, block of 256 nodes): J x
+  int n_nodes = 0;
+};
+
+// Krylov vector segmentation: tiles of kSegChunk elements, each inside one instance.
+constexpr int kSegChunk = 2048;
+struct SegSet {
+  int2* tiles = nullptr;    // (instance, chunk)
+  int ntiles = 0;
+  int2* ranges = nullptr;   // per instance [first tile, end tile)
+  int64_t* ioff = nullptr;  // per instance vector offset
+  int64_t* ilen = nullptr;  // per instance length n_x N_n
+};
+
 }  // namespace birk
 
 struct birk_plan {
@@ -102,6 +142,8 @@ struct birk_plan {
   std::vector<birk::Instance> inst;
   std::vector<birk::FastGroup> fgroups;
   birk::PairSet gen[2];           // general-path pairs: [0] 2N a power of two, [1] Bluestein
+  std::vector<birk::PinvClass> pclass;  // preconditioner scan schedule, one class per n_x
+  birk::SegSet seg;               // Krylov segmentation of the batch
   std::vector<void*> allocs;      // device tables owned by the plan
   int64_t total_len = 0;
   int64_t total_jnode = 0;
@@ -121,7 +163,9 @@ struct birk_plan {
   void* krylov_Q = nullptr;   // (2m + 1) vectors of the Krylov precision (Q and Z)
   void* krylov_vec = nullptr; // 4 vectors of the Krylov precision
   double* krylov_dots = nullptr;  // [batch][2][kKryMaxDots + 1]
-  double* krylov_part = nullptr;  // reduction partials
+  double* krylov_part = nullptr;  // reduction partials [tiles][kKryMaxDots + 1]
+  double* krylov_coef = nullptr;  // per instance: scale factors / combination coefficients
+  int* krylov_cnt = nullptr;      // per instance: number of combined basis vectors
   int* flag = nullptr;            // device flag: singular pivot seen
   int use_fast = 1;               // power-of-two N takes the three-pass path
   int fast_lds_kb[2] = {128, 64};  // LDS budget per workgroup of the three-pass kernels [8-byte, 4-byte reals]
@@ -159,6 +203,9 @@ hipError_t precond_inverse(birk_plan* p, int jac_kind, const double* J, const T*
                            T* jout, hipStream_t s, int* flag);
 int64_t pinv_scratch(int64_t Nn, int nx);
 int64_t pinv_jsw_size(int64_t Nn, int nx);
+// Build the per-n_x scan classes and the Krylov segmentation (after scan_off, jsw_off
+// and the weights exist); allocations are recorded in p->allocs.
+hipError_t plan_solve(birk_plan* p);
 // Lay out per-node J (or, for constant J, the weights) for the inverse scan; must precede
 // precond_inverse whenever J changes.
 // single = 1 lays the data out in float (for precond_inverse<float>), else in double.
@@ -168,21 +215,24 @@ hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int sing
 constexpr int kKryMaxDots = 32;
 namespace kry {
 template <typename T>
-void dots(const T* Q, int64_t ld, int nq, const T* u, int64_t n, double* part, double* out, hipStream_t s);
-template <typename T>
-void axpys(const T* Q, int64_t ld, int nq, const double* h, T* u, int64_t n, double* part, double* nrm_out,
-           hipStream_t s);
-template <typename T>
-void normalize(const T* u, const double* nrm2, T* q, int64_t n, hipStream_t s);
-template <typename TI, typename TO>
-void scale_conv(const TI* x, TO* y, double alpha, int64_t n, hipStream_t s);
-template <typename T>
 void sub(const T* a, const T* b, T* z, int64_t n, hipStream_t s);
 void residual(const double* beta, const double* x, const double* t, double* r, int64_t n, hipStream_t s);
 template <typename T>
 void add_to(double* x, const T* d, int64_t n, hipStream_t s);
+// Segmented forms over every instance of the batch at once (ld = plan length; per
+// instance i results at out + i * ostride).
 template <typename T>
-void combine(const T* Q, int64_t ld, int nq, const double* c, T* u, int64_t n, hipStream_t s);
+void sdots(const birk_plan* p, const T* Q, int nq, const T* u, double* out, int64_t ostride, hipStream_t s);
+template <typename T>
+void saxpys(const birk_plan* p, const T* Q, int nq, const double* h, int64_t hstride, T* u, double* nrm_out,
+            hipStream_t s);
+template <typename T>
+void snormalize(const birk_plan* p, const T* u, const double* nrm2, int64_t stride, T* q, hipStream_t s);
+template <typename TI, typename TO>
+void sscale_conv(const birk_plan* p, const TI* x, TO* y, const double* alpha, hipStream_t s);
+template <typename T>
+void scombine(const birk_plan* p, const T* Q, const double* c, int64_t cstride, const int* cnt, T* u,
+              hipStream_t s);
 }  // namespace kry
 
 }  // namespace birk

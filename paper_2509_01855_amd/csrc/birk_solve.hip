@@ -31,32 +31,6 @@ namespace birk {
 constexpr int kChunk = 16;
 constexpr int kFan = 16;
 
-// ------------------------------------------------------------------ J x per node
-template <typename T>
-__global__ void k_jac_times(const double* __restrict__ J, int per_node, const T* __restrict__ x,
-                            T* __restrict__ y, int nx, int64_t Nn) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= Nn) return;
-  for (int r = 0; r < nx; ++r) {
-    double acc = 0.0;
-    for (int c = 0; c < nx; ++c) {
-      const double j = per_node ? J[((int64_t)(r * nx + c)) * Nn + k] : J[r * nx + c];
-      acc += j * (double)x[(int64_t)c * Nn + k];
-    }
-    y[(int64_t)r * Nn + k] = (T)acc;
-  }
-}
-
-template <typename T>
-hipError_t jac_times(birk_plan* p, int jac_kind, const double* J, const T* x, T* y, hipStream_t s) {
-  for (const Instance& in : p->inst) {
-    const double* Ji = J + (jac_kind == BIRK_J_PER_NODE ? in.joff : in.jcoff);
-    hipLaunchKernelGGL(k_jac_times<T>, dim3((unsigned)((in.Nn + 255) / 256)), dim3(256), 0, s, Ji,
-                       jac_kind == BIRK_J_PER_NODE ? 1 : 0, x + in.off, y + in.off, in.nx, in.Nn);
-  }
-  return hipGetLastError();
-}
-
 // ------------------------------------------------------------------ P y (forward)
 constexpr int kScanItems = 4;
 constexpr int kScanBlock = 256 * kScanItems;
@@ -227,6 +201,10 @@ __device__ __forceinline__ void form_k(const double (&Jk)[NX][NX], double wk, do
 // i = (tau / 64) % kFan, lane l = tau % 64, g = 64 B + l, c = kFan g + i.
 // Every per-chunk array (swizzled Jacobians, aggregates, start states) is stored as
 // [B][i][field][l], so each access of a wave is 64 consecutive doubles.
+//
+// Batching: the instances of one n_x form a PinvClass; every phase below is one launch
+// over all of them, each block reading its instance from a (k, block) tile and the
+// instance's sizes and scratch offsets from a PinvDesc.
 __device__ __forceinline__ int64_t swz(int64_t B, int i, int field, int nfield, int l) {
   return (((B * kFan + i) * nfield) + field) * 64 + l;
 }
@@ -237,26 +215,31 @@ __device__ __forceinline__ int64_t swz(int64_t B, int i, int field, int nfield, 
 // jsw[(((B kFan + i) kChunk + j) E + e) 64 + l] with E = fields.  Nodes past N_n are zero
 // (identity maps).  One workgroup per (B, i, e): for each of the 64 lanes l it reads the
 // kChunk consecutive nodes of chunk (64 B + l) kFan + i, and writes kChunk rows of 64
-// consecutive lanes, transposing through LDS.
+// consecutive lanes, transposing through LDS.  tile = (k, (B kFan + i) E + e).
 template <typename JT>
-__global__ __launch_bounds__(256) void k_swizzle_nodes(const double* __restrict__ J, int per_node,
-                                                       const double* __restrict__ w, int nx, int64_t Nn,
-                                                       JT* __restrict__ jsw) {
+__global__ __launch_bounds__(256) void k_swizzle_nodes(const double* __restrict__ J, int per_node, int nx,
+                                                       const PinvDesc* __restrict__ pd,
+                                                       const int2* __restrict__ tiles, JT* __restrict__ jsw) {
   __shared__ double tile[64][kChunk + 1];
+  const int2 t = tiles[blockIdx.x];
+  const PinvDesc& d = pd[t.x];
   const int E = per_node ? nx * nx + 1 : 1;
-  const int e = blockIdx.y;
-  const int i = blockIdx.x % kFan;
-  const int64_t B = blockIdx.x / kFan;
-  const double* src = (e == E - 1) ? w : J + (int64_t)e * Nn;
-  for (int t = threadIdx.x; t < 64 * kChunk; t += blockDim.x) {
-    const int l = t / kChunk, j = t % kChunk;
+  const int e = t.y % E;
+  const int bx = t.y / E;
+  const int i = bx % kFan;
+  const int64_t B = bx / kFan;
+  const int64_t Nn = d.Nn;
+  const double* src = (e == E - 1) ? d.w : J + d.joff + (int64_t)e * Nn;
+  JT* dst = jsw + d.jsw_off;
+  for (int q = threadIdx.x; q < 64 * kChunk; q += blockDim.x) {
+    const int l = q / kChunk, j = q % kChunk;
     const int64_t k = (((B * 64 + l) * kFan + i) * kChunk) + j;
     tile[l][j] = (k < Nn) ? src[k] : 0.0;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < 64 * kChunk; t += blockDim.x) {
-    const int l = t & 63, j = t >> 6;
-    jsw[((((B * kFan + i) * kChunk) + j) * E + e) * 64 + l] = (JT)tile[l][j];
+  for (int q = threadIdx.x; q < 64 * kChunk; q += blockDim.x) {
+    const int l = q & 63, j = q >> 6;
+    dst[((((B * kFan + i) * kChunk) + j) * E + e) * 64 + l] = (JT)tile[l][j];
   }
 }
 
@@ -275,18 +258,26 @@ __device__ __forceinline__ void load_jk_sw(const JT* __restrict__ jsw, const dou
 }
 
 // Level-0 up-sweep: each thread reduces one chunk of kChunk nodes to (A, b) with
-// S_out = A S_in + b.
+// S_out = A S_in + b.  tile = (k, block of level-0 threads).
 template <int NX, typename T>
-__global__ __launch_bounds__(256) void k_pinv_up0(const T* __restrict__ jsw, const double* __restrict__ Jc,
-                                                  int per_node, int64_t Nn, const T* __restrict__ y,
-                                                  int64_t nchunks, double* __restrict__ agg, int* flag) {
-  const int64_t tau = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_pinv_up0(const T* __restrict__ jsw, const double* __restrict__ J,
+                                                  int per_node, const T* __restrict__ y,
+                                                  const PinvDesc* __restrict__ pd, const int2* __restrict__ tiles,
+                                                  double* __restrict__ scan, int* flag) {
+  const int2 t = tiles[blockIdx.x];
+  const PinvDesc& d = pd[t.x];
+  const int64_t tau = (int64_t)t.y * blockDim.x + threadIdx.x;
   const int64_t B = tau / (64 * kFan);
   const int i = (int)((tau >> 6) % kFan);
   const int l = (int)(tau & 63);
   const int64_t g = B * 64 + l;
   const int64_t c = g * kFan + i;
-  if (c >= nchunks) return;
+  if (c >= d.cnt[0]) return;
+  const int64_t Nn = d.Nn;
+  const double* Jc = J + d.jcoff;
+  const T* js = jsw + d.jsw_off;
+  const T* yi = y + d.off;
+  double* agg = scan + d.agg[0];
   constexpr int F = NX * NX + NX;
   double A[NX][NX], b[NX];
 #pragma unroll
@@ -300,10 +291,10 @@ __global__ __launch_bounds__(256) void k_pinv_up0(const T* __restrict__ jsw, con
   for (int j = 0; j < jn; ++j) {
     const int64_t k = k0 + j;
     double Jk[NX][NX], K[NX][NX], rp[NX], wk;
-    load_jk_sw<NX, T>(jsw, Jc, per_node, (B * kFan + i) * kChunk + j, Jk, wk);
+    load_jk_sw<NX, T>(js, Jc, per_node, (B * kFan + i) * kChunk + j, Jk, wk);
     double x[NX];
 #pragma unroll
-    for (int r = 0; r < NX; ++r) x[r] = (double)y[(int64_t)r * Nn + k];
+    for (int r = 0; r < NX; ++r) x[r] = (double)yi[(int64_t)r * Nn + k];
     form_k<NX>(Jk, wk, K);
     double jmax = 0.0;
 #pragma unroll
@@ -346,53 +337,53 @@ __global__ __launch_bounds__(256) void k_pinv_up0(const T* __restrict__ jsw, con
   for (int r = 0; r < NX; ++r) agg[swz(B, i, NX * NX + r, F, l)] = b[r];
 }
 
-// Level 0 -> 1 up-sweep: thread per group g combines its kFan chunk aggregates, stored
-// swizzled, into a plain-layout level-1 aggregate.
+// (A, b) <- (a_A A, a_A b + a_b) for the NX x NX + NX fields of aggregate a (field f at
+// a[f * fs]).
 template <int NX>
-__global__ __launch_bounds__(256) void k_pinv_up_sw(const double* __restrict__ child, int64_t nchild,
-                                                    double* __restrict__ parent, int64_t nparent) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nparent) return;
-  constexpr int F = NX * NX + NX;
-  const int64_t B = g >> 6;
-  const int l = (int)(g & 63);
-  double A[NX][NX], b[NX];
+__device__ __forceinline__ void compose(const double* __restrict__ a, int64_t fs, double (&A)[NX][NX],
+                                        double (&b)[NX]) {
+  double nb[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
-    b[r] = 0.0;
+    double acc = a[(NX * NX + r) * fs];
 #pragma unroll
-    for (int q = 0; q < NX; ++q) A[r][q] = (r == q) ? 1.0 : 0.0;
+    for (int q = 0; q < NX; ++q) acc += a[(r * NX + q) * fs] * b[q];
+    nb[r] = acc;
   }
-  const int nc = (int)min((int64_t)kFan, nchild - g * kFan);
-  for (int i = 0; i < nc; ++i) {
-    double a[F];
 #pragma unroll
-    for (int f = 0; f < F; ++f) a[f] = child[swz(B, i, f, F, l)];
-    double nb[NX];
+  for (int col = 0; col < NX; ++col) {
+    double ncol[NX];
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
-      double acc = a[NX * NX + r];
+      double acc = 0.0;
 #pragma unroll
-      for (int q = 0; q < NX; ++q) acc += a[r * NX + q] * b[q];
-      nb[r] = acc;
+      for (int q = 0; q < NX; ++q) acc += a[(r * NX + q) * fs] * A[q][col];
+      ncol[r] = acc;
     }
 #pragma unroll
-    for (int col = 0; col < NX; ++col) {
-      double ncol[NX];
-#pragma unroll
-      for (int r = 0; r < NX; ++r) {
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < NX; ++q) acc += a[r * NX + q] * A[q][col];
-        ncol[r] = acc;
-      }
-#pragma unroll
-      for (int r = 0; r < NX; ++r) A[r][col] = ncol[r];
-    }
-#pragma unroll
-    for (int r = 0; r < NX; ++r) b[r] = nb[r];
+    for (int r = 0; r < NX; ++r) A[r][col] = ncol[r];
   }
-  double* o = parent + g * F;
+#pragma unroll
+  for (int r = 0; r < NX; ++r) b[r] = nb[r];
+}
+
+// s <- a_A s + a_b
+template <int NX>
+__device__ __forceinline__ void advance(const double* __restrict__ a, int64_t fs, double (&s)[NX]) {
+  double ns[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    double acc = a[(NX * NX + r) * fs];
+#pragma unroll
+    for (int q = 0; q < NX; ++q) acc += a[(r * NX + q) * fs] * s[q];
+    ns[r] = acc;
+  }
+#pragma unroll
+  for (int r = 0; r < NX; ++r) s[r] = ns[r];
+}
+
+template <int NX>
+__device__ __forceinline__ void store_agg(double* __restrict__ o, const double (&A)[NX][NX], const double (&b)[NX]) {
 #pragma unroll
   for (int r = 0; r < NX; ++r)
 #pragma unroll
@@ -401,181 +392,121 @@ __global__ __launch_bounds__(256) void k_pinv_up_sw(const double* __restrict__ c
   for (int r = 0; r < NX; ++r) o[NX * NX + r] = b[r];
 }
 
-// Level 1 -> 0 down-sweep: group g pushes its start state through its chunks, writing
-// swizzled chunk start states.
 template <int NX>
-__global__ __launch_bounds__(256) void k_pinv_down_sw(const double* __restrict__ child, int64_t nchild,
-                                                      const double* __restrict__ pstate, int64_t nparent,
-                                                      double* __restrict__ cstate) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nparent) return;
-  constexpr int F = NX * NX + NX;
-  const int64_t B = g >> 6;
-  const int l = (int)(g & 63);
-  double s[NX];
-#pragma unroll
-  for (int r = 0; r < NX; ++r) s[r] = pstate[g * NX + r];
-  const int nc = (int)min((int64_t)kFan, nchild - g * kFan);
-  for (int i = 0; i < nc; ++i) {
-#pragma unroll
-    for (int r = 0; r < NX; ++r) cstate[swz(B, i, r, NX, l)] = s[r];
-    double ns[NX];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      double acc = child[swz(B, i, NX * NX + r, F, l)];
-#pragma unroll
-      for (int q = 0; q < NX; ++q) acc += child[swz(B, i, r * NX + q, F, l)] * s[q];
-      ns[r] = acc;
-    }
-#pragma unroll
-    for (int r = 0; r < NX; ++r) s[r] = ns[r];
-  }
-}
-
-// Up-sweep one level: thread per parent combines up to kFan child aggregates in order.
-template <int NX>
-__global__ __launch_bounds__(256) void k_pinv_up(const double* __restrict__ child, int64_t nchild,
-                                                 double* __restrict__ parent, int64_t nparent) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nparent) return;
-  constexpr int S = NX * NX + NX;
-  double A[NX][NX], b[NX];
+__device__ __forceinline__ void identity_agg(double (&A)[NX][NX], double (&b)[NX]) {
 #pragma unroll
   for (int r = 0; r < NX; ++r) {
     b[r] = 0.0;
 #pragma unroll
     for (int q = 0; q < NX; ++q) A[r][q] = (r == q) ? 1.0 : 0.0;
   }
-  const int64_t c0 = g * kFan, c1 = min(c0 + (int64_t)kFan, nchild);
-  for (int64_t c = c0; c < c1; ++c) {
-    const double* a = child + c * S;
-    // (A, b) <- (Ac A, Ac b + bc)
-    double nb[NX];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      double acc = a[NX * NX + r];
-#pragma unroll
-      for (int q = 0; q < NX; ++q) acc += a[r * NX + q] * b[q];
-      nb[r] = acc;
-    }
-#pragma unroll
-    for (int col = 0; col < NX; ++col) {
-      double nc[NX];
-#pragma unroll
-      for (int r = 0; r < NX; ++r) {
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < NX; ++q) acc += a[r * NX + q] * A[q][col];
-        nc[r] = acc;
-      }
-#pragma unroll
-      for (int r = 0; r < NX; ++r) A[r][col] = nc[r];
-    }
-#pragma unroll
-    for (int r = 0; r < NX; ++r) b[r] = nb[r];
-  }
-  double* o = parent + g * S;
-#pragma unroll
-  for (int r = 0; r < NX; ++r)
-#pragma unroll
-    for (int q = 0; q < NX; ++q) o[r * NX + q] = A[r][q];
-#pragma unroll
-  for (int r = 0; r < NX; ++r) o[NX * NX + r] = b[r];
 }
 
-// Top: one thread walks the top-level aggregates from S = 0, writing start states.
+// Up-sweep level lv -> lv + 1: thread per parent combines its kFan child aggregates in
+// order; level 0 is read swizzled.  tile = (k, block over cnt[lv + 1]).
 template <int NX>
-__global__ void k_pinv_top(const double* __restrict__ agg, int64_t n, double* __restrict__ state) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  constexpr int S = NX * NX + NX;
-  double s[NX];
-#pragma unroll
-  for (int r = 0; r < NX; ++r) s[r] = 0.0;
-  for (int64_t i = 0; i < n; ++i) {
-    const double* a = agg + i * S;
-#pragma unroll
-    for (int r = 0; r < NX; ++r) state[i * NX + r] = s[r];
-    double ns[NX];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      double acc = a[NX * NX + r];
-#pragma unroll
-      for (int q = 0; q < NX; ++q) acc += a[r * NX + q] * s[q];
-      ns[r] = acc;
-    }
-#pragma unroll
-    for (int r = 0; r < NX; ++r) s[r] = ns[r];
-  }
-}
-
-// Single group (at most kFan chunks): walk the swizzled level-0 aggregates of group 0
-// from S = 0 and write their swizzled start states.
-template <int NX>
-__global__ void k_pinv_top1(const double* __restrict__ agg, int64_t n, double* __restrict__ state) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+__global__ __launch_bounds__(256) void k_pinv_up(double* __restrict__ scan, const PinvDesc* __restrict__ pd,
+                                                 const int2* __restrict__ tiles, int lv) {
+  const int2 t = tiles[blockIdx.x];
+  const PinvDesc& d = pd[t.x];
+  const int64_t g = (int64_t)t.y * blockDim.x + threadIdx.x;
+  if (g >= d.cnt[lv + 1]) return;
   constexpr int F = NX * NX + NX;
+  const double* child = scan + d.agg[lv];
+  const int64_t nchild = d.cnt[lv];
+  double A[NX][NX], b[NX];
+  identity_agg<NX>(A, b);
+  const int nc = (int)min((int64_t)kFan, nchild - g * kFan);
+  for (int i = 0; i < nc; ++i) {
+    if (lv == 0) compose<NX>(child + swz(g >> 6, i, 0, F, (int)(g & 63)), 64, A, b);
+    else compose<NX>(child + (g * kFan + i) * F, 1, A, b);
+  }
+  store_agg<NX>(scan + d.agg[lv + 1] + g * F, A, b);
+}
+
+// Top: one thread per instance walks the top-level aggregates from S = 0 and writes
+// their start states (level 0 swizzled when the instance has a single group).
+template <int NX>
+__global__ void k_pinv_top(double* __restrict__ scan, const PinvDesc* __restrict__ pd) {
+  if (threadIdx.x != 0) return;
+  const PinvDesc& d = pd[blockIdx.x];
+  constexpr int F = NX * NX + NX;
+  const int L = d.L;
+  const double* agg = scan + d.agg[L];
+  double* state = scan + d.st[L];
   double s[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) s[r] = 0.0;
-  for (int i = 0; i < (int)n; ++i) {
+  for (int64_t i = 0; i < d.cnt[L]; ++i) {
+    if (L == 0) {
 #pragma unroll
-    for (int r = 0; r < NX; ++r) state[swz(0, i, r, NX, 0)] = s[r];
-    double ns[NX];
+      for (int r = 0; r < NX; ++r) state[swz(0, (int)i, r, NX, 0)] = s[r];
+      advance<NX>(agg + swz(0, (int)i, 0, F, 0), 64, s);
+    } else {
 #pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      double acc = agg[swz(0, i, NX * NX + r, F, 0)];
-#pragma unroll
-      for (int q = 0; q < NX; ++q) acc += agg[swz(0, i, r * NX + q, F, 0)] * s[q];
-      ns[r] = acc;
+      for (int r = 0; r < NX; ++r) state[i * NX + r] = s[r];
+      advance<NX>(agg + i * F, 1, s);
     }
-#pragma unroll
-    for (int r = 0; r < NX; ++r) s[r] = ns[r];
   }
 }
 
-// Down-sweep one level: thread per parent pushes its start state through its children.
+// Down-sweep level lv + 1 -> lv: thread per parent pushes its start state through its
+// children (level 0 written swizzled).  tile = (k, block over cnt[lv + 1]).
 template <int NX>
-__global__ __launch_bounds__(256) void k_pinv_down(const double* __restrict__ child, int64_t nchild,
-                                                   const double* __restrict__ pstate, int64_t nparent,
-                                                   double* __restrict__ cstate) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nparent) return;
-  constexpr int S = NX * NX + NX;
+__global__ __launch_bounds__(256) void k_pinv_down(double* __restrict__ scan, const PinvDesc* __restrict__ pd,
+                                                   const int2* __restrict__ tiles, int lv) {
+  const int2 t = tiles[blockIdx.x];
+  const PinvDesc& d = pd[t.x];
+  const int64_t g = (int64_t)t.y * blockDim.x + threadIdx.x;
+  if (g >= d.cnt[lv + 1]) return;
+  constexpr int F = NX * NX + NX;
+  const double* child = scan + d.agg[lv];
+  double* cstate = scan + d.st[lv];
+  const double* pstate = scan + d.st[lv + 1];
   double s[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) s[r] = pstate[g * NX + r];
-  const int64_t c0 = g * kFan, c1 = min(c0 + (int64_t)kFan, nchild);
-  for (int64_t c = c0; c < c1; ++c) {
-    const double* a = child + c * S;
+  const int nc = (int)min((int64_t)kFan, d.cnt[lv] - g * kFan);
+  for (int i = 0; i < nc; ++i) {
+    if (lv == 0) {
+      const int64_t B = g >> 6;
+      const int l = (int)(g & 63);
 #pragma unroll
-    for (int r = 0; r < NX; ++r) cstate[c * NX + r] = s[r];
-    double ns[NX];
+      for (int r = 0; r < NX; ++r) cstate[swz(B, i, r, NX, l)] = s[r];
+      advance<NX>(child + swz(B, i, 0, F, l), 64, s);
+    } else {
+      const int64_t c = g * kFan + i;
 #pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      double acc = a[NX * NX + r];
-#pragma unroll
-      for (int q = 0; q < NX; ++q) acc += a[r * NX + q] * s[q];
-      ns[r] = acc;
+      for (int r = 0; r < NX; ++r) cstate[c * NX + r] = s[r];
+      advance<NX>(child + c * F, 1, s);
     }
-#pragma unroll
-    for (int r = 0; r < NX; ++r) s[r] = ns[r];
   }
 }
 
 // Replay each chunk from its start state (same thread layout as k_pinv_up0): xi_k and
 // (J xi)_k.
 template <int NX, typename T>
-__global__ __launch_bounds__(256) void k_pinv_final(const T* __restrict__ jsw, const double* __restrict__ Jc,
-                                                    int per_node, int64_t Nn, const T* __restrict__ y,
-                                                    int64_t nchunks, const double* __restrict__ state,
-                                                    T* __restrict__ out, T* __restrict__ jout) {
-  const int64_t tau = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_pinv_final(const T* __restrict__ jsw, const double* __restrict__ J,
+                                                    int per_node, const T* __restrict__ y,
+                                                    const PinvDesc* __restrict__ pd, const int2* __restrict__ tiles,
+                                                    const double* __restrict__ scan, T* __restrict__ out,
+                                                    T* __restrict__ jout) {
+  const int2 t = tiles[blockIdx.x];
+  const PinvDesc& d = pd[t.x];
+  const int64_t tau = (int64_t)t.y * blockDim.x + threadIdx.x;
   const int64_t B = tau / (64 * kFan);
   const int i = (int)((tau >> 6) % kFan);
   const int l = (int)(tau & 63);
   const int64_t g = B * 64 + l;
   const int64_t c = g * kFan + i;
-  if (c >= nchunks) return;
+  if (c >= d.cnt[0]) return;
+  const int64_t Nn = d.Nn;
+  const double* Jc = J + d.jcoff;
+  const T* js = jsw + d.jsw_off;
+  const T* yi = y + d.off;
+  T* oi = out + d.off;
+  T* ji = jout ? jout + d.off : nullptr;
+  const double* state = scan + d.st[0];
   double s[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) s[r] = state[swz(B, i, r, NX, l)];
@@ -584,10 +515,10 @@ __global__ __launch_bounds__(256) void k_pinv_final(const T* __restrict__ jsw, c
   for (int j = 0; j < jn; ++j) {
     const int64_t k = k0 + j;
     double Jk[NX][NX], K[NX][NX], rp[NX], wk;
-    load_jk_sw<NX, T>(jsw, Jc, per_node, (B * kFan + i) * kChunk + j, Jk, wk);
+    load_jk_sw<NX, T>(js, Jc, per_node, (B * kFan + i) * kChunk + j, Jk, wk);
     double x[NX];
 #pragma unroll
-    for (int r = 0; r < NX; ++r) x[r] = s[r] + (double)y[(int64_t)r * Nn + k];
+    for (int r = 0; r < NX; ++r) x[r] = s[r] + (double)yi[(int64_t)r * Nn + k];
     form_k<NX>(Jk, wk, K);
     lu_kmat<NX>(K, rp, nullptr, 1.0);
     lu_solve<NX>(K, rp, x);
@@ -597,9 +528,36 @@ __global__ __launch_bounds__(256) void k_pinv_final(const T* __restrict__ jsw, c
 #pragma unroll
       for (int q = 0; q < NX; ++q) acc += Jk[r][q] * x[q];
       s[r] += wk * acc;
-      out[(int64_t)r * Nn + k] = (T)x[r];
-      if (jout) jout[(int64_t)r * Nn + k] = (T)acc;
+      oi[(int64_t)r * Nn + k] = (T)x[r];
+      if (ji) ji[(int64_t)r * Nn + k] = (T)acc;
     }
+  }
+}
+
+// y_k = J_k x_k per node for every instance of a class.  tile = (k, block of 256 nodes).
+template <int NX, typename T>
+__global__ __launch_bounds__(256) void k_jac_class(const double* __restrict__ J, int per_node,
+                                                   const T* __restrict__ x, T* __restrict__ y,
+                                                   const PinvDesc* __restrict__ pd, const int2* __restrict__ tiles) {
+  const int2 t = tiles[blockIdx.x];
+  const PinvDesc& d = pd[t.x];
+  const int64_t k = (int64_t)t.y * blockDim.x + threadIdx.x;
+  const int64_t Nn = d.Nn;
+  if (k >= Nn) return;
+  const T* xi = x + d.off;
+  T* yi = y + d.off;
+  double xv[NX];
+#pragma unroll
+  for (int c = 0; c < NX; ++c) xv[c] = (double)xi[(int64_t)c * Nn + k];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      const double j = per_node ? J[d.joff + ((int64_t)(r * NX + c)) * Nn + k] : J[d.jcoff + r * NX + c];
+      acc += j * xv[c];
+    }
+    yi[(int64_t)r * Nn + k] = (T)acc;
   }
 }
 
@@ -609,7 +567,7 @@ static inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 
 static int pinv_levels(int64_t Nn, int64_t* cnt) {
   int L = 0;
   cnt[0] = (Nn + kChunk - 1) / kChunk;
-  while (cnt[L] > kFan && L < 15) {
+  while (cnt[L] > kFan && L < kPinvMaxLevels - 1) {
     cnt[L + 1] = (cnt[L] + kFan - 1) / kFan;
     ++L;
   }
@@ -623,118 +581,201 @@ static int64_t pinv_blocks0(int64_t nchunks) {
 }
 
 int64_t pinv_jsw_size(int64_t Nn, int nx) {
-  int64_t cnt[16];
+  int64_t cnt[kPinvMaxLevels];
   pinv_levels(Nn, cnt);
   return pinv_blocks0(cnt[0]) * 64 * kFan * kChunk * ((int64_t)nx * nx + 1);
-}
-
-hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s) {
-  const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
-  for (const Instance& in : p->inst) {
-    int64_t cnt[16];
-    pinv_levels(in.Nn, cnt);
-    const int64_t nslots = pinv_blocks0(cnt[0]) * kFan * kChunk;
-    const int E = pn ? in.nx * in.nx + 1 : 1;
-    const double* Ji = J + (pn ? in.joff : in.jcoff);
-    const dim3 grid((unsigned)(pinv_blocks0(cnt[0]) * kFan), E);
-    (void)nslots;
-    if (single)
-      hipLaunchKernelGGL(k_swizzle_nodes<float>, grid, dim3(256), 0, s, Ji, pn, in.w, in.nx, in.Nn,
-                         (float*)p->jsw + in.jsw_off);
-    else
-      hipLaunchKernelGGL(k_swizzle_nodes<double>, grid, dim3(256), 0, s, Ji, pn, in.w, in.nx, in.Nn,
-                         p->jsw + in.jsw_off);
-  }
-  return hipGetLastError();
-}
-
-template <int NX, typename T>
-static void pinv_instance(birk_plan* p, const Instance& in, const double* Ji, int pn, const T* y, T* out,
-                          T* jout, int* flag, hipStream_t s) {
-  constexpr int S = NX * NX + NX;
-  int64_t cnt[16];
-  const int L = pinv_levels(in.Nn, cnt);
-  // scratch: for each level l: agg[cnt[l] * S], then state[cnt[l] * NX]; level 0 swizzled
-  const int64_t nb0 = pinv_blocks0(cnt[0]);
-  double* base = p->scan + in.scan_off;
-  double* agg[16];
-  double* st[16];
-  for (int l = 0; l <= L; ++l) {
-    const int64_t slots = (l == 0) ? nb0 * 64 * kFan : cnt[l];
-    agg[l] = base;
-    base += slots * S;
-    st[l] = base;
-    base += slots * NX;
-  }
-  // per-node data in the plan's storage type (float copies for float products)
-  const T* jsw = (const T*)p->jsw + in.jsw_off;
-  const int64_t thr0 = nb0 * 64 * kFan;
-  hipLaunchKernelGGL((k_pinv_up0<NX, T>), dim3(nblocks(thr0, 256)), dim3(256), 0, s, jsw, Ji, pn, in.Nn, y, cnt[0],
-                     agg[0], flag);
-  if (L == 0) {
-    // a single group of at most kFan chunks: walk it from zero in one thread
-    hipLaunchKernelGGL((k_pinv_top1<NX>), dim3(1), dim3(64), 0, s, agg[0], cnt[0], st[0]);
-  } else {
-    hipLaunchKernelGGL((k_pinv_up_sw<NX>), dim3(nblocks(cnt[1], 256)), dim3(256), 0, s, agg[0], cnt[0], agg[1],
-                       cnt[1]);
-    for (int l = 1; l < L; ++l)
-      hipLaunchKernelGGL((k_pinv_up<NX>), dim3(nblocks(cnt[l + 1], 256)), dim3(256), 0, s, agg[l], cnt[l],
-                         agg[l + 1], cnt[l + 1]);
-    hipLaunchKernelGGL((k_pinv_top<NX>), dim3(1), dim3(64), 0, s, agg[L], cnt[L], st[L]);
-    for (int l = L - 1; l >= 1; --l)
-      hipLaunchKernelGGL((k_pinv_down<NX>), dim3(nblocks(cnt[l + 1], 256)), dim3(256), 0, s, agg[l], cnt[l],
-                         st[l + 1], cnt[l + 1], st[l]);
-    hipLaunchKernelGGL((k_pinv_down_sw<NX>), dim3(nblocks(cnt[1], 256)), dim3(256), 0, s, agg[0], cnt[0], st[1],
-                       cnt[1], st[0]);
-  }
-  hipLaunchKernelGGL((k_pinv_final<NX, T>), dim3(nblocks(thr0, 256)), dim3(256), 0, s, jsw, Ji, pn, in.Nn, y,
-                     cnt[0], st[0], out, jout);
 }
 
 // Scratch (doubles) the inverse scan needs for one instance (level 0 in whole blocks).
 int64_t pinv_scratch(int64_t Nn, int nx) {
   const int64_t S = (int64_t)nx * nx + 2 * nx;
-  int64_t cnt[16];
+  int64_t cnt[kPinvMaxLevels];
   const int L = pinv_levels(Nn, cnt);
   int64_t tot = pinv_blocks0(cnt[0]) * 64 * kFan * S;
   for (int l = 1; l <= L; ++l) tot += cnt[l] * S;
   return tot;
 }
 
-template <typename T>
-hipError_t precond_inverse(birk_plan* p, int jac_kind, const double* J, const T* y, T* out, T* jout,
-                           hipStream_t s, int* flag) {
-  // the per-node data must have been swizzled for this J by precond_prepare
-  const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
-  for (const Instance& in : p->inst) {
-    const double* Ji = J + (pn ? in.joff : in.jcoff);
-    const T* yi = y + in.off;
-    T* oi = out + in.off;
-    T* ji = jout ? jout + in.off : nullptr;
-    switch (in.nx) {
-#define BIRK_PINV_CASE(n) \
-  case n:                 \
-    pinv_instance<n, T>(p, in, Ji, pn, yi, oi, ji, flag, s); \
-    break;
-      BIRK_PINV_CASE(1)
-      BIRK_PINV_CASE(2)
-      BIRK_PINV_CASE(3)
-      BIRK_PINV_CASE(4)
-      BIRK_PINV_CASE(5)
-      BIRK_PINV_CASE(6)
-      BIRK_PINV_CASE(7)
-      BIRK_PINV_CASE(8)
-      BIRK_PINV_CASE(9)
-      BIRK_PINV_CASE(10)
-      BIRK_PINV_CASE(11)
-      BIRK_PINV_CASE(12)
-#undef BIRK_PINV_CASE
-      default:
-        return hipErrorInvalidValue;
+static hipError_t upload_tiles(birk_plan* p, const std::vector<int2>& v, int2** dst) {
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, std::max<size_t>(v.size(), 1) * sizeof(int2));
+  if (e != hipSuccess) return e;
+  p->allocs.push_back(d);
+  *dst = (int2*)d;
+  if (v.empty()) return hipSuccess;
+  return hipMemcpy(d, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice);
+}
+
+hipError_t plan_solve(birk_plan* p) {
+  hipError_t e = hipSuccess;
+  p->pclass.clear();
+  for (int nx = 1; nx <= 12; ++nx) {
+    PinvClass pc;
+    pc.nx = nx;
+    for (const Instance& in : p->inst) {
+      if (in.nx != nx) continue;
+      PinvDesc d;
+      d.Nn = in.Nn;
+      d.off = in.off;
+      d.joff = in.joff;
+      d.jcoff = in.jcoff;
+      d.jsw_off = in.jsw_off;
+      d.w = in.w;
+      d.L = pinv_levels(in.Nn, d.cnt);
+      d.nb0 = (int)pinv_blocks0(d.cnt[0]);
+      // scratch: for each level l: agg[slots * S] then state[slots * NX]; level 0 swizzled
+      const int64_t S = (int64_t)nx * nx + nx;
+      int64_t base = in.scan_off;
+      for (int l = 0; l <= d.L; ++l) {
+        const int64_t slots = (l == 0) ? (int64_t)d.nb0 * 64 * kFan : d.cnt[l];
+        d.agg[l] = base;
+        base += slots * S;
+        d.st[l] = base;
+        base += slots * nx;
+      }
+      pc.host.push_back(d);
+      pc.Lmax = std::max(pc.Lmax, d.L);
     }
+    if (pc.host.empty()) continue;
+    pc.ninst = (int)pc.host.size();
+    std::vector<int2> t0, tn, tsw[2], tup[kPinvMaxLevels];
+    for (int k = 0; k < pc.ninst; ++k) {
+      const PinvDesc& d = pc.host[k];
+      const int64_t thr0 = (int64_t)d.nb0 * 64 * kFan;
+      for (unsigned b = 0; b < nblocks(thr0, 256); ++b) t0.push_back(make_int2(k, (int)b));
+      for (unsigned b = 0; b < nblocks(d.Nn, 256); ++b) tn.push_back(make_int2(k, (int)b));
+      for (int pn = 0; pn < 2; ++pn) {
+        const int E = pn ? nx * nx + 1 : 1;
+        for (int64_t bx = 0; bx < (int64_t)d.nb0 * kFan; ++bx)
+          for (int f = 0; f < E; ++f) tsw[pn].push_back(make_int2(k, (int)(bx * E + f)));
+      }
+      for (int l = 0; l < d.L; ++l)
+        for (unsigned b = 0; b < nblocks(d.cnt[l + 1], 256); ++b) tup[l].push_back(make_int2(k, (int)b));
+    }
+    void* dd = nullptr;
+    if ((e = hipMalloc(&dd, pc.host.size() * sizeof(PinvDesc))) != hipSuccess) return e;
+    p->allocs.push_back(dd);
+    pc.dev = (PinvDesc*)dd;
+    if ((e = hipMemcpy(dd, pc.host.data(), pc.host.size() * sizeof(PinvDesc), hipMemcpyHostToDevice)) != hipSuccess)
+      return e;
+    if ((e = upload_tiles(p, t0, &pc.t_node0)) != hipSuccess) return e;
+    pc.n_node0 = (int)t0.size();
+    if ((e = upload_tiles(p, tn, &pc.t_nodes)) != hipSuccess) return e;
+    pc.n_nodes = (int)tn.size();
+    for (int pn = 0; pn < 2; ++pn) {
+      if ((e = upload_tiles(p, tsw[pn], &pc.t_swz[pn])) != hipSuccess) return e;
+      pc.n_swz[pn] = (int)tsw[pn].size();
+    }
+    for (int l = 0; l < pc.Lmax; ++l) {
+      if ((e = upload_tiles(p, tup[l], &pc.t_up[l])) != hipSuccess) return e;
+      pc.n_up[l] = (int)tup[l].size();
+    }
+    p->pclass.push_back(std::move(pc));
+  }
+  // Krylov segmentation
+  {
+    const int B = (int)p->inst.size();
+    std::vector<int2> tiles, ranges(B);
+    std::vector<int64_t> ioff(B), ilen(B);
+    for (int i = 0; i < B; ++i) {
+      const Instance& in = p->inst[i];
+      ioff[i] = in.off;
+      ilen[i] = in.Nn * in.nx;
+      ranges[i].x = (int)tiles.size();
+      for (int64_t c = 0; c * kSegChunk < ilen[i]; ++c) tiles.push_back(make_int2(i, (int)c));
+      ranges[i].y = (int)tiles.size();
+    }
+    SegSet& sg = p->seg;
+    sg.ntiles = (int)tiles.size();
+    if ((e = upload_tiles(p, tiles, &sg.tiles)) != hipSuccess) return e;
+    if ((e = upload_tiles(p, ranges, &sg.ranges)) != hipSuccess) return e;
+    void* d1 = nullptr;
+    void* d2 = nullptr;
+    if ((e = hipMalloc(&d1, B * sizeof(int64_t))) != hipSuccess) return e;
+    p->allocs.push_back(d1);
+    if ((e = hipMalloc(&d2, B * sizeof(int64_t))) != hipSuccess) return e;
+    p->allocs.push_back(d2);
+    sg.ioff = (int64_t*)d1;
+    sg.ilen = (int64_t*)d2;
+    if ((e = hipMemcpy(d1, ioff.data(), B * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess) return e;
+    if ((e = hipMemcpy(d2, ilen.data(), B * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s) {
+  const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
+  for (const PinvClass& pc : p->pclass) {
+    if (pc.n_swz[pn] == 0) continue;
+    if (single)
+      hipLaunchKernelGGL(k_swizzle_nodes<float>, dim3(pc.n_swz[pn]), dim3(256), 0, s, J, pn, pc.nx, pc.dev,
+                         pc.t_swz[pn], (float*)p->jsw);
+    else
+      hipLaunchKernelGGL(k_swizzle_nodes<double>, dim3(pc.n_swz[pn]), dim3(256), 0, s, J, pn, pc.nx, pc.dev,
+                         pc.t_swz[pn], p->jsw);
   }
   return hipGetLastError();
 }
+
+template <int NX, typename T>
+static void pinv_class(birk_plan* p, const PinvClass& pc, const double* J, int pn, const T* y, T* out, T* jout,
+                       int* flag, hipStream_t s) {
+  const T* jsw = (const T*)p->jsw;
+  double* scan = p->scan;
+  hipLaunchKernelGGL((k_pinv_up0<NX, T>), dim3(pc.n_node0), dim3(256), 0, s, jsw, J, pn, y, pc.dev, pc.t_node0, scan,
+                     flag);
+  for (int l = 0; l < pc.Lmax; ++l)
+    hipLaunchKernelGGL((k_pinv_up<NX>), dim3(pc.n_up[l]), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
+  hipLaunchKernelGGL((k_pinv_top<NX>), dim3(pc.ninst), dim3(64), 0, s, scan, pc.dev);
+  for (int l = pc.Lmax - 1; l >= 0; --l)
+    hipLaunchKernelGGL((k_pinv_down<NX>), dim3(pc.n_up[l]), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
+  hipLaunchKernelGGL((k_pinv_final<NX, T>), dim3(pc.n_node0), dim3(256), 0, s, jsw, J, pn, y, pc.dev, pc.t_node0,
+                     scan, out, jout);
+}
+
+template <int NX, typename T>
+static void jac_class(const PinvClass& pc, const double* J, int pn, const T* x, T* y, hipStream_t s) {
+  hipLaunchKernelGGL((k_jac_class<NX, T>), dim3(pc.n_nodes), dim3(256), 0, s, J, pn, x, y, pc.dev, pc.t_nodes);
+}
+
+#define BIRK_NX_SWITCH(nx, CALL)                                       \
+  switch (nx) {                                                        \
+    case 1: { constexpr int NXC = 1; CALL; } break;                    \
+    case 2: { constexpr int NXC = 2; CALL; } break;                    \
+    case 3: { constexpr int NXC = 3; CALL; } break;                    \
+    case 4: { constexpr int NXC = 4; CALL; } break;                    \
+    case 5: { constexpr int NXC = 5; CALL; } break;                    \
+    case 6: { constexpr int NXC = 6; CALL; } break;                    \
+    case 7: { constexpr int NXC = 7; CALL; } break;                    \
+    case 8: { constexpr int NXC = 8; CALL; } break;                    \
+    case 9: { constexpr int NXC = 9; CALL; } break;                    \
+    case 10: { constexpr int NXC = 10; CALL; } break;                  \
+    case 11: { constexpr int NXC = 11; CALL; } break;                  \
+    case 12: { constexpr int NXC = 12; CALL; } break;                  \
+    default: return hipErrorInvalidValue;                              \
+  }
+
+template <typename T>
+hipError_t precond_inverse(birk_plan* p, int jac_kind, const double* J, const T* y, T* out, T* jout,
+                           hipStream_t s, int* flag) {
+  // the per-node data must have been laid out for this J by precond_prepare
+  const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
+  for (const PinvClass& pc : p->pclass) {
+    BIRK_NX_SWITCH(pc.nx, (pinv_class<NXC, T>(p, pc, J, pn, y, out, jout, flag, s)))
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t jac_times(birk_plan* p, int jac_kind, const double* J, const T* x, T* y, hipStream_t s) {
+  const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
+  for (const PinvClass& pc : p->pclass) {
+    BIRK_NX_SWITCH(pc.nx, (jac_class<NXC, T>(pc, J, pn, x, y, s)))
+  }
+  return hipGetLastError();
+}
+
+#undef BIRK_NX_SWITCH
 
 template hipError_t jac_times<double>(birk_plan*, int, const double*, const double*, double*, hipStream_t);
 template hipError_t jac_times<float>(birk_plan*, int, const double*, const float*, float*, hipStream_t);
@@ -746,87 +787,8 @@ template hipError_t precond_inverse<float>(birk_plan*, int, const double*, const
                                            hipStream_t, int*);
 
 // ------------------------------------------------------------------ Krylov BLAS-1
-// Dot products of u with up to kMaxDots basis vectors plus ||u||^2, accumulated in
-// double.  part[block][nq + 1]; k_reduce_parts then sums blocks in a fixed order.
+// Krylov BLAS-1: at most kMaxDots basis vectors per call, reductions in double.
 constexpr int kMaxDots = 32;
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_dots(const T* __restrict__ Q, int64_t ld, int nq,
-                                              const T* __restrict__ u, int64_t n, double* __restrict__ part) {
-  double acc[kMaxDots + 1];
-#pragma unroll
-  for (int i = 0; i <= kMaxDots; ++i) acc[i] = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    const double ue = (double)u[e];
-#pragma unroll
-    for (int i = 0; i < kMaxDots; ++i)
-      if (i < nq) acc[i] += (double)Q[(int64_t)i * ld + e] * ue;
-    acc[kMaxDots] += ue * ue;
-  }
-  __shared__ double sh[256];
-#pragma unroll
-  for (int i = 0; i <= kMaxDots; ++i) {
-    if (i < nq || i == kMaxDots) {
-      const double s = block_sum256(acc[i], sh);
-      if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (kMaxDots + 1) + i] = s;
-    }
-  }
-}
-
-// One block per needed output (index blockIdx.x < nq, or the norm slot kMaxDots for the
-// last block): strided partial sums, then a fixed-order tree; deterministic.
-__global__ __launch_bounds__(256) void k_reduce_parts(const double* __restrict__ part, int nblk, int nq,
-                                                      double* __restrict__ out) {
-  __shared__ double sh[256];
-  const int i = (blockIdx.x < (unsigned)nq) ? (int)blockIdx.x : kMaxDots;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(int64_t)b * (kMaxDots + 1) + i];
-  const double t = block_sum256(s, sh);
-  if (threadIdx.x == 0) out[i] = t;
-}
-
-// u -= sum_i h[i] Q_i ; optionally part <- block sums of ||u||^2
-template <typename T>
-__global__ __launch_bounds__(256) void k_axpys(const T* __restrict__ Q, int64_t ld, int nq,
-                                               const double* __restrict__ h, T* __restrict__ u, int64_t n,
-                                               double* __restrict__ part) {
-  __shared__ double hs[kMaxDots];
-  if (threadIdx.x < kMaxDots) hs[threadIdx.x] = threadIdx.x < nq ? h[threadIdx.x] : 0.0;
-  __syncthreads();
-  double nrm = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    double ue = (double)u[e];
-#pragma unroll
-    for (int i = 0; i < kMaxDots; ++i)
-      if (i < nq) ue -= hs[i] * (double)Q[(int64_t)i * ld + e];
-    const T us = (T)ue;
-    u[e] = us;
-    nrm += (double)us * (double)us;
-  }
-  if (part) {
-    __shared__ double sh[256];
-    const double s = block_sum256(nrm, sh);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (kMaxDots + 1) + kMaxDots] = s;
-  }
-}
-
-// q = u / sqrt(nrm2[0])
-template <typename T>
-__global__ void k_normalize(const T* __restrict__ u, const double* __restrict__ nrm2, T* __restrict__ q,
-                            int64_t n) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const double inv = 1.0 / sqrt(nrm2[0]);
-  q[e] = (T)((double)u[e] * inv);
-}
-
-// y = alpha * x (type conversion allowed)
-template <typename TI, typename TO>
-__global__ void k_scale_conv(const TI* __restrict__ x, TO* __restrict__ y, double alpha, int64_t n) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  y[e] = (TO)(alpha * (double)x[e]);
-}
 
 // z = a - b  (FastAX step 3)
 template <typename T>
@@ -852,14 +814,116 @@ __global__ void k_add_to(double* __restrict__ x, const T* __restrict__ d, int64_
   x[e] += (double)d[e];
 }
 
-// u = sum_i c_i Q_i with c on the host side passed through a small device array
+// ---- segmented forms: one launch over every instance of the batch ----
+// A tile is kSegChunk consecutive elements of one instance; partial results go to
+// part[tile][kMaxDots + 1] and are summed per instance over its tile range in a fixed
+// order.
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_combine(const T* __restrict__ Q, int64_t ld, int nq,
-                                                 const double* __restrict__ c, T* __restrict__ u, int64_t n) {
-  __shared__ double cs[kMaxDots];
-  if (threadIdx.x < kMaxDots) cs[threadIdx.x] = threadIdx.x < nq ? c[threadIdx.x] : 0.0;
+__global__ __launch_bounds__(256) void k_sdots(const T* __restrict__ Q, int64_t ld, int nq, const T* __restrict__ u,
+                                               SegSet sg, double* __restrict__ part) {
+  const int2 t = sg.tiles[blockIdx.x];
+  const int64_t base = sg.ioff[t.x] + (int64_t)t.y * kSegChunk;
+  const int64_t end = sg.ioff[t.x] + min((int64_t)(t.y + 1) * kSegChunk, sg.ilen[t.x]);
+  double acc[kMaxDots + 1];
+#pragma unroll
+  for (int i = 0; i <= kMaxDots; ++i) acc[i] = 0.0;
+  for (int64_t e = base + threadIdx.x; e < end; e += blockDim.x) {
+    const double ue = (double)u[e];
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i)
+      if (i < nq) acc[i] += (double)Q[(int64_t)i * ld + e] * ue;
+    acc[kMaxDots] += ue * ue;
+  }
+  __shared__ double sh[256];
+#pragma unroll
+  for (int i = 0; i <= kMaxDots; ++i) {
+    if (i < nq || i == kMaxDots) {
+      const double v = block_sum256(acc[i], sh);
+      if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (kMaxDots + 1) + i] = v;
+    }
+  }
+}
+
+// grid = (nq + 1, instances): block (x, i) sums output x (x == nq: the norm slot) of
+// instance i over its tiles into out[i * ostride + slot].
+__global__ __launch_bounds__(256) void k_sreduce(const double* __restrict__ part, SegSet sg, int nq,
+                                                 double* __restrict__ out, int64_t ostride) {
+  __shared__ double sh[256];
+  const int i = blockIdx.y;
+  const int slot = (blockIdx.x < (unsigned)nq) ? (int)blockIdx.x : kMaxDots;
+  const int2 r = sg.ranges[i];
+  double s = 0.0;
+  for (int b = r.x + threadIdx.x; b < r.y; b += blockDim.x) s += part[(int64_t)b * (kMaxDots + 1) + slot];
+  const double tot = block_sum256(s, sh);
+  if (threadIdx.x == 0) out[(int64_t)i * ostride + slot] = tot;
+}
+
+// u -= sum_k h[i][k] Q_k on instance i's tiles; part <- tile sums of ||u||^2 when asked
+template <typename T>
+__global__ __launch_bounds__(256) void k_saxpys(const T* __restrict__ Q, int64_t ld, int nq,
+                                                const double* __restrict__ h, int64_t hstride, T* __restrict__ u,
+                                                SegSet sg, double* __restrict__ part) {
+  const int2 t = sg.tiles[blockIdx.x];
+  __shared__ double hs[kMaxDots];
+  if (threadIdx.x < kMaxDots) hs[threadIdx.x] = (int)threadIdx.x < nq ? h[(int64_t)t.x * hstride + threadIdx.x] : 0.0;
   __syncthreads();
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t base = sg.ioff[t.x] + (int64_t)t.y * kSegChunk;
+  const int64_t end = sg.ioff[t.x] + min((int64_t)(t.y + 1) * kSegChunk, sg.ilen[t.x]);
+  double nrm = 0.0;
+  for (int64_t e = base + threadIdx.x; e < end; e += blockDim.x) {
+    double ue = (double)u[e];
+#pragma unroll
+    for (int i = 0; i < kMaxDots; ++i)
+      if (i < nq) ue -= hs[i] * (double)Q[(int64_t)i * ld + e];
+    const T us = (T)ue;
+    u[e] = us;
+    nrm += (double)us * (double)us;
+  }
+  if (part) {
+    __shared__ double sh[256];
+    const double v = block_sum256(nrm, sh);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (kMaxDots + 1) + kMaxDots] = v;
+  }
+}
+
+// q = u / sqrt(nrm2[i]) on instance i's tiles; a zero or non-finite norm writes zeros
+// (the instance has stopped; its later basis vectors are never combined).
+template <typename T>
+__global__ __launch_bounds__(256) void k_snormalize(const T* __restrict__ u, const double* __restrict__ nrm2,
+                                                    int64_t stride, T* __restrict__ q, SegSet sg) {
+  const int2 t = sg.tiles[blockIdx.x];
+  const double n2 = nrm2[(int64_t)t.x * stride];
+  const double inv = (n2 > 0.0 && isfinite(n2)) ? 1.0 / sqrt(n2) : 0.0;
+  const int64_t base = sg.ioff[t.x] + (int64_t)t.y * kSegChunk;
+  const int64_t end = sg.ioff[t.x] + min((int64_t)(t.y + 1) * kSegChunk, sg.ilen[t.x]);
+  for (int64_t e = base + threadIdx.x; e < end; e += blockDim.x) q[e] = (T)(inv == 0.0 ? 0.0 : (double)u[e] * inv);
+}
+
+// y = alpha[i] x on instance i's tiles
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_sscale_conv(const TI* __restrict__ x, TO* __restrict__ y,
+                                                     const double* __restrict__ alpha, SegSet sg) {
+  const int2 t = sg.tiles[blockIdx.x];
+  const double a = alpha[t.x];
+  const int64_t base = sg.ioff[t.x] + (int64_t)t.y * kSegChunk;
+  const int64_t end = sg.ioff[t.x] + min((int64_t)(t.y + 1) * kSegChunk, sg.ilen[t.x]);
+  for (int64_t e = base + threadIdx.x; e < end; e += blockDim.x) y[e] = (TO)(a == 0.0 ? 0.0 : a * (double)x[e]);
+}
+
+// u = sum_{k < cnt[i]} c[i][k] Q_k on instance i's tiles
+template <typename T>
+__global__ __launch_bounds__(256) void k_scombine(const T* __restrict__ Q, int64_t ld, const double* __restrict__ c,
+                                                  int64_t cstride, const int* __restrict__ cnt, T* __restrict__ u,
+                                                  SegSet sg) {
+  const int2 t = sg.tiles[blockIdx.x];
+  const int nq = cnt[t.x];
+  __shared__ double cs[kMaxDots];
+  if (threadIdx.x < kMaxDots) cs[threadIdx.x] = (int)threadIdx.x < nq ? c[(int64_t)t.x * cstride + threadIdx.x] : 0.0;
+  __syncthreads();
+  const int64_t base = sg.ioff[t.x] + (int64_t)t.y * kSegChunk;
+  const int64_t end = sg.ioff[t.x] + min((int64_t)(t.y + 1) * kSegChunk, sg.ilen[t.x]);
+  for (int64_t e = base + threadIdx.x; e < end; e += blockDim.x) {
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < kMaxDots; ++i)
@@ -870,36 +934,6 @@ __global__ __launch_bounds__(256) void k_combine(const T* __restrict__ Q, int64_
 
 // Host-side launch helpers used by the GMRES driver.
 namespace kry {
-
-static inline unsigned grid_for(int64_t n) {
-  int64_t b = (n + 255) / 256;
-  return (unsigned)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
-}
-
-template <typename T>
-void dots(const T* Q, int64_t ld, int nq, const T* u, int64_t n, double* part, double* out, hipStream_t s) {
-  const unsigned g = grid_for(n);
-  hipLaunchKernelGGL(k_dots<T>, dim3(g), dim3(256), 0, s, Q, ld, nq, u, n, part);
-  hipLaunchKernelGGL(k_reduce_parts, dim3(nq + 1), dim3(256), 0, s, part, (int)g, nq, out);
-}
-
-template <typename T>
-void axpys(const T* Q, int64_t ld, int nq, const double* h, T* u, int64_t n, double* part, double* nrm_out,
-           hipStream_t s) {
-  const unsigned g = grid_for(n);
-  hipLaunchKernelGGL(k_axpys<T>, dim3(g), dim3(256), 0, s, Q, ld, nq, h, u, n, part);
-  if (part) hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, part, (int)g, 0, nrm_out);
-}
-
-template <typename T>
-void normalize(const T* u, const double* nrm2, T* q, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_normalize<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, u, nrm2, q, n);
-}
-
-template <typename TI, typename TO>
-void scale_conv(const TI* x, TO* y, double alpha, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL((k_scale_conv<TI, TO>), dim3(nblocks(n, 256)), dim3(256), 0, s, x, y, alpha, n);
-}
 
 template <typename T>
 void sub(const T* a, const T* b, T* z, int64_t n, hipStream_t s) {
@@ -916,28 +950,59 @@ void add_to(double* x, const T* d, int64_t n, hipStream_t s) {
 }
 
 template <typename T>
-void combine(const T* Q, int64_t ld, int nq, const double* c, T* u, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_combine<T>, dim3(grid_for(n)), dim3(256), 0, s, Q, ld, nq, c, u, n);
+void sdots(const birk_plan* p, const T* Q, int nq, const T* u, double* out, int64_t ostride, hipStream_t s) {
+  const SegSet& sg = p->seg;
+  hipLaunchKernelGGL(k_sdots<T>, dim3(sg.ntiles), dim3(256), 0, s, Q, p->total_len, nq, u, sg, p->krylov_part);
+  hipLaunchKernelGGL(k_sreduce, dim3(nq + 1, (unsigned)p->inst.size()), dim3(256), 0, s, p->krylov_part, sg, nq, out,
+                     ostride);
 }
 
-template void dots<double>(const double*, int64_t, int, const double*, int64_t, double*, double*, hipStream_t);
-template void dots<float>(const float*, int64_t, int, const float*, int64_t, double*, double*, hipStream_t);
-template void axpys<double>(const double*, int64_t, int, const double*, double*, int64_t, double*, double*,
+template <typename T>
+void saxpys(const birk_plan* p, const T* Q, int nq, const double* h, int64_t hstride, T* u, double* nrm_out,
+            hipStream_t s) {
+  const SegSet& sg = p->seg;
+  hipLaunchKernelGGL(k_saxpys<T>, dim3(sg.ntiles), dim3(256), 0, s, Q, p->total_len, nq, h, hstride, u, sg,
+                     nrm_out ? p->krylov_part : nullptr);
+  if (nrm_out)
+    hipLaunchKernelGGL(k_sreduce, dim3(1, (unsigned)p->inst.size()), dim3(256), 0, s, p->krylov_part, sg, 0, nrm_out,
+                       hstride);
+}
+
+template <typename T>
+void snormalize(const birk_plan* p, const T* u, const double* nrm2, int64_t stride, T* q, hipStream_t s) {
+  hipLaunchKernelGGL(k_snormalize<T>, dim3(p->seg.ntiles), dim3(256), 0, s, u, nrm2, stride, q, p->seg);
+}
+
+template <typename TI, typename TO>
+void sscale_conv(const birk_plan* p, const TI* x, TO* y, const double* alpha, hipStream_t s) {
+  hipLaunchKernelGGL((k_sscale_conv<TI, TO>), dim3(p->seg.ntiles), dim3(256), 0, s, x, y, alpha, p->seg);
+}
+
+template <typename T>
+void scombine(const birk_plan* p, const T* Q, const double* c, int64_t cstride, const int* cnt, T* u,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_scombine<T>, dim3(p->seg.ntiles), dim3(256), 0, s, Q, p->total_len, c, cstride, cnt, u,
+                     p->seg);
+}
+
+template void sdots<double>(const birk_plan*, const double*, int, const double*, double*, int64_t, hipStream_t);
+template void sdots<float>(const birk_plan*, const float*, int, const float*, double*, int64_t, hipStream_t);
+template void saxpys<double>(const birk_plan*, const double*, int, const double*, int64_t, double*, double*,
+                             hipStream_t);
+template void saxpys<float>(const birk_plan*, const float*, int, const double*, int64_t, float*, double*,
                             hipStream_t);
-template void axpys<float>(const float*, int64_t, int, const double*, float*, int64_t, double*, double*,
-                           hipStream_t);
-template void normalize<double>(const double*, const double*, double*, int64_t, hipStream_t);
-template void normalize<float>(const float*, const double*, float*, int64_t, hipStream_t);
-template void scale_conv<double, double>(const double*, double*, double, int64_t, hipStream_t);
-template void scale_conv<double, float>(const double*, float*, double, int64_t, hipStream_t);
-template void scale_conv<float, double>(const float*, double*, double, int64_t, hipStream_t);
-template void scale_conv<float, float>(const float*, float*, double, int64_t, hipStream_t);
+template void snormalize<double>(const birk_plan*, const double*, const double*, int64_t, double*, hipStream_t);
+template void snormalize<float>(const birk_plan*, const float*, const double*, int64_t, float*, hipStream_t);
+template void sscale_conv<double, double>(const birk_plan*, const double*, double*, const double*, hipStream_t);
+template void sscale_conv<double, float>(const birk_plan*, const double*, float*, const double*, hipStream_t);
+template void scombine<double>(const birk_plan*, const double*, const double*, int64_t, const int*, double*,
+                               hipStream_t);
+template void scombine<float>(const birk_plan*, const float*, const double*, int64_t, const int*, float*,
+                              hipStream_t);
+
 template void sub<double>(const double*, const double*, double*, int64_t, hipStream_t);
 template void sub<float>(const float*, const float*, float*, int64_t, hipStream_t);
 template void add_to<double>(double*, const double*, int64_t, hipStream_t);
 template void add_to<float>(double*, const float*, int64_t, hipStream_t);
-template void combine<double>(const double*, int64_t, int, const double*, double*, int64_t, hipStream_t);
-template void combine<float>(const float*, int64_t, int, const double*, float*, int64_t, hipStream_t);
-
 }  // namespace kry
 }  // namespace birk

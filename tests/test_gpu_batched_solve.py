@@ -1,0 +1,87 @@
+"""GPU parity of the batched solve: 512 LTI instances of uneven size (N_n log-uniform in
+[2^8, 2^16], n_x in {4, 6, 12}) solved together by one plan, in double and in the
+mixed mode (float GMRES inside double refinement), to relative residual 1e-10.
+
+Reference: the exact solution of the LTI initial-value problem, X(tau) = expm(A (tau + 1))
+x_a (pinned against the oracle's dense solve in the CPU tests), at sampled nodes; the
+Birkhoff collocation solution equals it to rounding at these N.  kappa ~ 5, so residual
+1e-10 bounds the solution error near 5e-10; the bar is 1e-9.  Batching must not change
+any instance's arithmetic: a batched solve equals single-instance solves bit for bit.
+"""
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import birkhoff as bk
+from oracle import system as sy
+from paper_2509_01855_amd import workloads as wl
+from tests.gpu_util import announce, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2509_01855_amd import birk
+    return birk
+
+
+def _solve_batch(B, insts, prec, rtol):
+    import torch
+    plan = B.birk_plan_create([i.N_n for i in insts], [i.n_x for i in insts], prec)
+    J = np.concatenate([i.J.ravel() for i in insts])
+    beta = np.concatenate([sy.beta_vector(i.x_a, i.N_n) for i in insts])
+    Jd = dev(J, torch.float64)
+    bd = dev(beta, torch.float64)
+    xd = torch.zeros_like(bd)
+    info = B.birk_krylov_solve(plan, Jd, bd, xd, B.BIRK_J_CONSTANT, raise_on_error=False, rtol=rtol)
+    torch.cuda.synchronize()
+    x = host(xd)
+    plan.destroy()
+    return x, info
+
+
+def _closed_form_err(inst, X, nsample=33):
+    tau = bk.cgl_nodes(inst.N_n - 1)
+    idx = np.unique(np.linspace(0, inst.N_n - 1, nsample).astype(int))
+    Xe = np.stack([scipy.linalg.expm(inst.J * (tau[k] + 1.0)) @ inst.x_a for k in idx], axis=1)
+    return float(np.max(np.abs(X[:, idx] - Xe)) / np.max(np.abs(Xe)))
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_batched_solve_512(B, prec):
+    insts = wl.batched_instances(count=512)
+    announce(f"batched solve 512 instances prec={prec}")
+    p = B.BIRK_F64 if prec == "f64" else B.BIRK_F32_REFINE_F64
+    x, info = _solve_batch(B, insts, p, 1e-10)
+    st = np.asarray(info["inst_status"])
+    rr = np.asarray(info["rel_resid"])
+    announce(f"  status ok {int(np.sum(st == 0))}/512, worst residual {rr.max():.3e}, "
+             f"inner iterations {min(info['inner_iters'])}..{max(info['inner_iters'])}, "
+             f"outer {min(info['outer_iters'])}..{max(info['outer_iters'])}")
+    assert info["status"] == 0 and np.all(st == 0)
+    assert rr.max() <= 1e-10
+    worst = 0.0
+    o = 0
+    for k, ins in enumerate(insts):
+        n = ins.n_x * ins.N_n
+        if k % 8 == 0:
+            worst = max(worst, _closed_form_err(ins, x[o:o + n].reshape(ins.n_x, ins.N_n)))
+        o += n
+    announce(f"  worst closed-form error over sampled instances {worst:.3e}")
+    assert worst <= 1e-9
+
+
+def test_batched_solve_equals_single(B):
+    insts = wl.batched_instances(count=24)
+    announce("batched solve of 24 instances vs single-instance solves")
+    x, info = _solve_batch(B, insts, B.BIRK_F64, 1e-12)
+    assert info["status"] == 0
+    offs = np.cumsum([0] + [i.n_x * i.N_n for i in insts])
+    for k in (0, 5, 11, 23):
+        xs, inf1 = _solve_batch(B, [insts[k]], B.BIRK_F64, 1e-12)
+        assert inf1["inner_iters"][0] == info["inner_iters"][k]
+        assert np.array_equal(xs, x[offs[k]:offs[k + 1]])
