@@ -155,8 +155,14 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     if (l64) p->fast_lds_kb[0] = std::max(16, std::min(160, std::atoi(l64)));
     if (l32) p->fast_lds_kb[1] = std::max(16, std::min(160, std::atoi(l32)));
     if (sp) p->fast_split = std::atoi(sp) ? 1 : 0;
-    const char* pp = std::getenv("BIRK_FAST_PPT");
-    if (pp) p->fast_ppt = std::atoi(pp) == 16 ? 16 : 8;
+    const char* tb = std::getenv("BIRK_FAST_TB");
+    if (tb) p->fast_tb = std::max(0, std::min(14, std::atoi(tb))) & ~1;
+    const char* bt = std::getenv("BIRK_FAST_B_THREADS");
+    if (bt) p->fast_b_threads = std::atoi(bt) <= 256 ? 256 : 512;
+    const char* xc = std::getenv("BIRK_FAST_XCD");
+    if (xc) p->fast_xcd = std::atoi(xc) ? 1 : 0;
+    const char* b2 = std::getenv("BIRK_FAST_B2");
+    if (b2) p->fast_b2 = std::atoi(b2) ? 1 : 0;
   }
   p->inst.resize(batch);
   int64_t off = 0, joff = 0, jcoff = 0, soff = 0, jswoff = 0;

@@ -14,7 +14,7 @@
 // rows produced by the first DCT are exactly the columns the second one needs:
 //
 //   pass A: columns of DCT 1                       x        -> G  [k1][n2]
-//   pass B: rows of DCT 1, the coefficient stencil          G -> G2 [q1][r]
+//   pass B: rows of DCT 1, the coefficient stencil          G -> G2 [r][q1]
 //           (eq:c_k=bydef with the alias of eq:chatk=), columns of DCT 2
 //   pass C: rows of DCT 2, plus the constant c^_0 term      G2 -> out
 //
@@ -55,14 +55,7 @@ __device__ __forceinline__ cplx<T> conjg(cplx<T> a) {
   return mk<T>(a.x, -a.y);
 }
 
-// W_2N^t from the two-level table, t in [0, 2N)
-template <typename T>
-__device__ __forceinline__ cplx<T> tw2n(const cplx<T>* __restrict__ hi, const cplx<T>* __restrict__ lo, int sh,
-                                        int64_t t) {
-  return cmul<T>(hi[t >> sh], lo[t & ((int64_t(1) << sh) - 1)]);
-}
-
-// ---- in-register DFTs of length 2, 4, 8, 16 (forward, W_R = exp(-2 pi i / R)) ----
+// ---- in-register DFTs of length 2, 4, 8 (forward, W_R = exp(-2 pi i / R)) ----
 // vr/vi hold the R inputs in natural order and receive the R outputs in natural order.
 template <typename T>
 __device__ __forceinline__ void dft4(T& ar, T& ai, T& br, T& bi, T& cr, T& ci, T& dr, T& di) {
@@ -96,7 +89,8 @@ __device__ __forceinline__ void dft_reg(T (&vr)[R], T (&vi)[R]) {
     vi[1] = ai - vi[1];
   } else if constexpr (R == 4) {
     dft4<T>(vr[0], vi[0], vr[1], vi[1], vr[2], vi[2], vr[3], vi[3]);
-  } else if constexpr (R == 8) {
+  } else {
+    static_assert(R == 8, "radix 2, 4 or 8");
     // n = q + 2p, k = s + 4t: two DFT4 over p, twiddle W8^(q s), DFT2 over q
     dft4<T>(vr[0], vi[0], vr[2], vi[2], vr[4], vi[4], vr[6], vi[6]);
     dft4<T>(vr[1], vi[1], vr[3], vi[3], vr[5], vi[5], vr[7], vi[7]);
@@ -119,42 +113,6 @@ __device__ __forceinline__ void dft_reg(T (&vr)[R], T (&vi)[R]) {
       vr[i] = outr[i];
       vi[i] = outi[i];
     }
-  } else {
-    // R == 16: n = q + 4p, k = s + 4t: four DFT4 over p, twiddle W16^(q s), four DFT4 over q
-#pragma unroll
-    for (int q = 0; q < 4; ++q) dft4<T>(vr[q], vi[q], vr[q + 4], vi[q + 4], vr[q + 8], vi[q + 8], vr[q + 12], vi[q + 12]);
-    // element (q, s) now sits at index q + 4 s
-    const T c1 = T(0.92387953251128675613);  // cos(pi/8)
-    const T s1 = T(0.38268343236508977173);  // sin(pi/8)
-    const T h = T(0.70710678118654752440);
-    // W16^m = (cos(2 pi m/16), -sin(2 pi m/16)), m = q s
-    cmul_inplace<T>(vr[1 + 4], vi[1 + 4], c1, -s1);    // q1 s1: m1
-    cmul_inplace<T>(vr[1 + 8], vi[1 + 8], h, -h);      // q1 s2: m2
-    cmul_inplace<T>(vr[1 + 12], vi[1 + 12], s1, -c1);  // q1 s3: m3
-    cmul_inplace<T>(vr[2 + 4], vi[2 + 4], h, -h);      // q2 s1: m2
-    { const T a = vr[2 + 8]; vr[2 + 8] = vi[2 + 8]; vi[2 + 8] = -a; }  // q2 s2: m4 = -i
-    cmul_inplace<T>(vr[2 + 12], vi[2 + 12], -h, -h);   // q2 s3: m6
-    cmul_inplace<T>(vr[3 + 4], vi[3 + 4], s1, -c1);    // q3 s1: m3
-    cmul_inplace<T>(vr[3 + 8], vi[3 + 8], -h, -h);     // q3 s2: m6
-    cmul_inplace<T>(vr[3 + 12], vi[3 + 12], -c1, s1);  // q3 s3: m9
-#pragma unroll
-    for (int sI = 0; sI < 4; ++sI)
-      dft4<T>(vr[4 * sI], vi[4 * sI], vr[4 * sI + 1], vi[4 * sI + 1], vr[4 * sI + 2], vi[4 * sI + 2],
-              vr[4 * sI + 3], vi[4 * sI + 3]);
-    // element (s, t) now sits at index 4 s + t; output k = s + 4 t
-    T outr[16], outi[16];
-#pragma unroll
-    for (int sI = 0; sI < 4; ++sI)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        outr[sI + 4 * t] = vr[4 * sI + t];
-        outi[sI + 4 * t] = vi[4 * sI + t];
-      }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      vr[i] = outr[i];
-      vi[i] = outi[i];
-    }
   }
 }
 
@@ -164,22 +122,63 @@ __device__ __forceinline__ void dft_reg(T (&vr)[R], T (&vi)[R]) {
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int padded_ld(int L) { return L + (L >> 4) + 1; }
 
+// Complex points per thread in the LDS FFTs: one radix-8 butterfly per thread per stage.
+constexpr int kPPT = 8;
+
+// Twiddles of the radix-8 stages of one FFT length, per thread: a thread's butterfly
+// index within its transform depends only on threadIdx (not on which transforms a
+// chunk holds), so W^(jm), W^(2 jm), W^(4 jm) of every stage with Ns > 1 are read from
+// the table once per kernel and kept in registers; the other powers are products of
+// these.  Entry k belongs to the radix-8 stage at logNs = r + 3 k, r = logL mod 3 (3
+// when logL mod 3 = 0); for 9 <= logL <= 12 there are at most three such stages.
+template <typename T>
+struct TwCache {
+  cplx<T> w[3][3];
+};
+
+__device__ __forceinline__ int tw_base(int logL) {
+  const int rem = logL % 3;
+  return rem ? rem : 3;
+}
+
+// W^(jm), W^(2 jm), W^(4 jm) of the thread's butterfly in the radix-8 stage at logNs.
+template <typename T>
+__device__ __forceinline__ void load_tw_stage(cplx<T> (&w)[3], int logL, int logNs, const cplx<T>* __restrict__ tw) {
+  const int j = threadIdx.x & ((1 << (logL - 3)) - 1);
+  const int jm = logNs < logL ? (j & ((1 << logNs) - 1)) : 0;
+  if (jm != 0) {
+    const int tshift = kLdsMaxLog - (logNs + 3);
+    w[0] = tw[jm << tshift];
+    w[1] = tw[(2 * jm) << tshift];
+    w[2] = tw[(4 * jm) << tshift];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) w[q] = mk<T>(T(1), T(0));
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_twcache(TwCache<T>& c, int logL, const cplx<T>* __restrict__ tw) {
+  const int base = tw_base(logL);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) load_tw_stage<T>(c.w[k], logL, base + 3 * k, tw);
+}
+
 // One radix-R Stockham stage on `count` split-complex transforms: transform t has its
 // real part in row (first + 2t) and imaginary part in row (first + 2t + 1) of a
-// row-major array with `ld` reals per (padded) row.  Each thread owns PPT / R
-// butterflies, i.e. PPT complex values; all reads of the stage precede all writes.
-// Twiddles W_(Ns R)^(jm r) come from the table (powers 1, 2, 4, 8) and products of at
-// most three of them.
-template <typename T, int R, int PPT>
+// row-major array with `ld` reals per (padded) row.  Each thread owns kPPT / R
+// butterflies; all reads of the stage precede all writes.  Radix 2 and 4 occur only as
+// the first stage (Ns = 1, no twiddles); radix-8 stages take the thread's cached
+// twiddles w = (W^jm, W^2jm, W^4jm) of W = W_(8 Ns).
+template <typename T, int R>
 __device__ __forceinline__ void split_stage(T* buf, int first, int ld, int logL, int count, int logNs,
-                                            const cplx<T>* __restrict__ tw) {
-  constexpr int logR = (R == 16) ? 4 : (R == 8) ? 3 : (R == 4) ? 2 : 1;
-  constexpr int NB = PPT / R;
+                                            const cplx<T> (&w)[3]) {
+  constexpr int logR = (R == 8) ? 3 : (R == 4) ? 2 : 1;
+  constexpr int NB = kPPT / R;
   const int logNb = logL - logR;
   const int nb = 1 << logNb;
   const int total = count << logNb;
   const int Ns = 1 << logNs;
-  const int tshift = kLdsMaxLog - (logNs + logR);
   T vr[NB][R], vi[NB][R];
   int dst[NB], tt[NB];
 #pragma unroll
@@ -198,30 +197,18 @@ __device__ __forceinline__ void split_stage(T* buf, int first, int ld, int logL,
         vi[i][r] = im[pad(j + r * nb)];
       }
       const int jm = j & (Ns - 1);
-      if (jm != 0) {
-        // powers 1, 2, 4, 8 from the table; the others as products of at most three
-        const cplx<T> w1 = tw[jm << tshift];
-        cmul_inplace<T>(vr[i][1], vi[i][1], w1.x, w1.y);
-        if constexpr (R > 2) {
-          const cplx<T> w2 = tw[(2 * jm) << tshift];
+      if constexpr (R == 8) {
+        if (jm != 0) {
+          const cplx<T> w1 = w[0], w2 = w[1], w4 = w[2];
           const cplx<T> w3 = cmul<T>(w2, w1);
+          const cplx<T> w5 = cmul<T>(w4, w1), w6 = cmul<T>(w4, w2), w7 = cmul<T>(w4, w3);
+          cmul_inplace<T>(vr[i][1], vi[i][1], w1.x, w1.y);
           cmul_inplace<T>(vr[i][2], vi[i][2], w2.x, w2.y);
           cmul_inplace<T>(vr[i][3], vi[i][3], w3.x, w3.y);
-          if constexpr (R > 4) {
-            const cplx<T> w4 = tw[(4 * jm) << tshift];
-            const cplx<T> w5 = cmul<T>(w4, w1), w6 = cmul<T>(w4, w2), w7 = cmul<T>(w4, w3);
-            cmul_inplace<T>(vr[i][4], vi[i][4], w4.x, w4.y);
-            cmul_inplace<T>(vr[i][5], vi[i][5], w5.x, w5.y);
-            cmul_inplace<T>(vr[i][6], vi[i][6], w6.x, w6.y);
-            cmul_inplace<T>(vr[i][7], vi[i][7], w7.x, w7.y);
-            if constexpr (R > 8) {
-              const cplx<T> w8 = tw[(8 * jm) << tshift];
-              const cplx<T> wa[8] = {w8, cmul<T>(w8, w1), cmul<T>(w8, w2), cmul<T>(w8, w3),
-                                     cmul<T>(w8, w4), cmul<T>(w8, w5), cmul<T>(w8, w6), cmul<T>(w8, w7)};
-#pragma unroll
-              for (int r = 0; r < 8; ++r) cmul_inplace<T>(vr[i][8 + r], vi[i][8 + r], wa[r].x, wa[r].y);
-            }
-          }
+          cmul_inplace<T>(vr[i][4], vi[i][4], w4.x, w4.y);
+          cmul_inplace<T>(vr[i][5], vi[i][5], w5.x, w5.y);
+          cmul_inplace<T>(vr[i][6], vi[i][6], w6.x, w6.y);
+          cmul_inplace<T>(vr[i][7], vi[i][7], w7.x, w7.y);
         }
       }
       dft_reg<T, R>(vr[i], vi[i]);
@@ -245,45 +232,71 @@ __device__ __forceinline__ void split_stage(T* buf, int first, int ld, int logL,
   __syncthreads();
 }
 
-// `count` transforms of length 2^logL, processed in chunks of whole transforms that fit
-// PPT * blockDim.x complex points (2^logL itself must fit).  PPT = 16: radix-16 stages
-// and one radix-2/4/8 stage for the remainder of log2 L; PPT = 8: radix-8 stages and
-// one radix-2/4 stage.
-template <typename T, int PPT>
-__device__ void split_fft_chunk(T* buf, int first, int ld, int logL, int count, const cplx<T>* __restrict__ tw) {
-  int logNs = 0;
-  if constexpr (PPT == 16) {
-    const int rem = logL & 3;
-    if (rem == 1) {
-      split_stage<T, 2, PPT>(buf, first, ld, logL, count, 0, tw);
-      logNs = 1;
-    } else if (rem == 2) {
-      split_stage<T, 4, PPT>(buf, first, ld, logL, count, 0, tw);
-      logNs = 2;
-    } else if (rem == 3) {
-      split_stage<T, 8, PPT>(buf, first, ld, logL, count, 0, tw);
-      logNs = 3;
-    }
-    for (; logNs < logL; logNs += 4) split_stage<T, 16, PPT>(buf, first, ld, logL, count, logNs, tw);
-  } else {
-    const int rem = logL % 3;
-    if (rem == 1) {
-      split_stage<T, 2, PPT>(buf, first, ld, logL, count, 0, tw);
-      logNs = 1;
-    } else if (rem == 2) {
-      split_stage<T, 4, PPT>(buf, first, ld, logL, count, 0, tw);
-      logNs = 2;
-    }
-    for (; logNs < logL; logNs += 3) split_stage<T, 8, PPT>(buf, first, ld, logL, count, logNs, tw);
+// `count` transforms of length 2^logL (9 <= logL <= 12) that fit kPPT * blockDim.x
+// complex points: a first stage of radix 2, 4 or 8 (logL mod 3 = 1, 2, 0; Ns = 1, no
+// twiddles), then radix-8 stages with the cached twiddles.
+template <typename T>
+__device__ __forceinline__ void split_fft_chunk(T* buf, int first, int ld, int logL, int count,
+                                                const TwCache<T>& tc) {
+  const int rem = logL % 3;
+  if (rem == 1) split_stage<T, 2>(buf, first, ld, logL, count, 0, tc.w[0]);
+  else if (rem == 2) split_stage<T, 4>(buf, first, ld, logL, count, 0, tc.w[0]);
+  else split_stage<T, 8>(buf, first, ld, logL, count, 0, tc.w[0]);
+  const int base = tw_base(logL);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int logNs = base + 3 * k;
+    if (logNs < logL) split_stage<T, 8>(buf, first, ld, logL, count, logNs, tc.w[k]);
   }
 }
 
-template <typename T, int PPT>
-__device__ void split_fft(T* buf, int first, int ld, int logL, int count, const cplx<T>* __restrict__ tw) {
-  const int per = max(1, (PPT * (int)blockDim.x) >> logL);
+// The same with the twiddles of each stage read from the table just before it (fewer
+// registers than a TwCache held through the kernel).
+template <typename T>
+__device__ __forceinline__ void split_fft_chunk_tab(T* buf, int first, int ld, int logL, int count,
+                                                    const cplx<T>* __restrict__ tw) {
+  const int rem = logL % 3;
+  cplx<T> w[3];
+  if (rem == 1) split_stage<T, 2>(buf, first, ld, logL, count, 0, w);
+  else if (rem == 2) split_stage<T, 4>(buf, first, ld, logL, count, 0, w);
+  else split_stage<T, 8>(buf, first, ld, logL, count, 0, w);
+  const int base = tw_base(logL);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int logNs = base + 3 * k;
+    if (logNs < logL) {
+      load_tw_stage<T>(w, logL, logNs, tw);
+      split_stage<T, 8>(buf, first, ld, logL, count, logNs, w);
+    }
+  }
+}
+
+// Any number of transforms, in chunks of whole transforms.
+template <typename T>
+__device__ __forceinline__ void split_fft(T* buf, int first, int ld, int logL, int count, const TwCache<T>& tc) {
+  const int per = max(1, (kPPT * (int)blockDim.x) >> logL);
 #pragma nounroll
   for (int t0 = 0; t0 < count; t0 += per)
-    split_fft_chunk<T, PPT>(buf, first + 2 * t0, ld, logL, min(per, count - t0), tw);
+    split_fft_chunk<T>(buf, first + 2 * t0, ld, logL, min(per, count - t0), tc);
+}
+
+// Tile of a one-dimensional grid of nt tiles per component and nc components, mapped
+// so that each XCD (workgroups are dealt to the 8 XCDs round robin) runs a contiguous
+// range of tiles: neighbouring tiles, which share cache lines at their edges, then
+// meet in one L2.
+__device__ __forceinline__ void xcd_tile(int nt, int nc, int xcd_order, int& comp, int& tile) {
+  if (!xcd_order) {
+    comp = (int)blockIdx.x / nt;
+    tile = (int)blockIdx.x - comp * nt;
+    return;
+  }
+  const int total = nt * nc;
+  const int lid = (int)blockIdx.x;
+  const int xcd = lid & 7, idx = lid >> 3;
+  const int q = total >> 3, r = total & 7;
+  const int L = xcd * q + min(xcd, r) + idx;
+  comp = L / nt;
+  tile = L - comp * nt;
 }
 
 // Separate the DFTs of two real sequences a, b from F = DFT(a + i b):
@@ -313,24 +326,29 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // batch are issued before any of them is consumed, so each thread keeps several
 // requests in flight instead of one.
 constexpr int kUnroll = 8;
+constexpr int kUnrollB = 4;  // pass B keeps four complex values per element in flight
 
 // ---------------------------------------------------------------- pass A
 // Columns n2 in [c0, c0 + W) of the even extension of x (optionally with both end
 // points doubled: the E^{-1} pre-factor of the transpose), FFT over n1, keep k1 <= L1/2,
 // twiddle W_2N^(n2 k1), store G[k1][n2] for n2 <= L2/2.  W is a power of two.
-template <typename T, int PPT>
+template <typename T>
 __global__ __launch_bounds__(512) void k_fastA(const T* __restrict__ x, int64_t Nn, int logL1, int logL2, int logW,
                                                cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg,
                                                const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ thi,
-                                               const cplx<T>* __restrict__ tlo, int tsh, int ends2) {
+                                               const cplx<T>* __restrict__ tlo, int tsh, int ends2, int nt, int nc,
+                                               int xcd_order) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* A = reinterpret_cast<T*>(smem_raw);
-  const int comp = blockIdx.y;
+  int comp, tile;
+  xcd_tile(nt, nc, xcd_order, comp, tile);
+  TwCache<T> tc;
+  load_twcache<T>(tc, logL1, tw);
   const T* xc = x + (int64_t)comp * Nn;
   const int N = (int)(Nn - 1), N2 = 2 * N;
   const int L1 = 1 << logL1, L2 = 1 << logL2;
   const int W = 1 << logW;
-  const int c0 = blockIdx.x * W;
+  const int c0 = tile * W;
   const int ld1 = padded_ld(L1);
   const int n = W << logL1;
   for (int base = threadIdx.x; base < n; base += kUnroll * blockDim.x) {
@@ -354,7 +372,7 @@ __global__ __launch_bounds__(512) void k_fastA(const T* __restrict__ x, int64_t 
       if (dst[u] >= 0) A[dst[u]] = val[u];
   }
   __syncthreads();
-  split_fft_chunk<T, PPT>(A, 0, ld1, logL1, W / 2, tw);
+  split_fft_chunk<T>(A, 0, ld1, logL1, W / 2, tc);
   const int half1 = L1 / 2;
   cplx<T>* Gc = G + (int64_t)comp * gcomp;
   const int nout = (half1 + 1) << logW;
@@ -446,20 +464,24 @@ __device__ __forceinline__ double c0_coef(int k, int N) {
   return -ek / (((double)k - 1.0) * ((double)k + 1.0));
 }
 
-template <typename T, int TB, int TRANS, int PPT>
+template <typename T, int TB, int TRANS>
 __global__ __launch_bounds__(512) void k_fastB(const cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg,
                                                cplx<T>* __restrict__ G2, int64_t g2comp, int64_t sg2, int64_t N64,
                                                int logL1, int logL2, const cplx<T>* __restrict__ tw,
                                                const cplx<T>* __restrict__ thi, const cplx<T>* __restrict__ tlo,
-                                               int tsh, double* __restrict__ part) {
+                                               int tsh, double* __restrict__ part, int nt, int nc,
+                                               int xcd_order) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Y = reinterpret_cast<T*>(smem_raw);  // (TB + 2) real rows of L2
   __shared__ double red[16];
-  const int comp = blockIdx.y;
+  int comp, tile;
+  xcd_tile(nt, nc, xcd_order, comp, tile);
+  TwCache<T> tc;
+  load_twcache<T>(tc, logL2, tw);
   const int N = (int)N64;
   const int L1 = 1 << logL1, L2 = 1 << logL2;
   const int half2 = L2 / 2;
-  const int t0 = blockIdx.x * TB;
+  const int t0 = tile * TB;
   const int ld2 = padded_ld(L2);
   const int sgi = (int)sg;
   const cplx<T>* Gc = G + (int64_t)comp * gcomp;
@@ -468,11 +490,11 @@ __global__ __launch_bounds__(512) void k_fastB(const cplx<T>* __restrict__ G, in
   const int hp1 = half2 + 1;
   const int nin = (NR / 2) * hp1;
   const int twsh = kLdsMaxLog - logL2;
-  for (int base = threadIdx.x; base < nin; base += kUnroll * blockDim.x) {
-    cplx<T> ra[kUnroll], rb[kUnroll], wa[kUnroll], wb[kUnroll];
-    int ma[kUnroll], mb[kUnroll], pr_[kUnroll], n2_[kUnroll];
+  for (int base = threadIdx.x; base < nin; base += kUnrollB * blockDim.x) {
+    cplx<T> ra[kUnrollB], rb[kUnrollB], wa[kUnrollB], wb[kUnrollB];
+    int ma[kUnrollB], mb[kUnrollB], pr_[kUnrollB], n2_[kUnrollB];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < kUnrollB; ++u) {
       const int e = base + u * blockDim.x;
       pr_[u] = -1;
       if (e < nin) {
@@ -488,7 +510,7 @@ __global__ __launch_bounds__(512) void k_fastB(const cplx<T>* __restrict__ G, in
       }
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < kUnrollB; ++u) {
       if (pr_[u] < 0) continue;
       cplx<T> a = ra[u], b = rb[u];
       if (ma[u]) a = conjg<T>(a);
@@ -515,7 +537,7 @@ __global__ __launch_bounds__(512) void k_fastB(const cplx<T>* __restrict__ G, in
     p0 = (T)(0.5 * block_sum(acc, red));
   }
   __syncthreads();
-  split_fft<T, PPT>(Y, 0, ld2, logL2, NR / 2, tw);
+  split_fft<T>(Y, 0, ld2, logL2, NR / 2, tc);
   // stencil, one thread per m (owns column m of the tile: no cross-thread hazard)
   double c0acc = 0.0;
   const int N2 = 2 * N;
@@ -544,23 +566,23 @@ __global__ __launch_bounds__(512) void k_fastB(const cplx<T>* __restrict__ G, in
   }
   if (!TRANS) {
     const double tot = block_sum(c0acc, red);
-    if (threadIdx.x == 0) part[(int64_t)comp * gridDim.x + blockIdx.x] = tot;
+    if (threadIdx.x == 0) part[(int64_t)comp * nt + tile] = tot;
   }
   __syncthreads();
   // columns of the second DCT: d rows (1 + 2i, 2 + 2i) as one complex FFT each
-  split_fft<T, PPT>(Y, 1, ld2, logL2, TB / 2, tw);
+  split_fft<T>(Y, 1, ld2, logL2, TB / 2, tc);
   cplx<T>* G2c = G2 + (int64_t)comp * g2comp;
   const int nout = hp1 * TB;
   const int tmask = (1 << tsh) - 1;
   const int sg2i = (int)sg2;
-  for (int base = threadIdx.x; base < nout; base += kUnroll * blockDim.x) {
-    cplx<T> wh[kUnroll], wl[kUnroll], v[kUnroll];
-    int gi[kUnroll];
+  for (int base = threadIdx.x; base < nout; base += kUnrollB * blockDim.x) {
+    cplx<T> wh[kUnrollB], wl[kUnrollB], v[kUnrollB];
+    int gi[kUnrollB];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < kUnrollB; ++u) {
       const int e = base + u * blockDim.x;
       gi[u] = -1;
-      const int q = e / TB, rl = e - q * TB;
+      const int rl = e / hp1, q = e - rl * hp1;
       const int r = t0 + rl;
       if (e < nout && r <= L1 / 2) {
         const int t = r * q;
@@ -570,12 +592,227 @@ __global__ __launch_bounds__(512) void k_fastB(const cplx<T>* __restrict__ G, in
         const T* im = re + ld2;
         const int qm = (L2 - q) & (L2 - 1);
         v[u] = separate<T>(re[pad(q)], im[pad(q)], re[pad(qm)], im[pad(qm)], rl & 1);
-        gi[u] = q * sg2i + r;
+        gi[u] = r * sg2i + q;
       }
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
+    for (int u = 0; u < kUnrollB; ++u)
       if (gi[u] >= 0) G2c[gi[u]] = cmul<T>(v[u], cmul<T>(wh[u], wl[u]));
+  }
+}
+
+// ---- fixed-length transforms: COUNT transforms of length 2^LOGL, blockDim = COUNT 2^LOGL / 8 ----
+// Transform t has its real part in row 2t and its imaginary part in row 2t + 1 of a
+// split array with padded rows of padded_ld(2^LOGL) reals.  With the length known at
+// compile time every LDS address of a butterfly is the padded position of its first
+// element plus a constant: pad(j + r s) = pad(j) + r s + (r s) / 16 for s a power of two
+// (s divides 16 or 16 divides s), so a thread needs one address register per butterfly
+// and the element offsets become instruction immediates.
+template <typename T, int LOGL, int LOGNS, int R, int COUNT>
+__device__ __forceinline__ void stage_ct(T* __restrict__ buf, const cplx<T> (&w)[3]) {
+  constexpr int logR = (R == 8) ? 3 : (R == 4) ? 2 : 1;
+  constexpr int NB = kPPT / R;             // butterflies per thread
+  constexpr int LOGNBF = LOGL - logR;
+  constexpr int NBF = 1 << LOGNBF;         // butterflies per transform
+  constexpr int NTHR = COUNT << (LOGL - 3);  // threads (blockDim)
+  constexpr int NS = 1 << LOGNS;
+  constexpr int LD = padded_ld(1 << LOGL);
+  T vr[NB][R], vi[NB][R];
+  int pd[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = (int)threadIdx.x + i * NTHR;
+    const int t = b >> LOGNBF;
+    const int j = b & (NBF - 1);
+    const int rowoff = 2 * t * LD;
+    const int pj = rowoff + j + (j >> 4);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int off = r * NBF + ((r * NBF) >> 4);
+      vr[i][r] = buf[pj + off];
+      vi[i][r] = buf[pj + LD + off];
+    }
+    const int jm = j & (NS - 1);
+    if constexpr (R == 8 && LOGNS > 0) {
+      if (jm != 0) {
+        const cplx<T> w1 = w[0], w2 = w[1], w4 = w[2];
+        const cplx<T> w3 = cmul<T>(w2, w1);
+        const cplx<T> w5 = cmul<T>(w4, w1), w6 = cmul<T>(w4, w2), w7 = cmul<T>(w4, w3);
+        cmul_inplace<T>(vr[i][1], vi[i][1], w1.x, w1.y);
+        cmul_inplace<T>(vr[i][2], vi[i][2], w2.x, w2.y);
+        cmul_inplace<T>(vr[i][3], vi[i][3], w3.x, w3.y);
+        cmul_inplace<T>(vr[i][4], vi[i][4], w4.x, w4.y);
+        cmul_inplace<T>(vr[i][5], vi[i][5], w5.x, w5.y);
+        cmul_inplace<T>(vr[i][6], vi[i][6], w6.x, w6.y);
+        cmul_inplace<T>(vr[i][7], vi[i][7], w7.x, w7.y);
+      }
+    }
+    dft_reg<T, R>(vr[i], vi[i]);
+    const int dst = ((j >> LOGNS) << (LOGNS + logR)) + jm;
+    pd[i] = rowoff + dst + (dst >> 4);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int off = r * NS + ((r * NS) >> 4);
+      buf[pd[i] + off] = vr[i][r];
+      buf[pd[i] + LD + off] = vi[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int LOGL, int COUNT, int K>
+__device__ __forceinline__ void stages8_ct(T* __restrict__ buf, const cplx<T>* __restrict__ tw) {
+  constexpr int BASE = (LOGL % 3) ? (LOGL % 3) : 3;
+  constexpr int LOGNS = BASE + 3 * K;
+  if constexpr (LOGNS < LOGL) {
+    cplx<T> w[3];
+    load_tw_stage<T>(w, LOGL, LOGNS, tw);
+    stage_ct<T, LOGL, LOGNS, 8, COUNT>(buf, w);
+    stages8_ct<T, LOGL, COUNT, K + 1>(buf, tw);
+  }
+}
+
+// COUNT in-place transforms of length 2^LOGL (see stage_ct for the layout).
+template <typename T, int LOGL, int COUNT>
+__device__ __forceinline__ void fft_ct(T* __restrict__ buf, const cplx<T>* __restrict__ tw) {
+  cplx<T> w[3];
+  if constexpr (LOGL % 3 == 1) stage_ct<T, LOGL, 0, 2, COUNT>(buf, w);
+  else if constexpr (LOGL % 3 == 2) stage_ct<T, LOGL, 0, 4, COUNT>(buf, w);
+  else stage_ct<T, LOGL, 0, 8, COUNT>(buf, w);
+  stages8_ct<T, LOGL, COUNT, 0>(buf, tw);
+}
+
+// Pass B for rows of L2 = 2^LOGL2 (512..2048) points, blockDim = L2 / 8, two rows per
+// tile.  One LDS buffer holds one complex row transform at a time: the pair
+// (t0 - 1, t0) is transformed and each thread keeps its eight outputs
+// m = tid + i blockDim in registers, then the pair (t0 + 1, t0 + 2) the same way, so
+// the stencil of rows t0 and t0 + 1 runs in registers; d(t0) + i d(t0 + 1) then goes
+// back through the buffer for the column transform of DCT 2.  The small LDS footprint
+// (one row pair) lets several workgroups share a CU, which hides the latency of the
+// load / transform / store phases that one large workgroup exposes.
+template <typename T, int TRANS, int LOGL2>
+__global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB2(
+    const cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg, cplx<T>* __restrict__ G2, int64_t g2comp, int64_t sg2,
+    int64_t N64, int logL1, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ thi,
+    const cplx<T>* __restrict__ tlo, int tsh, double* __restrict__ part, int nt, int nc, int xcd_order) {
+  constexpr int L2 = 1 << LOGL2;
+  constexpr int NTHR = L2 / kPPT;
+  constexpr int half2 = L2 / 2, hp1 = half2 + 1;
+  constexpr int ld2 = padded_ld(L2);
+  constexpr int twsh = kLdsMaxLog - LOGL2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Yre = reinterpret_cast<T*>(smem_raw);  // one complex row: real part, imaginary part
+  T* Yim = Yre + ld2;
+  __shared__ double red[16];
+  int comp, tile;
+  xcd_tile(nt, nc, xcd_order, comp, tile);
+  const int N = (int)N64;
+  const int L1 = 1 << logL1;
+  const int t0 = 2 * tile;
+  const int sgi = (int)sg;
+  const cplx<T>* Gc = G + (int64_t)comp * gcomp;
+  T p0 = T(0);
+  if (TRANS) {
+    // Y_0 of the first DCT is the sum of row 0 of the Hermitian G: p_0 = Y_0 / 2
+    double acc = 0.0;
+    for (int n2 = threadIdx.x; n2 <= half2; n2 += NTHR)
+      acc += (double)Gc[n2].x * ((n2 == 0 || n2 == half2) ? 1.0 : 2.0);
+    p0 = (T)(0.5 * block_sum(acc, red));
+  }
+  // DCT-1 rows: yr[p][i] / yi[p][i] = rows t0 - 1 + 2p / t0 + 2p at m = tid + i NTHR
+  T yr[2][kPPT], yi[2][kPPT];
+#pragma unroll
+  for (int pp = 0; pp < 2; ++pp) {
+    int ma, mb;
+    const int sa = hrow_src(t0 - 1 + 2 * pp, L1, &ma);
+    const int sb = hrow_src(t0 + 2 * pp, L1, &mb);
+    constexpr int per = (hp1 + NTHR - 1) / NTHR;  // half-row elements per thread (5)
+#pragma unroll
+    for (int u = 0; u < per; ++u) {
+      const int n2 = (int)threadIdx.x + u * NTHR;
+      if (n2 < hp1) {
+        cplx<T> a = Gc[sa * sgi + n2], b = Gc[sb * sgi + n2];
+        if (ma) a = conjg<T>(a);
+        if (ma == 2) a = cmul<T>(a, tw[n2 << twsh]);
+        if (mb) b = conjg<T>(b);
+        if (mb == 2) b = cmul<T>(b, tw[n2 << twsh]);
+        Yre[pad(n2)] = a.x - b.y;
+        Yim[pad(n2)] = a.y + b.x;
+        if (n2 > 0 && n2 < half2) {
+          Yre[pad(L2 - n2)] = a.x + b.y;
+          Yim[pad(L2 - n2)] = b.x - a.y;
+        }
+      }
+    }
+    __syncthreads();
+    fft_ct<T, LOGL2, 1>(Yre, tw);
+#pragma unroll
+    for (int i = 0; i < kPPT; ++i) {
+      const int m = (int)threadIdx.x + i * NTHR;
+      yr[pp][i] = Yre[pad(m)];
+      yi[pp][i] = Yim[pad(m)];
+    }
+    __syncthreads();
+  }
+  // stencil of rows t0 (neighbours t0 - 1, t0 + 1) and t0 + 1 (neighbours t0, t0 + 2)
+  double c0acc = 0.0;
+  const int N2 = 2 * N;
+  const T invN = T(1) / T(N), inv4N1 = T(1) / T(4 * (int64_t)N + 4), inv2N1 = T(1) / T(2 * (int64_t)N + 2);
+#pragma unroll
+  for (int i = 0; i < kPPT; ++i) {
+    const int m = (int)threadIdx.x + i * NTHR;
+    T dv[2];
+#pragma unroll
+    for (int rl = 0; rl < 2; ++rl) {
+      const int k1 = t0 + rl;
+      const T ylo = rl ? yi[0][i] : yr[0][i];   // row k1 - 1
+      const T yhi = rl ? yi[1][i] : yr[1][i];   // row k1 + 1
+      const T ymid = rl ? yr[1][i] : yi[0][i];  // row k1
+      const int K = k1 + L1 * m;
+      const bool lowhalf = K <= N;
+      const int k = lowhalf ? K : N2 - K;
+      const T Ym = lowhalf ? ylo : yhi;
+      const T Yp = lowhalf ? yhi : ylo;
+      if (TRANS) {
+        dv[rl] = stencil_tr<T>(k, N, Ym, Yp, p0, inv2N1);
+      } else {
+        dv[rl] = stencil_fwd<T>(k, N, Ym, Yp, invN, inv4N1);
+        if (k1 <= L1 / 2 && ((k1 != 0 && k1 != L1 / 2) || lowhalf)) c0acc += c0_coef(k, N) * (double)ymid;
+      }
+    }
+    Yre[pad(m)] = dv[0];
+    Yim[pad(m)] = dv[1];
+  }
+  if (!TRANS) {
+    const double tot = block_sum(c0acc, red);
+    if (threadIdx.x == 0) part[(int64_t)comp * nt + tile] = tot;
+  }
+  __syncthreads();
+  // column transform of DCT 2 on d(t0) + i d(t0 + 1)
+  fft_ct<T, LOGL2, 1>(Yre, tw);
+  cplx<T>* G2c = G2 + (int64_t)comp * g2comp;
+  const int tmask = (1 << tsh) - 1;
+  const int sg2i = (int)sg2;
+#pragma unroll
+  for (int rl = 0; rl < 2; ++rl) {
+    const int r = t0 + rl;
+    if (r > L1 / 2) continue;
+    constexpr int per = (hp1 + NTHR - 1) / NTHR;
+#pragma unroll
+    for (int u = 0; u < per; ++u) {
+      const int q = (int)threadIdx.x + u * NTHR;
+      if (q < hp1) {
+        const int t = r * q;
+        const cplx<T> w = cmul<T>(thi[t >> tsh], tlo[t & tmask]);
+        const int qm = (L2 - q) & (L2 - 1);
+        const cplx<T> v = separate<T>(Yre[pad(q)], Yim[pad(q)], Yre[pad(qm)], Yim[pad(qm)], rl);
+        G2c[r * sg2i + q] = cmul<T>(v, w);
+      }
+    }
   }
 }
 
@@ -583,20 +820,23 @@ __global__ __launch_bounds__(512) void k_fastB(const cplx<T>* __restrict__ G, in
 // Rows q1 in [c0, c0 + W) of the second DCT (Hermitian in r, rebuilt from r <= L1/2),
 // two per complex FFT of length L1, written to the natural output positions
 // j = q1 + L2 q2 and, for 0 < q1 < L2/2, the mirrored j = (L2 - q1) + L2 q2.
-template <typename T, int TRANS, int PPT>
+template <typename T, int TRANS>
 __global__ __launch_bounds__(512) void k_fastC(const cplx<T>* __restrict__ G2, int64_t g2comp, int64_t sg2,
                                                T* __restrict__ out, int64_t Nn, int logL1, int logL2, int logW,
                                                const cplx<T>* __restrict__ tw, const double* __restrict__ part,
-                                               int ntB) {
+                                               int ntB, int nt, int nc, int xcd_order) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* U = reinterpret_cast<T*>(smem_raw);  // W real rows of L1
   __shared__ double red[16];
-  const int comp = blockIdx.y;
+  int comp, tile;
+  xcd_tile(nt, nc, xcd_order, comp, tile);
+  TwCache<T> tc;
+  load_twcache<T>(tc, logL1, tw);
   const int L1 = 1 << logL1, L2 = 1 << logL2;
   const int half1 = L1 / 2, half2 = L2 / 2;
   const int N = (int)(Nn - 1);
   const int W = 1 << logW;
-  const int c0 = blockIdx.x * W;
+  const int c0 = tile * W;
   const int ld1 = padded_ld(L1);
   const int sg2i = (int)sg2;
   T c0hat = T(0);
@@ -607,7 +847,8 @@ __global__ __launch_bounds__(512) void k_fastC(const cplx<T>* __restrict__ G2, i
   }
   const cplx<T>* G2c = G2 + (int64_t)comp * g2comp;
   const int hp1 = half1 + 1;
-  const int nin = (W / 2) * hp1;
+  const int np = W / 2;
+  const int nin = np * hp1;
   for (int base = threadIdx.x; base < nin; base += kUnroll * blockDim.x) {
     cplx<T> ra[kUnroll], rb[kUnroll];
     int pr_[kUnroll], r_[kUnroll];
@@ -616,10 +857,12 @@ __global__ __launch_bounds__(512) void k_fastC(const cplx<T>* __restrict__ G2, i
       const int e = base + u * blockDim.x;
       pr_[u] = -1;
       if (e < nin) {
-        const int pr = e / hp1, r = e - pr * hp1;
+        // G2 row r holds q = 0..L2/2 contiguously: the W columns of this tile are one
+        // contiguous segment per row
+        const int r = e / np, pr = e - r * np;
         const int qa = c0 + 2 * pr, qb = qa + 1;
-        ra[u] = qa <= half2 ? G2c[qa * sg2i + r] : mk<T>(T(0), T(0));
-        rb[u] = qb <= half2 ? G2c[qb * sg2i + r] : mk<T>(T(0), T(0));
+        ra[u] = qa <= half2 ? G2c[r * sg2i + qa] : mk<T>(T(0), T(0));
+        rb[u] = qb <= half2 ? G2c[r * sg2i + qb] : mk<T>(T(0), T(0));
         pr_[u] = pr;
         r_[u] = r;
       }
@@ -639,7 +882,7 @@ __global__ __launch_bounds__(512) void k_fastC(const cplx<T>* __restrict__ G2, i
     }
   }
   __syncthreads();
-  split_fft_chunk<T, PPT>(U, 0, ld1, logL1, W / 2, tw);
+  split_fft_chunk<T>(U, 0, ld1, logL1, W / 2, tc);
   T* oc = out + (int64_t)comp * Nn;
   const T invN = T(1) / T(N);
   const int nout = W * hp1;
@@ -648,6 +891,163 @@ __global__ __launch_bounds__(512) void k_fastC(const cplx<T>* __restrict__ G2, i
     const int q1 = c0 + w;
     if (q1 > half2) continue;
     const T* row = U + w * ld1;
+    if (q2 < half1 || (q1 == 0 && q2 == half1)) {
+      const int j = q1 + L2 * q2;
+      const T u = row[pad(q2)];
+      T o;
+      if (TRANS) o = ((j == 0 || j == N) ? T(0.5) : T(1)) * u * invN;
+      else o = T(0.5) * u + c0hat;
+      oc[j] = o;
+    }
+    if (q1 > 0 && q1 < half2 && q2 < half1) {
+      const int j = (L2 - q1) + L2 * q2;
+      const T u = row[pad(L1 - 1 - q2)];
+      T o;
+      if (TRANS) o = u * invN;
+      else o = T(0.5) * u + c0hat;
+      oc[j] = o;
+    }
+  }
+}
+
+// ---- passes A and C at fixed lengths (L1 = 2^LOGL1, W = 2^LOGW columns per tile,
+// blockDim = W L1 / 16: one radix-8 butterfly per thread per stage) ----
+template <typename T, int LOGL1, int LOGW>
+__global__ __launch_bounds__((1 << LOGW) << (LOGL1 - 4)) void k_fastA2(
+    const T* __restrict__ x, int64_t Nn, int logL2, cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg,
+    const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ thi, const cplx<T>* __restrict__ tlo, int tsh,
+    int ends2, int nt, int nc, int xcd_order) {
+  constexpr int L1 = 1 << LOGL1, W = 1 << LOGW;
+  constexpr int NTHR = W * L1 / 16;
+  constexpr int LD = padded_ld(L1);
+  constexpr int NIN = W * L1;
+  constexpr int PER = NIN / NTHR;  // 16 values per thread
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* A = reinterpret_cast<T*>(smem_raw);
+  int comp, tile;
+  xcd_tile(nt, nc, xcd_order, comp, tile);
+  const T* xc = x + (int64_t)comp * Nn;
+  const int N = (int)(Nn - 1), N2 = 2 * N;
+  const int c0 = tile * W;
+#pragma unroll
+  for (int h = 0; h < PER; h += 8) {
+    T val[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = (int)threadIdx.x + (h + u) * NTHR;
+      const int w = e & (W - 1), n1 = e >> LOGW;
+      const int m = (n1 << logL2) + c0 + w;
+      const int idx = m <= N ? m : N2 - m;
+      val[u] = xc[idx];
+      if (ends2 && (idx == 0 || idx == N)) val[u] *= T(2);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = (int)threadIdx.x + (h + u) * NTHR;
+      const int w = e & (W - 1), n1 = e >> LOGW;
+      A[w * LD + pad(n1)] = val[u];
+    }
+  }
+  __syncthreads();
+  fft_ct<T, LOGL1, W / 2>(A, tw);
+  constexpr int half1 = L1 / 2;
+  cplx<T>* Gc = G + (int64_t)comp * gcomp;
+  constexpr int NOUT = (half1 + 1) * W;
+  const int L2h = (1 << logL2) / 2;
+  const int tmask = (1 << tsh) - 1;
+  for (int base = threadIdx.x; base < NOUT; base += 4 * NTHR) {
+    cplx<T> v[4];
+    int gi[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = base + u * NTHR;
+      gi[u] = -1;
+      const int w = e & (W - 1), k1 = e >> LOGW;
+      const int n2 = c0 + w;
+      if (e < NOUT && n2 <= L2h) {
+        const int t = n2 * k1;
+        const cplx<T> tws = cmul<T>(thi[t >> tsh], tlo[t & tmask]);
+        const T* re = A + (w & ~1) * LD;
+        const int km = (L1 - k1) & (L1 - 1);
+        v[u] = cmul<T>(separate<T>(re[pad(k1)], re[LD + pad(k1)], re[pad(km)], re[LD + pad(km)], w & 1), tws);
+        gi[u] = k1 * (int)sg + n2;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (gi[u] >= 0) Gc[gi[u]] = v[u];
+  }
+}
+
+template <typename T, int TRANS, int LOGL1, int LOGW>
+__global__ __launch_bounds__((1 << LOGW) << (LOGL1 - 4)) void k_fastC2(
+    const cplx<T>* __restrict__ G2, int64_t g2comp, int64_t sg2, T* __restrict__ out, int64_t Nn, int logL2,
+    const cplx<T>* __restrict__ tw, const double* __restrict__ part, int ntB, int nt, int nc, int xcd_order) {
+  constexpr int L1 = 1 << LOGL1, W = 1 << LOGW;
+  constexpr int NTHR = W * L1 / 16;
+  constexpr int LD = padded_ld(L1);
+  constexpr int half1 = L1 / 2, hp1 = half1 + 1;
+  constexpr int NP = W / 2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* U = reinterpret_cast<T*>(smem_raw);  // W real rows of L1
+  __shared__ double red[16];
+  int comp, tile;
+  xcd_tile(nt, nc, xcd_order, comp, tile);
+  const int L2 = 1 << logL2;
+  const int half2 = L2 / 2;
+  const int N = (int)(Nn - 1);
+  const int c0 = tile * W;
+  const int sg2i = (int)sg2;
+  T c0hat = T(0);
+  if (!TRANS) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < ntB; i += NTHR) acc += part[(int64_t)comp * ntB + i];
+    c0hat = (T)(block_sum(acc, red) / (double)N);
+  }
+  const cplx<T>* G2c = G2 + (int64_t)comp * g2comp;
+  constexpr int NIN = NP * hp1;
+  for (int base = threadIdx.x; base < NIN; base += 4 * NTHR) {
+    cplx<T> ra[4], rb[4];
+    int pr_[4], r_[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = base + u * NTHR;
+      pr_[u] = -1;
+      if (e < NIN) {
+        // G2 row r holds q = 0..L2/2 contiguously: the W columns of this tile are one
+        // contiguous segment per row
+        const int r = e / NP, pr = e - r * NP;
+        const int qa = c0 + 2 * pr, qb = qa + 1;
+        ra[u] = qa <= half2 ? G2c[r * sg2i + qa] : mk<T>(T(0), T(0));
+        rb[u] = qb <= half2 ? G2c[r * sg2i + qb] : mk<T>(T(0), T(0));
+        pr_[u] = pr;
+        r_[u] = r;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (pr_[u] < 0) continue;
+      const int r = r_[u];
+      T* re = U + (2 * pr_[u]) * LD;
+      T* im = re + LD;
+      re[pad(r)] = ra[u].x - rb[u].y;
+      im[pad(r)] = ra[u].y + rb[u].x;
+      if (r > 0 && r < half1) {
+        re[pad(L1 - r)] = ra[u].x + rb[u].y;
+        im[pad(L1 - r)] = rb[u].x - ra[u].y;
+      }
+    }
+  }
+  __syncthreads();
+  fft_ct<T, LOGL1, NP>(U, tw);
+  T* oc = out + (int64_t)comp * Nn;
+  const T invN = T(1) / T(N);
+  constexpr int NOUT = W * hp1;
+  for (int e = threadIdx.x; e < NOUT; e += NTHR) {
+    const int w = e & (W - 1), q2 = e >> LOGW;
+    const int q1 = c0 + w;
+    if (q1 > half2) continue;
+    const T* row = U + w * LD;
     if (q2 < half1 || (q1 == 0 && q2 == half1)) {
       const int j = q1 + L2 * q2;
       const T u = row[pad(q2)];
@@ -697,15 +1097,36 @@ static void fast_shape(const birk_plan* p, int64_t N, int& logL1, int& logL2, in
   while (WA & (WA - 1)) WA &= WA - 1;  // power of two
   WC = WA;
   const int rows = std::max(4, std::min(16, budget / fast::padded_ld(L2)));
-  TB = std::max(2, (rows - 2) & ~1);
+  TB = p->fast_tb > 0 ? p->fast_tb : std::max(2, (rows - 2) & ~1);
   // the halo rows of a pass-B tile must stay inside [-1, L1)
   while (TB > 2 && TB > L1 / 2 - 2) TB -= 2;
-  // Passes A and C: one split_fft chunk per workgroup (W L1 / 2 <= 512 PPT points), which
+  while (TB > 2 && (int64_t)(TB + 2) * fast::padded_ld(L2) * (int64_t)sizeof(T) > 160 * 1024) TB -= 2;
+  // Passes A and C: one split_fft chunk per workgroup (W L1 / 2 <= 512 kPPT points), which
   // keeps tiles small and workgroups many.  Pass B: larger tiles amortise the two halo
   // rows; its split_fft works through the rows in chunks.
-  const int maxpts = 512 * p->fast_ppt;
+  const int maxpts = 512 * fast::kPPT;
   while (WA > 2 && WA * L1 / 2 > maxpts) WA /= 2;
   while (WC > 2 && WC * L1 / 2 > maxpts) WC /= 2;
+}
+
+// Pass B takes the two-row register kernel when its rows are 512..2048 points long.
+static bool use_b2(const birk_plan* p, int logL2) { return p->fast_b2 && logL2 >= 9 && logL2 <= 11; }
+
+// Pass-B tiles per component (rows 0..L1/2 in tiles of TB, or of 2 for the register kernel).
+template <typename T>
+static int fast_tiles_b(const birk_plan* p, int64_t N) {
+  int logL1, logL2, WA, TB, WC;
+  fast_shape<T>(p, N, logL1, logL2, WA, TB, WC);
+  const int rows = (1 << logL1) / 2 + 1;
+  const int tb = use_b2(p, logL2) ? 2 : TB;
+  return (rows + tb - 1) / tb;
+}
+
+// Passes A and C take the compile-time-length kernels for L1 = 2^8..2^11 (tiles of 8
+// columns, 4 at 2^11); returns log2 of the tile width, or 0 for the general kernels.
+static int fixed_logw(const birk_plan* p, int logL1) {
+  if (!p->fast_b2 || logL1 < 8 || logL1 > 11) return 0;
+  return logL1 == 11 ? 2 : 3;
 }
 
 static int ilog2i(int v) {
@@ -714,9 +1135,9 @@ static int ilog2i(int v) {
   return l;
 }
 
-// Threads per workgroup: one per PPT complex points of the largest split_fft call.
-static int threads_for(int complex_points, int ppt) {
-  int t = (complex_points + ppt - 1) / ppt;
+// Threads per workgroup: one per kPPT complex points of the largest split_fft call.
+static int threads_for(int complex_points) {
+  int t = (complex_points + fast::kPPT - 1) / fast::kPPT;
   t = (t + 63) / 64 * 64;
   return std::max(64, std::min(512, t));
 }
@@ -726,44 +1147,25 @@ static void lds_attr(F f, int bytes) {
   (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-template <typename T, int PPT>
-static void launch_A(dim3 grid, int thr, int lds, hipStream_t s, const T* x, int64_t Nn, int logL1, int logL2, int logW,
-                     cplx<T>* G, int64_t gcomp, int64_t sg, const cplx<T>* tw, const cplx<T>* thi,
-                     const cplx<T>* tlo, int tsh, int ends2) {
-  auto f = fast::k_fastA<T, PPT>;
-  lds_attr(f, lds);
-  hipLaunchKernelGGL(f, grid, dim3(thr), lds, s, x, Nn, logL1, logL2, logW, G, gcomp, sg, tw, thi, tlo, tsh, ends2);
-}
-
-template <typename T, int TB, int TRANS, int PPT>
-static void launch_B(dim3 grid, int thr, int lds, hipStream_t s, const cplx<T>* G, int64_t gcomp, int64_t sg,
+template <typename T, int TB, int TRANS>
+static void launch_B(const birk_plan* p, int nt, int nc, int thr, int lds, hipStream_t s, const cplx<T>* G, int64_t gcomp, int64_t sg,
                      cplx<T>* G2, int64_t g2comp, int64_t sg2, int64_t N, int logL1, int logL2, const cplx<T>* tw,
                      const cplx<T>* thi, const cplx<T>* tlo, int tsh, double* part) {
-  auto f = fast::k_fastB<T, TB, TRANS, PPT>;
+  auto f = fast::k_fastB<T, TB, TRANS>;
   lds_attr(f, lds);
-  hipLaunchKernelGGL(f, grid, dim3(thr), lds, s, G, gcomp, sg, G2, g2comp, sg2, N, logL1, logL2, tw, thi, tlo, tsh,
-                     part);
+  hipLaunchKernelGGL(f, dim3(nt * nc), dim3(thr), lds, s, G, gcomp, sg, G2, g2comp, sg2, N, logL1, logL2, tw, thi,
+                     tlo, tsh, part, nt, nc, p->fast_xcd);
 }
 
-template <typename T, int TRANS, int PPT>
-static void launch_C(dim3 grid, int thr, int lds, hipStream_t s, const cplx<T>* G2, int64_t g2comp, int64_t sg2,
-                     T* out, int64_t Nn, int logL1, int logL2, int logW, const cplx<T>* tw, const double* part,
-                     int ntB) {
-  auto f = fast::k_fastC<T, TRANS, PPT>;
-  lds_attr(f, lds);
-  hipLaunchKernelGGL(f, grid, dim3(thr), lds, s, G2, g2comp, sg2, out, Nn, logL1, logL2, logW, tw, part, ntB);
-}
-
-template <typename T, int PPT>
-static hipError_t fast_product_ppt(birk_plan* p, const FastGroup& g, const T* v, T* out, int transpose,
-                                   hipStream_t s) {
+template <typename T>
+hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, int transpose, hipStream_t s) {
   constexpr int pi = prec_index<T>();
   int logL1, logL2, WA, TB, WC;
   fast_shape<T>(p, g.N, logL1, logL2, WA, TB, WC);
   const int L1 = 1 << logL1, L2 = 1 << logL2;
   const int ld1 = fast::padded_ld(L1), ld2 = fast::padded_ld(L2);
-  const int64_t sg = L2 / 2 + 1, sg2 = L1 / 2 + 1;
-  const int64_t gcomp = (int64_t)(L1 / 2 + 1) * sg, g2comp = (int64_t)(L2 / 2 + 1) * sg2;
+  const int64_t sg = L2 / 2 + 1, sg2 = L2 / 2 + 1;  // G [k1][n2] and G2 [r][q]: rows of L2/2 + 1
+  const int64_t gcomp = (int64_t)(L1 / 2 + 1) * sg, g2comp = (int64_t)(L1 / 2 + 1) * sg2;
   cplx<T>* G = (cplx<T>*)p->work[0] + g.work_off;
   cplx<T>* G2 = (cplx<T>*)p->work[1] + g.work_off;
   double* part = p->partials + g.part_off;
@@ -772,25 +1174,57 @@ static hipError_t fast_product_ppt(birk_plan* p, const FastGroup& g, const T* v,
   const cplx<T>* tlo = (const cplx<T>*)g.tw.lo[pi];
   const int tsh = g.tw.shift;
   const int nc = g.nc;
-  {
+  const int lw = fixed_logw(p, logL1);
+  if (lw > 0) {
+    // compile-time lengths: one tile of W = 2^lw columns per workgroup
+    const int W = 1 << lw;
+    const int ntA = (L2 / 2 + 1 + W - 1) / W;
+    const int lds = W * ld1 * (int)sizeof(T);
+    auto f = fast::k_fastA2<T, 10, 3>;
+    switch (logL1) {
+      case 8: f = fast::k_fastA2<T, 8, 3>; break;
+      case 9: f = fast::k_fastA2<T, 9, 3>; break;
+      case 10: f = fast::k_fastA2<T, 10, 3>; break;
+      default: f = fast::k_fastA2<T, 11, 2>; break;
+    }
+    lds_attr(f, lds);
+    hipLaunchKernelGGL(f, dim3(ntA * nc), dim3(W * L1 / 16), lds, s, v + g.off, g.Nn, logL2, G, gcomp, sg, tw, thi,
+                       tlo, tsh, transpose ? 1 : 0, ntA, nc, p->fast_xcd);
+  } else {
     const int ntA = (L2 / 2 + 1 + WA - 1) / WA;
     const int lds = WA * ld1 * (int)sizeof(T);
-    launch_A<T, PPT>(dim3(ntA, nc), threads_for(WA * L1 / 2, PPT), lds, s, v + g.off, g.Nn, logL1, logL2,
-                     ilog2i(WA), G, gcomp, sg, tw, thi, tlo, tsh, transpose ? 1 : 0);
+    auto f = fast::k_fastA<T>;
+    lds_attr(f, lds);
+    hipLaunchKernelGGL(f, dim3(ntA * nc), dim3(threads_for(WA * L1 / 2)), lds, s, v + g.off, g.Nn, logL1, logL2,
+                       ilog2i(WA), G, gcomp, sg, tw, thi, tlo, tsh, transpose ? 1 : 0, ntA, nc, p->fast_xcd);
   }
-  const int ntB = (L1 / 2 + 1 + TB - 1) / TB;
-  {
+  const int ntB = fast_tiles_b<T>(p, g.N);
+  if (use_b2(p, logL2)) {
+    const int lds = 2 * ld2 * (int)sizeof(T);
+    const int thr = L2 / fast::kPPT;
+    auto f = fast::k_fastB2<T, 0, 11>;
+    switch (logL2 * 2 + (transpose ? 1 : 0)) {
+      case 18: f = fast::k_fastB2<T, 0, 9>; break;
+      case 19: f = fast::k_fastB2<T, 1, 9>; break;
+      case 20: f = fast::k_fastB2<T, 0, 10>; break;
+      case 21: f = fast::k_fastB2<T, 1, 10>; break;
+      case 22: f = fast::k_fastB2<T, 0, 11>; break;
+      default: f = fast::k_fastB2<T, 1, 11>; break;
+    }
+    lds_attr(f, lds);
+    hipLaunchKernelGGL(f, dim3(ntB * nc), dim3(thr), lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, tw, thi, tlo,
+                       tsh, part, ntB, nc, p->fast_xcd);
+  } else {
     const int lds = (TB + 2) * ld2 * (int)sizeof(T);
-    const int thr = threads_for((TB + 2) * L2 / 2, PPT);
-    const dim3 grid(ntB, nc);
+    const int thr = std::min(threads_for((TB + 2) * L2 / 2), p->fast_b_threads);
 #define BIRK_LB(tb)                                                                                                \
   case tb:                                                                                                         \
     if (transpose)                                                                                                 \
-      launch_B<T, tb, 1, PPT>(grid, thr, lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, logL2, tw, thi, tlo,   \
-                              tsh, part);                                                                          \
+      launch_B<T, tb, 1>(p, ntB, nc, thr, lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, logL2, tw, thi, tlo, tsh, \
+                         part);                                                                                    \
     else                                                                                                           \
-      launch_B<T, tb, 0, PPT>(grid, thr, lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, logL2, tw, thi, tlo,   \
-                              tsh, part);                                                                          \
+      launch_B<T, tb, 0>(p, ntB, nc, thr, lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, logL2, tw, thi, tlo, tsh, \
+                         part);                                                                                    \
     break;
     switch (TB) {
       BIRK_LB(2)
@@ -805,25 +1239,36 @@ static hipError_t fast_product_ppt(birk_plan* p, const FastGroup& g, const T* v,
     }
 #undef BIRK_LB
   }
-  {
+  if (lw > 0) {
+    const int W = 1 << lw;
+    const int ntC = (L2 / 2 + 1 + W - 1) / W;
+    const int lds = W * ld1 * (int)sizeof(T);
+    T* o = out + g.off;
+    auto f = fast::k_fastC2<T, 0, 10, 3>;
+    switch (logL1 * 2 + (transpose ? 1 : 0)) {
+      case 16: f = fast::k_fastC2<T, 0, 8, 3>; break;
+      case 17: f = fast::k_fastC2<T, 1, 8, 3>; break;
+      case 18: f = fast::k_fastC2<T, 0, 9, 3>; break;
+      case 19: f = fast::k_fastC2<T, 1, 9, 3>; break;
+      case 20: f = fast::k_fastC2<T, 0, 10, 3>; break;
+      case 21: f = fast::k_fastC2<T, 1, 10, 3>; break;
+      case 22: f = fast::k_fastC2<T, 0, 11, 2>; break;
+      default: f = fast::k_fastC2<T, 1, 11, 2>; break;
+    }
+    lds_attr(f, lds);
+    hipLaunchKernelGGL(f, dim3(ntC * nc), dim3(W * L1 / 16), lds, s, G2, g2comp, sg2, o, g.Nn, logL2, tw, part, ntB,
+                       ntC, nc, p->fast_xcd);
+  } else {
     const int ntC = (L2 / 2 + 1 + WC - 1) / WC;
     const int lds = WC * ld1 * (int)sizeof(T);
-    const int thr = threads_for(WC * L1 / 2, PPT);
+    const int thr = threads_for(WC * L1 / 2);
     T* o = out + g.off;
-    if (transpose)
-      launch_C<T, 1, PPT>(dim3(ntC, nc), thr, lds, s, G2, g2comp, sg2, o, g.Nn, logL1, logL2, ilog2i(WC), tw, part,
-                          ntB);
-    else
-      launch_C<T, 0, PPT>(dim3(ntC, nc), thr, lds, s, G2, g2comp, sg2, o, g.Nn, logL1, logL2, ilog2i(WC), tw, part,
-                          ntB);
+    auto f = transpose ? fast::k_fastC<T, 1> : fast::k_fastC<T, 0>;
+    lds_attr(f, lds);
+    hipLaunchKernelGGL(f, dim3(ntC * nc), dim3(thr), lds, s, G2, g2comp, sg2, o, g.Nn, logL1, logL2, ilog2i(WC), tw,
+                       part, ntB, ntC, nc, p->fast_xcd);
   }
   return hipGetLastError();
-}
-
-template <typename T>
-hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, int transpose, hipStream_t s) {
-  return p->fast_ppt == 8 ? fast_product_ppt<T, 8>(p, g, v, out, transpose, s)
-                          : fast_product_ppt<T, 16>(p, g, v, out, transpose, s);
 }
 
 // Work (complex elements per buffer) and partials (doubles) of the fast path for nc
@@ -834,7 +1279,9 @@ void fast_sizes(const birk_plan* p, int64_t N, int nc, int64_t* work, int64_t* p
   fast_shape<double>(p, N, l1d, l2d, wad, tbd, wcd);
   const int64_t L1 = int64_t(1) << l1f, L2 = int64_t(1) << l2f;
   *work = (int64_t)nc * (L1 / 2 + 1) * (L2 / 2 + 1);
-  const int64_t ntB = std::max((L1 / 2 + 1 + tbf - 1) / tbf, ((int64_t(1) << l1d) / 2 + 1 + tbd - 1) / tbd);
+  (void)tbf;
+  (void)tbd;
+  const int64_t ntB = std::max(fast_tiles_b<float>(p, N), std::max(fast_tiles_b<double>(p, N), fast_tiles_b<df32>(p, N)));
   *part = (int64_t)nc * ntB;
 }
 

@@ -169,8 +169,11 @@ struct birk_plan {
   int* flag = nullptr;            // device flag: singular pivot seen
   int use_fast = 1;               // power-of-two N takes the three-pass path
   int fast_lds_kb[2] = {128, 64};  // LDS budget per workgroup of the three-pass kernels [8-byte, 4-byte reals]
-  int fast_ppt = 8;               // complex points per thread in the three-pass FFTs (8 or 16)
   int fast_split = 0;             // 0: rows of the first DCT are the longer side (L2 >= L1); 1: L1 >= L2
+  int fast_tb = 0;                // rows per pass-B tile (0: from the LDS budget)
+  int fast_b_threads = 512;       // workgroup size cap of pass B
+  int fast_xcd = 1;               // XCD-aware tile order
+  int fast_b2 = 1;                // pass B by the two-row register kernel where it applies
 };
 
 namespace birk {
