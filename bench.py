@@ -1,22 +1,24 @@
 """Benchmark of the Birkhoff hot path on one MI355X.
 
-Workload: the million-point configuration -- N_n = 2^20 + 1 CGL nodes, n_x = 6 states,
-time-varying Jacobian of the two-body problem along a seeded Keplerian orbit
+Headline workload: the million-point configuration -- N_n = 2^20 + 1 CGL nodes, n_x = 6
+states, time-varying Jacobian of the two-body problem along a seeded Keplerian orbit
 (a = 7000 km, e ~ U(0, 0.2), canonical units, one period), synthetic inputs.
 
-One step is one pass of the whole hot path on that batch:
-  * B^a v (FastBV) in double, once per buffer of a rotation of R input/output pairs
-    whose footprint exceeds the 256 MB Infinity Cache, so that every product reads its
-    input from HBM;
-  * B^aT g in double (same rotation);
-  * B^a v in float;
-  * P^{-1} y (preconditioner inverse scan) in double;
-  * the preconditioned GMRES solve to relative residual 1e-10, once with float Krylov
-    bulk inside double refinement (mixed) and once in double (FP64).
+One step is one pass of the whole hot path:
+  * headline: B^a v (FastBV) in double, once per buffer of a rotation of R
+    input/output pairs whose footprint exceeds the 256 MB Infinity Cache, so that every
+    product reads its input from HBM; B^aT g in double (same rotation); B^a v in float;
+    P^{-1} y (inverse-preconditioner scan) in double; the preconditioned GMRES solve to
+    relative residual 1e-10, once with float Krylov bulk inside double refinement
+    (mixed) and once in double (FP64);
+  * batched uneven workload: 512 LTI instances (N_n log-uniform in [2^8, 2^16], n_x in
+    {4, 6, 12}) in one plan: B^a v in double, and the mixed and FP64 solves to 1e-10;
+  * many-RHS workload: 32 right-hand sides of N_n = 2^18 + 1, n_x = 6 in one plan:
+    B^a v in compensated double-float (DF32), in double and in float.
 
-value = Gpts/s of the double B^a product = n / (mean duration of one birk_apply), timed
-with HIP events on the plan's stream over the timed region.  The solve times (mixed vs
-FP64 at the same 1e-10 residual) are reported in "solve".
+value = Gpts/s of the headline double B^a product = n / (mean duration of one
+birk_apply), timed with HIP events on the plan's stream over the timed region.  The other
+rows are reported under "secondary", "solve", "batched" and "many_rhs".
 
 `python bench.py --gpus N --steps K --warmup W`; N must be 1 (single-GPU build).
 """
@@ -25,7 +27,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -48,6 +49,7 @@ def parse():
     ap.add_argument("--rotation", type=int, default=6, help="input/output buffer pairs per product sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--products-only", action="store_true", help="skip the solves (for profiling runs)")
+    ap.add_argument("--headline-only", action="store_true", help="skip the batched and many-RHS workloads")
     ap.add_argument("--cpu-sample", type=int, default=200, help="rows of B^a the oracle computes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration under rocprofv3)")
@@ -99,6 +101,39 @@ def cpu_baseline(N: int, sample_rows: int, v):
                       f"single thread), {dt:.1f} s"}
 
 
+class Timer:
+    """HIP-event timing of named regions on one stream; read after a synchronisation."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.pending = []
+        self.rec = {}
+
+    def region(self, name, fn):
+        import torch
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        fn()
+        e1.record(self.stream)
+        self.pending.append((name, e0, e1))
+
+    def wall(self, name, fn):
+        t0 = time.perf_counter()
+        out = fn()
+        self.rec.setdefault(name, []).append((time.perf_counter() - t0) * 1e3)
+        return out
+
+    def collect(self, keep: bool):
+        for name, e0, e1 in self.pending:
+            if keep:
+                self.rec.setdefault(name, []).append(e0.elapsed_time(e1))
+        self.pending = []
+
+    def mean_ms(self, name):
+        xs = self.rec.get(name, [])
+        return float(sum(xs) / len(xs)) if xs else float("nan")
+
+
 def main():
     a = parse()
     if a.calibrate_copy:
@@ -116,71 +151,86 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    tm = Timer(stream)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1234)
+
+    # ---- headline workload
     N = 1 << a.log2n
     Nn = N + 1
     nx = 6
     n = Nn * nx
     print(f"[bench] building inputs N_n={Nn} n_x={nx}", file=sys.stderr, flush=True)
     inst = wl.kepler_instance(2, Nn)
-    stream = torch.cuda.current_stream()
     plan64 = B.birk_plan_create([Nn], [nx], B.BIRK_F64, stream)
     planmx = B.birk_plan_create([Nn], [nx], B.BIRK_F32_REFINE_F64, stream)
     J = torch.from_numpy(inst.J.ravel()).to("cuda")
     R = max(1, a.rotation)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(1234)
     vin = [torch.randn(n, dtype=torch.float64, device="cuda", generator=gen) for _ in range(R)]
     vout = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(R)]
     v32 = [x.float() for x in vin[:2]]
     o32 = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(2)]
-    ex = inst.extra
-    Z = np.concatenate([ex["v"], ex["acc"]])
-    beta_np = np.repeat(inst.x_a, Nn)
-    beta = torch.from_numpy(beta_np).to("cuda")
+    beta = torch.from_numpy(np.repeat(inst.x_a, Nn)).to("cuda")
     chi = torch.zeros(n, dtype=torch.float64, device="cuda")
-    torch.cuda.synchronize()
-
-    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    rec = {"apply": [], "apply_T": [], "apply_f32": [], "pinv": [], "mixed": [], "fp64": []}
     solve_info = {}
 
+    # ---- batched uneven workload
+    extra = not a.headline_only
+    if extra:
+        print("[bench] building the 512-instance batch", file=sys.stderr, flush=True)
+        binst = wl.batched_instances(count=512)
+        bNn = [i.N_n for i in binst]
+        bnx = [i.n_x for i in binst]
+        bn = sum(p * q for p, q in zip(bNn, bnx))
+        bplan64 = B.birk_plan_create(bNn, bnx, B.BIRK_F64, stream)
+        bplanmx = B.birk_plan_create(bNn, bnx, B.BIRK_F32_REFINE_F64, stream)
+        bJ = torch.from_numpy(np.concatenate([i.J.ravel() for i in binst])).to("cuda")
+        bbeta = torch.from_numpy(np.concatenate([np.repeat(i.x_a, i.N_n) for i in binst])).to("cuda")
+        bchi = torch.zeros(bn, dtype=torch.float64, device="cuda")
+        bv = torch.randn(bn, dtype=torch.float64, device="cuda", generator=gen)
+        bo = torch.empty_like(bv)
+        # ---- many-RHS workload
+        print("[bench] building the 32-RHS workload", file=sys.stderr, flush=True)
+        mNn, mnx, mR = (1 << 18) + 1, 6, 32
+        mn = mNn * mnx * mR
+        mplans = {p: B.birk_plan_create([mNn] * mR, [mnx] * mR, p, stream)
+                  for p in (B.BIRK_F64, B.BIRK_F32, B.BIRK_DF32)}
+        mv = torch.randn(mn, dtype=torch.float64, device="cuda", generator=gen)
+        mo = torch.empty_like(mv)
+        mv32 = mv.float()
+        mo32 = torch.empty_like(mv32)
+        hi = mv.float()
+        lo = (mv - hi.double()).float()
+        mvdf = torch.stack([hi, lo], dim=1).reshape(-1).contiguous()
+        modf = torch.empty_like(mvdf)
+    torch.cuda.synchronize()
+
     def step(timed: bool):
-        pairs = []
         for i in range(R):
-            e0, e1 = ev(), ev()
-            e0.record(stream)
-            B.birk_apply(plan64, vin[i], vout[i])
-            e1.record(stream)
-            pairs.append(("apply", e0, e1))
+            tm.region("apply", lambda i=i: B.birk_apply(plan64, vin[i], vout[i]))
         for i in range(R):
-            e0, e1 = ev(), ev()
-            e0.record(stream)
-            B.birk_apply_T(plan64, vin[i], vout[(i + 1) % R])
-            e1.record(stream)
-            pairs.append(("apply_T", e0, e1))
+            tm.region("apply_T", lambda i=i: B.birk_apply_T(plan64, vin[i], vout[(i + 1) % R]))
         for i in range(2):
-            e0, e1 = ev(), ev()
-            e0.record(stream)
-            B.birk_apply(planmx, v32[i], o32[i])
-            e1.record(stream)
-            pairs.append(("apply_f32", e0, e1))
-        e0, e1 = ev(), ev()
-        e0.record(stream)
-        B.birk_precond(plan64, J, vin[0], vout[1], 1, B.BIRK_J_PER_NODE)
-        e1.record(stream)
-        pairs.append(("pinv", e0, e1))
-        if not a.products_only:
-            for name, plan in (("mixed", planmx), ("fp64", plan64)):
-                t0 = time.perf_counter()
-                info = B.birk_krylov_solve(plan, J, beta, chi, B.BIRK_J_PER_NODE, rtol=1e-10)
-                dt = (time.perf_counter() - t0) * 1e3
-                if timed:
-                    rec[name].append(dt)
-                    solve_info[name] = info
+            tm.region("apply_f32", lambda i=i: B.birk_apply(planmx, v32[i], o32[i]))
+        tm.region("pinv", lambda: B.birk_precond(plan64, J, vin[0], vout[1], 1, B.BIRK_J_PER_NODE))
+        if extra:
+            tm.region("b_apply", lambda: B.birk_apply(bplan64, bv, bo))
+            tm.region("m_apply_f64", lambda: B.birk_apply(mplans[B.BIRK_F64], mv, mo))
+            tm.region("m_apply_f32", lambda: B.birk_apply(mplans[B.BIRK_F32], mv32, mo32))
+            tm.region("m_apply_df32", lambda: B.birk_apply(mplans[B.BIRK_DF32], mvdf, modf))
         torch.cuda.synchronize()
-        if timed:
-            for name, e0, e1 in pairs:
-                rec[name].append(e0.elapsed_time(e1))
+        tm.collect(timed)
+        if not a.products_only:
+            solves = [("mixed", planmx, J, beta, chi, B.BIRK_J_PER_NODE),
+                      ("fp64", plan64, J, beta, chi, B.BIRK_J_PER_NODE)]
+            if extra:
+                solves += [("b_mixed", bplanmx, bJ, bbeta, bchi, B.BIRK_J_CONSTANT),
+                           ("b_fp64", bplan64, bJ, bbeta, bchi, B.BIRK_J_CONSTANT)]
+            for name, plan, Jm, bt, ch, jk in solves:
+                info = tm.wall(name if timed else "_warm",
+                               lambda: B.birk_krylov_solve(plan, Jm, bt, ch, jk, rtol=1e-10))
+                solve_info[name] = info
 
     for _ in range(a.warmup):
         step(False)
@@ -193,11 +243,11 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    mean = lambda xs: float(sum(xs) / len(xs)) if xs else float("nan")  # noqa: E731
-    t_apply = mean(rec["apply"]) * 1e-3
+    t_apply = tm.mean_ms("apply") * 1e-3
     gpts = n / t_apply / 1e9
     bytes_alg = 2.0 * n * 8.0
     achieved = bytes_alg / t_apply / 1e9
+    us = lambda name: round(tm.mean_ms(name) * 1e3, 2)  # noqa: E731
     out = {
         "metric": METRIC,
         "value": round(gpts, 3),
@@ -221,11 +271,11 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": bytes_alg, "avg_launch_us": round(t_apply * 1e6, 2)},
         "secondary": {
-            "apply_f64_us": round(mean(rec["apply"]) * 1e3, 2),
-            "apply_T_f64_us": round(mean(rec["apply_T"]) * 1e3, 2),
-            "apply_f32_us": round(mean(rec["apply_f32"]) * 1e3, 2),
-            "apply_f32_gpts": round(n / (mean(rec["apply_f32"]) * 1e-3) / 1e9, 3),
-            "precond_inverse_f64_us": round(mean(rec["pinv"]) * 1e3, 2),
+            "apply_f64_us": us("apply"),
+            "apply_T_f64_us": us("apply_T"),
+            "apply_f32_us": us("apply_f32"),
+            "apply_f32_gpts": round(n / (tm.mean_ms("apply_f32") * 1e-3) / 1e9, 3),
+            "precond_inverse_f64_us": us("pinv"),
         },
     }
     tr = traffic_record(KERNEL_SOURCES)
@@ -233,18 +283,44 @@ def main():
         out["roofline"]["traffic"] = tr["bytes_per_product"]
         out["roofline"]["traffic_source"] = "profiles/apply_f64_traffic.json"
     if not a.products_only:
-        mx, f64 = mean(rec["mixed"]), mean(rec["fp64"])
+        mx, f64 = tm.mean_ms("mixed"), tm.mean_ms("fp64")
         out["solve"] = {
             "rtol": 1e-10,
             "mixed_ms": round(mx, 3), "fp64_ms": round(f64, 3), "speedup_mixed_vs_fp64": round(f64 / mx, 3),
             "mixed": {k: solve_info["mixed"][k] for k in ("inner_iters", "outer_iters", "rel_resid")},
             "fp64": {k: solve_info["fp64"][k] for k in ("inner_iters", "outer_iters", "rel_resid")},
         }
+    if extra:
+        bt = tm.mean_ms("b_apply") * 1e-3
+        out["batched"] = {"workload": "512 LTI instances, N_n log-uniform in [2^8, 2^16], n_x in {4, 6, 12}",
+                          "n": bn, "apply_f64_us": us("b_apply"), "apply_f64_gpts": round(bn / bt / 1e9, 3)}
+        if not a.products_only:
+            bmx, b64 = tm.mean_ms("b_mixed"), tm.mean_ms("b_fp64")
+            summ = lambda info: {"inner_iters": [min(info["inner_iters"]), max(info["inner_iters"])],  # noqa: E731
+                                 "outer_iters": [min(info["outer_iters"]), max(info["outer_iters"])],
+                                 "worst_rel_resid": max(info["rel_resid"]), "status": info["status"]}
+            out["batched"].update({"rtol": 1e-10, "mixed_ms": round(bmx, 3), "fp64_ms": round(b64, 3),
+                                   "speedup_mixed_vs_fp64": round(b64 / bmx, 3),
+                                   "mixed": summ(solve_info["b_mixed"]), "fp64": summ(solve_info["b_fp64"])})
+        # deviation of the double-float and float products from the double product
+        hi_lo = modf.view(-1, 2).double()
+        dfv = hi_lo[:, 0] + hi_lo[:, 1]
+        scale = float(mo.abs().max())
+        dev_df = float((dfv - mo).abs().max()) / scale
+        dev_32 = float((mo32.double() - mo).abs().max()) / scale
+        out["many_rhs"] = {
+            "workload": "32 RHS x n_x = 6 at N_n = 2^18 + 1 in one plan (192 components)", "n": mn,
+            "apply_df32_us": us("m_apply_df32"), "apply_f64_us": us("m_apply_f64"), "apply_f32_us": us("m_apply_f32"),
+            "apply_df32_gpts": round(mn / (tm.mean_ms("m_apply_df32") * 1e-3) / 1e9, 3),
+            "apply_f64_gpts": round(mn / (tm.mean_ms("m_apply_f64") * 1e-3) / 1e9, 3),
+            "apply_f32_gpts": round(mn / (tm.mean_ms("m_apply_f32") * 1e-3) / 1e9, 3),
+            "max_dev_vs_f64": {"df32": dev_df, "f32": dev_32},
+        }
     if not a.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(N, a.cpu_sample, vin[0][:Nn].cpu().numpy())
-    plan64.destroy()
-    planmx.destroy()
+    for p in [plan64, planmx] + ([bplan64, bplanmx] + list(mplans.values()) if extra else []):
+        p.destroy()
     print(json.dumps(out), flush=True)
 
 

@@ -209,13 +209,15 @@ __device__ __forceinline__ int64_t swz(int64_t B, int i, int field, int nfield, 
   return (((B * kFan + i) * nfield) + field) * 64 + l;
 }
 
-// Swizzle per-node data for the level-0 kernels: field e < nx^2 is J entry e at the node
-// (per-node Jacobians only), the last field is w_k.  Node k -> chunk c = k / kChunk,
-// j = k % kChunk; g = c / kFan, i = c % kFan; B = g / 64, l = g % 64; stored at
-// jsw[(((B kFan + i) kChunk + j) E + e) 64 + l] with E = fields.  Nodes past N_n are zero
-// (identity maps).  One workgroup per (B, i, e): for each of the 64 lanes l it reads the
-// kChunk consecutive nodes of chunk (64 B + l) kFan + i, and writes kChunk rows of 64
-// consecutive lanes, transposing through LDS.  tile = (k, (B kFan + i) E + e).
+// Swizzle per-node data for the level-0 kernels.  E = nx^2 + 1 fields per node: fields
+// e < nx^2 take J entry e at the node (per-node Jacobians only; k_make_h then replaces
+// them by H_k), the last field is w_k.  Node k -> chunk c = k / kChunk, j = k % kChunk;
+// g = c / kFan, i = c % kFan; B = g / 64, l = g % 64; stored at
+// jsw[(((B kFan + i) kChunk + j) E + e) 64 + l].  Nodes past N_n are zero.  One
+// workgroup per (B, i, e): for each of the 64 lanes l it reads the kChunk consecutive
+// nodes of chunk (64 B + l) kFan + i, and writes kChunk rows of 64 consecutive lanes,
+// transposing through LDS.  tile = (k, (B kFan + i) nf + f) with nf = E fields written
+// for per-node J, nf = 1 (the weights) for constant J.
 template <typename JT>
 __global__ __launch_bounds__(256) void k_swizzle_nodes(const double* __restrict__ J, int per_node, int nx,
                                                        const PinvDesc* __restrict__ pd,
@@ -223,9 +225,11 @@ __global__ __launch_bounds__(256) void k_swizzle_nodes(const double* __restrict_
   __shared__ double tile[64][kChunk + 1];
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
-  const int E = per_node ? nx * nx + 1 : 1;
-  const int e = t.y % E;
-  const int bx = t.y / E;
+  const int E = nx * nx + 1;
+  const int nf = per_node ? E : 1;
+  const int f = t.y % nf;
+  const int e = per_node ? f : E - 1;
+  const int bx = t.y / nf;
   const int i = bx % kFan;
   const int64_t B = bx / kFan;
   const int64_t Nn = d.Nn;
@@ -243,98 +247,136 @@ __global__ __launch_bounds__(256) void k_swizzle_nodes(const double* __restrict_
   }
 }
 
+// Per node, H_k = w_k J_k K_k^{-1} with K_k = I - w_k J_k / 2, by an unpivoted LU of K_k
+// and NX solves K_k X = w_k J_k (J_k commutes with K_k^{-1}).  Everything the scan needs
+// follows from H_k:  K_k^{-1} = I + H_k / 2, so for u = y_k + S_k
+//     xi_k = u + H_k u / 2,   J_k xi_k = H_k u / w_k,   S_{k+1} = S_k + H_k u,
+// and the affine map of the node is S -> (I + H_k) S + H_k y_k.  H_k is written over
+// the J fields of the node's slot (in place; constant J: into the empty fields).  A
+// pivot that is non-finite or not above 1e-13 (1 + |w_k / 2| max |J_k|) sets *flag.
+// Thread per level-0 chunk in the level-0 layout (as k_pinv_final); nodes past N_n are
+// never read by the scan and are left alone.  tile = (k, block of 256 level-0 threads).
 template <int NX, typename JT>
-__device__ __forceinline__ void load_jk_sw(const JT* __restrict__ jsw, const double* __restrict__ Jc,
-                                           int per_node, int64_t slot, double (&Jk)[NX][NX], double& wk) {
-  // slot = ((B kFan + i) kChunk + j); per-node: fields 0..NX^2-1 then w; constant: w only
-  const int E = per_node ? NX * NX + 1 : 1;
-  const JT* base = jsw + slot * E * 64;
-  const int l = threadIdx.x & 63;
-#pragma unroll
-  for (int r = 0; r < NX; ++r)
-#pragma unroll
-    for (int q = 0; q < NX; ++q) Jk[r][q] = per_node ? (double)base[(r * NX + q) * 64 + l] : Jc[r * NX + q];
-  wk = (double)base[(E - 1) * 64 + l];
-}
-
-// Level-0 up-sweep: each thread reduces one chunk of kChunk nodes to (A, b) with
-// S_out = A S_in + b.  tile = (k, block of level-0 threads).
-template <int NX, typename T>
-__global__ __launch_bounds__(256) void k_pinv_up0(const T* __restrict__ jsw, const double* __restrict__ J,
-                                                  int per_node, const T* __restrict__ y,
-                                                  const PinvDesc* __restrict__ pd, const int2* __restrict__ tiles,
-                                                  double* __restrict__ scan, int* flag) {
+__global__ __launch_bounds__(256, 2) void k_make_h(JT* __restrict__ jsw, const double* __restrict__ J, int per_node,
+                                                const PinvDesc* __restrict__ pd, const int2* __restrict__ tiles,
+                                                int* flag) {
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
   const int64_t tau = (int64_t)t.y * blockDim.x + threadIdx.x;
   const int64_t B = tau / (64 * kFan);
   const int i = (int)((tau >> 6) % kFan);
   const int l = (int)(tau & 63);
-  const int64_t g = B * 64 + l;
-  const int64_t c = g * kFan + i;
+  const int64_t c = (B * 64 + l) * kFan + i;
   if (c >= d.cnt[0]) return;
-  const int64_t Nn = d.Nn;
+  constexpr int E = NX * NX + 1;
   const double* Jc = J + d.jcoff;
-  const T* js = jsw + d.jsw_off;
-  const T* yi = y + d.off;
-  double* agg = scan + d.agg[0];
-  constexpr int F = NX * NX + NX;
-  double A[NX][NX], b[NX];
-#pragma unroll
-  for (int r = 0; r < NX; ++r) {
-    b[r] = 0.0;
-#pragma unroll
-    for (int q = 0; q < NX; ++q) A[r][q] = (r == q) ? 1.0 : 0.0;
-  }
-  const int64_t k0 = c * kChunk;
-  const int jn = (int)min((int64_t)kChunk, Nn - k0);
+  JT* js = jsw + d.jsw_off + ((B * kFan + i) * kChunk) * E * 64 + l;
+  const int jn = (int)min((int64_t)kChunk, d.Nn - c * kChunk);
+#pragma unroll 1
   for (int j = 0; j < jn; ++j) {
-    const int64_t k = k0 + j;
-    double Jk[NX][NX], K[NX][NX], rp[NX], wk;
-    load_jk_sw<NX, T>(js, Jc, per_node, (B * kFan + i) * kChunk + j, Jk, wk);
-    double x[NX];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) x[r] = (double)yi[(int64_t)r * Nn + k];
-    form_k<NX>(Jk, wk, K);
+    JT* base = js + (int64_t)j * E * 64;
+    const double wk = (double)base[(E - 1) * 64];
+    double K[NX][NX], rp[NX];
     double jmax = 0.0;
 #pragma unroll
     for (int r = 0; r < NX; ++r)
 #pragma unroll
-      for (int q = 0; q < NX; ++q) jmax = fmax(jmax, fabs(Jk[r][q]));
+      for (int q = 0; q < NX; ++q) {
+        const double jv = per_node ? (double)base[(r * NX + q) * 64] : Jc[r * NX + q];
+        jmax = fmax(jmax, fabs(jv));
+        K[r][q] = (r == q ? 1.0 : 0.0) - 0.5 * wk * jv;
+      }
     lu_kmat<NX>(K, rp, flag, 1.0 + 0.5 * fabs(wk) * jmax);
-    // b <- b + wk Jk K^{-1} (b + y_k)
 #pragma unroll
-    for (int r = 0; r < NX; ++r) x[r] += b[r];
-    lu_solve<NX>(K, rp, x);
+    for (int cc = 0; cc < NX; ++cc) {
+      double x[NX];
+#pragma unroll
+      for (int r = 0; r < NX; ++r) x[r] = wk * (per_node ? (double)base[(r * NX + cc) * 64] : Jc[r * NX + cc]);
+      lu_solve<NX>(K, rp, x);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) base[(r * NX + cc) * 64] = (JT)x[r];
+    }
+  }
+}
+
+// The up-sweeps carry the NX + 1 columns of an aggregate (A, b): a thread holds PER of
+// them, all when NX <= 8 (blockIdx.y = 0), else groups of 4 (blockIdx.y picks the
+// group), and streams the row of the node map or child aggregate it applies, so the
+// map entries are read once per group.
+template <int NX>
+struct ColGroups {
+  static constexpr int per = (NX <= 8) ? NX + 1 : 4;
+  static constexpr int count = (NX + 1 + per - 1) / per;
+};
+
+// Level-0 up-sweep: each chunk of kChunk nodes is reduced to (A, b) with
+// S_out = A S_in + b by the node maps S -> (I + H_k) S + H_k y_k: column c < NX of A
+// starts at e_c and takes col <- col + H_k col, b starts at 0 and takes
+// col <- col + H_k (col + y_k).  Thread per chunk in the level-0 layout (as
+// k_pinv_final).  tile = (k, block of 256 level-0 threads).
+template <int NX, typename T>
+__global__ __launch_bounds__(256) void k_pinv_up0(const T* __restrict__ jsw, const T* __restrict__ y,
+                                                  const PinvDesc* __restrict__ pd, const int2* __restrict__ tiles,
+                                                  double* __restrict__ scan) {
+  constexpr int PER = ColGroups<NX>::per;
+  const int2 t = tiles[blockIdx.x];
+  const PinvDesc& d = pd[t.x];
+  const int64_t tau = (int64_t)t.y * blockDim.x + threadIdx.x;
+  const int64_t B = tau / (64 * kFan);
+  const int i = (int)((tau >> 6) % kFan);
+  const int l = (int)(tau & 63);
+  const int64_t ch = (B * 64 + l) * kFan + i;
+  if (ch >= d.cnt[0]) return;
+  const int c0 = (int)blockIdx.y * PER;
+  constexpr int E = NX * NX + 1;
+  constexpr int F = NX * NX + NX;
+  const int64_t Nn = d.Nn;
+  const T* js = jsw + d.jsw_off + ((B * kFan + i) * kChunk) * E * 64 + l;
+  const T* yi = y + d.off;
+  double col[PER][NX];
+#pragma unroll
+  for (int p = 0; p < PER; ++p)
+#pragma unroll
+    for (int r = 0; r < NX; ++r) col[p][r] = (r == c0 + p) ? 1.0 : 0.0;
+  const int64_t k0 = ch * kChunk;
+  const int jn = (int)min((int64_t)kChunk, Nn - k0);
+#pragma unroll 1
+  for (int j = 0; j < jn; ++j) {
+    const T* base = js + (int64_t)j * E * 64;
+    double u[PER][NX];
+#pragma unroll
+    for (int p = 0; p < PER; ++p)
+#pragma unroll
+      for (int r = 0; r < NX; ++r) u[p][r] = col[p][r];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      if (c0 + p == NX) {
+#pragma unroll
+        for (int r = 0; r < NX; ++r) u[p][r] += (double)yi[(int64_t)r * Nn + k0 + j];
+      }
+    }
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
-      double acc = 0.0;
+      double h[NX];
 #pragma unroll
-      for (int q = 0; q < NX; ++q) acc += Jk[r][q] * x[q];
-      b[r] += wk * acc;
-    }
-    // A <- A + wk Jk K^{-1} A, column by column
+      for (int q = 0; q < NX; ++q) h[q] = (double)base[(r * NX + q) * 64];
 #pragma unroll
-    for (int col = 0; col < NX; ++col) {
-      double xc[NX];
-#pragma unroll
-      for (int r = 0; r < NX; ++r) xc[r] = A[r][col];
-      lu_solve<NX>(K, rp, xc);
-#pragma unroll
-      for (int r = 0; r < NX; ++r) {
+      for (int p = 0; p < PER; ++p) {
         double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < NX; ++q) acc += Jk[r][q] * xc[q];
-        A[r][col] += wk * acc;
+        for (int q = 0; q < NX; ++q) acc += h[q] * u[p][q];
+        col[p][r] += acc;
       }
     }
   }
+  double* agg = scan + d.agg[0];
 #pragma unroll
-  for (int r = 0; r < NX; ++r)
+  for (int p = 0; p < PER; ++p) {
+    const int c = c0 + p;
+    if (c > NX) break;
 #pragma unroll
-    for (int q = 0; q < NX; ++q) agg[swz(B, i, r * NX + q, F, l)] = A[r][q];
-#pragma unroll
-  for (int r = 0; r < NX; ++r) agg[swz(B, i, NX * NX + r, F, l)] = b[r];
+    for (int r = 0; r < NX; ++r) agg[swz(B, i, (c < NX) ? r * NX + c : NX * NX + r, F, l)] = col[p][r];
+  }
 }
 
 // (A, b) <- (a_A A, a_A b + a_b) for the NX x NX + NX fields of aggregate a (field f at
@@ -403,25 +445,65 @@ __device__ __forceinline__ void identity_agg(double (&A)[NX][NX], double (&b)[NX
 }
 
 // Up-sweep level lv -> lv + 1: thread per parent combines its kFan child aggregates in
-// order; level 0 is read swizzled.  tile = (k, block over cnt[lv + 1]).
+// order, (A, b) <- (a_A A, a_A b + a_b), over its group of columns; level 0 is read
+// swizzled.  tile = (k, block of 256 parents).
 template <int NX>
 __global__ __launch_bounds__(256) void k_pinv_up(double* __restrict__ scan, const PinvDesc* __restrict__ pd,
                                                  const int2* __restrict__ tiles, int lv) {
+  constexpr int PER = ColGroups<NX>::per;
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
   const int64_t g = (int64_t)t.y * blockDim.x + threadIdx.x;
   if (g >= d.cnt[lv + 1]) return;
+  const int c0 = (int)blockIdx.y * PER;
   constexpr int F = NX * NX + NX;
   const double* child = scan + d.agg[lv];
   const int64_t nchild = d.cnt[lv];
-  double A[NX][NX], b[NX];
-  identity_agg<NX>(A, b);
+  double col[PER][NX];
+#pragma unroll
+  for (int p = 0; p < PER; ++p)
+#pragma unroll
+    for (int r = 0; r < NX; ++r) col[p][r] = (r == c0 + p) ? 1.0 : 0.0;
   const int nc = (int)min((int64_t)kFan, nchild - g * kFan);
+#pragma unroll 1
   for (int i = 0; i < nc; ++i) {
-    if (lv == 0) compose<NX>(child + swz(g >> 6, i, 0, F, (int)(g & 63)), 64, A, b);
-    else compose<NX>(child + (g * kFan + i) * F, 1, A, b);
+    const double* a;
+    int64_t fs;
+    if (lv == 0) {
+      a = child + swz(g >> 6, i, 0, F, (int)(g & 63));
+      fs = 64;
+    } else {
+      a = child + (g * kFan + i) * F;
+      fs = 1;
+    }
+    double u[PER][NX];
+#pragma unroll
+    for (int p = 0; p < PER; ++p)
+#pragma unroll
+      for (int r = 0; r < NX; ++r) u[p][r] = col[p][r];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      double h[NX];
+#pragma unroll
+      for (int q = 0; q < NX; ++q) h[q] = a[(r * NX + q) * fs];
+      const double ab = a[(NX * NX + r) * fs];
+#pragma unroll
+      for (int p = 0; p < PER; ++p) {
+        double acc = (c0 + p == NX) ? ab : 0.0;
+#pragma unroll
+        for (int q = 0; q < NX; ++q) acc += h[q] * u[p][q];
+        col[p][r] = acc;
+      }
+    }
   }
-  store_agg<NX>(scan + d.agg[lv + 1] + g * F, A, b);
+  double* o = scan + d.agg[lv + 1] + g * F;
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int c = c0 + p;
+    if (c > NX) break;
+#pragma unroll
+    for (int r = 0; r < NX; ++r) o[(c < NX) ? r * NX + c : NX * NX + r] = col[p][r];
+  }
 }
 
 // Top: one thread per instance walks the top-level aggregates from S = 0 and writes
@@ -483,11 +565,12 @@ __global__ __launch_bounds__(256) void k_pinv_down(double* __restrict__ scan, co
   }
 }
 
-// Replay each chunk from its start state (same thread layout as k_pinv_up0): xi_k and
-// (J xi)_k.
+// Replay each chunk from its start state: u = y_k + S, v = H_k u, xi_k = u + v / 2,
+// (J xi)_k = v / w_k, S <- S + v.  Thread per chunk in the level-0 layout: thread
+// tau -> block B = tau / (64 kFan), i = (tau / 64) % kFan, lane l = tau % 64.
+// tile = (k, block of 256 level-0 threads).
 template <int NX, typename T>
-__global__ __launch_bounds__(256) void k_pinv_final(const T* __restrict__ jsw, const double* __restrict__ J,
-                                                    int per_node, const T* __restrict__ y,
+__global__ __launch_bounds__(256) void k_pinv_final(const T* __restrict__ jsw, const T* __restrict__ y,
                                                     const PinvDesc* __restrict__ pd, const int2* __restrict__ tiles,
                                                     const double* __restrict__ scan, T* __restrict__ out,
                                                     T* __restrict__ jout) {
@@ -500,9 +583,9 @@ __global__ __launch_bounds__(256) void k_pinv_final(const T* __restrict__ jsw, c
   const int64_t g = B * 64 + l;
   const int64_t c = g * kFan + i;
   if (c >= d.cnt[0]) return;
+  constexpr int E = NX * NX + 1;
   const int64_t Nn = d.Nn;
-  const double* Jc = J + d.jcoff;
-  const T* js = jsw + d.jsw_off;
+  const T* js = jsw + d.jsw_off + ((B * kFan + i) * kChunk) * E * 64 + l;
   const T* yi = y + d.off;
   T* oi = out + d.off;
   T* ji = jout ? jout + d.off : nullptr;
@@ -514,22 +597,19 @@ __global__ __launch_bounds__(256) void k_pinv_final(const T* __restrict__ jsw, c
   const int jn = (int)min((int64_t)kChunk, Nn - k0);
   for (int j = 0; j < jn; ++j) {
     const int64_t k = k0 + j;
-    double Jk[NX][NX], K[NX][NX], rp[NX], wk;
-    load_jk_sw<NX, T>(js, Jc, per_node, (B * kFan + i) * kChunk + j, Jk, wk);
-    double x[NX];
+    const T* base = js + (int64_t)j * E * 64;
+    const double inv_w = 1.0 / (double)base[(E - 1) * 64];
+    double u[NX];
 #pragma unroll
-    for (int r = 0; r < NX; ++r) x[r] = s[r] + (double)yi[(int64_t)r * Nn + k];
-    form_k<NX>(Jk, wk, K);
-    lu_kmat<NX>(K, rp, nullptr, 1.0);
-    lu_solve<NX>(K, rp, x);
+    for (int r = 0; r < NX; ++r) u[r] = s[r] + (double)yi[(int64_t)r * Nn + k];
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
-      double acc = 0.0;
+      double v = 0.0;
 #pragma unroll
-      for (int q = 0; q < NX; ++q) acc += Jk[r][q] * x[q];
-      s[r] += wk * acc;
-      oi[(int64_t)r * Nn + k] = (T)x[r];
-      if (ji) ji[(int64_t)r * Nn + k] = (T)acc;
+      for (int q = 0; q < NX; ++q) v += (double)base[(r * NX + q) * 64] * u[q];
+      s[r] += v;
+      oi[(int64_t)r * Nn + k] = (T)(u[r] + 0.5 * v);
+      if (ji) ji[(int64_t)r * Nn + k] = (T)(v * inv_w);
     }
   }
 }
@@ -638,7 +718,7 @@ hipError_t plan_solve(birk_plan* p) {
     }
     if (pc.host.empty()) continue;
     pc.ninst = (int)pc.host.size();
-    std::vector<int2> t0, tn, tsw[2], tup[kPinvMaxLevels];
+    std::vector<int2> t0, tn, tsw[2], tup[kPinvMaxLevels], tupc[kPinvMaxLevels];
     for (int k = 0; k < pc.ninst; ++k) {
       const PinvDesc& d = pc.host[k];
       const int64_t thr0 = (int64_t)d.nb0 * 64 * kFan;
@@ -649,8 +729,10 @@ hipError_t plan_solve(birk_plan* p) {
         for (int64_t bx = 0; bx < (int64_t)d.nb0 * kFan; ++bx)
           for (int f = 0; f < E; ++f) tsw[pn].push_back(make_int2(k, (int)(bx * E + f)));
       }
-      for (int l = 0; l < d.L; ++l)
+      for (int l = 0; l < d.L; ++l) {
         for (unsigned b = 0; b < nblocks(d.cnt[l + 1], 256); ++b) tup[l].push_back(make_int2(k, (int)b));
+        for (unsigned b = 0; b < nblocks(d.cnt[l + 1], 64); ++b) tupc[l].push_back(make_int2(k, (int)b));
+      }
     }
     void* dd = nullptr;
     if ((e = hipMalloc(&dd, pc.host.size() * sizeof(PinvDesc))) != hipSuccess) return e;
@@ -669,6 +751,8 @@ hipError_t plan_solve(birk_plan* p) {
     for (int l = 0; l < pc.Lmax; ++l) {
       if ((e = upload_tiles(p, tup[l], &pc.t_up[l])) != hipSuccess) return e;
       pc.n_up[l] = (int)tup[l].size();
+      if ((e = upload_tiles(p, tupc[l], &pc.t_upc[l])) != hipSuccess) return e;
+      pc.n_upc[l] = (int)tupc[l].size();
     }
     p->pclass.push_back(std::move(pc));
   }
@@ -703,39 +787,10 @@ hipError_t plan_solve(birk_plan* p) {
   return hipSuccess;
 }
 
-hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s) {
-  const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
-  for (const PinvClass& pc : p->pclass) {
-    if (pc.n_swz[pn] == 0) continue;
-    if (single)
-      hipLaunchKernelGGL(k_swizzle_nodes<float>, dim3(pc.n_swz[pn]), dim3(256), 0, s, J, pn, pc.nx, pc.dev,
-                         pc.t_swz[pn], (float*)p->jsw);
-    else
-      hipLaunchKernelGGL(k_swizzle_nodes<double>, dim3(pc.n_swz[pn]), dim3(256), 0, s, J, pn, pc.nx, pc.dev,
-                         pc.t_swz[pn], p->jsw);
-  }
-  return hipGetLastError();
-}
-
-template <int NX, typename T>
-static void pinv_class(birk_plan* p, const PinvClass& pc, const double* J, int pn, const T* y, T* out, T* jout,
-                       int* flag, hipStream_t s) {
-  const T* jsw = (const T*)p->jsw;
-  double* scan = p->scan;
-  hipLaunchKernelGGL((k_pinv_up0<NX, T>), dim3(pc.n_node0), dim3(256), 0, s, jsw, J, pn, y, pc.dev, pc.t_node0, scan,
-                     flag);
-  for (int l = 0; l < pc.Lmax; ++l)
-    hipLaunchKernelGGL((k_pinv_up<NX>), dim3(pc.n_up[l]), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
-  hipLaunchKernelGGL((k_pinv_top<NX>), dim3(pc.ninst), dim3(64), 0, s, scan, pc.dev);
-  for (int l = pc.Lmax - 1; l >= 0; --l)
-    hipLaunchKernelGGL((k_pinv_down<NX>), dim3(pc.n_up[l]), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
-  hipLaunchKernelGGL((k_pinv_final<NX, T>), dim3(pc.n_node0), dim3(256), 0, s, jsw, J, pn, y, pc.dev, pc.t_node0,
-                     scan, out, jout);
-}
-
-template <int NX, typename T>
-static void jac_class(const PinvClass& pc, const double* J, int pn, const T* x, T* y, hipStream_t s) {
-  hipLaunchKernelGGL((k_jac_class<NX, T>), dim3(pc.n_nodes), dim3(256), 0, s, J, pn, x, y, pc.dev, pc.t_nodes);
+template <int NX, typename JT>
+static void make_h_class(birk_plan* p, const PinvClass& pc, const double* J, int pn, hipStream_t s) {
+  hipLaunchKernelGGL((k_make_h<NX, JT>), dim3(pc.n_node0), dim3(256), 0, s, (JT*)p->jsw, J, pn, pc.dev, pc.t_node0,
+                     p->flag);
 }
 
 #define BIRK_NX_SWITCH(nx, CALL)                                       \
@@ -755,13 +810,58 @@ static void jac_class(const PinvClass& pc, const double* J, int pn, const T* x, 
     default: return hipErrorInvalidValue;                              \
   }
 
+// Lay the weights (and per-node J) out in the level-0 slots, then replace the J fields by
+// H_k (k_make_h).  Runs once per Jacobian; the scan itself only reads H_k and w_k.
+hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s) {
+  const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
+  for (const PinvClass& pc : p->pclass) {
+    if (pc.n_swz[pn] == 0) continue;
+    if (single)
+      hipLaunchKernelGGL(k_swizzle_nodes<float>, dim3(pc.n_swz[pn]), dim3(256), 0, s, J, pn, pc.nx, pc.dev,
+                         pc.t_swz[pn], (float*)p->jsw);
+    else
+      hipLaunchKernelGGL(k_swizzle_nodes<double>, dim3(pc.n_swz[pn]), dim3(256), 0, s, J, pn, pc.nx, pc.dev,
+                         pc.t_swz[pn], p->jsw);
+    if (single) {
+      BIRK_NX_SWITCH(pc.nx, (make_h_class<NXC, float>(p, pc, J, pn, s)))
+    } else {
+      BIRK_NX_SWITCH(pc.nx, (make_h_class<NXC, double>(p, pc, J, pn, s)))
+    }
+  }
+  return hipGetLastError();
+}
+
+template <int NX, typename T>
+static void pinv_class(birk_plan* p, const PinvClass& pc, const T* y, T* out, T* jout, hipStream_t s) {
+  const T* jsw = (const T*)p->jsw;
+  double* scan = p->scan;
+  constexpr int ncg = ColGroups<NX>::count;
+  hipLaunchKernelGGL((k_pinv_up0<NX, T>), dim3(pc.n_node0, ncg), dim3(256), 0, s, jsw, y, pc.dev, pc.t_node0, scan);
+  for (int l = 0; l < pc.Lmax; ++l)
+    hipLaunchKernelGGL((k_pinv_up<NX>), dim3(pc.n_up[l], ncg), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
+  hipLaunchKernelGGL((k_pinv_top<NX>), dim3(pc.ninst), dim3(64), 0, s, scan, pc.dev);
+  for (int l = pc.Lmax - 1; l >= 0; --l)
+    hipLaunchKernelGGL((k_pinv_down<NX>), dim3(pc.n_up[l]), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
+  hipLaunchKernelGGL((k_pinv_final<NX, T>), dim3(pc.n_node0), dim3(256), 0, s, jsw, y, pc.dev, pc.t_node0, scan, out,
+                     jout);
+}
+
+template <int NX, typename T>
+static void jac_class(const PinvClass& pc, const double* J, int pn, const T* x, T* y, hipStream_t s) {
+  hipLaunchKernelGGL((k_jac_class<NX, T>), dim3(pc.n_nodes), dim3(256), 0, s, J, pn, x, y, pc.dev, pc.t_nodes);
+}
+
+
 template <typename T>
 hipError_t precond_inverse(birk_plan* p, int jac_kind, const double* J, const T* y, T* out, T* jout,
                            hipStream_t s, int* flag) {
-  // the per-node data must have been laid out for this J by precond_prepare
-  const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
+  // H_k and w_k must have been laid out for this J by precond_prepare (which also checks
+  // the pivots); J and jac_kind are not read again here
+  (void)jac_kind;
+  (void)J;
+  (void)flag;
   for (const PinvClass& pc : p->pclass) {
-    BIRK_NX_SWITCH(pc.nx, (pinv_class<NXC, T>(p, pc, J, pn, y, out, jout, flag, s)))
+    BIRK_NX_SWITCH(pc.nx, (pinv_class<NXC, T>(p, pc, y, out, jout, s)))
   }
   return hipGetLastError();
 }

@@ -20,7 +20,11 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SOURCES = ["paper_2509_01855_amd/csrc/birk_fast.hip", "paper_2509_01855_amd/csrc/birk_dct.hip"]
-PASSES = ("k_fastA<double", "k_fastB<double, ", "k_fastC<double, 0")
+import re
+
+# forward double product: pass A, pass B (TRANS = 0), pass C (TRANS = 0); the
+# fixed-length kernels (suffix 2) are used where they apply
+PASSES = (r"k_fastA2?<double", r"k_fastB2<double, 0,|k_fastB<double, \d+, 0>", r"k_fastC2?<double, 0")
 
 
 def _rows(d):
@@ -53,10 +57,9 @@ def main():
     write = _mean_by_kernel(write_dir, "WRITE_SIZE")
     per = {}
     for key in PASSES:
-        names = [k for k in fetch if key in k and "TRANS" not in k]
-        # forward pass B/C instances carry TRANS = 0 as the second template argument
-        if key.startswith("k_fastB"):
-            names = [k for k in names if ", 0, " in k]
+        names = [k for k in fetch if re.search(key, k)]
+        if not names:
+            raise SystemExit(f"no kernel matching {key} in the counter runs")
         name = names[0]
         per[name] = {"fetch_bytes": fetch[name] * sf, "write_bytes": write[name] * sw}
     total = sum(v["fetch_bytes"] + v["write_bytes"] for v in per.values())
