@@ -313,12 +313,13 @@ __device__ __forceinline__ cplx<T> dft_value(const cplx<T>* __restrict__ z, cons
 template <typename T>
 __global__ __launch_bounds__(256) void k_mid_fwd(const cplx<T>* __restrict__ z, cplx<T>* __restrict__ z2,
                                                  const PairDesc* __restrict__ pd, const int2* __restrict__ tiles,
-                                                 double* __restrict__ part) {
+                                                 double* __restrict__ part, int compact) {
   constexpr int pi = prec_index<T>();
   const int2 tile = tiles[blockIdx.x];
   const PairDesc& d = pd[tile.x];
   const int64_t N = d.N, L = d.L, M = d.M;
-  const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
+  // compact: z holds Y_k (chirp applied) and d_k, k <= N, goes to z2 as is
+  const cplx<T>* chirp = compact ? nullptr : (const cplx<T>*)d.chirp[pi];
   const cplx<T>* zz = z + d.work;
   cplx<T>* z2p = z2 + d.work;
   const int64_t k = (int64_t)tile.y * blockDim.x + threadIdx.x;
@@ -358,14 +359,15 @@ __global__ __launch_bounds__(256) void k_mid_fwd(const cplx<T>* __restrict__ z, 
       const T sc = invN / ek;
       cplx<T> dv = mk<T>(rx * sc, ry * sc);
       z2p[k] = chirp ? cmul<T>(dv, chirp[k]) : dv;
-      if (k < N) {
+      if (k < N && !compact) {
         const int64_t m = L - k;
         z2p[m] = chirp ? cmul<T>(dv, chirp[m]) : dv;
       }
     }
   }
   // zero fill of the Bluestein padding [L, M)
-  for (int64_t m = L + k; m < M; m += (int64_t)d.nblk * blockDim.x) z2p[m] = mk<T>(T(0), T(0));
+  if (!compact)
+    for (int64_t m = L + k; m < M; m += (int64_t)d.nblk * blockDim.x) z2p[m] = mk<T>(T(0), T(0));
   // block reduction of the c^_0 partials, fixed order
   __shared__ double r0[256], r1[256];
   r0[threadIdx.x] = s0;
@@ -417,12 +419,13 @@ __global__ __launch_bounds__(256) void k_c0(const double* __restrict__ part, cpl
 //   q_j = -p_0/(j^2-1) + p_{j-1} (1/(2(j-1)) - [j = N]/(2(N+1))) - [j < N] p_{j+1}/(2(j+1)).
 template <typename T>
 __global__ __launch_bounds__(256) void k_mid_tr(const cplx<T>* __restrict__ z, cplx<T>* __restrict__ z2,
-                                                const PairDesc* __restrict__ pd, const int2* __restrict__ tiles) {
+                                                const PairDesc* __restrict__ pd, const int2* __restrict__ tiles,
+                                                int compact) {
   constexpr int pi = prec_index<T>();
   const int2 tile = tiles[blockIdx.x];
   const PairDesc& d = pd[tile.x];
   const int64_t N = d.N, L = d.L, M = d.M;
-  const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
+  const cplx<T>* chirp = compact ? nullptr : (const cplx<T>*)d.chirp[pi];
   const cplx<T>* zz = z + d.work;
   cplx<T>* z2p = z2 + d.work;
   const int64_t j = (int64_t)tile.y * blockDim.x + threadIdx.x;
@@ -454,9 +457,10 @@ __global__ __launch_bounds__(256) void k_mid_tr(const cplx<T>* __restrict__ z, c
       q = mk<T>(qx, qy);
     }
     z2p[j] = chirp ? cmul<T>(q, chirp[j]) : q;
-    if (j >= 1 && j < N) z2p[L - j] = chirp ? cmul<T>(q, chirp[L - j]) : q;
+    if (j >= 1 && j < N && !compact) z2p[L - j] = chirp ? cmul<T>(q, chirp[L - j]) : q;
   }
-  for (int64_t m = L + j; m < M; m += (int64_t)d.nblk * blockDim.x) z2p[m] = mk<T>(T(0), T(0));
+  if (!compact)
+    for (int64_t m = L + j; m < M; m += (int64_t)d.nblk * blockDim.x) z2p[m] = mk<T>(T(0), T(0));
 }
 
 // Final stage: out_j = scale_j * Y_j for j in [0, N], unpacking the pair.
@@ -464,14 +468,14 @@ __global__ __launch_bounds__(256) void k_mid_tr(const cplx<T>* __restrict__ z, c
 template <typename T>
 __global__ __launch_bounds__(256) void k_final(const cplx<T>* __restrict__ z, T* __restrict__ out,
                                                const PairDesc* __restrict__ pd, const int2* __restrict__ tiles,
-                                               int transpose) {
+                                               int transpose, int compact) {
   constexpr int pi = prec_index<T>();
   const int2 tile = tiles[blockIdx.x];
   const PairDesc& d = pd[tile.x];
   const int64_t N = d.N;
   const int64_t j = (int64_t)tile.y * blockDim.x + threadIdx.x;
   if (j > N) return;
-  const cplx<T> Y = dft_value<T>(z + d.work, (const cplx<T>*)d.chirp[pi], j);
+  const cplx<T> Y = dft_value<T>(z + d.work, compact ? nullptr : (const cplx<T>*)d.chirp[pi], j);
   T sc;
   if (transpose) sc = ((j == 0 || j == N) ? T(0.5) : T(1)) / T(N);
   else sc = T(0.5);
@@ -500,14 +504,222 @@ static hipError_t product_set(birk_plan* p, const PairSet& ps, int bluestein, co
   hipError_t e = dct_set<T>(p, ps, bluestein, z, tmp, s);
   if (e != hipSuccess) return e;
   if (!transpose) {
-    hipLaunchKernelGGL(k_mid_fwd<T>, dim3(ps.n_n), dim3(256), 0, s, z, z2, ps.dev, ps.tiles_n, p->partials);
+    hipLaunchKernelGGL(k_mid_fwd<T>, dim3(ps.n_n), dim3(256), 0, s, z, z2, ps.dev, ps.tiles_n, p->partials, 0);
     hipLaunchKernelGGL(k_c0<T>, dim3((unsigned)ps.host.size()), dim3(256), 0, s, p->partials, z2, ps.dev);
   } else {
-    hipLaunchKernelGGL(k_mid_tr<T>, dim3(ps.n_n), dim3(256), 0, s, z, z2, ps.dev, ps.tiles_n);
+    hipLaunchKernelGGL(k_mid_tr<T>, dim3(ps.n_n), dim3(256), 0, s, z, z2, ps.dev, ps.tiles_n, 0);
   }
   e = dct_set<T>(p, ps, bluestein, z2, tmp, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_final<T>, dim3(ps.n_n), dim3(256), 0, s, z2, out, ps.dev, ps.tiles_n, transpose);
+  hipLaunchKernelGGL(k_final<T>, dim3(ps.n_n), dim3(256), 0, s, z2, out, ps.dev, ps.tiles_n, transpose, 0);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- fused Bluestein path
+// For 2N not a power of two each DCT-I is a Bluestein convolution of the chirped even
+// extension (length L = 2N, padded to M).  The fused path runs it in three passes over M
+// (two-step FFTs above the LDS limit, one kernel below it) instead of pack, FFT, filter,
+// inverse FFT as separate passes:
+//   columns:  even extension x chirp, column FFTs (length M1), twiddle    -> tmp
+//   rows:     row FFTs (M2), x filter spectrum, inverse row FFTs, inverse twiddle
+//   icolumns: inverse column FFTs, x chirp, only the N + 1 outputs Y_k are stored.
+// The inverse two-step transform takes its factors in the reverse order of the forward
+// one, so the rows pass sees the forward spectrum of a row, multiplies it by the filter,
+// and transforms it straight back.  Inputs: the pair's two components (first DCT,
+// optionally with doubled end points) or the compact stencil output d_k (second DCT);
+// outputs Y_k, k <= N, with the chirp applied.
+
+// Padded Bluestein input at position n: (even extension of the source) x chirp_n.
+template <typename T>
+__device__ __forceinline__ cplx<T> blu_in(const PairDesc& d, const T* __restrict__ x, const cplx<T>* __restrict__ dz,
+                                         int src_x, int ends2, const cplx<T>* __restrict__ chirp, int64_t n) {
+  if (n >= d.L) return mk<T>(T(0), T(0));
+  const int64_t k = n <= d.N ? n : d.L - n;
+  cplx<T> v;
+  if (src_x) {
+    const T* xa = x + d.src;
+    T a = xa[k];
+    T b = d.has2 ? xa[d.Nn + k] : T(0);
+    if (ends2 && (k == 0 || k == d.N)) {
+      a = a + a;
+      b = b + b;
+    }
+    v = mk<T>(a, b);
+  } else {
+    v = dz[d.work + k];
+  }
+  return cmul<T>(v, chirp[n]);
+}
+
+// Whole Bluestein convolutions of length M <= kLdsMax in LDS.  tile = (first pair,
+// count) of pairs with the same M.
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_blu_lds(const T* __restrict__ x, const cplx<T>* __restrict__ dz,
+                                                        cplx<T>* __restrict__ Y, const PairDesc* __restrict__ pd,
+                                                        const int2* __restrict__ tiles, const cplx<T>* __restrict__ tw,
+                                                        int src_x, int ends2) {
+  constexpr int pi = prec_index<T>();
+  __shared__ cplx<T> buf[kLdsMax];
+  const int2 tile = tiles[blockIdx.x];
+  const int logM = pd[tile.x].logM;
+  const int M = 1 << logM;
+  const int n = tile.y << logM;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const PairDesc& d = pd[tile.x + (e >> logM)];
+    buf[e] = blu_in<T>(d, x, dz, src_x, ends2, (const cplx<T>*)d.chirp[pi], e & (M - 1));
+  }
+  __syncthreads();
+  lds_fft<T, 4>(buf, logM, tile.y, tw, 0);
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const PairDesc& d = pd[tile.x + (e >> logM)];
+    buf[e] = cmul<T>(buf[e], ((const cplx<T>*)d.filt[pi])[e & (M - 1)]);
+  }
+  __syncthreads();
+  lds_fft<T, 4>(buf, logM, tile.y, tw, 1);
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const PairDesc& d = pd[tile.x + (e >> logM)];
+    const int k = e & (M - 1);
+    if (k <= d.N) Y[d.work + k] = cmul<T>(buf[e], ((const cplx<T>*)d.chirp[pi])[k]);
+  }
+}
+
+// Columns pass: n = M2 n1 + n2, FFT over n1 of the padded input, twiddle W_M^(n2 k1),
+// tmp[k1 M2 + n2].  tile = (pair, column block of W).
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_blu_cols(const T* __restrict__ x, const cplx<T>* __restrict__ dz,
+                                                         cplx<T>* __restrict__ tmp, const PairDesc* __restrict__ pd,
+                                                         const int2* __restrict__ tiles,
+                                                         const cplx<T>* __restrict__ tw, int src_x, int ends2) {
+  constexpr int pi = prec_index<T>();
+  __shared__ cplx<T> buf[kLdsMax];
+  const int2 tile = tiles[blockIdx.x];
+  const PairDesc& d = pd[tile.x];
+  const int logM1 = d.logM1, logM2 = d.logM2;
+  const int M1 = 1 << logM1;
+  const int logW = min(kLdsMaxLog - logM1, logM2);
+  const int W = 1 << logW;
+  const int c0 = tile.y << logW;
+  const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
+  cplx<T>* ts = tmp + d.work;
+  const int n = M1 << logW;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int w = e & (W - 1), n1 = e >> logW;
+    buf[(w << logM1) + n1] = blu_in<T>(d, x, dz, src_x, ends2, chirp, ((int64_t)n1 << logM2) + c0 + w);
+  }
+  __syncthreads();
+  lds_fft<T, 4>(buf, logM1, W, tw, 0);
+  const cplx<T>* thi = (const cplx<T>*)d.thi[pi];
+  const cplx<T>* tlo = (const cplx<T>*)d.tlo[pi];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int w = e & (W - 1), k1 = e >> logW;
+    const int64_t t = (int64_t)(c0 + w) * k1;
+    ts[((int64_t)k1 << logM2) + c0 + w] = cmul<T>(buf[(w << logM1) + k1], tw4<T>(thi, tlo, d.tw_shift, t, 0));
+  }
+}
+
+// Rows pass: for rows k1 of tmp, FFT over n2 (length M2, frequency k2 of k = k1 + M1 k2),
+// multiply by the filter spectrum, inverse FFT back to n2, multiply by W_M^(-n2 k1), in
+// place.  tile = (pair, row block of W).
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_blu_rows(cplx<T>* __restrict__ tmp, const PairDesc* __restrict__ pd,
+                                                         const int2* __restrict__ tiles,
+                                                         const cplx<T>* __restrict__ tw) {
+  constexpr int pi = prec_index<T>();
+  __shared__ cplx<T> buf[kLdsMax];
+  const int2 tile = tiles[blockIdx.x];
+  const PairDesc& d = pd[tile.x];
+  const int logM1 = d.logM1, logM2 = d.logM2;
+  const int M2 = 1 << logM2;
+  const int logW = min(kLdsMaxLog - logM2, logM1);
+  const int r0 = tile.y << logW;
+  cplx<T>* ts = tmp + d.work + ((int64_t)r0 << logM2);
+  const int n = M2 << logW;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) buf[e] = ts[e];
+  __syncthreads();
+  lds_fft<T, 4>(buf, logM2, 1 << logW, tw, 0);
+  const cplx<T>* filt = (const cplx<T>*)d.filt[pi];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int w = e >> logM2, k2 = e & (M2 - 1);
+    buf[e] = cmul<T>(buf[e], filt[(r0 + w) + ((int64_t)k2 << logM1)]);
+  }
+  __syncthreads();
+  lds_fft<T, 4>(buf, logM2, 1 << logW, tw, 1);
+  const cplx<T>* thi = (const cplx<T>*)d.thi[pi];
+  const cplx<T>* tlo = (const cplx<T>*)d.tlo[pi];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int w = e >> logM2, n2 = e & (M2 - 1);
+    ts[e] = cmul<T>(buf[e], tw4<T>(thi, tlo, d.tw_shift, (int64_t)n2 * (r0 + w), 1));
+  }
+}
+
+// Inverse columns pass: columns n2 of tmp[k1 M2 + n2], inverse FFT over k1 -> n1, output
+// index n = M2 n1 + n2; Y_n = value x chirp_n for n <= N.  tile = (pair, column block).
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_blu_icols(const cplx<T>* __restrict__ tmp, cplx<T>* __restrict__ Y,
+                                                          const PairDesc* __restrict__ pd,
+                                                          const int2* __restrict__ tiles,
+                                                          const cplx<T>* __restrict__ tw) {
+  constexpr int pi = prec_index<T>();
+  __shared__ cplx<T> buf[kLdsMax];
+  const int2 tile = tiles[blockIdx.x];
+  const PairDesc& d = pd[tile.x];
+  const int logM1 = d.logM1, logM2 = d.logM2;
+  const int M1 = 1 << logM1;
+  const int logW = min(kLdsMaxLog - logM1, logM2);
+  const int W = 1 << logW;
+  const int c0 = tile.y << logW;
+  const cplx<T>* ts = tmp + d.work;
+  const int n = M1 << logW;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int w = e & (W - 1), k1 = e >> logW;
+    buf[(w << logM1) + k1] = ts[((int64_t)k1 << logM2) + c0 + w];
+  }
+  __syncthreads();
+  lds_fft<T, 4>(buf, logM1, W, tw, 1);
+  const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int w = e & (W - 1), n1 = e >> logW;
+    const int64_t idx = ((int64_t)n1 << logM2) + c0 + w;
+    if (idx <= d.N) Y[d.work + idx] = cmul<T>(buf[(w << logM1) + n1], chirp[idx]);
+  }
+}
+
+// One DCT-I (= 2 C) of every pair of a Bluestein set by the fused passes; Y receives
+// Y_k, k <= N, at each pair's work offset.
+template <typename T>
+static hipError_t dct_blu(birk_plan* p, const PairSet& ps, const T* x, const cplx<T>* dz, cplx<T>* Y, int src_x,
+                          int ends2, hipStream_t s) {
+  const cplx<T>* tw = (const cplx<T>*)p->lds_tw[prec_index<T>()];
+  cplx<T>* tmp = (cplx<T>*)p->work[0];
+  if (ps.n_lds > 0)
+    hipLaunchKernelGGL(k_blu_lds<T>, dim3(ps.n_lds), dim3(kFftThreads), 0, s, x, dz, Y, ps.dev, ps.tiles_lds, tw,
+                       src_x, ends2);
+  if (ps.n_c4 > 0) {
+    hipLaunchKernelGGL(k_blu_cols<T>, dim3(ps.n_c4), dim3(kFftThreads), 0, s, x, dz, tmp, ps.dev, ps.tiles_c4, tw,
+                       src_x, ends2);
+    hipLaunchKernelGGL(k_blu_rows<T>, dim3(ps.n_r4), dim3(kFftThreads), 0, s, tmp, ps.dev, ps.tiles_r4, tw);
+    hipLaunchKernelGGL(k_blu_icols<T>, dim3(ps.n_c4), dim3(kFftThreads), 0, s, tmp, Y, ps.dev, ps.tiles_c4, tw);
+  }
+  return hipGetLastError();
+}
+
+// Product over a Bluestein set: DCT (fused) -> stencil and c^_0 -> DCT (fused) -> unpack.
+template <typename T>
+static hipError_t product_blu(birk_plan* p, const PairSet& ps, const T* v, T* out, int transpose, hipStream_t s) {
+  if (ps.host.empty()) return hipSuccess;
+  cplx<T>* Y = (cplx<T>*)p->work[1];
+  cplx<T>* dz = (cplx<T>*)p->work[2];
+  hipError_t e = dct_blu<T>(p, ps, v, nullptr, Y, 1, transpose, s);
+  if (e != hipSuccess) return e;
+  if (!transpose) {
+    hipLaunchKernelGGL(k_mid_fwd<T>, dim3(ps.n_n), dim3(256), 0, s, Y, dz, ps.dev, ps.tiles_n, p->partials, 1);
+    hipLaunchKernelGGL(k_c0<T>, dim3((unsigned)ps.host.size()), dim3(256), 0, s, p->partials, dz, ps.dev);
+  } else {
+    hipLaunchKernelGGL(k_mid_tr<T>, dim3(ps.n_n), dim3(256), 0, s, Y, dz, ps.dev, ps.tiles_n, 1);
+  }
+  e = dct_blu<T>(p, ps, nullptr, dz, Y, 0, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_final<T>, dim3(ps.n_n), dim3(256), 0, s, Y, out, ps.dev, ps.tiles_n, transpose, 1);
   return hipGetLastError();
 }
 
@@ -518,7 +730,7 @@ hipError_t apply_product(birk_plan* p, const T* v, T* out, int transpose, hipStr
     if (e != hipSuccess) return e;
   }
   hipError_t e = product_set<T>(p, p->gen[0], 0, v, out, transpose, s);
-  if (e == hipSuccess) e = product_set<T>(p, p->gen[1], 1, v, out, transpose, s);
+  if (e == hipSuccess) e = product_blu<T>(p, p->gen[1], v, out, transpose, s);
   return e;
 }
 
