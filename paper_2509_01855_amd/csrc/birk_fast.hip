@@ -686,15 +686,15 @@ __device__ __forceinline__ void fft_ct(T* __restrict__ buf, const cplx<T>* __res
   stages8_ct<T, LOGL, COUNT, 0>(buf, tw);
 }
 
-// Pass B for rows of L2 = 2^LOGL2 (512..2048) points, blockDim = L2 / 8, two rows per
-// tile.  One LDS buffer holds one complex row transform at a time: the pair
-// (t0 - 1, t0) is transformed and each thread keeps its eight outputs
-// m = tid + i blockDim in registers, then the pair (t0 + 1, t0 + 2) the same way, so
-// the stencil of rows t0 and t0 + 1 runs in registers; d(t0) + i d(t0 + 1) then goes
-// back through the buffer for the column transform of DCT 2.  The small LDS footprint
-// (one row pair) lets several workgroups share a CU, which hides the latency of the
-// load / transform / store phases that one large workgroup exposes.
-template <typename T, int TRANS, int LOGL2>
+// Pass B for rows of L2 = 2^LOGL2 (512..2048) points, blockDim = L2 / 8, TB = 2 or 4
+// rows per tile.  One LDS buffer holds one complex row transform at a time: the pairs
+// of DCT-1 rows (t0 - 1 + 2p, t0 + 2p), p = 0..TB/2, are transformed one after the other
+// and each thread keeps its eight outputs m = tid + i blockDim of every row in
+// registers, so the stencil of rows t0..t0+TB-1 runs in registers; the pairs
+// d(t0 + 2q) + i d(t0 + 2q + 1) then go back through the buffer for the column transforms
+// of DCT 2.  The small LDS footprint (one row pair) lets several workgroups share a CU,
+// which hides the latency of the load / transform / store phases.
+template <typename T, int TRANS, int LOGL2, int TB>
 __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB2(
     const cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg, cplx<T>* __restrict__ G2, int64_t g2comp, int64_t sg2,
     int64_t N64, int logL1, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ thi,
@@ -704,6 +704,7 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB2(
   constexpr int half2 = L2 / 2, hp1 = half2 + 1;
   constexpr int ld2 = padded_ld(L2);
   constexpr int twsh = kLdsMaxLog - LOGL2;
+  constexpr int NP = TB / 2 + 1;  // DCT-1 row pairs (TB rows and the two halo rows)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Yre = reinterpret_cast<T*>(smem_raw);  // one complex row: real part, imaginary part
   T* Yim = Yre + ld2;
@@ -712,7 +713,7 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB2(
   xcd_tile(nt, nc, xcd_order, comp, tile);
   const int N = (int)N64;
   const int L1 = 1 << logL1;
-  const int t0 = 2 * tile;
+  const int t0 = TB * tile;
   const int sgi = (int)sg;
   const cplx<T>* Gc = G + (int64_t)comp * gcomp;
   T p0 = T(0);
@@ -723,10 +724,10 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB2(
       acc += (double)Gc[n2].x * ((n2 == 0 || n2 == half2) ? 1.0 : 2.0);
     p0 = (T)(0.5 * block_sum(acc, red));
   }
-  // DCT-1 rows: yr[p][i] / yi[p][i] = rows t0 - 1 + 2p / t0 + 2p at m = tid + i NTHR
-  T yr[2][kPPT], yi[2][kPPT];
+  // DCT-1 rows: y[rho][i] = row t0 - 1 + rho at m = tid + i NTHR, rho = 0..TB+1
+  T y[2 * NP][kPPT];
 #pragma unroll
-  for (int pp = 0; pp < 2; ++pp) {
+  for (int pp = 0; pp < NP; ++pp) {
     int ma, mb;
     const int sa = hrow_src(t0 - 1 + 2 * pp, L1, &ma);
     const int sb = hrow_src(t0 + 2 * pp, L1, &mb);
@@ -753,66 +754,74 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB2(
 #pragma unroll
     for (int i = 0; i < kPPT; ++i) {
       const int m = (int)threadIdx.x + i * NTHR;
-      yr[pp][i] = Yre[pad(m)];
-      yi[pp][i] = Yim[pad(m)];
+      y[2 * pp][i] = Yre[pad(m)];
+      y[2 * pp + 1][i] = Yim[pad(m)];
     }
     __syncthreads();
   }
-  // stencil of rows t0 (neighbours t0 - 1, t0 + 1) and t0 + 1 (neighbours t0, t0 + 2)
+  // stencil of rows t0 + rl (rho = rl + 1, neighbours rho - 1 and rho + 1)
   double c0acc = 0.0;
   const int N2 = 2 * N;
   const T invN = T(1) / T(N), inv4N1 = T(1) / T(4 * (int64_t)N + 4), inv2N1 = T(1) / T(2 * (int64_t)N + 2);
+  T dv[TB][kPPT];
 #pragma unroll
   for (int i = 0; i < kPPT; ++i) {
     const int m = (int)threadIdx.x + i * NTHR;
-    T dv[2];
 #pragma unroll
-    for (int rl = 0; rl < 2; ++rl) {
+    for (int rl = 0; rl < TB; ++rl) {
       const int k1 = t0 + rl;
-      const T ylo = rl ? yi[0][i] : yr[0][i];   // row k1 - 1
-      const T yhi = rl ? yi[1][i] : yr[1][i];   // row k1 + 1
-      const T ymid = rl ? yr[1][i] : yi[0][i];  // row k1
+      const T ylo = y[rl][i];      // row k1 - 1
+      const T ymid = y[rl + 1][i]; // row k1
+      const T yhi = y[rl + 2][i];  // row k1 + 1
       const int K = k1 + L1 * m;
       const bool lowhalf = K <= N;
       const int k = lowhalf ? K : N2 - K;
       const T Ym = lowhalf ? ylo : yhi;
       const T Yp = lowhalf ? yhi : ylo;
       if (TRANS) {
-        dv[rl] = stencil_tr<T>(k, N, Ym, Yp, p0, inv2N1);
+        dv[rl][i] = stencil_tr<T>(k, N, Ym, Yp, p0, inv2N1);
       } else {
-        dv[rl] = stencil_fwd<T>(k, N, Ym, Yp, invN, inv4N1);
+        dv[rl][i] = stencil_fwd<T>(k, N, Ym, Yp, invN, inv4N1);
         if (k1 <= L1 / 2 && ((k1 != 0 && k1 != L1 / 2) || lowhalf)) c0acc += c0_coef(k, N) * (double)ymid;
       }
     }
-    Yre[pad(m)] = dv[0];
-    Yim[pad(m)] = dv[1];
   }
   if (!TRANS) {
     const double tot = block_sum(c0acc, red);
     if (threadIdx.x == 0) part[(int64_t)comp * nt + tile] = tot;
   }
-  __syncthreads();
-  // column transform of DCT 2 on d(t0) + i d(t0 + 1)
-  fft_ct<T, LOGL2, 1>(Yre, tw);
   cplx<T>* G2c = G2 + (int64_t)comp * g2comp;
   const int tmask = (1 << tsh) - 1;
   const int sg2i = (int)sg2;
+  // column transforms of DCT 2 on d(t0 + 2q) + i d(t0 + 2q + 1)
 #pragma unroll
-  for (int rl = 0; rl < 2; ++rl) {
-    const int r = t0 + rl;
-    if (r > L1 / 2) continue;
-    constexpr int per = (hp1 + NTHR - 1) / NTHR;
+  for (int qq = 0; qq < TB / 2; ++qq) {
 #pragma unroll
-    for (int u = 0; u < per; ++u) {
-      const int q = (int)threadIdx.x + u * NTHR;
-      if (q < hp1) {
-        const int t = r * q;
-        const cplx<T> w = cmul<T>(thi[t >> tsh], tlo[t & tmask]);
-        const int qm = (L2 - q) & (L2 - 1);
-        const cplx<T> v = separate<T>(Yre[pad(q)], Yim[pad(q)], Yre[pad(qm)], Yim[pad(qm)], rl);
-        G2c[r * sg2i + q] = cmul<T>(v, w);
+    for (int i = 0; i < kPPT; ++i) {
+      const int m = (int)threadIdx.x + i * NTHR;
+      Yre[pad(m)] = dv[2 * qq][i];
+      Yim[pad(m)] = dv[2 * qq + 1][i];
+    }
+    __syncthreads();
+    fft_ct<T, LOGL2, 1>(Yre, tw);
+#pragma unroll
+    for (int rl = 0; rl < 2; ++rl) {
+      const int r = t0 + 2 * qq + rl;
+      if (r > L1 / 2) continue;
+      constexpr int per = (hp1 + NTHR - 1) / NTHR;
+#pragma unroll
+      for (int u = 0; u < per; ++u) {
+        const int q = (int)threadIdx.x + u * NTHR;
+        if (q < hp1) {
+          const int t = r * q;
+          const cplx<T> w = cmul<T>(thi[t >> tsh], tlo[t & tmask]);
+          const int qm = (L2 - q) & (L2 - 1);
+          const cplx<T> v = separate<T>(Yre[pad(q)], Yim[pad(q)], Yre[pad(qm)], Yim[pad(qm)], rl);
+          G2c[r * sg2i + q] = cmul<T>(v, w);
+        }
       }
     }
+    __syncthreads();
   }
 }
 
@@ -1109,8 +1118,10 @@ static void fast_shape(const birk_plan* p, int64_t N, int& logL1, int& logL2, in
   while (WC > 2 && WC * L1 / 2 > maxpts) WC /= 2;
 }
 
-// Pass B takes the two-row register kernel when its rows are 512..2048 points long.
+// Pass B takes the register kernel when its rows are 512..2048 points long, with 2 or 4
+// rows per tile.
 static bool use_b2(const birk_plan* p, int logL2) { return p->fast_b2 && logL2 >= 9 && logL2 <= 11; }
+static int b2_rows(const birk_plan* p) { return p->fast_tb == 4 ? 4 : 2; }
 
 // Pass-B tiles per component (rows 0..L1/2 in tiles of TB, or of 2 for the register kernel).
 template <typename T>
@@ -1118,7 +1129,7 @@ static int fast_tiles_b(const birk_plan* p, int64_t N) {
   int logL1, logL2, WA, TB, WC;
   fast_shape<T>(p, N, logL1, logL2, WA, TB, WC);
   const int rows = (1 << logL1) / 2 + 1;
-  const int tb = use_b2(p, logL2) ? 2 : TB;
+  const int tb = use_b2(p, logL2) ? b2_rows(p) : TB;
   return (rows + tb - 1) / tb;
 }
 
@@ -1202,14 +1213,21 @@ hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, in
   if (use_b2(p, logL2)) {
     const int lds = 2 * ld2 * (int)sizeof(T);
     const int thr = L2 / fast::kPPT;
-    auto f = fast::k_fastB2<T, 0, 11>;
-    switch (logL2 * 2 + (transpose ? 1 : 0)) {
-      case 18: f = fast::k_fastB2<T, 0, 9>; break;
-      case 19: f = fast::k_fastB2<T, 1, 9>; break;
-      case 20: f = fast::k_fastB2<T, 0, 10>; break;
-      case 21: f = fast::k_fastB2<T, 1, 10>; break;
-      case 22: f = fast::k_fastB2<T, 0, 11>; break;
-      default: f = fast::k_fastB2<T, 1, 11>; break;
+    auto f = fast::k_fastB2<T, 0, 11, 2>;
+    const int tb4 = b2_rows(p) == 4;
+    switch ((logL2 * 2 + (transpose ? 1 : 0)) * 2 + tb4) {
+      case 36: f = fast::k_fastB2<T, 0, 9, 2>; break;
+      case 37: f = fast::k_fastB2<T, 0, 9, 4>; break;
+      case 38: f = fast::k_fastB2<T, 1, 9, 2>; break;
+      case 39: f = fast::k_fastB2<T, 1, 9, 4>; break;
+      case 40: f = fast::k_fastB2<T, 0, 10, 2>; break;
+      case 41: f = fast::k_fastB2<T, 0, 10, 4>; break;
+      case 42: f = fast::k_fastB2<T, 1, 10, 2>; break;
+      case 43: f = fast::k_fastB2<T, 1, 10, 4>; break;
+      case 44: f = fast::k_fastB2<T, 0, 11, 2>; break;
+      case 45: f = fast::k_fastB2<T, 0, 11, 4>; break;
+      case 46: f = fast::k_fastB2<T, 1, 11, 2>; break;
+      default: f = fast::k_fastB2<T, 1, 11, 4>; break;
     }
     lds_attr(f, lds);
     hipLaunchKernelGGL(f, dim3(ntB * nc), dim3(thr), lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, tw, thi, tlo,
