@@ -104,6 +104,9 @@ struct PinvDesc {
   int64_t st[kPinvMaxLevels] = {};      // start-state offsets (doubles) per level
   int L = 0;                            // top level
   int nb0 = 0;                          // level-0 blocks of 64 groups
+  // wave-scan path (n_x <= kWaveNx): tiles of kTileNodes nodes
+  int64_t ntile = 0;                    // tiles of the instance
+  int64_t tagg = 0, tst = 0;            // tile aggregates and tile start states (doubles)
 };
 
 // Instances with one state count n_x: each scan phase is one launch over all of them.
@@ -124,6 +127,8 @@ struct PinvClass {
   int n_swz[2] = {0, 0};
   int2* t_nodes = nullptr;                   // (k, block of 256 nodes): J x
   int n_nodes = 0;
+  int2* t_tile = nullptr;                    // (k, tile) of the wave-scan path
+  int n_tile = 0;
 };
 
 // Krylov vector segmentation: tiles of kSegChunk elements, each inside one instance.

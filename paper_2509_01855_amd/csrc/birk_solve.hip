@@ -614,6 +614,386 @@ __global__ __launch_bounds__(256) void k_pinv_final(const T* __restrict__ jsw, c
   }
 }
 
+// ---- wave-scan path (n_x <= kWaveNx) ----
+// A tile is kTileThreads threads of kTC consecutive nodes each: thread t of tile g owns
+// chunk c = g kTileThreads + t, nodes k = c kTC + j (j < kTC), so the lanes of a wave
+// hold consecutive chunks in node order.  Per-node fields (the n_x^2 entries of H_k, then
+// w_k) are stored as [g][j][e][t]: each access of a wave is 64 consecutive values.
+// Three launches per class:
+//   reduce  each thread composes its chunk's node maps; a DPP scan across the wave and
+//           a 4-lane scan of the wave totals give the tile aggregate;
+//   tiles   one workgroup per instance scans the tile aggregates into tile start states;
+//   apply   each tile rebuilds its chunk maps, scans them across the wave, derives every
+//           chunk's start state from the tile's and replays its nodes.
+// Nodes past N_n carry H = 0 (identity maps) and are neither read from y nor written.
+constexpr int kWaveNx = 8;
+constexpr int kTileThreads = 256;
+constexpr int kTC = 4;
+constexpr int64_t kTileNodes = (int64_t)kTileThreads * kTC;
+
+template <int NX>
+struct Aff {
+  double A[NX][NX];
+  double b[NX];
+};
+
+template <int NX>
+__device__ __forceinline__ void aff_identity(Aff<NX>& m) {
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    m.b[r] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NX; ++q) m.A[r][q] = (r == q) ? 1.0 : 0.0;
+  }
+}
+
+// s <- m(s) = A s + b
+template <int NX>
+__device__ __forceinline__ void aff_apply(const Aff<NX>& m, double (&s)[NX]) {
+  double ns[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    double acc = m.b[r];
+#pragma unroll
+    for (int q = 0; q < NX; ++q) acc += m.A[r][q] * s[q];
+    ns[r] = acc;
+  }
+#pragma unroll
+  for (int r = 0; r < NX; ++r) s[r] = ns[r];
+}
+
+// v of the lane that DPP control CTRL selects, in the rows that ROWMASK enables
+// (row_shr:n = 0x110 + n, row_bcast:15 = 0x142, row_bcast:31 = 0x143); a lane with no
+// source keeps its own v.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long x = __builtin_bit_cast(unsigned long long, v);
+  const int lo = (int)(unsigned)x, hi = (int)(unsigned)(x >> 32);
+  const int rlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
+  const int rhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)rhi << 32) | (unsigned)(unsigned)rlo);
+}
+
+// Where take: m <- m o e, e = the map of the source lane (applied first):
+// (A_m A_e, A_m b_e + b_m).  e arrives one row at a time.
+template <int NX, int CTRL, int ROWMASK>
+__device__ __forceinline__ void scan_step(Aff<NX>& m, bool take) {
+  double nA[NX][NX], nb[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    nb[r] = m.b[r];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) nA[r][c] = 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < NX; ++q) {
+    double er[NX];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) er[c] = dpp_f64<CTRL, ROWMASK>(m.A[q][c]);
+    const double eb = dpp_f64<CTRL, ROWMASK>(m.b[q]);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      const double a = m.A[r][q];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) nA[r][c] += a * er[c];
+      nb[r] += a * eb;
+    }
+  }
+  if (take) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      m.b[r] = nb[r];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) m.A[r][c] = nA[r][c];
+    }
+  }
+}
+
+// Inclusive scan of the lanes' maps in lane order: lane l ends with m_l o ... o m_0.
+// Rows of 16 lanes scan by row_shr 1, 2, 4, 8; row_bcast:15 then row_bcast:31 carry the
+// totals of the earlier rows.
+template <int NX>
+__device__ __forceinline__ void wave_scan(Aff<NX>& m) {
+  const int l = (int)(threadIdx.x & 63), lr = l & 15;
+  scan_step<NX, 0x111, 0xF>(m, lr >= 1);
+  scan_step<NX, 0x112, 0xF>(m, lr >= 2);
+  scan_step<NX, 0x114, 0xF>(m, lr >= 4);
+  scan_step<NX, 0x118, 0xF>(m, lr >= 8);
+  scan_step<NX, 0x142, 0xA>(m, ((l >> 4) & 1) != 0);
+  scan_step<NX, 0x143, 0xC>(m, l >= 32);
+}
+
+// The map of one chunk: node k takes S -> (I + H_k) S + H_k y_k, so from A = I, b = 0 the
+// first node gives (I + H, H y) and each further node A <- A + H A, b <- b + H (b + y).
+// hs points at the thread's slot of field 0, node 0 of its tile.
+template <int NX, typename T>
+__device__ __forceinline__ void chunk_map(const T* __restrict__ hs, const T* __restrict__ yi, int64_t Nn, int64_t k0,
+                                          Aff<NX>& m) {
+  constexpr int E = NX * NX + 1;
+#pragma unroll 1
+  for (int j = 0; j < kTC; ++j) {
+    const int64_t k = k0 + j;
+    const T* base = hs + (int64_t)j * E * kTileThreads;
+    double H[NX][NX], yv[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int q = 0; q < NX; ++q) H[r][q] = (double)base[(r * NX + q) * kTileThreads];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) yv[r] = (k < Nn) ? (double)yi[(int64_t)r * Nn + k] : 0.0;
+    if (j == 0) {
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < NX; ++q) {
+          m.A[r][q] = H[r][q] + ((r == q) ? 1.0 : 0.0);
+          acc += H[r][q] * yv[q];
+        }
+        m.b[r] = acc;
+      }
+    } else {
+      double u[NX];
+#pragma unroll
+      for (int r = 0; r < NX; ++r) u[r] = m.b[r] + yv[r];
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < NX; ++q) acc += H[r][q] * u[q];
+        m.b[r] += acc;
+      }
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        double t[NX];
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+          double acc = 0.0;
+#pragma unroll
+          for (int q = 0; q < NX; ++q) acc += H[r][q] * m.A[q][c];
+          t[r] = acc;
+        }
+#pragma unroll
+        for (int r = 0; r < NX; ++r) m.A[r][c] += t[r];
+      }
+    }
+  }
+}
+
+template <int NX>
+__device__ __forceinline__ void aff_store(double* __restrict__ o, const Aff<NX>& m) {
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+#pragma unroll
+    for (int q = 0; q < NX; ++q) o[r * NX + q] = m.A[r][q];
+    o[NX * NX + r] = m.b[r];
+  }
+}
+
+template <int NX>
+__device__ __forceinline__ void aff_load(const double* __restrict__ o, Aff<NX>& m) {
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+#pragma unroll
+    for (int q = 0; q < NX; ++q) m.A[r][q] = o[r * NX + q];
+    m.b[r] = o[NX * NX + r];
+  }
+}
+
+// H_k and w_k of every node in the tile layout, straight from J (per node or constant)
+// and the weights: K = I - (w_k / 2) J_k by unpivoted LU (pivot check as lu_kmat), then
+// H_k = K^{-1} (w_k J_k) column by column.  Slots of nodes past N_n are zeroed.  Each
+// of the kTC rounds of the workgroup takes kTileThreads consecutive nodes (coalesced
+// reads of J and w) and writes each node to its chunk's slot.  tile = (k, g).
+template <int NX, typename JT>
+__global__ __launch_bounds__(kTileThreads, 2) void k_tmake_h(JT* __restrict__ jsw, const double* __restrict__ J,
+                                                            int per_node, const PinvDesc* __restrict__ pd,
+                                                            const int2* __restrict__ tiles, int* flag) {
+  const int2 t = tiles[blockIdx.x];
+  const PinvDesc& d = pd[t.x];
+  const int64_t g = t.y;
+  constexpr int E = NX * NX + 1;
+  const int64_t Nn = d.Nn;
+  JT* tb = jsw + d.jsw_off + g * kTC * E * kTileThreads;
+  const double* Jn = J + d.joff;
+  const double* Jc = J + d.jcoff;
+#pragma unroll 1
+  for (int j = 0; j < kTC; ++j) {
+    const int i = j * kTileThreads + (int)threadIdx.x;  // node within the tile
+    const int64_t k = g * kTileNodes + i;
+    JT* base = tb + (int64_t)(i % kTC) * E * kTileThreads + i / kTC;
+    if (k >= Nn) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) base[e * kTileThreads] = (JT)0;
+      continue;
+    }
+    const double wk = d.w[k];
+    double Jk[NX][NX], K[NX][NX], rp[NX];
+    double jmax = 0.0;
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int q = 0; q < NX; ++q) {
+        const double jv = per_node ? Jn[(int64_t)(r * NX + q) * Nn + k] : Jc[r * NX + q];
+        Jk[r][q] = jv;
+        jmax = fmax(jmax, fabs(jv));
+        K[r][q] = (r == q ? 1.0 : 0.0) - 0.5 * wk * jv;
+      }
+    lu_kmat<NX>(K, rp, flag, 1.0 + 0.5 * fabs(wk) * jmax);
+#pragma unroll
+    for (int cc = 0; cc < NX; ++cc) {
+      double x[NX];
+#pragma unroll
+      for (int r = 0; r < NX; ++r) x[r] = wk * Jk[r][cc];
+      lu_solve<NX>(K, rp, x);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) base[(r * NX + cc) * kTileThreads] = (JT)x[r];
+    }
+    base[(E - 1) * kTileThreads] = (JT)wk;
+  }
+}
+
+// Tile aggregate: the composition of the tile's node maps, to scan[tagg + g F].
+// tile = (k, g).
+template <int NX, typename T>
+__global__ __launch_bounds__(kTileThreads) void k_tscan_reduce(const T* __restrict__ jsw, const T* __restrict__ y,
+                                                             const PinvDesc* __restrict__ pd,
+                                                             const int2* __restrict__ tiles,
+                                                             double* __restrict__ scan) {
+  constexpr int E = NX * NX + 1;
+  constexpr int F = NX * NX + NX;
+  constexpr int NW = kTileThreads / 64;
+  __shared__ double tot[NW][F];
+  const int2 t = tiles[blockIdx.x];
+  const PinvDesc& d = pd[t.x];
+  const int64_t g = t.y;
+  const T* hs = jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x;
+  const int64_t k0 = (g * kTileThreads + threadIdx.x) * kTC;
+  Aff<NX> m;
+  chunk_map<NX, T>(hs, y + d.off, d.Nn, k0, m);
+  wave_scan<NX>(m);
+  const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
+  if (l == 63) aff_store<NX>(&tot[w][0], m);
+  __syncthreads();
+  if (w == 0) {
+    // lanes 0..NW-1 hold the wave totals; a row_shr scan over them leaves the tile
+    // aggregate in lane NW - 1
+    if (l < NW)
+      aff_load<NX>(&tot[l][0], m);
+    else
+      aff_identity<NX>(m);
+    scan_step<NX, 0x111, 0xF>(m, l >= 1);
+    scan_step<NX, 0x112, 0xF>(m, l >= 2);
+    if (l == NW - 1) aff_store<NX>(scan + d.tagg + g * F, m);
+  }
+}
+
+// Tile start states of one instance (S = 0 before node 0), one workgroup per instance:
+// thread t composes the aggregates of tiles [t q, t q + q), the maps are scanned across
+// the workgroup, and each thread then walks its tiles from its start state.
+template <int NX>
+__global__ __launch_bounds__(256) void k_tscan_tiles(double* __restrict__ scan, const PinvDesc* __restrict__ pd) {
+  constexpr int F = NX * NX + NX;
+  __shared__ double tot[4][F];
+  const PinvDesc& d = pd[blockIdx.x];
+  const int64_t nt = d.ntile;
+  const int64_t q = (nt + 255) / 256;
+  const int64_t i0 = (int64_t)threadIdx.x * q;
+  const int64_t i1 = min(nt, i0 + q);
+  const double* agg = scan + d.tagg;
+  Aff<NX> m;
+  aff_identity<NX>(m);
+  for (int64_t i = i0; i < i1; ++i) compose<NX>(agg + i * F, 1, m.A, m.b);
+  wave_scan<NX>(m);
+  const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
+  if (l == 63) aff_store<NX>(&tot[w][0], m);
+  __syncthreads();
+  double s[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) s[r] = 0.0;
+  for (int v = 0; v < w; ++v) advance<NX>(&tot[v][0], 1, s);
+  double x[NX];
+#pragma unroll
+  for (int r = 0; r < NX; ++r) x[r] = s[r];
+  aff_apply<NX>(m, x);
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    const double up = __shfl_up(x[r], 1);
+    s[r] = (l == 0) ? s[r] : up;
+  }
+  double* st = scan + d.tst;
+  for (int64_t i = i0; i < i1; ++i) {
+#pragma unroll
+    for (int r = 0; r < NX; ++r) st[i * NX + r] = s[r];
+    advance<NX>(agg + i * F, 1, s);
+  }
+}
+
+// Replay of one tile from its start state: chunk maps are rebuilt and scanned across
+// the wave; chunk start state = (maps of the earlier chunks)(tile start state); then per
+// node u = y_k + S, v = H_k u, xi_k = u + v / 2, (J xi)_k = v / w_k, S <- S + v.
+// tile = (k, g).
+template <int NX, typename T>
+__global__ __launch_bounds__(kTileThreads, 2) void k_tscan_apply(const T* __restrict__ jsw, const T* __restrict__ y,
+                                                            const PinvDesc* __restrict__ pd,
+                                                            const int2* __restrict__ tiles,
+                                                            const double* __restrict__ scan, T* __restrict__ out,
+                                                            T* __restrict__ jout) {
+  constexpr int E = NX * NX + 1;
+  constexpr int F = NX * NX + NX;
+  constexpr int NW = kTileThreads / 64;
+  __shared__ double tot[NW][F];
+  const int2 t = tiles[blockIdx.x];
+  const PinvDesc& d = pd[t.x];
+  const int64_t g = t.y;
+  const int64_t Nn = d.Nn;
+  const T* hs = jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x;
+  const T* yi = y + d.off;
+  const int64_t k0 = (g * kTileThreads + threadIdx.x) * kTC;
+  double s[NX];
+  {
+    Aff<NX> m;
+    chunk_map<NX, T>(hs, yi, Nn, k0, m);
+    wave_scan<NX>(m);
+    const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
+    if (l == 63) aff_store<NX>(&tot[w][0], m);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NX; ++r) s[r] = scan[d.tst + g * NX + r];
+    for (int v = 0; v < w; ++v) advance<NX>(&tot[v][0], 1, s);
+    double x[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) x[r] = s[r];
+    aff_apply<NX>(m, x);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      const double up = __shfl_up(x[r], 1);
+      s[r] = (l == 0) ? s[r] : up;
+    }
+  }
+  T* oi = out + d.off;
+  T* ji = jout ? jout + d.off : nullptr;
+#pragma unroll 1
+  for (int j = 0; j < kTC; ++j) {
+    const int64_t k = k0 + j;
+    if (k >= Nn) break;
+    const T* base = hs + (int64_t)j * E * kTileThreads;
+    const double inv_w = 1.0 / (double)base[(E - 1) * kTileThreads];
+    double u[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) u[r] = s[r] + (double)yi[(int64_t)r * Nn + k];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < NX; ++q) v += (double)base[(r * NX + q) * kTileThreads] * u[q];
+      s[r] += v;
+      oi[(int64_t)r * Nn + k] = (T)(u[r] + 0.5 * v);
+      if (ji) ji[(int64_t)r * Nn + k] = (T)(v * inv_w);
+    }
+  }
+}
+
 // y_k = J_k x_k per node for every instance of a class.  tile = (k, block of 256 nodes).
 template <int NX, typename T>
 __global__ __launch_bounds__(256) void k_jac_class(const double* __restrict__ J, int per_node,
@@ -660,7 +1040,10 @@ static int64_t pinv_blocks0(int64_t nchunks) {
   return (groups + 63) / 64;
 }
 
+static int64_t pinv_tiles(int64_t Nn) { return (Nn + kTileNodes - 1) / kTileNodes; }
+
 int64_t pinv_jsw_size(int64_t Nn, int nx) {
+  if (nx <= kWaveNx) return pinv_tiles(Nn) * kTileNodes * ((int64_t)nx * nx + 1);
   int64_t cnt[kPinvMaxLevels];
   pinv_levels(Nn, cnt);
   return pinv_blocks0(cnt[0]) * 64 * kFan * kChunk * ((int64_t)nx * nx + 1);
@@ -669,6 +1052,7 @@ int64_t pinv_jsw_size(int64_t Nn, int nx) {
 // Scratch (doubles) the inverse scan needs for one instance (level 0 in whole blocks).
 int64_t pinv_scratch(int64_t Nn, int nx) {
   const int64_t S = (int64_t)nx * nx + 2 * nx;
+  if (nx <= kWaveNx) return pinv_tiles(Nn) * S;
   int64_t cnt[kPinvMaxLevels];
   const int L = pinv_levels(Nn, cnt);
   int64_t tot = pinv_blocks0(cnt[0]) * 64 * kFan * S;
@@ -701,11 +1085,19 @@ hipError_t plan_solve(birk_plan* p) {
       d.jcoff = in.jcoff;
       d.jsw_off = in.jsw_off;
       d.w = in.w;
+      const int64_t S = (int64_t)nx * nx + nx;
+      int64_t base = in.scan_off;
+      if (nx <= kWaveNx) {
+        // scratch: tile aggregates, then tile start states
+        d.ntile = pinv_tiles(in.Nn);
+        d.tagg = base;
+        d.tst = base + d.ntile * S;
+        pc.host.push_back(d);
+        continue;
+      }
       d.L = pinv_levels(in.Nn, d.cnt);
       d.nb0 = (int)pinv_blocks0(d.cnt[0]);
       // scratch: for each level l: agg[slots * S] then state[slots * NX]; level 0 swizzled
-      const int64_t S = (int64_t)nx * nx + nx;
-      int64_t base = in.scan_off;
       for (int l = 0; l <= d.L; ++l) {
         const int64_t slots = (l == 0) ? (int64_t)d.nb0 * 64 * kFan : d.cnt[l];
         d.agg[l] = base;
@@ -718,9 +1110,14 @@ hipError_t plan_solve(birk_plan* p) {
     }
     if (pc.host.empty()) continue;
     pc.ninst = (int)pc.host.size();
-    std::vector<int2> t0, tn, tsw[2], tup[kPinvMaxLevels], tupc[kPinvMaxLevels];
+    std::vector<int2> t0, tn, tt, tsw[2], tup[kPinvMaxLevels], tupc[kPinvMaxLevels];
     for (int k = 0; k < pc.ninst; ++k) {
       const PinvDesc& d = pc.host[k];
+      if (nx <= kWaveNx) {
+        for (int64_t g = 0; g < d.ntile; ++g) tt.push_back(make_int2(k, (int)g));
+        for (unsigned b = 0; b < nblocks(d.Nn, 256); ++b) tn.push_back(make_int2(k, (int)b));
+        continue;
+      }
       const int64_t thr0 = (int64_t)d.nb0 * 64 * kFan;
       for (unsigned b = 0; b < nblocks(thr0, 256); ++b) t0.push_back(make_int2(k, (int)b));
       for (unsigned b = 0; b < nblocks(d.Nn, 256); ++b) tn.push_back(make_int2(k, (int)b));
@@ -744,6 +1141,8 @@ hipError_t plan_solve(birk_plan* p) {
     pc.n_node0 = (int)t0.size();
     if ((e = upload_tiles(p, tn, &pc.t_nodes)) != hipSuccess) return e;
     pc.n_nodes = (int)tn.size();
+    if ((e = upload_tiles(p, tt, &pc.t_tile)) != hipSuccess) return e;
+    pc.n_tile = (int)tt.size();
     for (int pn = 0; pn < 2; ++pn) {
       if ((e = upload_tiles(p, tsw[pn], &pc.t_swz[pn])) != hipSuccess) return e;
       pc.n_swz[pn] = (int)tsw[pn].size();
@@ -789,8 +1188,16 @@ hipError_t plan_solve(birk_plan* p) {
 
 template <int NX, typename JT>
 static void make_h_class(birk_plan* p, const PinvClass& pc, const double* J, int pn, hipStream_t s) {
-  hipLaunchKernelGGL((k_make_h<NX, JT>), dim3(pc.n_node0), dim3(256), 0, s, (JT*)p->jsw, J, pn, pc.dev, pc.t_node0,
-                     p->flag);
+  if constexpr (NX <= kWaveNx) {
+    hipLaunchKernelGGL((k_tmake_h<NX, JT>), dim3(pc.n_tile), dim3(kTileThreads), 0, s, (JT*)p->jsw, J, pn, pc.dev,
+                       pc.t_tile, p->flag);
+  } else {
+    if (pc.n_swz[pn] == 0) return;
+    hipLaunchKernelGGL(k_swizzle_nodes<JT>, dim3(pc.n_swz[pn]), dim3(256), 0, s, J, pn, pc.nx, pc.dev, pc.t_swz[pn],
+                       (JT*)p->jsw);
+    hipLaunchKernelGGL((k_make_h<NX, JT>), dim3(pc.n_node0), dim3(256), 0, s, (JT*)p->jsw, J, pn, pc.dev, pc.t_node0,
+                       p->flag);
+  }
 }
 
 #define BIRK_NX_SWITCH(nx, CALL)                                       \
@@ -810,18 +1217,12 @@ static void make_h_class(birk_plan* p, const PinvClass& pc, const double* J, int
     default: return hipErrorInvalidValue;                              \
   }
 
-// Lay the weights (and per-node J) out in the level-0 slots, then replace the J fields by
-// H_k (k_make_h).  Runs once per Jacobian; the scan itself only reads H_k and w_k.
+// H_k and w_k in the scan's node slots, once per Jacobian: n_x <= kWaveNx straight from J
+// in the tile layout (k_tmake_h); larger n_x lay J and w out in the level-0 slots and
+// replace the J fields by H_k (k_make_h).  The scans themselves only read H_k and w_k.
 hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s) {
   const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
   for (const PinvClass& pc : p->pclass) {
-    if (pc.n_swz[pn] == 0) continue;
-    if (single)
-      hipLaunchKernelGGL(k_swizzle_nodes<float>, dim3(pc.n_swz[pn]), dim3(256), 0, s, J, pn, pc.nx, pc.dev,
-                         pc.t_swz[pn], (float*)p->jsw);
-    else
-      hipLaunchKernelGGL(k_swizzle_nodes<double>, dim3(pc.n_swz[pn]), dim3(256), 0, s, J, pn, pc.nx, pc.dev,
-                         pc.t_swz[pn], p->jsw);
     if (single) {
       BIRK_NX_SWITCH(pc.nx, (make_h_class<NXC, float>(p, pc, J, pn, s)))
     } else {
@@ -835,15 +1236,23 @@ template <int NX, typename T>
 static void pinv_class(birk_plan* p, const PinvClass& pc, const T* y, T* out, T* jout, hipStream_t s) {
   const T* jsw = (const T*)p->jsw;
   double* scan = p->scan;
-  constexpr int ncg = ColGroups<NX>::count;
-  hipLaunchKernelGGL((k_pinv_up0<NX, T>), dim3(pc.n_node0, ncg), dim3(256), 0, s, jsw, y, pc.dev, pc.t_node0, scan);
-  for (int l = 0; l < pc.Lmax; ++l)
-    hipLaunchKernelGGL((k_pinv_up<NX>), dim3(pc.n_up[l], ncg), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
-  hipLaunchKernelGGL((k_pinv_top<NX>), dim3(pc.ninst), dim3(64), 0, s, scan, pc.dev);
-  for (int l = pc.Lmax - 1; l >= 0; --l)
-    hipLaunchKernelGGL((k_pinv_down<NX>), dim3(pc.n_up[l]), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
-  hipLaunchKernelGGL((k_pinv_final<NX, T>), dim3(pc.n_node0), dim3(256), 0, s, jsw, y, pc.dev, pc.t_node0, scan, out,
-                     jout);
+  if constexpr (NX <= kWaveNx) {
+    hipLaunchKernelGGL((k_tscan_reduce<NX, T>), dim3(pc.n_tile), dim3(kTileThreads), 0, s, jsw, y, pc.dev, pc.t_tile,
+                       scan);
+    hipLaunchKernelGGL((k_tscan_tiles<NX>), dim3(pc.ninst), dim3(256), 0, s, scan, pc.dev);
+    hipLaunchKernelGGL((k_tscan_apply<NX, T>), dim3(pc.n_tile), dim3(kTileThreads), 0, s, jsw, y, pc.dev, pc.t_tile,
+                       scan, out, jout);
+  } else {
+    constexpr int ncg = ColGroups<NX>::count;
+    hipLaunchKernelGGL((k_pinv_up0<NX, T>), dim3(pc.n_node0, ncg), dim3(256), 0, s, jsw, y, pc.dev, pc.t_node0, scan);
+    for (int l = 0; l < pc.Lmax; ++l)
+      hipLaunchKernelGGL((k_pinv_up<NX>), dim3(pc.n_up[l], ncg), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
+    hipLaunchKernelGGL((k_pinv_top<NX>), dim3(pc.ninst), dim3(64), 0, s, scan, pc.dev);
+    for (int l = pc.Lmax - 1; l >= 0; --l)
+      hipLaunchKernelGGL((k_pinv_down<NX>), dim3(pc.n_up[l]), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
+    hipLaunchKernelGGL((k_pinv_final<NX, T>), dim3(pc.n_node0), dim3(256), 0, s, jsw, y, pc.dev, pc.t_node0, scan,
+                       out, jout);
+  }
 }
 
 template <int NX, typename T>
