@@ -16,7 +16,10 @@
 // length L = 2N.  Two real vectors are packed into one complex sequence (the DFT of a
 // real even sequence is real, so real and imaginary parts separate).  L a power of
 // two: radix-4/2 Stockham FFTs in LDS, four-step above the LDS limit.  Any other L:
-// Bluestein's chirp-z identity with a power-of-two FFT of length M >= 2L - 1.
+// Bluestein's chirp-z identity with a power-of-two FFT of length M >= N + L = 3N.  Only
+// the N + 1 outputs k = 0..N are needed, so the lags k - n of the convolution lie in
+// [-(L - 1), N]: the filter holds lags 0..N at the start and -1..-(L - 1) at the end of
+// the circular buffer, which do not meet once M >= N + L.
 //
 // Batching: the pairs of all instances of one kind (plain power of two, or Bluestein)
 // form a PairSet.  Each phase of the product (pack, FFT passes, filter, stencil, c^_0,
@@ -792,13 +795,15 @@ static hipError_t upload_all(birk_plan* p, const std::vector<double>& re, const 
   return e;
 }
 
+// Bluestein filter b_m = conj(chirp_|lag|) on the circular buffer of length M: lags
+// 0..N at m = lag, lags -1..-(L - 1) at m = M + lag, zero between.
 template <typename T>
 __global__ void k_build_filter(cplx<T>* __restrict__ b, const cplx<T>* __restrict__ chirp, int64_t L,
                                int64_t M) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= M) return;
   cplx<T> v = mk<T>(T(0), T(0));
-  if (m < L) {
+  if (m <= L / 2) {
     v = chirp[m];
     v.y = -v.y;
   } else if (M - m < L) {
@@ -829,7 +834,7 @@ static PairDesc make_pair(int64_t src, int64_t Nn, int has2) {
   d.N = Nn - 1;
   d.L = 2 * d.N;
   const bool pow2 = (d.L & (d.L - 1)) == 0;
-  d.M = pow2 ? d.L : (int64_t(1) << ilog2_ceil(2 * d.L - 1));
+  d.M = pow2 ? d.L : (int64_t(1) << ilog2_ceil(d.N + d.L));
   d.logM = ilog2_ceil(d.M);
   if (d.logM > kLdsMaxLog) {
     d.logM1 = (d.logM + 1) / 2;

@@ -24,7 +24,10 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-12, "f32": 2e-5}
 
-SIZES = [3, 4, 5, 6, 9, 10, 17, 33, 100, 256, 257, 1000, 1025, 2049, 3000, 4097]
+# Bluestein lengths M = 2^ceil(log2(3N)): 342 and 1366 fill M exactly (3N = M - 1), 343
+# and 1367 step to the next M (1366 is the largest in one LDS kernel, 1367 the smallest
+# in the three fused passes).
+SIZES = [3, 4, 5, 6, 9, 10, 17, 33, 100, 256, 257, 342, 343, 1000, 1025, 1366, 1367, 2049, 3000, 4097]
 
 
 @pytest.fixture(scope="module")
