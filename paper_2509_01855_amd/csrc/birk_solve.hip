@@ -210,7 +210,7 @@ __device__ __forceinline__ int64_t swz(int64_t B, int i, int field, int nfield, 
 }
 
 // Swizzle per-node data for the level-0 kernels.  E = nx^2 + 1 fields per node: fields
-// e < nx^2 take J entry e at the node (per-node Jacobians only; k_make_h then replaces
+// e < nx^2 take J entry e at the node (per-node Jacobians only; k_make_h_rows then replaces
 // them by H_k), the last field is w_k.  Node k -> chunk c = k / kChunk, j = k % kChunk;
 // g = c / kFan, i = c % kFan; B = g / 64, l = g % 64; stored at
 // jsw[(((B kFan + i) kChunk + j) E + e) 64 + l].  Nodes past N_n are zero.  One
@@ -247,54 +247,80 @@ __global__ __launch_bounds__(256) void k_swizzle_nodes(const double* __restrict_
   }
 }
 
-// Per node, H_k = w_k J_k K_k^{-1} with K_k = I - w_k J_k / 2, by an unpivoted LU of K_k
-// and NX solves K_k X = w_k J_k (J_k commutes with K_k^{-1}).  Everything the scan needs
-// follows from H_k:  K_k^{-1} = I + H_k / 2, so for u = y_k + S_k
+// Per node, H_k = w_k J_k K_k^{-1} with K_k = I - w_k J_k / 2 (J_k commutes with K_k^{-1}).
+// Everything the scan needs follows from H_k:  K_k^{-1} = I + H_k / 2, so for
+// u = y_k + S_k
 //     xi_k = u + H_k u / 2,   J_k xi_k = H_k u / w_k,   S_{k+1} = S_k + H_k u,
-// and the affine map of the node is S -> (I + H_k) S + H_k y_k.  H_k is written over
-// the J fields of the node's slot (in place; constant J: into the empty fields).  A
-// pivot that is non-finite or not above 1e-13 (1 + |w_k / 2| max |J_k|) sets *flag.
-// Thread per level-0 chunk in the level-0 layout (as k_pinv_final); nodes past N_n are
-// never read by the scan and are left alone.  tile = (k, block of 256 level-0 threads).
+// and the affine map of the node is S -> (I + H_k) S + H_k y_k.  H_k is written over the
+// J fields of the node's level-0 slot (in place; constant J: into the empty fields).
+// Sixteen lanes per chunk: lane r < NX holds row r of [K_k | w_k J_k] and Gauss-Jordan
+// elimination without pivoting, the pivot row broadcast across the sixteen lanes, turns
+// it into [I | K_k^{-1} w_k J_k]; its pivots are those of the unpivoted LU, and one that
+// is non-finite or not above 1e-13 (1 + |w_k / 2| max |J_k|) sets *flag.  A chunk's 16
+// nodes are taken in turn; the four chunks of a wave are neighbours in the slot layout.
+// grid = (tile (k, block of 256 level-0 threads), 16 groups of 16 chunks).
 template <int NX, typename JT>
-__global__ __launch_bounds__(256, 2) void k_make_h(JT* __restrict__ jsw, const double* __restrict__ J, int per_node,
-                                                const PinvDesc* __restrict__ pd, const int2* __restrict__ tiles,
-                                                int* flag) {
+__global__ __launch_bounds__(256) void k_make_h_rows(JT* __restrict__ jsw, const double* __restrict__ J,
+                                                    int per_node, const PinvDesc* __restrict__ pd,
+                                                    const int2* __restrict__ tiles, int* flag) {
+  static_assert(NX <= 16, "one row per lane of a 16-lane group");
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
-  const int64_t tau = (int64_t)t.y * blockDim.x + threadIdx.x;
+  const int64_t tau = (int64_t)t.y * 256 + blockIdx.y * 16 + (threadIdx.x >> 4);
+  const int r = (int)(threadIdx.x & 15);
   const int64_t B = tau / (64 * kFan);
   const int i = (int)((tau >> 6) % kFan);
   const int l = (int)(tau & 63);
   const int64_t c = (B * 64 + l) * kFan + i;
-  if (c >= d.cnt[0]) return;
+  if (c >= d.cnt[0]) return;  // the whole group leaves together
   constexpr int E = NX * NX + 1;
   const double* Jc = J + d.jcoff;
   JT* js = jsw + d.jsw_off + ((B * kFan + i) * kChunk) * E * 64 + l;
   const int jn = (int)min((int64_t)kChunk, d.Nn - c * kChunk);
+  const bool act = r < NX;
+  const int rr = act ? r : 0;
 #pragma unroll 1
   for (int j = 0; j < jn; ++j) {
     JT* base = js + (int64_t)j * E * 64;
     const double wk = (double)base[(E - 1) * 64];
-    double K[NX][NX], rp[NX];
-    double jmax = 0.0;
+    double Kr[NX], Xr[NX];
+    double jm = 0.0;
 #pragma unroll
-    for (int r = 0; r < NX; ++r)
+    for (int q = 0; q < NX; ++q) {
+      const double jv = act ? (per_node ? (double)base[(rr * NX + q) * 64] : Jc[rr * NX + q]) : 0.0;
+      jm = fmax(jm, fabs(jv));
+      Xr[q] = wk * jv;
+      Kr[q] = (r == q ? 1.0 : 0.0) - 0.5 * wk * jv;
+    }
 #pragma unroll
-      for (int q = 0; q < NX; ++q) {
-        const double jv = per_node ? (double)base[(r * NX + q) * 64] : Jc[r * NX + q];
-        jmax = fmax(jmax, fabs(jv));
-        K[r][q] = (r == q ? 1.0 : 0.0) - 0.5 * wk * jv;
+    for (int o = 8; o >= 1; o >>= 1) jm = fmax(jm, __shfl_xor(jm, o, 16));
+    const double scale = 1.0 + 0.5 * fabs(wk) * jm;
+#pragma unroll
+    for (int p = 0; p < NX; ++p) {
+      double pk[NX], px[NX];
+#pragma unroll
+      for (int q = p; q < NX; ++q) pk[q] = __shfl(Kr[q], p, 16);
+#pragma unroll
+      for (int q = 0; q < NX; ++q) px[q] = __shfl(Xr[q], p, 16);
+      const double piv = pk[p];
+      if (r == 0 && flag && (!(fabs(piv) > 1e-13 * scale) || !isfinite(piv))) atomicOr(flag, 1);
+      const double rp = 1.0 / piv;
+      if (r == p) {
+#pragma unroll
+        for (int q = p + 1; q < NX; ++q) Kr[q] *= rp;
+#pragma unroll
+        for (int q = 0; q < NX; ++q) Xr[q] *= rp;
+      } else {
+        const double f = Kr[p] * rp;
+#pragma unroll
+        for (int q = p + 1; q < NX; ++q) Kr[q] -= f * pk[q];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) Xr[q] -= f * px[q];
       }
-    lu_kmat<NX>(K, rp, flag, 1.0 + 0.5 * fabs(wk) * jmax);
+    }
+    if (act) {
 #pragma unroll
-    for (int cc = 0; cc < NX; ++cc) {
-      double x[NX];
-#pragma unroll
-      for (int r = 0; r < NX; ++r) x[r] = wk * (per_node ? (double)base[(r * NX + cc) * 64] : Jc[r * NX + cc]);
-      lu_solve<NX>(K, rp, x);
-#pragma unroll
-      for (int r = 0; r < NX; ++r) base[(r * NX + cc) * 64] = (JT)x[r];
+      for (int q = 0; q < NX; ++q) base[(r * NX + q) * 64] = (JT)Xr[q];
     }
   }
 }
@@ -1195,8 +1221,8 @@ static void make_h_class(birk_plan* p, const PinvClass& pc, const double* J, int
     if (pc.n_swz[pn] == 0) return;
     hipLaunchKernelGGL(k_swizzle_nodes<JT>, dim3(pc.n_swz[pn]), dim3(256), 0, s, J, pn, pc.nx, pc.dev, pc.t_swz[pn],
                        (JT*)p->jsw);
-    hipLaunchKernelGGL((k_make_h<NX, JT>), dim3(pc.n_node0), dim3(256), 0, s, (JT*)p->jsw, J, pn, pc.dev, pc.t_node0,
-                       p->flag);
+    hipLaunchKernelGGL((k_make_h_rows<NX, JT>), dim3(pc.n_node0, 16), dim3(256), 0, s, (JT*)p->jsw, J, pn, pc.dev,
+                       pc.t_node0, p->flag);
   }
 }
 
@@ -1219,7 +1245,7 @@ static void make_h_class(birk_plan* p, const PinvClass& pc, const double* J, int
 
 // H_k and w_k in the scan's node slots, once per Jacobian: n_x <= kWaveNx straight from J
 // in the tile layout (k_tmake_h); larger n_x lay J and w out in the level-0 slots and
-// replace the J fields by H_k (k_make_h).  The scans themselves only read H_k and w_k.
+// replace the J fields by H_k (k_make_h_rows).  The scans themselves only read H_k and w_k.
 hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s) {
   const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
   for (const PinvClass& pc : p->pclass) {
