@@ -13,12 +13,14 @@
 //                 S_{k+1} = S_k + w_k J_k xi_k.
 //             As an affine map of the carried sum, S_{k+1} = G_k S_k + h_k with
 //             G_k = I + w_k J_k K_k^{-1} and h_k = w_k J_k K_k^{-1} y_k.  The chain is
-//             evaluated as a hierarchical scan of affine maps: chunks of kChunk nodes
-//             (one thread each) are reduced to (A, b) with S_out = A S_in + b, then
-//             groups of kFan aggregates per level up to a single sequential top, then
-//             start states are pushed back down and each chunk is replayed from its
-//             start state, emitting xi_k and J_k xi_k (the latter feeds FastAX).
-//             All arithmetic in double; y, xi and J xi are stored in the plan type.
+//             evaluated as a scan of affine maps S_out = A S_in + b.  n_x <= 8: each
+//             thread holds whole maps; a DPP scan across waves, tile aggregates and
+//             tile start states (three launches).  Larger n_x: chunks of kChunk nodes
+//             worked by sixteen-lane groups, groups of kFan aggregates per level up to a
+//             sequential top, start states pushed back down.  Either way each chunk is
+//             replayed from its start state, emitting xi_k and J_k xi_k (the latter
+//             feeds FastAX).  All arithmetic in double; y, xi and J xi are stored in the
+//             plan type.
 
 #include <hip/hip_runtime.h>
 
@@ -193,14 +195,15 @@ __device__ __forceinline__ void form_k(const double (&Jk)[NX][NX], double wk, do
     for (int c = 0; c < NX; ++c) K[r][c] = (r == c ? 1.0 : 0.0) - 0.5 * wk * Jk[r][c];
 }
 
-// ---- level-0 layout ----
-// Chunks of kChunk consecutive nodes are reduced by one thread each.  Chunk c is child
-// i = c % kFan of level-1 group g = c / kFan.  Level-0 threads are laid out so that the
-// 64 lanes of a wave hold 64 consecutive groups g and the wave index within a block of
-// kFan waves is the child index i:  thread tau -> block B = tau / (64 kFan),
+// ---- hierarchical path (n_x > kWaveNx): level-0 layout ----
+// Chunks of kChunk consecutive nodes are the level-0 slots (each worked by a group of
+// sixteen lanes).  Chunk c is child i = c % kFan of level-1 group g = c / kFan.  Slot
+// indices tau are laid out so that the
+// 64 slots of a block of 64 hold 64 consecutive groups g and the index of that block
+// within kFan of them is the child index i:  slot tau -> block B = tau / (64 kFan),
 // i = (tau / 64) % kFan, lane l = tau % 64, g = 64 B + l, c = kFan g + i.
 // Every per-chunk array (swizzled Jacobians, aggregates, start states) is stored as
-// [B][i][field][l], so each access of a wave is 64 consecutive doubles.
+// [B][i][field][l]: neighbouring slots hold neighbouring values of a field.
 //
 // Batching: the instances of one n_x form a PinvClass; every phase below is one launch
 // over all of them, each block reading its instance from a (k, block) tile and the
@@ -325,35 +328,38 @@ __global__ __launch_bounds__(256) void k_make_h_rows(JT* __restrict__ jsw, const
   }
 }
 
-// The up-sweeps carry the NX + 1 columns of an aggregate (A, b): a thread holds PER of
-// them, all when NX <= 8 (blockIdx.y = 0), else groups of 4 (blockIdx.y picks the
-// group), and streams the row of the node map or child aggregate it applies, so the
-// map entries are read once per group.
+// The upper up-sweep levels carry the NX + 1 columns of an aggregate (A, b): a thread
+// holds PER of them, all when NX <= 8 (blockIdx.y = 0), else one of four groups
+// (blockIdx.y picks the group), and streams the rows of the child aggregates it applies, so their
+// entries are read once per group.
 template <int NX>
 struct ColGroups {
-  static constexpr int per = (NX <= 8) ? NX + 1 : 4;
+  static constexpr int per = (NX <= 8) ? NX + 1 : (NX + 4) / 4;  // four groups above 8
   static constexpr int count = (NX + 1 + per - 1) / per;
 };
 
 // Level-0 up-sweep: each chunk of kChunk nodes is reduced to (A, b) with
 // S_out = A S_in + b by the node maps S -> (I + H_k) S + H_k y_k: column c < NX of A
 // starts at e_c and takes col <- col + H_k col, b starts at 0 and takes
-// col <- col + H_k (col + y_k).  Thread per chunk in the level-0 layout (as
-// k_pinv_final).  tile = (k, block of 256 level-0 threads).
+// col <- col + H_k (col + y_k).  G = ColGroups<NX>::count neighbouring lanes share a
+// chunk, lane g carrying column group g, so each H_k entry is fetched once for the G
+// lanes.  grid = (tile (k, block of 256 level-0 threads), G): block y of a tile takes
+// slots tau = 256 t + (256 / G) y + threadIdx.x / G.
 template <int NX, typename T>
 __global__ __launch_bounds__(256) void k_pinv_up0(const T* __restrict__ jsw, const T* __restrict__ y,
                                                   const PinvDesc* __restrict__ pd, const int2* __restrict__ tiles,
                                                   double* __restrict__ scan) {
   constexpr int PER = ColGroups<NX>::per;
+  constexpr int G = ColGroups<NX>::count;
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
-  const int64_t tau = (int64_t)t.y * blockDim.x + threadIdx.x;
+  const int64_t tau = (int64_t)t.y * 256 + (int64_t)blockIdx.y * (256 / G) + threadIdx.x / G;
   const int64_t B = tau / (64 * kFan);
   const int i = (int)((tau >> 6) % kFan);
   const int l = (int)(tau & 63);
   const int64_t ch = (B * 64 + l) * kFan + i;
   if (ch >= d.cnt[0]) return;
-  const int c0 = (int)blockIdx.y * PER;
+  const int c0 = (int)(threadIdx.x % G) * PER;
   constexpr int E = NX * NX + 1;
   constexpr int F = NX * NX + NX;
   const int64_t Nn = d.Nn;
@@ -587,55 +593,6 @@ __global__ __launch_bounds__(256) void k_pinv_down(double* __restrict__ scan, co
 #pragma unroll
       for (int r = 0; r < NX; ++r) cstate[c * NX + r] = s[r];
       advance<NX>(child + c * F, 1, s);
-    }
-  }
-}
-
-// Replay each chunk from its start state: u = y_k + S, v = H_k u, xi_k = u + v / 2,
-// (J xi)_k = v / w_k, S <- S + v.  Thread per chunk in the level-0 layout: thread
-// tau -> block B = tau / (64 kFan), i = (tau / 64) % kFan, lane l = tau % 64.
-// tile = (k, block of 256 level-0 threads).
-template <int NX, typename T>
-__global__ __launch_bounds__(256) void k_pinv_final(const T* __restrict__ jsw, const T* __restrict__ y,
-                                                    const PinvDesc* __restrict__ pd, const int2* __restrict__ tiles,
-                                                    const double* __restrict__ scan, T* __restrict__ out,
-                                                    T* __restrict__ jout) {
-  const int2 t = tiles[blockIdx.x];
-  const PinvDesc& d = pd[t.x];
-  const int64_t tau = (int64_t)t.y * blockDim.x + threadIdx.x;
-  const int64_t B = tau / (64 * kFan);
-  const int i = (int)((tau >> 6) % kFan);
-  const int l = (int)(tau & 63);
-  const int64_t g = B * 64 + l;
-  const int64_t c = g * kFan + i;
-  if (c >= d.cnt[0]) return;
-  constexpr int E = NX * NX + 1;
-  const int64_t Nn = d.Nn;
-  const T* js = jsw + d.jsw_off + ((B * kFan + i) * kChunk) * E * 64 + l;
-  const T* yi = y + d.off;
-  T* oi = out + d.off;
-  T* ji = jout ? jout + d.off : nullptr;
-  const double* state = scan + d.st[0];
-  double s[NX];
-#pragma unroll
-  for (int r = 0; r < NX; ++r) s[r] = state[swz(B, i, r, NX, l)];
-  const int64_t k0 = c * kChunk;
-  const int jn = (int)min((int64_t)kChunk, Nn - k0);
-  for (int j = 0; j < jn; ++j) {
-    const int64_t k = k0 + j;
-    const T* base = js + (int64_t)j * E * 64;
-    const double inv_w = 1.0 / (double)base[(E - 1) * 64];
-    double u[NX];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) u[r] = s[r] + (double)yi[(int64_t)r * Nn + k];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      double v = 0.0;
-#pragma unroll
-      for (int q = 0; q < NX; ++q) v += (double)base[(r * NX + q) * 64] * u[q];
-      s[r] += v;
-      oi[(int64_t)r * Nn + k] = (T)(u[r] + 0.5 * v);
-      if (ji) ji[(int64_t)r * Nn + k] = (T)(v * inv_w);
     }
   }
 }
@@ -1020,6 +977,57 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tscan_apply(const T* __rest
   }
 }
 
+// Replay for n_x > 8, sixteen lanes per chunk: lane r < NX carries component r of the
+// state; per node u_r = y_r + S_r, v_r = (H_k u)_r with u gathered across the group,
+// xi_r = u_r + v_r / 2, (J xi)_r = v_r / w_k, S_r <- S_r + v_r, from the chunk's level-0
+// start state.  grid = (tile (k, block of 256 level-0 threads), 16 groups of 16 chunks).
+template <int NX, typename T>
+__global__ __launch_bounds__(256) void k_pinv_final_lanes(const T* __restrict__ jsw, const T* __restrict__ y,
+                                                          const PinvDesc* __restrict__ pd,
+                                                          const int2* __restrict__ tiles,
+                                                          const double* __restrict__ scan, T* __restrict__ out,
+                                                          T* __restrict__ jout) {
+  static_assert(NX <= 16, "one state component per lane of a 16-lane group");
+  const int2 t = tiles[blockIdx.x];
+  const PinvDesc& d = pd[t.x];
+  const int64_t tau = (int64_t)t.y * 256 + blockIdx.y * 16 + (threadIdx.x >> 4);
+  const int r = (int)(threadIdx.x & 15);
+  const int64_t B = tau / (64 * kFan);
+  const int i = (int)((tau >> 6) % kFan);
+  const int l = (int)(tau & 63);
+  const int64_t c = (B * 64 + l) * kFan + i;
+  if (c >= d.cnt[0]) return;  // the whole group leaves together
+  constexpr int E = NX * NX + 1;
+  const int64_t Nn = d.Nn;
+  const bool act = r < NX;
+  const int rr = act ? r : 0;
+  const T* js = jsw + d.jsw_off + ((B * kFan + i) * kChunk) * E * 64 + l;
+  const T* yi = y + d.off;
+  T* oi = out + d.off;
+  T* ji = jout ? jout + d.off : nullptr;
+  double s = act ? scan[d.st[0] + swz(B, i, rr, NX, l)] : 0.0;
+  const int64_t k0 = c * kChunk;
+  const int jn = (int)min((int64_t)kChunk, Nn - k0);
+#pragma unroll 1
+  for (int j = 0; j < jn; ++j) {
+    const int64_t k = k0 + j;
+    const T* base = js + (int64_t)j * E * 64;
+    const double inv_w = 1.0 / (double)base[(E - 1) * 64];
+    const double u = s + (act ? (double)yi[(int64_t)rr * Nn + k] : 0.0);
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      const double uq = __shfl(u, q, 16);
+      v += (act ? (double)base[(rr * NX + q) * 64] : 0.0) * uq;
+    }
+    s += v;
+    if (act) {
+      oi[(int64_t)r * Nn + k] = (T)(u + 0.5 * v);
+      if (ji) ji[(int64_t)r * Nn + k] = (T)(v * inv_w);
+    }
+  }
+}
+
 // y_k = J_k x_k per node for every instance of a class.  tile = (k, block of 256 nodes).
 template <int NX, typename T>
 __global__ __launch_bounds__(256) void k_jac_class(const double* __restrict__ J, int per_node,
@@ -1276,8 +1284,8 @@ static void pinv_class(birk_plan* p, const PinvClass& pc, const T* y, T* out, T*
     hipLaunchKernelGGL((k_pinv_top<NX>), dim3(pc.ninst), dim3(64), 0, s, scan, pc.dev);
     for (int l = pc.Lmax - 1; l >= 0; --l)
       hipLaunchKernelGGL((k_pinv_down<NX>), dim3(pc.n_up[l]), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
-    hipLaunchKernelGGL((k_pinv_final<NX, T>), dim3(pc.n_node0), dim3(256), 0, s, jsw, y, pc.dev, pc.t_node0, scan,
-                       out, jout);
+    hipLaunchKernelGGL((k_pinv_final_lanes<NX, T>), dim3(pc.n_node0, 16), dim3(256), 0, s, jsw, y, pc.dev,
+                       pc.t_node0, scan, out, jout);
   }
 }
 
