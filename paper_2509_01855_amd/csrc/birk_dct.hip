@@ -254,19 +254,17 @@ static hipError_t fft_set(const birk_plan* p, const PairSet& ps, cplx<T>* data, 
 
 // ----------------------------------------------------------------- DCT-I plumbing
 
-// Pack components (2p, 2p+1) into the even extension of length L, optionally scaling
-// the end points by `endscale` (2 for the E^{-1} pre-factor of the transpose) and
-// multiplying by the Bluestein chirp; zero-fill [L, M).  tile = (pair, block over M).
+// Pack components (2p, 2p+1) into the even extension of length L = M, optionally
+// doubling the end points (the E^{-1} pre-factor of the transpose).  tile = (pair, block
+// over M).
 template <typename T>
 __global__ __launch_bounds__(256) void k_pack(const T* __restrict__ x, cplx<T>* __restrict__ z,
                                               const PairDesc* __restrict__ pd, const int2* __restrict__ tiles,
                                               int ends2) {
-  constexpr int pi = prec_index<T>();
   const int2 tile = tiles[blockIdx.x];
   const PairDesc& d = pd[tile.x];
   const int64_t n = (int64_t)tile.y * blockDim.x + threadIdx.x;
   if (n >= d.M) return;
-  const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
   cplx<T> val = mk<T>(T(0), T(0));
   if (n < d.L) {
     const int64_t N = d.N;
@@ -279,23 +277,8 @@ __global__ __launch_bounds__(256) void k_pack(const T* __restrict__ x, cplx<T>* 
       b = b + b;
     }
     val = mk<T>(a, b);
-    if (chirp) val = cmul<T>(val, chirp[n]);
   }
   z[d.work + n] = val;
-}
-
-// Bluestein: multiply by the filter spectrum.  tile = (pair, block over M).
-template <typename T>
-__global__ __launch_bounds__(256) void k_pointwise(cplx<T>* __restrict__ z, const PairDesc* __restrict__ pd,
-                                                   const int2* __restrict__ tiles) {
-  constexpr int pi = prec_index<T>();
-  const int2 tile = tiles[blockIdx.x];
-  const PairDesc& d = pd[tile.x];
-  const int64_t n = (int64_t)tile.y * blockDim.x + threadIdx.x;
-  if (n >= d.M) return;
-  const cplx<T>* f = (const cplx<T>*)d.filt[pi];
-  cplx<T>* zz = z + d.work;
-  zz[n] = cmul<T>(zz[n], f[n]);
 }
 
 // DFT value Y_k (k in [0, N]) of the even extension from the FFT output.
@@ -487,24 +470,16 @@ __global__ __launch_bounds__(256) void k_final(const cplx<T>* __restrict__ z, T*
   if (d.has2) o[d.Nn + j] = Y.y * sc;
 }
 
-// DCT-I (unnormalised, = 2 C) of every pair of the set, in place in z.
+// Product over a set with L = 2N a power of two: pack, FFT (= DCT-I, unnormalised), stencil
+// and c^_0, FFT, unpack.
 template <typename T>
-static hipError_t dct_set(birk_plan* p, const PairSet& ps, int bluestein, cplx<T>* z, cplx<T>* tmp, hipStream_t s) {
-  hipError_t e = fft_set<T>(p, ps, z, tmp, 0, s);
-  if (e != hipSuccess || !bluestein) return e;
-  hipLaunchKernelGGL(k_pointwise<T>, dim3(ps.n_m), dim3(256), 0, s, z, ps.dev, ps.tiles_m);
-  return fft_set<T>(p, ps, z, tmp, 1, s);
-}
-
-template <typename T>
-static hipError_t product_set(birk_plan* p, const PairSet& ps, int bluestein, const T* v, T* out, int transpose,
-                              hipStream_t s) {
+static hipError_t product_set(birk_plan* p, const PairSet& ps, const T* v, T* out, int transpose, hipStream_t s) {
   if (ps.host.empty()) return hipSuccess;
   cplx<T>* z = (cplx<T>*)p->work[0];
   cplx<T>* z2 = (cplx<T>*)p->work[1];
   cplx<T>* tmp = (cplx<T>*)p->work[2];
   hipLaunchKernelGGL(k_pack<T>, dim3(ps.n_m), dim3(256), 0, s, v, z, ps.dev, ps.tiles_m, transpose);
-  hipError_t e = dct_set<T>(p, ps, bluestein, z, tmp, s);
+  hipError_t e = fft_set<T>(p, ps, z, tmp, 0, s);
   if (e != hipSuccess) return e;
   if (!transpose) {
     hipLaunchKernelGGL(k_mid_fwd<T>, dim3(ps.n_n), dim3(256), 0, s, z, z2, ps.dev, ps.tiles_n, p->partials, 0);
@@ -512,7 +487,7 @@ static hipError_t product_set(birk_plan* p, const PairSet& ps, int bluestein, co
   } else {
     hipLaunchKernelGGL(k_mid_tr<T>, dim3(ps.n_n), dim3(256), 0, s, z, z2, ps.dev, ps.tiles_n, 0);
   }
-  e = dct_set<T>(p, ps, bluestein, z2, tmp, s);
+  e = fft_set<T>(p, ps, z2, tmp, 0, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_final<T>, dim3(ps.n_n), dim3(256), 0, s, z2, out, ps.dev, ps.tiles_n, transpose, 0);
   return hipGetLastError();
@@ -643,7 +618,7 @@ __global__ __launch_bounds__(kFftThreads) void k_blu_rows(cplx<T>* __restrict__ 
   const cplx<T>* filt = (const cplx<T>*)d.filt[pi];
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int w = e >> logM2, k2 = e & (M2 - 1);
-    buf[e] = cmul<T>(buf[e], filt[(r0 + w) + ((int64_t)k2 << logM1)]);
+    buf[e] = cmul<T>(buf[e], filt[((int64_t)(r0 + w) << logM2) + k2]);
   }
   __syncthreads();
   lds_fft<T, 4>(buf, logM2, 1 << logW, tw, 1);
@@ -732,7 +707,7 @@ hipError_t apply_product(birk_plan* p, const T* v, T* out, int transpose, hipStr
     hipError_t e = fast_product<T>(p, g, v, out, transpose, s);
     if (e != hipSuccess) return e;
   }
-  hipError_t e = product_set<T>(p, p->gen[0], 0, v, out, transpose, s);
+  hipError_t e = product_set<T>(p, p->gen[0], v, out, transpose, s);
   if (e == hipSuccess) e = product_blu<T>(p, p->gen[1], v, out, transpose, s);
   return e;
 }
@@ -813,12 +788,16 @@ __global__ void k_build_filter(cplx<T>* __restrict__ b, const cplx<T>* __restric
   b[m] = v;
 }
 
+// dst = s src; with logM1 > 0 in the order of the two-step rows pass: dst[k1 M2 + k2] =
+// s src[k1 + M1 k2] (frequency k = k1 + M1 k2), so each row reads its filter contiguously.
 template <typename T>
 __global__ void k_scale_to(const cplx<double>* __restrict__ src, cplx<T>* __restrict__ dst, int64_t M,
-                           double s) {
+                           double s, int logM1, int logM2) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= M) return;
-  dst[m] = mk<T>((T)(src[m].x * s), (T)(src[m].y * s));
+  int64_t from = m;
+  if (logM1 > 0) from = (m >> logM2) + ((m & ((int64_t(1) << logM2) - 1)) << logM1);
+  dst[m] = mk<T>((T)(src[from].x * s), (T)(src[from].y * s));
 }
 
 static int ilog2_ceil(int64_t x) {
@@ -1045,9 +1024,11 @@ hipError_t build_tables(birk_plan* p) {
       p->allocs.push_back(d1);
       if ((e = hipMalloc(&d2, f.M * sizeof(cplx<df32>))) != hipSuccess) return e;
       p->allocs.push_back(d2);
-      hipLaunchKernelGGL(k_scale_to<double>, grid, dim3(256), 0, p->stream, bw, (cplx<double>*)d0, f.M, s);
-      hipLaunchKernelGGL(k_scale_to<float>, grid, dim3(256), 0, p->stream, bw, (cplx<float>*)d1, f.M, s);
-      hipLaunchKernelGGL(k_scale_to<df32>, grid, dim3(256), 0, p->stream, bw, (cplx<df32>*)d2, f.M, s);
+      const int l1 = f.logM > kLdsMaxLog ? f.logM1 : 0;  // two-step rows pass order
+      const int l2 = f.logM2;
+      hipLaunchKernelGGL(k_scale_to<double>, grid, dim3(256), 0, p->stream, bw, (cplx<double>*)d0, f.M, s, l1, l2);
+      hipLaunchKernelGGL(k_scale_to<float>, grid, dim3(256), 0, p->stream, bw, (cplx<float>*)d1, f.M, s, l1, l2);
+      hipLaunchKernelGGL(k_scale_to<df32>, grid, dim3(256), 0, p->stream, bw, (cplx<df32>*)d2, f.M, s, l1, l2);
       b.filt[0] = d0;
       b.filt[1] = d1;
       b.filt[2] = d2;
