@@ -37,6 +37,7 @@
 #include <map>
 #include <vector>
 
+#include "birk_fft.h"
 #include "birk_internal.h"
 
 namespace birk {
@@ -529,138 +530,227 @@ __device__ __forceinline__ cplx<T> blu_in(const PairDesc& d, const T* __restrict
   return cmul<T>(v, chirp[n]);
 }
 
-// Whole Bluestein convolutions of length M <= kLdsMax in LDS.  tile = (first pair,
-// count) of pairs with the same M.
+// ---- fused Bluestein passes on the compile-time FFTs of birk_fft.h ----
+// A block of kBluThreads threads transforms kLdsMax points: kLdsMax / 2^LOGL transforms
+// of length 2^LOGL in the split layout of fast::fft_ct (transform t: real parts in row
+// 2t, imaginary parts in row 2t + 1, rows padded_ld(2^LOGL) reals apart).  A pair's
+// length is known only at run time, so each kernel switches to the body compiled for
+// it.  The inverse transform is conj(FFT(conj(.))), unnormalised (the filter spectrum
+// carries 1/M).
+constexpr int kBluThreads = kLdsMax / fast::kPPT;
+
+__host__ __device__ constexpr int blu_lds_reals(int logL) {
+  return 2 * (kLdsMax >> logL) * fast::padded_ld(1 << logL);
+}
+constexpr int blu_lds_reals_max() {
+  int m = 0;
+  for (int l = 3; l <= kLdsMaxLog; ++l) m = blu_lds_reals(l) > m ? blu_lds_reals(l) : m;
+  return m;
+}
+constexpr int kBluLdsReals = blu_lds_reals_max();
+
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_blu_lds(const T* __restrict__ x, const cplx<T>* __restrict__ dz,
+__device__ __forceinline__ cplx<T> cconj(cplx<T> a) {
+  return mk<T>(a.x, -a.y);
+}
+
+template <typename T, int LOGL>
+__device__ __forceinline__ void sput(T* sm, int t, int n, cplx<T> v) {
+  constexpr int LD = fast::padded_ld(1 << LOGL);
+  sm[2 * t * LD + fast::pad(n)] = v.x;
+  sm[(2 * t + 1) * LD + fast::pad(n)] = v.y;
+}
+
+template <typename T, int LOGL>
+__device__ __forceinline__ cplx<T> sget(const T* sm, int t, int n) {
+  constexpr int LD = fast::padded_ld(1 << LOGL);
+  return mk<T>(sm[2 * t * LD + fast::pad(n)], sm[(2 * t + 1) * LD + fast::pad(n)]);
+}
+
+#define BIRK_LOG_SWITCH(val, LO, CALL)                                         \
+  switch (val) {                                                               \
+    case 3: if constexpr (3 >= LO) { constexpr int LG = 3; CALL; } break;      \
+    case 4: if constexpr (4 >= LO) { constexpr int LG = 4; CALL; } break;      \
+    case 5: if constexpr (5 >= LO) { constexpr int LG = 5; CALL; } break;      \
+    case 6: if constexpr (6 >= LO) { constexpr int LG = 6; CALL; } break;      \
+    case 7: { constexpr int LG = 7; CALL; } break;                             \
+    case 8: { constexpr int LG = 8; CALL; } break;                             \
+    case 9: { constexpr int LG = 9; CALL; } break;                             \
+    case 10: { constexpr int LG = 10; CALL; } break;                           \
+    case 11: { constexpr int LG = 11; CALL; } break;                           \
+    case 12: { constexpr int LG = 12; CALL; } break;                           \
+    default: break;                                                            \
+  }
+
+// Whole convolutions of length M = 2^LOGM <= kLdsMax, kLdsMax / M pairs per block (the
+// tile's pairs share M; the remaining transforms of the block run on zeros).
+template <typename T, int LOGM>
+__device__ __forceinline__ void blu_lds_body(const T* __restrict__ x, const cplx<T>* __restrict__ dz,
+                                             cplx<T>* __restrict__ Y, const PairDesc* __restrict__ pd, int2 tile,
+                                             const cplx<T>* __restrict__ tw, int src_x, int ends2, T* sm) {
+  constexpr int pi = prec_index<T>();
+  constexpr int M = 1 << LOGM;
+  constexpr int COUNT = kLdsMax >> LOGM;
+  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+    const int t = e >> LOGM, n = e & (M - 1);
+    cplx<T> v = mk<T>(T(0), T(0));
+    if (t < tile.y) {
+      const PairDesc& d = pd[tile.x + t];
+      v = blu_in<T>(d, x, dz, src_x, ends2, (const cplx<T>*)d.chirp[pi], n);
+    }
+    sput<T, LOGM>(sm, t, n, v);
+  }
+  __syncthreads();
+  fast::fft_ct<T, LOGM, COUNT>(sm, tw);
+  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+    const int t = e >> LOGM, k = e & (M - 1);
+    if (t < tile.y) {
+      const cplx<T>* filt = (const cplx<T>*)pd[tile.x + t].filt[pi];
+      sput<T, LOGM>(sm, t, k, cconj<T>(cmul<T>(sget<T, LOGM>(sm, t, k), filt[k])));
+    }
+  }
+  __syncthreads();
+  fast::fft_ct<T, LOGM, COUNT>(sm, tw);
+  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+    const int t = e >> LOGM, k = e & (M - 1);
+    if (t < tile.y) {
+      const PairDesc& d = pd[tile.x + t];
+      if (k <= d.N) Y[d.work + k] = cmul<T>(cconj<T>(sget<T, LOGM>(sm, t, k)), ((const cplx<T>*)d.chirp[pi])[k]);
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBluThreads) void k_blu_lds(const T* __restrict__ x, const cplx<T>* __restrict__ dz,
                                                         cplx<T>* __restrict__ Y, const PairDesc* __restrict__ pd,
                                                         const int2* __restrict__ tiles, const cplx<T>* __restrict__ tw,
                                                         int src_x, int ends2) {
-  constexpr int pi = prec_index<T>();
-  __shared__ cplx<T> buf[kLdsMax];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
   const int2 tile = tiles[blockIdx.x];
-  const int logM = pd[tile.x].logM;
-  const int M = 1 << logM;
-  const int n = tile.y << logM;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const PairDesc& d = pd[tile.x + (e >> logM)];
-    buf[e] = blu_in<T>(d, x, dz, src_x, ends2, (const cplx<T>*)d.chirp[pi], e & (M - 1));
+  BIRK_LOG_SWITCH(pd[tile.x].logM, 3, (blu_lds_body<T, LG>(x, dz, Y, pd, tile, tw, src_x, ends2, sm)))
+}
+
+// Columns pass: n = M2 n1 + n2; the W = kLdsMax / M1 columns [c0, c0 + W) of the padded
+// input, FFT over n1, twiddle W_M^(n2 k1), tmp[k1 M2 + n2].  tile = (pair, column block).
+template <typename T, int LOGM1>
+__device__ __forceinline__ void blu_cols_body(const T* __restrict__ x, const cplx<T>* __restrict__ dz,
+                                              cplx<T>* __restrict__ tmp, const PairDesc& d, int ty,
+                                              const cplx<T>* __restrict__ tw, int src_x, int ends2, T* sm) {
+  constexpr int pi = prec_index<T>();
+  constexpr int LOGW = kLdsMaxLog - LOGM1;
+  constexpr int W = 1 << LOGW;
+  const int logM2 = d.logM2;
+  const int c0 = ty << LOGW;
+  const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
+  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+    const int w = e & (W - 1), n1 = e >> LOGW;
+    sput<T, LOGM1>(sm, w, n1, blu_in<T>(d, x, dz, src_x, ends2, chirp, ((int64_t)n1 << logM2) + c0 + w));
   }
   __syncthreads();
-  lds_fft<T, 4>(buf, logM, tile.y, tw, 0);
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const PairDesc& d = pd[tile.x + (e >> logM)];
-    buf[e] = cmul<T>(buf[e], ((const cplx<T>*)d.filt[pi])[e & (M - 1)]);
-  }
-  __syncthreads();
-  lds_fft<T, 4>(buf, logM, tile.y, tw, 1);
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const PairDesc& d = pd[tile.x + (e >> logM)];
-    const int k = e & (M - 1);
-    if (k <= d.N) Y[d.work + k] = cmul<T>(buf[e], ((const cplx<T>*)d.chirp[pi])[k]);
+  fast::fft_ct<T, LOGM1, W>(sm, tw);
+  const cplx<T>* thi = (const cplx<T>*)d.thi[pi];
+  const cplx<T>* tlo = (const cplx<T>*)d.tlo[pi];
+  cplx<T>* ts = tmp + d.work;
+  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+    const int w = e & (W - 1), k1 = e >> LOGW;
+    const int64_t t = (int64_t)(c0 + w) * k1;
+    ts[((int64_t)k1 << logM2) + c0 + w] = cmul<T>(sget<T, LOGM1>(sm, w, k1), tw4<T>(thi, tlo, d.tw_shift, t, 0));
   }
 }
 
-// Columns pass: n = M2 n1 + n2, FFT over n1 of the padded input, twiddle W_M^(n2 k1),
-// tmp[k1 M2 + n2].  tile = (pair, column block of W).
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_blu_cols(const T* __restrict__ x, const cplx<T>* __restrict__ dz,
+__global__ __launch_bounds__(kBluThreads) void k_blu_cols(const T* __restrict__ x, const cplx<T>* __restrict__ dz,
                                                          cplx<T>* __restrict__ tmp, const PairDesc* __restrict__ pd,
                                                          const int2* __restrict__ tiles,
                                                          const cplx<T>* __restrict__ tw, int src_x, int ends2) {
-  constexpr int pi = prec_index<T>();
-  __shared__ cplx<T> buf[kLdsMax];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
   const int2 tile = tiles[blockIdx.x];
   const PairDesc& d = pd[tile.x];
-  const int logM1 = d.logM1, logM2 = d.logM2;
-  const int M1 = 1 << logM1;
-  const int logW = min(kLdsMaxLog - logM1, logM2);
-  const int W = 1 << logW;
-  const int c0 = tile.y << logW;
-  const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
-  cplx<T>* ts = tmp + d.work;
-  const int n = M1 << logW;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int w = e & (W - 1), n1 = e >> logW;
-    buf[(w << logM1) + n1] = blu_in<T>(d, x, dz, src_x, ends2, chirp, ((int64_t)n1 << logM2) + c0 + w);
+  BIRK_LOG_SWITCH(d.logM1, 7, (blu_cols_body<T, LG>(x, dz, tmp, d, tile.y, tw, src_x, ends2, sm)))
+}
+
+// Rows pass: the W = kLdsMax / M2 rows k1 in [r0, r0 + W) of tmp; FFT over n2 (frequency
+// k2 of k = k1 + M1 k2), times the filter spectrum (stored in this order), inverse FFT
+// back to n2, times W_M^(-n2 k1), in place.  tile = (pair, row block).
+template <typename T, int LOGM2>
+__device__ __forceinline__ void blu_rows_body(cplx<T>* __restrict__ tmp, const PairDesc& d, int ty,
+                                              const cplx<T>* __restrict__ tw, T* sm) {
+  constexpr int pi = prec_index<T>();
+  constexpr int M2 = 1 << LOGM2;
+  constexpr int LOGW = kLdsMaxLog - LOGM2;
+  constexpr int W = 1 << LOGW;
+  const int r0 = ty << LOGW;
+  cplx<T>* ts = tmp + d.work + ((int64_t)r0 << LOGM2);
+  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) sput<T, LOGM2>(sm, e >> LOGM2, e & (M2 - 1), ts[e]);
+  __syncthreads();
+  fast::fft_ct<T, LOGM2, W>(sm, tw);
+  const cplx<T>* filt = (const cplx<T>*)d.filt[pi] + ((int64_t)r0 << LOGM2);
+  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+    const int w = e >> LOGM2, k2 = e & (M2 - 1);
+    sput<T, LOGM2>(sm, w, k2, cconj<T>(cmul<T>(sget<T, LOGM2>(sm, w, k2), filt[e])));
   }
   __syncthreads();
-  lds_fft<T, 4>(buf, logM1, W, tw, 0);
+  fast::fft_ct<T, LOGM2, W>(sm, tw);
   const cplx<T>* thi = (const cplx<T>*)d.thi[pi];
   const cplx<T>* tlo = (const cplx<T>*)d.tlo[pi];
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int w = e & (W - 1), k1 = e >> logW;
-    const int64_t t = (int64_t)(c0 + w) * k1;
-    ts[((int64_t)k1 << logM2) + c0 + w] = cmul<T>(buf[(w << logM1) + k1], tw4<T>(thi, tlo, d.tw_shift, t, 0));
+  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+    const int w = e >> LOGM2, n2 = e & (M2 - 1);
+    ts[e] = cmul<T>(cconj<T>(sget<T, LOGM2>(sm, w, n2)), tw4<T>(thi, tlo, d.tw_shift, (int64_t)n2 * (r0 + w), 1));
   }
 }
 
-// Rows pass: for rows k1 of tmp, FFT over n2 (length M2, frequency k2 of k = k1 + M1 k2),
-// multiply by the filter spectrum, inverse FFT back to n2, multiply by W_M^(-n2 k1), in
-// place.  tile = (pair, row block of W).
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_blu_rows(cplx<T>* __restrict__ tmp, const PairDesc* __restrict__ pd,
+__global__ __launch_bounds__(kBluThreads) void k_blu_rows(cplx<T>* __restrict__ tmp, const PairDesc* __restrict__ pd,
                                                          const int2* __restrict__ tiles,
                                                          const cplx<T>* __restrict__ tw) {
-  constexpr int pi = prec_index<T>();
-  __shared__ cplx<T> buf[kLdsMax];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
   const int2 tile = tiles[blockIdx.x];
   const PairDesc& d = pd[tile.x];
-  const int logM1 = d.logM1, logM2 = d.logM2;
-  const int M2 = 1 << logM2;
-  const int logW = min(kLdsMaxLog - logM2, logM1);
-  const int r0 = tile.y << logW;
-  cplx<T>* ts = tmp + d.work + ((int64_t)r0 << logM2);
-  const int n = M2 << logW;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) buf[e] = ts[e];
-  __syncthreads();
-  lds_fft<T, 4>(buf, logM2, 1 << logW, tw, 0);
-  const cplx<T>* filt = (const cplx<T>*)d.filt[pi];
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int w = e >> logM2, k2 = e & (M2 - 1);
-    buf[e] = cmul<T>(buf[e], filt[((int64_t)(r0 + w) << logM2) + k2]);
+  BIRK_LOG_SWITCH(d.logM2, 6, (blu_rows_body<T, LG>(tmp, d, tile.y, tw, sm)))
+}
+
+// Inverse columns pass: columns n2 in [c0, c0 + W) of tmp[k1 M2 + n2], inverse FFT over
+// k1 -> n1, output index n = M2 n1 + n2; Y_n = value x chirp_n for n <= N.
+// tile = (pair, column block).
+template <typename T, int LOGM1>
+__device__ __forceinline__ void blu_icols_body(const cplx<T>* __restrict__ tmp, cplx<T>* __restrict__ Y,
+                                               const PairDesc& d, int ty, const cplx<T>* __restrict__ tw, T* sm) {
+  constexpr int pi = prec_index<T>();
+  constexpr int LOGW = kLdsMaxLog - LOGM1;
+  constexpr int W = 1 << LOGW;
+  const int logM2 = d.logM2;
+  const int c0 = ty << LOGW;
+  const cplx<T>* ts = tmp + d.work;
+  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+    const int w = e & (W - 1), k1 = e >> LOGW;
+    sput<T, LOGM1>(sm, w, k1, cconj<T>(ts[((int64_t)k1 << logM2) + c0 + w]));
   }
   __syncthreads();
-  lds_fft<T, 4>(buf, logM2, 1 << logW, tw, 1);
-  const cplx<T>* thi = (const cplx<T>*)d.thi[pi];
-  const cplx<T>* tlo = (const cplx<T>*)d.tlo[pi];
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int w = e >> logM2, n2 = e & (M2 - 1);
-    ts[e] = cmul<T>(buf[e], tw4<T>(thi, tlo, d.tw_shift, (int64_t)n2 * (r0 + w), 1));
+  fast::fft_ct<T, LOGM1, W>(sm, tw);
+  const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
+  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+    const int w = e & (W - 1), n1 = e >> LOGW;
+    const int64_t idx = ((int64_t)n1 << logM2) + c0 + w;
+    if (idx <= d.N) Y[d.work + idx] = cmul<T>(cconj<T>(sget<T, LOGM1>(sm, w, n1)), chirp[idx]);
   }
 }
 
-// Inverse columns pass: columns n2 of tmp[k1 M2 + n2], inverse FFT over k1 -> n1, output
-// index n = M2 n1 + n2; Y_n = value x chirp_n for n <= N.  tile = (pair, column block).
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_blu_icols(const cplx<T>* __restrict__ tmp, cplx<T>* __restrict__ Y,
+__global__ __launch_bounds__(kBluThreads) void k_blu_icols(const cplx<T>* __restrict__ tmp, cplx<T>* __restrict__ Y,
                                                           const PairDesc* __restrict__ pd,
                                                           const int2* __restrict__ tiles,
                                                           const cplx<T>* __restrict__ tw) {
-  constexpr int pi = prec_index<T>();
-  __shared__ cplx<T> buf[kLdsMax];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
   const int2 tile = tiles[blockIdx.x];
   const PairDesc& d = pd[tile.x];
-  const int logM1 = d.logM1, logM2 = d.logM2;
-  const int M1 = 1 << logM1;
-  const int logW = min(kLdsMaxLog - logM1, logM2);
-  const int W = 1 << logW;
-  const int c0 = tile.y << logW;
-  const cplx<T>* ts = tmp + d.work;
-  const int n = M1 << logW;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int w = e & (W - 1), k1 = e >> logW;
-    buf[(w << logM1) + k1] = ts[((int64_t)k1 << logM2) + c0 + w];
-  }
-  __syncthreads();
-  lds_fft<T, 4>(buf, logM1, W, tw, 1);
-  const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int w = e & (W - 1), n1 = e >> logW;
-    const int64_t idx = ((int64_t)n1 << logM2) + c0 + w;
-    if (idx <= d.N) Y[d.work + idx] = cmul<T>(buf[(w << logM1) + n1], chirp[idx]);
-  }
+  BIRK_LOG_SWITCH(d.logM1, 7, (blu_icols_body<T, LG>(tmp, Y, d, tile.y, tw, sm)))
 }
+
+#undef BIRK_LOG_SWITCH
 
 // One DCT-I (= 2 C) of every pair of a Bluestein set by the fused passes; Y receives
 // Y_k, k <= N, at each pair's work offset.
@@ -669,14 +759,23 @@ static hipError_t dct_blu(birk_plan* p, const PairSet& ps, const T* x, const cpl
                           int ends2, hipStream_t s) {
   const cplx<T>* tw = (const cplx<T>*)p->lds_tw[prec_index<T>()];
   cplx<T>* tmp = (cplx<T>*)p->work[0];
+  const size_t lds = (size_t)kBluLdsReals * sizeof(T);
+  static const bool attr = [lds] {  // above the default dynamic LDS limit in double
+    (void)hipFuncSetAttribute((const void*)k_blu_lds<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_blu_cols<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_blu_rows<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)k_blu_icols<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return true;
+  }();
+  (void)attr;
   if (ps.n_lds > 0)
-    hipLaunchKernelGGL(k_blu_lds<T>, dim3(ps.n_lds), dim3(kFftThreads), 0, s, x, dz, Y, ps.dev, ps.tiles_lds, tw,
+    hipLaunchKernelGGL(k_blu_lds<T>, dim3(ps.n_lds), dim3(kBluThreads), lds, s, x, dz, Y, ps.dev, ps.tiles_lds, tw,
                        src_x, ends2);
   if (ps.n_c4 > 0) {
-    hipLaunchKernelGGL(k_blu_cols<T>, dim3(ps.n_c4), dim3(kFftThreads), 0, s, x, dz, tmp, ps.dev, ps.tiles_c4, tw,
+    hipLaunchKernelGGL(k_blu_cols<T>, dim3(ps.n_c4), dim3(kBluThreads), lds, s, x, dz, tmp, ps.dev, ps.tiles_c4, tw,
                        src_x, ends2);
-    hipLaunchKernelGGL(k_blu_rows<T>, dim3(ps.n_r4), dim3(kFftThreads), 0, s, tmp, ps.dev, ps.tiles_r4, tw);
-    hipLaunchKernelGGL(k_blu_icols<T>, dim3(ps.n_c4), dim3(kFftThreads), 0, s, tmp, Y, ps.dev, ps.tiles_c4, tw);
+    hipLaunchKernelGGL(k_blu_rows<T>, dim3(ps.n_r4), dim3(kBluThreads), lds, s, tmp, ps.dev, ps.tiles_r4, tw);
+    hipLaunchKernelGGL(k_blu_icols<T>, dim3(ps.n_c4), dim3(kBluThreads), lds, s, tmp, Y, ps.dev, ps.tiles_c4, tw);
   }
   return hipGetLastError();
 }
