@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--log2n", type=int, default=20, help="N = 2^log2n (N_n = N + 1)")
     ap.add_argument("--rotation", type=int, default=6, help="input/output buffer pairs per product sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip birk_plan_tune (default tile schedules)")
     ap.add_argument("--products-only", action="store_true", help="skip the solves (for profiling runs)")
     ap.add_argument("--headline-only", action="store_true", help="skip the batched and many-RHS workloads")
     ap.add_argument("--cpu-sample", type=int, default=200, help="rows of B^a the oracle computes")
@@ -206,6 +207,20 @@ def main():
         modf = torch.empty_like(mvdf)
     torch.cuda.synchronize()
 
+    # autotuner of the power-of-two product path (plan setup, outside the timed region)
+    tuned = {}
+    if not a.no_tune:
+        print("[bench] autotuning the power-of-two plans", file=sys.stderr, flush=True)
+        tplans = {"headline_f64": plan64, "headline_f32": planmx}
+        if extra:
+            tplans.update({"many_rhs_f64": mplans[B.BIRK_F64], "many_rhs_f32": mplans[B.BIRK_F32],
+                           "many_rhs_df32": mplans[B.BIRK_DF32]})
+        for name, plan in tplans.items():
+            rep = B.birk_plan_tune(plan)
+            tuned[name] = [ln.split(" chosen ")[0].split(":")[0] + ": " + ln.split(" chosen ")[1]
+                           for ln in rep.splitlines() if " chosen " in ln]
+        torch.cuda.synchronize()
+
     def step(timed: bool):
         for i in range(R):
             tm.region("apply", lambda i=i: B.birk_apply(plan64, vin[i], vout[i]))
@@ -270,6 +285,7 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": bytes_alg, "avg_launch_us": round(t_apply * 1e6, 2)},
+        "autotune": tuned if tuned else None,
         "secondary": {
             "apply_f64_us": us("apply"),
             "apply_T_f64_us": us("apply_T"),

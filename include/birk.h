@@ -102,6 +102,19 @@ birk_status birk_plan_destroy(birk_plan* plan);
 /* Total vector length sum_i n_x[i] * N_n[i] of the plan (elements, not bytes). */
 int64_t birk_plan_length(const birk_plan* plan);
 
+/* Autotuner of the power-of-two product path (N = 2^p >= 512).  For each group of
+ * same-length components it times B^a (FastBV box) in the plan's precision over a
+ * fixed set of tile schedules: both splits 2N = L1 L2 of the two-step DCTs, two or four
+ * rows per middle-pass tile, and the plain or XCD-grouped tile order.  Each candidate
+ * runs once to warm up, then five times between events on the plan's stream; the
+ * fastest stays with the plan for every later product.  The schedule changes only the
+ * order of floating-point operations (results stay within the product tolerance).
+ * Inputs are the plan's own scratch vectors; no allocation.  Blocks until done.
+ * report: optional host buffer (NULL, or report_len > 0) that receives a NUL-terminated
+ * summary of every timing and choice, truncated to report_len - 1 characters.
+ * Errors: BIRK_ERR_ARG (NULL plan), BIRK_ERR_DEVICE. */
+birk_status birk_plan_tune(birk_plan* plan, char* report, int64_t report_len);
+
 /* Copy the Clenshaw-Curtis weights w_B (the last row of B^a, eq:manyDefs and the
  * B~^a section) of instance inst into w_host[0 .. N_n-1] (host memory, double).
  * Synchronises the plan's stream.  Errors: BIRK_ERR_ARG (NULL), BIRK_ERR_SIZE (inst

@@ -22,6 +22,7 @@
 #include <cstring>
 #include <limits>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "birk_internal.h"
@@ -117,6 +118,18 @@ void birk_solve_opts_default(birk_solve_opts* o) {
 
 int64_t birk_plan_length(const birk_plan* p) { return p ? p->total_len : 0; }
 
+birk_status birk_plan_tune(birk_plan* p, char* report, int64_t report_len) {
+  if (!p || (report && report_len <= 0)) return BIRK_ERR_ARG;
+  std::string text;
+  const hipError_t e = tune_fast(p, p->stream, &text);
+  if (report) {
+    const size_t n = std::min<size_t>(text.size(), (size_t)report_len - 1);
+    std::memcpy(report, text.data(), n);
+    report[n] = '\0';
+  }
+  return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+}
+
 birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_nodes_host,
                              const int32_t* n_x_host, birk_precision prec, void* hip_stream) {
   if (!out) return BIRK_ERR_ARG;
@@ -152,17 +165,17 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     const char* l64 = std::getenv("BIRK_FAST_LDS_KB_F64");
     const char* l32 = std::getenv("BIRK_FAST_LDS_KB_F32");
     const char* sp = std::getenv("BIRK_FAST_SPLIT");
-    if (l64) p->fast_lds_kb[0] = std::max(16, std::min(160, std::atoi(l64)));
-    if (l32) p->fast_lds_kb[1] = std::max(16, std::min(160, std::atoi(l32)));
-    if (sp) p->fast_split = std::atoi(sp) ? 1 : 0;
+    if (l64) p->fast_kn.lds_kb[0] = std::max(16, std::min(160, std::atoi(l64)));
+    if (l32) p->fast_kn.lds_kb[1] = std::max(16, std::min(160, std::atoi(l32)));
+    if (sp) p->fast_kn.split = std::atoi(sp) ? 1 : 0;
     const char* tb = std::getenv("BIRK_FAST_TB");
-    if (tb) p->fast_tb = std::max(0, std::min(14, std::atoi(tb))) & ~1;
+    if (tb) p->fast_kn.tb = std::max(0, std::min(14, std::atoi(tb))) & ~1;
     const char* bt = std::getenv("BIRK_FAST_B_THREADS");
-    if (bt) p->fast_b_threads = std::atoi(bt) <= 256 ? 256 : 512;
+    if (bt) p->fast_kn.b_threads = std::atoi(bt) <= 256 ? 256 : 512;
     const char* xc = std::getenv("BIRK_FAST_XCD");
-    if (xc) p->fast_xcd = std::atoi(xc) ? 1 : 0;
+    if (xc) p->fast_kn.xcd = std::atoi(xc) ? 1 : 0;
     const char* b2 = std::getenv("BIRK_FAST_B2");
-    if (b2) p->fast_b2 = std::atoi(b2) ? 1 : 0;
+    if (b2) p->fast_kn.b2 = std::atoi(b2) ? 1 : 0;
   }
   p->inst.resize(batch);
   int64_t off = 0, joff = 0, jcoff = 0, soff = 0, jswoff = 0;

@@ -954,6 +954,7 @@ void plan_products(birk_plan* p) {
       g.Nn = in.Nn;
       g.N = in.N;
       g.off = in.off;
+      g.kn = p->fast_kn;
       int j = i;
       while (j < B && p->inst[j].N == in.N) g.nc += p->inst[j++].nx;
       int64_t fw = 0, fp = 0;

@@ -29,6 +29,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <string>
 #include <vector>
 
 #include "birk_fft.h"
@@ -901,24 +903,24 @@ bool fast_eligible(int64_t N) {
 }
 
 template <typename T>
-static void fast_shape(const birk_plan* p, int64_t N, int& logL1, int& logL2, int& WA, int& TB, int& WC) {
+static void fast_shape(const FastKnobs& kn, int64_t N, int& logL1, int& logL2, int& WA, int& TB, int& WC) {
   int s = 0;
   while ((int64_t(1) << s) < 2 * N) ++s;
-  if (p->fast_split == 0) {
+  if (kn.split == 0) {
     logL2 = (s + 1) / 2;  // rows of the first DCT (pass B) are the longer side
     logL1 = s - logL2;
   } else {
     logL1 = (s + 1) / 2;
     logL2 = s - logL1;
   }
-  const int kb = p->fast_lds_kb[sizeof(T) == 8 ? 0 : 1];
+  const int kb = kn.lds_kb[sizeof(T) == 8 ? 0 : 1];
   const int budget = (int)((int64_t)kb * 1024 / sizeof(T));  // reals of LDS per workgroup
   const int L1 = 1 << logL1, L2 = 1 << logL2;
   WA = std::max(2, std::min(16, budget / fast::padded_ld(L1)));
   while (WA & (WA - 1)) WA &= WA - 1;  // power of two
   WC = WA;
   const int rows = std::max(4, std::min(16, budget / fast::padded_ld(L2)));
-  TB = p->fast_tb > 0 ? p->fast_tb : std::max(2, (rows - 2) & ~1);
+  TB = kn.tb > 0 ? kn.tb : std::max(2, (rows - 2) & ~1);
   // the halo rows of a pass-B tile must stay inside [-1, L1)
   while (TB > 2 && TB > L1 / 2 - 2) TB -= 2;
   while (TB > 2 && (int64_t)(TB + 2) * fast::padded_ld(L2) * (int64_t)sizeof(T) > 160 * 1024) TB -= 2;
@@ -932,23 +934,23 @@ static void fast_shape(const birk_plan* p, int64_t N, int& logL1, int& logL2, in
 
 // Pass B takes the register kernel when its rows are 512..2048 points long, with 2 or 4
 // rows per tile.
-static bool use_b2(const birk_plan* p, int logL2) { return p->fast_b2 && logL2 >= 9 && logL2 <= 11; }
-static int b2_rows(const birk_plan* p) { return p->fast_tb == 4 ? 4 : 2; }
+static bool use_b2(const FastKnobs& kn, int logL2) { return kn.b2 && logL2 >= 9 && logL2 <= 11; }
+static int b2_rows(const FastKnobs& kn) { return kn.tb == 4 ? 4 : 2; }
 
 // Pass-B tiles per component (rows 0..L1/2 in tiles of TB, or of 2 for the register kernel).
 template <typename T>
-static int fast_tiles_b(const birk_plan* p, int64_t N) {
+static int fast_tiles_b(const FastKnobs& kn, int64_t N) {
   int logL1, logL2, WA, TB, WC;
-  fast_shape<T>(p, N, logL1, logL2, WA, TB, WC);
+  fast_shape<T>(kn, N, logL1, logL2, WA, TB, WC);
   const int rows = (1 << logL1) / 2 + 1;
-  const int tb = use_b2(p, logL2) ? b2_rows(p) : TB;
+  const int tb = use_b2(kn, logL2) ? b2_rows(kn) : TB;
   return (rows + tb - 1) / tb;
 }
 
 // Passes A and C take the compile-time-length kernels for L1 = 2^8..2^11 (tiles of 8
 // columns, 4 at 2^11); returns log2 of the tile width, or 0 for the general kernels.
-static int fixed_logw(const birk_plan* p, int logL1) {
-  if (!p->fast_b2 || logL1 < 8 || logL1 > 11) return 0;
+static int fixed_logw(const FastKnobs& kn, int logL1) {
+  if (!kn.b2 || logL1 < 8 || logL1 > 11) return 0;
   return logL1 == 11 ? 2 : 3;
 }
 
@@ -971,20 +973,21 @@ static void lds_attr(F f, int bytes) {
 }
 
 template <typename T, int TB, int TRANS>
-static void launch_B(const birk_plan* p, int nt, int nc, int thr, int lds, hipStream_t s, const cplx<T>* G, int64_t gcomp, int64_t sg,
+static void launch_B(int xcd, int nt, int nc, int thr, int lds, hipStream_t s, const cplx<T>* G, int64_t gcomp, int64_t sg,
                      cplx<T>* G2, int64_t g2comp, int64_t sg2, int64_t N, int logL1, int logL2, const cplx<T>* tw,
                      const cplx<T>* thi, const cplx<T>* tlo, int tsh, double* part) {
   auto f = fast::k_fastB<T, TB, TRANS>;
   lds_attr(f, lds);
   hipLaunchKernelGGL(f, dim3(nt * nc), dim3(thr), lds, s, G, gcomp, sg, G2, g2comp, sg2, N, logL1, logL2, tw, thi,
-                     tlo, tsh, part, nt, nc, p->fast_xcd);
+                     tlo, tsh, part, nt, nc, xcd);
 }
 
 template <typename T>
 hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, int transpose, hipStream_t s) {
   constexpr int pi = prec_index<T>();
   int logL1, logL2, WA, TB, WC;
-  fast_shape<T>(p, g.N, logL1, logL2, WA, TB, WC);
+  const FastKnobs& kn = g.kn;
+  fast_shape<T>(kn, g.N, logL1, logL2, WA, TB, WC);
   const int L1 = 1 << logL1, L2 = 1 << logL2;
   const int ld1 = fast::padded_ld(L1), ld2 = fast::padded_ld(L2);
   const int64_t sg = L2 / 2 + 1, sg2 = L2 / 2 + 1;  // G [k1][n2] and G2 [r][q]: rows of L2/2 + 1
@@ -997,7 +1000,7 @@ hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, in
   const cplx<T>* tlo = (const cplx<T>*)g.tw.lo[pi];
   const int tsh = g.tw.shift;
   const int nc = g.nc;
-  const int lw = fixed_logw(p, logL1);
+  const int lw = fixed_logw(kn, logL1);
   if (lw > 0) {
     // compile-time lengths: one tile of W = 2^lw columns per workgroup
     const int W = 1 << lw;
@@ -1012,21 +1015,21 @@ hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, in
     }
     lds_attr(f, lds);
     hipLaunchKernelGGL(f, dim3(ntA * nc), dim3(W * L1 / 16), lds, s, v + g.off, g.Nn, logL2, G, gcomp, sg, tw, thi,
-                       tlo, tsh, transpose ? 1 : 0, ntA, nc, p->fast_xcd);
+                       tlo, tsh, transpose ? 1 : 0, ntA, nc, kn.xcd);
   } else {
     const int ntA = (L2 / 2 + 1 + WA - 1) / WA;
     const int lds = WA * ld1 * (int)sizeof(T);
     auto f = fast::k_fastA<T>;
     lds_attr(f, lds);
     hipLaunchKernelGGL(f, dim3(ntA * nc), dim3(threads_for(WA * L1 / 2)), lds, s, v + g.off, g.Nn, logL1, logL2,
-                       ilog2i(WA), G, gcomp, sg, tw, thi, tlo, tsh, transpose ? 1 : 0, ntA, nc, p->fast_xcd);
+                       ilog2i(WA), G, gcomp, sg, tw, thi, tlo, tsh, transpose ? 1 : 0, ntA, nc, kn.xcd);
   }
-  const int ntB = fast_tiles_b<T>(p, g.N);
-  if (use_b2(p, logL2)) {
+  const int ntB = fast_tiles_b<T>(kn, g.N);
+  if (use_b2(kn, logL2)) {
     const int lds = 2 * ld2 * (int)sizeof(T);
     const int thr = L2 / fast::kPPT;
     auto f = fast::k_fastB2<T, 0, 11, 2>;
-    const int tb4 = b2_rows(p) == 4;
+    const int tb4 = b2_rows(kn) == 4;
     switch ((logL2 * 2 + (transpose ? 1 : 0)) * 2 + tb4) {
       case 36: f = fast::k_fastB2<T, 0, 9, 2>; break;
       case 37: f = fast::k_fastB2<T, 0, 9, 4>; break;
@@ -1043,17 +1046,17 @@ hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, in
     }
     lds_attr(f, lds);
     hipLaunchKernelGGL(f, dim3(ntB * nc), dim3(thr), lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, tw, thi, tlo,
-                       tsh, part, ntB, nc, p->fast_xcd);
+                       tsh, part, ntB, nc, kn.xcd);
   } else {
     const int lds = (TB + 2) * ld2 * (int)sizeof(T);
-    const int thr = std::min(threads_for((TB + 2) * L2 / 2), p->fast_b_threads);
+    const int thr = std::min(threads_for((TB + 2) * L2 / 2), kn.b_threads);
 #define BIRK_LB(tb)                                                                                                \
   case tb:                                                                                                         \
     if (transpose)                                                                                                 \
-      launch_B<T, tb, 1>(p, ntB, nc, thr, lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, logL2, tw, thi, tlo, tsh, \
+      launch_B<T, tb, 1>(kn.xcd, ntB, nc, thr, lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, logL2, tw, thi, tlo, tsh, \
                          part);                                                                                    \
     else                                                                                                           \
-      launch_B<T, tb, 0>(p, ntB, nc, thr, lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, logL2, tw, thi, tlo, tsh, \
+      launch_B<T, tb, 0>(kn.xcd, ntB, nc, thr, lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, logL2, tw, thi, tlo, tsh, \
                          part);                                                                                    \
     break;
     switch (TB) {
@@ -1087,7 +1090,7 @@ hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, in
     }
     lds_attr(f, lds);
     hipLaunchKernelGGL(f, dim3(ntC * nc), dim3(W * L1 / 16), lds, s, G2, g2comp, sg2, o, g.Nn, logL2, tw, part, ntB,
-                       ntC, nc, p->fast_xcd);
+                       ntC, nc, kn.xcd);
   } else {
     const int ntC = (L2 / 2 + 1 + WC - 1) / WC;
     const int lds = WC * ld1 * (int)sizeof(T);
@@ -1096,23 +1099,99 @@ hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, in
     auto f = transpose ? fast::k_fastC<T, 1> : fast::k_fastC<T, 0>;
     lds_attr(f, lds);
     hipLaunchKernelGGL(f, dim3(ntC * nc), dim3(thr), lds, s, G2, g2comp, sg2, o, g.Nn, logL1, logL2, ilog2i(WC), tw,
-                       part, ntB, ntC, nc, p->fast_xcd);
+                       part, ntB, ntC, nc, kn.xcd);
   }
   return hipGetLastError();
 }
 
+// Tile schedules the autotuner tries for a group: the defaults first, then both splits of
+// 2N = L1 L2, two or four rows per pass-B tile and both tile orders.
+static std::vector<FastKnobs> tune_candidates(const FastKnobs& base) {
+  std::vector<FastKnobs> c{base};
+  for (int split = 0; split < 2; ++split)
+    for (int tb = 2; tb <= 4; tb += 2)
+      for (int xcd = 0; xcd < 2; ++xcd) {
+        FastKnobs k = base;
+        k.split = split;
+        k.tb = tb;
+        k.xcd = xcd;
+        if (k.split != base.split || k.tb != base.tb || k.xcd != base.xcd) c.push_back(k);
+      }
+  return c;
+}
+
 // Work (complex elements per buffer) and partials (doubles) of the fast path for nc
-// components of length N + 1, for any of the storage types.
+// components of length N + 1, for any of the storage types and any schedule the
+// autotuner may choose.
 void fast_sizes(const birk_plan* p, int64_t N, int nc, int64_t* work, int64_t* part) {
-  int l1f, l2f, waf, tbf, wcf, l1d, l2d, wad, tbd, wcd;
-  fast_shape<float>(p, N, l1f, l2f, waf, tbf, wcf);
-  fast_shape<double>(p, N, l1d, l2d, wad, tbd, wcd);
-  const int64_t L1 = int64_t(1) << l1f, L2 = int64_t(1) << l2f;
-  *work = (int64_t)nc * (L1 / 2 + 1) * (L2 / 2 + 1);
-  (void)tbf;
-  (void)tbd;
-  const int64_t ntB = std::max(fast_tiles_b<float>(p, N), std::max(fast_tiles_b<double>(p, N), fast_tiles_b<df32>(p, N)));
+  int64_t w = 0, ntB = 0;
+  for (const FastKnobs& kn : tune_candidates(p->fast_kn)) {
+    int l1, l2, wa, tb, wc;
+    fast_shape<double>(kn, N, l1, l2, wa, tb, wc);
+    w = std::max(w, (int64_t)nc * ((int64_t(1) << l1) / 2 + 1) * ((int64_t(1) << l2) / 2 + 1));
+    ntB = std::max(ntB, (int64_t)std::max(fast_tiles_b<float>(kn, N),
+                                          std::max(fast_tiles_b<double>(kn, N), fast_tiles_b<df32>(kn, N))));
+  }
+  *work = w;
   *part = (int64_t)nc * ntB;
+}
+
+// Autotuner: per group, B^a over every candidate schedule on the plan's scratch vectors
+// (one warm-up call, then kTuneReps timed calls between HIP events); the fastest stays.
+constexpr int kTuneReps = 5;
+
+template <typename T>
+static hipError_t tune_groups(birk_plan* p, hipStream_t s, std::string* report) {
+  T* in = (T*)p->tmp_vec[0];
+  T* out = (T*)p->tmp_vec[1];
+  hipError_t e = hipMemsetAsync(in, 0, (size_t)p->total_len * sizeof(T), s);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  char line[160];
+  for (FastGroup& g : p->fgroups) {
+    if (e != hipSuccess) break;
+    FastKnobs best = g.kn;
+    float best_ms = 0.0f;
+    bool first = true;
+    snprintf(line, sizeof line, "N=%lld x %d:", (long long)g.N, g.nc);
+    *report += line;
+    for (const FastKnobs& c : tune_candidates(p->fast_kn)) {
+      g.kn = c;
+      if ((e = fast_product<T>(p, g, in, out, 0, s)) != hipSuccess) break;
+      if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+      for (int r = 0; r < kTuneReps && e == hipSuccess; ++r) e = fast_product<T>(p, g, in, out, 0, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) break;
+      ms /= kTuneReps;
+      snprintf(line, sizeof line, " [split %d, tb %d, xcd %d] %.1f us;", c.split, c.tb, c.xcd, 1000.0 * ms);
+      *report += line;
+      if (first || ms < best_ms) {
+        best = c;
+        best_ms = ms;
+        first = false;
+      }
+    }
+    g.kn = best;
+    snprintf(line, sizeof line, " chosen [split %d, tb %d, xcd %d]\n", best.split, best.tb, best.xcd);
+    *report += line;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return e;
+}
+
+hipError_t tune_fast(birk_plan* p, hipStream_t s, std::string* report) {
+  if (p->fgroups.empty()) {
+    *report += "no power-of-two groups to tune\n";
+    return hipSuccess;
+  }
+  if (p->prec == BIRK_F64) return tune_groups<double>(p, s, report);
+  if (p->prec == BIRK_DF32) return tune_groups<df32>(p, s, report);
+  return tune_groups<float>(p, s, report);  // float storage, with or without refinement
 }
 
 template hipError_t fast_product<double>(birk_plan*, const FastGroup&, const double*, double*, int, hipStream_t);

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <type_traits>
+#include <string>
 #include <vector>
 
 #include "birk.h"
@@ -53,6 +54,17 @@ struct TwiddleSet {
 
 // Three-pass power-of-two product (birk_fast.hip): a run of consecutive instances with
 // the same N, whose nc components are then contiguous with stride N_n.
+// Tile schedule of the three-pass kernels (environment defaults, or the autotuner's
+// choice per group of same-length components).
+struct FastKnobs {
+  int lds_kb[2] = {128, 64};  // LDS budget per workgroup of the runtime-length kernels [8-byte, 4-byte reals]
+  int split = 0;              // 0: rows of the first DCT are the longer side (L2 >= L1); 1: L1 >= L2
+  int tb = 0;                 // rows per pass-B tile (0: from the LDS budget; 2 or 4 in the register kernel)
+  int b_threads = 512;        // workgroup size cap of the runtime-length pass B
+  int xcd = 1;                // XCD-aware tile order
+  int b2 = 1;                 // compile-time-length kernels where they apply
+};
+
 struct FastGroup {
   int64_t Nn = 0, N = 0;
   int nc = 0;
@@ -60,6 +72,7 @@ struct FastGroup {
   int64_t work_off = 0;  // complex elements into work[0], work[1]
   int64_t part_off = 0;  // doubles into partials
   TwiddleSet tw;         // M = 2N
+  FastKnobs kn;          // tile schedule of this group
 };
 
 // General product path (birk_dct.hip): one pair of components (2p, 2p + 1) of one
@@ -176,12 +189,7 @@ struct birk_plan {
   int* krylov_cnt = nullptr;      // per instance: number of combined basis vectors
   int* flag = nullptr;            // device flag: singular pivot seen
   int use_fast = 1;               // power-of-two N takes the three-pass path
-  int fast_lds_kb[2] = {128, 64};  // LDS budget per workgroup of the three-pass kernels [8-byte, 4-byte reals]
-  int fast_split = 0;             // 0: rows of the first DCT are the longer side (L2 >= L1); 1: L1 >= L2
-  int fast_tb = 0;                // rows per pass-B tile (0: from the LDS budget)
-  int fast_b_threads = 512;       // workgroup size cap of pass B
-  int fast_xcd = 1;               // XCD-aware tile order
-  int fast_b2 = 1;                // pass B by the two-row register kernel where it applies
+  birk::FastKnobs fast_kn;        // default tile schedule of the three-pass groups
 };
 
 namespace birk {
@@ -201,6 +209,8 @@ bool fast_eligible(int64_t N);
 template <typename T>
 hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, int transpose, hipStream_t s);
 void fast_sizes(const birk_plan* p, int64_t N, int nc, int64_t* work, int64_t* part);
+// Autotuner of the three-pass groups (birk_plan_tune); appends a summary to *report.
+hipError_t tune_fast(birk_plan* p, hipStream_t s, std::string* report);
 
 // ---- preconditioner, Jacobian products and Krylov kernels (birk_solve.hip) ----
 template <typename T>

@@ -159,3 +159,49 @@ def test_general_path_matches_fast_path(B, Nn, monkeypatch):
         ref = bk.apply_Ba_extended(Nn - 1, X)
         assert rel_err(outs[1][0].reshape(nx, Nn), ref) <= TOL["f64"]
         assert rel_err(outs[0][0].reshape(nx, Nn), ref) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("Nn,prec", [((1 << 16) + 1, "f64"), ((1 << 20) + 1, "f64"), ((1 << 18) + 1, "f32")])
+def test_autotuned_schedule_keeps_results(B, Nn, prec):
+    """birk_plan_tune times every candidate tile schedule of the power-of-two path and
+    keeps the fastest; products and transposes afterwards still match the exact
+    sparse-mode series (B^a) and the untuned plan."""
+    import torch
+    N = Nn - 1
+    nx = 2
+    announce(f"autotune Nn={Nn} prec={prec}")
+    rows, refs = [], []
+    for c in range(nx):
+        modes, alphas = wl.sparse_modes([11, c, Nn], N, count=64)
+        rows.append(bk.sparse_mode_values(N, modes, alphas))
+        refs.append(bk.sparse_mode_exact(N, modes, alphas))
+    X = np.stack(rows).ravel()
+    p = B.BIRK_F64 if prec == "f64" else B.BIRK_F32
+    dt = torch.float64 if prec == "f64" else torch.float32
+    plan = B.birk_plan_create([Nn], [nx], p)
+    v = dev(X, dt)
+    before = []
+    for t in (0, 1):
+        out = torch.empty_like(v)
+        (B.birk_apply_T if t else B.birk_apply)(plan, v, out)
+        torch.cuda.synchronize()
+        before.append(host(out).astype(np.float64))
+    report = B.birk_plan_tune(plan)
+    print(report, flush=True)
+    assert "chosen" in report and report.count("us;") == 9
+    after = []
+    for t in (0, 1):
+        out = torch.empty_like(v)
+        (B.birk_apply_T if t else B.birk_apply)(plan, v, out)
+        torch.cuda.synchronize()
+        after.append(host(out).astype(np.float64))
+    plan.destroy()
+    assert rel_err(after[0].reshape(nx, Nn), np.stack(refs)) <= TOL[prec]
+    for t in (0, 1):
+        assert rel_err(after[t], before[t]) <= (1e-13 if prec == "f64" else 1e-5)
+
+
+def test_autotune_without_power_of_two_groups(B):
+    plan = B.birk_plan_create([1000], [3], B.BIRK_F64)
+    assert "no power-of-two groups" in B.birk_plan_tune(plan)
+    plan.destroy()
