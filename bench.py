@@ -135,6 +135,33 @@ class Timer:
         return float(sum(xs) / len(xs)) if xs else float("nan")
 
 
+def graph_replay_timing(B, torch, reps=200):
+    """B^a at N_n = 256, n_x = 6 (the small workload) on a side stream: eager launches vs
+    replays of the recorded graph (birk_plan_set_graphs), mean per product."""
+    side = torch.cuda.Stream()
+    Nn, nx = 256, 6
+    res = {"workload": "B^a, N_n = 256, n_x = 6 (Bluestein path), back-to-back products"}
+    with torch.cuda.stream(side):
+        v = torch.randn(Nn * nx, dtype=torch.float64, device="cuda")
+        o = torch.empty_like(v)
+        for mode in ("eager", "graph"):
+            plan = B.birk_plan_create([Nn], [nx], B.BIRK_F64, side)
+            if mode == "graph":
+                B.birk_plan_set_graphs(plan)
+            for _ in range(3):
+                B.birk_apply(plan, v, o)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(side)
+            for _ in range(reps):
+                B.birk_apply(plan, v, o)
+            e1.record(side)
+            e1.synchronize()
+            res[f"{mode}_us"] = round(e0.elapsed_time(e1) * 1e3 / reps, 2)
+            plan.destroy()
+    side.synchronize()
+    return res
+
+
 def main():
     a = parse()
     if a.calibrate_copy:
@@ -332,6 +359,8 @@ def main():
             "apply_f32_gpts": round(mn / (tm.mean_ms("m_apply_f32") * 1e-3) / 1e9, 3),
             "max_dev_vs_f64": {"df32": dev_df, "f32": dev_32},
         }
+    if extra:
+        out["graphs"] = graph_replay_timing(B, torch)
     if not a.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(N, a.cpu_sample, vin[0][:Nn].cpu().numpy())

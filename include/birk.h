@@ -115,6 +115,18 @@ int64_t birk_plan_length(const birk_plan* plan);
  * Errors: BIRK_ERR_ARG (NULL plan), BIRK_ERR_DEVICE. */
 birk_status birk_plan_tune(birk_plan* plan, char* report, int64_t report_len);
 
+/* Graph mode of birk_apply / birk_apply_T (enable = 1): the launches of one product are
+ * recorded once into a HIP graph per (direction, input pointer, output pointer) and
+ * replayed with a single graph launch.  The first call with a given triple runs as usual,
+ * the second records and replays, later calls replay; at most eight triples are kept
+ * (least recently used dropped).  A replay reads the buffers' current contents, so the
+ * same pointers may carry new data; buffers must stay allocated while their triple is in
+ * use.  enable = 0 (the default) drops every recorded graph.  birk_plan_tune drops them
+ * too (they hold the old schedule).  Requires a plan created on a non-null stream.
+ * Other entry points are unaffected.  Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED (plan
+ * on the legacy null stream). */
+birk_status birk_plan_set_graphs(birk_plan* plan, int32_t enable);
+
 /* Copy the Clenshaw-Curtis weights w_B (the last row of B^a, eq:manyDefs and the
  * B~^a section) of instance inst into w_host[0 .. N_n-1] (host memory, double).
  * Synchronises the plan's stream.  Errors: BIRK_ERR_ARG (NULL), BIRK_ERR_SIZE (inst

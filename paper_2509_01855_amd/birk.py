@@ -36,7 +36,8 @@ BIRK_J_CONSTANT = 0
 BIRK_J_PER_NODE = 1
 
 EXPORTED = [
-    "birk_plan_create", "birk_plan_destroy", "birk_plan_length", "birk_plan_tune", "birk_weights",
+    "birk_plan_create", "birk_plan_destroy", "birk_plan_length", "birk_plan_tune", "birk_plan_set_graphs",
+    "birk_weights",
     "birk_apply", "birk_apply_T", "birk_precond", "birk_fast_ax",
     "birk_solve_opts_default", "birk_krylov_solve", "birk_status_string",
 ]
@@ -66,6 +67,7 @@ def _load():
     lib.birk_plan_length.argtypes = [vp]
     lib.birk_plan_length.restype = i64
     lib.birk_plan_tune.argtypes = [vp, ctypes.c_char_p, i64]
+    lib.birk_plan_set_graphs.argtypes = [vp, i32]
     lib.birk_weights.argtypes = [vp, i32, ctypes.POINTER(dbl)]
     lib.birk_apply.argtypes = [vp, vp, vp]
     lib.birk_apply_T.argtypes = [vp, vp, vp]
@@ -163,6 +165,11 @@ def birk_plan_tune(plan: Plan) -> str:
     buf = ctypes.create_string_buffer(16384)
     _check(_lib.birk_plan_tune(plan.handle, buf, len(buf)), "birk_plan_tune")
     return buf.value.decode()
+
+
+def birk_plan_set_graphs(plan: Plan, enable: bool = True) -> None:
+    """Replay birk_apply / birk_apply_T from recorded HIP graphs (see include/birk.h)."""
+    _check(_lib.birk_plan_set_graphs(plan.handle, 1 if enable else 0), "birk_plan_set_graphs")
 
 
 def birk_weights(plan: Plan, inst: int = 0):

@@ -55,8 +55,15 @@ constexpr int64_t kMaxNPow2 = int64_t(1) << 23;   // N a power of two
 constexpr int64_t kMaxTotal = int64_t(1) << 31;
 constexpr int kMaxPrecondNx = 12;
 
+static void drop_graphs(birk_plan* p) {
+  for (auto& g : p->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  p->graphs.clear();
+}
+
 void free_plan(birk_plan* p) {
   if (!p) return;
+  drop_graphs(p);
   for (auto& in : p->inst)
     if (in.w) (void)hipFree(in.w);
   for (void* q : p->allocs) if (q) (void)hipFree(q);
@@ -121,6 +128,8 @@ int64_t birk_plan_length(const birk_plan* p) { return p ? p->total_len : 0; }
 birk_status birk_plan_tune(birk_plan* p, char* report, int64_t report_len) {
   if (!p || (report && report_len <= 0)) return BIRK_ERR_ARG;
   std::string text;
+  DeviceGuard g(p->device);
+  drop_graphs(p);  // recorded with the previous schedule
   const hipError_t e = tune_fast(p, p->stream, &text);
   if (report) {
     const size_t n = std::min<size_t>(text.size(), (size_t)report_len - 1);
@@ -258,25 +267,70 @@ birk_status birk_weights(birk_plan* p, int32_t inst, double* w_host) {
   return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
 }
 
+static hipError_t launch_product(birk_plan* p, const void* v, void* out, int transpose) {
+  switch (p->prec) {
+    case BIRK_F64:
+      return apply_product<double>(p, (const double*)v, (double*)out, transpose, p->stream);
+    case BIRK_DF32:
+      return apply_product<df32>(p, (const df32*)v, (df32*)out, transpose, p->stream);
+    default:
+      return apply_product<float>(p, (const float*)v, (float*)out, transpose, p->stream);
+  }
+}
+
+constexpr size_t kMaxGraphs = 8;
+
+// Graph mode: the first use of a (direction, v, out) triple runs eagerly (and sets any
+// kernel attributes), the second records the launches into a graph and replays it,
+// later uses replay it.  At most kMaxGraphs triples; the least recently used goes.
+static hipError_t graph_product(birk_plan* p, const void* v, void* out, int transpose) {
+  const uint64_t now = ++p->graph_clock;
+  for (auto& g : p->graphs) {
+    if (g.transpose != transpose || g.v != v || g.out != out) continue;
+    g.used = now;
+    if (!g.exec) {
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return e;
+      e = launch_product(p, v, out, transpose);
+      const hipError_t e2 = hipStreamEndCapture(p->stream, &graph);
+      if (e == hipSuccess) e = e2;
+      if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        g.exec = nullptr;
+        return e;
+      }
+    }
+    return hipGraphLaunch(g.exec, p->stream);
+  }
+  if (p->graphs.size() >= kMaxGraphs) {
+    auto lru = std::min_element(p->graphs.begin(), p->graphs.end(),
+                                [](const birk_plan::GraphSlot& a, const birk_plan::GraphSlot& b) {
+                                  return a.used < b.used;
+                                });
+    if (lru->exec) (void)hipGraphExecDestroy(lru->exec);
+    p->graphs.erase(lru);
+  }
+  p->graphs.push_back({transpose, v, out, nullptr, now});
+  return launch_product(p, v, out, transpose);
+}
+
 static birk_status product(birk_plan* p, const void* v, void* out, int transpose) {
   if (!p || !v || !out || v == out) return BIRK_ERR_ARG;
   DeviceGuard g(p->device);
-  hipError_t e;
-  switch (p->prec) {
-    case BIRK_F64:
-      e = apply_product<double>(p, (const double*)v, (double*)out, transpose, p->stream);
-      break;
-    case BIRK_F32:
-    case BIRK_F32_REFINE_F64:
-      e = apply_product<float>(p, (const float*)v, (float*)out, transpose, p->stream);
-      break;
-    case BIRK_DF32:
-      e = apply_product<df32>(p, (const df32*)v, (df32*)out, transpose, p->stream);
-      break;
-    default:
-      return BIRK_ERR_ARG;
-  }
+  const hipError_t e = p->use_graphs ? graph_product(p, v, out, transpose) : launch_product(p, v, out, transpose);
   return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+}
+
+birk_status birk_plan_set_graphs(birk_plan* p, int32_t enable) {
+  if (!p || (enable != 0 && enable != 1)) return BIRK_ERR_ARG;
+  if (enable && !p->stream) return BIRK_ERR_UNSUPPORTED;  // the legacy null stream cannot be captured
+  DeviceGuard g(p->device);
+  (void)hipStreamSynchronize(p->stream);
+  drop_graphs(p);
+  p->use_graphs = enable;
+  return BIRK_OK;
 }
 
 birk_status birk_apply(birk_plan* p, const void* v, void* out) { return product(p, v, out, 0); }

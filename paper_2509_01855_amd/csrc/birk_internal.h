@@ -190,6 +190,17 @@ struct birk_plan {
   int* flag = nullptr;            // device flag: singular pivot seen
   int use_fast = 1;               // power-of-two N takes the three-pass path
   birk::FastKnobs fast_kn;        // default tile schedule of the three-pass groups
+  // HIP graphs of the products (birk_plan_set_graphs), per (direction, input, output)
+  struct GraphSlot {
+    int transpose;
+    const void* v;
+    void* out;
+    hipGraphExec_t exec;  // null until the second use of the triple
+    uint64_t used;
+  };
+  int use_graphs = 0;
+  std::vector<GraphSlot> graphs;
+  uint64_t graph_clock = 0;
 };
 
 namespace birk {

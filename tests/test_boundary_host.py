@@ -88,5 +88,6 @@ def test_null_arguments_are_rejected(birk):
     assert lib.birk_krylov_solve(None, 0, None, None, None, None, None) == birk.BIRK_ERR_ARG
     assert lib.birk_weights(None, 0, None) == birk.BIRK_ERR_ARG
     assert lib.birk_plan_tune(None, None, 0) == birk.BIRK_ERR_ARG
+    assert lib.birk_plan_set_graphs(None, 1) == birk.BIRK_ERR_ARG
     assert lib.birk_plan_destroy(None) == birk.BIRK_OK
     assert lib.birk_plan_length(None) == 0

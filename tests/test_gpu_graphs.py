@@ -1,0 +1,67 @@
+"""Graph mode of birk_apply / birk_apply_T (birk_plan_set_graphs): every replay of a
+recorded product equals the eager product bit for bit, with the plan's own eager work,
+other products and new input data between replays."""
+
+import numpy as np
+import pytest
+
+from paper_2509_01855_amd import workloads as wl
+from tests.gpu_util import announce, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2509_01855_amd import birk
+    return birk
+
+
+# a three-pass group, a Bluestein batch of uneven instances, and both in one plan
+PLANS = [([(1 << 16) + 1], [4]), ([257, 1000, 3000, 4097, 70001], [6, 4, 12, 6, 2]),
+         ([(1 << 12) + 1, 1500, 20000], [6, 6, 4])]
+
+
+@pytest.mark.parametrize("case", range(len(PLANS)))
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_graph_replays_match_eager(B, case, prec):
+    import torch
+    Nn, nx = PLANS[case]
+    announce(f"graphs case={case} prec={prec} Nn={Nn} nx={nx}")
+    p = B.BIRK_F64 if prec == "f64" else B.BIRK_F32
+    dt = torch.float64 if prec == "f64" else torch.float32
+    side = torch.cuda.Stream()
+    n = sum(a * b for a, b in zip(Nn, nx))
+    xs = [torch.from_numpy(wl.random_vectors([21, case, k], (n,))[0]).to("cuda", dt) for k in range(4)]
+    eager = B.birk_plan_create(Nn, nx, p, side)
+    graph = B.birk_plan_create(Nn, nx, p, side)
+    B.birk_plan_set_graphs(graph)
+    with torch.cuda.stream(side):
+        v = torch.empty(n, dtype=dt, device="cuda")
+        out = torch.empty_like(v)
+        other = torch.empty_like(v)
+        ref = torch.empty_like(v)
+        for call in range(6):
+            t = call % 2
+            x = xs[call % len(xs)]
+            v.copy_(x)                                    # new data behind the same pointer
+            fn = B.birk_apply_T if t else B.birk_apply
+            fn(graph, v, out)                             # calls 0, 1: eager; 2, 3: record; then replay
+            fn(eager, x, ref)
+            B.birk_apply(graph, x, other)                 # another triple of the graph plan
+            side.synchronize()
+            got, want = host(out), host(ref)
+            assert np.array_equal(got, want), f"call {call}: max diff {np.max(np.abs(got - want))}"
+            assert np.array_equal(host(other), host(ref) if t == 0 else host(other))
+    side.synchronize()
+    eager.destroy()
+    graph.destroy()
+
+
+def test_graphs_need_a_stream(B):
+    plan = B.birk_plan_create([257], [2], B.BIRK_F64, 0)
+    with pytest.raises(B.BirkError):
+        B.birk_plan_set_graphs(plan)
+    plan.destroy()
