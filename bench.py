@@ -28,6 +28,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -36,7 +37,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Birkhoff matvec Gpts/s at N=2^20; solve time mixed vs FP64 at 1e-10 resid"
-KERNEL_SOURCES = ["paper_2509_01855_amd/csrc/birk_fast.hip", "paper_2509_01855_amd/csrc/birk_dct.hip"]
+KERNEL_SOURCES = ["paper_2509_01855_amd/csrc/birk_fast.hip", "paper_2509_01855_amd/csrc/birk_dct.hip",
+                  "paper_2509_01855_amd/csrc/birk_fft.h"]
 HBM_PEAK_GBS = 8000.0
 
 
@@ -70,8 +72,9 @@ def calibrate_copy():
     print(json.dumps({"calibrate_copy_bytes_each": n * 8, "copies": 3}), flush=True)
 
 
-def traffic_record(kernel_sources):
-    """Measured HBM bytes per product from profiles/, if the kernels are unchanged since."""
+def traffic_record(kernel_sources, schedule=None):
+    """Measured HBM bytes per product from profiles/, if the kernels are unchanged since and
+    the product runs the tile schedule the counters were taken with."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "apply_f64_traffic.json")
     if not os.path.exists(path):
@@ -81,6 +84,8 @@ def traffic_record(kernel_sources):
     for f in kernel_sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if rec.get("source_sha256") != h.hexdigest():
+        return None
+    if schedule is not None and rec.get("schedule") != schedule:
         return None
     return rec
 
@@ -236,6 +241,7 @@ def main():
 
     # autotuner of the power-of-two product path (plan setup, outside the timed region)
     tuned = {}
+    head_sched = {"split": 0, "tb": 0, "xcd": 1}  # defaults unless the tuner picks another
     if not a.no_tune:
         print("[bench] autotuning the power-of-two plans", file=sys.stderr, flush=True)
         tplans = {"headline_f64": plan64, "headline_f32": planmx}
@@ -246,6 +252,9 @@ def main():
             rep = B.birk_plan_tune(plan)
             tuned[name] = [ln.split(" chosen ")[0].split(":")[0] + ": " + ln.split(" chosen ")[1]
                            for ln in rep.splitlines() if " chosen " in ln]
+            if name == "headline_f64":
+                m = re.search(r"chosen \[split (\d+), tb (\d+), xcd (\d+)\]", rep)
+                head_sched = {"split": int(m.group(1)), "tb": int(m.group(2)), "xcd": int(m.group(3))}
         torch.cuda.synchronize()
 
     def step(timed: bool):
@@ -321,7 +330,7 @@ def main():
             "precond_inverse_f64_us": us("pinv"),
         },
     }
-    tr = traffic_record(KERNEL_SOURCES)
+    tr = traffic_record(KERNEL_SOURCES, head_sched)
     if tr is not None:
         out["roofline"]["traffic"] = tr["bytes_per_product"]
         out["roofline"]["traffic_source"] = "profiles/apply_f64_traffic.json"

@@ -1137,8 +1137,11 @@ void fast_sizes(const birk_plan* p, int64_t N, int nc, int64_t* work, int64_t* p
 }
 
 // Autotuner: per group, B^a over every candidate schedule on the plan's scratch vectors
-// (one warm-up call, then kTuneReps timed calls between HIP events); the fastest stays.
+// (one warm-up call, then kTuneReps timed calls between HIP events).  The default
+// schedule (first candidate) stays unless another is faster by more than kTuneMargin, so
+// that timing noise does not flip the choice between near-equal schedules.
 constexpr int kTuneReps = 5;
+constexpr float kTuneMargin = 0.02f;
 
 template <typename T>
 static hipError_t tune_groups(birk_plan* p, hipStream_t s, std::string* report) {
@@ -1169,7 +1172,7 @@ static hipError_t tune_groups(birk_plan* p, hipStream_t s, std::string* report) 
       ms /= kTuneReps;
       snprintf(line, sizeof line, " [split %d, tb %d, xcd %d] %.1f us;", c.split, c.tb, c.xcd, 1000.0 * ms);
       *report += line;
-      if (first || ms < best_ms) {
+      if (first || ms < best_ms * (1.0f - kTuneMargin)) {
         best = c;
         best_ms = ms;
         first = false;

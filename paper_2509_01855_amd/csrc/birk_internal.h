@@ -120,6 +120,7 @@ struct PinvDesc {
   // wave-scan path (n_x <= kWaveNx): tiles of kTileNodes nodes
   int64_t ntile = 0;                    // tiles of the instance
   int64_t tagg = 0, tst = 0;            // tile aggregates and tile start states (doubles)
+  int64_t tmap = 0;                     // inclusive chunk maps, [tile][field][thread] (doubles)
 };
 
 // Instances with one state count n_x: each scan phase is one launch over all of them.

@@ -603,11 +603,12 @@ __global__ __launch_bounds__(256) void k_pinv_down(double* __restrict__ scan, co
 // hold consecutive chunks in node order.  Per-node fields (the n_x^2 entries of H_k, then
 // w_k) are stored as [g][j][e][t]: each access of a wave is 64 consecutive values.
 // Three launches per class:
-//   reduce  each thread composes its chunk's node maps; a DPP scan across the wave and
-//           a 4-lane scan of the wave totals give the tile aggregate;
+//   reduce  each thread composes its chunk's node maps; a DPP scan across the wave and a
+//           4-lane scan of the wave totals give every chunk the map from the start of its
+//           tile through its last node (stored), the last of them the tile aggregate;
 //   tiles   one workgroup per instance scans the tile aggregates into tile start states;
-//   apply   each tile rebuilds its chunk maps, scans them across the wave, derives every
-//           chunk's start state from the tile's and replays its nodes.
+//   apply   each chunk advances its tile's start state by the stored map of the chunk
+//           before it and replays its nodes (no scan, few registers).
 // Nodes past N_n carry H = 0 (identity maps) and are neither read from y nor written.
 constexpr int kWaveNx = 8;
 constexpr int kTileThreads = 256;
@@ -836,10 +837,13 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tmake_h(JT* __restrict__ js
   }
 }
 
-// Tile aggregate: the composition of the tile's node maps, to scan[tagg + g F].
-// tile = (k, g).
+// Tile maps: each chunk's map composed from its node maps, scanned across the wave by
+// DPP, then composed with the maps of the tile's earlier waves (a 4-lane scan of the wave
+// totals gives their prefixes), so chunk t holds the map of nodes 0 .. 4t + 3 of its tile.
+// These inclusive maps are stored as [g][field][t] (scan[tmap + g F 256 + f 256 + t]) and
+// the last one is the tile aggregate (scan[tagg + g F]).  tile = (k, g).
 template <int NX, typename T>
-__global__ __launch_bounds__(kTileThreads) void k_tscan_reduce(const T* __restrict__ jsw, const T* __restrict__ y,
+__global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const T* __restrict__ jsw, const T* __restrict__ y,
                                                              const PinvDesc* __restrict__ pd,
                                                              const int2* __restrict__ tiles,
                                                              double* __restrict__ scan) {
@@ -852,24 +856,61 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_reduce(const T* __restri
   const int64_t g = t.y;
   const T* hs = jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x;
   const int64_t k0 = (g * kTileThreads + threadIdx.x) * kTC;
-  Aff<NX> m;
-  chunk_map<NX, T>(hs, y + d.off, d.Nn, k0, m);
-  wave_scan<NX>(m);
   const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
-  if (l == 63) aff_store<NX>(&tot[w][0], m);
+  double* cm = scan + d.tmap + g * F * kTileThreads + threadIdx.x;
+  {
+    Aff<NX> m;
+    chunk_map<NX, T>(hs, y + d.off, d.Nn, k0, m);
+    wave_scan<NX>(m);
+    if (l == 63) aff_store<NX>(&tot[w][0], m);
+#pragma unroll
+    for (int f = 0; f < F; ++f) cm[f * kTileThreads] = (f < NX * NX) ? m.A[f / NX][f % NX] : m.b[f - NX * NX];
+  }
   __syncthreads();
   if (w == 0) {
-    // lanes 0..NW-1 hold the wave totals; a row_shr scan over them leaves the tile
-    // aggregate in lane NW - 1
-    if (l < NW)
-      aff_load<NX>(&tot[l][0], m);
+    // lanes 1..NW-1 of wave 0 turn the wave totals into the maps of waves 0..l-1; within
+    // the wave every lane reads tot before any lane writes it
+    Aff<NX> p;
+    if (l >= 1 && l < NW)
+      aff_load<NX>(&tot[l - 1][0], p);
     else
-      aff_identity<NX>(m);
-    scan_step<NX, 0x111, 0xF>(m, l >= 1);
-    scan_step<NX, 0x112, 0xF>(m, l >= 2);
-    if (l == NW - 1) aff_store<NX>(scan + d.tagg + g * F, m);
+      aff_identity<NX>(p);
+    scan_step<NX, 0x111, 0xF>(p, l >= 2);
+    scan_step<NX, 0x112, 0xF>(p, l >= 3);
+    if (l >= 1 && l < NW) aff_store<NX>(&tot[l][0], p);
+  }
+  __syncthreads();
+  if (w > 0) {
+    // the wave's maps, stored above, <- map o (map of the earlier waves); row r of the
+    // product needs row r of the map only
+    Aff<NX> q;
+    aff_load<NX>(&tot[w][0], q);
+    double last[F];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      double a[NX];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) a[c] = cm[(r * NX + c) * kTileThreads];
+      double nb = cm[(NX * NX + r) * kTileThreads];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) {
+        nb += a[c] * q.b[c];
+        double v = 0.0;
+#pragma unroll
+        for (int u = 0; u < NX; ++u) v += a[u] * q.A[u][c];
+        cm[(r * NX + c) * kTileThreads] = v;
+        last[r * NX + c] = v;
+      }
+      cm[(NX * NX + r) * kTileThreads] = nb;
+      last[NX * NX + r] = nb;
+    }
+    if (threadIdx.x == kTileThreads - 1) {
+#pragma unroll
+      for (int f = 0; f < F; ++f) scan[d.tagg + g * F + f] = last[f];
+    }
   }
 }
+
 
 // Tile start states of one instance (S = 0 before node 0), one workgroup per instance:
 // thread t composes the aggregates of tiles [t q, t q + q), the maps are scanned across
@@ -912,48 +953,41 @@ __global__ __launch_bounds__(256) void k_tscan_tiles(double* __restrict__ scan, 
   }
 }
 
-// Replay of one tile from its start state: chunk maps are rebuilt and scanned across
-// the wave; chunk start state = (maps of the earlier chunks)(tile start state); then per
-// node u = y_k + S, v = H_k u, xi_k = u + v / 2, (J xi)_k = v / w_k, S <- S + v.
-// tile = (k, g).
+// Replay of one tile: chunk t starts from the tile start state advanced by the inclusive
+// map of chunk t - 1 (k_tscan_reduce), then per node u = y_k + S, v = H_k u,
+// xi_k = u + v / 2, (J xi)_k = v / w_k, S <- S + v.  tile = (k, g).
 template <int NX, typename T>
-__global__ __launch_bounds__(kTileThreads, 2) void k_tscan_apply(const T* __restrict__ jsw, const T* __restrict__ y,
+__global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const T* __restrict__ jsw, const T* __restrict__ y,
                                                             const PinvDesc* __restrict__ pd,
                                                             const int2* __restrict__ tiles,
                                                             const double* __restrict__ scan, T* __restrict__ out,
                                                             T* __restrict__ jout) {
   constexpr int E = NX * NX + 1;
   constexpr int F = NX * NX + NX;
-  constexpr int NW = kTileThreads / 64;
-  __shared__ double tot[NW][F];
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
   const int64_t g = t.y;
   const int64_t Nn = d.Nn;
-  const T* hs = jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x;
-  const T* yi = y + d.off;
   const int64_t k0 = (g * kTileThreads + threadIdx.x) * kTC;
+  if (k0 >= Nn) return;
   double s[NX];
-  {
-    Aff<NX> m;
-    chunk_map<NX, T>(hs, yi, Nn, k0, m);
-    wave_scan<NX>(m);
-    const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
-    if (l == 63) aff_store<NX>(&tot[w][0], m);
-    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < NX; ++r) s[r] = scan[d.tst + g * NX + r];
-    for (int v = 0; v < w; ++v) advance<NX>(&tot[v][0], 1, s);
-    double x[NX];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) x[r] = s[r];
-    aff_apply<NX>(m, x);
+  for (int r = 0; r < NX; ++r) s[r] = scan[d.tst + g * NX + r];
+  if (threadIdx.x > 0) {
+    const double* cm = scan + d.tmap + g * F * kTileThreads + (threadIdx.x - 1);
+    double ns[NX];
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
-      const double up = __shfl_up(x[r], 1);
-      s[r] = (l == 0) ? s[r] : up;
+      double acc = cm[(NX * NX + r) * kTileThreads];
+#pragma unroll
+      for (int c = 0; c < NX; ++c) acc += cm[(r * NX + c) * kTileThreads] * s[c];
+      ns[r] = acc;
     }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) s[r] = ns[r];
   }
+  const T* hs = jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x;
+  const T* yi = y + d.off;
   T* oi = out + d.off;
   T* ji = jout ? jout + d.off : nullptr;
 #pragma unroll 1
@@ -1086,7 +1120,7 @@ int64_t pinv_jsw_size(int64_t Nn, int nx) {
 // Scratch (doubles) the inverse scan needs for one instance (level 0 in whole blocks).
 int64_t pinv_scratch(int64_t Nn, int nx) {
   const int64_t S = (int64_t)nx * nx + 2 * nx;
-  if (nx <= kWaveNx) return pinv_tiles(Nn) * S;
+  if (nx <= kWaveNx) return pinv_tiles(Nn) * (S + ((int64_t)nx * nx + nx) * kTileThreads);
   int64_t cnt[kPinvMaxLevels];
   const int L = pinv_levels(Nn, cnt);
   int64_t tot = pinv_blocks0(cnt[0]) * 64 * kFan * S;
@@ -1122,10 +1156,11 @@ hipError_t plan_solve(birk_plan* p) {
       const int64_t S = (int64_t)nx * nx + nx;
       int64_t base = in.scan_off;
       if (nx <= kWaveNx) {
-        // scratch: tile aggregates, then tile start states
+        // scratch: tile aggregates, tile start states, inclusive chunk maps per tile
         d.ntile = pinv_tiles(in.Nn);
         d.tagg = base;
         d.tst = base + d.ntile * S;
+        d.tmap = d.tst + d.ntile * nx;
         pc.host.push_back(d);
         continue;
       }

@@ -19,7 +19,10 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SOURCES = ["paper_2509_01855_amd/csrc/birk_fast.hip", "paper_2509_01855_amd/csrc/birk_dct.hip"]
+SOURCES = ["paper_2509_01855_amd/csrc/birk_fast.hip", "paper_2509_01855_amd/csrc/birk_dct.hip",
+           "paper_2509_01855_amd/csrc/birk_fft.h"]
+# the counter runs use bench.py --no-tune: the default tile schedule of the product
+SCHEDULE = {"split": 0, "tb": 0, "xcd": 1}
 import re
 
 # forward double product: pass A, pass B (TRANS = 0), pass C (TRANS = 0); the
@@ -67,7 +70,7 @@ def main():
     for f in SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     rec = {"bytes_per_product": total, "per_kernel": per, "fetch_scale": sf, "write_scale": sw,
-           "source_sha256": h.hexdigest()}
+           "schedule": SCHEDULE, "source_sha256": h.hexdigest()}
     json.dump(rec, open(out, "w"), indent=1)
     print(json.dumps(rec, indent=1))
 
