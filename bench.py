@@ -85,9 +85,10 @@ def traffic_record(kernel_sources, schedule=None):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if rec.get("source_sha256") != h.hexdigest():
         return None
-    if schedule is not None and rec.get("schedule") != schedule:
-        return None
-    return rec
+    for r in rec.get("records", []):
+        if schedule is None or r["schedule"] == schedule:
+            return r
+    return None
 
 
 def cpu_baseline(N: int, sample_rows: int, v):

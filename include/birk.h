@@ -105,9 +105,11 @@ int64_t birk_plan_length(const birk_plan* plan);
 /* Autotuner of the power-of-two product path (N = 2^p >= 512).  For each group of
  * same-length components it times B^a (FastBV box) in the plan's precision over a
  * fixed set of tile schedules: both splits 2N = L1 L2 of the two-step DCTs, two or four
- * rows per middle-pass tile, and the plain or XCD-grouped tile order.  Each candidate
- * runs once to warm up, then five times between events on the plan's stream; the
- * fastest stays with the plan for every later product.  The schedule changes only the
+ * rows per middle-pass tile, and the plain or XCD-grouped tile order.  In each of two
+ * interleaved rounds a candidate runs once to warm up, then four times between events on
+ * the plan's stream, alternating two input/output pairs; its best round counts.  The
+ * default schedule stays unless a candidate is more than 2 % faster; the choice stays
+ * with the plan for every later product.  The schedule changes only the
  * order of floating-point operations (results stay within the product tolerance).
  * Inputs are the plan's own scratch vectors; no allocation.  Blocks until done.
  * report: optional host buffer (NULL, or report_len > 0) that receives a NUL-terminated

@@ -1136,50 +1136,56 @@ void fast_sizes(const birk_plan* p, int64_t N, int nc, int64_t* work, int64_t* p
   *part = (int64_t)nc * ntB;
 }
 
-// Autotuner: per group, B^a over every candidate schedule on the plan's scratch vectors
-// (one warm-up call, then kTuneReps timed calls between HIP events).  The default
-// schedule (first candidate) stays unless another is faster by more than kTuneMargin, so
-// that timing noise does not flip the choice between near-equal schedules.
-constexpr int kTuneReps = 5;
+// Autotuner: per group, B^a over every candidate schedule on the plan's scratch vectors,
+// alternating two input/output pairs; each candidate runs once to warm up and then
+// kTuneReps times between HIP events, in kTuneRounds interleaved rounds, and keeps its
+// best round.  The default schedule (first candidate) stays unless another is faster by
+// more than kTuneMargin, so that timing noise does not flip the choice between
+// near-equal schedules.
+constexpr int kTuneReps = 4;
+constexpr int kTuneRounds = 2;
 constexpr float kTuneMargin = 0.02f;
 
 template <typename T>
 static hipError_t tune_groups(birk_plan* p, hipStream_t s, std::string* report) {
-  T* in = (T*)p->tmp_vec[0];
-  T* out = (T*)p->tmp_vec[1];
-  hipError_t e = hipMemsetAsync(in, 0, (size_t)p->total_len * sizeof(T), s);
+  T* in[2] = {(T*)p->tmp_vec[0], (T*)p->tmp_vec[2]};
+  T* out[2] = {(T*)p->tmp_vec[1], (T*)p->tmp_vec[3]};
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMemsetAsync(in[b], 0, (size_t)p->total_len * sizeof(T), s);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   char line[160];
   for (FastGroup& g : p->fgroups) {
     if (e != hipSuccess) break;
-    FastKnobs best = g.kn;
-    float best_ms = 0.0f;
-    bool first = true;
-    snprintf(line, sizeof line, "N=%lld x %d:", (long long)g.N, g.nc);
-    *report += line;
-    for (const FastKnobs& c : tune_candidates(p->fast_kn)) {
-      g.kn = c;
-      if ((e = fast_product<T>(p, g, in, out, 0, s)) != hipSuccess) break;
-      if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
-      for (int r = 0; r < kTuneReps && e == hipSuccess; ++r) e = fast_product<T>(p, g, in, out, 0, s);
-      if (e == hipSuccess) e = hipEventRecord(e1, s);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) break;
-      ms /= kTuneReps;
-      snprintf(line, sizeof line, " [split %d, tb %d, xcd %d] %.1f us;", c.split, c.tb, c.xcd, 1000.0 * ms);
-      *report += line;
-      if (first || ms < best_ms * (1.0f - kTuneMargin)) {
-        best = c;
-        best_ms = ms;
-        first = false;
+    const std::vector<FastKnobs> cand = tune_candidates(p->fast_kn);
+    std::vector<float> best_of(cand.size(), 0.0f);
+    for (int round = 0; round < kTuneRounds && e == hipSuccess; ++round) {
+      for (size_t ci = 0; ci < cand.size() && e == hipSuccess; ++ci) {
+        g.kn = cand[ci];
+        if ((e = fast_product<T>(p, g, in[0], out[0], 0, s)) != hipSuccess) break;
+        if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+        for (int r = 0; r < kTuneReps && e == hipSuccess; ++r) e = fast_product<T>(p, g, in[r & 1], out[r & 1], 0, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        ms /= kTuneReps;
+        if (round == 0 || ms < best_of[ci]) best_of[ci] = ms;
       }
     }
-    g.kn = best;
-    snprintf(line, sizeof line, " chosen [split %d, tb %d, xcd %d]\n", best.split, best.tb, best.xcd);
+    if (e != hipSuccess) break;
+    snprintf(line, sizeof line, "N=%lld x %d:", (long long)g.N, g.nc);
+    *report += line;
+    size_t best = 0;
+    for (size_t ci = 0; ci < cand.size(); ++ci) {
+      snprintf(line, sizeof line, " [split %d, tb %d, xcd %d] %.1f us;", cand[ci].split, cand[ci].tb, cand[ci].xcd,
+               1000.0 * best_of[ci]);
+      *report += line;
+      if (best_of[ci] < best_of[best] * (1.0f - kTuneMargin)) best = ci;
+    }
+    g.kn = cand[best];
+    snprintf(line, sizeof line, " chosen [split %d, tb %d, xcd %d]\n", g.kn.split, g.kn.tb, g.kn.xcd);
     *report += line;
   }
   if (e0) (void)hipEventDestroy(e0);

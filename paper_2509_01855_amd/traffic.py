@@ -1,5 +1,9 @@
 """Turn rocprofv3 FETCH_SIZE / WRITE_SIZE runs into HBM bytes per B^a product.
 
+The record of one tile schedule (taken from the BIRK_FAST_SPLIT / BIRK_FAST_TB /
+BIRK_FAST_XCD environment of the counter runs, defaults 0 / 0 / 1) is merged into
+<out.json>, which keeps one record per schedule for the current kernel sources.
+
 Usage (after the four counter runs described in profiles/README.md):
     python -m paper_2509_01855_amd.traffic <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir> <out.json>
 
@@ -21,8 +25,13 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SOURCES = ["paper_2509_01855_amd/csrc/birk_fast.hip", "paper_2509_01855_amd/csrc/birk_dct.hip",
            "paper_2509_01855_amd/csrc/birk_fft.h"]
-# the counter runs use bench.py --no-tune: the default tile schedule of the product
-SCHEDULE = {"split": 0, "tb": 0, "xcd": 1}
+
+
+def _schedule():
+    """Tile schedule of the counter runs (bench.py --no-tune with the environment defaults)."""
+    return {"split": int(os.environ.get("BIRK_FAST_SPLIT", "0")) and 1,
+            "tb": max(0, min(14, int(os.environ.get("BIRK_FAST_TB", "0")))) & ~1,
+            "xcd": int(os.environ.get("BIRK_FAST_XCD", "1")) and 1}
 import re
 
 # forward double product: pass A, pass B (TRANS = 0), pass C (TRANS = 0); the
@@ -69,9 +78,15 @@ def main():
     h = hashlib.sha256()
     for f in SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    rec = {"bytes_per_product": total, "per_kernel": per, "fetch_scale": sf, "write_scale": sw,
-           "schedule": SCHEDULE, "source_sha256": h.hexdigest()}
-    json.dump(rec, open(out, "w"), indent=1)
+    rec = {"schedule": _schedule(), "bytes_per_product": total, "per_kernel": per, "fetch_scale": sf,
+           "write_scale": sw}
+    doc = {"source_sha256": h.hexdigest(), "records": []}
+    if os.path.exists(out):
+        old = json.load(open(out))
+        if old.get("source_sha256") == doc["source_sha256"]:
+            doc["records"] = [r for r in old.get("records", []) if r["schedule"] != rec["schedule"]]
+    doc["records"].append(rec)
+    json.dump(doc, open(out, "w"), indent=1)
     print(json.dumps(rec, indent=1))
 
 
