@@ -417,8 +417,10 @@ hipError_t ensure_krylov(birk_plan* p, int m, size_t esize) {
   // sized for double so that one allocation serves either Krylov precision
   (void)esize;
   // Q: m + 1 basis vectors; Z: m preconditioned vectors z_j = P^{-1} q_j (kept so the
-  // update chi += P^{-1} Q y = Z y needs no further preconditioner application)
-  e = hipMalloc(&p->krylov_Q, (size_t)(2 * m + 1) * p->total_len * sizeof(double));
+  // update chi += P^{-1} Q y = Z y needs no further preconditioner application); double
+  // plans also keep Y: the m vectors J z_j, so that J chi follows by the same combination
+  const int nvec = (p->prec == BIRK_F64 ? 3 : 2) * m + 1;
+  e = hipMalloc(&p->krylov_Q, (size_t)nvec * p->total_len * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&p->krylov_vec, (size_t)4 * p->total_len * sizeof(double));
   if (e == hipSuccess) p->krylov_m = m;
   return e;
@@ -442,10 +444,12 @@ hipError_t seg_norms(birk_plan* p, const double* v, std::vector<double>& out) {
 }
 
 // One right-preconditioned GMRES cycle in precision TK on A d = r / ||r||, for every
-// instance not yet done; chi += ||r|| d.  r lives in tmp_vec[0] (double).
+// instance not yet done; chi += ||r|| d.  r: the current residual (double).  jchi
+// (double plans, else null): J chi, updated alongside chi from the kept J z_j.
 template <typename TK>
-birk_status gmres_cycle(birk_plan* p, int jk, const double* J, double* chi, std::vector<InstState>& st,
-                        const std::vector<double>& tol_inner, int m, int use_precond, int& budget) {
+birk_status gmres_cycle(birk_plan* p, int jk, const double* J, const double* r, double* chi, double* jchi,
+                        std::vector<InstState>& st, const std::vector<double>& tol_inner, int m, int use_precond,
+                        int& budget) {
   const int B = (int)p->inst.size();
   const int64_t n = p->total_len;
   hipStream_t s = p->stream;
@@ -454,8 +458,8 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, double* chi, std:
   TK* u = (TK*)p->krylov_vec;
   TK* y = u + n;
   TK* t = y + n;
-  const double* r = (const double*)p->tmp_vec[0];
   const int64_t ld = n;
+  TK* Yb = jchi ? Z + (size_t)m * ld : nullptr;  // J z_j, j < m
   hipError_t e = hipSuccess;
 
   std::vector<char> active(B, 0);
@@ -484,6 +488,7 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, double* chi, std:
     if (!any) break;
     const TK* qj = Q + (size_t)j * ld;
     TK* z = Z + (size_t)j * ld;
+    if (Yb) y = Yb + (size_t)j * ld;
     // z = P^{-1} q_j, y = J z; t = B^a y; u = z - t
     if (use_precond) {
       e = precond_inverse<TK>(p, jk, J, qj, z, y, s, p->flag);
@@ -505,8 +510,7 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, double* chi, std:
       double* d2 = d1 + kDotsStride;
       const int64_t ds = 2 * kDotsStride;
       kry::sdots<TK>(p, Q, j + 1, u, d1, ds, s);
-      kry::saxpys<TK>(p, Q, j + 1, d1, ds, u, nullptr, s);
-      kry::sdots<TK>(p, Q, j + 1, u, d2, ds, s);
+      kry::saxpys_dots<TK>(p, Q, j + 1, d1, ds, u, d2, ds, s);
       kry::saxpys<TK>(p, Q, j + 1, d2, ds, u, d2, s);
       kry::snormalize<TK>(p, u, d2 + kKryMaxDots, ds, Q + (size_t)(j + 1) * ld, s);
     }
@@ -586,6 +590,11 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, double* chi, std:
   const TK* basis = use_precond ? Z : Q;
   kry::scombine<TK>(p, basis, p->krylov_coef, kDotsStride, p->krylov_cnt, t, s);
   kry::add_to<TK>(chi, t, n, s);
+  if (Yb) {
+    // J chi += ||r|| J Z y (J Q y without preconditioning) from the kept J z_j
+    kry::scombine<TK>(p, Yb, p->krylov_coef, kDotsStride, p->krylov_cnt, t, s);
+    kry::add_to<TK>(jchi, t, n, s);
+  }
   e = hipStreamSynchronize(s);
   return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
 }
@@ -626,18 +635,27 @@ extern "C" birk_status birk_krylov_solve(birk_plan* p, birk_jac_kind jk, const d
   birk_status result = BIRK_OK;
   double* r = (double*)p->tmp_vec[0];
   double* t = (double*)p->tmp_vec[1];
+  // double plans carry J chi (tmp_vec[2]) alongside chi, updated from the kept J z_j, so
+  // the true residual needs no Jacobian product; mixed plans form J chi from chi in double
+  double* jchi = mixed ? nullptr : (double*)p->tmp_vec[2];
+  if (jchi) {
+    e = o.use_x0 ? jac_times<double>(p, jk, J, chi, jchi, s) : hipMemsetAsync(jchi, 0, n * sizeof(double), s);
+    if (e != hipSuccess) return BIRK_ERR_DEVICE;
+  }
   for (int outer = 0;; ++outer) {
-    // true residual r = beta - A chi in double (chi = 0 on the first step without x0: r = beta)
+    // true residual r = beta - A chi = beta - chi + B^a (J chi) in double (chi = 0 on the
+    // first step without x0: r = beta, whose norms are known)
+    const double* rcur = r;
+    std::vector<double> rn;
     if (outer == 0 && !o.use_x0) {
-      if (hipMemcpyAsync(r, beta, n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return BIRK_ERR_DEVICE;
+      rcur = beta;
+      rn = nb;
     } else {
-      e = fast_ax_f64(p, jk, J, chi, t);
+      e = jchi ? apply_product<double>(p, jchi, t, 0, s) : fast_ax_f64(p, jk, J, chi, t);
       if (e != hipSuccess) return BIRK_ERR_DEVICE;
       kry::residual(beta, chi, t, r, n, s);
+      if (seg_norms(p, r, rn) != hipSuccess) return BIRK_ERR_DEVICE;
     }
-    std::vector<double> rn;
-    if (seg_norms(p, r, rn) != hipSuccess) return BIRK_ERR_DEVICE;
     bool all_done = true;
     for (int i = 0; i < B; ++i) {
       st[i].rnorm = rn[i];
@@ -676,8 +694,8 @@ extern "C" birk_status birk_krylov_solve(birk_plan* p, birk_jac_kind jk, const d
       st[i].breakdown_last = st[i].status == BIRK_ERR_BREAKDOWN;
       if (st[i].status == BIRK_ERR_BREAKDOWN) st[i].status = BIRK_OK;
     }
-    birk_status cs = mixed ? gmres_cycle<float>(p, jk, J, chi, st, tol, o.restart, o.use_precond, budget)
-                           : gmres_cycle<double>(p, jk, J, chi, st, tol, o.restart, o.use_precond, budget);
+    birk_status cs = mixed ? gmres_cycle<float>(p, jk, J, rcur, chi, nullptr, st, tol, o.restart, o.use_precond, budget)
+                           : gmres_cycle<double>(p, jk, J, rcur, chi, jchi, st, tol, o.restart, o.use_precond, budget);
     if (cs == BIRK_ERR_SINGULAR || cs == BIRK_ERR_DEVICE) {
       result = cs;
       for (int i = 0; i < B; ++i) st[i].done = true;

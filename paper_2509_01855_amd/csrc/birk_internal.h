@@ -259,6 +259,11 @@ void sdots(const birk_plan* p, const T* Q, int nq, const T* u, double* out, int6
 template <typename T>
 void saxpys(const birk_plan* p, const T* Q, int nq, const double* h, int64_t hstride, T* u, double* nrm_out,
             hipStream_t s);
+// u -= sum_k h_k Q_k, then out = (Q_k . u for k < nq, ||u||^2 in the norm slot): the
+// update and the next Gram-Schmidt dot products in one pass
+template <typename T>
+void saxpys_dots(const birk_plan* p, const T* Q, int nq, const double* h, int64_t hstride, T* u, double* out,
+                 int64_t ostride, hipStream_t s);
 template <typename T>
 void snormalize(const birk_plan* p, const T* u, const double* nrm2, int64_t stride, T* q, hipStream_t s);
 template <typename TI, typename TO>

@@ -1397,31 +1397,40 @@ __global__ void k_add_to(double* __restrict__ x, const T* __restrict__ d, int64_
 // part[tile][kMaxDots + 1] and are summed per instance over its tile range in a fixed
 // order.
 
-template <typename T>
+// MAXQ >= nq bounds the per-thread accumulators (registers) at compile time.
+template <typename T, int MAXQ>
 __global__ __launch_bounds__(256) void k_sdots(const T* __restrict__ Q, int64_t ld, int nq, const T* __restrict__ u,
                                                SegSet sg, double* __restrict__ part) {
   const int2 t = sg.tiles[blockIdx.x];
   const int64_t base = sg.ioff[t.x] + (int64_t)t.y * kSegChunk;
   const int64_t end = sg.ioff[t.x] + min((int64_t)(t.y + 1) * kSegChunk, sg.ilen[t.x]);
-  double acc[kMaxDots + 1];
+  double acc[MAXQ], nrm = 0.0;
 #pragma unroll
-  for (int i = 0; i <= kMaxDots; ++i) acc[i] = 0.0;
+  for (int i = 0; i < MAXQ; ++i) acc[i] = 0.0;
   for (int64_t e = base + threadIdx.x; e < end; e += blockDim.x) {
     const double ue = (double)u[e];
 #pragma unroll
-    for (int i = 0; i < kMaxDots; ++i)
+    for (int i = 0; i < MAXQ; ++i)
       if (i < nq) acc[i] += (double)Q[(int64_t)i * ld + e] * ue;
-    acc[kMaxDots] += ue * ue;
+    nrm += ue * ue;
   }
   __shared__ double sh[256];
 #pragma unroll
-  for (int i = 0; i <= kMaxDots; ++i) {
-    if (i < nq || i == kMaxDots) {
+  for (int i = 0; i < MAXQ; ++i) {
+    if (i < nq) {
       const double v = block_sum256(acc[i], sh);
       if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (kMaxDots + 1) + i] = v;
     }
   }
+  const double v = block_sum256(nrm, sh);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (kMaxDots + 1) + kMaxDots] = v;
 }
+
+// Smallest accumulator bound of the Krylov kernels that covers nq basis vectors.
+#define BIRK_MAXQ_SWITCH(nq, CALL)                         \
+  if ((nq) <= 2) { constexpr int MQ = 2; CALL; }           \
+  else if ((nq) <= 8) { constexpr int MQ = 8; CALL; }      \
+  else { constexpr int MQ = kMaxDots; CALL; }
 
 // grid = (nq + 1, instances): block (x, i) sums output x (x == nq: the norm slot) of
 // instance i over its tiles into out[i * ostride + slot].
@@ -1437,8 +1446,10 @@ __global__ __launch_bounds__(256) void k_sreduce(const double* __restrict__ part
   if (threadIdx.x == 0) out[(int64_t)i * ostride + slot] = tot;
 }
 
-// u -= sum_k h[i][k] Q_k on instance i's tiles; part <- tile sums of ||u||^2 when asked
-template <typename T>
+// u -= sum_k h[i][k] Q_k on instance i's tiles; part <- tile sums of ||u||^2 when asked,
+// and with DOTS also of Q_k . u (the updated u), the first half of the next Gram-Schmidt
+// pass fused into this one.
+template <typename T, bool DOTS, int MAXQ>
 __global__ __launch_bounds__(256) void k_saxpys(const T* __restrict__ Q, int64_t ld, int nq,
                                                 const double* __restrict__ h, int64_t hstride, T* __restrict__ u,
                                                 SegSet sg, double* __restrict__ part) {
@@ -1448,18 +1459,42 @@ __global__ __launch_bounds__(256) void k_saxpys(const T* __restrict__ Q, int64_t
   __syncthreads();
   const int64_t base = sg.ioff[t.x] + (int64_t)t.y * kSegChunk;
   const int64_t end = sg.ioff[t.x] + min((int64_t)(t.y + 1) * kSegChunk, sg.ilen[t.x]);
+  constexpr int ND = DOTS ? MAXQ : 1;
+  double acc[ND];
+#pragma unroll
+  for (int i = 0; i < ND; ++i) acc[i] = 0.0;
   double nrm = 0.0;
   for (int64_t e = base + threadIdx.x; e < end; e += blockDim.x) {
     double ue = (double)u[e];
+    double qv[ND];
 #pragma unroll
-    for (int i = 0; i < kMaxDots; ++i)
-      if (i < nq) ue -= hs[i] * (double)Q[(int64_t)i * ld + e];
+    for (int i = 0; i < MAXQ; ++i)
+      if (i < nq) {
+        const double q = (double)Q[(int64_t)i * ld + e];
+        if constexpr (DOTS) qv[i] = q;
+        ue -= hs[i] * q;
+      }
     const T us = (T)ue;
     u[e] = us;
-    nrm += (double)us * (double)us;
+    const double un = (double)us;
+    nrm += un * un;
+    if constexpr (DOTS) {
+#pragma unroll
+      for (int i = 0; i < MAXQ; ++i)
+        if (i < nq) acc[i] += qv[i] * un;
+    }
   }
   if (part) {
     __shared__ double sh[256];
+    if constexpr (DOTS) {
+#pragma unroll
+      for (int i = 0; i < MAXQ; ++i) {
+        if (i < nq) {
+          const double v = block_sum256(acc[i], sh);
+          if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (kMaxDots + 1) + i] = v;
+        }
+      }
+    }
     const double v = block_sum256(nrm, sh);
     if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (kMaxDots + 1) + kMaxDots] = v;
   }
@@ -1530,7 +1565,8 @@ void add_to(double* x, const T* d, int64_t n, hipStream_t s) {
 template <typename T>
 void sdots(const birk_plan* p, const T* Q, int nq, const T* u, double* out, int64_t ostride, hipStream_t s) {
   const SegSet& sg = p->seg;
-  hipLaunchKernelGGL(k_sdots<T>, dim3(sg.ntiles), dim3(256), 0, s, Q, p->total_len, nq, u, sg, p->krylov_part);
+  BIRK_MAXQ_SWITCH(nq, hipLaunchKernelGGL((k_sdots<T, MQ>), dim3(sg.ntiles), dim3(256), 0, s, Q, p->total_len, nq, u,
+                                           sg, p->krylov_part))
   hipLaunchKernelGGL(k_sreduce, dim3(nq + 1, (unsigned)p->inst.size()), dim3(256), 0, s, p->krylov_part, sg, nq, out,
                      ostride);
 }
@@ -1539,11 +1575,21 @@ template <typename T>
 void saxpys(const birk_plan* p, const T* Q, int nq, const double* h, int64_t hstride, T* u, double* nrm_out,
             hipStream_t s) {
   const SegSet& sg = p->seg;
-  hipLaunchKernelGGL(k_saxpys<T>, dim3(sg.ntiles), dim3(256), 0, s, Q, p->total_len, nq, h, hstride, u, sg,
-                     nrm_out ? p->krylov_part : nullptr);
+  BIRK_MAXQ_SWITCH(nq, hipLaunchKernelGGL((k_saxpys<T, false, MQ>), dim3(sg.ntiles), dim3(256), 0, s, Q,
+                                           p->total_len, nq, h, hstride, u, sg, nrm_out ? p->krylov_part : nullptr))
   if (nrm_out)
     hipLaunchKernelGGL(k_sreduce, dim3(1, (unsigned)p->inst.size()), dim3(256), 0, s, p->krylov_part, sg, 0, nrm_out,
                        hstride);
+}
+
+template <typename T>
+void saxpys_dots(const birk_plan* p, const T* Q, int nq, const double* h, int64_t hstride, T* u, double* out,
+                 int64_t ostride, hipStream_t s) {
+  const SegSet& sg = p->seg;
+  BIRK_MAXQ_SWITCH(nq, hipLaunchKernelGGL((k_saxpys<T, true, MQ>), dim3(sg.ntiles), dim3(256), 0, s, Q,
+                                           p->total_len, nq, h, hstride, u, sg, p->krylov_part))
+  hipLaunchKernelGGL(k_sreduce, dim3(nq + 1, (unsigned)p->inst.size()), dim3(256), 0, s, p->krylov_part, sg, nq, out,
+                     ostride);
 }
 
 template <typename T>
@@ -1565,6 +1611,10 @@ void scombine(const birk_plan* p, const T* Q, const double* c, int64_t cstride, 
 
 template void sdots<double>(const birk_plan*, const double*, int, const double*, double*, int64_t, hipStream_t);
 template void sdots<float>(const birk_plan*, const float*, int, const float*, double*, int64_t, hipStream_t);
+template void saxpys_dots<double>(const birk_plan*, const double*, int, const double*, int64_t, double*, double*,
+                                  int64_t, hipStream_t);
+template void saxpys_dots<float>(const birk_plan*, const float*, int, const double*, int64_t, float*, double*,
+                                 int64_t, hipStream_t);
 template void saxpys<double>(const birk_plan*, const double*, int, const double*, int64_t, double*, double*,
                              hipStream_t);
 template void saxpys<float>(const birk_plan*, const float*, int, const double*, int64_t, float*, double*,
