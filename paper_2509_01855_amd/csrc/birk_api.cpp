@@ -588,13 +588,9 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, const double* r, 
   if (e != hipSuccess) return BIRK_ERR_DEVICE;
   // chi += ||r|| P^{-1} Q y = ||r|| Z y (Z = Q without preconditioning)
   const TK* basis = use_precond ? Z : Q;
-  kry::scombine<TK>(p, basis, p->krylov_coef, kDotsStride, p->krylov_cnt, t, s);
-  kry::add_to<TK>(chi, t, n, s);
-  if (Yb) {
-    // J chi += ||r|| J Z y (J Q y without preconditioning) from the kept J z_j
-    kry::scombine<TK>(p, Yb, p->krylov_coef, kDotsStride, p->krylov_cnt, t, s);
-    kry::add_to<TK>(jchi, t, n, s);
-  }
+  kry::scombine<TK>(p, basis, p->krylov_coef, kDotsStride, p->krylov_cnt, chi, s);
+  // J chi += ||r|| J Z y (J Q y without preconditioning) from the kept J z_j
+  if (Yb) kry::scombine<TK>(p, Yb, p->krylov_coef, kDotsStride, p->krylov_cnt, jchi, s);
   e = hipStreamSynchronize(s);
   return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
 }

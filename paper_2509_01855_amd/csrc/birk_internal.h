@@ -250,8 +250,6 @@ namespace kry {
 template <typename T>
 void sub(const T* a, const T* b, T* z, int64_t n, hipStream_t s);
 void residual(const double* beta, const double* x, const double* t, double* r, int64_t n, hipStream_t s);
-template <typename T>
-void add_to(double* x, const T* d, int64_t n, hipStream_t s);
 // Segmented forms over every instance of the batch at once (ld = plan length; per
 // instance i results at out + i * ostride).
 template <typename T>
@@ -268,8 +266,9 @@ template <typename T>
 void snormalize(const birk_plan* p, const T* u, const double* nrm2, int64_t stride, T* q, hipStream_t s);
 template <typename TI, typename TO>
 void sscale_conv(const birk_plan* p, const TI* x, TO* y, const double* alpha, hipStream_t s);
+// x += sum_{k < cnt[i]} c[i][k] Q_k (x double, the sum in double)
 template <typename T>
-void scombine(const birk_plan* p, const T* Q, const double* c, int64_t cstride, const int* cnt, T* u,
+void scombine(const birk_plan* p, const T* Q, const double* c, int64_t cstride, const int* cnt, double* x,
               hipStream_t s);
 }  // namespace kry
 

@@ -1384,13 +1384,6 @@ __global__ void k_residual(const double* __restrict__ beta, const double* __rest
   r[e] = beta[e] - x[e] + t[e];
 }
 
-// x += (double) d
-template <typename T>
-__global__ void k_add_to(double* __restrict__ x, const T* __restrict__ d, int64_t n) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  x[e] += (double)d[e];
-}
 
 // ---- segmented forms: one launch over every instance of the batch ----
 // A tile is kSegChunk consecutive elements of one instance; partial results go to
@@ -1524,11 +1517,11 @@ __global__ __launch_bounds__(256) void k_sscale_conv(const TI* __restrict__ x, T
   for (int64_t e = base + threadIdx.x; e < end; e += blockDim.x) y[e] = (TO)(a == 0.0 ? 0.0 : a * (double)x[e]);
 }
 
-// u = sum_{k < cnt[i]} c[i][k] Q_k on instance i's tiles
+// x += sum_{k < cnt[i]} c[i][k] Q_k on instance i's tiles (x double, sum in double)
 template <typename T>
 __global__ __launch_bounds__(256) void k_scombine(const T* __restrict__ Q, int64_t ld, const double* __restrict__ c,
-                                                  int64_t cstride, const int* __restrict__ cnt, T* __restrict__ u,
-                                                  SegSet sg) {
+                                                  int64_t cstride, const int* __restrict__ cnt,
+                                                  double* __restrict__ x, SegSet sg) {
   const int2 t = sg.tiles[blockIdx.x];
   const int nq = cnt[t.x];
   __shared__ double cs[kMaxDots];
@@ -1541,7 +1534,7 @@ __global__ __launch_bounds__(256) void k_scombine(const T* __restrict__ Q, int64
 #pragma unroll
     for (int i = 0; i < kMaxDots; ++i)
       if (i < nq) acc += cs[i] * (double)Q[(int64_t)i * ld + e];
-    u[e] = (T)acc;
+    x[e] += acc;
   }
 }
 
@@ -1557,10 +1550,6 @@ void residual(const double* beta, const double* x, const double* t, double* r, i
   hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, s, beta, x, t, r, n);
 }
 
-template <typename T>
-void add_to(double* x, const T* d, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_add_to<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, x, d, n);
-}
 
 template <typename T>
 void sdots(const birk_plan* p, const T* Q, int nq, const T* u, double* out, int64_t ostride, hipStream_t s) {
@@ -1603,9 +1592,9 @@ void sscale_conv(const birk_plan* p, const TI* x, TO* y, const double* alpha, hi
 }
 
 template <typename T>
-void scombine(const birk_plan* p, const T* Q, const double* c, int64_t cstride, const int* cnt, T* u,
+void scombine(const birk_plan* p, const T* Q, const double* c, int64_t cstride, const int* cnt, double* x,
               hipStream_t s) {
-  hipLaunchKernelGGL(k_scombine<T>, dim3(p->seg.ntiles), dim3(256), 0, s, Q, p->total_len, c, cstride, cnt, u,
+  hipLaunchKernelGGL(k_scombine<T>, dim3(p->seg.ntiles), dim3(256), 0, s, Q, p->total_len, c, cstride, cnt, x,
                      p->seg);
 }
 
@@ -1625,12 +1614,10 @@ template void sscale_conv<double, double>(const birk_plan*, const double*, doubl
 template void sscale_conv<double, float>(const birk_plan*, const double*, float*, const double*, hipStream_t);
 template void scombine<double>(const birk_plan*, const double*, const double*, int64_t, const int*, double*,
                                hipStream_t);
-template void scombine<float>(const birk_plan*, const float*, const double*, int64_t, const int*, float*,
+template void scombine<float>(const birk_plan*, const float*, const double*, int64_t, const int*, double*,
                               hipStream_t);
 
 template void sub<double>(const double*, const double*, double*, int64_t, hipStream_t);
 template void sub<float>(const float*, const float*, float*, int64_t, hipStream_t);
-template void add_to<double>(double*, const double*, int64_t, hipStream_t);
-template void add_to<float>(double*, const float*, int64_t, hipStream_t);
 }  // namespace kry
 }  // namespace birk
