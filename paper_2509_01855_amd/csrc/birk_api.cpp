@@ -77,7 +77,7 @@ void free_plan(birk_plan* p) {
   if (p->krylov_dots) (void)hipFree(p->krylov_dots);
   if (p->krylov_part) (void)hipFree(p->krylov_part);
   if (p->krylov_coef) (void)hipFree(p->krylov_coef);
-  if (p->krylov_cnt) (void)hipFree(p->krylov_cnt);
+  if (p->krylov_stage) (void)hipHostFree(p->krylov_stage);
   if (p->flag) (void)hipFree(p->flag);
   delete p;
 }
@@ -401,14 +401,26 @@ struct InstState {
   bool breakdown_last = false;
 };
 
+// Pinned host staging of the Krylov driver: [dots: B x 2 x kDotsStride doubles][flag: one
+// double slot][coefficients: B x kDotsStride doubles][counts: B ints], the last two laid
+// out like krylov_coef on the device so one copy uploads both.
+size_t stage_bytes(size_t B) { return (B * 3 * kDotsStride + 1) * sizeof(double) + B * sizeof(int); }
+double* stage_dots(birk_plan* p) { return (double*)p->krylov_stage; }
+int* stage_flag(birk_plan* p) { return (int*)(stage_dots(p) + p->inst.size() * 2 * kDotsStride); }
+double* stage_coef(birk_plan* p) { return stage_dots(p) + p->inst.size() * 2 * kDotsStride + 1; }
+int* stage_cnt(birk_plan* p) { return (int*)(stage_coef(p) + p->inst.size() * kDotsStride); }
+
 hipError_t ensure_krylov(birk_plan* p, int m, size_t esize) {
   hipError_t e = hipSuccess;
   const size_t B = p->inst.size();
   if (!p->krylov_dots) e = hipMalloc(&p->krylov_dots, B * 2 * kDotsStride * sizeof(double));
   if (e == hipSuccess && !p->krylov_part)
     e = hipMalloc(&p->krylov_part, (size_t)std::max(p->seg.ntiles, 1) * kDotsStride * sizeof(double));
-  if (e == hipSuccess && !p->krylov_coef) e = hipMalloc(&p->krylov_coef, B * kDotsStride * sizeof(double));
-  if (e == hipSuccess && !p->krylov_cnt) e = hipMalloc(&p->krylov_cnt, B * sizeof(int));
+  if (e == hipSuccess && !p->krylov_coef) {
+    e = hipMalloc(&p->krylov_coef, B * kDotsStride * sizeof(double) + B * sizeof(int));
+    if (e == hipSuccess) p->krylov_cnt = (int*)(p->krylov_coef + B * kDotsStride);
+  }
+  if (e == hipSuccess && !p->krylov_stage) e = hipHostMalloc(&p->krylov_stage, stage_bytes(B), hipHostMallocDefault);
   if (e != hipSuccess) return e;
   if (p->krylov_Q && p->krylov_m >= m) return hipSuccess;
   if (p->krylov_Q) (void)hipFree(p->krylov_Q);
@@ -430,9 +442,9 @@ hipError_t ensure_krylov(birk_plan* p, int m, size_t esize) {
 hipError_t seg_norms(birk_plan* p, const double* v, std::vector<double>& out) {
   const int B = (int)p->inst.size();
   kry::sdots<double>(p, nullptr, 0, v, p->krylov_dots, 2 * kDotsStride, p->stream);
-  std::vector<double> h((size_t)B * 2 * kDotsStride);
-  hipError_t e = hipMemcpyAsync(h.data(), p->krylov_dots, h.size() * sizeof(double), hipMemcpyDeviceToHost,
-                                p->stream);
+  const double* h = stage_dots(p);
+  hipError_t e = hipMemcpyAsync(stage_dots(p), p->krylov_dots, (size_t)B * 2 * kDotsStride * sizeof(double),
+                                hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   out.resize(B);
   for (int i = 0; i < B; ++i) {
@@ -464,12 +476,12 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, const double* r, 
 
   std::vector<char> active(B, 0);
   for (int i = 0; i < B; ++i) active[i] = !st[i].done;
-  // q_0 = r / ||r|| (zero for inactive instances); host arrays handed to async copies
-  // live until the synchronisation at the end of the cycle
-  std::vector<double> sc(B, 0.0);
+  // q_0 = r / ||r|| (zero for inactive instances); the pinned staging is rewritten only
+  // after the synchronisations that follow this copy
   {
+    double* sc = stage_coef(p);
     for (int i = 0; i < B; ++i) sc[i] = active[i] && st[i].rnorm > 0 ? 1.0 / st[i].rnorm : 0.0;
-    e = hipMemcpyAsync(p->krylov_coef, sc.data(), B * sizeof(double), hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(p->krylov_coef, sc, B * sizeof(double), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return BIRK_ERR_DEVICE;
     kry::sscale_conv<double, TK>(p, r, Q, p->krylov_coef, s);
   }
@@ -479,8 +491,9 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, const double* r, 
   std::vector<int> jend(B, 0);
   std::vector<char> running(active);
   for (int i = 0; i < B; ++i) gv[i][0] = 1.0;
-  std::vector<double> hbuf((size_t)B * 2 * kDotsStride);
+  const double* hbuf = stage_dots(p);
   int flag_checked = 0;
+  bool synced = false;  // a synchronisation has passed since the q_0 scales were staged
 
   for (int j = 0; j < m && budget > 0; ++j) {
     bool any = false;
@@ -514,12 +527,15 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, const double* r, 
       kry::saxpys<TK>(p, Q, j + 1, d2, ds, u, d2, s);
       kry::snormalize<TK>(p, u, d2 + kKryMaxDots, ds, Q + (size_t)(j + 1) * ld, s);
     }
-    e = hipMemcpyAsync(hbuf.data(), p->krylov_dots, hbuf.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(stage_dots(p), p->krylov_dots, (size_t)B * 2 * kDotsStride * sizeof(double),
+                       hipMemcpyDeviceToHost, s);
+    const bool check_flag = use_precond && !flag_checked;
+    if (e == hipSuccess && check_flag) e = hipMemcpyAsync(stage_flag(p), p->flag, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return BIRK_ERR_DEVICE;
-    if (use_precond && !flag_checked) {
-      int f = 0;
-      if (hipMemcpy(&f, p->flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return BIRK_ERR_DEVICE;
+    synced = true;
+    if (check_flag) {
+      const int f = *stage_flag(p);
       flag_checked = 1;
       if (f) {
         for (int i = 0; i < B; ++i) st[i].status = BIRK_ERR_SINGULAR;
@@ -530,7 +546,7 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, const double* r, 
     for (int i = 0; i < B; ++i) {
       if (!running[i]) continue;
       st[i].inner += 1;
-      const double* d1 = hbuf.data() + (size_t)i * 2 * kDotsStride;
+      const double* d1 = hbuf + (size_t)i * 2 * kDotsStride;
       const double* d2 = d1 + kDotsStride;
       double* Hc = H[i].data() + (size_t)j * (m + 1);  // column j, rows 0..j+1
       for (int k = 0; k <= j; ++k) Hc[k] = d1[k] + d2[k];
@@ -569,7 +585,10 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, const double* r, 
     }
   }
   // back substitution and chi += ||r|| P^{-1} (Q y)
-  std::vector<double> coef((size_t)B * kDotsStride, 0.0);
+  // the staging still holds the q_0 scales until a synchronisation has passed
+  if (!synced && hipStreamSynchronize(s) != hipSuccess) return BIRK_ERR_DEVICE;
+  double* coef = stage_coef(p);
+  std::fill(coef, coef + (size_t)B * kDotsStride, 0.0);
   for (int i = 0; i < B; ++i) {
     if (!active[i]) continue;
     const int k = jend[i];
@@ -581,10 +600,10 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, const double* r, 
     }
     for (int a = 0; a < k; ++a) coef[(size_t)i * kDotsStride + a] = yv[a] * st[i].rnorm;
   }
-  std::vector<int> cnt(B, 0);
+  int* cnt = stage_cnt(p);
   for (int i = 0; i < B; ++i) cnt[i] = active[i] ? jend[i] : 0;
-  e = hipMemcpyAsync(p->krylov_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(p->krylov_cnt, cnt.data(), B * sizeof(int), hipMemcpyHostToDevice, s);
+  e = hipMemcpyAsync(p->krylov_coef, coef, (size_t)B * kDotsStride * sizeof(double) + B * sizeof(int),
+                     hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return BIRK_ERR_DEVICE;
   // chi += ||r|| P^{-1} Q y = ||r|| Z y (Z = Q without preconditioning)
   const TK* basis = use_precond ? Z : Q;

@@ -186,8 +186,10 @@ struct birk_plan {
   void* krylov_vec = nullptr; // 4 vectors of the Krylov precision
   double* krylov_dots = nullptr;  // [batch][2][kKryMaxDots + 1]
   double* krylov_part = nullptr;  // reduction partials [tiles][kKryMaxDots + 1]
-  double* krylov_coef = nullptr;  // per instance: scale factors / combination coefficients
+  double* krylov_coef = nullptr;  // per instance: scale factors / combination coefficients,
+                                  // followed by the counts krylov_cnt (one upload for both)
   int* krylov_cnt = nullptr;      // per instance: number of combined basis vectors
+  void* krylov_stage = nullptr;   // pinned host staging: dots, singular flag, coefficients + counts
   int* flag = nullptr;            // device flag: singular pivot seen
   int use_fast = 1;               // power-of-two N takes the three-pass path
   birk::FastKnobs fast_kn;        // default tile schedule of the three-pass groups
