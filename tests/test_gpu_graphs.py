@@ -65,3 +65,27 @@ def test_graphs_need_a_stream(B):
     with pytest.raises(B.BirkError):
         B.birk_plan_set_graphs(plan)
     plan.destroy()
+
+
+def test_graph_replays_double_float(B):
+    """Graph mode with a double-float plan (Bluestein and three-pass groups together)."""
+    import torch
+    from tests.gpu_util import to_df32
+    Nn, nx = [(1 << 12) + 1, 3000], [2, 2]
+    side = torch.cuda.Stream()
+    n = sum(a * b for a, b in zip(Nn, nx))
+    X = wl.random_vectors([23, 0], (n,))[0]
+    v = torch.from_numpy(to_df32(X[None, :])[0]).to("cuda")
+    eager = B.birk_plan_create(Nn, nx, B.BIRK_DF32, side)
+    graph = B.birk_plan_create(Nn, nx, B.BIRK_DF32, side)
+    B.birk_plan_set_graphs(graph)
+    with torch.cuda.stream(side):
+        out = torch.empty_like(v)
+        ref = torch.empty_like(v)
+        for call in range(4):
+            B.birk_apply(graph, v, out)
+            B.birk_apply(eager, v, ref)
+            side.synchronize()
+            assert torch.equal(out, ref), f"call {call}"
+    eager.destroy()
+    graph.destroy()

@@ -201,6 +201,30 @@ def test_autotuned_schedule_keeps_results(B, Nn, prec):
         assert rel_err(after[t], before[t]) <= (1e-13 if prec == "f64" else 1e-5)
 
 
+def test_autotune_double_float_plan(B):
+    """The tuner times the double-float kernels of a DF32 plan and keeps 1e-13 parity."""
+    import torch
+    from tests.gpu_util import from_df32, to_df32
+    Nn, nx = (1 << 15) + 1, 2
+    N = Nn - 1
+    rows, refs = [], []
+    for c in range(nx):
+        modes, alphas = wl.sparse_modes([13, c, Nn], N, count=32)
+        rows.append(bk.sparse_mode_values(N, modes, alphas))
+        refs.append(bk.sparse_mode_exact(N, modes, alphas))
+    X = np.stack(rows).ravel()
+    plan = B.birk_plan_create([Nn], [nx], B.BIRK_DF32)
+    report = B.birk_plan_tune(plan)
+    assert "chosen" in report
+    v = torch.from_numpy(to_df32(X[None, :])[0]).to("cuda")
+    out = torch.empty_like(v)
+    B.birk_apply(plan, v, out)
+    torch.cuda.synchronize()
+    got = from_df32(host(out)[None, :])[0]
+    plan.destroy()
+    assert rel_err(got.reshape(nx, Nn), np.stack(refs)) <= 1e-13
+
+
 def test_autotune_without_power_of_two_groups(B):
     plan = B.birk_plan_create([1000], [3], B.BIRK_F64)
     assert "no power-of-two groups" in B.birk_plan_tune(plan)
