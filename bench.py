@@ -72,6 +72,11 @@ def calibrate_copy():
     print(json.dumps({"calibrate_copy_bytes_each": n * 8, "copies": 3}), flush=True)
 
 
+def traffic_key(split, tb, xcd):
+    from paper_2509_01855_amd.traffic import schedule_key
+    return schedule_key(split, tb, xcd)
+
+
 def traffic_record(kernel_sources, schedule=None):
     """Measured HBM bytes per product from profiles/, if the kernels are unchanged since and
     the product runs the tile schedule the counters were taken with."""
@@ -242,7 +247,7 @@ def main():
 
     # autotuner of the power-of-two product path (plan setup, outside the timed region)
     tuned = {}
-    head_sched = {"split": 0, "tb": 0, "xcd": 1}  # defaults unless the tuner picks another
+    head_sched = traffic_key(0, 0, 1)  # defaults unless the tuner picks another
     if not a.no_tune:
         print("[bench] autotuning the power-of-two plans", file=sys.stderr, flush=True)
         tplans = {"headline_f64": plan64, "headline_f32": planmx}
@@ -254,8 +259,8 @@ def main():
             tuned[name] = [ln.split(" chosen ")[0].split(":")[0] + ": " + ln.split(" chosen ")[1]
                            for ln in rep.splitlines() if " chosen " in ln]
             if name == "headline_f64":
-                m = re.search(r"chosen \[split (\d+), tb (\d+), xcd (\d+)\]", rep)
-                head_sched = {"split": int(m.group(1)), "tb": int(m.group(2)), "xcd": int(m.group(3))}
+                m = re.search(r"chosen \[split (\d+), tb (\d+), xcd (\d+), streams \d+\]", rep)
+                head_sched = traffic_key(int(m.group(1)), int(m.group(2)), int(m.group(3)))
         torch.cuda.synchronize()
 
     def step(timed: bool):

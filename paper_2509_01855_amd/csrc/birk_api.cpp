@@ -64,6 +64,9 @@ static void drop_graphs(birk_plan* p) {
 void free_plan(birk_plan* p) {
   if (!p) return;
   drop_graphs(p);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  if (p->stream2) (void)hipStreamDestroy(p->stream2);
   for (auto& in : p->inst)
     if (in.w) (void)hipFree(in.w);
   for (void* q : p->allocs) if (q) (void)hipFree(q);
@@ -185,6 +188,8 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     if (xc) p->fast_kn.xcd = std::atoi(xc) ? 1 : 0;
     const char* b2 = std::getenv("BIRK_FAST_B2");
     if (b2) p->fast_kn.b2 = std::atoi(b2) ? 1 : 0;
+    const char* st = std::getenv("BIRK_FAST_STREAMS");
+    if (st) p->fast_kn.streams = std::atoi(st) >= 2 ? 2 : 1;
   }
   p->inst.resize(batch);
   int64_t off = 0, joff = 0, jcoff = 0, soff = 0, jswoff = 0;
@@ -220,6 +225,10 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
   if (e == hipSuccess) e = hipMalloc(&p->scan, std::max<int64_t>(soff, 1) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&p->jsw, std::max<int64_t>(jswoff, 1) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&p->flag, sizeof(int));
+  // second stream (default priority) for the two-stream schedule of the three-pass groups
+  if (e == hipSuccess && !p->fgroups.empty()) e = hipStreamCreateWithFlags(&p->stream2, hipStreamNonBlocking);
+  if (e == hipSuccess && p->stream2) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess && p->stream2) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
   for (int i = 0; i < batch && e == hipSuccess; ++i) e = hipMalloc(&p->inst[i].w, p->inst[i].Nn * sizeof(double));
   if (e == hipSuccess) e = build_tables(p);
   // CC weights: w = B^aT e_N (the last row of B^a), instance by instance on component 0

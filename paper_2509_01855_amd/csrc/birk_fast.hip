@@ -982,8 +982,9 @@ static void launch_B(int xcd, int nt, int nc, int thr, int lds, hipStream_t s, c
                      tlo, tsh, part, nt, nc, xcd);
 }
 
+// The three passes for the components of g (a whole group or a contiguous part of one).
 template <typename T>
-hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, int transpose, hipStream_t s) {
+static hipError_t fast_passes(birk_plan* p, const FastGroup& g, const T* v, T* out, int transpose, hipStream_t s) {
   constexpr int pi = prec_index<T>();
   int logL1, logL2, WA, TB, WC;
   const FastKnobs& kn = g.kn;
@@ -1105,19 +1106,48 @@ hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, in
 }
 
 // Tile schedules the autotuner tries for a group: the defaults first, then both splits of
-// 2N = L1 L2, two or four rows per pass-B tile and both tile orders.
+// 2N = L1 L2, two or four rows per pass-B tile, both tile orders, one or two streams.
 static std::vector<FastKnobs> tune_candidates(const FastKnobs& base) {
   std::vector<FastKnobs> c{base};
   for (int split = 0; split < 2; ++split)
     for (int tb = 2; tb <= 4; tb += 2)
-      for (int xcd = 0; xcd < 2; ++xcd) {
-        FastKnobs k = base;
-        k.split = split;
-        k.tb = tb;
-        k.xcd = xcd;
-        if (k.split != base.split || k.tb != base.tb || k.xcd != base.xcd) c.push_back(k);
-      }
+      for (int xcd = 0; xcd < 2; ++xcd)
+        for (int st = 1; st <= 2; ++st) {
+          FastKnobs k = base;
+          k.split = split;
+          k.tb = tb;
+          k.xcd = xcd;
+          k.streams = st;
+          if (k.split != base.split || k.tb != base.tb || k.xcd != base.xcd || k.streams != base.streams)
+            c.push_back(k);
+        }
   return c;
+}
+
+// A group's product.  With kn.streams = 2 the components are split into two halves, the
+// second on the plan's second stream (fork and join by events on the caller's stream), so
+// that when one half's pass runs out of tiles the other's keeps the CUs busy.  Each
+// component's kernels, tiles and partial sums are those of the one-stream schedule.
+template <typename T>
+hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, int transpose, hipStream_t s) {
+  if (g.kn.streams < 2 || g.nc < 2 || !p->stream2) return fast_passes<T>(p, g, v, out, transpose, s);
+  int logL1, logL2, WA, TB, WC;
+  fast_shape<T>(g.kn, g.N, logL1, logL2, WA, TB, WC);
+  const int64_t gcomp = (int64_t)((1 << logL1) / 2 + 1) * ((1 << logL2) / 2 + 1);
+  const int64_t ntB = fast_tiles_b<T>(g.kn, g.N);
+  FastGroup a = g, b = g;
+  a.nc = g.nc / 2;
+  b.nc = g.nc - a.nc;
+  b.off = g.off + (int64_t)a.nc * g.Nn;
+  b.work_off = g.work_off + (int64_t)a.nc * gcomp;
+  b.part_off = g.part_off + (int64_t)a.nc * ntB;
+  hipError_t e = hipEventRecord(p->ev_fork, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(p->stream2, p->ev_fork, 0);
+  if (e == hipSuccess) e = fast_passes<T>(p, b, v, out, transpose, p->stream2);
+  if (e == hipSuccess) e = fast_passes<T>(p, a, v, out, transpose, s);
+  if (e == hipSuccess) e = hipEventRecord(p->ev_join, p->stream2);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join, 0);
+  return e;
 }
 
 // Work (complex elements per buffer) and partials (doubles) of the fast path for nc
@@ -1179,13 +1209,14 @@ static hipError_t tune_groups(birk_plan* p, hipStream_t s, std::string* report) 
     *report += line;
     size_t best = 0;
     for (size_t ci = 0; ci < cand.size(); ++ci) {
-      snprintf(line, sizeof line, " [split %d, tb %d, xcd %d] %.1f us;", cand[ci].split, cand[ci].tb, cand[ci].xcd,
-               1000.0 * best_of[ci]);
+      snprintf(line, sizeof line, " [split %d, tb %d, xcd %d, streams %d] %.1f us;", cand[ci].split, cand[ci].tb,
+               cand[ci].xcd, cand[ci].streams, 1000.0 * best_of[ci]);
       *report += line;
       if (best_of[ci] < best_of[best] * (1.0f - kTuneMargin)) best = ci;
     }
     g.kn = cand[best];
-    snprintf(line, sizeof line, " chosen [split %d, tb %d, xcd %d]\n", g.kn.split, g.kn.tb, g.kn.xcd);
+    snprintf(line, sizeof line, " chosen [split %d, tb %d, xcd %d, streams %d]\n", g.kn.split, g.kn.tb, g.kn.xcd,
+             g.kn.streams);
     *report += line;
   }
   if (e0) (void)hipEventDestroy(e0);

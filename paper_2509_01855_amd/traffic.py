@@ -27,11 +27,18 @@ SOURCES = ["paper_2509_01855_amd/csrc/birk_fast.hip", "paper_2509_01855_amd/csrc
            "paper_2509_01855_amd/csrc/birk_fft.h"]
 
 
+def schedule_key(split, tb, xcd):
+    """What fixes the kernels of the double product at N = 2^20: the split of 2N = L1 L2,
+    the rows per pass-B tile of the register kernel (4 when asked for, else 2) and the
+    tile order.  (The one- or two-stream schedule runs the same kernels.)"""
+    return {"split": 1 if split else 0, "rows_b": 4 if tb == 4 else 2, "xcd": 1 if xcd else 0}
+
+
 def _schedule():
     """Tile schedule of the counter runs (bench.py --no-tune with the environment defaults)."""
-    return {"split": int(os.environ.get("BIRK_FAST_SPLIT", "0")) and 1,
-            "tb": max(0, min(14, int(os.environ.get("BIRK_FAST_TB", "0")))) & ~1,
-            "xcd": int(os.environ.get("BIRK_FAST_XCD", "1")) and 1}
+    return schedule_key(int(os.environ.get("BIRK_FAST_SPLIT", "0")),
+                        max(0, min(14, int(os.environ.get("BIRK_FAST_TB", "0")))) & ~1,
+                        int(os.environ.get("BIRK_FAST_XCD", "1")))
 import re
 
 # forward double product: pass A, pass B (TRANS = 0), pass C (TRANS = 0); the

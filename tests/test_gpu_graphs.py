@@ -89,3 +89,28 @@ def test_graph_replays_double_float(B):
             assert torch.equal(out, ref), f"call {call}"
     eager.destroy()
     graph.destroy()
+
+
+def test_graph_replays_two_stream_schedule(B, monkeypatch):
+    """A recorded product whose three-pass group forks onto the plan's second stream."""
+    import torch
+    monkeypatch.setenv("BIRK_FAST_STREAMS", "2")
+    Nn, nx = [(1 << 16) + 1], [4]
+    side = torch.cuda.Stream()
+    n = Nn[0] * nx[0]
+    xs = [torch.from_numpy(wl.random_vectors([29, k], (n,))[0]).to("cuda") for k in range(3)]
+    eager = B.birk_plan_create(Nn, nx, B.BIRK_F64, side)
+    graph = B.birk_plan_create(Nn, nx, B.BIRK_F64, side)
+    B.birk_plan_set_graphs(graph)
+    with torch.cuda.stream(side):
+        v = torch.empty(n, dtype=torch.float64, device="cuda")
+        out = torch.empty_like(v)
+        ref = torch.empty_like(v)
+        for call in range(5):
+            v.copy_(xs[call % 3])
+            B.birk_apply(graph, v, out)
+            B.birk_apply(eager, v, ref)
+            side.synchronize()
+            assert torch.equal(out, ref), f"call {call}"
+    eager.destroy()
+    graph.destroy()

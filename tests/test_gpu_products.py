@@ -188,7 +188,7 @@ def test_autotuned_schedule_keeps_results(B, Nn, prec):
         before.append(host(out).astype(np.float64))
     report = B.birk_plan_tune(plan)
     print(report, flush=True)
-    assert "chosen" in report and report.count("us;") == 9
+    assert "chosen" in report and report.count("us;") == 17
     after = []
     for t in (0, 1):
         out = torch.empty_like(v)
@@ -199,6 +199,34 @@ def test_autotuned_schedule_keeps_results(B, Nn, prec):
     assert rel_err(after[0].reshape(nx, Nn), np.stack(refs)) <= TOL[prec]
     for t in (0, 1):
         assert rel_err(after[t], before[t]) <= (1e-13 if prec == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["f64", "df32"])
+def test_two_stream_schedule_is_bit_identical(B, prec, monkeypatch):
+    """BIRK_FAST_STREAMS=2 runs the two halves of a group's components on two streams;
+    every component's kernels and sums are unchanged, so the products are bit for bit
+    those of the one-stream schedule."""
+    import torch
+    from tests.gpu_util import to_df32
+    Nn, nx = (1 << 16) + 1, 5
+    X = wl.random_vectors([17, Nn], (nx * Nn,))[0]
+    if prec == "f64":
+        v = dev(X, torch.float64)
+        p = B.BIRK_F64
+    else:
+        v = torch.from_numpy(to_df32(X[None, :])[0]).to("cuda")
+        p = B.BIRK_DF32
+    outs = []
+    for st in ("1", "2"):
+        monkeypatch.setenv("BIRK_FAST_STREAMS", st)
+        plan = B.birk_plan_create([Nn], [nx], p)
+        for t in (0, 1):
+            out = torch.empty_like(v)
+            (B.birk_apply_T if t else B.birk_apply)(plan, v, out)
+            torch.cuda.synchronize()
+            outs.append(host(out))
+        plan.destroy()
+    assert np.array_equal(outs[0], outs[2]) and np.array_equal(outs[1], outs[3])
 
 
 def test_autotune_double_float_plan(B):
