@@ -106,8 +106,8 @@ int64_t birk_plan_length(const birk_plan* plan);
  * same-length components it times B^a (FastBV box) in the plan's precision over a
  * fixed set of tile schedules: both splits 2N = L1 L2 of the two-step DCTs, two or four
  * rows per middle-pass tile, the plain or XCD-grouped tile order, and the components on
- * one stream or in two halves on two streams (forked from and joined back into the
- * plan's stream by events; same kernels per component).  In each of two
+ * one stream or in two or three parts on as many streams (forked from and joined back
+ * into the plan's stream by events; same kernels per component).  In each of two
  * interleaved rounds a candidate runs once to warm up, then four times between events on
  * the plan's stream, alternating two input/output pairs; its best round counts.  The
  * default schedule stays unless a candidate is more than 2 % faster; the choice stays

@@ -65,8 +65,10 @@ void free_plan(birk_plan* p) {
   if (!p) return;
   drop_graphs(p);
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
-  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
-  if (p->stream2) (void)hipStreamDestroy(p->stream2);
+  for (int k = 0; k < birk_plan::kExtraStreams; ++k) {
+    if (p->ev_join[k]) (void)hipEventDestroy(p->ev_join[k]);
+    if (p->xstream[k]) (void)hipStreamDestroy(p->xstream[k]);
+  }
   for (auto& in : p->inst)
     if (in.w) (void)hipFree(in.w);
   for (void* q : p->allocs) if (q) (void)hipFree(q);
@@ -189,7 +191,7 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     const char* b2 = std::getenv("BIRK_FAST_B2");
     if (b2) p->fast_kn.b2 = std::atoi(b2) ? 1 : 0;
     const char* st = std::getenv("BIRK_FAST_STREAMS");
-    if (st) p->fast_kn.streams = std::atoi(st) >= 2 ? 2 : 1;
+    if (st) p->fast_kn.streams = std::max(1, std::min(1 + birk_plan::kExtraStreams, std::atoi(st)));
   }
   p->inst.resize(batch);
   int64_t off = 0, joff = 0, jcoff = 0, soff = 0, jswoff = 0;
@@ -225,10 +227,14 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
   if (e == hipSuccess) e = hipMalloc(&p->scan, std::max<int64_t>(soff, 1) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&p->jsw, std::max<int64_t>(jswoff, 1) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&p->flag, sizeof(int));
-  // second stream (default priority) for the two-stream schedule of the three-pass groups
-  if (e == hipSuccess && !p->fgroups.empty()) e = hipStreamCreateWithFlags(&p->stream2, hipStreamNonBlocking);
-  if (e == hipSuccess && p->stream2) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
-  if (e == hipSuccess && p->stream2) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+  // extra streams (default priority) for the multi-stream schedule of the three-pass groups
+  if (e == hipSuccess && !p->fgroups.empty()) {
+    e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+    for (int k = 0; k < birk_plan::kExtraStreams && e == hipSuccess; ++k) {
+      e = hipStreamCreateWithFlags(&p->xstream[k], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join[k], hipEventDisableTiming);
+    }
+  }
   for (int i = 0; i < batch && e == hipSuccess; ++i) e = hipMalloc(&p->inst[i].w, p->inst[i].Nn * sizeof(double));
   if (e == hipSuccess) e = build_tables(p);
   // CC weights: w = B^aT e_N (the last row of B^a), instance by instance on component 0

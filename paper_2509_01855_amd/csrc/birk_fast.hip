@@ -1112,7 +1112,7 @@ static std::vector<FastKnobs> tune_candidates(const FastKnobs& base) {
   for (int split = 0; split < 2; ++split)
     for (int tb = 2; tb <= 4; tb += 2)
       for (int xcd = 0; xcd < 2; ++xcd)
-        for (int st = 1; st <= 2; ++st) {
+        for (int st = 1; st <= 3; ++st) {
           FastKnobs k = base;
           k.split = split;
           k.tb = tb;
@@ -1124,29 +1124,39 @@ static std::vector<FastKnobs> tune_candidates(const FastKnobs& base) {
   return c;
 }
 
-// A group's product.  With kn.streams = 2 the components are split into two halves, the
-// second on the plan's second stream (fork and join by events on the caller's stream), so
-// that when one half's pass runs out of tiles the other's keeps the CUs busy.  Each
-// component's kernels, tiles and partial sums are those of the one-stream schedule.
+// A group's product.  With kn.streams = S > 1 the components are split into S contiguous
+// parts, part k > 0 on the plan's extra stream k - 1 (forked from and joined back into the
+// caller's stream by events), so that when one part's pass runs out of tiles another's
+// keeps the CUs busy.  Each component's kernels, tiles and partial sums are those of the
+// one-stream schedule.
 template <typename T>
 hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, int transpose, hipStream_t s) {
-  if (g.kn.streams < 2 || g.nc < 2 || !p->stream2) return fast_passes<T>(p, g, v, out, transpose, s);
+  const int S = std::min(std::min(g.kn.streams, g.nc), 1 + birk_plan::kExtraStreams);
+  if (S < 2 || !p->xstream[0]) return fast_passes<T>(p, g, v, out, transpose, s);
   int logL1, logL2, WA, TB, WC;
   fast_shape<T>(g.kn, g.N, logL1, logL2, WA, TB, WC);
   const int64_t gcomp = (int64_t)((1 << logL1) / 2 + 1) * ((1 << logL2) / 2 + 1);
   const int64_t ntB = fast_tiles_b<T>(g.kn, g.N);
-  FastGroup a = g, b = g;
-  a.nc = g.nc / 2;
-  b.nc = g.nc - a.nc;
-  b.off = g.off + (int64_t)a.nc * g.Nn;
-  b.work_off = g.work_off + (int64_t)a.nc * gcomp;
-  b.part_off = g.part_off + (int64_t)a.nc * ntB;
   hipError_t e = hipEventRecord(p->ev_fork, s);
-  if (e == hipSuccess) e = hipStreamWaitEvent(p->stream2, p->ev_fork, 0);
-  if (e == hipSuccess) e = fast_passes<T>(p, b, v, out, transpose, p->stream2);
-  if (e == hipSuccess) e = fast_passes<T>(p, a, v, out, transpose, s);
-  if (e == hipSuccess) e = hipEventRecord(p->ev_join, p->stream2);
-  if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join, 0);
+  int c0 = 0;
+  for (int k = 0; k < S && e == hipSuccess; ++k) {
+    const int c1 = (int)((int64_t)g.nc * (k + 1) / S);
+    FastGroup part = g;
+    part.nc = c1 - c0;
+    part.off = g.off + (int64_t)c0 * g.Nn;
+    part.work_off = g.work_off + (int64_t)c0 * gcomp;
+    part.part_off = g.part_off + (int64_t)c0 * ntB;
+    if (k == 0) {
+      e = fast_passes<T>(p, part, v, out, transpose, s);
+    } else {
+      hipStream_t x = p->xstream[k - 1];
+      e = hipStreamWaitEvent(x, p->ev_fork, 0);
+      if (e == hipSuccess) e = fast_passes<T>(p, part, v, out, transpose, x);
+      if (e == hipSuccess) e = hipEventRecord(p->ev_join[k - 1], x);
+    }
+    c0 = c1;
+  }
+  for (int k = 1; k < S && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, p->ev_join[k - 1], 0);
   return e;
 }
 

@@ -63,8 +63,8 @@ struct FastKnobs {
   int b_threads = 512;        // workgroup size cap of the runtime-length pass B
   int xcd = 1;                // XCD-aware tile order
   int b2 = 1;                 // compile-time-length kernels where they apply
-  int streams = 1;            // 2: the components run in two halves on two streams, so that
-                              // one half's next pass fills the other's tail
+  int streams = 1;            // 2 or 3: the components run in that many parts on as many
+                              // streams, so that one part's next pass fills another's tail
 };
 
 struct FastGroup {
@@ -206,9 +206,11 @@ struct birk_plan {
   int use_graphs = 0;
   std::vector<GraphSlot> graphs;
   uint64_t graph_clock = 0;
-  // second stream and fork / join events of the two-stream three-pass schedule
-  hipStream_t stream2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // extra streams and their fork / join events of the multi-stream three-pass schedule
+  static constexpr int kExtraStreams = 2;
+  hipStream_t xstream[kExtraStreams] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kExtraStreams] = {nullptr, nullptr};
 };
 
 namespace birk {

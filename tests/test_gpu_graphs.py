@@ -92,9 +92,9 @@ def test_graph_replays_double_float(B):
 
 
 def test_graph_replays_two_stream_schedule(B, monkeypatch):
-    """A recorded product whose three-pass group forks onto the plan's second stream."""
+    """A recorded product whose three-pass group forks onto the plan's extra streams."""
     import torch
-    monkeypatch.setenv("BIRK_FAST_STREAMS", "2")
+    monkeypatch.setenv("BIRK_FAST_STREAMS", "3")
     Nn, nx = [(1 << 16) + 1], [4]
     side = torch.cuda.Stream()
     n = Nn[0] * nx[0]

@@ -188,7 +188,7 @@ def test_autotuned_schedule_keeps_results(B, Nn, prec):
         before.append(host(out).astype(np.float64))
     report = B.birk_plan_tune(plan)
     print(report, flush=True)
-    assert "chosen" in report and report.count("us;") == 17
+    assert "chosen" in report and report.count("us;") == 25
     after = []
     for t in (0, 1):
         out = torch.empty_like(v)
@@ -202,10 +202,10 @@ def test_autotuned_schedule_keeps_results(B, Nn, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "df32"])
-def test_two_stream_schedule_is_bit_identical(B, prec, monkeypatch):
-    """BIRK_FAST_STREAMS=2 runs the two halves of a group's components on two streams;
-    every component's kernels and sums are unchanged, so the products are bit for bit
-    those of the one-stream schedule."""
+def test_multi_stream_schedule_is_bit_identical(B, prec, monkeypatch):
+    """BIRK_FAST_STREAMS=2 or 3 runs a group's components in that many parts on as many
+    streams; every component's kernels and sums are unchanged, so the products are bit for
+    bit those of the one-stream schedule."""
     import torch
     from tests.gpu_util import to_df32
     Nn, nx = (1 << 16) + 1, 5
@@ -217,7 +217,7 @@ def test_two_stream_schedule_is_bit_identical(B, prec, monkeypatch):
         v = torch.from_numpy(to_df32(X[None, :])[0]).to("cuda")
         p = B.BIRK_DF32
     outs = []
-    for st in ("1", "2"):
+    for st in ("1", "2", "3"):
         monkeypatch.setenv("BIRK_FAST_STREAMS", st)
         plan = B.birk_plan_create([Nn], [nx], p)
         for t in (0, 1):
@@ -226,7 +226,8 @@ def test_two_stream_schedule_is_bit_identical(B, prec, monkeypatch):
             torch.cuda.synchronize()
             outs.append(host(out))
         plan.destroy()
-    assert np.array_equal(outs[0], outs[2]) and np.array_equal(outs[1], outs[3])
+    for k in (2, 4):
+        assert np.array_equal(outs[0], outs[k]) and np.array_equal(outs[1], outs[k + 1])
 
 
 def test_autotune_double_float_plan(B):
