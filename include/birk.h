@@ -21,8 +21,11 @@
  * ---------------------------------------
  * Plan.     A plan fixes a batch of independent instances i = 0..batch-1, each with its
  *           own node count N_n[i] >= 3 and state count n_x[i] >= 1, the storage
- *           precision, and a HIP stream.  It owns every scratch buffer (allocated at
- *           creation); the product and preconditioner calls allocate nothing.
+ *           precision, and a HIP stream.  It owns every scratch buffer: those of the
+ *           products and the preconditioner are allocated at creation (those calls
+ *           allocate nothing); the Krylov workspace (3 restart + 1 vectors in double
+ *           plans, 2 restart + 1 in mixed ones, plus a small pinned host staging
+ *           buffer) on the first birk_krylov_solve that needs it, kept for later solves.
  * Layout.   Component-major and contiguous: instance i, component r, node k lives at
  *           offset(i) + r * N_n[i] + k, where offset(i) is the prefix sum of
  *           n_x * N_n over earlier instances.  Per-node Jacobians are stored
@@ -59,7 +62,7 @@ typedef enum {
   BIRK_ERR_ARG = -1,         /* null pointer, bad enum, inconsistent arguments          */
   BIRK_ERR_SIZE = -2,        /* batch < 1, N_n < 3, n_x < 1, or a size beyond limits    */
   BIRK_ERR_DEVICE = -3,      /* a HIP runtime call failed                               */
-  BIRK_ERR_NOMEM = -4,       /* device allocation failed at plan creation               */
+  BIRK_ERR_NOMEM = -4,       /* allocation failed (plan creation, first Krylov solve)   */
   BIRK_ERR_SINGULAR = -5,    /* I - w_k J_k / 2 is singular at some node                */
   BIRK_ERR_NOCONV = -6,      /* the solve hit max_iter before rtol                      */
   BIRK_ERR_BREAKDOWN = -7,   /* Krylov breakdown without convergence                    */
@@ -200,9 +203,10 @@ typedef struct {
  * chi holds x0 on entry when opts->use_x0, and the best iterate on return, also when
  * the status is an error.  opts may be NULL (defaults); info may be NULL.
  * Returns BIRK_OK when every instance converged, else the first failing instance's
- * status.  Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED (MINRES, BIRK_F32 or BIRK_DF32
- * plans, n_x > 12), BIRK_ERR_SINGULAR, BIRK_ERR_NOCONV, BIRK_ERR_BREAKDOWN,
- * BIRK_ERR_NONFINITE, BIRK_ERR_DEVICE. */
+ * status.  The first call (or one with a larger restart) allocates the Krylov workspace
+ * (see Plan).  Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED (MINRES, BIRK_F32 or BIRK_DF32
+ * plans, n_x > 12), BIRK_ERR_NOMEM, BIRK_ERR_SINGULAR, BIRK_ERR_NOCONV,
+ * BIRK_ERR_BREAKDOWN, BIRK_ERR_NONFINITE, BIRK_ERR_DEVICE. */
 birk_status birk_krylov_solve(birk_plan* plan, birk_jac_kind jac_kind, const double* J,
                               const double* beta, double* chi, const birk_solve_opts* opts,
                               birk_solve_info* info);
