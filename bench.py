@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip birk_plan_tune (default tile schedules)")
     ap.add_argument("--products-only", action="store_true", help="skip the solves (for profiling runs)")
     ap.add_argument("--headline-only", action="store_true", help="skip the batched and many-RHS workloads")
-    ap.add_argument("--cpu-sample", type=int, default=200, help="rows of B^a the oracle computes")
+    ap.add_argument("--cpu-sample", type=int, default=400, help="rows of B^a the oracle computes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -144,6 +144,33 @@ class Timer:
     def mean_ms(self, name):
         xs = self.rec.get(name, [])
         return float(sum(xs) / len(xs)) if xs else float("nan")
+
+    def median_ms(self, name):
+        xs = sorted(self.rec.get(name, []))
+        return float(xs[len(xs) // 2]) if xs else float("nan")
+
+    def min_ms(self, name):
+        xs = self.rec.get(name, [])
+        return float(min(xs)) if xs else float("nan")
+
+
+def copy_ceiling_gbs(torch, stream, reps=5):
+    """Measured HBM ceiling: a 1 GiB device-to-device copy (read + write counted), best of
+    `reps`, timed with events on the bench stream."""
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dst.copy_(src)
+        e1.record(stream)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    return round(2.0 * n * 8 / best / 1e9, 1)
 
 
 def graph_replay_timing(B, torch, reps=200):
@@ -330,12 +357,16 @@ def main():
         "autotune": tuned if tuned else None,
         "secondary": {
             "apply_f64_us": us("apply"),
+            "apply_f64_us_median": round(tm.median_ms("apply") * 1e3, 2),
+            "apply_f64_us_min": round(tm.min_ms("apply") * 1e3, 2),
             "apply_T_f64_us": us("apply_T"),
             "apply_f32_us": us("apply_f32"),
             "apply_f32_gpts": round(n / (tm.mean_ms("apply_f32") * 1e-3) / 1e9, 3),
             "precond_inverse_f64_us": us("pinv"),
         },
     }
+    out["roofline"]["measured_copy_GBs"] = copy_ceiling_gbs(torch, stream)
+    out["roofline"]["frac_of_copy"] = round(achieved / out["roofline"]["measured_copy_GBs"], 4)
     tr = traffic_record(KERNEL_SOURCES, head_sched)
     if tr is not None:
         out["roofline"]["traffic"] = tr["bytes_per_product"]
