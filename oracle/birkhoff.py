@@ -14,6 +14,9 @@ Optimization Solver"):
 * App. B, eq:ak=3      modal coefficients from nodal values (discrete orthogonality).
 * Sec. "Development of a Special Birkhoff-Centric Preconditioner"
                        last row of B^a = CC weights; the lower-triangular B~^a.
+* eq:xN=Birka+b        the b-form: B_j^b(+1) = 0 with the same derivative conditions,
+                       so B_j^b = B_j^a - B_j^a(+1) and B^b = B^a - 1 w_B^T.
+* eq:Prob-PNa          the endpoint row x^b = x^a + w_B^T V.
 """
 
 from __future__ import annotations
@@ -41,6 +44,11 @@ __all__ = [
     "sparse_mode_exact",
     "sparse_mode_values",
     "apply_Ba_extended",
+    "dense_Bb_quadrature",
+    "dense_Bb",
+    "sparse_mode_exact_b",
+    "apply_Bb_extended",
+    "endpoint_b",
 ]
 
 
@@ -285,12 +293,16 @@ def apply_Ba_extended(N: int, X: np.ndarray, transpose: bool = False) -> np.ndar
     the product reference where the double-precision dense matrix is itself only good
     to ~1e-12 relative (N in the thousands).  Cost O(N^2) per row plus O(N^2) set-up.
     """
+    return _apply_Ba_ld(N, X, transpose).astype(np.float64)
+
+
+def _apply_Ba_ld(N: int, X: np.ndarray, transpose: bool) -> np.ndarray:
     ld = np.longdouble
     X = np.atleast_2d(np.asarray(X, dtype=np.float64)).astype(ld)
     Tinv, Int = _extended_factors(N)
     if transpose:
-        return ((X @ Int) @ Tinv).astype(np.float64)
-    return ((X @ Tinv.T) @ Int.T).astype(np.float64)
+        return (X @ Int) @ Tinv
+    return (X @ Tinv.T) @ Int.T
 
 
 @functools.lru_cache(maxsize=1)
@@ -315,3 +327,63 @@ def _extended_factors(N: int):
                   - Tm[:, 1:N] / (ld(2) * (kk - 1).astype(ld))
                   - sgn / (kk.astype(ld) ** 2 - ld(1)))
     return Tinv, Int
+
+
+# ------------------------------------------------------------------------ b-form
+def dense_Bb_quadrature(N: int) -> np.ndarray:
+    """B^b from its own conditions (eq:xN=Birka+b, eq:birk-conditions with the anchor at
+    tau = +1): B_j^b(1) = 0 and dB_j^b/dtau(tau_i) = delta_ij, so
+    [B^b]_ij = -integral_{tau_i}^{1} l_j.
+
+    Gauss-Legendre quadrature with N//2 + 2 points on [tau_i, 1], exact for the
+    degree-N integrand; independent of B^a and of the CC weights.  Cost O(N^3).
+    """
+    tau = cgl_nodes(N)
+    nq = N // 2 + 2
+    t, wq = np.polynomial.legendre.leggauss(nq)
+    B = np.zeros((N + 1, N + 1))
+    for i in range(N):
+        half = 0.5 * (1.0 - tau[i])
+        x = tau[i] + half * (t + 1.0)
+        B[i] = -half * (wq @ lagrange_basis(N, x))
+    return B
+
+
+def dense_Bb(N: int) -> np.ndarray:
+    """Dense B^b = B^a - 1 w_B^T: B_j^b and B_j^a share their derivative at the nodes
+    and B_j^b vanishes at +1, so B_j^b = B_j^a - B_j^a(1), and B_j^a(1) = (w_B)_j."""
+    return dense_Ba(N) - np.outer(np.ones(N + 1), weights(N))
+
+
+def sparse_mode_exact_b(N: int, modes, alphas) -> np.ndarray:
+    """Exact B^b v for v = sum_s alpha_s T_{k_s} (k_s <= N): the antiderivative of the
+    series anchored at +1, integral_{1}^{tau_j} v = I(tau_j) - I(1) with I from
+    eq:intChebPoly= (tau_N = 1).  Cost O(len(modes) * N)."""
+    full = sparse_mode_exact(N, modes, alphas)
+    return full - full[N]
+
+
+def apply_Bb_extended(N: int, X: np.ndarray, transpose: bool = False) -> np.ndarray:
+    """Rows of X times B^b^T (transpose=False: x -> B^b x) or times B^b (transpose=True:
+    x -> B^bT x) in x87 extended precision.
+
+    B^b x = B^a x - 1 (w_B^T x), and w_B^T x is the last entry of B^a x;
+    B^bT g = B^aT g - w_B (1^T g), with w_B = B^aT e_N.  Both from the extended
+    factors of apply_Ba_extended, rounded to double once at the end.
+    """
+    ld = np.longdouble
+    Y = _apply_Ba_ld(N, X, transpose)
+    if not transpose:
+        return (Y - Y[:, N:N + 1]).astype(np.float64)
+    e_N = np.zeros((1, N + 1))
+    e_N[0, N] = 1.0
+    w = _apply_Ba_ld(N, e_N, True)[0]
+    Xl = np.atleast_2d(np.asarray(X, dtype=np.float64)).astype(ld)
+    return (Y - Xl.sum(axis=1, keepdims=True) * w[None, :]).astype(np.float64)
+
+
+def endpoint_b(N: int, xa: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """x^b = x^a + w_B^T V per component (eq:Prob-PNa): xa has shape (n_x,), V has
+    shape (n_x, N + 1); the weights are the last row of B^a."""
+    V = np.atleast_2d(np.asarray(V, dtype=np.float64))
+    return np.asarray(xa, dtype=np.float64) + V @ weights(N)

@@ -332,3 +332,68 @@ def test_extended_products_exact_on_modes():
     modes, alphas = wl.sparse_modes(3, N, count=20)
     v = bk.sparse_mode_values(N, modes, alphas)
     assert np.max(np.abs(bk.apply_Ba_extended(N, v)[0] - bk.sparse_mode_exact(N, modes, alphas))) <= 1e-15
+
+
+# ---------------------------------------------------------------- b-form and endpoint row
+@pytest.mark.parametrize("N", [2, 3, 9, 16, 64, 127])
+def test_bform_two_constructions_agree(N):
+    """B^b from its own conditions (anchor +1, quadrature on [tau_i, 1]) against
+    B^a - 1 w^T (eq:xN=Birka+b); the two share only the Lagrange basis."""
+    assert np.max(np.abs(bk.dense_Bb_quadrature(N) - bk.dense_Bb(N))) <= 5e-14
+
+
+@pytest.mark.parametrize("N", [2, 9, 16, 255, 256])
+def test_bform_rows(N):
+    B = bk.dense_Bb(N)
+    assert np.max(np.abs(B[N])) <= 1e-15                                   # B_j^b(1) = 0
+    assert np.max(np.abs(B[0] + bk.cc_weights_closed_form(N))) <= 1e-14     # B_j^b(-1) = -w_j
+    tau = bk.cgl_nodes(N)
+    assert np.max(np.abs(B @ np.ones(N + 1) - (tau - 1.0))) <= 1e-13       # integral from 1 of 1
+
+
+@pytest.mark.parametrize("N", [4, 9, 33, 64])
+def test_bform_exact_for_polynomials_monomial_basis(N):
+    """B^b p(tau) = P(tau) - P(1), P' = p, p of degree <= N (monomial basis)."""
+    rng = np.random.default_rng(100 + N)
+    p = np.polynomial.Polynomial(rng.standard_normal(min(N, 12) + 1))
+    Pint = p.integ(lbnd=1.0)
+    tau = bk.cgl_nodes(N)
+    assert np.max(np.abs(bk.dense_Bb_quadrature(N) @ p(tau) - Pint(tau))) <= 1e-12
+
+
+@pytest.mark.parametrize("N", [2, 9, 64, 255])
+def test_bform_extended_products(N):
+    X = np.random.default_rng(N + 7).standard_normal((3, N + 1))
+    Bq = bk.dense_Bb_quadrature(N)
+    assert np.max(np.abs(bk.apply_Bb_extended(N, X) - X @ Bq.T)) <= 1e-13
+    # the transposed product sums N + 1 quadrature entries per output, each off by a
+    # few ulps of the barycentric evaluation: 5e-13 at N = 255
+    assert np.max(np.abs(bk.apply_Bb_extended(N, X, transpose=True) - X @ Bq)) <= 5e-13
+
+
+def test_bform_sparse_modes():
+    N = 64
+    modes, alphas = wl.sparse_modes(5, N, count=12)
+    v = bk.sparse_mode_values(N, modes, alphas)
+    ref = bk.sparse_mode_exact_b(N, modes, alphas)
+    assert np.max(np.abs(bk.dense_Bb_quadrature(N) @ v - ref)) <= 1e-13
+    assert abs(ref[N]) == 0.0
+
+
+@pytest.mark.parametrize("N", [5, 16, 63])
+def test_endpoint_row(N):
+    """x^b = x^a + w^T V (eq:Prob-PNa): for V = p(tau), x^b - x^a is the integral of p
+    over [-1, 1], and it equals the last node of X = x^a + B^a V."""
+    rng = np.random.default_rng(200 + N)
+    tau = bk.cgl_nodes(N)
+    ps = [np.polynomial.Polynomial(rng.standard_normal(min(N, 10) + 1)) for _ in range(3)]
+    V = np.stack([p(tau) for p in ps])
+    xa = rng.standard_normal(3)
+    xb = bk.endpoint_b(N, xa, V)
+    exact = xa + np.array([p.integ(lbnd=-1.0)(1.0) for p in ps])
+    assert np.max(np.abs(xb - exact)) <= 1e-13
+    X = xa[:, None] + V @ bk.dense_Ba_quadrature(N).T
+    assert np.max(np.abs(X[:, N] - xb)) <= 1e-13
+    # the two forms describe the same trajectory: x^a + B^a V = x^b + B^b V
+    Xb = xb[:, None] + V @ bk.dense_Bb_quadrature(N).T
+    assert np.max(np.abs(X - Xb)) <= 1e-13
