@@ -272,6 +272,9 @@ def main():
         modf = torch.empty_like(mvdf)
     torch.cuda.synchronize()
 
+    xa_end = torch.zeros(nx, dtype=torch.float64, device="cuda")
+    xb_end = torch.empty_like(xa_end)
+
     # autotuner of the power-of-two product path (plan setup, outside the timed region)
     tuned = {}
     head_sched = traffic_key(0, 0, 1)  # defaults unless the tuner picks another
@@ -298,6 +301,9 @@ def main():
         for i in range(2):
             tm.region("apply_f32", lambda i=i: B.birk_apply(planmx, v32[i], o32[i]))
         tm.region("pinv", lambda: B.birk_precond(plan64, J, vin[0], vout[1], 1, B.BIRK_J_PER_NODE))
+        tm.region("apply_b", lambda: B.birk_apply_b(plan64, vin[1], vout[0]))
+        tm.region("apply_bT", lambda: B.birk_apply_bT(plan64, vin[0], vout[1]))
+        tm.region("endpoint", lambda: B.birk_endpoint(plan64, xa_end, vin[1], xb_end))
         if extra:
             tm.region("b_apply", lambda: B.birk_apply(bplan64, bv, bo))
             tm.region("m_apply_f64", lambda: B.birk_apply(mplans[B.BIRK_F64], mv, mo))
@@ -349,6 +355,7 @@ def main():
                                "P^{-1}, preconditioned GMRES to 1e-10",
                    "N_n": Nn, "n_x": nx, "n": n, "rotation_buffers": R,
                    "products_per_step": {"apply_f64": R, "apply_T_f64": R, "apply_f32": 2, "precond_inverse": 1,
+                                         "apply_b_f64": 1, "apply_bT_f64": 1, "endpoint_f64": 1,
                                          "solves": 0 if a.products_only else 2}},
         "roofline": {"bound": "hbm", "kernel": "birk_apply (FastBV, three-pass, double)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -363,6 +370,10 @@ def main():
             "apply_f32_us": us("apply_f32"),
             "apply_f32_gpts": round(n / (tm.mean_ms("apply_f32") * 1e-3) / 1e9, 3),
             "precond_inverse_f64_us": us("pinv"),
+            "apply_b_f64_us": us("apply_b"),
+            "apply_bT_f64_us": us("apply_bT"),
+            "endpoint_f64_us": us("endpoint"),
+            "endpoint_f64_GBs": round(n * 8.0 / (tm.mean_ms("endpoint") * 1e-3) / 1e9, 1),
         },
     }
     out["roofline"]["measured_copy_GBs"] = copy_ceiling_gbs(torch, stream)

@@ -154,6 +154,27 @@ birk_status birk_apply(birk_plan* plan, const void* v, void* out);
  * and M the integration recurrence.  Same arguments and errors as birk_apply. */
 birk_status birk_apply_T(birk_plan* plan, const void* g, void* out);
 
+/* out = (I_{n_x} (x) B^b) v: the b-form product (eq:xN=Birka+b).  B_j^b is anchored at
+ * tau = +1 (B_j^b(1) = 0) with the derivative conditions of eq:birk-conditions, so
+ * B^b = B^a - 1 w_B^T.  Computed as the B^a product (FastBV) followed by subtracting,
+ * per component, its last node (B^a v)_N = w_B^T v from every node; node N of out is
+ * exactly zero.  Same arguments, storage types and errors as birk_apply; graph mode
+ * covers the B^a part.  Uses the plan's per-component scratch (allocates nothing). */
+birk_status birk_apply_b(birk_plan* plan, const void* v, void* out);
+
+/* out = (I_{n_x} (x) B^bT) g = B^aT g - w_B (1^T g) per component.  The component sums
+ * 1^T g accumulate in double over a fixed tile split.  Same arguments and errors as
+ * birk_apply_T. */
+birk_status birk_apply_bT(birk_plan* plan, const void* g, void* out);
+
+/* The endpoint row of (P_a^N) (eq:Prob-PNa): xb = xa + (I_{n_x} (x) w_B^T) v, one value
+ * per component.  xa, xb: device double arrays with one entry per component, instance
+ * by instance (instance i, component r at the prefix sum of n_x over earlier instances
+ * plus r); xa == xb is allowed; neither may overlap v.  v: plan storage type, plan
+ * layout.  The weighted sums accumulate in double over a fixed tile split.
+ * Asynchronous; allocates nothing.  Errors: BIRK_ERR_ARG (NULL). */
+birk_status birk_endpoint(birk_plan* plan, const double* xa, const void* v, double* xb);
+
 /* Birkhoff preconditioner P = I - (I (x) B~^a) J (B~^a section).
  * inverse = 0: out = P y  (FastBccV applied to J y; an exclusive prefix sum).
  * inverse = 1: out = P^{-1} y by exact block forward substitution,

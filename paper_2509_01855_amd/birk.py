@@ -38,7 +38,8 @@ BIRK_J_PER_NODE = 1
 EXPORTED = [
     "birk_plan_create", "birk_plan_destroy", "birk_plan_length", "birk_plan_tune", "birk_plan_set_graphs",
     "birk_weights",
-    "birk_apply", "birk_apply_T", "birk_precond", "birk_fast_ax",
+    "birk_apply", "birk_apply_T", "birk_apply_b", "birk_apply_bT", "birk_endpoint", "birk_precond",
+    "birk_fast_ax",
     "birk_solve_opts_default", "birk_krylov_solve", "birk_status_string",
 ]
 
@@ -71,6 +72,9 @@ def _load():
     lib.birk_weights.argtypes = [vp, i32, ctypes.POINTER(dbl)]
     lib.birk_apply.argtypes = [vp, vp, vp]
     lib.birk_apply_T.argtypes = [vp, vp, vp]
+    lib.birk_apply_b.argtypes = [vp, vp, vp]
+    lib.birk_apply_bT.argtypes = [vp, vp, vp]
+    lib.birk_endpoint.argtypes = [vp, vp, vp, vp]
     lib.birk_precond.argtypes = [vp, i32, vp, vp, vp, i32]
     lib.birk_fast_ax.argtypes = [vp, i32, vp, vp, vp]
     lib.birk_solve_opts_default.argtypes = [ctypes.POINTER(birk_solve_opts)]
@@ -186,6 +190,19 @@ def birk_apply(plan: Plan, v, out) -> None:
 
 def birk_apply_T(plan: Plan, g, out) -> None:
     _check(_lib.birk_apply_T(plan.handle, _ptr(g), _ptr(out)), "birk_apply_T")
+
+
+def birk_apply_b(plan: Plan, v, out) -> None:
+    _check(_lib.birk_apply_b(plan.handle, _ptr(v), _ptr(out)), "birk_apply_b")
+
+
+def birk_apply_bT(plan: Plan, g, out) -> None:
+    _check(_lib.birk_apply_bT(plan.handle, _ptr(g), _ptr(out)), "birk_apply_bT")
+
+
+def birk_endpoint(plan: Plan, xa, v, xb) -> None:
+    """xb = xa + w^T v per component (device double arrays of one entry per component)."""
+    _check(_lib.birk_endpoint(plan.handle, _ptr(xa), _ptr(v), _ptr(xb)), "birk_endpoint")
 
 
 def birk_precond(plan: Plan, J, y, out, inverse: bool, jac_kind: int = BIRK_J_PER_NODE) -> None:

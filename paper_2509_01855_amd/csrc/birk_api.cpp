@@ -255,6 +255,7 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     }
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   }
+  if (e == hipSuccess) e = plan_bform(p);
   if (e == hipSuccess) e = plan_solve(p);
   if (e != hipSuccess) {
     free_plan(p);
@@ -350,6 +351,56 @@ birk_status birk_plan_set_graphs(birk_plan* p, int32_t enable) {
 
 birk_status birk_apply(birk_plan* p, const void* v, void* out) { return product(p, v, out, 0); }
 birk_status birk_apply_T(birk_plan* p, const void* g, void* out) { return product(p, g, out, 1); }
+
+// b-form products (eq:xN=Birka+b): the B^a product and a per-component rank-one
+// correction on the plan's stream.
+birk_status birk_apply_b(birk_plan* p, const void* v, void* out) {
+  const birk_status st = product(p, v, out, 0);
+  if (st != BIRK_OK) return st;
+  DeviceGuard g(p->device);
+  hipError_t e;
+  switch (p->prec) {
+    case BIRK_F64: e = bform_correct<double>(p, (double*)out, p->stream); break;
+    case BIRK_DF32: e = bform_correct<df32>(p, (df32*)out, p->stream); break;
+    default: e = bform_correct<float>(p, (float*)out, p->stream); break;
+  }
+  return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+}
+
+birk_status birk_apply_bT(birk_plan* p, const void* gv, void* out) {
+  if (!p || !gv || !out || gv == out) return BIRK_ERR_ARG;
+  hipError_t e;
+  {
+    DeviceGuard g(p->device);
+    switch (p->prec) {
+      case BIRK_F64: e = bform_sums<double>(p, (const double*)gv, p->stream); break;
+      case BIRK_DF32: e = bform_sums<df32>(p, (const df32*)gv, p->stream); break;
+      default: e = bform_sums<float>(p, (const float*)gv, p->stream); break;
+    }
+    if (e != hipSuccess) return BIRK_ERR_DEVICE;
+  }
+  const birk_status st = product(p, gv, out, 1);
+  if (st != BIRK_OK) return st;
+  DeviceGuard g(p->device);
+  switch (p->prec) {
+    case BIRK_F64: e = bform_correct_T<double>(p, (double*)out, p->stream); break;
+    case BIRK_DF32: e = bform_correct_T<df32>(p, (df32*)out, p->stream); break;
+    default: e = bform_correct_T<float>(p, (float*)out, p->stream); break;
+  }
+  return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+}
+
+birk_status birk_endpoint(birk_plan* p, const double* xa, const void* v, double* xb) {
+  if (!p || !xa || !v || !xb) return BIRK_ERR_ARG;
+  DeviceGuard g(p->device);
+  hipError_t e;
+  switch (p->prec) {
+    case BIRK_F64: e = endpoint<double>(p, xa, (const double*)v, xb, p->stream); break;
+    case BIRK_DF32: e = endpoint<df32>(p, xa, (const df32*)v, xb, p->stream); break;
+    default: e = endpoint<float>(p, xa, (const float*)v, xb, p->stream); break;
+  }
+  return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+}
 
 static bool nx_ok_for_precond(const birk_plan* p) {
   for (const auto& in : p->inst)

@@ -44,6 +44,15 @@ struct Instance {
   double* w = nullptr;  // CC weights on the device [Nn]
 };
 
+// One component of one instance, for the per-component corrections of the b-form
+// products and the endpoint row (birk_bform.hip).
+struct CompDesc {
+  int64_t off;       // vector offset of the component
+  int64_t Nn;        // its node count
+  const double* w;   // CC weights of its instance
+};
+constexpr int kCompTiles = 64;   // most reduction tiles per component
+
 // Four-step twiddles W_M^t = hi[t >> shift] * lo[t & (2^shift - 1)], one array pair per
 // precision, shared by every transform of length M in the plan.
 struct TwiddleSet {
@@ -193,6 +202,10 @@ struct birk_plan {
   int* krylov_cnt = nullptr;      // per instance: number of combined basis vectors
   void* krylov_stage = nullptr;   // pinned host staging: dots, singular flag, coefficients + counts
   int* flag = nullptr;            // device flag: singular pivot seen
+  birk::CompDesc* comps = nullptr;  // component table (device), one entry per component
+  int64_t ncomp = 0;
+  int64_t max_nn = 0;               // longest component
+  double* comp_part = nullptr;      // per-component partial sums [ncomp][kCompTiles]
   int use_fast = 1;               // power-of-two N takes the three-pass path
   birk::FastKnobs fast_kn;        // default tile schedule of the three-pass groups
   // HIP graphs of the products (birk_plan_set_graphs), per (direction, input, output)
@@ -232,6 +245,22 @@ hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, in
 void fast_sizes(const birk_plan* p, int64_t N, int nc, int64_t* work, int64_t* part);
 // Autotuner of the three-pass groups (birk_plan_tune); appends a summary to *report.
 hipError_t tune_fast(birk_plan* p, hipStream_t s, std::string* report);
+
+// ---- b-form corrections and the endpoint row (birk_bform.hip) ----
+// Build the component table and its partial-sum scratch (after the weights exist).
+hipError_t plan_bform(birk_plan* p);
+// out[c][k] -= out[c][N] for every component c (B^a v -> B^b v).
+template <typename T>
+hipError_t bform_correct(birk_plan* p, T* out, hipStream_t s);
+// Partial sums of every component of g, kept for bform_correct_T.
+template <typename T>
+hipError_t bform_sums(birk_plan* p, const T* g, hipStream_t s);
+// out[c][k] -= w_k (1^T g_c) from the sums of bform_sums (B^aT g -> B^bT g).
+template <typename T>
+hipError_t bform_correct_T(birk_plan* p, T* out, hipStream_t s);
+// xb[c] = xa[c] + w^T v_c.
+template <typename T>
+hipError_t endpoint(birk_plan* p, const double* xa, const T* v, double* xb, hipStream_t s);
 
 // ---- preconditioner, Jacobian products and Krylov kernels (birk_solve.hip) ----
 template <typename T>

@@ -83,6 +83,9 @@ def test_null_arguments_are_rejected(birk):
     assert lib.birk_plan_create(ctypes.byref(h), 0, nn, nx, 0, None) == birk.BIRK_ERR_SIZE
     assert lib.birk_apply(None, None, None) == birk.BIRK_ERR_ARG
     assert lib.birk_apply_T(None, None, None) == birk.BIRK_ERR_ARG
+    assert lib.birk_apply_b(None, None, None) == birk.BIRK_ERR_ARG
+    assert lib.birk_apply_bT(None, None, None) == birk.BIRK_ERR_ARG
+    assert lib.birk_endpoint(None, None, None, None) == birk.BIRK_ERR_ARG
     assert lib.birk_precond(None, 0, None, None, None, 1) == birk.BIRK_ERR_ARG
     assert lib.birk_fast_ax(None, 0, None, None, None) == birk.BIRK_ERR_ARG
     assert lib.birk_krylov_solve(None, 0, None, None, None, None, None) == birk.BIRK_ERR_ARG
