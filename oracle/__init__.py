@@ -12,10 +12,13 @@ Every function here is the plain, slow definition of what the GPU path computes:
 * ``system``    -- the dense linear system [I - B^a df] dX = x^a b, the dense Birkhoff
   preconditioner P = I - B~^a df, its forward substitution, dense LU solves, and a
   plain right-preconditioned GMRES used only to compare iteration counts.
+* ``newton``    -- the two-body right-hand side and its Jacobian, the residual
+  X - x^a b - B^a f(X) of the nonlinear IVP, and Newton's method on it with dense
+  linear solves and Armijo backtracking.
 
 It shares no code with the HIP path.  Arithmetic is float64 throughout; library
 primitives (LAPACK solves, matrix products, scipy's DCT, Gauss-Legendre nodes) serve
 as single steps only.
 """
 
-from . import birkhoff, system  # noqa: F401
+from . import birkhoff, newton, system  # noqa: F401

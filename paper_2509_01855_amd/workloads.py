@@ -39,6 +39,7 @@ __all__ = [
     "batched_instances",
     "sparse_modes",
     "random_vectors",
+    "kepler_ivp",
     "Instance",
 ]
 
@@ -187,3 +188,25 @@ def sparse_modes(seed, N: int, count: int = 64):
     modes = modes[modes <= N]
     alphas = rng.standard_normal(modes.shape[0])
     return modes, alphas
+
+
+def kepler_ivp(seed, N_n: int, e: float | None = None):
+    """The nonlinear two-body initial value problem over one period of a seeded orbit.
+
+    mu = a = 1, period 2 pi, time scale s = pi for tau in [-1, 1].  Returns a dict with
+    the scale, mu, the initial state x_a (periapsis), the closed-form solution at the
+    nodes (6, N_n) and the starting guess: the circular orbit of the same period in the
+    same plane and phase.
+    """
+    rng = np.random.default_rng(seed)
+    if e is None:
+        e = float(rng.uniform(0.0, 0.2))
+    R = _random_rotation(rng)
+    period = 2.0 * math.pi
+    tau = grid_times(N_n - 1)
+    t = (tau + 1.0) * (0.5 * period)
+    r, v, _ = kepler_orbit(t, e, R)
+    r0, v0, _ = kepler_orbit(t, 0.0, R)
+    X = np.concatenate([r, v])
+    return {"scale": 0.5 * period, "mu": 1.0, "e": e, "x_a": X[:, 0].copy(), "exact": X,
+            "guess": np.concatenate([r0, v0])}

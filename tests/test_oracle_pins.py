@@ -397,3 +397,64 @@ def test_endpoint_row(N):
     # the two forms describe the same trajectory: x^a + B^a V = x^b + B^b V
     Xb = xb[:, None] + V @ bk.dense_Bb_quadrature(N).T
     assert np.max(np.abs(X - Xb)) <= 1e-13
+
+
+# ---------------------------------------------------------------- Newton on the nonlinear IVP
+from oracle import newton as nw  # noqa: E402
+
+
+def test_two_body_jacobian_matches_finite_differences():
+    rng = np.random.default_rng(40)
+    X = rng.standard_normal((6, 7))
+    X[:3] += 2.0 * np.sign(X[:3])          # keep |r| away from 0
+    J = nw.two_body_jacobian(X, 1.7, 0.9)
+    h = 1e-6
+    for c in range(6):
+        E = np.zeros_like(X)
+        E[c] = h
+        fd = (nw.two_body_rhs(X + E, 1.7, 0.9) - nw.two_body_rhs(X - E, 1.7, 0.9)) / (2 * h)
+        assert np.max(np.abs(fd - J[:, c, :])) <= 1e-8
+
+
+def test_two_body_rhs_is_the_orbit_derivative():
+    """f(X) on the closed-form orbit equals s dX/dt, by central differences in time of
+    Kepler's solution (independent of the formula for f)."""
+    R = np.linalg.qr(np.random.default_rng(41).standard_normal((3, 3)))[0]
+    t = np.linspace(0.3, 6.0, 9)
+    h = 1e-5
+    rp, vp, _ = wl.kepler_orbit(t + h, 0.15, R)
+    rm, vm, _ = wl.kepler_orbit(t - h, 0.15, R)
+    r, v, _ = wl.kepler_orbit(t, 0.15, R)
+    dX = np.concatenate([rp - rm, vp - vm]) / (2 * h)
+    F = nw.two_body_rhs(np.concatenate([r, v]), 2.5)
+    assert np.max(np.abs(F - 2.5 * dX)) <= 1e-8
+
+
+@pytest.mark.parametrize("e", [0.0, 0.1, 0.2])
+def test_newton_ivp_reaches_kepler_closed_form(e):
+    """Newton on eq:X-V=nonlin from the circular orbit reaches Kepler's solution at the
+    nodes (spectral accuracy at N = 200 over one period), with quadratic convergence at
+    the end."""
+    N = 200
+    ivp = wl.kepler_ivp(42, N + 1, e)
+    X, its, hist, steps = nw.newton_ivp(N, ivp["x_a"], ivp["guess"], ivp["scale"], ivp["mu"])
+    assert np.max(np.abs(X - ivp["exact"])) <= 1e-11
+    assert its <= 10
+    if its >= 3:
+        # quadratic: the last reductions outpace any linear rate
+        assert hist[-2] <= 1e-3 * hist[-3] or hist[-2] <= 1e-10
+    # the exact orbit satisfies the discrete equations to the interpolation error
+    Ba = bk.dense_Ba(N)
+    G = nw.ivp_residual(Ba, ivp["x_a"], ivp["exact"], nw.two_body_rhs(ivp["exact"], ivp["scale"]))
+    assert np.max(np.abs(G)) <= 1e-11
+
+
+def test_newton_ivp_line_search_engages():
+    """From a poor guess (the circular orbit at e = 0.3) full steps are rejected at
+    first and the damped iteration still converges."""
+    N = 120
+    ivp = wl.kepler_ivp(43, N + 1, 0.3)
+    X, its, hist, steps = nw.newton_ivp(N, ivp["x_a"], ivp["guess"], ivp["scale"], ivp["mu"])
+    assert np.max(np.abs(X - ivp["exact"])) <= 1e-9
+    assert min(steps) < 1.0 and steps[-1] == 1.0
+    assert all(b < a for a, b in zip(hist, hist[1:]))
