@@ -50,8 +50,9 @@ struct CompDesc {
   int64_t off;       // vector offset of the component
   int64_t Nn;        // its node count
   const double* w;   // CC weights of its instance
+  int64_t part;      // offset of its reduction partials
 };
-constexpr int kCompTiles = 64;   // most reduction tiles per component
+constexpr int kCompTiles = 256;  // most reduction tiles per component
 
 // Four-step twiddles W_M^t = hi[t >> shift] * lo[t & (2^shift - 1)], one array pair per
 // precision, shared by every transform of length M in the plan.
@@ -205,7 +206,8 @@ struct birk_plan {
   birk::CompDesc* comps = nullptr;  // component table (device), one entry per component
   int64_t ncomp = 0;
   int64_t max_nn = 0;               // longest component
-  double* comp_part = nullptr;      // per-component partial sums [ncomp][kCompTiles]
+  double* comp_val = nullptr;       // one double per component (last node, or a total)
+  double* comp_part = nullptr;      // per-component reduction partials (CompDesc::part)
   int use_fast = 1;               // power-of-two N takes the three-pass path
   birk::FastKnobs fast_kn;        // default tile schedule of the three-pass groups
   // HIP graphs of the products (birk_plan_set_graphs), per (direction, input, output)
