@@ -10,7 +10,9 @@ One step is one pass of the whole hot path:
     product reads its input from HBM; B^aT g in double (same rotation); B^a v in float;
     P^{-1} y (inverse-preconditioner scan) in double; the preconditioned GMRES solve to
     relative residual 1e-10, once with float Krylov bulk inside double refinement
-    (mixed) and once in double (FP64);
+    (mixed) and once in double (FP64); the b-form products B^b v, B^bT g and the
+    endpoint row x^b = x^a + w^T v in double; Newton's method on the nonlinear two-body
+    IVP over one period (e = 0.15) from the circular orbit, to ||G|| <= 1e-13 ||X||;
   * batched uneven workload: 512 LTI instances (N_n log-uniform in [2^8, 2^16], n_x in
     {4, 6, 12}) in one plan: B^a v in double, and the mixed and FP64 solves to 1e-10;
   * many-RHS workload: 32 right-hand sides of N_n = 2^18 + 1, n_x = 6 in one plan:
@@ -18,7 +20,7 @@ One step is one pass of the whole hot path:
 
 value = Gpts/s of the headline double B^a product = n / (mean duration of one
 birk_apply), timed with HIP events on the plan's stream over the timed region.  The other
-rows are reported under "secondary", "solve", "batched" and "many_rhs".
+rows are reported under "secondary", "solve", "newton_ivp", "batched" and "many_rhs".
 
 `python bench.py --gpus N --steps K --warmup W`; N must be 1 (single-GPU build).
 """
@@ -240,6 +242,12 @@ def main():
     beta = torch.from_numpy(np.repeat(inst.x_a, Nn)).to("cuda")
     chi = torch.zeros(n, dtype=torch.float64, device="cuda")
     solve_info = {}
+    # nonlinear IVP: one period of a Kepler orbit (e = 0.15) by Newton from the circular orbit
+    ivp = wl.kepler_ivp(44, Nn, 0.15)
+    ivp_guess = torch.from_numpy(ivp["guess"].ravel()).to("cuda")
+    ivp_xa = torch.from_numpy(ivp["x_a"]).to("cuda")
+    ivp_X = torch.empty_like(ivp_guess)
+    ivp_info = {}
 
     # ---- batched uneven workload
     extra = not a.headline_only
@@ -322,6 +330,11 @@ def main():
                                lambda: B.birk_krylov_solve(plan, Jm, bt, ch, jk, rtol=1e-10))
                 solve_info[name] = info
 
+            def newton():
+                ivp_X.copy_(ivp_guess)
+                ivp_info.update(B.birk_newton_ivp(plan64, ivp_xa, ivp_X, mu=ivp["mu"], scale=ivp["scale"]))
+            tm.wall("newton" if timed else "_warm", newton)
+
     for _ in range(a.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -390,6 +403,13 @@ def main():
             "mixed": {k: solve_info["mixed"][k] for k in ("inner_iters", "outer_iters", "rel_resid")},
             "fp64": {k: solve_info["fp64"][k] for k in ("inner_iters", "outer_iters", "rel_resid")},
         }
+    if not a.products_only:
+        err = float(np.max(np.abs(ivp_X.cpu().numpy().reshape(6, Nn) - ivp["exact"])))
+        out["newton_ivp"] = {
+            "workload": "two-body IVP over one period (e = 0.15), N_n = 2^20 + 1, Newton from the circular orbit",
+            "ms": round(tm.mean_ms("newton"), 3), "newton_iters": ivp_info["newton_iters"][0],
+            "linear_iters": ivp_info["linear_iters"][0], "rel_resid": ivp_info["rel_resid"][0],
+            "max_abs_err_vs_kepler": err}
     if extra:
         bt = tm.mean_ms("b_apply") * 1e-3
         out["batched"] = {"workload": "512 LTI instances, N_n log-uniform in [2^8, 2^16], n_x in {4, 6, 12}",

@@ -232,6 +232,70 @@ birk_status birk_krylov_solve(birk_plan* plan, birk_jac_kind jac_kind, const dou
                               const double* beta, double* chi, const birk_solve_opts* opts,
                               birk_solve_info* info);
 
+/* ---- Nonlinear IVP: Newton's method on X - x^a b - B^a f(X) = 0 (eq:X-V=nonlin) ---- */
+
+/* Caller-supplied right-hand side: enqueue on hip_stream (a hipStream_t) the evaluation
+ * F = f(X) node by node and, when J is not NULL, the per-node Jacobian df/dx in the
+ * BIRK_J_PER_NODE layout.  X, F, J: device, double, plan layout.  Return BIRK_OK, or an
+ * error status, which ends the Newton solve with that status. */
+typedef birk_status (*birk_rhs_fn)(void* ctx, const double* X, double* F, double* J, void* hip_stream);
+
+typedef enum {
+  BIRK_MODEL_TWO_BODY = 0,   /* built in: x = (r, v), dx/dtau = scale (v, -mu r / |r|^3)   */
+  BIRK_MODEL_CALLBACK = 1    /* fn(ctx, ...) as above                                      */
+} birk_model_kind;
+
+typedef struct {
+  int32_t kind;        /* birk_model_kind                                                  */
+  double mu;           /* two-body: gravitational parameter                                */
+  double scale;        /* two-body: (t_b - t_a) / 2, the time scale of tau in [-1, 1]      */
+  birk_rhs_fn fn;      /* callback model                                                   */
+  void* ctx;           /* passed to fn                                                     */
+} birk_ivp_model;
+
+/* The two-body right-hand side F = scale (v, -mu r / |r|^3) and its Jacobian
+ * J = scale [[0, I], [mu (3 r r^T / |r|^2 - I) / |r|^3, 0]] at every node of every
+ * instance (all instances need n_x = 6: components r_x, r_y, r_z, v_x, v_y, v_z).
+ * X, F, J: device, double; F or J may be NULL (not both); neither may be X.
+ * Asynchronous.  Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED (an instance with n_x != 6). */
+birk_status birk_two_body(birk_plan* plan, double mu, double scale, const double* X, double* F, double* J);
+
+typedef struct {
+  int32_t max_newton;        /* Newton steps allowed (default 30)                           */
+  double tol;                /* stop when ||G||_2 <= tol ||X||_2 per instance (1e-13)       */
+  int32_t line_search;       /* 1 = Armijo backtracking on ||G||_2 (default), 0 = full steps */
+  birk_solve_opts linear;    /* the Newton systems (birk_krylov_solve; use_x0 is ignored)    */
+} birk_newton_opts;
+
+/* Fill opts with the defaults listed above (linear: birk_solve_opts_default). */
+void birk_newton_opts_default(birk_newton_opts* opts);
+
+typedef struct {
+  int32_t* status;        /* per instance birk_status, or NULL                             */
+  int32_t* newton_iters;  /* per instance Newton steps taken, or NULL                      */
+  int32_t* linear_iters;  /* per instance Krylov iterations over all steps, or NULL        */
+  double* rel_resid;      /* per instance final ||G||_2 / ||X||_2, or NULL                 */
+} birk_newton_info;
+
+/* Solve the a-form IVP X - x^a b - (I (x) B^a) f(X) = 0 (eq:X-V=nonlin, b = ones) for
+ * every instance by Newton's method: each step solves [I - (I (x) B^a) df(X)] D = -G(X)
+ * (eq:Newton-ivp) with birk_krylov_solve (right-preconditioned GMRES, per-node Jacobian)
+ * and, with line_search, halves the step until ||G(X + l D)|| <= (1 - 1e-4 l) ||G(X)||
+ * (the paper gives the Newton system only; this globalisation is the library's).  A step
+ * below 2^-12 fails the instance with BIRK_ERR_NOCONV and keeps its X.
+ * xa: device, double, one entry per component (the layout of birk_endpoint); X: device,
+ * double, plan layout, the starting guess on entry and the last iterate on return.
+ * Plans of precision BIRK_F64 (or BIRK_F32_REFINE_F64, whose linear solves then use
+ * refinement); the product in G(X) is always double.  Synchronous.  The first call
+ * allocates the Newton workspace (6 vectors plus the per-node Jacobians), kept with the
+ * plan.  Returns BIRK_OK when every instance converged, else the first failing status.
+ * Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED (two-body model with n_x != 6, BIRK_F32 or
+ * BIRK_DF32 plans, n_x > 12 with the preconditioner), BIRK_ERR_NOMEM,
+ * BIRK_ERR_SINGULAR, BIRK_ERR_NOCONV, BIRK_ERR_NONFINITE, BIRK_ERR_DEVICE, or the
+ * callback's own status. */
+birk_status birk_newton_ivp(birk_plan* plan, const birk_ivp_model* model, const double* xa, double* X,
+                            const birk_newton_opts* opts, birk_newton_info* info);
+
 /* Static, NUL-terminated description of a status code (never NULL). */
 const char* birk_status_string(birk_status status);
 

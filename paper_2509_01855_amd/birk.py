@@ -41,7 +41,15 @@ EXPORTED = [
     "birk_apply", "birk_apply_T", "birk_apply_b", "birk_apply_bT", "birk_endpoint", "birk_precond",
     "birk_fast_ax",
     "birk_solve_opts_default", "birk_krylov_solve", "birk_status_string",
+    "birk_two_body", "birk_newton_opts_default", "birk_newton_ivp",
 ]
+
+BIRK_MODEL_TWO_BODY = 0
+BIRK_MODEL_CALLBACK = 1
+
+# birk_rhs_fn: (ctx, X, F, J, hip_stream) -> birk_status
+RHS_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.c_void_p)
 
 
 class birk_solve_opts(ctypes.Structure):
@@ -56,6 +64,23 @@ class birk_solve_info(ctypes.Structure):
                 ("inner_iters", ctypes.POINTER(ctypes.c_int32)),
                 ("outer_iters", ctypes.POINTER(ctypes.c_int32)),
                 ("rel_resid_fp64", ctypes.POINTER(ctypes.c_double))]
+
+
+class birk_ivp_model(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("mu", ctypes.c_double), ("scale", ctypes.c_double),
+                ("fn", RHS_FN), ("ctx", ctypes.c_void_p)]
+
+
+class birk_newton_opts(ctypes.Structure):
+    _fields_ = [("max_newton", ctypes.c_int32), ("tol", ctypes.c_double), ("line_search", ctypes.c_int32),
+                ("linear", birk_solve_opts)]
+
+
+class birk_newton_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.POINTER(ctypes.c_int32)),
+                ("newton_iters", ctypes.POINTER(ctypes.c_int32)),
+                ("linear_iters", ctypes.POINTER(ctypes.c_int32)),
+                ("rel_resid", ctypes.POINTER(ctypes.c_double))]
 
 
 def _load():
@@ -81,10 +106,16 @@ def _load():
     lib.birk_solve_opts_default.restype = None
     lib.birk_krylov_solve.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(birk_solve_opts),
                                       ctypes.POINTER(birk_solve_info)]
+    lib.birk_two_body.argtypes = [vp, dbl, dbl, vp, vp, vp]
+    lib.birk_newton_opts_default.argtypes = [ctypes.POINTER(birk_newton_opts)]
+    lib.birk_newton_opts_default.restype = None
+    lib.birk_newton_ivp.argtypes = [vp, ctypes.POINTER(birk_ivp_model), vp, vp, ctypes.POINTER(birk_newton_opts),
+                                    ctypes.POINTER(birk_newton_info)]
     lib.birk_status_string.argtypes = [i32]
     lib.birk_status_string.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("birk_plan_length", "birk_solve_opts_default", "birk_status_string"):
+        if name not in ("birk_plan_length", "birk_solve_opts_default", "birk_newton_opts_default",
+                        "birk_status_string"):
             getattr(lib, name).restype = i32
     return lib
 
@@ -241,4 +272,53 @@ def birk_krylov_solve(plan: Plan, J, beta, chi, jac_kind: int = BIRK_J_PER_NODE,
            "outer_iters": list(outer), "rel_resid": list(res)}
     if raise_on_error and st != BIRK_OK:
         raise BirkError(st, "birk_krylov_solve")
+    return out
+
+
+def birk_two_body(plan: Plan, X, F, J, mu: float = 1.0, scale: float = 1.0) -> None:
+    """Two-body right-hand side F and per-node Jacobian J at X (F or J may be None)."""
+    _check(_lib.birk_two_body(plan.handle, float(mu), float(scale), _ptr(X), _ptr(F), _ptr(J)), "birk_two_body")
+
+
+def birk_newton_opts_default() -> birk_newton_opts:
+    o = birk_newton_opts()
+    _lib.birk_newton_opts_default(ctypes.byref(o))
+    return o
+
+
+def birk_newton_ivp(plan: Plan, xa, X, mu: float = 1.0, scale: float = 1.0, rhs=None, raise_on_error: bool = True,
+                    linear=None, **opts):
+    """Newton's method on X - x^a b - B^a f(X) = 0.  With rhs=None the built-in two-body model
+    (mu, scale); otherwise rhs(X_ptr, F_ptr, J_ptr, stream_ptr) -> birk_status is called to
+    evaluate f (and df/dx when J_ptr is not 0).  linear: dict of birk_solve_opts fields for the
+    Newton systems.  Returns a dict with per-instance status, Newton and Krylov iteration
+    counts and final ||G|| / ||X||."""
+    o = birk_newton_opts_default()
+    for k, v in opts.items():
+        if k == "linear" or not hasattr(o, k):
+            raise TypeError(f"unknown Newton option {k}")
+        setattr(o, k, v)
+    for k, v in (linear or {}).items():
+        if not hasattr(o.linear, k):
+            raise TypeError(f"unknown solve option {k}")
+        setattr(o.linear, k, v)
+    if rhs is None:
+        model = birk_ivp_model(BIRK_MODEL_TWO_BODY, float(mu), float(scale), RHS_FN(), None)
+        cb = None
+    else:
+        cb = RHS_FN(lambda ctx, x, f, j, stream: int(rhs(x or 0, f or 0, j or 0, stream or 0)))
+        model = birk_ivp_model(BIRK_MODEL_CALLBACK, 0.0, 0.0, cb, None)
+    b = len(plan.n_nodes)
+    stv = (ctypes.c_int32 * b)()
+    nit = (ctypes.c_int32 * b)()
+    lit = (ctypes.c_int32 * b)()
+    res = (ctypes.c_double * b)()
+    info = birk_newton_info(stv, nit, lit, res)
+    st = _lib.birk_newton_ivp(plan.handle, ctypes.byref(model), _ptr(xa), _ptr(X), ctypes.byref(o),
+                              ctypes.byref(info))
+    del cb
+    out = {"status": int(st), "inst_status": list(stv), "newton_iters": list(nit), "linear_iters": list(lit),
+           "rel_resid": list(res)}
+    if raise_on_error and st != BIRK_OK:
+        raise BirkError(st, "birk_newton_ivp")
     return out

@@ -79,6 +79,7 @@ void free_plan(birk_plan* p) {
   if (p->jsw) (void)hipFree(p->jsw);
   if (p->krylov_Q) (void)hipFree(p->krylov_Q);
   if (p->krylov_vec) (void)hipFree(p->krylov_vec);
+  if (p->newton_buf) (void)hipFree(p->newton_buf);
   if (p->krylov_dots) (void)hipFree(p->krylov_dots);
   if (p->krylov_part) (void)hipFree(p->krylov_part);
   if (p->krylov_coef) (void)hipFree(p->krylov_coef);
@@ -256,6 +257,7 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   }
   if (e == hipSuccess) e = plan_bform(p);
+  if (e == hipSuccess) e = plan_instances(p);
   if (e == hipSuccess) e = plan_solve(p);
   if (e != hipSuccess) {
     free_plan(p);
@@ -798,3 +800,232 @@ extern "C" birk_status birk_krylov_solve(birk_plan* p, birk_jac_kind jk, const d
     for (int i = 0; i < B; ++i) info->status[i] = BIRK_ERR_SINGULAR;
   return result;
 }
+
+// ------------------------------------------------------------------ Newton on the IVP
+namespace {
+
+constexpr double kArmijo = 1e-4;
+constexpr double kMinStep = 1.0 / 4096.0;
+
+// Newton workspace: F, G, Gt, D, Xt, beta (total_len each), the per-node Jacobians, and
+// per-instance step lengths, beta scales and combination counts.
+hipError_t ensure_newton(birk_plan* p) {
+  if (p->newton_buf) return hipSuccess;
+  const size_t B = p->inst.size();
+  const size_t bytes = (6 * (size_t)p->total_len + (size_t)p->total_jnode + 2 * B) * sizeof(double) + B * sizeof(int);
+  return hipMalloc(&p->newton_buf, bytes);
+}
+
+struct NewtonBufs {
+  double *F, *G, *Gt, *D, *Xt, *beta, *J, *lam, *alpha;
+  int* cnt;
+};
+
+NewtonBufs newton_bufs(birk_plan* p) {
+  NewtonBufs b;
+  const int64_t n = p->total_len;
+  double* q = (double*)p->newton_buf;
+  b.F = q;
+  b.G = q + n;
+  b.Gt = q + 2 * n;
+  b.D = q + 3 * n;
+  b.Xt = q + 4 * n;
+  b.beta = q + 5 * n;
+  b.J = q + 6 * n;
+  b.lam = b.J + p->total_jnode;
+  b.alpha = b.lam + p->inst.size();
+  b.cnt = (int*)(b.alpha + p->inst.size());
+  return b;
+}
+
+birk_status eval_model(birk_plan* p, const birk_ivp_model& m, const double* X, double* F, double* J) {
+  if (m.kind == BIRK_MODEL_TWO_BODY)
+    return two_body(p, m.mu, m.scale, X, F, J, p->stream) == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+  return m.fn(m.ctx, X, F, J, (void*)p->stream);
+}
+
+// G = X - x^a b - B^a F(X), then the per-instance norms ||G|| and ||X||.
+birk_status newton_residual(birk_plan* p, const birk_ivp_model& m, const double* xa, const double* X, double* F,
+                            double* G, std::vector<double>& gn, std::vector<double>& xn) {
+  birk_status st = eval_model(p, m, X, F, nullptr);
+  if (st != BIRK_OK) return st;
+  if (apply_product<double>(p, F, G, 0, p->stream) != hipSuccess) return BIRK_ERR_DEVICE;
+  if (ivp_residual(p, xa, X, G, p->stream) != hipSuccess) return BIRK_ERR_DEVICE;
+  if (seg_norms(p, G, gn) != hipSuccess || seg_norms(p, X, xn) != hipSuccess) return BIRK_ERR_DEVICE;
+  return BIRK_OK;
+}
+
+hipError_t upload(double* dst, const std::vector<double>& h, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(dst, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  return e == hipSuccess ? hipStreamSynchronize(s) : e;
+}
+
+}  // namespace
+
+extern "C" {
+
+void birk_newton_opts_default(birk_newton_opts* o) {
+  if (!o) return;
+  o->max_newton = 30;
+  o->tol = 1e-13;
+  o->line_search = 1;
+  birk_solve_opts_default(&o->linear);
+}
+
+birk_status birk_two_body(birk_plan* p, double mu, double scale, const double* X, double* F, double* J) {
+  if (!p || !X || (!F && !J) || X == F || X == J) return BIRK_ERR_ARG;
+  for (const auto& in : p->inst)
+    if (in.nx != 6) return BIRK_ERR_UNSUPPORTED;
+  DeviceGuard g(p->device);
+  return two_body(p, mu, scale, X, F, J, p->stream) == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+}
+
+birk_status birk_newton_ivp(birk_plan* p, const birk_ivp_model* model, const double* xa, double* X,
+                            const birk_newton_opts* opts_in, birk_newton_info* info) {
+  if (!p || !model || !xa || !X) return BIRK_ERR_ARG;
+  if (model->kind == BIRK_MODEL_TWO_BODY) {
+    for (const auto& in : p->inst)
+      if (in.nx != 6) return BIRK_ERR_UNSUPPORTED;
+  } else if (model->kind != BIRK_MODEL_CALLBACK || !model->fn) {
+    return BIRK_ERR_ARG;
+  }
+  birk_newton_opts o;
+  birk_newton_opts_default(&o);
+  if (opts_in) o = *opts_in;
+  if (o.max_newton < 1 || !(o.tol > 0.0) || (o.line_search != 0 && o.line_search != 1)) return BIRK_ERR_ARG;
+  if (o.linear.method != 0 || o.linear.restart < 1 || o.linear.restart > kKryMaxDots - 1 || o.linear.max_iter < 1 ||
+      !(o.linear.rtol > 0.0))
+    return o.linear.method == 1 ? BIRK_ERR_UNSUPPORTED : BIRK_ERR_ARG;
+  if (p->prec == BIRK_F32_REFINE_F64 && (!(o.linear.inner_rtol > 0.0) || o.linear.max_refine < 1)) return BIRK_ERR_ARG;
+  if (p->prec == BIRK_F32 || p->prec == BIRK_DF32) return BIRK_ERR_UNSUPPORTED;
+  if (o.linear.use_precond && !nx_ok_for_precond(p)) return BIRK_ERR_UNSUPPORTED;
+  DeviceGuard g(p->device);
+  const int B = (int)p->inst.size();
+  hipStream_t s = p->stream;
+  hipError_t e = ensure_newton(p);
+  if (e == hipSuccess) e = ensure_krylov(p, o.linear.restart, sizeof(double));
+  if (e != hipSuccess) return dev_err(e);
+  NewtonBufs b = newton_bufs(p);
+  std::vector<int> status(B, BIRK_OK), iters(B, 0), lin(B, 0);
+  std::vector<bool> done(B, false);
+  std::vector<double> gn, xn, gtn, xtn;
+  birk_status result = newton_residual(p, *model, xa, X, b.F, b.G, gn, xn);
+  birk_solve_opts lo = o.linear;
+  lo.use_x0 = 0;
+  std::vector<int32_t> lst(B), lin_it(B);
+  birk_solve_info li{lst.data(), lin_it.data(), nullptr, nullptr};
+  for (int it = 0; result == BIRK_OK; ++it) {
+    bool all_done = true;
+    for (int i = 0; i < B; ++i) {
+      if (done[i]) continue;
+      if (!std::isfinite(gn[i])) {
+        status[i] = BIRK_ERR_NONFINITE;
+        done[i] = true;
+      } else if (gn[i] <= o.tol * xn[i]) {
+        done[i] = true;
+      } else if (it == o.max_newton) {
+        status[i] = BIRK_ERR_NOCONV;
+        done[i] = true;
+      } else {
+        all_done = false;
+      }
+    }
+    if (all_done) break;
+    // Newton system [I - B^a df(X)] D = -G for the instances still running (zero
+    // right-hand side, hence D = 0, for the others)
+    result = eval_model(p, *model, X, b.F, b.J);
+    if (result != BIRK_OK) break;
+    std::vector<double> alpha(B);
+    for (int i = 0; i < B; ++i) alpha[i] = done[i] ? 0.0 : -1.0;
+    if (upload(b.alpha, alpha, s) != hipSuccess) {
+      result = BIRK_ERR_DEVICE;
+      break;
+    }
+    kry::sscale_conv<double, double>(p, b.G, b.beta, b.alpha, s);
+    std::fill(lst.begin(), lst.end(), BIRK_OK);
+    std::fill(lin_it.begin(), lin_it.end(), 0);
+    const birk_status ls = birk_krylov_solve(p, BIRK_J_PER_NODE, b.J, b.beta, b.D, &lo, &li);
+    if (ls != BIRK_OK && ls != BIRK_ERR_NOCONV && ls != BIRK_ERR_BREAKDOWN && ls != BIRK_ERR_NONFINITE) {
+      result = ls;
+      break;
+    }
+    for (int i = 0; i < B; ++i) {
+      if (done[i]) continue;
+      lin[i] += lin_it[i];
+      iters[i] = it + 1;
+      // an inexact step (NOCONV, BREAKDOWN) is still tried; a non-finite one is not
+      if (lst[i] == BIRK_ERR_NONFINITE) {
+        status[i] = BIRK_ERR_NONFINITE;
+        done[i] = true;
+      }
+    }
+    // backtracking: X_t = X + lam_i D per instance; accepted steps keep their length while
+    // other instances go on halving; a failed instance keeps X (lam = 0)
+    std::vector<double> lam(B);
+    std::vector<int> pending(B, 0);
+    for (int i = 0; i < B; ++i) {
+      lam[i] = done[i] ? 0.0 : 1.0;
+      pending[i] = done[i] ? 0 : 1;
+    }
+    for (;;) {
+      // lam_i = 0 takes instance i out of the update (its D may not be finite)
+      std::vector<int> cnt(B);
+      for (int i = 0; i < B; ++i) cnt[i] = lam[i] > 0.0 ? 1 : 0;
+      e = hipMemcpyAsync(b.cnt, cnt.data(), B * sizeof(int), hipMemcpyHostToDevice, s);
+      if (e != hipSuccess || upload(b.lam, lam, s) != hipSuccess) {
+        result = BIRK_ERR_DEVICE;
+        break;
+      }
+      if (hipMemcpyAsync(b.Xt, X, p->total_len * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        result = BIRK_ERR_DEVICE;
+        break;
+      }
+      kry::scombine<double>(p, b.D, b.lam, 1, b.cnt, b.Xt, s);
+      result = newton_residual(p, *model, xa, b.Xt, b.F, b.Gt, gtn, xtn);
+      if (result != BIRK_OK) break;
+      bool again = false;
+      for (int i = 0; i < B; ++i) {
+        if (!pending[i]) continue;
+        const bool ok = gtn[i] <= (1.0 - kArmijo * lam[i]) * gn[i] || gtn[i] <= o.tol * xtn[i];
+        if (ok || !o.line_search) {
+          pending[i] = 0;
+          continue;
+        }
+        lam[i] *= 0.5;
+        if (lam[i] < kMinStep) {
+          lam[i] = 0.0;
+          pending[i] = 0;
+          status[i] = BIRK_ERR_NOCONV;
+          done[i] = true;
+        }
+        again = true;   // X_t must be formed again with the new lengths
+      }
+      if (!again) break;
+    }
+    if (result != BIRK_OK) break;
+    if (hipMemcpyAsync(X, b.Xt, p->total_len * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+      result = BIRK_ERR_DEVICE;
+      break;
+    }
+    std::swap(b.G, b.Gt);
+    for (int i = 0; i < B; ++i) {
+      if (lam[i] > 0.0 || !done[i]) {
+        gn[i] = gtn[i];
+        xn[i] = xtn[i];
+      }
+    }
+  }
+  if (result == BIRK_OK && hipStreamSynchronize(s) != hipSuccess) result = BIRK_ERR_DEVICE;
+  for (int i = 0; i < B; ++i) {
+    if (result == BIRK_OK && status[i] != BIRK_OK) result = (birk_status)status[i];
+    if (info) {
+      if (info->status) info->status[i] = status[i];
+      if (info->newton_iters) info->newton_iters[i] = iters[i];
+      if (info->linear_iters) info->linear_iters[i] = lin[i];
+      if (info->rel_resid) info->rel_resid[i] = (i < (int)gn.size() && xn[i] > 0.0) ? gn[i] / xn[i] : gn.empty() ? -1.0 : gn[i];
+    }
+  }
+  return result;
+}
+
+}  // extern "C"

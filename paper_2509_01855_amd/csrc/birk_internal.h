@@ -54,6 +54,14 @@ struct CompDesc {
 };
 constexpr int kCompTiles = 256;  // most reduction tiles per component
 
+// One instance, for the node-wise model kernels of the Newton solve (birk_newton.hip).
+struct InstDesc {
+  int64_t off;    // vector offset
+  int64_t Nn;     // node count
+  int64_t joff;   // per-node Jacobian offset
+  int64_t nx;     // state count
+};
+
 // Four-step twiddles W_M^t = hi[t >> shift] * lo[t & (2^shift - 1)], one array pair per
 // precision, shared by every transform of length M in the plan.
 struct TwiddleSet {
@@ -206,6 +214,8 @@ struct birk_plan {
   birk::CompDesc* comps = nullptr;  // component table (device), one entry per component
   int64_t ncomp = 0;
   int64_t max_nn = 0;               // longest component
+  birk::InstDesc* idesc = nullptr;  // instance table (device)
+  void* newton_buf = nullptr;       // Newton workspace, allocated by the first Newton solve
   double* comp_val = nullptr;       // one double per component (last node, or a total)
   double* comp_part = nullptr;      // per-component reduction partials (CompDesc::part)
   int use_fast = 1;               // power-of-two N takes the three-pass path
@@ -263,6 +273,13 @@ hipError_t bform_correct_T(birk_plan* p, T* out, hipStream_t s);
 // xb[c] = xa[c] + w^T v_c.
 template <typename T>
 hipError_t endpoint(birk_plan* p, const double* xa, const T* v, double* xb, hipStream_t s);
+
+// ---- Newton solve of the nonlinear IVP (birk_newton.hip) ----
+hipError_t plan_instances(birk_plan* p);
+// Two-body right-hand side F and per-node Jacobian J (either may be null), n_x = 6.
+hipError_t two_body(birk_plan* p, double mu, double scale, const double* X, double* F, double* J, hipStream_t s);
+// G = X - xa - G per component (G holds B^a F on entry).
+hipError_t ivp_residual(birk_plan* p, const double* xa, const double* X, double* G, hipStream_t s);
 
 // ---- preconditioner, Jacobian products and Krylov kernels (birk_solve.hip) ----
 template <typename T>

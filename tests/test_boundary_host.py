@@ -15,6 +15,7 @@ HEADER = os.path.join(ROOT, "include", "birk.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"typedef[^;]*;", "", text)   # function-pointer and struct typedefs
     return sorted(set(re.findall(r"\b(birk_[A-Za-z0-9_]+)\s*\(", text)))
 
 
@@ -58,6 +59,36 @@ def test_struct_layouts(birk):
     assert ctypes.sizeof(birk.birk_solve_info) == 32
 
 
+def test_struct_layouts_match_the_c_header(birk, tmp_path):
+    """Sizes and field offsets of every struct in include/birk.h, from a C program compiled
+    against the header with gcc, equal those of the ctypes mirrors."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    structs = {"birk_solve_opts": birk.birk_solve_opts, "birk_solve_info": birk.birk_solve_info,
+               "birk_ivp_model": birk.birk_ivp_model, "birk_newton_opts": birk.birk_newton_opts,
+               "birk_newton_info": birk.birk_newton_info}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "birk.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            lines.append(f'  printf("{name}.{f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([gcc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f in cls._fields_:
+            assert int(got[f"{name}.{f[0]}"]) == getattr(cls, f[0]).offset, f"{name}.{f[0]}"
+
+
 @pytest.mark.parametrize("n_nodes,n_x,prec,expect", [
     ([2], [6], 0, -2),          # N_n < 3
     ([256], [0], 0, -2),        # n_x < 1
@@ -86,6 +117,8 @@ def test_null_arguments_are_rejected(birk):
     assert lib.birk_apply_b(None, None, None) == birk.BIRK_ERR_ARG
     assert lib.birk_apply_bT(None, None, None) == birk.BIRK_ERR_ARG
     assert lib.birk_endpoint(None, None, None, None) == birk.BIRK_ERR_ARG
+    assert lib.birk_two_body(None, 1.0, 1.0, None, None, None) == birk.BIRK_ERR_ARG
+    assert lib.birk_newton_ivp(None, None, None, None, None, None) == birk.BIRK_ERR_ARG
     assert lib.birk_precond(None, 0, None, None, None, 1) == birk.BIRK_ERR_ARG
     assert lib.birk_fast_ax(None, 0, None, None, None) == birk.BIRK_ERR_ARG
     assert lib.birk_krylov_solve(None, 0, None, None, None, None, None) == birk.BIRK_ERR_ARG
