@@ -74,9 +74,9 @@ def calibrate_copy():
     print(json.dumps({"calibrate_copy_bytes_each": n * 8, "copies": 3}), flush=True)
 
 
-def traffic_key(split, tb, xcd):
+def traffic_key(split, tb, xcd, narrow=0):
     from paper_2509_01855_amd.traffic import schedule_key
-    return schedule_key(split, tb, xcd)
+    return schedule_key(split, tb, xcd, narrow)
 
 
 def traffic_record(kernel_sources, schedule=None):
@@ -297,8 +297,8 @@ def main():
             tuned[name] = [ln.split(" chosen ")[0].split(":")[0] + ": " + ln.split(" chosen ")[1]
                            for ln in rep.splitlines() if " chosen " in ln]
             if name == "headline_f64":
-                m = re.search(r"chosen \[split (\d+), tb (\d+), xcd (\d+), streams \d+\]", rep)
-                head_sched = traffic_key(int(m.group(1)), int(m.group(2)), int(m.group(3)))
+                m = re.search(r"chosen \[split (\d+), tb (\d+), xcd (\d+), streams \d+, narrow (\d+)\]", rep)
+                head_sched = traffic_key(int(m.group(1)), int(m.group(2)), int(m.group(3)), int(m.group(4)))
         torch.cuda.synchronize()
 
     def step(timed: bool):

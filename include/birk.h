@@ -108,11 +108,13 @@ int64_t birk_plan_length(const birk_plan* plan);
 /* Autotuner of the power-of-two product path (N = 2^p >= 512).  For each group of
  * same-length components it times B^a (FastBV box) in the plan's precision over a
  * fixed set of tile schedules: both splits 2N = L1 L2 of the two-step DCTs, two or four
- * rows per middle-pass tile, the plain or XCD-grouped tile order, and the components on
- * one stream or in two or three parts on as many streams (forked from and joined back
- * into the plan's stream by events; same kernels per component).  In each of two
- * interleaved rounds a candidate runs once to warm up, then four times between events on
- * the plan's stream, alternating two input/output pairs; its best round counts.  The
+ * rows per middle-pass tile, the plain or XCD-grouped tile order, four- or eight-column
+ * tiles in the first and last passes where their transforms are 512 or 1024 points long,
+ * and the components on one stream or in two or three parts on as many streams (forked
+ * from and joined back into the plan's stream by events; same kernels per component).
+ * In each of two interleaved rounds a candidate runs once to warm up, then four times
+ * between events on the plan's stream, alternating two input/output pairs; its best
+ * round counts.  The
  * default schedule stays unless a candidate is more than 2 % faster; the choice stays
  * with the plan for every later product.  The schedule changes only the
  * order of floating-point operations (results stay within the product tolerance).

@@ -191,6 +191,8 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     if (xc) p->fast_kn.xcd = std::atoi(xc) ? 1 : 0;
     const char* b2 = std::getenv("BIRK_FAST_B2");
     if (b2) p->fast_kn.b2 = std::atoi(b2) ? 1 : 0;
+    const char* nw = std::getenv("BIRK_FAST_NARROW");
+    if (nw) p->fast_kn.narrow = std::atoi(nw) ? 1 : 0;
     const char* st = std::getenv("BIRK_FAST_STREAMS");
     if (st) p->fast_kn.streams = std::max(1, std::min(1 + birk_plan::kExtraStreams, std::atoi(st)));
   }

@@ -538,19 +538,33 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB2(
       acc += (double)Gc[n2].x * ((n2 == 0 || n2 == half2) ? 1.0 : 2.0);
     p0 = (T)(0.5 * block_sum(acc, red));
   }
-  // DCT-1 rows: y[rho][i] = row t0 - 1 + rho at m = tid + i NTHR, rho = 0..TB+1
+  // DCT-1 rows: y[rho][i] = row t0 - 1 + rho at m = tid + i NTHR, rho = 0..TB+1.  The
+  // loads of row pair pp + 1 are issued before the FFT of pair pp, so that they are in
+  // flight while it runs.
   T y[2 * NP][kPPT];
-#pragma unroll
-  for (int pp = 0; pp < NP; ++pp) {
-    int ma, mb;
-    const int sa = hrow_src(t0 - 1 + 2 * pp, L1, &ma);
-    const int sb = hrow_src(t0 + 2 * pp, L1, &mb);
-    constexpr int per = (hp1 + NTHR - 1) / NTHR;  // half-row elements per thread (5)
+  constexpr int per = (hp1 + NTHR - 1) / NTHR;  // half-row elements per thread (5)
+  cplx<T> na[per], nb[per];
+  int nma, nmb;
+  {
+    const int sa = hrow_src(t0 - 1, L1, &nma);
+    const int sb = hrow_src(t0, L1, &nmb);
 #pragma unroll
     for (int u = 0; u < per; ++u) {
       const int n2 = (int)threadIdx.x + u * NTHR;
       if (n2 < hp1) {
-        cplx<T> a = Gc[sa * sgi + n2], b = Gc[sb * sgi + n2];
+        na[u] = Gc[sa * sgi + n2];
+        nb[u] = Gc[sb * sgi + n2];
+      }
+    }
+  }
+#pragma unroll
+  for (int pp = 0; pp < NP; ++pp) {
+    const int ma = nma, mb = nmb;
+#pragma unroll
+    for (int u = 0; u < per; ++u) {
+      const int n2 = (int)threadIdx.x + u * NTHR;
+      if (n2 < hp1) {
+        cplx<T> a = na[u], b = nb[u];
         if (ma) a = conjg<T>(a);
         if (ma == 2) a = cmul<T>(a, tw[n2 << twsh]);
         if (mb) b = conjg<T>(b);
@@ -560,6 +574,18 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB2(
         if (n2 > 0 && n2 < half2) {
           Yre[pad(L2 - n2)] = a.x + b.y;
           Yim[pad(L2 - n2)] = b.x - a.y;
+        }
+      }
+    }
+    if (pp + 1 < NP) {
+      const int sa = hrow_src(t0 + 1 + 2 * pp, L1, &nma);
+      const int sb = hrow_src(t0 + 2 + 2 * pp, L1, &nmb);
+#pragma unroll
+      for (int u = 0; u < per; ++u) {
+        const int n2 = (int)threadIdx.x + u * NTHR;
+        if (n2 < hp1) {
+          na[u] = Gc[sa * sgi + n2];
+          nb[u] = Gc[sb * sgi + n2];
         }
       }
     }
@@ -951,6 +977,7 @@ static int fast_tiles_b(const FastKnobs& kn, int64_t N) {
 // columns, 4 at 2^11); returns log2 of the tile width, or 0 for the general kernels.
 static int fixed_logw(const FastKnobs& kn, int logL1) {
   if (!kn.b2 || logL1 < 8 || logL1 > 11) return 0;
+  if (kn.narrow && (logL1 == 9 || logL1 == 10)) return 2;
   return logL1 == 11 ? 2 : 3;
 }
 
@@ -1010,8 +1037,8 @@ static hipError_t fast_passes(birk_plan* p, const FastGroup& g, const T* v, T* o
     auto f = fast::k_fastA2<T, 10, 3>;
     switch (logL1) {
       case 8: f = fast::k_fastA2<T, 8, 3>; break;
-      case 9: f = fast::k_fastA2<T, 9, 3>; break;
-      case 10: f = fast::k_fastA2<T, 10, 3>; break;
+      case 9: f = lw == 2 ? fast::k_fastA2<T, 9, 2> : fast::k_fastA2<T, 9, 3>; break;
+      case 10: f = lw == 2 ? fast::k_fastA2<T, 10, 2> : fast::k_fastA2<T, 10, 3>; break;
       default: f = fast::k_fastA2<T, 11, 2>; break;
     }
     lds_attr(f, lds);
@@ -1082,10 +1109,10 @@ static hipError_t fast_passes(birk_plan* p, const FastGroup& g, const T* v, T* o
     switch (logL1 * 2 + (transpose ? 1 : 0)) {
       case 16: f = fast::k_fastC2<T, 0, 8, 3>; break;
       case 17: f = fast::k_fastC2<T, 1, 8, 3>; break;
-      case 18: f = fast::k_fastC2<T, 0, 9, 3>; break;
-      case 19: f = fast::k_fastC2<T, 1, 9, 3>; break;
-      case 20: f = fast::k_fastC2<T, 0, 10, 3>; break;
-      case 21: f = fast::k_fastC2<T, 1, 10, 3>; break;
+      case 18: f = lw == 2 ? fast::k_fastC2<T, 0, 9, 2> : fast::k_fastC2<T, 0, 9, 3>; break;
+      case 19: f = lw == 2 ? fast::k_fastC2<T, 1, 9, 2> : fast::k_fastC2<T, 1, 9, 3>; break;
+      case 20: f = lw == 2 ? fast::k_fastC2<T, 0, 10, 2> : fast::k_fastC2<T, 0, 10, 3>; break;
+      case 21: f = lw == 2 ? fast::k_fastC2<T, 1, 10, 2> : fast::k_fastC2<T, 1, 10, 3>; break;
       case 22: f = fast::k_fastC2<T, 0, 11, 2>; break;
       default: f = fast::k_fastC2<T, 1, 11, 2>; break;
     }
@@ -1106,21 +1133,35 @@ static hipError_t fast_passes(birk_plan* p, const FastGroup& g, const T* v, T* o
 }
 
 // Tile schedules the autotuner tries for a group: the defaults first, then both splits of
-// 2N = L1 L2, two or four rows per pass-B tile, both tile orders, one or two streams.
-static std::vector<FastKnobs> tune_candidates(const FastKnobs& base) {
+// 2N = L1 L2, two or four rows per pass-B tile, both tile orders, one to three streams,
+// and, where L1 is 2^9 or 2^10, tiles of four or eight columns in passes A and C.
+static int log_l1(const FastKnobs& kn, int64_t N) {
+  int s = 0;
+  while ((int64_t(1) << s) < 2 * N) ++s;
+  return kn.split == 0 ? s - (s + 1) / 2 : (s + 1) / 2;
+}
+
+static std::vector<FastKnobs> tune_candidates(const FastKnobs& base, int64_t N) {
   std::vector<FastKnobs> c{base};
   for (int split = 0; split < 2; ++split)
     for (int tb = 2; tb <= 4; tb += 2)
       for (int xcd = 0; xcd < 2; ++xcd)
-        for (int st = 1; st <= 3; ++st) {
-          FastKnobs k = base;
-          k.split = split;
-          k.tb = tb;
-          k.xcd = xcd;
-          k.streams = st;
-          if (k.split != base.split || k.tb != base.tb || k.xcd != base.xcd || k.streams != base.streams)
-            c.push_back(k);
-        }
+        for (int st = 1; st <= 3; ++st)
+          for (int nw = 0; nw < 2; ++nw) {
+            FastKnobs k = base;
+            k.split = split;
+            k.tb = tb;
+            k.xcd = xcd;
+            k.streams = st;
+            k.narrow = nw;
+            FastKnobs k0 = k;
+            k0.narrow = 0;
+            const int l1 = log_l1(k, N);
+            if (nw && fixed_logw(k, l1) == fixed_logw(k0, l1)) continue;   // no effect at this size
+            if (k.split != base.split || k.tb != base.tb || k.xcd != base.xcd || k.streams != base.streams ||
+                k.narrow != base.narrow)
+              c.push_back(k);
+          }
   return c;
 }
 
@@ -1165,7 +1206,7 @@ hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, in
 // autotuner may choose.
 void fast_sizes(const birk_plan* p, int64_t N, int nc, int64_t* work, int64_t* part) {
   int64_t w = 0, ntB = 0;
-  for (const FastKnobs& kn : tune_candidates(p->fast_kn)) {
+  for (const FastKnobs& kn : tune_candidates(p->fast_kn, N)) {
     int l1, l2, wa, tb, wc;
     fast_shape<double>(kn, N, l1, l2, wa, tb, wc);
     w = std::max(w, (int64_t)nc * ((int64_t(1) << l1) / 2 + 1) * ((int64_t(1) << l2) / 2 + 1));
@@ -1198,7 +1239,7 @@ static hipError_t tune_groups(birk_plan* p, hipStream_t s, std::string* report) 
   char line[160];
   for (FastGroup& g : p->fgroups) {
     if (e != hipSuccess) break;
-    const std::vector<FastKnobs> cand = tune_candidates(p->fast_kn);
+    const std::vector<FastKnobs> cand = tune_candidates(p->fast_kn, g.N);
     std::vector<float> best_of(cand.size(), 0.0f);
     for (int round = 0; round < kTuneRounds && e == hipSuccess; ++round) {
       for (size_t ci = 0; ci < cand.size() && e == hipSuccess; ++ci) {
@@ -1219,14 +1260,14 @@ static hipError_t tune_groups(birk_plan* p, hipStream_t s, std::string* report) 
     *report += line;
     size_t best = 0;
     for (size_t ci = 0; ci < cand.size(); ++ci) {
-      snprintf(line, sizeof line, " [split %d, tb %d, xcd %d, streams %d] %.1f us;", cand[ci].split, cand[ci].tb,
-               cand[ci].xcd, cand[ci].streams, 1000.0 * best_of[ci]);
+      snprintf(line, sizeof line, " [split %d, tb %d, xcd %d, streams %d, narrow %d] %.1f us;", cand[ci].split,
+               cand[ci].tb, cand[ci].xcd, cand[ci].streams, cand[ci].narrow, 1000.0 * best_of[ci]);
       *report += line;
       if (best_of[ci] < best_of[best] * (1.0f - kTuneMargin)) best = ci;
     }
     g.kn = cand[best];
-    snprintf(line, sizeof line, " chosen [split %d, tb %d, xcd %d, streams %d]\n", g.kn.split, g.kn.tb, g.kn.xcd,
-             g.kn.streams);
+    snprintf(line, sizeof line, " chosen [split %d, tb %d, xcd %d, streams %d, narrow %d]\n", g.kn.split, g.kn.tb,
+             g.kn.xcd, g.kn.streams, g.kn.narrow);
     *report += line;
   }
   if (e0) (void)hipEventDestroy(e0);

@@ -1,7 +1,8 @@
 """Turn rocprofv3 FETCH_SIZE / WRITE_SIZE runs into HBM bytes per B^a product.
 
 The record of one tile schedule (taken from the BIRK_FAST_SPLIT / BIRK_FAST_TB /
-BIRK_FAST_XCD environment of the counter runs, defaults 0 / 0 / 1) is merged into
+BIRK_FAST_XCD / BIRK_FAST_NARROW environment of the counter runs, defaults 0 / 0 / 1 / 0)
+is merged into
 <out.json>, which keeps one record per schedule for the current kernel sources.
 
 Usage (after the four counter runs described in profiles/README.md):
@@ -27,18 +28,22 @@ SOURCES = ["paper_2509_01855_amd/csrc/birk_fast.hip", "paper_2509_01855_amd/csrc
            "paper_2509_01855_amd/csrc/birk_fft.h"]
 
 
-def schedule_key(split, tb, xcd):
+def schedule_key(split, tb, xcd, narrow=0):
     """What fixes the kernels of the double product at N = 2^20: the split of 2N = L1 L2,
-    the rows per pass-B tile of the register kernel (4 when asked for, else 2) and the
-    tile order.  (The one- or two-stream schedule runs the same kernels.)"""
-    return {"split": 1 if split else 0, "rows_b": 4 if tb == 4 else 2, "xcd": 1 if xcd else 0}
+    the rows per pass-B tile of the register kernel (4 when asked for, else 2), the tile
+    order and the column tiles of passes A and C (4 with narrow where L1 = 2^10, else 8).
+    (The multi-stream schedules run the same kernels.)"""
+    narrow_applies = bool(narrow) and not split     # L1 = 2^10 only with split 0 at N = 2^20
+    return {"split": 1 if split else 0, "rows_b": 4 if tb == 4 else 2, "xcd": 1 if xcd else 0,
+            "cols_ac": 4 if narrow_applies else 8}
 
 
 def _schedule():
     """Tile schedule of the counter runs (bench.py --no-tune with the environment defaults)."""
     return schedule_key(int(os.environ.get("BIRK_FAST_SPLIT", "0")),
                         max(0, min(14, int(os.environ.get("BIRK_FAST_TB", "0")))) & ~1,
-                        int(os.environ.get("BIRK_FAST_XCD", "1")))
+                        int(os.environ.get("BIRK_FAST_XCD", "1")),
+                        int(os.environ.get("BIRK_FAST_NARROW", "0")))
 import re
 
 # forward double product: pass A, pass B (TRANS = 0), pass C (TRANS = 0); the

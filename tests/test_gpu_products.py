@@ -188,7 +188,11 @@ def test_autotuned_schedule_keeps_results(B, Nn, prec):
         before.append(host(out).astype(np.float64))
     report = B.birk_plan_tune(plan)
     print(report, flush=True)
-    assert "chosen" in report and report.count("us;") == 25
+    # 24 candidates and the default, plus 12 with narrow pass-A/C tiles for each split
+    # whose L1 is 2^9 or 2^10
+    s = (2 * (Nn - 1) - 1).bit_length()
+    l1s = (s - (s + 1) // 2, (s + 1) // 2)
+    assert "chosen" in report and report.count("us;") == 25 + 12 * sum(l in (9, 10) for l in l1s)
     after = []
     for t in (0, 1):
         out = torch.empty_like(v)
