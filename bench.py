@@ -285,7 +285,9 @@ def main():
 
     # autotuner of the power-of-two product path (plan setup, outside the timed region)
     tuned = {}
-    head_sched = traffic_key(0, 0, 1)  # defaults unless the tuner picks another
+    # the double plan's default schedule unless the tuner picks another
+    head_sched = traffic_key(int(os.environ.get("BIRK_FAST_SPLIT", "0")), int(os.environ.get("BIRK_FAST_TB", "0")),
+                             int(os.environ.get("BIRK_FAST_XCD", "1")), int(os.environ.get("BIRK_FAST_NARROW", "1")))
     if not a.no_tune:
         print("[bench] autotuning the power-of-two plans", file=sys.stderr, flush=True)
         tplans = {"headline_f64": plan64, "headline_f32": planmx}

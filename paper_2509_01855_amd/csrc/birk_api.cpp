@@ -191,6 +191,9 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     if (xc) p->fast_kn.xcd = std::atoi(xc) ? 1 : 0;
     const char* b2 = std::getenv("BIRK_FAST_B2");
     if (b2) p->fast_kn.b2 = std::atoi(b2) ? 1 : 0;
+    // four-column tiles in passes A and C measured faster for 8-byte reals (double and
+    // double-float), eight-column ones for float
+    p->fast_kn.narrow = prec == BIRK_F32 || prec == BIRK_F32_REFINE_F64 ? 0 : 1;
     const char* nw = std::getenv("BIRK_FAST_NARROW");
     if (nw) p->fast_kn.narrow = std::atoi(nw) ? 1 : 0;
     const char* st = std::getenv("BIRK_FAST_STREAMS");

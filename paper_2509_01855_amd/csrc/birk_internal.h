@@ -83,7 +83,8 @@ struct FastKnobs {
   int b2 = 1;                 // compile-time-length kernels where they apply
   int streams = 1;            // 2 or 3: the components run in that many parts on as many
                               // streams, so that one part's next pass fills another's tail
-  int narrow = 0;             // 1: passes A and C of L1 = 2^9, 2^10 in tiles of 4 columns (else 8)
+  int narrow = 0;             // 1: passes A and C of L1 = 2^9, 2^10 in tiles of 4 columns (else 8);
+                              // plans of 8-byte reals start with 1
 };
 
 struct FastGroup {

@@ -1,7 +1,8 @@
 """Turn rocprofv3 FETCH_SIZE / WRITE_SIZE runs into HBM bytes per B^a product.
 
 The record of one tile schedule (taken from the BIRK_FAST_SPLIT / BIRK_FAST_TB /
-BIRK_FAST_XCD / BIRK_FAST_NARROW environment of the counter runs, defaults 0 / 0 / 1 / 0)
+BIRK_FAST_XCD / BIRK_FAST_NARROW environment of the counter runs, defaults 0 / 0 / 1 / 1
+for a double plan)
 is merged into
 <out.json>, which keeps one record per schedule for the current kernel sources.
 
@@ -43,7 +44,7 @@ def _schedule():
     return schedule_key(int(os.environ.get("BIRK_FAST_SPLIT", "0")),
                         max(0, min(14, int(os.environ.get("BIRK_FAST_TB", "0")))) & ~1,
                         int(os.environ.get("BIRK_FAST_XCD", "1")),
-                        int(os.environ.get("BIRK_FAST_NARROW", "0")))
+                        int(os.environ.get("BIRK_FAST_NARROW", "1")))
 import re
 
 # forward double product: pass A, pass B (TRANS = 0), pass C (TRANS = 0); the
