@@ -8,7 +8,8 @@ One step is one pass of the whole hot path:
   * headline: B^a v (FastBV) in double, once per buffer of a rotation of R
     input/output pairs whose footprint exceeds the 256 MB Infinity Cache, so that every
     product reads its input from HBM; B^aT g in double (same rotation); B^a v in float;
-    P^{-1} y (inverse-preconditioner scan) in double; the preconditioned GMRES solve to
+    P^{-1} y (inverse-preconditioner scan) and P y in double; FastAX (x - B^a (J x)) in
+    double; the preconditioned GMRES solve to
     relative residual 1e-10, once with float Krylov bulk inside double refinement
     (mixed) and once in double (FP64); the b-form products B^b v, B^bT g and the
     endpoint row x^b = x^a + w^T v in double; Newton's method on the nonlinear two-body
@@ -311,6 +312,8 @@ def main():
         for i in range(2):
             tm.region("apply_f32", lambda i=i: B.birk_apply(planmx, v32[i], o32[i]))
         tm.region("pinv", lambda: B.birk_precond(plan64, J, vin[0], vout[1], 1, B.BIRK_J_PER_NODE))
+        tm.region("fast_ax", lambda: B.birk_fast_ax(plan64, J, vin[0], vout[0], B.BIRK_J_PER_NODE))
+        tm.region("pfwd", lambda: B.birk_precond(plan64, J, vin[1], vout[1], 0, B.BIRK_J_PER_NODE))
         tm.region("apply_b", lambda: B.birk_apply_b(plan64, vin[1], vout[0]))
         tm.region("apply_bT", lambda: B.birk_apply_bT(plan64, vin[0], vout[1]))
         tm.region("endpoint", lambda: B.birk_endpoint(plan64, xa_end, vin[1], xb_end))
@@ -370,6 +373,7 @@ def main():
                                "P^{-1}, preconditioned GMRES to 1e-10",
                    "N_n": Nn, "n_x": nx, "n": n, "rotation_buffers": R,
                    "products_per_step": {"apply_f64": R, "apply_T_f64": R, "apply_f32": 2, "precond_inverse": 1,
+                                         "precond_forward": 1, "fast_ax_f64": 1,
                                          "apply_b_f64": 1, "apply_bT_f64": 1, "endpoint_f64": 1,
                                          "solves": 0 if a.products_only else 2}},
         "roofline": {"bound": "hbm", "kernel": "birk_apply (FastBV, three-pass, double)",
@@ -385,6 +389,8 @@ def main():
             "apply_f32_us": us("apply_f32"),
             "apply_f32_gpts": round(n / (tm.mean_ms("apply_f32") * 1e-3) / 1e9, 3),
             "precond_inverse_f64_us": us("pinv"),
+            "precond_forward_f64_us": us("pfwd"),
+            "fast_ax_f64_us": us("fast_ax"),
             "apply_b_f64_us": us("apply_b"),
             "apply_bT_f64_us": us("apply_bT"),
             "endpoint_f64_us": us("endpoint"),

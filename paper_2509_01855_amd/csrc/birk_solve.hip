@@ -60,7 +60,14 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
   return r;
 }
 
-// grid = (blocks over nodes, nx)
+// P y = y - B~^a (J y) per component r: an exclusive prefix sum of u_k = w_k (J_k y_k)_r
+// plus half the node's own term (B~^a: w_j below the diagonal, w_k / 2 on it).  Three
+// launches: block sums over tiles of kScanBlock nodes, an exclusive scan of the block sums
+// (one workgroup per component), and the final pass, which rebuilds u and scans inside
+// the tile.  Global accesses are coalesced (node k = tile base + i * 256 + thread); the
+// final pass moves u through LDS to scan it in node order.
+
+// grid = (tiles over nodes, nx)
 template <typename T>
 __global__ __launch_bounds__(256) void k_pfwd_sums(const double* __restrict__ J, int per_node,
                                                    const T* __restrict__ y, const double* __restrict__ w,
@@ -69,22 +76,45 @@ __global__ __launch_bounds__(256) void k_pfwd_sums(const double* __restrict__ J,
   const int r = blockIdx.y;
   const int64_t base = (int64_t)blockIdx.x * kScanBlock;
   double acc = 0.0;
+#pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    const int64_t k = base + threadIdx.x * kScanItems + i;
+    const int64_t k = base + i * 256 + threadIdx.x;
     if (k < Nn) acc += wju<T>(J, per_node, y, w, r, nx, Nn, k);
   }
   const double s = block_sum256(acc, sh);
   if (threadIdx.x == 0) part[(int64_t)r * gridDim.x + blockIdx.x] = s;
 }
 
-__global__ void k_pfwd_scanparts(double* __restrict__ part, int nblk, int nx) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nx) return;
-  double run = 0.0;
-  for (int b = 0; b < nblk; ++b) {
-    const double v = part[(int64_t)r * nblk + b];
-    part[(int64_t)r * nblk + b] = run;
-    run += v;
+// Inclusive scan of v over the 256 threads of the workgroup (Hillis-Steele in LDS).
+__device__ __forceinline__ double block_scan256(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = 1; st < 256; st <<= 1) {
+    const double a = threadIdx.x >= st ? sh[threadIdx.x - st] : 0.0;
+    __syncthreads();
+    sh[threadIdx.x] += a;
+    __syncthreads();
+  }
+  const double r = sh[threadIdx.x];
+  __syncthreads();
+  return r;
+}
+
+// Exclusive scan of the nblk tile sums of component r = blockIdx.x, in chunks of 256.
+__global__ __launch_bounds__(256) void k_pfwd_scanparts(double* __restrict__ part, int nblk) {
+  __shared__ double sh[256];
+  __shared__ double total;
+  double* pr = part + (int64_t)blockIdx.x * nblk;
+  double carry = 0.0;
+  for (int b0 = 0; b0 < nblk; b0 += 256) {
+    const int b = b0 + (int)threadIdx.x;
+    const double v = b < nblk ? pr[b] : 0.0;
+    const double incl = block_scan256(v, sh);
+    if (b < nblk) pr[b] = carry + incl - v;
+    if (threadIdx.x == 255) total = incl;
+    __syncthreads();
+    carry += total;
+    __syncthreads();
   }
 }
 
@@ -93,33 +123,36 @@ __global__ __launch_bounds__(256) void k_pfwd_final(const double* __restrict__ J
                                                     const T* __restrict__ y, const double* __restrict__ w,
                                                     int nx, int64_t Nn, const double* __restrict__ part,
                                                     T* __restrict__ out) {
+  __shared__ double su[kScanBlock];
   __shared__ double sh[256];
   const int r = blockIdx.y;
   const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t k = base + i * 256 + threadIdx.x;
+    su[i * 256 + threadIdx.x] = (k < Nn) ? wju<T>(J, per_node, y, w, r, nx, Nn, k) : 0.0;
+  }
+  __syncthreads();
+  // thread t scans nodes base + kScanItems t + j, j < kScanItems, in order
   double u[kScanItems];
   double tsum = 0.0;
-  for (int i = 0; i < kScanItems; ++i) {
-    const int64_t k = base + threadIdx.x * kScanItems + i;
-    u[i] = (k < Nn) ? wju<T>(J, per_node, y, w, r, nx, Nn, k) : 0.0;
-    tsum += u[i];
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    u[j] = su[threadIdx.x * kScanItems + j];
+    tsum += u[j];
   }
-  // exclusive scan of the per-thread sums (Hillis-Steele in LDS)
-  sh[threadIdx.x] = tsum;
+  double run = part[(int64_t)r * gridDim.x + blockIdx.x] + block_scan256(tsum, sh) - tsum;
+  // block_scan256 ends with a barrier, so every thread has read its u before su is reused
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    su[threadIdx.x * kScanItems + j] = run + 0.5 * u[j];
+    run += u[j];
+  }
   __syncthreads();
-  for (int st = 1; st < 256; st <<= 1) {
-    const double v = threadIdx.x >= st ? sh[threadIdx.x - st] : 0.0;
-    __syncthreads();
-    sh[threadIdx.x] += v;
-    __syncthreads();
-  }
-  double run = part[(int64_t)r * gridDim.x + blockIdx.x] + sh[threadIdx.x] - tsum;
+#pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    const int64_t k = base + threadIdx.x * kScanItems + i;
-    if (k < Nn) {
-      const double bt = run + 0.5 * u[i];
-      out[(int64_t)r * Nn + k] = (T)((double)y[(int64_t)r * Nn + k] - bt);
-    }
-    run += u[i];
+    const int64_t k = base + i * 256 + threadIdx.x;
+    if (k < Nn) out[(int64_t)r * Nn + k] = (T)((double)y[(int64_t)r * Nn + k] - su[i * 256 + threadIdx.x]);
   }
 }
 
@@ -133,7 +166,7 @@ hipError_t precond_forward(birk_plan* p, int jac_kind, const double* J, const T*
     double* part = p->scan + in.scan_off;  // nx * nblk doubles (fits: scan scratch is larger)
     hipLaunchKernelGGL(k_pfwd_sums<T>, dim3(nblk, in.nx), dim3(256), 0, s, Ji, pn, y + in.off, in.w,
                        in.nx, in.Nn, part);
-    hipLaunchKernelGGL(k_pfwd_scanparts, dim3(1), dim3(64), 0, s, part, nblk, in.nx);
+    hipLaunchKernelGGL(k_pfwd_scanparts, dim3(in.nx), dim3(256), 0, s, part, nblk);
     hipLaunchKernelGGL(k_pfwd_final<T>, dim3(nblk, in.nx), dim3(256), 0, s, Ji, pn, y + in.off, in.w,
                        in.nx, in.Nn, part, out + in.off);
   }
