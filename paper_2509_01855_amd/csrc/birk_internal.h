@@ -56,10 +56,13 @@ constexpr int kCompTiles = 256;  // most reduction tiles per component
 
 // One instance, for the node-wise model kernels of the Newton solve (birk_newton.hip).
 struct InstDesc {
-  int64_t off;    // vector offset
-  int64_t Nn;     // node count
-  int64_t joff;   // per-node Jacobian offset
-  int64_t nx;     // state count
+  int64_t off;       // vector offset
+  int64_t Nn;        // node count
+  int64_t joff;      // per-node Jacobian offset
+  int64_t nx;        // state count
+  int64_t jcoff;     // constant Jacobian offset
+  int64_t scan_off;  // offset into the preconditioner scan scratch
+  const double* w;   // CC weights
 };
 
 // Four-step twiddles W_M^t = hi[t >> shift] * lo[t & (2^shift - 1)], one array pair per
@@ -217,6 +220,10 @@ struct birk_plan {
   int64_t ncomp = 0;
   int64_t max_nn = 0;               // longest component
   birk::InstDesc* idesc = nullptr;  // instance table (device)
+  int2* pfwd_tiles = nullptr;       // P y tiles: (instance, component * tiles + tile)
+  int pfwd_ntiles = 0;
+  int2* pfwd_pairs = nullptr;       // P y scans: (instance, component)
+  int pfwd_npairs = 0;
   void* newton_buf = nullptr;       // Newton workspace, allocated by the first Newton solve
   double* comp_val = nullptr;       // one double per component (last node, or a total)
   double* comp_part = nullptr;      // per-component reduction partials (CompDesc::part)

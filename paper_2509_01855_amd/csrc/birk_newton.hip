@@ -82,7 +82,8 @@ inline unsigned node_tiles(const birk_plan* p) {
 hipError_t plan_instances(birk_plan* p) {
   std::vector<InstDesc> h;
   h.reserve(p->inst.size());
-  for (const Instance& in : p->inst) h.push_back({in.off, in.Nn, in.joff, (int64_t)in.nx});
+  for (const Instance& in : p->inst)
+    h.push_back({in.off, in.Nn, in.joff, (int64_t)in.nx, in.jcoff, in.scan_off, in.w});
   void* d = nullptr;
   hipError_t e = hipMalloc(&d, h.size() * sizeof(InstDesc));
   if (e != hipSuccess) return e;

@@ -67,22 +67,31 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
 // the tile.  Global accesses are coalesced (node k = tile base + i * 256 + thread); the
 // final pass moves u through LDS to scan it in node order.
 
-// grid = (tiles over nodes, nx)
+// One workgroup per tile of kScanBlock nodes of one component of one instance, over the
+// whole batch: tile = (instance, component * ntiles + tile index); the tile sums of
+// (instance i, component r) sit at scan[scan_off(i) + r * ntiles(i) + tile].
+__device__ __forceinline__ int pfwd_ntiles(int64_t Nn) { return (int)((Nn + kScanBlock - 1) / kScanBlock); }
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_pfwd_sums(const double* __restrict__ J, int per_node,
-                                                   const T* __restrict__ y, const double* __restrict__ w,
-                                                   int nx, int64_t Nn, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_pfwd_sums(const int2* __restrict__ tiles, const InstDesc* __restrict__ idesc,
+                                                   const double* __restrict__ J, int per_node,
+                                                   const T* __restrict__ y, double* __restrict__ scan) {
   __shared__ double sh[256];
-  const int r = blockIdx.y;
-  const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  const int2 t = tiles[blockIdx.x];
+  const InstDesc d = idesc[t.x];
+  const int nt = pfwd_ntiles(d.Nn);
+  const int r = t.y / nt, b = t.y - r * nt;
+  const double* Ji = J + (per_node ? d.joff : d.jcoff);
+  const T* yi = y + d.off;
+  const int64_t base = (int64_t)b * kScanBlock;
   double acc = 0.0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     const int64_t k = base + i * 256 + threadIdx.x;
-    if (k < Nn) acc += wju<T>(J, per_node, y, w, r, nx, Nn, k);
+    if (k < d.Nn) acc += wju<T>(Ji, per_node, yi, d.w, r, (int)d.nx, d.Nn, k);
   }
   const double s = block_sum256(acc, sh);
-  if (threadIdx.x == 0) part[(int64_t)r * gridDim.x + blockIdx.x] = s;
+  if (threadIdx.x == 0) scan[d.scan_off + t.y] = s;
 }
 
 // Inclusive scan of v over the 256 threads of the workgroup (Hillis-Steele in LDS).
@@ -100,11 +109,17 @@ __device__ __forceinline__ double block_scan256(double v, double* sh) {
   return r;
 }
 
-// Exclusive scan of the nblk tile sums of component r = blockIdx.x, in chunks of 256.
-__global__ __launch_bounds__(256) void k_pfwd_scanparts(double* __restrict__ part, int nblk) {
+// Exclusive scan of the tile sums of one (instance, component) per workgroup, in chunks
+// of 256.
+__global__ __launch_bounds__(256) void k_pfwd_scanparts(const int2* __restrict__ pairs,
+                                                        const InstDesc* __restrict__ idesc,
+                                                        double* __restrict__ scan) {
   __shared__ double sh[256];
   __shared__ double total;
-  double* pr = part + (int64_t)blockIdx.x * nblk;
+  const int2 q = pairs[blockIdx.x];
+  const InstDesc d = idesc[q.x];
+  const int nblk = pfwd_ntiles(d.Nn);
+  double* pr = scan + d.scan_off + (int64_t)q.y * nblk;
   double carry = 0.0;
   for (int b0 = 0; b0 < nblk; b0 += 256) {
     const int b = b0 + (int)threadIdx.x;
@@ -119,18 +134,23 @@ __global__ __launch_bounds__(256) void k_pfwd_scanparts(double* __restrict__ par
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_pfwd_final(const double* __restrict__ J, int per_node,
-                                                    const T* __restrict__ y, const double* __restrict__ w,
-                                                    int nx, int64_t Nn, const double* __restrict__ part,
+__global__ __launch_bounds__(256) void k_pfwd_final(const int2* __restrict__ tiles, const InstDesc* __restrict__ idesc,
+                                                    const double* __restrict__ J, int per_node,
+                                                    const T* __restrict__ y, const double* __restrict__ scan,
                                                     T* __restrict__ out) {
   __shared__ double su[kScanBlock];
   __shared__ double sh[256];
-  const int r = blockIdx.y;
-  const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  const int2 t = tiles[blockIdx.x];
+  const InstDesc d = idesc[t.x];
+  const int nt = pfwd_ntiles(d.Nn);
+  const int r = t.y / nt, b = t.y - r * nt;
+  const double* Ji = J + (per_node ? d.joff : d.jcoff);
+  const T* yi = y + d.off;
+  const int64_t base = (int64_t)b * kScanBlock;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     const int64_t k = base + i * 256 + threadIdx.x;
-    su[i * 256 + threadIdx.x] = (k < Nn) ? wju<T>(J, per_node, y, w, r, nx, Nn, k) : 0.0;
+    su[i * 256 + threadIdx.x] = (k < d.Nn) ? wju<T>(Ji, per_node, yi, d.w, r, (int)d.nx, d.Nn, k) : 0.0;
   }
   __syncthreads();
   // thread t scans nodes base + kScanItems t + j, j < kScanItems, in order
@@ -141,18 +161,20 @@ __global__ __launch_bounds__(256) void k_pfwd_final(const double* __restrict__ J
     u[j] = su[threadIdx.x * kScanItems + j];
     tsum += u[j];
   }
-  double run = part[(int64_t)r * gridDim.x + blockIdx.x] + block_scan256(tsum, sh) - tsum;
-  // block_scan256 ends with a barrier, so every thread has read its u before su is reused
+  double run = scan[d.scan_off + t.y] + block_scan256(tsum, sh) - tsum;
+  // each thread rewrites only the entries it read itself
 #pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
     su[threadIdx.x * kScanItems + j] = run + 0.5 * u[j];
     run += u[j];
   }
   __syncthreads();
+  T* oi = out + d.off + (int64_t)r * d.Nn;
+  const T* yr = yi + (int64_t)r * d.Nn;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     const int64_t k = base + i * 256 + threadIdx.x;
-    if (k < Nn) out[(int64_t)r * Nn + k] = (T)((double)y[(int64_t)r * Nn + k] - su[i * 256 + threadIdx.x]);
+    if (k < d.Nn) oi[k] = (T)((double)yr[k] - su[i * 256 + threadIdx.x]);
   }
 }
 
@@ -160,16 +182,11 @@ template <typename T>
 hipError_t precond_forward(birk_plan* p, int jac_kind, const double* J, const T* y, T* out,
                            hipStream_t s) {
   const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
-  for (const Instance& in : p->inst) {
-    const double* Ji = J + (pn ? in.joff : in.jcoff);
-    const int nblk = (int)((in.Nn + kScanBlock - 1) / kScanBlock);
-    double* part = p->scan + in.scan_off;  // nx * nblk doubles (fits: scan scratch is larger)
-    hipLaunchKernelGGL(k_pfwd_sums<T>, dim3(nblk, in.nx), dim3(256), 0, s, Ji, pn, y + in.off, in.w,
-                       in.nx, in.Nn, part);
-    hipLaunchKernelGGL(k_pfwd_scanparts, dim3(in.nx), dim3(256), 0, s, part, nblk);
-    hipLaunchKernelGGL(k_pfwd_final<T>, dim3(nblk, in.nx), dim3(256), 0, s, Ji, pn, y + in.off, in.w,
-                       in.nx, in.Nn, part, out + in.off);
-  }
+  hipLaunchKernelGGL(k_pfwd_sums<T>, dim3(p->pfwd_ntiles), dim3(256), 0, s, p->pfwd_tiles, p->idesc, J, pn, y,
+                     p->scan);
+  hipLaunchKernelGGL(k_pfwd_scanparts, dim3(p->pfwd_npairs), dim3(256), 0, s, p->pfwd_pairs, p->idesc, p->scan);
+  hipLaunchKernelGGL(k_pfwd_final<T>, dim3(p->pfwd_ntiles), dim3(256), 0, s, p->pfwd_tiles, p->idesc, J, pn, y,
+                     (const double*)p->scan, out);
   return hipGetLastError();
 }
 
@@ -1173,6 +1190,23 @@ static hipError_t upload_tiles(birk_plan* p, const std::vector<int2>& v, int2** 
 
 hipError_t plan_solve(birk_plan* p) {
   hipError_t e = hipSuccess;
+  {
+    // P y work lists: every tile of every component of every instance, and every
+    // (instance, component) scan
+    std::vector<int2> tl, pr;
+    for (int i = 0; i < (int)p->inst.size(); ++i) {
+      const Instance& in = p->inst[i];
+      const int nt = (int)((in.Nn + kScanBlock - 1) / kScanBlock);
+      for (int r = 0; r < in.nx; ++r) {
+        pr.push_back(make_int2(i, r));
+        for (int b = 0; b < nt; ++b) tl.push_back(make_int2(i, r * nt + b));
+      }
+    }
+    if ((e = upload_tiles(p, tl, &p->pfwd_tiles)) != hipSuccess) return e;
+    p->pfwd_ntiles = (int)tl.size();
+    if ((e = upload_tiles(p, pr, &p->pfwd_pairs)) != hipSuccess) return e;
+    p->pfwd_npairs = (int)pr.size();
+  }
   p->pclass.clear();
   for (int nx = 1; nx <= 12; ++nx) {
     PinvClass pc;

@@ -118,3 +118,39 @@ def test_fast_ax(B, kind, Nn, nx):
     ref = sy.apply_A(dense_Ba(Nn - 1), inst.J, x)
     assert rel_err(host(out), ref) <= 1e-12
     plan.destroy()
+
+
+@pytest.mark.parametrize("jkind", ["per_node", "constant"])
+def test_precond_batched_instances(B, jkind):
+    """P y and P^{-1} y over a batch of uneven instances in one plan (one set of launches
+    for the whole batch), each instance against the oracle; 2^18 + 1 nodes give a
+    component more than 256 tiles, so the scan of the tile sums takes two chunks."""
+    import torch
+    Nn_list = [3, 300, 1025, 4097, (1 << 18) + 1, 70001]
+    nx_list = [1, 6, 4, 12, 3, 2]
+    announce(f"precond batched {jkind}")
+    rng = np.random.default_rng(70)
+    Js, ys = [], []
+    for Nn, nx in zip(Nn_list, nx_list):
+        if jkind == "per_node":
+            J = rng.standard_normal((nx, nx, Nn)) / np.sqrt(nx) - 2.0 * np.eye(nx)[:, :, None]
+        else:
+            J = rng.standard_normal((nx, nx)) / np.sqrt(nx) - 2.0 * np.eye(nx)
+        Js.append(J)
+        ys.append(rng.standard_normal(nx * Nn))
+    jk = B.BIRK_J_PER_NODE if jkind == "per_node" else B.BIRK_J_CONSTANT
+    plan = B.birk_plan_create(Nn_list, nx_list, B.BIRK_F64)
+    Jd = dev(np.concatenate([J.ravel() for J in Js]), torch.float64)
+    yd = dev(np.concatenate(ys), torch.float64)
+    for inverse in (0, 1):
+        out = torch.empty_like(yd)
+        B.birk_precond(plan, Jd, yd, out, inverse, jk)
+        torch.cuda.synchronize()
+        got = host(out)
+        o = 0
+        for Nn, nx, J, y in zip(Nn_list, nx_list, Js, ys):
+            w = bk.weights(Nn - 1)
+            ref = sy.precond_inverse(w, J, y) if inverse else sy.precond_apply(w, J, y)
+            assert rel_err(got[o:o + nx * Nn], ref) <= 1e-12
+            o += nx * Nn
+    plan.destroy()
