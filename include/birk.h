@@ -258,7 +258,7 @@ typedef struct {
 /* The two-body right-hand side F = scale (v, -mu r / |r|^3) and its Jacobian
  * J = scale [[0, I], [mu (3 r r^T / |r|^2 - I) / |r|^3, 0]] at every node of every
  * instance (all instances need n_x = 6: components r_x, r_y, r_z, v_x, v_y, v_z).
- * X, F, J: device, double; F or J may be NULL (not both); neither may be X.
+ * X, F, J: device, double; F or J may be NULL (not both); no two may be the same array.
  * Asynchronous.  Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED (an instance with n_x != 6). */
 birk_status birk_two_body(birk_plan* plan, double mu, double scale, const double* X, double* F, double* J);
 

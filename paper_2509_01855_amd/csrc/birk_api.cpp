@@ -878,7 +878,7 @@ void birk_newton_opts_default(birk_newton_opts* o) {
 }
 
 birk_status birk_two_body(birk_plan* p, double mu, double scale, const double* X, double* F, double* J) {
-  if (!p || !X || (!F && !J) || X == F || X == J) return BIRK_ERR_ARG;
+  if (!p || !X || (!F && !J) || X == F || X == J || (F && F == J)) return BIRK_ERR_ARG;
   for (const auto& in : p->inst)
     if (in.nx != 6) return BIRK_ERR_UNSUPPORTED;
   DeviceGuard g(p->device);
