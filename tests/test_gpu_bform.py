@@ -287,3 +287,40 @@ def test_bform_graph_mode_and_repeat_calls(B):
                         assert rel_err(got, bk.apply_Bb_extended(Nn - 1, X, transpose=bool(tr))) <= TOL["f64"]
         plan_g.destroy()
         plan_e.destroy()
+
+
+def test_bform_more_components_than_one_grid_row(B):
+    """72,000 components (12,000 instances of n_x = 6 at N_n = 3 and 5): the component
+    loops of the correction and reduction kernels wrap around the 65,535 grid rows."""
+    import torch
+    Nn_list = [3] * 11000 + [5] * 1000
+    nx = 6
+    announce(f"b-form with {len(Nn_list) * nx} components")
+    rng = np.random.default_rng(35)
+    flat = rng.standard_normal(sum(Nn_list) * nx)
+    xa = rng.standard_normal(len(Nn_list) * nx)
+    plan = B.birk_plan_create(Nn_list, [nx] * len(Nn_list), B.BIRK_F64)
+    v = dev(flat, torch.float64)
+    outs = []
+    for fn in (B.birk_apply_b, B.birk_apply_bT):
+        out = torch.empty_like(v)
+        fn(plan, v, out)
+        outs.append(out)
+    xa_d = dev(xa, torch.float64)
+    xb_d = torch.empty_like(xa_d)
+    B.birk_endpoint(plan, xa_d, v, xb_d)
+    torch.cuda.synchronize()
+    got_b, got_bt, got_xb = host(outs[0]), host(outs[1]), host(xb_d)
+    plan.destroy()
+    o = 0
+    c = 0
+    for Nn, count in ((3, 11000), (5, 1000)):
+        Bb = bk.dense_Bb_quadrature(Nn - 1)
+        w = bk.weights(Nn - 1)
+        m = count * nx
+        V = flat[o:o + m * Nn].reshape(m, Nn)
+        assert np.max(np.abs(got_b[o:o + m * Nn].reshape(m, Nn) - V @ Bb.T)) <= 1e-13 * max(1.0, np.max(np.abs(V)))
+        assert np.max(np.abs(got_bt[o:o + m * Nn].reshape(m, Nn) - V @ Bb)) <= 1e-13 * max(1.0, np.max(np.abs(V)))
+        assert np.max(np.abs(got_xb[c:c + m] - (xa[c:c + m] + V @ w))) <= 1e-13 * max(1.0, np.max(np.abs(V)))
+        o += m * Nn
+        c += m
