@@ -1040,7 +1040,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const T* __restric
   const T* yi = y + d.off;
   T* oi = out + d.off;
   T* ji = jout ? jout + d.off : nullptr;
-#pragma unroll 1
+  // the thread's four nodes of y are loaded together, so that the loads of one 32-byte
+  // sector are issued back to back
+  double yv[kTC][NX];
+#pragma unroll
+  for (int j = 0; j < kTC; ++j)
+#pragma unroll
+    for (int r = 0; r < NX; ++r) yv[j][r] = (k0 + j < Nn) ? (double)yi[(int64_t)r * Nn + k0 + j] : 0.0;
+#pragma unroll
   for (int j = 0; j < kTC; ++j) {
     const int64_t k = k0 + j;
     if (k >= Nn) break;
@@ -1048,7 +1055,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const T* __restric
     const double inv_w = 1.0 / (double)base[(E - 1) * kTileThreads];
     double u[NX];
 #pragma unroll
-    for (int r = 0; r < NX; ++r) u[r] = s[r] + (double)yi[(int64_t)r * Nn + k];
+    for (int r = 0; r < NX; ++r) u[r] = s[r] + yv[j][r];
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
       double v = 0.0;
