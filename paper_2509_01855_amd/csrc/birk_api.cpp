@@ -575,19 +575,19 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, const double* r, 
     const TK* qj = Q + (size_t)j * ld;
     TK* z = Z + (size_t)j * ld;
     if (Yb) y = Yb + (size_t)j * ld;
-    // z = P^{-1} q_j, y = J z; t = B^a y; u = z - t
+    // z = P^{-1} q_j, y = J z; t = B^a y; u = z - t (formed with the first dot products)
+    const TK* uz = qj;
     if (use_precond) {
       e = precond_inverse<TK>(p, jk, J, qj, z, y, s, p->flag);
       if (e != hipSuccess) return BIRK_ERR_DEVICE;
       e = apply_product<TK>(p, y, t, 0, s);
       if (e != hipSuccess) return BIRK_ERR_DEVICE;
-      kry::sub<TK>(z, t, u, n, s);
+      uz = z;
     } else {
       e = jac_times<TK>(p, jk, J, qj, y, s);
       if (e != hipSuccess) return BIRK_ERR_DEVICE;
       e = apply_product<TK>(p, y, t, 0, s);
       if (e != hipSuccess) return BIRK_ERR_DEVICE;
-      kry::sub<TK>(qj, t, u, n, s);
     }
     // CGS2 on every instance at once (segmented launches; stopped instances are
     // carried along and their results ignored)
@@ -595,7 +595,7 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, const double* r, 
       double* d1 = p->krylov_dots;
       double* d2 = d1 + kDotsStride;
       const int64_t ds = 2 * kDotsStride;
-      kry::sdots<TK>(p, Q, j + 1, u, d1, ds, s);
+      kry::sub_sdots<TK>(p, Q, j + 1, uz, t, u, d1, ds, s);
       kry::saxpys_dots<TK>(p, Q, j + 1, d1, ds, u, d2, ds, s);
       kry::saxpys<TK>(p, Q, j + 1, d2, ds, u, d2, s);
       kry::snormalize<TK>(p, u, d2 + kKryMaxDots, ds, Q + (size_t)(j + 1) * ld, s);

@@ -320,6 +320,10 @@ void residual(const double* beta, const double* x, const double* t, double* r, i
 // instance i results at out + i * ostride).
 template <typename T>
 void sdots(const birk_plan* p, const T* Q, int nq, const T* u, double* out, int64_t ostride, hipStream_t s);
+// u = a - b, then the dots of sdots, in one pass
+template <typename T>
+void sub_sdots(const birk_plan* p, const T* Q, int nq, const T* a, const T* b, T* u, double* out, int64_t ostride,
+               hipStream_t s);
 template <typename T>
 void saxpys(const birk_plan* p, const T* Q, int nq, const double* h, int64_t hstride, T* u, double* nrm_out,
             hipStream_t s);

@@ -1464,9 +1464,11 @@ __global__ void k_residual(const double* __restrict__ beta, const double* __rest
 // part[tile][kMaxDots + 1] and are summed per instance over its tile range in a fixed
 // order.
 
-// MAXQ >= nq bounds the per-thread accumulators (registers) at compile time.
-template <typename T, int MAXQ>
-__global__ __launch_bounds__(256) void k_sdots(const T* __restrict__ Q, int64_t ld, int nq, const T* __restrict__ u,
+// MAXQ >= nq bounds the per-thread accumulators (registers) at compile time.  SUB = 1
+// first forms u = a - b (in T, as k_sub does) and stores it, in the same pass.
+template <typename T, int MAXQ, int SUB>
+__global__ __launch_bounds__(256) void k_sdots(const T* __restrict__ Q, int64_t ld, int nq, const T* u_in,
+                                               const T* __restrict__ a, const T* __restrict__ b, T* u_out,
                                                SegSet sg, double* __restrict__ part) {
   const int2 t = sg.tiles[blockIdx.x];
   const int64_t base = sg.ioff[t.x] + (int64_t)t.y * kSegChunk;
@@ -1475,7 +1477,14 @@ __global__ __launch_bounds__(256) void k_sdots(const T* __restrict__ Q, int64_t 
 #pragma unroll
   for (int i = 0; i < MAXQ; ++i) acc[i] = 0.0;
   for (int64_t e = base + threadIdx.x; e < end; e += blockDim.x) {
-    const double ue = (double)u[e];
+    double ue;
+    if (SUB) {
+      const T d = a[e] - b[e];
+      u_out[e] = d;
+      ue = (double)d;
+    } else {
+      ue = (double)u_in[e];
+    }
 #pragma unroll
     for (int i = 0; i < MAXQ; ++i)
       if (i < nq) acc[i] += (double)Q[(int64_t)i * ld + e] * ue;
@@ -1628,8 +1637,18 @@ void residual(const double* beta, const double* x, const double* t, double* r, i
 template <typename T>
 void sdots(const birk_plan* p, const T* Q, int nq, const T* u, double* out, int64_t ostride, hipStream_t s) {
   const SegSet& sg = p->seg;
-  BIRK_MAXQ_SWITCH(nq, hipLaunchKernelGGL((k_sdots<T, MQ>), dim3(sg.ntiles), dim3(256), 0, s, Q, p->total_len, nq, u,
-                                           sg, p->krylov_part))
+  BIRK_MAXQ_SWITCH(nq, hipLaunchKernelGGL((k_sdots<T, MQ, 0>), dim3(sg.ntiles), dim3(256), 0, s, Q, p->total_len, nq,
+                                           u, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, sg, p->krylov_part))
+  hipLaunchKernelGGL(k_sreduce, dim3(nq + 1, (unsigned)p->inst.size()), dim3(256), 0, s, p->krylov_part, sg, nq, out,
+                     ostride);
+}
+
+template <typename T>
+void sub_sdots(const birk_plan* p, const T* Q, int nq, const T* a, const T* b, T* u, double* out, int64_t ostride,
+               hipStream_t s) {
+  const SegSet& sg = p->seg;
+  BIRK_MAXQ_SWITCH(nq, hipLaunchKernelGGL((k_sdots<T, MQ, 1>), dim3(sg.ntiles), dim3(256), 0, s, Q, p->total_len, nq,
+                                           (const T*)nullptr, a, b, u, sg, p->krylov_part))
   hipLaunchKernelGGL(k_sreduce, dim3(nq + 1, (unsigned)p->inst.size()), dim3(256), 0, s, p->krylov_part, sg, nq, out,
                      ostride);
 }
@@ -1674,6 +1693,10 @@ void scombine(const birk_plan* p, const T* Q, const double* c, int64_t cstride, 
 
 template void sdots<double>(const birk_plan*, const double*, int, const double*, double*, int64_t, hipStream_t);
 template void sdots<float>(const birk_plan*, const float*, int, const float*, double*, int64_t, hipStream_t);
+template void sub_sdots<double>(const birk_plan*, const double*, int, const double*, const double*, double*, double*,
+                                int64_t, hipStream_t);
+template void sub_sdots<float>(const birk_plan*, const float*, int, const float*, const float*, float*, double*,
+                               int64_t, hipStream_t);
 template void saxpys_dots<double>(const birk_plan*, const double*, int, const double*, int64_t, double*, double*,
                                   int64_t, hipStream_t);
 template void saxpys_dots<float>(const birk_plan*, const float*, int, const double*, int64_t, float*, double*,
