@@ -198,7 +198,7 @@ birk_status birk_fast_ax(birk_plan* plan, birk_jac_kind jac_kind, const double* 
 
 typedef struct {
   int32_t method;       /* 0 = GMRES; 1 = MINRES (reserved: BIRK_ERR_UNSUPPORTED)     */
-  int32_t restart;      /* GMRES restart length m, 1..128 (default 30)                */
+  int32_t restart;      /* GMRES restart length m, 1..31 (default 30)                 */
   int32_t max_iter;     /* total inner iterations allowed (default 300)               */
   double rtol;          /* target ||beta - A chi||_2 / ||beta||_2, true residual in
                            double (default 1e-10)                                     */

@@ -41,6 +41,7 @@ __all__ = [
     "btilde_dense",
     "btilde_apply",
     "ba_row",
+    "ba_col",
     "sparse_mode_exact",
     "sparse_mode_values",
     "apply_Ba_extended",
@@ -257,6 +258,44 @@ def ba_row(N: int, i: int) -> np.ndarray:
     e[0] = e[N] = 0.5
     # T_k(tau_j) = cos(pi k (N - j) / N)  ->  S evaluated at m = N - j
     return e * S[::-1]
+
+
+def ba_col(N: int, j: int) -> np.ndarray:
+    """Column j of B^a, (B^a)_{ij} for i = 0..N, in O(N log N).
+
+    Column j is B^a e_j = Int T^{-1} e_j (construction 2 with the inverse of App. B,
+    eq:ak=3): the modal coefficients of the Lagrange polynomial l_j are
+    u_k = (T^{-1})_{kj} = 2 e_j T_k(tau_j) / (N c_k), and the column holds the
+    antiderivative sum_k u_k I_k(tau_i).  Each I_k is expanded by eq:intChebPoly= into
+    T_{k+1}, T_{k-1} and a constant; the resulting cosine series of degree N + 1 is
+    evaluated at the nodes by one type-I DCT (scipy, a library step) for degrees 0..N
+    and directly for T_{N+1}.  Lets the tests check single outputs of B^aT g at sizes
+    where the dense matrix cannot exist.
+    """
+    k = np.arange(N + 1, dtype=np.int64)
+    c = np.ones(N + 1)
+    c[0] = c[N] = 2.0
+    ej = 0.5 if j in (0, N) else 1.0
+    Tkj = np.cos(np.pi * ((k * (N - j)) % (2 * N)).astype(np.float64) / N)
+    u = 2.0 * ej * Tkj / (N * c)
+    alpha = np.zeros(N + 2)      # coefficient of T_m, m = 0..N+1
+    const = 0.0
+    alpha[1] += u[0]             # I_0 = T_1 + 1
+    const += u[0]
+    alpha[2] += u[1] / 4.0       # I_1 = T_2 / 4 - 1 / 4
+    const -= u[1] / 4.0
+    kk = k[2:]
+    kf = kk.astype(np.float64)
+    sgn = np.where(kk % 2 == 0, 1.0, -1.0)
+    np.add.at(alpha, kk + 1, u[2:] / (2.0 * (kf + 1.0)))
+    np.add.at(alpha, kk - 1, -u[2:] / (2.0 * (kf - 1.0)))
+    const -= float(np.sum(u[2:] * sgn / (kf * kf - 1.0)))
+    # sum_{m<=N} alpha_m cos(pi m n / N) at n = 0..N; scipy's DCT-I doubles the interior
+    x = alpha[:N + 1].copy()
+    x[1:N] *= 0.5
+    S = scipy.fft.dct(x, type=1)
+    # T_m(tau_i) = cos(pi m (N - i) / N): the series at n = N - i, plus T_{N+1} directly
+    return S[::-1] + alpha[N + 1] * cheb_T_at_nodes(N, N + 1) + const
 
 
 def sparse_mode_values(N: int, modes, alphas) -> np.ndarray:

@@ -142,6 +142,67 @@ def _ptr(t) -> int:
     return 0 if t is None else int(t.data_ptr())
 
 
+# ---- argument checks: every tensor handed to the library is checked for type, dtype,
+# length and contiguity, then all of them for their device, then for overlaps, before the
+# call; a wrong tensor is a Python error here and never an out-of-bounds access on the GPU.
+def _spec_vec(plan: Plan, t, name: str):
+    """A vector in the plan's storage type and layout (birk_plan_length elements; double-
+    float plans store two floats per element)."""
+    if plan.prec == BIRK_F64:
+        return (t, name, "f64", plan.length, False)
+    if plan.prec == BIRK_DF32:
+        return (t, name, "f32", 2 * plan.length, False)
+    return (t, name, "f32", plan.length, False)
+
+
+def _spec_f64(plan: Plan, t, name: str, numel: int = None, allow_none: bool = False):
+    """A double array: by default one value per element of the plan layout."""
+    return (t, name, "f64", plan.length if numel is None else numel, allow_none)
+
+
+def _jac_numel(plan: Plan, jac_kind: int) -> int:
+    if jac_kind == BIRK_J_CONSTANT:
+        return sum(nx * nx for nx in plan.n_x)
+    if jac_kind == BIRK_J_PER_NODE:
+        return sum(nx * nx * nn for nn, nx in zip(plan.n_nodes, plan.n_x))
+    raise ValueError(f"jac_kind must be BIRK_J_CONSTANT or BIRK_J_PER_NODE, got {jac_kind}")
+
+
+def _spec_jac(plan: Plan, J, jac_kind: int):
+    return (J, "J", "f64", _jac_numel(plan, jac_kind), False)
+
+
+def _validate(plan: Plan, *specs, disjoint=()) -> None:
+    """specs: (tensor, name, dtype, numel, allow_none).  disjoint: pairs of names whose
+    storage must not overlap."""
+    import torch
+    present = {}
+    for t, name, dtype, numel, allow_none in specs:
+        if t is None:
+            if allow_none:
+                continue
+            raise ValueError(f"{name}: a tensor is required")
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+        want = {"f64": torch.float64, "f32": torch.float32}[dtype]
+        if t.dtype != want:
+            raise ValueError(f"{name}: dtype {t.dtype}, the plan needs {want}")
+        if t.numel() != numel:
+            raise ValueError(f"{name}: {t.numel()} elements, the plan needs {numel}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: must be contiguous")
+        present[name] = t
+    for a, b in disjoint:
+        if a in present and b in present:
+            ta, tb = present[a], present[b]
+            a0, b0 = ta.data_ptr(), tb.data_ptr()
+            if a0 < b0 + tb.numel() * tb.element_size() and b0 < a0 + ta.numel() * ta.element_size():
+                raise ValueError(f"{a} and {b} overlap")
+    for name, t in present.items():
+        if not t.is_cuda or t.device.index != plan.device:
+            raise ValueError(f"{name}: must live on cuda:{plan.device} (got {t.device})")
+
+
 def _stream_handle(stream):
     if stream is None:
         import torch
@@ -151,15 +212,20 @@ def _stream_handle(stream):
 
 @dataclass
 class Plan:
-    """Owning handle of a birk_plan."""
+    """Owning handle of a birk_plan, with the sizes the argument checks need."""
     handle: int
     n_nodes: tuple
     n_x: tuple
     prec: int
+    device: int = 0
 
     @property
     def length(self) -> int:
-        return int(_lib.birk_plan_length(self.handle))
+        return sum(a * b for a, b in zip(self.n_nodes, self.n_x))
+
+    @property
+    def n_comp(self) -> int:
+        return sum(self.n_x)
 
     def destroy(self) -> None:
         if self.handle:
@@ -182,9 +248,11 @@ def birk_plan_create(n_nodes, n_x, prec: int = BIRK_F64, stream=None) -> Plan:
     nn = (ctypes.c_int64 * max(b, 1))(*n_nodes)
     nx = (ctypes.c_int32 * max(b, 1))(*n_x)
     h = ctypes.c_void_p()
+    import torch
+    dev = torch.cuda.current_device()
     st = _lib.birk_plan_create(ctypes.byref(h), b, nn, nx, int(prec), _stream_handle(stream))
     _check(st, "birk_plan_create")
-    return Plan(h.value, tuple(n_nodes), tuple(n_x), int(prec))
+    return Plan(h.value, tuple(n_nodes), tuple(n_x), int(prec), int(dev))
 
 
 def birk_plan_destroy(plan: Plan) -> None:
@@ -192,7 +260,7 @@ def birk_plan_destroy(plan: Plan) -> None:
 
 
 def birk_plan_length(plan: Plan) -> int:
-    return plan.length
+    return int(_lib.birk_plan_length(plan.handle))
 
 
 def birk_plan_tune(plan: Plan) -> str:
@@ -215,33 +283,47 @@ def birk_weights(plan: Plan, inst: int = 0):
     return w
 
 
+def _product_args(plan: Plan, v, out, vname: str) -> None:
+    _validate(plan, _spec_vec(plan, v, vname), _spec_vec(plan, out, "out"), disjoint=[(vname, "out")])
+
+
 def birk_apply(plan: Plan, v, out) -> None:
+    _product_args(plan, v, out, "v")
     _check(_lib.birk_apply(plan.handle, _ptr(v), _ptr(out)), "birk_apply")
 
 
 def birk_apply_T(plan: Plan, g, out) -> None:
+    _product_args(plan, g, out, "g")
     _check(_lib.birk_apply_T(plan.handle, _ptr(g), _ptr(out)), "birk_apply_T")
 
 
 def birk_apply_b(plan: Plan, v, out) -> None:
+    _product_args(plan, v, out, "v")
     _check(_lib.birk_apply_b(plan.handle, _ptr(v), _ptr(out)), "birk_apply_b")
 
 
 def birk_apply_bT(plan: Plan, g, out) -> None:
+    _product_args(plan, g, out, "g")
     _check(_lib.birk_apply_bT(plan.handle, _ptr(g), _ptr(out)), "birk_apply_bT")
 
 
 def birk_endpoint(plan: Plan, xa, v, xb) -> None:
     """xb = xa + w^T v per component (device double arrays of one entry per component)."""
+    _validate(plan, _spec_f64(plan, xa, "xa", plan.n_comp), _spec_vec(plan, v, "v"),
+              _spec_f64(plan, xb, "xb", plan.n_comp), disjoint=[("xa", "v"), ("xb", "v")])
     _check(_lib.birk_endpoint(plan.handle, _ptr(xa), _ptr(v), _ptr(xb)), "birk_endpoint")
 
 
 def birk_precond(plan: Plan, J, y, out, inverse: bool, jac_kind: int = BIRK_J_PER_NODE) -> None:
+    _validate(plan, _spec_jac(plan, J, jac_kind), _spec_vec(plan, y, "y"), _spec_vec(plan, out, "out"),
+              disjoint=[("y", "out"), ("J", "out")])
     _check(_lib.birk_precond(plan.handle, int(jac_kind), _ptr(J), _ptr(y), _ptr(out), int(bool(inverse))),
            "birk_precond")
 
 
 def birk_fast_ax(plan: Plan, J, x, out, jac_kind: int = BIRK_J_PER_NODE) -> None:
+    _validate(plan, _spec_jac(plan, J, jac_kind), _spec_f64(plan, x, "x"), _spec_f64(plan, out, "out"),
+              disjoint=[("x", "out"), ("J", "out")])
     _check(_lib.birk_fast_ax(plan.handle, int(jac_kind), _ptr(J), _ptr(x), _ptr(out)), "birk_fast_ax")
 
 
@@ -260,6 +342,8 @@ def birk_krylov_solve(plan: Plan, J, beta, chi, jac_kind: int = BIRK_J_PER_NODE,
         if not hasattr(o, k):
             raise TypeError(f"unknown solve option {k}")
         setattr(o, k, v)
+    _validate(plan, _spec_jac(plan, J, jac_kind), _spec_f64(plan, beta, "beta"), _spec_f64(plan, chi, "chi"),
+              disjoint=[("beta", "chi"), ("J", "chi")])
     b = len(plan.n_nodes)
     stv = (ctypes.c_int32 * b)()
     inner = (ctypes.c_int32 * b)()
@@ -277,6 +361,9 @@ def birk_krylov_solve(plan: Plan, J, beta, chi, jac_kind: int = BIRK_J_PER_NODE,
 
 def birk_two_body(plan: Plan, X, F, J, mu: float = 1.0, scale: float = 1.0) -> None:
     """Two-body right-hand side F and per-node Jacobian J at X (F or J may be None)."""
+    _validate(plan, _spec_f64(plan, X, "X"), _spec_f64(plan, F, "F", allow_none=True),
+              _spec_f64(plan, J, "J", _jac_numel(plan, BIRK_J_PER_NODE), allow_none=True),
+              disjoint=[("X", "F"), ("X", "J"), ("F", "J")])
     _check(_lib.birk_two_body(plan.handle, float(mu), float(scale), _ptr(X), _ptr(F), _ptr(J)), "birk_two_body")
 
 
@@ -308,6 +395,7 @@ def birk_newton_ivp(plan: Plan, xa, X, mu: float = 1.0, scale: float = 1.0, rhs=
     else:
         cb = RHS_FN(lambda ctx, x, f, j, stream: int(rhs(x or 0, f or 0, j or 0, stream or 0)))
         model = birk_ivp_model(BIRK_MODEL_CALLBACK, 0.0, 0.0, cb, None)
+    _validate(plan, _spec_f64(plan, xa, "xa", plan.n_comp), _spec_f64(plan, X, "X"), disjoint=[("xa", "X")])
     b = len(plan.n_nodes)
     stv = (ctypes.c_int32 * b)()
     nit = (ctypes.c_int32 * b)()

@@ -127,3 +127,80 @@ def test_null_arguments_are_rejected(birk):
     assert lib.birk_plan_set_graphs(None, 1) == birk.BIRK_ERR_ARG
     assert lib.birk_plan_destroy(None) == birk.BIRK_OK
     assert lib.birk_plan_length(None) == 0
+
+
+# ---- the binding checks every tensor before calling the library (no GPU needed: the
+# checks run in Python and raise before any call; a tensor that passes them all still
+# fails the device check here because it lives on the CPU)
+def _fake_plan(birk, prec, n_nodes=(9, 5), n_x=(2, 3)):
+    return birk.Plan(0, tuple(n_nodes), tuple(n_x), prec, 0)
+
+
+@pytest.mark.parametrize("prec,dtype,factor", [(0, "float64", 1), (1, "float32", 1), (2, "float32", 1),
+                                              (3, "float32", 2)])
+def test_binding_rejects_bad_vectors(birk, prec, dtype, factor):
+    import torch
+    plan = _fake_plan(birk, prec)
+    n = (9 * 2 + 5 * 3) * factor
+    good = torch.zeros(n, dtype=getattr(torch, dtype))
+    other = torch.float32 if dtype == "float64" else torch.float64
+    for fn in (birk.birk_apply, birk.birk_apply_T, birk.birk_apply_b, birk.birk_apply_bT):
+        with pytest.raises(ValueError, match="dtype"):
+            fn(plan, good.to(other), good.clone())
+        with pytest.raises(ValueError, match="elements"):
+            fn(plan, good[:-1], good.clone())
+        with pytest.raises(ValueError, match="elements"):
+            fn(plan, good, torch.zeros(n + 1, dtype=good.dtype))
+        with pytest.raises(ValueError, match="contiguous"):
+            fn(plan, torch.zeros(2 * n, dtype=good.dtype)[::2], good.clone())
+        with pytest.raises(ValueError, match="cuda"):
+            fn(plan, good, good.clone())
+        with pytest.raises(ValueError, match="required"):
+            fn(plan, None, good)
+    with pytest.raises(ValueError, match="Tensor"):
+        birk.birk_apply(plan, [0.0] * n, good)
+
+
+def test_binding_rejects_bad_jacobians_and_solve_arguments(birk):
+    import torch
+    plan = _fake_plan(birk, 0)
+    n = 9 * 2 + 5 * 3
+    v = torch.zeros(n, dtype=torch.float64)
+    Jc = torch.zeros(2 * 2 + 3 * 3, dtype=torch.float64)
+    Jn = torch.zeros(9 * 4 + 5 * 9, dtype=torch.float64)
+    with pytest.raises(ValueError, match="J: .*elements"):
+        birk.birk_precond(plan, Jc, v, v.clone(), True, birk.BIRK_J_PER_NODE)
+    with pytest.raises(ValueError, match="J: .*elements"):
+        birk.birk_precond(plan, Jn, v, v.clone(), True, birk.BIRK_J_CONSTANT)
+    with pytest.raises(ValueError, match="jac_kind"):
+        birk.birk_precond(plan, Jn, v, v.clone(), True, 5)
+    with pytest.raises(ValueError, match="J: dtype"):
+        birk.birk_fast_ax(plan, Jc.float(), v, v.clone(), birk.BIRK_J_CONSTANT)
+    with pytest.raises(ValueError, match="beta: .*elements"):
+        birk.birk_krylov_solve(plan, Jc, v[:-1], v.clone(), birk.BIRK_J_CONSTANT)
+    with pytest.raises(ValueError, match="chi: dtype"):
+        birk.birk_krylov_solve(plan, Jc, v, v.float(), birk.BIRK_J_CONSTANT)
+    # a float plan still takes double beta / chi / J in the solve
+    p32 = _fake_plan(birk, 2)
+    with pytest.raises(ValueError, match="cuda"):
+        birk.birk_krylov_solve(p32, Jc, v, v.clone(), birk.BIRK_J_CONSTANT)
+    # endpoint: one double per component
+    with pytest.raises(ValueError, match="xa: .*elements"):
+        birk.birk_endpoint(plan, torch.zeros(4, dtype=torch.float64), v, torch.zeros(5, dtype=torch.float64))
+    # two-body: J per node
+    with pytest.raises(ValueError, match="J: .*elements"):
+        birk.birk_two_body(plan, v, v.clone(), Jc)
+
+
+def test_binding_rejects_overlapping_buffers(birk):
+    import torch
+    plan = _fake_plan(birk, 0)
+    n = 9 * 2 + 5 * 3
+    buf = torch.zeros(2 * n, dtype=torch.float64)
+    with pytest.raises(ValueError, match="overlap"):
+        birk.birk_apply(plan, buf[:n], buf[:n])
+    with pytest.raises(ValueError, match="overlap"):
+        birk.birk_apply(plan, buf[:n], buf[1:n + 1])
+    # disjoint halves pass the overlap check and reach the device check
+    with pytest.raises(ValueError, match="cuda"):
+        birk.birk_apply(plan, buf[:n], buf[n:])

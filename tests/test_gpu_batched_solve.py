@@ -3,10 +3,13 @@
 mixed mode (float GMRES inside double refinement), to relative residual 1e-10.
 
 Reference: the exact solution of the LTI initial-value problem, X(tau) = expm(A (tau + 1))
-x_a (pinned against the oracle's dense solve in the CPU tests), at sampled nodes; the
-Birkhoff collocation solution equals it to rounding at these N.  kappa ~ 5, so residual
-1e-10 bounds the solution error near 5e-10; the bar is 1e-9.  Batching must not change
-any instance's arithmetic: a batched solve equals single-instance solves bit for bit.
+x_a (pinned against the oracle's dense solve in the CPU tests), at 33 sampled nodes of
+every instance; the Birkhoff collocation solution equals it to rounding at these N.
+kappa ~ 5, so a relative residual rho bounds the solution error near 5 rho: double
+solves run to 1e-13 and are held to 1e-12, mixed solves to 1e-11 and are held to 1e-10
+(the accuracy targets of the two paths).  The configuration's own tolerance (residual
+1e-10) is checked on the residuals the library reports.  Batching must not change any
+instance's arithmetic: a batched solve equals single-instance solves bit for bit.
 """
 
 import numpy as np
@@ -51,28 +54,29 @@ def _closed_form_err(inst, X, nsample=33):
     return float(np.max(np.abs(X[:, idx] - Xe)) / np.max(np.abs(Xe)))
 
 
-@pytest.mark.parametrize("prec", ["f64", "mixed"])
-def test_batched_solve_512(B, prec):
+@pytest.mark.parametrize("prec,rtol,bar", [("f64", 1e-13, 1e-12), ("mixed", 1e-11, 1e-10),
+                                           ("f64", 1e-10, None), ("mixed", 1e-10, None)])
+def test_batched_solve_512(B, prec, rtol, bar):
     insts = wl.batched_instances(count=512)
-    announce(f"batched solve 512 instances prec={prec}")
+    announce(f"batched solve 512 instances prec={prec} rtol={rtol}")
     p = B.BIRK_F64 if prec == "f64" else B.BIRK_F32_REFINE_F64
-    x, info = _solve_batch(B, insts, p, 1e-10)
+    x, info = _solve_batch(B, insts, p, rtol)
     st = np.asarray(info["inst_status"])
     rr = np.asarray(info["rel_resid"])
     announce(f"  status ok {int(np.sum(st == 0))}/512, worst residual {rr.max():.3e}, "
              f"inner iterations {min(info['inner_iters'])}..{max(info['inner_iters'])}, "
              f"outer {min(info['outer_iters'])}..{max(info['outer_iters'])}")
     assert info["status"] == 0 and np.all(st == 0)
-    assert rr.max() <= 1e-10
+    assert rr.max() <= rtol
     worst = 0.0
     o = 0
-    for k, ins in enumerate(insts):
+    for ins in insts:
         n = ins.n_x * ins.N_n
-        if k % 8 == 0:
-            worst = max(worst, _closed_form_err(ins, x[o:o + n].reshape(ins.n_x, ins.N_n)))
+        worst = max(worst, _closed_form_err(ins, x[o:o + n].reshape(ins.n_x, ins.N_n)))
         o += n
-    announce(f"  worst closed-form error over sampled instances {worst:.3e}")
-    assert worst <= 1e-9
+    announce(f"  worst closed-form error over all 512 instances {worst:.3e}")
+    # at the configuration's residual 1e-10 the bound is kappa * rtol with kappa <= 5
+    assert worst <= (bar if bar is not None else 5 * rtol)
 
 
 def test_batched_solve_equals_single(B):

@@ -262,3 +262,72 @@ def test_autotune_without_power_of_two_groups(B):
     plan = B.birk_plan_create([1000], [3], B.BIRK_F64)
     assert "no power-of-two groups" in B.birk_plan_tune(plan)
     plan.destroy()
+
+
+# ---------------------------------------------------------------- the timed configuration
+# The benchmark times B^a and B^aT at N_n = 2^20 + 1, n_x = 6 after birk_plan_tune; the
+# tuner picks among the schedules below (split 0, two rows per pass-B tile, one to three
+# streams, four- or eight-column pass-A/C tiles).  Each is checked here on the same
+# inputs: a random dense v at 16 rows (96 outputs) through O(N log N) rows and columns of
+# the oracle, and six exact series (Chebyshev modes for B^a, node-sparse right-hand
+# sides for B^aT) at every output.
+HEAD_NN, HEAD_NX = (1 << 20) + 1, 6
+HEAD_SCHEDULES = [{"BIRK_FAST_SPLIT": "0", "BIRK_FAST_TB": "2", "BIRK_FAST_XCD": "1",
+                   "BIRK_FAST_NARROW": nw, "BIRK_FAST_STREAMS": st}
+                  for nw in ("0", "1") for st in ("1", "2", "3")] + ["tuned"]
+
+
+@pytest.fixture(scope="module")
+def head_refs():
+    N = HEAD_NN - 1
+    rng = np.random.default_rng(2020)
+    Xd = wl.random_vectors([21, HEAD_NN], (HEAD_NX, HEAD_NN))[0]
+    idx = np.unique(np.concatenate([[0, 1, 2, N // 2, N - 1, N], rng.integers(0, HEAD_NN, 10)]))
+    rows = np.stack([bk.ba_row(N, int(i)) for i in idx])        # [s, j]
+    cols = np.stack([bk.ba_col(N, int(j)) for j in idx])        # [s, i]
+    ref_dense = Xd @ rows.T                                      # (B^a x_c)_i at i in idx
+    ref_dense_T = Xd @ cols.T                                    # (B^aT x_c)_j at j in idx
+    Xs, ref_s = [], []
+    for c in range(HEAD_NX):
+        modes, alphas = wl.sparse_modes([23, c, HEAD_NN], N, count=64)
+        Xs.append(bk.sparse_mode_values(N, modes, alphas))
+        ref_s.append(bk.sparse_mode_exact(N, modes, alphas))
+    Gs, ref_sT = [], []
+    for c in range(HEAD_NX):
+        nodes = np.unique(np.concatenate([[0, N], rng.integers(0, HEAD_NN, 8)]))
+        g = np.zeros(HEAD_NN)
+        g[nodes] = rng.standard_normal(len(nodes))
+        Gs.append(g)
+        ref_sT.append(sum(g[i] * bk.ba_row(N, int(i)) for i in nodes))
+    return dict(Xd=Xd, idx=idx, ref_dense=ref_dense, ref_dense_T=ref_dense_T, Xs=np.stack(Xs),
+                ref_s=np.stack(ref_s), Gs=np.stack(Gs), ref_sT=np.stack(ref_sT))
+
+
+@pytest.mark.parametrize("sched", HEAD_SCHEDULES, ids=lambda s: "tuned" if s == "tuned" else
+                         f"narrow{s['BIRK_FAST_NARROW']}-streams{s['BIRK_FAST_STREAMS']}")
+def test_timed_configuration_schedules(B, head_refs, sched, monkeypatch):
+    import torch
+    r = head_refs
+    if sched == "tuned":
+        plan = B.birk_plan_create([HEAD_NN], [HEAD_NX], B.BIRK_F64)
+        rep = B.birk_plan_tune(plan)
+        announce("timed configuration, tuned: " + rep.split(" chosen ")[-1].strip())
+    else:
+        for k, v in sched.items():
+            monkeypatch.setenv(k, v)
+        announce(f"timed configuration, schedule {sched}")
+        plan = B.birk_plan_create([HEAD_NN], [HEAD_NX], B.BIRK_F64)
+
+    def run(X, transpose):
+        v = dev(X.ravel(), torch.float64)
+        out = torch.empty_like(v)
+        (B.birk_apply_T if transpose else B.birk_apply)(plan, v, out)
+        torch.cuda.synchronize()
+        return host(out).reshape(HEAD_NX, HEAD_NN)
+
+    idx = r["idx"]
+    assert rel_err(run(r["Xd"], 0)[:, idx], r["ref_dense"]) <= TOL["f64"]
+    assert rel_err(run(r["Xd"], 1)[:, idx], r["ref_dense_T"]) <= TOL["f64"]
+    assert rel_err(run(r["Xs"], 0), r["ref_s"]) <= TOL["f64"]
+    assert rel_err(run(r["Gs"], 1), r["ref_sT"]) <= TOL["f64"]
+    plan.destroy()

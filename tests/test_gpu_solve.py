@@ -4,9 +4,11 @@ oracle's plain GMRES, and the error paths.
 
 Tolerances: the system is well conditioned (kappa ~ 5 for these workloads, pinned in the
 oracle tests), so a relative residual rho bounds the relative solution error by about
-kappa * rho.  FP64 solves run to rtol 1e-13 and are compared at 1e-11; mixed solves run
-to rtol 1e-10 and are compared at 1e-9; closed-form pins add the discretisation error
-of the exact ODE solution (< 1e-12 at these N)."""
+kappa * rho.  FP64 solves run to rtol 1e-13 and are held to 1e-12 (the accuracy target
+of the double path); mixed solves (float Krylov inside double refinement) run to rtol
+1e-11 and are held to 1e-10 (the target after refinement).  The collocation solution
+meets the exact ODE solution to rounding at these N (spectral convergence), so the
+closed-form pins use the same bars."""
 
 import math
 
@@ -55,13 +57,13 @@ def test_solve_vs_dense_lu(B, kind, Nn, prec):
     ref = sy.solve_dense(A, beta)
     if prec == "f64":
         x, info = _solve(B, inst, beta, B.BIRK_F64, rtol=1e-13)
-        tol = 1e-11
+        tol = 1e-12
     else:
-        x, info = _solve(B, inst, beta, B.BIRK_F32_REFINE_F64, rtol=1e-10)
-        tol = 1e-9
+        x, info = _solve(B, inst, beta, B.BIRK_F32_REFINE_F64, rtol=1e-11)
+        tol = 1e-10
     assert info["status"] == 0, info
-    assert info["rel_resid"][0] <= (1e-13 if prec == "f64" else 1e-10)
-    assert sy.rel_residual(lambda z: A @ z, beta, x) <= (1e-12 if prec == "f64" else 2e-10)
+    assert info["rel_resid"][0] <= (1e-13 if prec == "f64" else 1e-11)
+    assert sy.rel_residual(lambda z: A @ z, beta, x) <= (1e-12 if prec == "f64" else 2e-11)
     assert rel_err(x, ref) <= tol
 
 
@@ -86,7 +88,7 @@ def test_lti_closed_form_65537(B):
     tau = bk.cgl_nodes(Nn - 1)
     idx = np.unique(np.linspace(0, Nn - 1, 257).astype(int))
     Xe = np.stack([scipy.linalg.expm(inst.J * (tau[k] + 1.0)) @ inst.x_a for k in idx], axis=1)
-    for prec, rtol, tol in ((B.BIRK_F64, 1e-12, 1e-11), (B.BIRK_F32_REFINE_F64, 1e-10, 1e-9)):
+    for prec, rtol, tol in ((B.BIRK_F64, 1e-13, 1e-12), (B.BIRK_F32_REFINE_F64, 1e-11, 1e-10)):
         x, info = _solve(B, inst, beta, prec, rtol=rtol)
         assert info["status"] == 0, info
         X = x.reshape(inst.n_x, Nn)[:, idx]
@@ -104,10 +106,31 @@ def test_kepler_time_shift_solution_million_points(B, prec):
     Z = np.concatenate([ex["v"], ex["acc"]])
     beta = sy.beta_vector(Z[:, 0], Nn)
     p = B.BIRK_F64 if prec == "f64" else B.BIRK_F32_REFINE_F64
+    # kappa(A) ~ 720 for the Kepler systems (oracle pin), so the residual is taken two
+    # orders below each bar
+    rtol, tol = (1e-14, 1e-12) if prec == "f64" else (1e-12, 1e-10)
+    x, info = _solve(B, inst, beta, p, rtol=rtol)
+    assert info["status"] == 0, info
+    assert info["rel_resid"][0] <= rtol
+    assert rel_err(x.reshape(6, Nn), Z) <= tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_kepler_headline_residual_1e10(B, prec):
+    """The timed configuration's tolerance: 2^20 + 1 nodes, Kepler Jacobian, solved to the
+    relative residual 1e-10 (the time-shift right-hand side, whose solution is known);
+    the error is held to the bound kappa * rtol with kappa(A) < 1000 (oracle pin)."""
+    Nn = (1 << 20) + 1
+    announce(f"Kepler 2^20+1 time-shift, rtol 1e-10, prec={prec}")
+    inst = wl.kepler_instance(2, Nn)
+    ex = inst.extra
+    Z = np.concatenate([ex["v"], ex["acc"]])
+    beta = sy.beta_vector(Z[:, 0], Nn)
+    p = B.BIRK_F64 if prec == "f64" else B.BIRK_F32_REFINE_F64
     x, info = _solve(B, inst, beta, p, rtol=1e-10)
     assert info["status"] == 0, info
     assert info["rel_resid"][0] <= 1e-10
-    assert rel_err(x.reshape(6, Nn), Z) <= 1e-9
+    assert rel_err(x.reshape(6, Nn), Z) <= 1000 * 1e-10
 
 
 def test_error_paths(B):
@@ -135,3 +158,8 @@ def test_error_paths(B):
     # plain float plans do not solve
     _, info = _solve(B, inst, beta, B.BIRK_F32)
     assert info["status"] == B.BIRK_ERR_UNSUPPORTED
+    # restart lengths 1..31 (the multi-dot kernels hold 32 vectors: the basis and u)
+    _, info = _solve(B, inst, beta, B.BIRK_F64, restart=32)
+    assert info["status"] == B.BIRK_ERR_ARG
+    x, info = _solve(B, inst, beta, B.BIRK_F64, restart=31, rtol=1e-12)
+    assert info["status"] == B.BIRK_OK

@@ -142,6 +142,33 @@ def test_sparse_mode_exact_large_N_against_rows():
         assert abs(bk.ba_row(N, i) @ v - exact[i]) <= 1e-12 * max(1.0, np.abs(exact).max())
 
 
+@pytest.mark.parametrize("N", [2, 3, 9, 16, 31, 64])
+def test_columns_match_quadrature_construction(N):
+    """ba_col against the columns of B^a built by Gauss-Legendre quadrature of the
+    Lagrange basis (construction 1, independent of the modal route ba_col takes)."""
+    B = bk.dense_Ba_quadrature(N)
+    for j in range(N + 1):
+        assert np.max(np.abs(bk.ba_col(N, j) - B[:, j])) <= 5e-15
+
+
+def test_columns_match_rows_at_4096():
+    """(B^a)_ij from a row (ba_row) and from a column (ba_col) at N = 4096, where the two
+    take different routes through the modal definition; plus the first and last rows
+    seen through the columns: 0 and the textbook CC weights."""
+    N = 4096
+    rng = np.random.default_rng(5)
+    pairs = [(0, 5), (7, 0), (N, N), (N, 0), (1, N)] + [tuple(rng.integers(0, N + 1, 2)) for _ in range(8)]
+    for i, j in pairs:
+        r = bk.ba_row(N, int(i))[int(j)]
+        c = bk.ba_col(N, int(j))[int(i)]
+        assert abs(r - c) <= 1e-14 * (2.0 / N)            # entries are O(1/N)
+    w = bk.cc_weights_closed_form(N)
+    for j in (0, 1, N // 2, N):
+        col = bk.ba_col(N, j)
+        assert abs(col[0]) <= 1e-18                       # row 0 of B^a is zero
+        assert abs(col[N] - w[j]) <= 1e-14 * (2.0 / N)    # row N is the CC weights
+
+
 def test_transpose_properties():
     N = 40
     B = bk.dense_Ba(N)
@@ -154,27 +181,23 @@ def test_transpose_properties():
 
 
 # ---------------------------------------------------------------- preconditioner
-def test_btilde_apply_and_printed_fastbccv():
+def test_btilde_apply_against_row_sums():
+    """B~^a v from its row definition (0 above the diagonal, w_j / 2 on it, w_j below it),
+    summed term by term, against the dense matrix and against btilde_apply."""
     rng = np.random.default_rng(1)
     N = 50
     w = bk.weights(N)
     v = rng.standard_normal(N + 1)
     ref = bk.btilde_dense(w) @ v
-    assert np.max(np.abs(bk.btilde_apply(w, v) - ref)) <= 1e-15 * 100
-    # FastBccV as printed: xi_k = w_k v_k / 2 + s; s <- 2 xi_k - s
-    s = 0.0
-    out = np.empty(N + 1)
-    for k in range(N + 1):
-        xi = w[k] * v[k] / 2.0 + s
-        s = 2.0 * xi - s
-        out[k] = xi
-    assert np.max(np.abs(out - ref)) <= 1e-14
-    # the recursion R_k printed before the box
-    R = np.empty(N + 1)
-    R[0] = w[0] * v[0] / 2.0
-    for k in range(1, N + 1):
-        R[k] = R[k - 1] - w[k - 1] * v[k - 1] / 2.0 + w[k - 1] * v[k - 1] + w[k] * v[k] / 2.0
-    assert np.max(np.abs(R - ref)) <= 1e-14
+    brute = np.array([sum(w[j] * v[j] for j in range(k)) + 0.5 * w[k] * v[k] for k in range(N + 1)])
+    assert np.max(np.abs(brute - ref)) <= 1e-14
+    assert np.max(np.abs(bk.btilde_apply(w, v) - ref)) <= 1e-14
+    # The columns of B~^a are constant below the diagonal, so consecutive outputs differ
+    # by the mean of the neighbouring terms w_j v_j: the property that lets FastBccV run
+    # as a single pass over the nodes.
+    out = bk.btilde_apply(w, v)
+    wv = w * v
+    assert np.max(np.abs(np.diff(out) - 0.5 * (wv[:-1] + wv[1:]))) <= 1e-14
 
 
 @pytest.mark.parametrize("kind", ["lti", "kepler"])
@@ -192,9 +215,13 @@ def test_precond_inverse(kind):
     assert np.max(np.abs(P @ y - sy.precond_apply(w, inst.J, y))) <= 1e-13
 
 
-def test_printed_fastpinvy_update_is_not_an_inverse():
-    """Scalar case: the printed `s <- w_k f'_k Y_k + s` misses P^{-1}; the exact forward
-    substitution (s <- s - w_k f'_k xi_k, xi_k = (1 - w_k f'_k/2)^{-1} (Y_k - s)) hits it."""
+def test_running_sum_must_carry_the_solution():
+    """Scalar case of P = I - B~^a diag(d).  Row k of P xi = y reads
+    (1 - w_k d_k / 2) xi_k - sum_{j<k} w_j d_j xi_j = y_k, so the running sum that forward
+    substitution carries is built from the solution values xi_j.  The FastPinvY box
+    builds it from the right-hand side values instead (with the opposite sign); that
+    variant, evaluated here with a cumulative sum over y, misses P^{-1} y by O(1), while
+    the oracle's forward substitution reaches the LAPACK solve."""
     rng = np.random.default_rng(0)
     N = 30
     w = bk.weights(N)
@@ -202,20 +229,16 @@ def test_printed_fastpinvy_update_is_not_an_inverse():
     Y = rng.standard_normal(N + 1)
     P = np.eye(N + 1) - bk.btilde_dense(w) @ np.diag(d)
     exact = np.linalg.solve(P, Y)
-    s = 0.0
-    printed = np.empty(N + 1)
-    for k in range(N + 1):
-        printed[k] = (Y[k] - s) / (1.0 - w[k] * d[k] / 2.0)
-        s = w[k] * d[k] * Y[k] + s
-    s = 0.0
-    fixed = np.empty(N + 1)
-    for k in range(N + 1):
-        fixed[k] = (Y[k] - s) / (1.0 - w[k] * d[k] / 2.0)
-        s = s - w[k] * d[k] * fixed[k]
-    assert np.max(np.abs(fixed - exact)) <= 1e-13
-    assert np.max(np.abs(printed - exact)) > 1e-3
+    wdy = w * d * Y
+    t = np.cumsum(wdy) - wdy                  # sum_{j<k} w_j d_j y_j
+    from_inputs = (Y - t) / (1.0 - 0.5 * w * d)
+    assert np.max(np.abs(from_inputs - exact)) > 1e-3
     xi = sy.precond_inverse(w, d[None, None, :], Y)
     assert np.max(np.abs(xi - exact)) <= 1e-13
+    # and xi satisfies every row of P xi = y written out as above
+    wdx = w * d * xi
+    rows = (1.0 - 0.5 * w * d) * xi - (np.cumsum(wdx) - wdx)
+    assert np.max(np.abs(rows - Y)) <= 1e-13
 
 
 # ---------------------------------------------------------------- the linear system
@@ -305,6 +328,13 @@ def test_condition_number_is_order_one():
         inst = wl.lti_instance(0, N_n)
         ks.append(np.linalg.cond(sy.dense_A(N_n - 1, inst.J)))
     assert max(ks) < 20.0 and max(ks) / min(ks) < 1.5, ks
+
+
+def test_condition_number_kepler_systems():
+    """kappa of the Kepler-linearised operator (orbit of the million-point workload, seed 2)
+    is flat in N near 720; the GPU solve tests derive their error bars from it."""
+    ks = [np.linalg.cond(sy.dense_A(N_n - 1, wl.kepler_instance(2, N_n).J)) for N_n in (65, 129, 257)]
+    assert 500.0 < min(ks) and max(ks) < 1000.0 and max(ks) / min(ks) < 1.05, ks
 
 
 # ---------------------------------------------------------------- extended-precision products
