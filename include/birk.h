@@ -156,6 +156,25 @@ birk_status birk_apply(birk_plan* plan, const void* v, void* out);
  * and M the integration recurrence.  Same arguments and errors as birk_apply. */
 birk_status birk_apply_T(birk_plan* plan, const void* g, void* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): transpose = 0 computes birk_apply,
+ * transpose = 1 birk_apply_T, with the same kernels, but their work buffers and partial
+ * sums live in one fixed array of 128 MiB per device inside the library instead of the
+ * plan's buffers.  The call allocates nothing and never uses graph mode.  The array is
+ * created with the library's device code on each device it runs on and held until the
+ * process ends; its address is resolved once per device (at the first plan creation,
+ * else the first call).  Every call on one device shares that device's array, so calls
+ * that overlap in time on one device (two streams, two threads, two plans) race: the
+ * caller orders them.  Nothing carries over between calls (each kernel writes every
+ * workspace element before reading it).  The plan's products need at most 128 MiB of
+ * workspace: two complex double work buffers of the plan's transform size (three when
+ * an instance has a non-power-of-two N or N < 512) plus the partial sums, about
+ * 2 x 16 x N_n n_x / 2 bytes for power-of-two N, e.g. 101 MB for N_n = 2^20 + 1 with
+ * n_x = 6.  v, out: as for birk_apply.  Asynchronous on the plan's stream.
+ * Errors: BIRK_ERR_ARG (NULL, v == out, transpose not 0 or 1), BIRK_ERR_SIZE (the plan
+ * needs more workspace than the array holds; nothing is enqueued), BIRK_ERR_DEVICE. */
+birk_status birk_apply_noalloc(birk_plan* plan, const void* v, void* out, int32_t transpose);
+
 /* out = (I_{n_x} (x) B^b) v: the b-form product (eq:xN=Birka+b).  B_j^b is anchored at
  * tau = +1 (B_j^b(1) = 0) with the derivative conditions of eq:birk-conditions, so
  * B^b = B^a - 1 w_B^T.  Computed as the B^a product (FastBV) followed by subtracting,

@@ -38,7 +38,7 @@ BIRK_J_PER_NODE = 1
 EXPORTED = [
     "birk_plan_create", "birk_plan_destroy", "birk_plan_length", "birk_plan_tune", "birk_plan_set_graphs",
     "birk_weights",
-    "birk_apply", "birk_apply_T", "birk_apply_b", "birk_apply_bT", "birk_endpoint", "birk_precond",
+    "birk_apply", "birk_apply_T", "birk_apply_noalloc", "birk_apply_b", "birk_apply_bT", "birk_endpoint", "birk_precond",
     "birk_fast_ax",
     "birk_solve_opts_default", "birk_krylov_solve", "birk_status_string",
     "birk_two_body", "birk_newton_opts_default", "birk_newton_ivp",
@@ -97,6 +97,7 @@ def _load():
     lib.birk_weights.argtypes = [vp, i32, ctypes.POINTER(dbl)]
     lib.birk_apply.argtypes = [vp, vp, vp]
     lib.birk_apply_T.argtypes = [vp, vp, vp]
+    lib.birk_apply_noalloc.argtypes = [vp, vp, vp, i32]
     lib.birk_apply_b.argtypes = [vp, vp, vp]
     lib.birk_apply_bT.argtypes = [vp, vp, vp]
     lib.birk_endpoint.argtypes = [vp, vp, vp, vp]
@@ -295,6 +296,12 @@ def birk_apply(plan: Plan, v, out) -> None:
 def birk_apply_T(plan: Plan, g, out) -> None:
     _product_args(plan, g, out, "g")
     _check(_lib.birk_apply_T(plan.handle, _ptr(g), _ptr(out)), "birk_apply_T")
+
+
+def birk_apply_noalloc(plan: Plan, v, out, transpose: bool = False) -> None:
+    """birk_apply (or birk_apply_T) with the library's fixed device workspace; allocates nothing."""
+    _product_args(plan, v, out, "v")
+    _check(_lib.birk_apply_noalloc(plan.handle, _ptr(v), _ptr(out), int(bool(transpose))), "birk_apply_noalloc")
 
 
 def birk_apply_b(plan: Plan, v, out) -> None:

@@ -21,6 +21,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -96,6 +97,48 @@ __global__ void k_extract_weights(const double* __restrict__ v, double* __restri
 }
 
 __global__ void k_set_unit(double* __restrict__ v, int64_t idx) { v[idx] = 1.0; }
+
+}  // namespace
+
+// ---- fixed product workspace of birk_apply_noalloc
+// One array per device, held from the library's first use on that device to the end of
+// the process.  Host code never uses the array's name as an address: every device needs
+// its own copy's address, resolved once per device by noalloc_base (with that device
+// current) and kept in noalloc_ptr.
+constexpr size_t kNoallocBytes = size_t(128) << 20;
+constexpr int kNoallocMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+
+std::mutex noalloc_mu;
+void* noalloc_ptr[kNoallocMaxDevices] = {};
+
+// Address of this device's array; the caller has made `dev` the current device.
+hipError_t noalloc_base(int dev, void** base) {
+  *base = nullptr;
+  if (dev < 0 || dev >= kNoallocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    noalloc_ptr[dev] = ptr;
+  }
+  *base = noalloc_ptr[dev];
+  return hipSuccess;
+}
+
+constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Bytes of the product workspace of a plan inside the fixed array: the complex work
+// buffers (two for power-of-two groups only, three when the general path runs) and the
+// c^_0 partials, each 256-byte aligned.
+size_t noalloc_need(const birk_plan* p, int* nbuf) {
+  *nbuf = (p->gen[0].host.empty() && p->gen[1].host.empty()) ? 2 : 3;
+  return (size_t)*nbuf * align256((size_t)std::max<int64_t>(p->total_work, 1) * sizeof(double2)) +
+         align256((size_t)std::max<int64_t>(p->total_part, 1) * sizeof(double));
+}
 
 }  // namespace
 
@@ -268,6 +311,11 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     free_plan(p);
     return dev_err(e);
   }
+  // set-up of birk_apply_noalloc on this device (its first call retries if this fails)
+  {
+    void* base = nullptr;
+    (void)noalloc_base(p->device, &base);
+  }
   *out = p;
   return BIRK_OK;
 }
@@ -358,6 +406,30 @@ birk_status birk_plan_set_graphs(birk_plan* p, int32_t enable) {
 
 birk_status birk_apply(birk_plan* p, const void* v, void* out) { return product(p, v, out, 0); }
 birk_status birk_apply_T(birk_plan* p, const void* g, void* out) { return product(p, g, out, 1); }
+
+// birk_apply / birk_apply_T with the product kernels' work buffers and partial sums in
+// the device's fixed array instead of the plan's own buffers: no allocation, no graph.
+// Every kernel writes each workspace element before it reads it, so nothing needs
+// clearing between calls.
+birk_status birk_apply_noalloc(birk_plan* p, const void* v, void* out, int32_t transpose) {
+  if (!p || !v || !out || v == out || (transpose != 0 && transpose != 1)) return BIRK_ERR_ARG;
+  int nbuf = 0;
+  const size_t need = noalloc_need(p, &nbuf);
+  if (need > kNoallocBytes) return BIRK_ERR_SIZE;
+  DeviceGuard g(p->device);
+  void* base = nullptr;
+  if (noalloc_base(p->device, &base) != hipSuccess) return BIRK_ERR_DEVICE;
+  const size_t buf = align256((size_t)std::max<int64_t>(p->total_work, 1) * sizeof(double2));
+  void* saved_work[3] = {p->work[0], p->work[1], p->work[2]};
+  double* saved_part = p->partials;
+  unsigned char* b = (unsigned char*)base;
+  for (int k = 0; k < 3; ++k) p->work[k] = k < nbuf ? (void*)(b + k * buf) : nullptr;
+  p->partials = (double*)(b + nbuf * buf);
+  const hipError_t e = launch_product(p, v, out, transpose);
+  for (int k = 0; k < 3; ++k) p->work[k] = saved_work[k];
+  p->partials = saved_part;
+  return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+}
 
 // b-form products (eq:xN=Birka+b): the B^a product and a per-component rank-one
 // correction on the plan's stream.
