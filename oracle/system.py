@@ -70,14 +70,25 @@ def dense_jacobian(J: np.ndarray, N_n: int) -> np.ndarray:
 
 
 def dense_A(N: int, J: np.ndarray, Ba: np.ndarray | None = None) -> np.ndarray:
-    """A = I - (I (x) B^a) blockdiag(J) (eq:Newton-ivp / eq:Achibetadef)."""
+    """A = I - (I (x) B^a) blockdiag(J) (eq:Newton-ivp / eq:Achibetadef).
+
+    Written block by block: component block (r, c) of (I (x) B^a) blockdiag(J) is B^a with
+    its column k scaled by J_k[r, c], so A_rc = delta_rc I - B^a diag(J[r, c, :]).  (The
+    same numbers as forming the Kronecker product and multiplying by the block-diagonal
+    Jacobian: each entry of that product has a single nonzero term.)"""
     N_n = N + 1
     if Ba is None:
         Ba = bk.dense_Ba(N)
     Jf = expand_jacobian(J, N_n)
     n_x = Jf.shape[0]
-    BJ = np.kron(np.eye(n_x), Ba) @ dense_jacobian(Jf, N_n)
-    return np.eye(n_x * N_n) - BJ
+    A = np.zeros((n_x * N_n, n_x * N_n))
+    for r in range(n_x):
+        for c in range(n_x):
+            blk = A[r * N_n:(r + 1) * N_n, c * N_n:(c + 1) * N_n]
+            blk -= Ba * Jf[r, c][None, :]
+            if r == c:
+                blk[np.diag_indices(N_n)] += 1.0
+    return A
 
 
 def dense_P(N: int, J: np.ndarray, w: np.ndarray | None = None) -> np.ndarray:

@@ -239,6 +239,8 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
     p->fast_kn.narrow = prec == BIRK_F32 || prec == BIRK_F32_REFINE_F64 ? 0 : 1;
     const char* nw = std::getenv("BIRK_FAST_NARROW");
     if (nw) p->fast_kn.narrow = std::atoi(nw) ? 1 : 0;
+    const char* b3 = std::getenv("BIRK_FAST_B3");
+    if (b3) p->fast_kn.b3 = std::atoi(b3) ? 1 : 0;
     const char* st = std::getenv("BIRK_FAST_STREAMS");
     if (st) p->fast_kn.streams = std::max(1, std::min(1 + birk_plan::kExtraStreams, std::atoi(st)));
   }

@@ -665,6 +665,250 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB2(
   }
 }
 
+// Reciprocal of a positive integer-valued x: the hardware estimate refined by two Newton
+// steps in double (within an ulp of 1/x, several times cheaper than a division); a plain
+// division for the other storage types.
+template <typename T>
+__device__ __forceinline__ T recip_int(T x) {
+  return T(1) / x;
+}
+template <>
+__device__ __forceinline__ double recip_int<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// stencil_fwd, stencil_tr and c0_coef with one or two reciprocals per element in place of
+// their divisions (same formulas).
+template <typename T>
+__device__ __forceinline__ T stencil_fwd_r(int k, int N, T Ym, T Yp, T invN, T inv4N1) {
+  if (k == 0) return T(0);
+  const T i2k = recip_int<T>(T(2 * k));
+  const T lo = (k == 1) ? T(1) : i2k;
+  const T em1 = (k == 1) ? T(0.5) : T(1);
+  T r = -lo * em1 * Ym;
+  if (k < N) {
+    const T ep1 = (k + 1 == N) ? T(0.5) : T(1);
+    r += ep1 * Yp * i2k;
+  }
+  if (k == N - 1) r -= Yp * inv4N1;
+  const T sc = (k == N) ? T(2) : T(1);
+  return r * invN * sc;
+}
+
+template <typename T>
+__device__ __forceinline__ T stencil_tr_r(int j, int N, T Ym, T Yp, T p0, T inv2N1) {
+  const T h = T(0.5);
+  if (j == 0) return p0 - h * Yp;
+  if (j == 1) return T(0.25) * (p0 - h * Yp);
+  const T rm = recip_int<T>(T(j - 1)), rp = recip_int<T>(T(j + 1));
+  T cm = h * rm;
+  if (j == N) cm -= inv2N1;
+  T q = -p0 * rm * rp + cm * h * Ym;
+  if (j < N) q -= T(0.25) * Yp * rp;
+  return q;
+}
+
+__device__ __forceinline__ double c0_coef_r(int k, int N) {
+  if (k == 0) return 0.5;
+  if (k == 1) return 0.25;
+  const double ek = (k == N) ? 0.5 : 1.0;
+  return -ek * recip_int<double>((double)(k - 1) * (double)(k + 1));
+}
+
+// Pass B for rows of L2 = 2^LOGL2 (512..2048) points, TB rows per tile (2 or 4), blockDim
+// = L2 / 8, with the row transforms kept in registers at both ends (fft_regs): each thread
+// builds its eight elements m = tid + i blockDim of a Hermitian row pair straight from G
+// (the elements above L2/2 from their mirror images, so each G value is read by two
+// threads), runs the first butterflies in registers, and receives its outputs
+// m = tid + i blockDim of the last stage in registers, which is the layout the stencil and
+// the second DCT's column transform use.  Only the stages in between, and the mirror
+// reads of the final separation, go through LDS.  The tile's rows are swept in pairs with
+// a rolling window: DCT-1 row pair (t0 + 2q + 1, t0 + 2q + 2) joins the pair before it,
+// the stencil of rows t0 + 2q, t0 + 2q + 1 follows, then their DCT-2 column transform and
+// store; so TB rows cost TB/2 + 1 DCT-1 and TB/2 DCT-2 transforms.
+template <typename T, int TRANS, int LOGL2, int TB>
+__global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB3(
+    const cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg, cplx<T>* __restrict__ G2, int64_t g2comp, int64_t sg2,
+    int64_t N64, int logL1, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ thi,
+    const cplx<T>* __restrict__ tlo, int tsh, double* __restrict__ part, int nt, int nc, int xcd_order) {
+  constexpr int L2 = 1 << LOGL2;
+  constexpr int NTHR = L2 / kPPT;
+  constexpr int half2 = L2 / 2, hp1 = half2 + 1;
+  constexpr int ld2 = padded_ld(L2);
+  constexpr int twsh = kLdsMaxLog - LOGL2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Yre = reinterpret_cast<T*>(smem_raw);  // one complex row: real part, imaginary part
+  T* Yim = Yre + ld2;
+  __shared__ double red[16];
+  int comp, tile;
+  xcd_tile(nt, nc, xcd_order, comp, tile);
+  const int N = (int)N64;
+  const int L1 = 1 << logL1;
+  const int t0 = TB * tile;
+  const int sgi = (int)sg;
+  const int t = (int)threadIdx.x;
+  const cplx<T>* Gc = G + (int64_t)comp * gcomp;
+  cplx<T>* G2c = G2 + (int64_t)comp * g2comp;
+  const int tmask = (1 << tsh) - 1;
+  const int sg2i = (int)sg2;
+  T p0 = T(0);
+  if (TRANS) {
+    double acc = 0.0;
+    for (int n2 = t; n2 <= half2; n2 += NTHR) acc += (double)Gc[n2].x * ((n2 == 0 || n2 == half2) ? 1.0 : 2.0);
+    p0 = (T)(0.5 * block_sum(acc, red));
+  }
+  // one DCT-1 row pair (k1a, k1a + 1) into registers: element m = t + i NTHR
+  auto dct1_pair = [&](int k1a, T (&vr)[kPPT], T (&vi)[kPPT]) {
+    int ma, mb;
+    const int sa = hrow_src(k1a, L1, &ma);
+    const int sb = hrow_src(k1a + 1, L1, &mb);
+    const cplx<T>* ga = Gc + (int64_t)sa * sgi;
+    const cplx<T>* gb = Gc + (int64_t)sb * sgi;
+    cplx<T> a[kPPT], b[kPPT];
+#pragma unroll
+    for (int i = 0; i < kPPT; ++i) {
+      const int m = t + i * NTHR;
+      const int gi = m <= half2 ? m : L2 - m;
+      a[i] = ga[gi];
+      b[i] = gb[gi];
+    }
+#pragma unroll
+    for (int i = 0; i < kPPT; ++i) {
+      const int m = t + i * NTHR;
+      const int gi = m <= half2 ? m : L2 - m;
+      cplx<T> aa = a[i], bb = b[i];
+      if (ma) aa = conjg<T>(aa);
+      if (ma == 2) aa = cmul<T>(aa, tw[gi << twsh]);
+      if (mb) bb = conjg<T>(bb);
+      if (mb == 2) bb = cmul<T>(bb, tw[gi << twsh]);
+      if (m <= half2) {
+        vr[i] = aa.x - bb.y;
+        vi[i] = aa.y + bb.x;
+      } else {
+        vr[i] = aa.x + bb.y;
+        vi[i] = bb.x - aa.y;
+      }
+    }
+    fft_regs<T, LOGL2>(Yre, vr, vi, tw);
+  };
+  const int N2 = 2 * N;
+  const T invN = T(1) / T(N), inv4N1 = T(1) / T(4 * (int64_t)N + 4), inv2N1 = T(1) / T(2 * (int64_t)N + 2);
+  double c0acc = 0.0;
+  // window: rows k1 - 1, k1 (pa*) and k1 + 1, k1 + 2 (pb*) around the pair k1 = t0 + 2q
+  T par[kPPT], pai[kPPT];
+  dct1_pair(t0 - 1, par, pai);
+#pragma unroll
+  for (int q = 0; q < TB / 2; ++q) {
+    const int k1 = t0 + 2 * q;
+    T pbr[kPPT], pbi[kPPT];
+    dct1_pair(k1 + 1, pbr, pbi);
+    // stencil of rows k1 and k1 + 1; rows k1 - 1, k1, k1 + 1, k1 + 2 = par, pai, pbr, pbi
+    T dr[kPPT], di[kPPT];
+    if (t0 >= 2) {
+      // rows k1 >= 2: every coefficient index k = K or 2N - K lies in [2, N - 2], where the
+      // stencil has no special terms, and K = k1 + L1 m <= N exactly when m < L2 / 2, i.e.
+      // for the thread's elements i < 4
+#pragma unroll
+      for (int i = 0; i < kPPT; ++i) {
+        const int m = t + i * NTHR;
+#pragma unroll
+        for (int rl = 0; rl < 2; ++rl) {
+          const int K = k1 + rl + L1 * m;
+          const int k = i < 4 ? K : N2 - K;
+          const T ylo = rl ? pai[i] : par[i];
+          const T ymid = rl ? pbr[i] : pai[i];
+          const T yhi = rl ? pbi[i] : pbr[i];
+          const T Ym = i < 4 ? ylo : yhi;
+          const T Yp = i < 4 ? yhi : ylo;
+          T d;
+          if (TRANS) {
+            // stencil_tr for 2 <= j < N: -p0 / (j^2 - 1) + (Ym / (j - 1) - Yp / (j + 1)) / 4
+            const T rm = recip_int<T>(T(k - 1)), rp = recip_int<T>(T(k + 1));
+            d = -p0 * rm * rp + T(0.25) * (Ym * rm - Yp * rp);
+          } else {
+            // stencil_fwd for 2 <= k < N - 1: (Yp - Ym) / (2 k N); c0 weight -1 / (k^2 - 1),
+            // from rows up to L1 / 2 (the upper half of row L1 / 2 mirrors its lower half)
+            const double kd = (double)k;
+            const int kr = k1 + rl;
+            d = (Yp - Ym) * recip_int<T>(T(2 * k)) * invN;
+            if (kr < L1 / 2 || (kr == L1 / 2 && i < 4)) c0acc -= (double)ymid * recip_int<double>(kd * kd - 1.0);
+          }
+          if (rl == 0) dr[i] = d;
+          else di[i] = d;
+        }
+      }
+    } else {
+#pragma unroll
+    for (int i = 0; i < kPPT; ++i) {
+      const int m = t + i * NTHR;
+#pragma unroll
+      for (int rl = 0; rl < 2; ++rl) {
+        const int kr = k1 + rl;
+        const T ylo = rl ? pai[i] : par[i];
+        const T ymid = rl ? pbr[i] : pai[i];
+        const T yhi = rl ? pbi[i] : pbr[i];
+        const int K = kr + L1 * m;
+        const bool lowhalf = K <= N;
+        const int k = lowhalf ? K : N2 - K;
+        const T Ym = lowhalf ? ylo : yhi;
+        const T Yp = lowhalf ? yhi : ylo;
+        T d;
+        if (TRANS) {
+          d = stencil_tr_r<T>(k, N, Ym, Yp, p0, inv2N1);
+        } else {
+          d = stencil_fwd_r<T>(k, N, Ym, Yp, invN, inv4N1);
+          if (kr <= L1 / 2 && ((kr != 0 && kr != L1 / 2) || lowhalf)) c0acc += c0_coef_r(k, N) * (double)ymid;
+        }
+        if (rl == 0) dr[i] = d;
+        else di[i] = d;
+      }
+    }
+    }
+    // column transform of DCT 2 on d(k1) + i d(k1 + 1); the separation needs the mirror
+    // element L2 - q, held by another thread, so the outputs go through LDS once
+    fft_regs<T, LOGL2>(Yre, dr, di, tw);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kPPT; ++i) {
+      const int m = t + i * NTHR;
+      Yre[pad(m)] = dr[i];
+      Yim[pad(m)] = di[i];
+    }
+    __syncthreads();
+    constexpr int per = (hp1 + NTHR - 1) / NTHR;  // 5
+#pragma unroll
+    for (int u = 0; u < per; ++u) {
+      const int qq = t + u * NTHR;
+      if (qq < hp1) {
+        const int qm = (L2 - qq) & (L2 - 1);
+        const T mr = Yre[pad(qm)], mi = Yim[pad(qm)];
+#pragma unroll
+        for (int rl = 0; rl < 2; ++rl) {
+          const int r = k1 + rl;
+          if (r > L1 / 2) continue;
+          const int tt = r * qq;
+          const cplx<T> w = cmul<T>(thi[tt >> tsh], tlo[tt & tmask]);
+          const cplx<T> v = separate<T>(dr[u], di[u], mr, mi, rl);
+          G2c[r * sg2i + qq] = cmul<T>(v, w);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kPPT; ++i) {
+      par[i] = pbr[i];
+      pai[i] = pbi[i];
+    }
+  }
+  if (!TRANS) {
+    const double tot = block_sum(c0acc, red);
+    if (t == 0) part[(int64_t)comp * nt + tile] = tot;
+  }
+}
+
 // ---------------------------------------------------------------- pass C
 // Rows q1 in [c0, c0 + W) of the second DCT (Hermitian in r, rebuilt from r <= L1/2),
 // two per complex FFT of length L1, written to the natural output positions
@@ -1053,7 +1297,29 @@ static hipError_t fast_passes(birk_plan* p, const FastGroup& g, const T* v, T* o
                        ilog2i(WA), G, gcomp, sg, tw, thi, tlo, tsh, transpose ? 1 : 0, ntA, nc, kn.xcd);
   }
   const int ntB = fast_tiles_b<T>(kn, g.N);
-  if (use_b2(kn, logL2)) {
+  if (use_b2(kn, logL2) && kn.b3) {
+    const int lds = 2 * ld2 * (int)sizeof(T);
+    const int thr = L2 / fast::kPPT;
+    const int tb4 = b2_rows(kn) == 4;
+    auto f = fast::k_fastB3<T, 0, 11, 2>;
+    switch ((logL2 * 2 + (transpose ? 1 : 0)) * 2 + tb4) {
+      case 36: f = fast::k_fastB3<T, 0, 9, 2>; break;
+      case 37: f = fast::k_fastB3<T, 0, 9, 4>; break;
+      case 38: f = fast::k_fastB3<T, 1, 9, 2>; break;
+      case 39: f = fast::k_fastB3<T, 1, 9, 4>; break;
+      case 40: f = fast::k_fastB3<T, 0, 10, 2>; break;
+      case 41: f = fast::k_fastB3<T, 0, 10, 4>; break;
+      case 42: f = fast::k_fastB3<T, 1, 10, 2>; break;
+      case 43: f = fast::k_fastB3<T, 1, 10, 4>; break;
+      case 44: f = fast::k_fastB3<T, 0, 11, 2>; break;
+      case 45: f = fast::k_fastB3<T, 0, 11, 4>; break;
+      case 46: f = fast::k_fastB3<T, 1, 11, 2>; break;
+      default: f = fast::k_fastB3<T, 1, 11, 4>; break;
+    }
+    lds_attr(f, lds);
+    hipLaunchKernelGGL(f, dim3(ntB * nc), dim3(thr), lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, tw, thi, tlo,
+                       tsh, part, ntB, nc, kn.xcd);
+  } else if (use_b2(kn, logL2)) {
     const int lds = 2 * ld2 * (int)sizeof(T);
     const int thr = L2 / fast::kPPT;
     auto f = fast::k_fastB2<T, 0, 11, 2>;

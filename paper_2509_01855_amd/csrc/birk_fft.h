@@ -202,5 +202,93 @@ __device__ __forceinline__ void fft_ct(T* __restrict__ buf, const cplx<T>* __res
   stages8_ct<T, LOGL, COUNT, 0>(buf, tw);
 }
 
+// ---- one transform of length 2^LOGL per workgroup (blockDim = 2^LOGL / 8) whose input
+// and output live in registers: v[i] is element m = threadIdx.x + NT i (NT = 2^LOGL / 8)
+// both before and after.  The first stage (radix 2^(LOGL mod 3), or 8; no twiddles) reads
+// its butterfly inputs straight from the registers, and the last radix-8 stage (Ns = NT)
+// leaves butterfly t's outputs exactly at m = t + NT r, so only the stages in between
+// pass through the LDS rows (two fewer LDS round trips than fft_ct).
+template <typename T, int LOGL>
+__device__ __forceinline__ void stage_first_regs(T* __restrict__ buf, const T (&vr)[kPPT], const T (&vi)[kPPT]) {
+  constexpr int R = (LOGL % 3 == 1) ? 2 : (LOGL % 3 == 2) ? 4 : 8;
+  constexpr int logR = (R == 8) ? 3 : (R == 4) ? 2 : 1;
+  constexpr int NB = kPPT / R;
+  constexpr int NT = 1 << (LOGL - 3);
+  constexpr int LD = padded_ld(1 << LOGL);
+  T xr[NB][R], xi[NB][R];
+#pragma unroll
+  for (int ib = 0; ib < NB; ++ib) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      xr[ib][r] = vr[ib + NB * r];   // butterfly b = t + NT ib takes b + (L / R) r = t + NT (ib + NB r)
+      xi[ib][r] = vi[ib + NB * r];
+    }
+    dft_reg<T, R>(xr[ib], xi[ib]);
+  }
+  __syncthreads();  // earlier readers of buf are done
+#pragma unroll
+  for (int ib = 0; ib < NB; ++ib) {
+    const int dst = ((int)threadIdx.x + NT * ib) << logR;   // Ns = 1: outputs at R b + r
+    const int pd = dst + (dst >> 4);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      buf[pd + r] = xr[ib][r];
+      buf[LD + pd + r] = xi[ib][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int LOGL, int K>
+__device__ __forceinline__ void stages8_mid(T* __restrict__ buf, const cplx<T>* __restrict__ tw) {
+  constexpr int BASE = (LOGL % 3) ? (LOGL % 3) : 3;
+  constexpr int LOGNS = BASE + 3 * K;
+  if constexpr (LOGNS < LOGL - 3) {
+    cplx<T> w[3];
+    load_tw_stage<T>(w, LOGL, LOGNS, tw);
+    stage_ct<T, LOGL, LOGNS, 8, 1>(buf, w);
+    stages8_mid<T, LOGL, K + 1>(buf, tw);
+  }
+}
+
+template <typename T, int LOGL>
+__device__ __forceinline__ void stage_last_regs(const T* __restrict__ buf, T (&vr)[kPPT], T (&vi)[kPPT],
+                                                const cplx<T>* __restrict__ tw) {
+  constexpr int NT = 1 << (LOGL - 3);
+  constexpr int LD = padded_ld(1 << LOGL);
+  const int t = (int)threadIdx.x;
+  const int pj = t + (t >> 4);
+#pragma unroll
+  for (int r = 0; r < kPPT; ++r) {
+    const int off = r * NT + ((r * NT) >> 4);
+    vr[r] = buf[pj + off];
+    vi[r] = buf[LD + pj + off];
+  }
+  if (t != 0) {   // butterfly j = t of the stage at Ns = NT: twiddles W_(8 NT)^(t r)
+    cplx<T> w[3];
+    load_tw_stage<T>(w, LOGL, LOGL - 3, tw);
+    const cplx<T> w1 = w[0], w2 = w[1], w4 = w[2];
+    const cplx<T> w3 = fast::cmul<T>(w2, w1);
+    const cplx<T> w5 = fast::cmul<T>(w4, w1), w6 = fast::cmul<T>(w4, w2), w7 = fast::cmul<T>(w4, w3);
+    cmul_inplace<T>(vr[1], vi[1], w1.x, w1.y);
+    cmul_inplace<T>(vr[2], vi[2], w2.x, w2.y);
+    cmul_inplace<T>(vr[3], vi[3], w3.x, w3.y);
+    cmul_inplace<T>(vr[4], vi[4], w4.x, w4.y);
+    cmul_inplace<T>(vr[5], vi[5], w5.x, w5.y);
+    cmul_inplace<T>(vr[6], vi[6], w6.x, w6.y);
+    cmul_inplace<T>(vr[7], vi[7], w7.x, w7.y);
+  }
+  dft_reg<T, 8>(vr, vi);
+}
+
+// The whole transform; buf is one split complex row (real part, then imaginary part).
+template <typename T, int LOGL>
+__device__ __forceinline__ void fft_regs(T* __restrict__ buf, T (&vr)[kPPT], T (&vi)[kPPT],
+                                         const cplx<T>* __restrict__ tw) {
+  stage_first_regs<T, LOGL>(buf, vr, vi);
+  stages8_mid<T, LOGL, 0>(buf, tw);
+  stage_last_regs<T, LOGL>(buf, vr, vi, tw);
+}
+
 }  // namespace fast
 }  // namespace birk

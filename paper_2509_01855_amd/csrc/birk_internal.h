@@ -88,6 +88,7 @@ struct FastKnobs {
                               // streams, so that one part's next pass fills another's tail
   int narrow = 0;             // 1: passes A and C of L1 = 2^9, 2^10 in tiles of 4 columns (else 8);
                               // plans of 8-byte reals start with 1
+  int b3 = 1;                 // two-row pass B with the row transforms register-resident at both ends
 };
 
 struct FastGroup {

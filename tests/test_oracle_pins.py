@@ -488,3 +488,15 @@ def test_newton_ivp_line_search_engages():
     assert np.max(np.abs(X - ivp["exact"])) <= 1e-9
     assert min(steps) < 1.0 and steps[-1] == 1.0
     assert all(b < a for a, b in zip(hist, hist[1:]))
+
+
+@pytest.mark.parametrize("kind,N_n", [("lti", 17), ("kepler", 33)])
+def test_dense_A_is_the_kronecker_form(kind, N_n):
+    """The block-by-block construction of A equals I - kron(I, B^a) blockdiag(J) formed
+    literally, bit for bit."""
+    inst = wl.lti_instance(0, N_n) if kind == "lti" else wl.kepler_instance(2, N_n)
+    N = N_n - 1
+    Ba = bk.dense_Ba(N)
+    Jf = sy.expand_jacobian(inst.J, N_n)
+    lit = np.eye(inst.n) - np.kron(np.eye(inst.n_x), Ba) @ sy.dense_jacobian(Jf, N_n)
+    assert np.array_equal(sy.dense_A(N, inst.J, Ba), lit)
