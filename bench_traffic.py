@@ -7,7 +7,7 @@ is merged into
 <out.json>, which keeps one record per schedule for the current kernel sources.
 
 Usage (after the four counter runs described in profiles/README.md):
-    python -m paper_2509_01855_amd.traffic <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir> <out.json>
+    python bench_traffic.py <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir> <out.json>
 
 Each counter is scaled by what it reads for a plain 1 GiB copy (bench.py --calibrate-copy):
 scale = known bytes / counter value, separately for FETCH_SIZE and WRITE_SIZE.  The
@@ -24,7 +24,7 @@ import json
 import os
 import sys
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["paper_2509_01855_amd/csrc/birk_fast.hip", "paper_2509_01855_amd/csrc/birk_dct.hip",
            "paper_2509_01855_amd/csrc/birk_fft.h"]
 

@@ -38,6 +38,8 @@ __all__ = [
     "kepler_instance",
     "batched_instances",
     "sparse_modes",
+    "sparse_series",
+    "node_sparse",
     "random_vectors",
     "kepler_ivp",
     "Instance",
@@ -188,6 +190,36 @@ def sparse_modes(seed, N: int, count: int = 64):
     modes = modes[modes <= N]
     alphas = rng.standard_normal(modes.shape[0])
     return modes, alphas
+
+
+def sparse_series(seed, N: int, ncomp: int, count: int):
+    """ncomp sparse Chebyshev series sampled on the N + 1 CGL nodes: component c takes the
+    modes and amplitudes of sparse_modes([*seed, c, N], N, count) and its values
+    v_j = sum_s alpha_s cos(pi k_s (N - j) / N) (the integer argument reduced exactly).
+    Returns (values (ncomp, N + 1), [(modes, alphas) per component])."""
+    seed = list(seed) if isinstance(seed, (list, tuple)) else [seed]
+    j = np.arange(N + 1, dtype=np.int64)
+    X = np.zeros((ncomp, N + 1))
+    specs = []
+    for c in range(ncomp):
+        modes, alphas = sparse_modes([*seed, c, N], N, count=count)
+        for k, a in zip(modes, alphas):
+            X[c] += a * np.cos(np.pi * ((int(k) * (N - j)) % (2 * N)).astype(np.float64) / N)
+        specs.append((modes, alphas))
+    return X, specs
+
+
+def node_sparse(seed, N: int, ncomp: int, per: int = 6):
+    """ncomp vectors on N + 1 nodes, each with N(0, 1) values at `per` seeded nodes (the
+    two end nodes among them) and zeros elsewhere.  Returns (values, [nodes per component])."""
+    rng = np.random.default_rng(seed)
+    G = np.zeros((ncomp, N + 1))
+    nodes = []
+    for c in range(ncomp):
+        idx = np.unique(np.concatenate([[0, N], rng.integers(0, N + 1, per - 2)]))
+        G[c, idx] = rng.standard_normal(idx.shape[0])
+        nodes.append(idx)
+    return G, nodes
 
 
 def kepler_ivp(seed, N_n: int, e: float | None = None):

@@ -1,5 +1,5 @@
 """Host-side logic of the measurement tools (no GPU): the traffic records' schedule keys
-and the HBM-byte arithmetic of paper_2509_01855_amd.traffic on synthetic counter files."""
+and the HBM-byte arithmetic of bench_traffic.py on synthetic counter files."""
 
 import csv
 import json
@@ -7,7 +7,7 @@ import os
 
 import pytest
 
-from paper_2509_01855_amd import traffic
+import bench_traffic as traffic
 
 
 def test_schedule_keys():
