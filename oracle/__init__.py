@@ -15,10 +15,13 @@ Every function here is the plain, slow definition of what the GPU path computes:
 * ``newton``    -- the two-body right-hand side and its Jacobian, the residual
   X - x^a b - B^a f(X) of the nonlinear IVP, and Newton's method on it with dense
   linear solves and Armijo backtracking.
+* ``kkt``       -- the symmetric saddle-point (KKT) form of the collocated system, the
+  backward substitution P^{-T}, the block-diagonal SPD preconditioner, and a plain
+  preconditioned MINRES.
 
 It shares no code with the HIP path.  Arithmetic is float64 throughout; library
 primitives (LAPACK solves, matrix products, scipy's DCT, Gauss-Legendre nodes) serve
 as single steps only.
 """
 
-from . import birkhoff, newton, system  # noqa: F401
+from . import birkhoff, kkt, newton, system  # noqa: F401
