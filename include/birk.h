@@ -202,11 +202,15 @@ birk_status birk_endpoint(birk_plan* plan, const double* xa, const void* v, doub
  *              xi_k = (I - w_k J_k/2)^{-1} (y_k + S_k), S_{k+1} = S_k + w_k J_k xi_k
  *              (FastPinvY box; its printed running-sum update is read as exact
  *              forward substitution), evaluated as a parallel scan of affine maps.
+ * inverse = 2: out = P^{-T} y by block backward substitution with P^T (row j:
+ *              (I - w_j J_j^T / 2) x_j - w_j J_j^T sum_{k>j} x_k = y_j), evaluated as a
+ *              scan of affine maps from the last node down; BIRK_F64 plans only (the
+ *              preconditioner of birk_kkt_solve).
  * J: device, double, laid out per jac_kind (see Layout).  y, out: plan storage type
  * (BIRK_DF32 plans: not supported, BIRK_ERR_UNSUPPORTED).  out must not overlap y.
- * Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED (n_x > 12 or BIRK_DF32).  A singular
- * pivot is not reported by this call (it yields non-finite values); birk_krylov_solve
- * checks pivots and returns BIRK_ERR_SINGULAR. */
+ * Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED (n_x > 12, BIRK_DF32, inverse = 2 on plans
+ * other than BIRK_F64).  A singular pivot is not reported by this call (it yields
+ * non-finite values); birk_krylov_solve checks pivots and returns BIRK_ERR_SINGULAR. */
 birk_status birk_precond(birk_plan* plan, birk_jac_kind jac_kind, const double* J,
                          const void* y, void* out, int32_t inverse);
 
@@ -216,7 +220,9 @@ birk_status birk_fast_ax(birk_plan* plan, birk_jac_kind jac_kind, const double* 
                          const double* x, double* out);
 
 typedef struct {
-  int32_t method;       /* 0 = GMRES; 1 = MINRES (reserved: BIRK_ERR_UNSUPPORTED)     */
+  int32_t method;       /* 0 = GMRES; 1 = MINRES on the symmetric KKT form (see
+                           birk_kkt_solve; in birk_krylov_solve: H = I, f = 0, g = beta,
+                           BIRK_F64 plans, no use_x0)                                  */
   int32_t restart;      /* GMRES restart length m, 1..31 (default 30)                 */
   int32_t max_iter;     /* total inner iterations allowed (default 300)               */
   double rtol;          /* target ||beta - A chi||_2 / ||beta||_2, true residual in
@@ -246,12 +252,44 @@ typedef struct {
  * the status is an error.  opts may be NULL (defaults); info may be NULL.
  * Returns BIRK_OK when every instance converged, else the first failing instance's
  * status.  The first call (or one with a larger restart) allocates the Krylov workspace
- * (see Plan).  Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED (MINRES, BIRK_F32 or BIRK_DF32
- * plans, n_x > 12), BIRK_ERR_NOMEM, BIRK_ERR_SINGULAR, BIRK_ERR_NOCONV,
+ * (see Plan).  opts->method = 1 solves the same system by MINRES on the symmetric form
+ * [[I, A^T], [A, 0]] [chi; lambda] = [0; beta] (birk_kkt_solve with H = I, f = 0; A is
+ * square and invertible, so chi solves A chi = beta; the stopping test is then on the
+ * residual of the symmetric system).  Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED
+ * (BIRK_F32 or BIRK_DF32 plans, n_x > 12 with the preconditioner; MINRES also: mixed
+ * plans or use_x0), BIRK_ERR_NOMEM, BIRK_ERR_SINGULAR, BIRK_ERR_NOCONV,
  * BIRK_ERR_BREAKDOWN, BIRK_ERR_NONFINITE, BIRK_ERR_DEVICE. */
 birk_status birk_krylov_solve(birk_plan* plan, birk_jac_kind jac_kind, const double* J,
                               const double* beta, double* chi, const birk_solve_opts* opts,
                               birk_solve_info* info);
+
+/* Symmetric saddle-point (KKT) form, solved by MINRES.  The paper counts matrix-free KKT
+ * solves per SQP iteration (Table 1 and the orbit-transfer results) without stating the
+ * system; this library's reading is the equality-constrained quadratic model of one step,
+ *     min 1/2 (chi - chi_r)^T H (chi - chi_r)   s.t.   A chi = g,
+ * A = I - (I (x) B^a) J (eq:Newton-ivp), H = diag(h) > 0, f = H chi_r, whose optimality
+ * conditions are
+ *     [ H  A^T ] [ chi    ]   [ f ]
+ *     [ A  0   ] [ lambda ] = [ g ].
+ * MINRES (Paige-Saunders) on this symmetric indefinite system, preconditioned (use_precond)
+ * by M = blockdiag(H, P H^{-1} P^T) with the Birkhoff preconditioner P = I - B~^a J
+ * (B~^a section; P^{-T} by backward substitution), restarted on the true residual in
+ * double until ||[f; g] - K [chi; lambda]||_2 <= rtol ||[f; g]||_2 per instance.  The
+ * Lanczos, rotation and step scalars stay on the device; the host reads them once per
+ * eight iterations.
+ * J: as for birk_krylov_solve.  h: device double, birk_plan_length entries, positive, or
+ * NULL for H = I.  f: device double (length as h) or NULL for f = 0.  g: device double.
+ * chi (and lam, if not NULL): device double outputs (and the starting point when
+ * opts->use_x0 = 1, which needs lam).  BIRK_F64 plans only.  opts: rtol, max_iter (total
+ * MINRES iterations), use_precond and use_x0 are used; NULL = defaults.  info: inner =
+ * MINRES iterations, outer = restarts, rel_resid = the final relative KKT residual.
+ * The first call allocates the KKT workspace (nine pairs of vectors and the scan
+ * scratch), kept with the plan.  Synchronous.  Errors: BIRK_ERR_ARG (NULL, overlaps,
+ * bad options), BIRK_ERR_UNSUPPORTED (plans other than BIRK_F64, n_x > 12 with the
+ * preconditioner), BIRK_ERR_NOMEM, BIRK_ERR_NOCONV, BIRK_ERR_NONFINITE, BIRK_ERR_DEVICE. */
+birk_status birk_kkt_solve(birk_plan* plan, birk_jac_kind jac_kind, const double* J, const double* h,
+                           const double* f, const double* g, double* chi, double* lam,
+                           const birk_solve_opts* opts, birk_solve_info* info);
 
 /* ---- Nonlinear IVP: Newton's method on X - x^a b - B^a f(X) = 0 (eq:X-V=nonlin) ---- */
 

@@ -40,7 +40,7 @@ EXPORTED = [
     "birk_weights",
     "birk_apply", "birk_apply_T", "birk_apply_noalloc", "birk_apply_b", "birk_apply_bT", "birk_endpoint", "birk_precond",
     "birk_fast_ax",
-    "birk_solve_opts_default", "birk_krylov_solve", "birk_status_string",
+    "birk_solve_opts_default", "birk_krylov_solve", "birk_kkt_solve", "birk_status_string",
     "birk_two_body", "birk_newton_opts_default", "birk_newton_ivp",
 ]
 
@@ -107,6 +107,8 @@ def _load():
     lib.birk_solve_opts_default.restype = None
     lib.birk_krylov_solve.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(birk_solve_opts),
                                       ctypes.POINTER(birk_solve_info)]
+    lib.birk_kkt_solve.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(birk_solve_opts),
+                                   ctypes.POINTER(birk_solve_info)]
     lib.birk_two_body.argtypes = [vp, dbl, dbl, vp, vp, vp]
     lib.birk_newton_opts_default.argtypes = [ctypes.POINTER(birk_newton_opts)]
     lib.birk_newton_opts_default.restype = None
@@ -321,10 +323,11 @@ def birk_endpoint(plan: Plan, xa, v, xb) -> None:
     _check(_lib.birk_endpoint(plan.handle, _ptr(xa), _ptr(v), _ptr(xb)), "birk_endpoint")
 
 
-def birk_precond(plan: Plan, J, y, out, inverse: bool, jac_kind: int = BIRK_J_PER_NODE) -> None:
+def birk_precond(plan: Plan, J, y, out, inverse, jac_kind: int = BIRK_J_PER_NODE) -> None:
+    """inverse: 0 (or False) P y, 1 (or True) P^{-1} y, 2 P^{-T} y."""
     _validate(plan, _spec_jac(plan, J, jac_kind), _spec_vec(plan, y, "y"), _spec_vec(plan, out, "out"),
               disjoint=[("y", "out"), ("J", "out")])
-    _check(_lib.birk_precond(plan.handle, int(jac_kind), _ptr(J), _ptr(y), _ptr(out), int(bool(inverse))),
+    _check(_lib.birk_precond(plan.handle, int(jac_kind), _ptr(J), _ptr(y), _ptr(out), int(inverse)),
            "birk_precond")
 
 
@@ -363,6 +366,35 @@ def birk_krylov_solve(plan: Plan, J, beta, chi, jac_kind: int = BIRK_J_PER_NODE,
            "outer_iters": list(outer), "rel_resid": list(res)}
     if raise_on_error and st != BIRK_OK:
         raise BirkError(st, "birk_krylov_solve")
+    return out
+
+
+def birk_kkt_solve(plan: Plan, J, g, chi, lam=None, h=None, f=None, jac_kind: int = BIRK_J_PER_NODE,
+                   raise_on_error: bool = True, **opts):
+    """MINRES on [[diag(h), A^T], [A, 0]] [chi; lam] = [f; g] (h None: identity, f None: zero,
+    lam None: the multipliers are not returned).  Returns a dict like birk_krylov_solve."""
+    o = birk_solve_opts_default()
+    o.method = 1
+    for k, v in opts.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown solve option {k}")
+        setattr(o, k, v)
+    _validate(plan, _spec_jac(plan, J, jac_kind), _spec_f64(plan, g, "g"), _spec_f64(plan, chi, "chi"),
+              _spec_f64(plan, lam, "lam", allow_none=True), _spec_f64(plan, h, "h", allow_none=True),
+              _spec_f64(plan, f, "f", allow_none=True),
+              disjoint=[(a, b) for a in ("chi", "lam") for b in ("J", "g", "h", "f")] + [("chi", "lam")])
+    b = len(plan.n_nodes)
+    stv = (ctypes.c_int32 * b)()
+    inner = (ctypes.c_int32 * b)()
+    outer = (ctypes.c_int32 * b)()
+    res = (ctypes.c_double * b)()
+    info = birk_solve_info(stv, inner, outer, res)
+    st = _lib.birk_kkt_solve(plan.handle, int(jac_kind), _ptr(J), _ptr(h), _ptr(f), _ptr(g), _ptr(chi), _ptr(lam),
+                             ctypes.byref(o), ctypes.byref(info))
+    out = {"status": int(st), "inst_status": list(stv), "inner_iters": list(inner),
+           "outer_iters": list(outer), "rel_resid": list(res)}
+    if raise_on_error and st != BIRK_OK:
+        raise BirkError(st, "birk_kkt_solve")
     return out
 
 

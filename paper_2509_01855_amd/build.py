@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libbirk.so")
 
-SOURCES = ["birk_dct.hip", "birk_fast.hip", "birk_solve.hip", "birk_bform.hip", "birk_newton.hip", "birk_api.cpp"]
+SOURCES = ["birk_dct.hip", "birk_fast.hip", "birk_solve.hip", "birk_bform.hip", "birk_newton.hip", "birk_kkt.hip",
+           "birk_api.cpp"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -81,6 +81,7 @@ void free_plan(birk_plan* p) {
   if (p->krylov_Q) (void)hipFree(p->krylov_Q);
   if (p->krylov_vec) (void)hipFree(p->krylov_vec);
   if (p->newton_buf) (void)hipFree(p->newton_buf);
+  if (p->kkt_buf) (void)hipFree(p->kkt_buf);
   if (p->krylov_dots) (void)hipFree(p->krylov_dots);
   if (p->krylov_part) (void)hipFree(p->krylov_part);
   if (p->krylov_coef) (void)hipFree(p->krylov_coef);
@@ -309,6 +310,7 @@ birk_status birk_plan_create(birk_plan** out, int32_t batch, const int64_t* n_no
   if (e == hipSuccess) e = plan_bform(p);
   if (e == hipSuccess) e = plan_instances(p);
   if (e == hipSuccess) e = plan_solve(p);
+  if (e == hipSuccess) e = plan_kkt(p);
   if (e != hipSuccess) {
     free_plan(p);
     return dev_err(e);
@@ -493,11 +495,16 @@ birk_status birk_precond(birk_plan* p, birk_jac_kind jk, const double* J, const 
                          int32_t inverse) {
   if (!p || !J || !y || !out || y == out) return BIRK_ERR_ARG;
   if (jk != BIRK_J_CONSTANT && jk != BIRK_J_PER_NODE) return BIRK_ERR_ARG;
-  if (inverse != 0 && inverse != 1) return BIRK_ERR_ARG;
+  if (inverse != 0 && inverse != 1 && inverse != 2) return BIRK_ERR_ARG;
   if (p->prec == BIRK_DF32) return BIRK_ERR_UNSUPPORTED;
   if (inverse && !nx_ok_for_precond(p)) return BIRK_ERR_UNSUPPORTED;
+  if (inverse == 2 && p->prec != BIRK_F64) return BIRK_ERR_UNSUPPORTED;
   DeviceGuard g(p->device);
   hipError_t e;
+  if (inverse == 2) {
+    e = precond_inverse_t(p, jk, J, (const double*)y, (double*)out, p->bt_scr, p->stream);
+    return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+  }
   if (inverse) {
     e = precond_prepare(p, jk, J, p->prec == BIRK_F64 ? 0 : 1, p->stream);
     if (e != hipSuccess) return BIRK_ERR_DEVICE;
@@ -770,7 +777,18 @@ extern "C" birk_status birk_krylov_solve(birk_plan* p, birk_jac_kind jk, const d
   birk_solve_opts o;
   birk_solve_opts_default(&o);
   if (opts_in) o = *opts_in;
-  if (o.method == 1) return BIRK_ERR_UNSUPPORTED;
+  if (o.method == 1) {
+    // MINRES on the symmetric form [[I, A^T], [A, 0]] [chi; lambda] = [0; beta]: A is square
+    // and invertible, so its chi part solves A chi = beta
+    if (o.max_iter < 1 || !(o.rtol > 0.0)) return BIRK_ERR_ARG;
+    if (p->prec != BIRK_F64) return BIRK_ERR_UNSUPPORTED;
+    if (o.use_precond && !nx_ok_for_precond(p)) return BIRK_ERR_UNSUPPORTED;
+    DeviceGuard g(p->device);
+    birk_solve_opts k = o;
+    k.use_x0 = 0;
+    if (o.use_x0) return BIRK_ERR_UNSUPPORTED;
+    return kkt_solve(p, jk, J, nullptr, nullptr, beta, chi, nullptr, &k, info);
+  }
   if (o.method != 0) return BIRK_ERR_ARG;
   if (o.restart < 1 || o.restart > kKryMaxDots - 1 || o.max_iter < 1 || !(o.rtol > 0.0)) return BIRK_ERR_ARG;
   if (p->prec == BIRK_F32 || p->prec == BIRK_DF32) return BIRK_ERR_UNSUPPORTED;
@@ -878,6 +896,28 @@ extern "C" birk_status birk_krylov_solve(birk_plan* p, birk_jac_kind jk, const d
   if (result == BIRK_ERR_SINGULAR && info && info->status)
     for (int i = 0; i < B; ++i) info->status[i] = BIRK_ERR_SINGULAR;
   return result;
+}
+
+// ------------------------------------------------------------------ the KKT form
+extern "C" birk_status birk_kkt_solve(birk_plan* p, birk_jac_kind jk, const double* J, const double* h,
+                                      const double* f, const double* g, double* chi, double* lam,
+                                      const birk_solve_opts* opts_in, birk_solve_info* info) {
+  if (!p || !J || !g || !chi) return BIRK_ERR_ARG;
+  if (jk != BIRK_J_CONSTANT && jk != BIRK_J_PER_NODE) return BIRK_ERR_ARG;
+  const void* in[] = {J, h, f, g};
+  for (const void* a : in)
+    if (a && (a == chi || a == lam)) return BIRK_ERR_ARG;
+  if (lam && lam == chi) return BIRK_ERR_ARG;
+  birk_solve_opts o;
+  birk_solve_opts_default(&o);
+  o.method = 1;
+  if (opts_in) o = *opts_in;
+  if (o.max_iter < 1 || !(o.rtol > 0.0) || (o.use_x0 != 0 && o.use_x0 != 1)) return BIRK_ERR_ARG;
+  if (o.use_x0 && !lam) return BIRK_ERR_ARG;
+  if (p->prec != BIRK_F64) return BIRK_ERR_UNSUPPORTED;
+  if (o.use_precond && !nx_ok_for_precond(p)) return BIRK_ERR_UNSUPPORTED;
+  DeviceGuard gd(p->device);
+  return kkt_solve(p, jk, J, h, f, g, chi, lam, &o, info);
 }
 
 // ------------------------------------------------------------------ Newton on the IVP

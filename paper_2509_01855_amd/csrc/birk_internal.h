@@ -171,6 +171,22 @@ struct PinvClass {
   int n_tile = 0;
 };
 
+// Backward scan of P^{-T} (birk_kkt.hip): one instance of one n_x class.
+struct BtDesc {
+  int64_t Nn, off, joff, jcoff;
+  int64_t nblk;        // blocks of 1024 nodes
+  int64_t soff;        // offset of its block maps and entry states in the scan scratch (doubles)
+  const double* w;     // CC weights
+};
+struct BtClass {
+  int nx = 0, ninst = 0;
+  int nblk = 0;        // (instance, block) tiles over all instances
+  int nnode = 0;       // (instance, block of 256 nodes) tiles
+  BtDesc* dev = nullptr;
+  int2* tiles = nullptr;
+  int2* ntiles256 = nullptr;
+};
+
 // Krylov vector segmentation: tiles of kSegChunk elements, each inside one instance.
 constexpr int kSegChunk = 2048;
 struct SegSet {
@@ -226,6 +242,10 @@ struct birk_plan {
   int2* pfwd_pairs = nullptr;       // P y scans: (instance, component)
   int pfwd_npairs = 0;
   void* newton_buf = nullptr;       // Newton workspace, allocated by the first Newton solve
+  std::vector<birk::BtClass> btclass;  // P^{-T} scan schedule, one class per n_x
+  int64_t total_bt = 0;             // doubles of P^{-T} scan scratch
+  double* bt_scr = nullptr;         // P^{-T} scan scratch (block maps and entry states)
+  void* kkt_buf = nullptr;          // KKT / MINRES workspace, allocated by the first KKT solve
   double* comp_val = nullptr;       // one double per component (last node, or a total)
   double* comp_part = nullptr;      // per-component reduction partials (CompDesc::part)
   int use_fast = 1;               // power-of-two N takes the three-pass path
@@ -342,5 +362,17 @@ template <typename T>
 void scombine(const birk_plan* p, const T* Q, const double* c, int64_t cstride, const int* cnt, double* x,
               hipStream_t s);
 }  // namespace kry
+
+// ---- the KKT form and MINRES (birk_kkt.hip) ----
+// Build the P^{-T} scan classes (after the weights exist).
+hipError_t plan_kkt(birk_plan* p);
+// x = P^{-T} y in double (scr: the plan's KKT scan scratch).
+hipError_t precond_inverse_t(birk_plan* p, int jac_kind, const double* J, const double* y, double* x, double* scr,
+                             hipStream_t s);
+// y_k = J_k^T x_k per node, double.
+hipError_t jac_t_times(birk_plan* p, int jac_kind, const double* J, const double* x, double* y, hipStream_t s);
+// MINRES on [[H, A^T], [A, 0]] [chi; lambda] = [f; g] (h or f null: identity, zero).
+birk_status kkt_solve(birk_plan* p, int jac_kind, const double* J, const double* h, const double* f,
+                      const double* g, double* chi, double* lam, const birk_solve_opts* o, birk_solve_info* info);
 
 }  // namespace birk
