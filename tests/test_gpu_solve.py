@@ -152,9 +152,15 @@ def test_error_paths(B):
     # iteration limit
     _, info = _solve(B, inst, beta, B.BIRK_F64, rtol=1e-15, max_iter=1)
     assert info["status"] == B.BIRK_ERR_NOCONV, info
-    # MINRES is reserved
-    _, info = _solve(B, inst, beta, B.BIRK_F64, method=1)
+    # MINRES (method 1) runs on double plans without a starting point
+    _, info = _solve(B, inst, beta, B.BIRK_F64, method=1, rtol=1e-12)
+    assert info["status"] == B.BIRK_OK
+    _, info = _solve(B, inst, beta, B.BIRK_F32_REFINE_F64, method=1)
     assert info["status"] == B.BIRK_ERR_UNSUPPORTED
+    _, info = _solve(B, inst, beta, B.BIRK_F64, method=1, use_x0=1)
+    assert info["status"] == B.BIRK_ERR_UNSUPPORTED
+    _, info = _solve(B, inst, beta, B.BIRK_F64, method=2)
+    assert info["status"] == B.BIRK_ERR_ARG
     # plain float plans do not solve
     _, info = _solve(B, inst, beta, B.BIRK_F32)
     assert info["status"] == B.BIRK_ERR_UNSUPPORTED
