@@ -130,10 +130,16 @@ birk_status birk_plan_tune(birk_plan* plan, char* report, int64_t report_len);
  * the second records and replays, later calls replay; at most eight triples are kept
  * (least recently used dropped).  A replay reads the buffers' current contents, so the
  * same pointers may carry new data; buffers must stay allocated while their triple is in
- * use.  enable = 0 (the default) drops every recorded graph.  birk_plan_tune drops them
- * too (they hold the old schedule).  Requires a plan created on a non-null stream.
- * Other entry points are unaffected.  Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED (plan
- * on the legacy null stream). */
+ * use.  In graph mode birk_krylov_solve also records each chunk of Arnoldi steps it runs
+ * (the steps between two host reads of the convergence flags: single steps at first, then
+ * 2 and 4 steps on plans shorter than 2^20 elements) the
+ * first time a (precision, first step, chunk length, restart, Jacobian pointer and kind,
+ * preconditioner) chunk occurs, and replays it afterwards; the Jacobian must stay
+ * allocated while such graphs exist (at most 48, all dropped beyond that).  enable = 0
+ * (the default) drops every recorded graph.  birk_plan_tune drops them too (they hold the
+ * old schedule).  Requires a plan created on a non-null stream.  Other entry points are
+ * unaffected.  Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED (plan on the legacy null
+ * stream). */
 birk_status birk_plan_set_graphs(birk_plan* plan, int32_t enable);
 
 /* Copy the Clenshaw-Curtis weights w_B (the last row of B^a, eq:manyDefs and the

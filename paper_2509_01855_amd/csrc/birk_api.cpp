@@ -60,6 +60,9 @@ static void drop_graphs(birk_plan* p) {
   for (auto& g : p->graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   p->graphs.clear();
+  for (auto& g : p->kgraphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  p->kgraphs.clear();
 }
 
 void free_plan(birk_plan* p) {
@@ -85,6 +88,8 @@ void free_plan(birk_plan* p) {
   if (p->krylov_dots) (void)hipFree(p->krylov_dots);
   if (p->krylov_part) (void)hipFree(p->krylov_part);
   if (p->krylov_coef) (void)hipFree(p->krylov_coef);
+  if (p->krylov_gm) (void)hipFree(p->krylov_gm);
+  if (p->krylov_prm) (void)hipFree(p->krylov_prm);
   if (p->krylov_stage) (void)hipHostFree(p->krylov_stage);
   if (p->flag) (void)hipFree(p->flag);
   delete p;
@@ -575,8 +580,14 @@ hipError_t ensure_krylov(birk_plan* p, int m, size_t esize) {
     if (e == hipSuccess) p->krylov_cnt = (int*)(p->krylov_coef + B * kDotsStride);
   }
   if (e == hipSuccess && !p->krylov_stage) e = hipHostMalloc(&p->krylov_stage, stage_bytes(B), hipHostMallocDefault);
+  if (e == hipSuccess && !p->krylov_gm) e = hipMalloc(&p->krylov_gm, B * kGmStride * sizeof(double));
+  if (e == hipSuccess && !p->krylov_prm) e = hipMalloc(&p->krylov_prm, 6 * B * sizeof(double));
   if (e != hipSuccess) return e;
   if (p->krylov_Q && p->krylov_m >= m) return hipSuccess;
+  // recorded Arnoldi chunks hold the old buffers' addresses
+  for (auto& g : p->kgraphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  p->kgraphs.clear();
   if (p->krylov_Q) (void)hipFree(p->krylov_Q);
   if (p->krylov_vec) (void)hipFree(p->krylov_vec);
   p->krylov_Q = p->krylov_vec = nullptr;
@@ -609,9 +620,85 @@ hipError_t seg_norms(birk_plan* p, const double* v, std::vector<double>& out) {
   return e;
 }
 
+// One Arnoldi step j of every instance (stopped instances are carried along; the device
+// state ignores their columns): z = P^{-1} q_j and y = J z (or y = J q_j without the
+// preconditioner), t = B^a y, u = z - t, CGS2 against q_0..q_j, q_{j+1} = u / ||u||, and
+// the device update of the Hessenberg column, rotations and g.
+template <typename TK>
+static hipError_t arnoldi_step(birk_plan* p, int jk, const double* J, int j, int m, int use_precond, bool keep_jz) {
+  const int64_t n = p->total_len;
+  hipStream_t s = p->stream;
+  TK* Q = (TK*)p->krylov_Q;
+  TK* Z = Q + (size_t)(m + 1) * n;
+  TK* u = (TK*)p->krylov_vec;
+  TK* y = keep_jz ? Z + (size_t)m * n + (size_t)j * n : u + n;
+  TK* t = u + 2 * n;
+  const TK* qj = Q + (size_t)j * n;
+  TK* z = Z + (size_t)j * n;
+  const TK* uz = qj;
+  hipError_t e;
+  if (use_precond) {
+    e = precond_inverse<TK>(p, jk, J, qj, z, y, s, p->flag);
+    uz = z;
+  } else {
+    e = jac_times<TK>(p, jk, J, qj, y, s);
+  }
+  if (e == hipSuccess) e = apply_product<TK>(p, y, t, 0, s);
+  if (e != hipSuccess) return e;
+  double* d1 = p->krylov_dots;
+  double* d2 = d1 + kDotsStride;
+  const int64_t ds = 2 * kDotsStride;
+  kry::sub_sdots<TK>(p, Q, j + 1, uz, t, u, d1, ds, s);
+  kry::saxpys_dots<TK>(p, Q, j + 1, d1, ds, u, d2, ds, s);
+  kry::saxpys<TK>(p, Q, j + 1, d2, ds, u, d2, s);
+  kry::snormalize<TK>(p, u, d2 + kKryMaxDots, ds, Q + (size_t)(j + 1) * n, s);
+  kry::gm_column(p, j, p->krylov_dots, ds, p->krylov_gm, s);
+  return hipGetLastError();
+}
+
+constexpr size_t kMaxKryGraphs = 48;
+
+// Arnoldi steps [j0, j0 + k) on the plan's stream: launched eagerly, or in graph mode
+// from a HIP graph recorded the first time this (precision, steps, Jacobian) chunk runs.
+template <typename TK>
+static hipError_t arnoldi_chunk(birk_plan* p, int jk, const double* J, int j0, int k, int m, int use_precond,
+                                bool keep_jz) {
+  if (!p->use_graphs) {
+    for (int j = j0; j < j0 + k; ++j) {
+      const hipError_t e = arnoldi_step<TK>(p, jk, J, j, m, use_precond, keep_jz);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  const int prec = sizeof(TK) == 8 ? 0 : 1;
+  for (const auto& g : p->kgraphs)
+    if (g.prec == prec && g.j0 == j0 && g.k == k && g.m == m && g.J == J && g.jk == jk &&
+        g.use_precond == use_precond && g.keep_jz == (int)keep_jz)
+      return hipGraphLaunch(g.exec, p->stream);
+  if (p->kgraphs.size() >= kMaxKryGraphs) {
+    for (auto& g : p->kgraphs) (void)hipGraphExecDestroy(g.exec);
+    p->kgraphs.clear();
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  for (int j = j0; j < j0 + k && e == hipSuccess; ++j) e = arnoldi_step<TK>(p, jk, J, j, m, use_precond, keep_jz);
+  const hipError_t e2 = hipStreamEndCapture(p->stream, &graph);
+  if (e == hipSuccess) e = e2;
+  birk_plan::KryGraph kg{prec, j0, k, m, J, jk, use_precond, (int)keep_jz, nullptr};
+  if (e == hipSuccess) e = hipGraphInstantiate(&kg.exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return e;
+  p->kgraphs.push_back(kg);
+  return hipGraphLaunch(kg.exec, p->stream);
+}
+
 // One right-preconditioned GMRES cycle in precision TK on A d = r / ||r||, for every
 // instance not yet done; chi += ||r|| d.  r: the current residual (double).  jchi
-// (double plans, else null): J chi, updated alongside chi from the kept J z_j.
+// (double plans, else null): J chi, updated alongside chi from the kept J z_j.  The
+// Hessenberg columns, rotations and the small least-squares solve run on the device; the
+// host reads the per-instance running flags after each of the first three steps, then
+// (plans shorter than 2^20 elements) after chunks of 2, then 4 steps.
 template <typename TK>
 birk_status gmres_cycle(birk_plan* p, int jk, const double* J, const double* r, double* chi, double* jchi,
                         std::vector<InstState>& st, const std::vector<double>& tol_inner, int m, int use_precond,
@@ -621,151 +708,76 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, const double* r, 
   hipStream_t s = p->stream;
   TK* Q = (TK*)p->krylov_Q;
   TK* Z = Q + (size_t)(m + 1) * n;
-  TK* u = (TK*)p->krylov_vec;
-  TK* y = u + n;
-  TK* t = y + n;
-  const int64_t ld = n;
-  TK* Yb = jchi ? Z + (size_t)m * ld : nullptr;  // J z_j, j < m
+  TK* Yb = jchi ? Z + (size_t)m * n : nullptr;  // J z_j, j < m
   hipError_t e = hipSuccess;
 
   std::vector<char> active(B, 0);
   for (int i = 0; i < B; ++i) active[i] = !st[i].done;
-  // q_0 = r / ||r|| (zero for inactive instances); the pinned staging is rewritten only
-  // after the synchronisations that follow this copy
+  // q_0 = r / ||r|| (zero for inactive instances), and the device state (active,
+  // tolerance, ||r||); the pinned staging is rewritten only after the synchronisations
+  // that follow these copies
   {
     double* sc = stage_coef(p);
-    for (int i = 0; i < B; ++i) sc[i] = active[i] && st[i].rnorm > 0 ? 1.0 / st[i].rnorm : 0.0;
+    double* prm = sc + B;
+    for (int i = 0; i < B; ++i) {
+      sc[i] = active[i] && st[i].rnorm > 0 ? 1.0 / st[i].rnorm : 0.0;
+      prm[3 * i] = active[i] ? 1.0 : 0.0;
+      prm[3 * i + 1] = tol_inner[i];
+      prm[3 * i + 2] = st[i].rnorm;
+    }
     e = hipMemcpyAsync(p->krylov_coef, sc, B * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->krylov_prm, prm, 3 * B * sizeof(double), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return BIRK_ERR_DEVICE;
     kry::sscale_conv<double, TK>(p, r, Q, p->krylov_coef, s);
+    kry::gm_init(p, p->krylov_prm, p->krylov_gm, s);
   }
-  std::vector<std::vector<double>> H(B, std::vector<double>((size_t)(m + 1) * m, 0.0));
-  std::vector<std::vector<double>> cs(B, std::vector<double>(m, 0.0)), sn(B, std::vector<double>(m, 0.0));
-  std::vector<std::vector<double>> gv(B, std::vector<double>(m + 1, 0.0));
-  std::vector<int> jend(B, 0);
-  std::vector<char> running(active);
-  for (int i = 0; i < B; ++i) gv[i][0] = 1.0;
-  const double* hbuf = stage_dots(p);
-  int flag_checked = 0;
-  bool synced = false;  // a synchronisation has passed since the q_0 scales were staged
-
-  for (int j = 0; j < m && budget > 0; ++j) {
-    bool any = false;
-    for (int i = 0; i < B; ++i) any = any || running[i];
-    if (!any) break;
-    const TK* qj = Q + (size_t)j * ld;
-    TK* z = Z + (size_t)j * ld;
-    if (Yb) y = Yb + (size_t)j * ld;
-    // z = P^{-1} q_j, y = J z; t = B^a y; u = z - t (formed with the first dot products)
-    const TK* uz = qj;
-    if (use_precond) {
-      e = precond_inverse<TK>(p, jk, J, qj, z, y, s, p->flag);
-      if (e != hipSuccess) return BIRK_ERR_DEVICE;
-      e = apply_product<TK>(p, y, t, 0, s);
-      if (e != hipSuccess) return BIRK_ERR_DEVICE;
-      uz = z;
-    } else {
-      e = jac_times<TK>(p, jk, J, qj, y, s);
-      if (e != hipSuccess) return BIRK_ERR_DEVICE;
-      e = apply_product<TK>(p, y, t, 0, s);
-      if (e != hipSuccess) return BIRK_ERR_DEVICE;
-    }
-    // CGS2 on every instance at once (segmented launches; stopped instances are
-    // carried along and their results ignored)
-    {
-      double* d1 = p->krylov_dots;
-      double* d2 = d1 + kDotsStride;
-      const int64_t ds = 2 * kDotsStride;
-      kry::sub_sdots<TK>(p, Q, j + 1, uz, t, u, d1, ds, s);
-      kry::saxpys_dots<TK>(p, Q, j + 1, d1, ds, u, d2, ds, s);
-      kry::saxpys<TK>(p, Q, j + 1, d2, ds, u, d2, s);
-      kry::snormalize<TK>(p, u, d2 + kKryMaxDots, ds, Q + (size_t)(j + 1) * ld, s);
-    }
-    e = hipMemcpyAsync(stage_dots(p), p->krylov_dots, (size_t)B * 2 * kDotsStride * sizeof(double),
-                       hipMemcpyDeviceToHost, s);
-    const bool check_flag = use_precond && !flag_checked;
-    if (e == hipSuccess && check_flag) e = hipMemcpyAsync(stage_flag(p), p->flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  double* flags = stage_dots(p);
+  int j = 0, checks = 0;
+  bool flag_checked = !use_precond;
+  // the first three chunks are single steps (most solves here converge within them, and a
+  // step past convergence of a large batch costs more than a host read); small plans,
+  // whose steps are short, then read the flags every 2, then 4 steps
+  const bool small = n < (int64_t(1) << 20);
+  while (j < m && budget > 0) {
+    const int want = (!small || checks < 3) ? 1 : checks < 4 ? 2 : 4;
+    const int k = std::min(want, std::min(m - j, budget));
+    e = arnoldi_chunk<TK>(p, jk, J, j, k, m, use_precond, Yb != nullptr);
+    if (e != hipSuccess) return BIRK_ERR_DEVICE;
+    j += k;
+    budget -= k;
+    ++checks;
+    kry::gm_running(p, p->krylov_gm, p->krylov_prm + 3 * B, s);
+    e = hipMemcpyAsync(flags, p->krylov_prm + 3 * B, B * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && !flag_checked) e = hipMemcpyAsync(stage_flag(p), p->flag, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return BIRK_ERR_DEVICE;
-    synced = true;
-    if (check_flag) {
-      const int f = *stage_flag(p);
-      flag_checked = 1;
-      if (f) {
+    if (!flag_checked) {
+      flag_checked = true;
+      if (*stage_flag(p)) {
         for (int i = 0; i < B; ++i) st[i].status = BIRK_ERR_SINGULAR;
         return BIRK_ERR_SINGULAR;
       }
     }
-    --budget;
-    for (int i = 0; i < B; ++i) {
-      if (!running[i]) continue;
-      st[i].inner += 1;
-      const double* d1 = hbuf + (size_t)i * 2 * kDotsStride;
-      const double* d2 = d1 + kDotsStride;
-      double* Hc = H[i].data() + (size_t)j * (m + 1);  // column j, rows 0..j+1
-      for (int k = 0; k <= j; ++k) Hc[k] = d1[k] + d2[k];
-      const double hn2 = d2[kKryMaxDots];
-      double hn = std::isfinite(hn2) ? std::sqrt(hn2 > 0.0 ? hn2 : 0.0) : std::numeric_limits<double>::quiet_NaN();
-      Hc[j + 1] = hn;
-      bool finite = std::isfinite(hn);
-      for (int k = 0; k <= j; ++k) finite = finite && std::isfinite(Hc[k]);
-      if (!finite) {
-        st[i].status = BIRK_ERR_NONFINITE;
-        running[i] = 0;
-        jend[i] = j;  // discard this column
-        continue;
-      }
-      for (int k = 0; k < j; ++k) {
-        const double a = cs[i][k] * Hc[k] + sn[i][k] * Hc[k + 1];
-        Hc[k + 1] = -sn[i][k] * Hc[k] + cs[i][k] * Hc[k + 1];
-        Hc[k] = a;
-      }
-      const double den = std::hypot(Hc[j], Hc[j + 1]);
-      if (den == 0.0) {
-        st[i].status = BIRK_ERR_BREAKDOWN;
-        running[i] = 0;
-        jend[i] = j;
-        continue;
-      }
-      cs[i][j] = Hc[j] / den;
-      sn[i][j] = Hc[j + 1] / den;
-      Hc[j] = den;
-      Hc[j + 1] = 0.0;
-      gv[i][j + 1] = -sn[i][j] * gv[i][j];
-      gv[i][j] = cs[i][j] * gv[i][j];
-      jend[i] = j + 1;
-      const bool lucky = hn <= 1e-14 * den;
-      if (std::fabs(gv[i][j + 1]) <= tol_inner[i] || lucky) running[i] = 0;
-    }
+    bool any = false;
+    for (int i = 0; i < B; ++i) any = any || flags[i] != 0.0;
+    if (!any) break;
   }
-  // back substitution and chi += ||r|| P^{-1} (Q y)
-  // the staging still holds the q_0 scales until a synchronisation has passed
-  if (!synced && hipStreamSynchronize(s) != hipSuccess) return BIRK_ERR_DEVICE;
-  double* coef = stage_coef(p);
-  std::fill(coef, coef + (size_t)B * kDotsStride, 0.0);
-  for (int i = 0; i < B; ++i) {
-    if (!active[i]) continue;
-    const int k = jend[i];
-    std::vector<double> yv(k, 0.0);
-    for (int a = k - 1; a >= 0; --a) {
-      double sacc = gv[i][a];
-      for (int b = a + 1; b < k; ++b) sacc -= H[i][(size_t)b * (m + 1) + a] * yv[b];
-      yv[a] = sacc / H[i][(size_t)a * (m + 1) + a];
-    }
-    for (int a = 0; a < k; ++a) coef[(size_t)i * kDotsStride + a] = yv[a] * st[i].rnorm;
-  }
-  int* cnt = stage_cnt(p);
-  for (int i = 0; i < B; ++i) cnt[i] = active[i] ? jend[i] : 0;
-  e = hipMemcpyAsync(p->krylov_coef, coef, (size_t)B * kDotsStride * sizeof(double) + B * sizeof(int),
-                     hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return BIRK_ERR_DEVICE;
-  // chi += ||r|| P^{-1} Q y = ||r|| Z y (Z = Q without preconditioning)
+  // y = R^{-1} g and chi += ||r|| Z y (Z = Q without preconditioning) on the device
+  kry::gm_solve(p, p->krylov_gm, p->krylov_coef, kDotsStride, p->krylov_cnt, p->krylov_prm + 3 * B, s);
   const TK* basis = use_precond ? Z : Q;
   kry::scombine<TK>(p, basis, p->krylov_coef, kDotsStride, p->krylov_cnt, chi, s);
   // J chi += ||r|| J Z y (J Q y without preconditioning) from the kept J z_j
   if (Yb) kry::scombine<TK>(p, Yb, p->krylov_coef, kDotsStride, p->krylov_cnt, jchi, s);
-  e = hipStreamSynchronize(s);
-  return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
+  e = hipMemcpyAsync(flags, p->krylov_prm + 3 * B, 3 * B * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return BIRK_ERR_DEVICE;
+  for (int i = 0; i < B; ++i) {
+    if (!active[i]) continue;
+    st[i].inner += (int)flags[3 * i + 1];
+    const int stat = (int)flags[3 * i + 2];
+    if (stat != 0) st[i].status = stat;
+  }
+  return BIRK_OK;
 }
 
 }  // namespace

@@ -231,6 +231,8 @@ struct birk_plan {
   double* krylov_coef = nullptr;  // per instance: scale factors / combination coefficients,
                                   // followed by the counts krylov_cnt (one upload for both)
   int* krylov_cnt = nullptr;      // per instance: number of combined basis vectors
+  double* krylov_gm = nullptr;    // device-side GMRES state, kGmStride doubles per instance
+  double* krylov_prm = nullptr;   // per instance (active, tolerance, ||r||), then 3 flags
   void* krylov_stage = nullptr;   // pinned host staging: dots, singular flag, coefficients + counts
   int* flag = nullptr;            // device flag: singular pivot seen
   birk::CompDesc* comps = nullptr;  // component table (device), one entry per component
@@ -260,6 +262,15 @@ struct birk_plan {
   };
   int use_graphs = 0;
   std::vector<GraphSlot> graphs;
+  // HIP graphs of GMRES chunks (graph mode): Arnoldi steps [j0, j0 + k) for one precision,
+  // restart length, Jacobian pointer and kind, preconditioner setting and J z storage
+  struct KryGraph {
+    int prec, j0, k, m;
+    const double* J;
+    int jk, use_precond, keep_jz;
+    hipGraphExec_t exec;
+  };
+  std::vector<KryGraph> kgraphs;
   uint64_t graph_clock = 0;
   // extra streams and their fork / join events of the multi-stream three-pass schedule
   static constexpr int kExtraStreams = 2;
@@ -333,6 +344,16 @@ hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int sing
 
 // Krylov BLAS-1 launchers (birk_solve.hip).  Reductions accumulate in double.
 constexpr int kKryMaxDots = 32;
+// Device-side GMRES state per instance (doubles): rotated Hessenberg columns R
+// (column-major, kGmLd rows per column), g, cos, sin, then the scalars of GM_*.
+constexpr int kGmLd = kKryMaxDots + 1;
+constexpr int kGmR = 0;
+constexpr int kGmG = kGmLd * kKryMaxDots;
+constexpr int kGmCs = kGmG + kGmLd;
+constexpr int kGmSn = kGmCs + kKryMaxDots;
+constexpr int kGmMisc = kGmSn + kKryMaxDots;
+enum { GM_RUN, GM_ACTIVE, GM_JEND, GM_INNER, GM_STATUS, GM_TOL, GM_RNORM, kGmMiscLen };
+constexpr int kGmStride = kGmMisc + kGmMiscLen + 1;
 namespace kry {
 template <typename T>
 void sub(const T* a, const T* b, T* z, int64_t n, hipStream_t s);
@@ -361,6 +382,11 @@ void sscale_conv(const birk_plan* p, const TI* x, TO* y, const double* alpha, hi
 template <typename T>
 void scombine(const birk_plan* p, const T* Q, const double* c, int64_t cstride, const int* cnt, double* x,
               hipStream_t s);
+// device-side GMRES scalars: prm = (active, tolerance, ||r||) per instance
+void gm_init(const birk_plan* p, const double* prm, double* st, hipStream_t s);
+void gm_column(const birk_plan* p, int j, const double* dots, int64_t dstride, double* st, hipStream_t s);
+void gm_solve(const birk_plan* p, double* st, double* coef, int64_t cstride, int* cnt, double* flags, hipStream_t s);
+void gm_running(const birk_plan* p, const double* st, double* flags, hipStream_t s);
 }  // namespace kry
 
 // ---- the KKT form and MINRES (birk_kkt.hip) ----

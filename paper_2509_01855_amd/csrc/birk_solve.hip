@@ -1621,6 +1621,111 @@ __global__ __launch_bounds__(256) void k_scombine(const T* __restrict__ Q, int64
   }
 }
 
+// ---- GMRES scalars on the device: per instance the rotated Hessenberg columns R, the
+// right-hand side g of the small least-squares problem, the Givens rotations, and
+// (running, columns kept, iterations, status, tolerance, ||r||); one thread per instance.
+__global__ void k_gm_init(const double* __restrict__ prm, double* __restrict__ st, int ninst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  double* s = st + (int64_t)i * kGmStride;
+  for (int k = 0; k < kGmLd; ++k) s[kGmG + k] = 0.0;
+  s[kGmG] = 1.0;
+  s[kGmMisc + GM_RUN] = prm[3 * i];
+  s[kGmMisc + GM_ACTIVE] = prm[3 * i];
+  s[kGmMisc + GM_JEND] = 0.0;
+  s[kGmMisc + GM_INNER] = 0.0;
+  s[kGmMisc + GM_STATUS] = 0.0;
+  s[kGmMisc + GM_TOL] = prm[3 * i + 1];
+  s[kGmMisc + GM_RNORM] = prm[3 * i + 2];
+}
+
+// Arnoldi column j of every running instance from the CGS2 dot products (d1 + d2 = the
+// coefficients, the norm slot of d2 = ||u||^2): earlier rotations, a new rotation that
+// annihilates h_{j+1,j}, the update of g; the instance stops when |g_{j+1}| <= tol, on a
+// lucky breakdown, on breakdown (no column kept) or on a non-finite value.
+__global__ void k_gm_column(int j, const double* __restrict__ dots, int64_t dstride, double* __restrict__ st,
+                            int ninst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  double* s = st + (int64_t)i * kGmStride;
+  double* misc = s + kGmMisc;
+  if (misc[GM_RUN] == 0.0) return;
+  misc[GM_INNER] += 1.0;
+  const double* d1 = dots + (int64_t)i * dstride;
+  const double* d2 = d1 + kGmLd;
+  double* col = s + kGmR + (int64_t)j * kGmLd;
+  double* cs = s + kGmCs;
+  double* sn = s + kGmSn;
+  double* g = s + kGmG;
+  const double hn2 = d2[kMaxDots];
+  const double hn = isfinite(hn2) ? sqrt(hn2 > 0.0 ? hn2 : 0.0) : NAN;
+  bool finite = isfinite(hn);
+  for (int k = 0; k <= j; ++k) {
+    col[k] = d1[k] + d2[k];
+    finite = finite && isfinite(col[k]);
+  }
+  if (!finite) {
+    misc[GM_STATUS] = (double)BIRK_ERR_NONFINITE;
+    misc[GM_RUN] = 0.0;
+    misc[GM_JEND] = (double)j;
+    return;
+  }
+  double below = hn;
+  for (int k = 0; k < j; ++k) {
+    const double a = cs[k] * col[k] + sn[k] * col[k + 1];
+    col[k + 1] = -sn[k] * col[k] + cs[k] * col[k + 1];
+    col[k] = a;
+  }
+  const double den = hypot(col[j], below);
+  if (den == 0.0) {
+    misc[GM_STATUS] = (double)BIRK_ERR_BREAKDOWN;
+    misc[GM_RUN] = 0.0;
+    misc[GM_JEND] = (double)j;
+    return;
+  }
+  cs[j] = col[j] / den;
+  sn[j] = below / den;
+  col[j] = den;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  misc[GM_JEND] = (double)(j + 1);
+  const bool lucky = hn <= 1e-14 * den;
+  if (fabs(g[j + 1]) <= misc[GM_TOL] || lucky) misc[GM_RUN] = 0.0;
+}
+
+// End of a cycle: y = R^{-1} g on the kept columns, coefficients ||r|| y and their count
+// for the combination chi += sum_k c_k z_k; (running, iterations, status) per instance
+// into flags[3 i ...] for the host.
+__global__ void k_gm_solve(double* __restrict__ st, double* __restrict__ coef, int64_t cstride, int* __restrict__ cnt,
+                           double* __restrict__ flags, int ninst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  double* s = st + (int64_t)i * kGmStride;
+  const double* misc = s + kGmMisc;
+  double* c = coef + (int64_t)i * cstride;
+  const int k = misc[GM_ACTIVE] != 0.0 ? (int)misc[GM_JEND] : 0;
+  const double* R = s + kGmR;
+  const double* g = s + kGmG;
+  double y[kMaxDots];
+  for (int a = k - 1; a >= 0; --a) {
+    double acc = g[a];
+    for (int b = a + 1; b < k; ++b) acc -= R[(int64_t)b * kGmLd + a] * y[b];
+    y[a] = acc / R[(int64_t)a * kGmLd + a];
+  }
+  for (int a = 0; a < k; ++a) c[a] = y[a] * misc[GM_RNORM];
+  cnt[i] = k;
+  flags[3 * i] = misc[GM_RUN];
+  flags[3 * i + 1] = misc[GM_INNER];
+  flags[3 * i + 2] = misc[GM_STATUS];
+}
+
+// running flag per instance into flags[i] (read by the host between chunks)
+__global__ void k_gm_running(const double* __restrict__ st, double* __restrict__ flags, int ninst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ninst) return;
+  flags[i] = st[(int64_t)i * kGmStride + kGmMisc + GM_RUN];
+}
+
 // Host-side launch helpers used by the GMRES driver.
 namespace kry {
 
@@ -1689,6 +1794,23 @@ void scombine(const birk_plan* p, const T* Q, const double* c, int64_t cstride, 
               hipStream_t s) {
   hipLaunchKernelGGL(k_scombine<T>, dim3(p->seg.ntiles), dim3(256), 0, s, Q, p->total_len, c, cstride, cnt, x,
                      p->seg);
+}
+
+void gm_init(const birk_plan* p, const double* prm, double* st, hipStream_t s) {
+  const int B = (int)p->inst.size();
+  hipLaunchKernelGGL(k_gm_init, dim3(nblocks(B, 64)), dim3(64), 0, s, prm, st, B);
+}
+void gm_column(const birk_plan* p, int j, const double* dots, int64_t dstride, double* st, hipStream_t s) {
+  const int B = (int)p->inst.size();
+  hipLaunchKernelGGL(k_gm_column, dim3(nblocks(B, 64)), dim3(64), 0, s, j, dots, dstride, st, B);
+}
+void gm_solve(const birk_plan* p, double* st, double* coef, int64_t cstride, int* cnt, double* flags, hipStream_t s) {
+  const int B = (int)p->inst.size();
+  hipLaunchKernelGGL(k_gm_solve, dim3(nblocks(B, 64)), dim3(64), 0, s, st, coef, cstride, cnt, flags, B);
+}
+void gm_running(const birk_plan* p, const double* st, double* flags, hipStream_t s) {
+  const int B = (int)p->inst.size();
+  hipLaunchKernelGGL(k_gm_running, dim3(nblocks(B, 64)), dim3(64), 0, s, st, flags, B);
 }
 
 template void sdots<double>(const birk_plan*, const double*, int, const double*, double*, int64_t, hipStream_t);

@@ -114,3 +114,37 @@ def test_graph_replays_two_stream_schedule(B, monkeypatch):
             assert torch.equal(out, ref), f"call {call}"
     eager.destroy()
     graph.destroy()
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_graph_mode_solves_match_eager(B, prec):
+    """Graph mode also records the chunks of Arnoldi steps of birk_krylov_solve; repeated
+    solves (recording, then replays, with other solves, new right-hand sides and a second
+    Jacobian between them) equal the eager plan's solves bit for bit."""
+    import torch
+    from oracle import system as sy
+    insts = [wl.lti_instance(k, Nn) for k, Nn in enumerate((257, 1000, 4097))]
+    announce(f"graph-mode solves prec={prec}")
+    p = B.BIRK_F64 if prec == "f64" else B.BIRK_F32_REFINE_F64
+    side = torch.cuda.Stream()
+    Nn, nx = [i.N_n for i in insts], [i.n_x for i in insts]
+    eager = B.birk_plan_create(Nn, nx, p, side)
+    graph = B.birk_plan_create(Nn, nx, p, side)
+    B.birk_plan_set_graphs(graph)
+    with torch.cuda.stream(side):
+        Js = [torch.from_numpy(np.concatenate([(i.J * s).ravel() for i in insts])).to("cuda")
+              for s in (1.0, 0.5)]
+        for call in range(5):
+            J = Js[call % 2 if call > 2 else 0]
+            xa = [np.random.default_rng([41, call, k]).standard_normal(i.n_x) for k, i in enumerate(insts)]
+            beta = torch.from_numpy(np.concatenate([sy.beta_vector(a, i.N_n) for a, i in zip(xa, insts)])).to("cuda")
+            x1 = torch.zeros_like(beta)
+            x2 = torch.zeros_like(beta)
+            i1 = B.birk_krylov_solve(graph, J, beta, x1, B.BIRK_J_CONSTANT, rtol=1e-12)
+            i2 = B.birk_krylov_solve(eager, J, beta, x2, B.BIRK_J_CONSTANT, rtol=1e-12)
+            side.synchronize()
+            assert i1["inner_iters"] == i2["inner_iters"] and i1["status"] == 0
+            assert np.array_equal(host(x1), host(x2)), f"call {call}"
+    side.synchronize()
+    eager.destroy()
+    graph.destroy()
