@@ -520,7 +520,8 @@ def main():
         print("[bench] autotuning the power-of-two plans", file=sys.stderr, flush=True)
         tplans = {"headline_f64": plan64, "headline_f32": planmx}
         if extra:
-            tplans.update({"c1_f64": c1["plan"], "many_rhs_f64": mplans[B.BIRK_F64],
+            tplans.update({"c1_f64": c1["plan"], "batched_f64": bplan64, "batched_f32": bplanmx,
+                           "many_rhs_f64": mplans[B.BIRK_F64],
                            "many_rhs_f32": mplans[B.BIRK_F32], "many_rhs_df32": mplans[B.BIRK_DF32]})
         for name, plan in tplans.items():
             rep = B.birk_plan_tune(plan)

@@ -105,7 +105,7 @@ birk_status birk_plan_destroy(birk_plan* plan);
 /* Total vector length sum_i n_x[i] * N_n[i] of the plan (elements, not bytes). */
 int64_t birk_plan_length(const birk_plan* plan);
 
-/* Autotuner of the power-of-two product path (N = 2^p >= 512).  For each group of
+/* Autotuner of the product schedules.  Power-of-two path (N = 2^p >= 512): for each group of
  * same-length components it times B^a (FastBV box) in the plan's precision over a
  * fixed set of tile schedules: both splits 2N = L1 L2 of the two-step DCTs, two or four
  * rows per middle-pass tile, the plain or XCD-grouped tile order, four- or eight-column
@@ -118,7 +118,13 @@ int64_t birk_plan_length(const birk_plan* plan);
  * default schedule stays unless a candidate is more than 2 % faster; the choice stays
  * with the plan for every later product.  The schedule changes only the
  * order of floating-point operations (results stay within the product tolerance).
- * Inputs are the plan's own scratch vectors; no allocation.  Blocks until done.
+ * Then the general path (N not a power of two: DCT-I by Bluestein's chirp convolution): for each
+ * chirp-convolution length M = 2^m above 4096 in the plan, the two-step FFTs M = M1 M2 are
+ * timed (whole products, same rounds) with every split 2^7 <= M1 <= 2^12, 2^6 <= M2 <= 2^12,
+ * one length at a time, and the fastest kept (default M1 = 2^ceil(m/2), again kept unless
+ * beaten by 2 %); the filter spectra of that length are moved into the new order and the
+ * tile lists rebuilt (re-allocated: the only allocations of the call).
+ * Inputs are the plan's own scratch vectors.  Blocks until done.
  * report: optional host buffer (NULL, or report_len > 0) that receives a NUL-terminated
  * summary of every timing and choice, truncated to report_len - 1 characters.
  * Errors: BIRK_ERR_ARG (NULL plan), BIRK_ERR_DEVICE. */

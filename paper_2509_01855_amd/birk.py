@@ -267,7 +267,8 @@ def birk_plan_length(plan: Plan) -> int:
 
 
 def birk_plan_tune(plan: Plan) -> str:
-    """Run the autotuner of the power-of-two product path; returns its report."""
+    """Run the autotuner of the product schedules (power-of-two groups, then the
+    Bluestein two-step splits); returns its report."""
     buf = ctypes.create_string_buffer(16384)
     _check(_lib.birk_plan_tune(plan.handle, buf, len(buf)), "birk_plan_tune")
     return buf.value.decode()

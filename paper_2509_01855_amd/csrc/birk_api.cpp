@@ -185,7 +185,8 @@ birk_status birk_plan_tune(birk_plan* p, char* report, int64_t report_len) {
   std::string text;
   DeviceGuard g(p->device);
   drop_graphs(p);  // recorded with the previous schedule
-  const hipError_t e = tune_fast(p, p->stream, &text);
+  hipError_t e = tune_fast(p, p->stream, &text);
+  if (e == hipSuccess && !p->gen[1].host.empty()) e = tune_general(p, p->stream, &text);
   if (report) {
     const size_t n = std::min<size_t>(text.size(), (size_t)report_len - 1);
     std::memcpy(report, text.data(), n);

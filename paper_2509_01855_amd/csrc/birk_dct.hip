@@ -899,13 +899,25 @@ __global__ void k_scale_to(const cplx<double>* __restrict__ src, cplx<T>* __rest
   dst[m] = mk<T>((T)(src[from].x * s), (T)(src[from].y * s));
 }
 
+// Filter spectrum moved from the rows-pass order of the split (a1, a2) of M to that of
+// (b1, b2): dst[k1 M2' + k2] = src at the position of frequency k1 + M1' k2 in the old order.
+template <typename T>
+__global__ void k_relayout(const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst, int64_t M, int a1, int a2,
+                           int b1, int b2) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const int64_t q = (m >> b2) + ((m & ((int64_t(1) << b2) - 1)) << b1);     // frequency
+  const int64_t from = ((q & ((int64_t(1) << a1) - 1)) << a2) + (q >> a1);  // its old position
+  dst[m] = src[from];
+}
+
 static int ilog2_ceil(int64_t x) {
   int l = 0;
   while ((int64_t(1) << l) < x) ++l;
   return l;
 }
 
-static PairDesc make_pair(int64_t src, int64_t Nn, int has2) {
+static PairDesc make_pair(int64_t src, int64_t Nn, int has2, const int* split) {
   PairDesc d;
   d.src = src;
   d.Nn = Nn;
@@ -915,7 +927,7 @@ static PairDesc make_pair(int64_t src, int64_t Nn, int has2) {
   d.M = pow2 ? d.L : (int64_t(1) << ilog2_ceil(d.N + d.L));
   d.logM = ilog2_ceil(d.M);
   if (d.logM > kLdsMaxLog) {
-    d.logM1 = (d.logM + 1) / 2;
+    d.logM1 = (split && split[d.logM] > 0) ? split[d.logM] : (d.logM + 1) / 2;
     d.logM2 = d.logM - d.logM1;
   }
   d.tw_shift = (d.logM + 1) / 2;
@@ -969,7 +981,7 @@ void plan_products(birk_plan* p) {
     }
     const int np = (in.nx + 1) / 2;
     for (int q = 0; q < np; ++q) {
-      PairDesc d = make_pair(in.off + 2 * (int64_t)q * in.Nn, in.Nn, 2 * q + 1 < in.nx);
+      PairDesc d = make_pair(in.off + 2 * (int64_t)q * in.Nn, in.Nn, 2 * q + 1 < in.nx, p->blu_split);
       p->gen[(d.L == d.M) ? 0 : 1].host.push_back(d);
     }
     ++i;
@@ -1027,6 +1039,145 @@ static hipError_t finalize_set(birk_plan* p, PairSet& ps) {
   up(tc, &ps.tiles_c4);
   up(tr, &ps.tiles_r4);
   return e;
+}
+
+// ----------------------------------------------------------------- general-path tuner
+// Bluestein pairs with M above the LDS limit run their two-step FFTs with M = M1 M2; the
+// default M1 = 2^ceil(log2(M) / 2).  For each such size (2^logM) the tuner times the plan's
+// product with every split the compile-time kernels support (7 <= log2 M1 <= 12,
+// 6 <= log2 M2 <= 12), one size at a time with the others fixed, and keeps the fastest
+// (the current choice stays unless another is more than 2 % faster).  A change of split
+// moves the filter spectra of that size into the new rows-pass order and rebuilds the
+// four-step tile lists; the products change only in rounding order.
+
+// Split (log2 M1) of every pair of size 2^logM in the Bluestein set: descriptors,
+// filter tables (each distinct filter once) and the cols / rows tile lists.
+static hipError_t set_blu_split(birk_plan* p, int logM, int logM1, hipStream_t s) {
+  PairSet& ps = p->gen[1];
+  hipError_t e = hipSuccess;
+  std::vector<const void*> moved;
+  cplx<double>* tmp = (cplx<double>*)p->work[0];
+  for (PairDesc& d : ps.host) {
+    if (d.logM != logM || d.logM1 == logM1) continue;
+    const int a1 = d.logM1, a2 = d.logM2, b1 = logM1, b2 = logM - logM1;
+    if (std::find(moved.begin(), moved.end(), d.filt[0]) == moved.end()) {
+      moved.push_back(d.filt[0]);
+      const dim3 grid((unsigned)((d.M + 255) / 256));
+      // through work[0] (free between products), one precision at a time
+      hipLaunchKernelGGL(k_relayout<double>, grid, dim3(256), 0, s, (const cplx<double>*)d.filt[0], tmp, d.M, a1, a2,
+                         b1, b2);
+      e = hipMemcpyAsync((void*)d.filt[0], tmp, d.M * sizeof(cplx<double>), hipMemcpyDeviceToDevice, s);
+      hipLaunchKernelGGL(k_relayout<float>, grid, dim3(256), 0, s, (const cplx<float>*)d.filt[1], (cplx<float>*)tmp,
+                         d.M, a1, a2, b1, b2);
+      if (e == hipSuccess) e = hipMemcpyAsync((void*)d.filt[1], tmp, d.M * sizeof(cplx<float>), hipMemcpyDeviceToDevice, s);
+      hipLaunchKernelGGL(k_relayout<df32>, grid, dim3(256), 0, s, (const cplx<df32>*)d.filt[2], (cplx<df32>*)tmp,
+                         d.M, a1, a2, b1, b2);
+      if (e == hipSuccess) e = hipMemcpyAsync((void*)d.filt[2], tmp, d.M * sizeof(cplx<df32>), hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return e;
+    }
+    d.logM1 = b1;
+    d.logM2 = b2;
+  }
+  p->blu_split[logM] = logM1;
+  // descriptors in place; cols / rows tile lists rebuilt (their lengths depend on the split)
+  e = hipMemcpyAsync(ps.dev, ps.host.data(), ps.host.size() * sizeof(PairDesc), hipMemcpyHostToDevice, s);
+  std::vector<int2> tc, tr;
+  for (int q = 0; q < (int)ps.host.size(); ++q) {
+    const PairDesc& d = ps.host[q];
+    if (d.logM <= kLdsMaxLog) continue;
+    const int logW1 = std::min(kLdsMaxLog - d.logM1, d.logM2);
+    const int logW2 = std::min(kLdsMaxLog - d.logM2, d.logM1);
+    for (int b = 0; b < (1 << (d.logM2 - logW1)); ++b) tc.push_back(make_int2(q, b));
+    for (int b = 0; b < (1 << (d.logM1 - logW2)); ++b) tr.push_back(make_int2(q, b));
+  }
+  auto replace = [&](const std::vector<int2>& v, int2** dst, int* cnt) {
+    if (e != hipSuccess) return;
+    if (*dst) {
+      e = hipStreamSynchronize(s);
+      auto it = std::find(p->allocs.begin(), p->allocs.end(), (void*)*dst);
+      if (it != p->allocs.end()) p->allocs.erase(it);
+      if (e == hipSuccess) e = hipFree(*dst);
+    }
+    void* x = nullptr;
+    if (e == hipSuccess) e = upload_raw(p, v.data(), v.size() * sizeof(int2), &x);
+    *dst = (int2*)x;
+    *cnt = (int)v.size();
+  };
+  replace(tc, &ps.tiles_c4, &ps.n_c4);
+  replace(tr, &ps.tiles_r4, &ps.n_r4);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
+}
+
+template <typename T>
+static hipError_t tune_general_t(birk_plan* p, hipStream_t s, std::string* report) {
+  std::vector<int> sizes;
+  for (const PairDesc& d : p->gen[1].host)
+    if (d.logM > kLdsMaxLog && std::find(sizes.begin(), sizes.end(), d.logM) == sizes.end()) sizes.push_back(d.logM);
+  if (sizes.empty()) {
+    *report += "general path: no Bluestein sizes above the LDS limit\n";
+    return hipSuccess;
+  }
+  T* in[2] = {(T*)p->tmp_vec[0], (T*)p->tmp_vec[2]};
+  T* out[2] = {(T*)p->tmp_vec[1], (T*)p->tmp_vec[3]};
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMemsetAsync(in[b], 0, (size_t)p->total_len * sizeof(T), s);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  auto time_product = [&](float* ms) -> hipError_t {
+    hipError_t r = apply_product<T>(p, in[0], out[0], 0, s);
+    float best = 0.0f;
+    for (int round = 0; round < 2 && r == hipSuccess; ++round) {
+      r = hipEventRecord(e0, s);
+      for (int k = 0; k < 3 && r == hipSuccess; ++k) r = apply_product<T>(p, in[k & 1], out[k & 1], 0, s);
+      if (r == hipSuccess) r = hipEventRecord(e1, s);
+      if (r == hipSuccess) r = hipEventSynchronize(e1);
+      float t = 0.0f;
+      if (r == hipSuccess) r = hipEventElapsedTime(&t, e0, e1);
+      if (round == 0 || t < best) best = t;
+    }
+    *ms = best / 3.0f;
+    return r;
+  };
+  std::sort(sizes.begin(), sizes.end());
+  char line[160];
+  for (int logM : sizes) {
+    if (e != hipSuccess) break;
+    int cur = 0;
+    for (const PairDesc& d : p->gen[1].host)
+      if (d.logM == logM) cur = d.logM1;
+    float best_ms = 0.0f;
+    if ((e = time_product(&best_ms)) != hipSuccess) break;
+    snprintf(line, sizeof line, "general path M=2^%d: [M1 2^%d] %.1f us;", logM, cur, 1000.0 * best_ms);
+    *report += line;
+    int best = cur;
+    const int lo = std::max(7, logM - kLdsMaxLog), hi = std::min(kLdsMaxLog, logM - 6);
+    for (int l1 = lo; l1 <= hi && e == hipSuccess; ++l1) {
+      if (l1 == cur) continue;
+      if ((e = set_blu_split(p, logM, l1, s)) != hipSuccess) break;
+      float ms = 0.0f;
+      if ((e = time_product(&ms)) != hipSuccess) break;
+      snprintf(line, sizeof line, " [M1 2^%d] %.1f us;", l1, 1000.0 * ms);
+      *report += line;
+      if (ms < best_ms * (1.0f - 0.02f)) {
+        best_ms = ms;
+        best = l1;
+      }
+    }
+    if (e == hipSuccess) e = set_blu_split(p, logM, best, s);
+    snprintf(line, sizeof line, " chosen [M1 2^%d]\n", best);
+    *report += line;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return e;
+}
+
+hipError_t tune_general(birk_plan* p, hipStream_t s, std::string* report) {
+  if (p->prec == BIRK_F64) return tune_general_t<double>(p, s, report);
+  if (p->prec == BIRK_DF32) return tune_general_t<df32>(p, s, report);
+  return tune_general_t<float>(p, s, report);
 }
 
 hipError_t build_tables(birk_plan* p) {

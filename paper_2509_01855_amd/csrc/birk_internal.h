@@ -251,6 +251,7 @@ struct birk_plan {
   double* comp_val = nullptr;       // one double per component (last node, or a total)
   double* comp_part = nullptr;      // per-component reduction partials (CompDesc::part)
   int use_fast = 1;               // power-of-two N takes the three-pass path
+  int blu_split[40] = {};         // log2 M1 of the Bluestein two-step FFTs per log2 M (0: default)
   birk::FastKnobs fast_kn;        // default tile schedule of the three-pass groups
   // HIP graphs of the products (birk_plan_set_graphs), per (direction, input, output)
   struct GraphSlot {
@@ -298,6 +299,8 @@ hipError_t fast_product(birk_plan* p, const FastGroup& g, const T* v, T* out, in
 void fast_sizes(const birk_plan* p, int64_t N, int nc, int64_t* work, int64_t* part);
 // Autotuner of the three-pass groups (birk_plan_tune); appends a summary to *report.
 hipError_t tune_fast(birk_plan* p, hipStream_t s, std::string* report);
+// Autotuner of the general path: the two-step split of each Bluestein size (birk_dct.hip).
+hipError_t tune_general(birk_plan* p, hipStream_t s, std::string* report);
 
 // ---- b-form corrections and the endpoint row (birk_bform.hip) ----
 // Build the component table and its partial-sum scratch (after the weights exist).

@@ -331,3 +331,49 @@ def test_timed_configuration_schedules(B, head_refs, sched, monkeypatch):
     assert rel_err(run(r["Xs"], 0), r["ref_s"]) <= TOL["f64"]
     assert rel_err(run(r["Gs"], 1), r["ref_sT"]) <= TOL["f64"]
     plan.destroy()
+
+
+def test_autotuned_general_path_keeps_results(B):
+    """birk_plan_tune on a batch of non-power-of-two sizes times every two-step split of each
+    Bluestein length 2^13..2^18 and moves the filter spectra into the chosen order; the
+    products afterwards match the exact sparse-mode series (B^a), node-sparse rows (B^aT)
+    and the untuned plan."""
+    import torch
+    Nns = [2000, 5000, 9000, 12000, 30000, 60001]
+    nx = 1
+    announce(f"general-path autotune N_n {Nns}")
+    X, refs, G, refsT = [], [], [], []
+    rng = np.random.default_rng(404)
+    for k, Nn in enumerate(Nns):
+        N = Nn - 1
+        modes, alphas = wl.sparse_modes([41, k, Nn], N, count=32)
+        X.append(bk.sparse_mode_values(N, modes, alphas))
+        refs.append(bk.sparse_mode_exact(N, modes, alphas))
+        nodes = np.unique(np.concatenate([[0, N], rng.integers(0, Nn, 4)]))
+        g = np.zeros(Nn)
+        g[nodes] = rng.standard_normal(len(nodes))
+        G.append(g)
+        refsT.append(sum(g[i] * bk.ba_row(N, int(i)) for i in nodes))
+    plan = B.birk_plan_create(Nns, [nx] * len(Nns), B.BIRK_F64)
+
+    def run(vec, transpose):
+        v = dev(np.concatenate(vec), torch.float64)
+        out = torch.empty_like(v)
+        (B.birk_apply_T if transpose else B.birk_apply)(plan, v, out)
+        torch.cuda.synchronize()
+        return host(out)
+
+    before = [run(X, 0), run(G, 1)]
+    report = B.birk_plan_tune(plan)
+    print(report, flush=True)
+    lines = [ln for ln in report.splitlines() if ln.startswith("general path M=2^")]
+    assert len(lines) == 6 and all(" chosen [M1 2^" in ln for ln in lines), report
+    after = [run(X, 0), run(G, 1)]
+    plan.destroy()
+    o = 0
+    for k, Nn in enumerate(Nns):
+        assert rel_err(after[0][o:o + Nn], refs[k]) <= TOL["f64"]
+        assert rel_err(after[1][o:o + Nn], refsT[k]) <= TOL["f64"]
+        o += Nn
+    for t in (0, 1):
+        assert rel_err(after[t], before[t]) <= 1e-13
