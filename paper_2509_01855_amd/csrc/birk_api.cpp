@@ -512,14 +512,14 @@ birk_status birk_precond(birk_plan* p, birk_jac_kind jk, const double* J, const 
     return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
   }
   if (inverse) {
-    e = precond_prepare(p, jk, J, p->prec == BIRK_F64 ? 0 : 1, p->stream);
+    e = precond_prepare(p, jk, J, p->prec == BIRK_F64 ? 0 : 1, p->stream, 0);
     if (e != hipSuccess) return BIRK_ERR_DEVICE;
   }
   if (p->prec == BIRK_F64) {
-    e = inverse ? precond_inverse<double>(p, jk, J, (const double*)y, (double*)out, nullptr, p->stream, nullptr)
+    e = inverse ? precond_inverse<double>(p, jk, J, (const double*)y, (double*)out, nullptr, p->stream, nullptr, 0)
                 : precond_forward<double>(p, jk, J, (const double*)y, (double*)out, p->stream);
   } else {
-    e = inverse ? precond_inverse<float>(p, jk, J, (const float*)y, (float*)out, nullptr, p->stream, nullptr)
+    e = inverse ? precond_inverse<float>(p, jk, J, (const float*)y, (float*)out, nullptr, p->stream, nullptr, 0)
                 : precond_forward<float>(p, jk, J, (const float*)y, (float*)out, p->stream);
   }
   return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
@@ -639,7 +639,7 @@ static hipError_t arnoldi_step(birk_plan* p, int jk, const double* J, int j, int
   const TK* uz = qj;
   hipError_t e;
   if (use_precond) {
-    e = precond_inverse<TK>(p, jk, J, qj, z, y, s, p->flag);
+    e = precond_inverse<TK>(p, jk, J, qj, z, y, s, p->flag, 1);
     uz = z;
   } else {
     e = jac_times<TK>(p, jk, J, qj, y, s);
@@ -815,7 +815,7 @@ extern "C" birk_status birk_krylov_solve(birk_plan* p, birk_jac_kind jk, const d
   hipError_t e = ensure_krylov(p, o.restart, mixed ? sizeof(float) : sizeof(double));
   if (e != hipSuccess) return dev_err(e);
   if (hipMemsetAsync(p->flag, 0, sizeof(int), s) != hipSuccess) return BIRK_ERR_DEVICE;
-  if (o.use_precond && precond_prepare(p, jk, J, mixed ? 1 : 0, s) != hipSuccess) return BIRK_ERR_DEVICE;
+  if (o.use_precond && precond_prepare(p, jk, J, mixed ? 1 : 0, s, 1) != hipSuccess) return BIRK_ERR_DEVICE;
   if (!o.use_x0 && hipMemsetAsync(chi, 0, n * sizeof(double), s) != hipSuccess) return BIRK_ERR_DEVICE;
 
   std::vector<InstState> st(B);

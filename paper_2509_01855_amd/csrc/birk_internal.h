@@ -332,18 +332,21 @@ hipError_t jac_times(birk_plan* p, int jac_kind, const double* J, const T* x, T*
 template <typename T>
 hipError_t precond_forward(birk_plan* p, int jac_kind, const double* J, const T* y, T* out,
                            hipStream_t s);
+// cached = 1: per-node H_k laid out by precond_prepare(..., repeated = 1) for this J.
 template <typename T>
 hipError_t precond_inverse(birk_plan* p, int jac_kind, const double* J, const T* y, T* out,
-                           T* jout, hipStream_t s, int* flag);
+                           T* jout, hipStream_t s, int* flag, int cached);
 int64_t pinv_scratch(int64_t Nn, int nx);
 int64_t pinv_jsw_size(int64_t Nn, int nx);
 // Build the per-n_x scan classes and the Krylov segmentation (after scan_off, jsw_off
 // and the weights exist); allocations are recorded in p->allocs.
 hipError_t plan_solve(birk_plan* p);
-// Lay out per-node J (or, for constant J, the weights) for the inverse scan; must precede
-// precond_inverse whenever J changes.
+// Per-J preparation of the inverse scan; must precede precond_inverse whenever J changes.
+// n_x > 8: H_k in the level-0 slots, always.  n_x <= 8: with repeated = 1 and per-node J,
+// H_k in the tile layout (read by precond_inverse with cached = 1); nothing otherwise.
 // single = 1 lays the data out in float (for precond_inverse<float>), else in double.
-hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s);
+hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s,
+                           int repeated);
 
 // Krylov BLAS-1 launchers (birk_solve.hip).  Reductions accumulate in double.
 constexpr int kKryMaxDots = 32;

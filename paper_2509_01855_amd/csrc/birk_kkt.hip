@@ -718,7 +718,7 @@ static hipError_t kkt_prec(birk_plan* p, int jk, const double* J, const double* 
   if (!use_precond) return hipMemcpyAsync(z, r, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s);
   hipLaunchKernelGGL(k_hscale, dim3(nb256(n)), dim3(256), 0, s, r, h, z, n, 1);
   double* t0 = (double*)p->tmp_vec[0];
-  hipError_t e = precond_inverse<double>(p, jk, J, r + n, t0, nullptr, s, nullptr);
+  hipError_t e = precond_inverse<double>(p, jk, J, r + n, t0, nullptr, s, nullptr, 1);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_hscale, dim3(nb256(n)), dim3(256), 0, s, t0, h, t0, n, 0);
   return precond_inverse_t(p, jk, J, t0, z + n, scr, s);
@@ -750,7 +750,7 @@ birk_status kkt_solve(birk_plan* p, int jk, const double* J, const double* h, co
   } else if (e == hipSuccess) {
     e = hipMemsetAsync(b.x, 0, 2 * n * sizeof(double), s);
   }
-  if (e == hipSuccess && o->use_precond) e = precond_prepare(p, jk, J, 0, s);
+  if (e == hipSuccess && o->use_precond) e = precond_prepare(p, jk, J, 0, s, 1);
   if (e != hipSuccess) return BIRK_ERR_DEVICE;
   std::vector<double> hst((size_t)B * kSt), bn(B), rn(B), tolv(B);
   std::vector<int> run(B, 1), status(B, BIRK_OK), inner(B, 0), outer(B, 0);

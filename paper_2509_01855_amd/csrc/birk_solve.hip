@@ -15,7 +15,8 @@
 //             G_k = I + w_k J_k K_k^{-1} and h_k = w_k J_k K_k^{-1} y_k.  The chain is
 //             evaluated as a scan of affine maps S_out = A S_in + b.  n_x <= 8: each
 //             thread holds whole maps; a DPP scan across waves, tile aggregates and
-//             tile start states (three launches).  Larger n_x: chunks of kChunk nodes
+//             tile start states (three launches), each node's K_k formed from J and
+//             w_k and factored where it is used.  Larger n_x: chunks of kChunk nodes
 //             worked by sixteen-lane groups, groups of kFan aggregates per level up to a
 //             sequential top, start states pushed back down.  Either way each chunk is
 //             replayed from its start state, emitting xi_k and J_k xi_k (the latter
@@ -192,6 +193,16 @@ hipError_t precond_forward(birk_plan* p, int jac_kind, const double* J, const T*
 
 // ------------------------------------------------------------------ P^{-1} y (inverse)
 
+// 1 / x from the hardware estimate and two Newton steps (within an ulp of the quotient;
+// several times cheaper than a division).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 // Unpivoted LU of K = I - (w/2) Jk in place, with reciprocal pivots.  K is strongly
 // diagonally dominant on the configurations of interest (w_k <= ~pi/N).  A pivot that
 // is non-finite, or not above 1e-13 times the scale 1 + |w/2| max|J_k| of K, marks K as
@@ -202,7 +213,7 @@ __device__ __forceinline__ void lu_kmat(double (&K)[NX][NX], double (&rp)[NX], i
   for (int p = 0; p < NX; ++p) {
     const double piv = K[p][p];
     if (flag && (!(fabs(piv) > 1e-13 * scale) || !isfinite(piv))) atomicOr(flag, 1);
-    rp[p] = 1.0 / piv;
+    rp[p] = recip(piv);
 #pragma unroll
     for (int i = p + 1; i < NX; ++i) {
       const double f = K[i][p] * rp[p];
@@ -664,6 +675,10 @@ constexpr int kWaveNx = 8;
 constexpr int kTileThreads = 256;
 constexpr int kTC = 4;
 constexpr int64_t kTileNodes = (int64_t)kTileThreads * kTC;
+// Where the scan kernels take K_k from: formed from one J per instance (uniform), formed
+// from per-node J staged through LDS, or H_k = w_k J_k K_k^{-1} laid out once per J by
+// precond_prepare (k_tmake_h) and read coalesced, for solves that apply P^{-1} repeatedly.
+constexpr int kFlyConst = 0, kFlyPerNode = 1, kCachedH = 2;
 
 template <int NX>
 struct Aff {
@@ -757,11 +772,110 @@ __device__ __forceinline__ void wave_scan(Aff<NX>& m) {
   scan_step<NX, 0x143, 0xC>(m, l >= 32);
 }
 
+// K_k = I - (w_k / 2) J_k of node k, factored in place by lu_kmat (pivot check into *flag
+// when flag is set); entry (r, q) of J_k at Jp[(r NX + q) js] (per node in global memory:
+// Jp = J + k, js = N_n; staged in LDS: js = 64; one J for the instance: js = 1).  With u
+// given, also ju = J_k u (J is read once, for both).
+template <int NX, typename P>
+__device__ __forceinline__ void node_lu(P Jp, int64_t js, double wk, double (&K)[NX][NX], double (&rp)[NX],
+                                        int* flag, const double* u, double* ju) {
+  double jmax = 0.0;
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      const double jv = Jp[(int64_t)(r * NX + q) * js];
+      if (flag) jmax = fmax(jmax, fabs(jv));
+      if (u) acc += jv * u[q];
+      K[r][q] = (r == q ? 1.0 : 0.0) - 0.5 * wk * jv;
+    }
+    if (u) ju[r] = acc;
+  }
+  lu_kmat<NX>(K, rp, flag, 1.0 + 0.5 * fabs(wk) * jmax);
+}
+
+// Per-node J staged through LDS: the kTC nodes of a chunk are consecutive, so a lane's
+// direct reads of J would be 32 bytes apart across the wave.  Instead each of kTC rounds
+// stages 64 consecutive nodes of the wave's 4 * 64 (J entry e of node 64 j + l at
+// lds[e * 64 + l], coalesced global reads), and the 16 lanes whose chunks lie in them
+// (lanes 16 j .. 16 j + 15) then work their nodes from LDS.
+template <int NX>
+__device__ __forceinline__ void stage_j(double* __restrict__ jw, const double* __restrict__ Jn, int64_t Nn,
+                                        int64_t kl, int l) {
+#pragma unroll
+  for (int e = 0; e < NX * NX; ++e) jw[e * 64 + l] = (kl < Nn) ? Jn[(int64_t)e * Nn + kl] : 0.0;
+}
+
+// The map of one chunk, composed node by node from A = I, b = 0.  Node k takes
+// S -> S + w_k J_k K_k^{-1} (y_k + S); since w_k J_k = 2 (I - K_k), that is
+// S -> C_k S + (C_k - I) y_k with C_k = 2 K_k^{-1} - I, so with x = K_k^{-1} v
+//     A <- C_k A:  each column a of A becomes a + 2 (K_k^{-1} a - a),
+//     b <- C_k b + (C_k - I) y_k = b + 2 (K_k^{-1} u - u),  u = b + y_k,
+// which needs only the factors of K_k (no J_k and no H_k kept).  Nodes past N_n are
+// identity maps.
+template <int NX, typename P, typename T>
+__device__ __forceinline__ void chunk_map(P Jp, int64_t jstep, int64_t js, const double* __restrict__ w,
+                                          const T* __restrict__ yi, int64_t Nn, int64_t k0, Aff<NX>& m, int* flag) {
+#pragma unroll 1
+  for (int j = 0; j < kTC; ++j) {
+    const int64_t k = k0 + j;
+    if (k >= Nn) break;
+    const double wk = w[k];
+    double K[NX][NX], rp[NX];
+    node_lu<NX>(Jp + j * jstep, js, wk, K, rp, flag, nullptr, nullptr);
+    double u[NX], x[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      u[r] = m.b[r] + (double)yi[(int64_t)r * Nn + k];
+      x[r] = u[r];
+    }
+    lu_solve<NX>(K, rp, x);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) m.b[r] += 2.0 * (x[r] - u[r]);
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+#pragma unroll
+      for (int r = 0; r < NX; ++r) x[r] = m.A[r][c];
+      lu_solve<NX>(K, rp, x);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) m.A[r][c] += 2.0 * (x[r] - m.A[r][c]);
+    }
+  }
+}
+
+// Replay of a chunk from state s (FastPinvY box): per node u = y_k + S,
+// xi_k = K_k^{-1} u, (J xi)_k = K_k^{-1} (J_k u) (J_k commutes with K_k^{-1}),
+// S <- S + w_k (J xi)_k.
+template <int NX, typename P, typename T>
+__device__ __forceinline__ void chunk_replay(P Jp, int64_t jstep, int64_t js, const double* __restrict__ w,
+                                             const T* __restrict__ yi, T* __restrict__ oi, T* __restrict__ ji,
+                                             int64_t Nn, int64_t k0, double (&s)[NX]) {
+#pragma unroll 1
+  for (int j = 0; j < kTC; ++j) {
+    const int64_t k = k0 + j;
+    if (k >= Nn) break;
+    const double wk = w[k];
+    double u[NX], ju[NX], K[NX][NX], rp[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) u[r] = s[r] + (double)yi[(int64_t)r * Nn + k];
+    node_lu<NX>(Jp + j * jstep, js, wk, K, rp, nullptr, u, ju);
+    lu_solve<NX>(K, rp, u);
+    lu_solve<NX>(K, rp, ju);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      s[r] += wk * ju[r];
+      oi[(int64_t)r * Nn + k] = (T)u[r];
+      if (ji) ji[(int64_t)r * Nn + k] = (T)ju[r];
+    }
+  }
+}
+
 // The map of one chunk: node k takes S -> (I + H_k) S + H_k y_k, so from A = I, b = 0 the
 // first node gives (I + H, H y) and each further node A <- A + H A, b <- b + H (b + y).
 // hs points at the thread's slot of field 0, node 0 of its tile.
 template <int NX, typename T>
-__device__ __forceinline__ void chunk_map(const T* __restrict__ hs, const T* __restrict__ yi, int64_t Nn, int64_t k0,
+__device__ __forceinline__ void chunk_map_h(const T* __restrict__ hs, const T* __restrict__ yi, int64_t Nn, int64_t k0,
                                           Aff<NX>& m) {
   constexpr int E = NX * NX + 1;
 #pragma unroll 1
@@ -892,25 +1006,40 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tmake_h(JT* __restrict__ js
 // totals gives their prefixes), so chunk t holds the map of nodes 0 .. 4t + 3 of its tile.
 // These inclusive maps are stored as [g][field][t] (scan[tmap + g F 256 + f 256 + t]) and
 // the last one is the tile aggregate (scan[tagg + g F]).  tile = (k, g).
-template <int NX, typename T>
-__global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const T* __restrict__ jsw, const T* __restrict__ y,
+template <int NX, int MODE, typename T>
+__global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const double* __restrict__ J, const T* __restrict__ jsw,
+                                                             const T* __restrict__ y,
                                                              const PinvDesc* __restrict__ pd,
                                                              const int2* __restrict__ tiles,
-                                                             double* __restrict__ scan) {
-  constexpr int E = NX * NX + 1;
+                                                             double* __restrict__ scan, int* flag) {
   constexpr int F = NX * NX + NX;
   constexpr int NW = kTileThreads / 64;
   __shared__ double tot[NW][F];
+  __shared__ double jl[MODE == kFlyPerNode ? NW * 64 * NX * NX : 1];
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
   const int64_t g = t.y;
-  const T* hs = jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x;
   const int64_t k0 = (g * kTileThreads + threadIdx.x) * kTC;
   const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
   double* cm = scan + d.tmap + g * F * kTileThreads + threadIdx.x;
   {
     Aff<NX> m;
-    chunk_map<NX, T>(hs, y + d.off, d.Nn, k0, m);
+    aff_identity<NX>(m);
+    if constexpr (MODE == kFlyPerNode) {
+      double* jw = jl + w * 64 * NX * NX;
+      const int64_t kw = g * kTileNodes + (int64_t)w * 64 * kTC;
+      for (int j = 0; j < kTC; ++j) {
+        stage_j<NX>(jw, J + d.joff, d.Nn, kw + 64 * j + l, l);
+        __syncthreads();
+        if ((l >> 4) == j) chunk_map<NX>(jw + (4 * l - 64 * j), int64_t(1), int64_t(64), d.w, y + d.off, d.Nn, k0, m, flag);
+        __syncthreads();
+      }
+    } else if constexpr (MODE == kFlyConst) {
+      chunk_map<NX>(J + d.jcoff, int64_t(0), int64_t(1), d.w, y + d.off, d.Nn, k0, m, flag);
+    } else {
+      constexpr int E = NX * NX + 1;
+      chunk_map_h<NX, T>(jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x, y + d.off, d.Nn, k0, m);
+    }
     wave_scan<NX>(m);
     if (l == 63) aff_store<NX>(&tot[w][0], m);
 #pragma unroll
@@ -1004,26 +1133,27 @@ __global__ __launch_bounds__(256) void k_tscan_tiles(double* __restrict__ scan, 
 }
 
 // Replay of one tile: chunk t starts from the tile start state advanced by the inclusive
-// map of chunk t - 1 (k_tscan_reduce), then per node u = y_k + S, v = H_k u,
-// xi_k = u + v / 2, (J xi)_k = v / w_k, S <- S + v.  tile = (k, g).
-template <int NX, typename T>
-__global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const T* __restrict__ jsw, const T* __restrict__ y,
+// map of chunk t - 1 (k_tscan_reduce), then replays its nodes (chunk_replay); K_k is
+// formed and factored here again from J_k and w_k.  tile = (k, g).
+template <int NX, int MODE, typename T>
+__global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const double* __restrict__ J, const T* __restrict__ jsw,
+                                                            const T* __restrict__ y,
                                                             const PinvDesc* __restrict__ pd,
                                                             const int2* __restrict__ tiles,
                                                             const double* __restrict__ scan, T* __restrict__ out,
                                                             T* __restrict__ jout) {
-  constexpr int E = NX * NX + 1;
   constexpr int F = NX * NX + NX;
+  constexpr int NW = kTileThreads / 64;
+  __shared__ double jl[MODE == kFlyPerNode ? NW * 64 * NX * NX : 1];
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
   const int64_t g = t.y;
   const int64_t Nn = d.Nn;
   const int64_t k0 = (g * kTileThreads + threadIdx.x) * kTC;
-  if (k0 >= Nn) return;
   double s[NX];
 #pragma unroll
   for (int r = 0; r < NX; ++r) s[r] = scan[d.tst + g * NX + r];
-  if (threadIdx.x > 0) {
+  if (threadIdx.x > 0 && k0 < Nn) {
     const double* cm = scan + d.tmap + g * F * kTileThreads + (threadIdx.x - 1);
     double ns[NX];
 #pragma unroll
@@ -1036,34 +1166,44 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const T* __restric
 #pragma unroll
     for (int r = 0; r < NX; ++r) s[r] = ns[r];
   }
-  const T* hs = jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x;
   const T* yi = y + d.off;
   T* oi = out + d.off;
   T* ji = jout ? jout + d.off : nullptr;
-  // the thread's four nodes of y are loaded together, so that the loads of one 32-byte
-  // sector are issued back to back
-  double yv[kTC][NX];
+  if constexpr (MODE == kFlyPerNode) {
+    // every thread takes part in the staging rounds (no early exit before the barriers)
+    const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
+    double* jw = jl + w * 64 * NX * NX;
+    const int64_t kw = g * kTileNodes + (int64_t)w * 64 * kTC;
+    for (int j = 0; j < kTC; ++j) {
+      stage_j<NX>(jw, J + d.joff, Nn, kw + 64 * j + l, l);
+      __syncthreads();
+      if ((l >> 4) == j) chunk_replay<NX>(jw + (4 * l - 64 * j), int64_t(1), int64_t(64), d.w, yi, oi, ji, Nn, k0, s);
+      __syncthreads();
+    }
+  } else if constexpr (MODE == kFlyConst) {
+    chunk_replay<NX>(J + d.jcoff, int64_t(0), int64_t(1), d.w, yi, oi, ji, Nn, k0, s);
+  } else {
+    // H_k from precond_prepare: v = H_k u, xi_k = u + v / 2, (J xi)_k = v / w_k, S <- S + v
+    constexpr int E = NX * NX + 1;
+    const T* hs = jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x;
+#pragma unroll 1
+    for (int j = 0; j < kTC; ++j) {
+      const int64_t k = k0 + j;
+      if (k >= Nn) break;
+      const T* base = hs + (int64_t)j * E * kTileThreads;
+      const double inv_w = 1.0 / (double)base[(E - 1) * kTileThreads];
+      double u[NX];
 #pragma unroll
-  for (int j = 0; j < kTC; ++j)
+      for (int r = 0; r < NX; ++r) u[r] = s[r] + (double)yi[(int64_t)r * Nn + k];
 #pragma unroll
-    for (int r = 0; r < NX; ++r) yv[j][r] = (k0 + j < Nn) ? (double)yi[(int64_t)r * Nn + k0 + j] : 0.0;
+      for (int r = 0; r < NX; ++r) {
+        double v = 0.0;
 #pragma unroll
-  for (int j = 0; j < kTC; ++j) {
-    const int64_t k = k0 + j;
-    if (k >= Nn) break;
-    const T* base = hs + (int64_t)j * E * kTileThreads;
-    const double inv_w = 1.0 / (double)base[(E - 1) * kTileThreads];
-    double u[NX];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) u[r] = s[r] + yv[j][r];
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      double v = 0.0;
-#pragma unroll
-      for (int q = 0; q < NX; ++q) v += (double)base[(r * NX + q) * kTileThreads] * u[q];
-      s[r] += v;
-      oi[(int64_t)r * Nn + k] = (T)(u[r] + 0.5 * v);
-      if (ji) ji[(int64_t)r * Nn + k] = (T)(v * inv_w);
+        for (int q = 0; q < NX; ++q) v += (double)base[(r * NX + q) * kTileThreads] * u[q];
+        s[r] += v;
+        oi[(int64_t)r * Nn + k] = (T)(u[r] + 0.5 * v);
+        if (ji) ji[(int64_t)r * Nn + k] = (T)(v * inv_w);
+      }
     }
   }
 }
@@ -1330,11 +1470,15 @@ hipError_t plan_solve(birk_plan* p) {
 }
 
 template <int NX, typename JT>
-static void make_h_class(birk_plan* p, const PinvClass& pc, const double* J, int pn, hipStream_t s) {
+static void make_h_class(birk_plan* p, const PinvClass& pc, const double* J, int pn, int repeated, hipStream_t s) {
   if constexpr (NX <= kWaveNx) {
-    hipLaunchKernelGGL((k_tmake_h<NX, JT>), dim3(pc.n_tile), dim3(kTileThreads), 0, s, (JT*)p->jsw, J, pn, pc.dev,
-                       pc.t_tile, p->flag);
+    // per-node J applied repeatedly: H_k cached in the tile layout; otherwise the scan
+    // kernels form K_k from J and w_k themselves
+    if (pn && repeated)
+      hipLaunchKernelGGL((k_tmake_h<NX, JT>), dim3(pc.n_tile), dim3(kTileThreads), 0, s, (JT*)p->jsw, J, pn, pc.dev,
+                         pc.t_tile, p->flag);
   } else {
+    (void)repeated;
     if (pc.n_swz[pn] == 0) return;
     hipLaunchKernelGGL(k_swizzle_nodes<JT>, dim3(pc.n_swz[pn]), dim3(256), 0, s, J, pn, pc.nx, pc.dev, pc.t_swz[pn],
                        (JT*)p->jsw);
@@ -1360,32 +1504,55 @@ static void make_h_class(birk_plan* p, const PinvClass& pc, const double* J, int
     default: return hipErrorInvalidValue;                              \
   }
 
-// H_k and w_k in the scan's node slots, once per Jacobian: n_x <= kWaveNx straight from J
-// in the tile layout (k_tmake_h); larger n_x lay J and w out in the level-0 slots and
-// replace the J fields by H_k (k_make_h_rows).  The scans themselves only read H_k and w_k.
-hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s) {
+// Per-Jacobian preparation of the scan: n_x > kWaveNx lay J and w out in the level-0
+// slots and replace the J fields by H_k (k_make_h_rows), which their scan kernels read.
+// n_x <= kWaveNx with per-node J and repeated = 1 (a solve) cache H_k in the tile layout
+// (k_tmake_h: one pass that turns the later applications' strided J reads and per-node
+// factorisations into coalesced H_k reads); otherwise they need nothing.
+hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s, int repeated) {
   const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
   for (const PinvClass& pc : p->pclass) {
     if (single) {
-      BIRK_NX_SWITCH(pc.nx, (make_h_class<NXC, float>(p, pc, J, pn, s)))
+      BIRK_NX_SWITCH(pc.nx, (make_h_class<NXC, float>(p, pc, J, pn, repeated, s)))
     } else {
-      BIRK_NX_SWITCH(pc.nx, (make_h_class<NXC, double>(p, pc, J, pn, s)))
+      BIRK_NX_SWITCH(pc.nx, (make_h_class<NXC, double>(p, pc, J, pn, repeated, s)))
     }
   }
   return hipGetLastError();
 }
 
 template <int NX, typename T>
-static void pinv_class(birk_plan* p, const PinvClass& pc, const T* y, T* out, T* jout, hipStream_t s) {
+static void pinv_class(birk_plan* p, const PinvClass& pc, const double* J, int pn, int cached, const T* y, T* out,
+                       T* jout, hipStream_t s) {
   const T* jsw = (const T*)p->jsw;
   double* scan = p->scan;
   if constexpr (NX <= kWaveNx) {
-    hipLaunchKernelGGL((k_tscan_reduce<NX, T>), dim3(pc.n_tile), dim3(kTileThreads), 0, s, jsw, y, pc.dev, pc.t_tile,
-                       scan);
+    const dim3 grid(pc.n_tile), block(kTileThreads);
+    if (!pn) {
+      hipLaunchKernelGGL((k_tscan_reduce<NX, kFlyConst, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan,
+                         p->flag);
+    } else if (cached) {
+      hipLaunchKernelGGL((k_tscan_reduce<NX, kCachedH, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan,
+                         p->flag);
+    } else {
+      hipLaunchKernelGGL((k_tscan_reduce<NX, kFlyPerNode, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan,
+                         p->flag);
+    }
     hipLaunchKernelGGL((k_tscan_tiles<NX>), dim3(pc.ninst), dim3(256), 0, s, scan, pc.dev);
-    hipLaunchKernelGGL((k_tscan_apply<NX, T>), dim3(pc.n_tile), dim3(kTileThreads), 0, s, jsw, y, pc.dev, pc.t_tile,
-                       scan, out, jout);
+    if (!pn) {
+      hipLaunchKernelGGL((k_tscan_apply<NX, kFlyConst, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan, out,
+                         jout);
+    } else if (cached) {
+      hipLaunchKernelGGL((k_tscan_apply<NX, kCachedH, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan, out,
+                         jout);
+    } else {
+      hipLaunchKernelGGL((k_tscan_apply<NX, kFlyPerNode, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan,
+                         out, jout);
+    }
   } else {
+    (void)J;
+    (void)pn;
+    (void)cached;
     constexpr int ncg = ColGroups<NX>::count;
     hipLaunchKernelGGL((k_pinv_up0<NX, T>), dim3(pc.n_node0, ncg), dim3(256), 0, s, jsw, y, pc.dev, pc.t_node0, scan);
     for (int l = 0; l < pc.Lmax; ++l)
@@ -1406,14 +1573,15 @@ static void jac_class(const PinvClass& pc, const double* J, int pn, const T* x, 
 
 template <typename T>
 hipError_t precond_inverse(birk_plan* p, int jac_kind, const double* J, const T* y, T* out, T* jout,
-                           hipStream_t s, int* flag) {
-  // H_k and w_k must have been laid out for this J by precond_prepare (which also checks
-  // the pivots); J and jac_kind are not read again here
-  (void)jac_kind;
-  (void)J;
+                           hipStream_t s, int* flag, int cached) {
+  // n_x <= 8: K_k formed from J and factored inside the scan kernels (pivot checks into
+  // the plan's flag), or, per-node J with cached = 1, the H_k that precond_prepare laid
+  // out with repeated = 1; larger n_x read the H_k that precond_prepare laid out for this
+  // J (checking the pivots there)
   (void)flag;
+  const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
   for (const PinvClass& pc : p->pclass) {
-    BIRK_NX_SWITCH(pc.nx, (pinv_class<NXC, T>(p, pc, y, out, jout, s)))
+    BIRK_NX_SWITCH(pc.nx, (pinv_class<NXC, T>(p, pc, J, pn, cached, y, out, jout, s)))
   }
   return hipGetLastError();
 }
@@ -1434,9 +1602,9 @@ template hipError_t jac_times<float>(birk_plan*, int, const double*, const float
 template hipError_t precond_forward<double>(birk_plan*, int, const double*, const double*, double*, hipStream_t);
 template hipError_t precond_forward<float>(birk_plan*, int, const double*, const float*, float*, hipStream_t);
 template hipError_t precond_inverse<double>(birk_plan*, int, const double*, const double*, double*, double*,
-                                            hipStream_t, int*);
+                                            hipStream_t, int*, int);
 template hipError_t precond_inverse<float>(birk_plan*, int, const double*, const float*, float*, float*,
-                                           hipStream_t, int*);
+                                           hipStream_t, int*, int);
 
 // ------------------------------------------------------------------ Krylov BLAS-1
 // Krylov BLAS-1: at most kMaxDots basis vectors per call, reductions in double.
