@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "birk_internal.h"
 
@@ -33,6 +34,26 @@ namespace birk {
 
 constexpr int kChunk = 16;
 constexpr int kFan = 16;
+
+// Lane P of each row of sixteen lanes, broadcast across its row (DPP row_newbcast: a VALU
+// move, in place of an LDS permute), for a double.
+template <int P>
+__device__ __forceinline__ double row_bcast(double v) {
+  const unsigned long long x = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)x, (int)(unsigned)x, 0x150 + P, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(x >> 32), (int)(unsigned)(x >> 32), 0x150 + P, 0xF, 0xF,
+                                             false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// f(std::integral_constant<int, P>) for P = B .. E - 1, in order (compile-time lane indices).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 // ------------------------------------------------------------------ P y (forward)
 constexpr int kScanItems = 4;
@@ -359,16 +380,16 @@ __global__ __launch_bounds__(256) void k_make_h_rows(JT* __restrict__ jsw, const
 #pragma unroll
     for (int o = 8; o >= 1; o >>= 1) jm = fmax(jm, __shfl_xor(jm, o, 16));
     const double scale = 1.0 + 0.5 * fabs(wk) * jm;
-#pragma unroll
-    for (int p = 0; p < NX; ++p) {
+    static_for<0, NX>([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
       double pk[NX], px[NX];
 #pragma unroll
-      for (int q = p; q < NX; ++q) pk[q] = __shfl(Kr[q], p, 16);
+      for (int q = p; q < NX; ++q) pk[q] = row_bcast<p>(Kr[q]);
 #pragma unroll
-      for (int q = 0; q < NX; ++q) px[q] = __shfl(Xr[q], p, 16);
+      for (int q = 0; q < NX; ++q) px[q] = row_bcast<p>(Xr[q]);
       const double piv = pk[p];
       if (r == 0 && flag && (!(fabs(piv) > 1e-13 * scale) || !isfinite(piv))) atomicOr(flag, 1);
-      const double rp = 1.0 / piv;
+      const double rp = recip(piv);
       if (r == p) {
 #pragma unroll
         for (int q = p + 1; q < NX; ++q) Kr[q] *= rp;
@@ -381,7 +402,7 @@ __global__ __launch_bounds__(256) void k_make_h_rows(JT* __restrict__ jsw, const
 #pragma unroll
         for (int q = 0; q < NX; ++q) Xr[q] -= f * px[q];
       }
-    }
+    });
     if (act) {
 #pragma unroll
       for (int q = 0; q < NX; ++q) base[(r * NX + q) * 64] = (JT)Xr[q];
@@ -1246,11 +1267,10 @@ __global__ __launch_bounds__(256) void k_pinv_final_lanes(const T* __restrict__ 
     const double inv_w = 1.0 / (double)base[(E - 1) * 64];
     const double u = s + (act ? (double)yi[(int64_t)rr * Nn + k] : 0.0);
     double v = 0.0;
-#pragma unroll
-    for (int q = 0; q < NX; ++q) {
-      const double uq = __shfl(u, q, 16);
-      v += (act ? (double)base[(rr * NX + q) * 64] : 0.0) * uq;
-    }
+    static_for<0, NX>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      v += (act ? (double)base[(rr * NX + q) * 64] : 0.0) * row_bcast<q>(u);
+    });
     s += v;
     if (act) {
       oi[(int64_t)r * Nn + k] = (T)(u + 0.5 * v);
