@@ -13,7 +13,8 @@ One step is one pass of the whole hot path:
     Krylov bulk inside double refinement (mixed) and once in double (FP64); the b-form
     products B^b v, B^bT g and the endpoint row x^b = x^a + w^T v in double; Newton's
     method on the nonlinear two-body IVP over one period (e = 0.15) from the circular
-    orbit, to ||G|| <= 1e-13 ||X||;
+    orbit, to ||G|| <= 1e-13 ||X||; MINRES on the symmetric KKT form
+    [[I, A^T], [A, 0]] [chi; lambda] = [0; beta] to 1e-10;
   * small workloads: N_n = 256 and 257, n_x = 6 (LTI, B^a, B^aT and the solve to 1e-12)
     and N_n = 2^16 + 1, n_x = 6 (LTI, B^a, B^aT and both solves to 1e-10);
   * batched uneven workload: 512 LTI instances (N_n log-uniform in [2^8, 2^16], n_x in
@@ -65,6 +66,8 @@ def parse():
     ap.add_argument("--products-only", action="store_true", help="skip the solves (for profiling runs)")
     ap.add_argument("--headline-only", action="store_true", help="skip the small, batched and many-RHS workloads")
     ap.add_argument("--cpu-sample", type=int, default=800, help="rows of B^a the oracle computes at N = 2^20")
+    ap.add_argument("--solve-only", choices=["fp64", "mixed"], default=None,
+                    help="time only the headline solve in this precision (per-kernel profiles of one solve)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -230,6 +233,8 @@ def oracle_leg(a, acc, nproc):
         err["solve_mixed_vs_closed_form"] = rel(acc["head_solve"]["mixed"], Z)
         err["solve_note"] = ("time-shift right-hand side Z(-1) of the headline Kepler system, exact "
                              "solution (v, a)(t) along the orbit; solved to 1e-10 like the timed solves")
+        if "head_kkt_chi" in acc:
+            err["kkt_minres_chi_vs_closed_form"] = rel(acc["head_kkt_chi"], Z)
     if "newton_err" in acc:
         err["newton_ivp_vs_kepler"] = acc["newton_err"]
     if "small" in acc:
@@ -459,7 +464,7 @@ def main():
     ivp_X = torch.empty_like(ivp_guess)
     ivp_info = {}
 
-    extra = not a.headline_only
+    extra = not a.headline_only and not a.solve_only
     if extra:
         # ---- small workloads (N_n = 256, 257 with n_x = 6; N_n = 2^16 + 1 with n_x = 6)
         print("[bench] building the small workloads", file=sys.stderr, flush=True)
@@ -509,6 +514,7 @@ def main():
         modf = torch.empty_like(mvdf)
     torch.cuda.synchronize()
 
+    kkt_lam = torch.zeros(n, dtype=torch.float64, device="cuda")
     xa_end = torch.zeros(nx, dtype=torch.float64, device="cuda")
     xb_end = torch.empty_like(xa_end)
 
@@ -533,6 +539,12 @@ def main():
         torch.cuda.synchronize()
 
     def step(timed: bool):
+        if a.solve_only:
+            plan = plan64 if a.solve_only == "fp64" else planmx
+            solve_info[a.solve_only] = tm.wall(a.solve_only if timed else "_warm",
+                                               lambda: B.birk_krylov_solve(plan, J, beta, chi, B.BIRK_J_PER_NODE,
+                                                                           rtol=1e-10))
+            return
         for i in range(R):
             tm.region("apply", lambda i=i: B.birk_apply(plan64, vin[i], vout[i]))
         for i in range(R):
@@ -581,6 +593,10 @@ def main():
                 ivp_X.copy_(ivp_guess)
                 ivp_info.update(B.birk_newton_ivp(plan64, ivp_xa, ivp_X, mu=ivp["mu"], scale=ivp["scale"]))
             tm.wall("newton" if timed else "_warm", newton)
+            # MINRES on the KKT form with H = I, f = 0 (chi = A^{-1} beta, lambda = -A^{-T} chi)
+            solve_info["kkt"] = tm.wall("kkt" if timed else "_warm",
+                                        lambda: B.birk_kkt_solve(plan64, J, beta, chi, kkt_lam,
+                                                                 jac_kind=B.BIRK_J_PER_NODE, rtol=1e-10))
 
     for _ in range(a.warmup):
         step(False)
@@ -593,6 +609,12 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
+    if a.solve_only:
+        info = solve_info[a.solve_only]
+        print(json.dumps({"solve_only": a.solve_only, "workload": "headline Kepler system, rtol 1e-10",
+                          "ms": round(tm.mean_ms(a.solve_only), 3), "inner_iters": info["inner_iters"],
+                          "outer_iters": info["outer_iters"], "rel_resid": info["rel_resid"]}), flush=True)
+        return
     t_apply = tm.mean_ms("apply") * 1e-3
     gpts = n / t_apply / 1e9
     bytes_alg = 2.0 * n * 8.0
@@ -653,6 +675,12 @@ def main():
             "mixed": {k: solve_info["mixed"][k] for k in ("inner_iters", "outer_iters", "rel_resid")},
             "fp64": {k: solve_info["fp64"][k] for k in ("inner_iters", "outer_iters", "rel_resid")},
         }
+        ki = solve_info["kkt"]
+        out["kkt_minres"] = {
+            "workload": "MINRES on [[I, A^T], [A, 0]] [chi; lambda] = [0; beta], headline Kepler system, "
+                        "preconditioner blockdiag(I, P P^T)^{-1}, rtol 1e-10",
+            "ms": round(tm.mean_ms("kkt"), 3), "minres_iters": ki["inner_iters"][0],
+            "restarts": ki["outer_iters"][0], "rel_resid": ki["rel_resid"][0]}
         err = float(np.max(np.abs(ivp_X.cpu().numpy().reshape(6, Nn) - ivp["exact"])))
         out["newton_ivp"] = {
             "workload": "two-body IVP over one period (e = 0.15), N_n = 2^20 + 1, Newton from the circular orbit",
@@ -722,6 +750,10 @@ def main():
                 B.birk_krylov_solve(plan, J, bz, xz, B.BIRK_J_PER_NODE, rtol=1e-10)
                 acc["head_solve"][p] = host(xz).reshape(6, Nn)
             acc["head_solve_exact"] = Z
+            xk = torch.zeros_like(bz)
+            lk = torch.zeros_like(bz)
+            B.birk_kkt_solve(plan64, J, bz, xk, lk, jac_kind=B.BIRK_J_PER_NODE, rtol=1e-10)
+            acc["head_kkt_chi"] = host(xk).reshape(6, Nn)
             acc["newton_err"] = out["newton_ivp"]["max_abs_err_vs_kepler"] / float(np.max(np.abs(ivp["exact"])))
         if extra:
             c0d = {}

@@ -49,7 +49,7 @@ import re
 
 # forward double product: pass A, pass B (TRANS = 0), pass C (TRANS = 0); the
 # fixed-length kernels (suffix 2) are used where they apply
-PASSES = (r"k_fastA2?<double", r"k_fastB2<double, 0,|k_fastB<double, \d+, 0>", r"k_fastC2?<double, 0")
+PASSES = (r"k_fastA2?<double", r"k_fastB[23]<double, 0,|k_fastB<double, \d+, 0>", r"k_fastC2?<double, 0")
 
 
 def _rows(d):

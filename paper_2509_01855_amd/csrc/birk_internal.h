@@ -336,6 +336,10 @@ hipError_t precond_forward(birk_plan* p, int jac_kind, const double* J, const T*
 template <typename T>
 hipError_t precond_inverse(birk_plan* p, int jac_kind, const double* J, const T* y, T* out,
                            T* jout, hipStream_t s, int* flag, int cached);
+// P^{-T} y for the instances with n_x <= 8 (backward wave scan, double); the instances
+// with larger n_x are left untouched (birk_kkt.hip covers them).
+hipError_t precond_inverse_t_wave(birk_plan* p, int jac_kind, const double* J, const double* y, double* out,
+                                  hipStream_t s);
 int64_t pinv_scratch(int64_t Nn, int nx);
 int64_t pinv_jsw_size(int64_t Nn, int nx);
 // Build the per-n_x scan classes and the Krylov segmentation (after scan_off, jsw_off

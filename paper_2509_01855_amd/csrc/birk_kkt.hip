@@ -622,7 +622,11 @@ hipError_t plan_kkt(birk_plan* p) {
 
 hipError_t precond_inverse_t(birk_plan* p, int jac_kind, const double* J, const double* y, double* x, double* scr,
                              hipStream_t s) {
+  // n_x <= 8: the backward wave scan of birk_solve.hip; larger n_x: the chunked scan here
+  hipError_t e = precond_inverse_t_wave(p, jac_kind, J, y, x, s);
+  if (e != hipSuccess) return e;
   for (const BtClass& bc : p->btclass) {
+    if (bc.nx <= 8) continue;
     BIRK_NX_SWITCH(bc.nx, (bt_class<NX>(bc, J, jac_kind == BIRK_J_PER_NODE, y, x, scr, s)))
   }
   return hipGetLastError();

@@ -796,8 +796,9 @@ __device__ __forceinline__ void wave_scan(Aff<NX>& m) {
 // K_k = I - (w_k / 2) J_k of node k, factored in place by lu_kmat (pivot check into *flag
 // when flag is set); entry (r, q) of J_k at Jp[(r NX + q) js] (per node in global memory:
 // Jp = J + k, js = N_n; staged in LDS: js = 64; one J for the instance: js = 1).  With u
-// given, also ju = J_k u (J is read once, for both).
-template <int NX, typename P>
+// given, also ju = J_k u (J is read once, for both).  TRJ: the same with J_k^T in place
+// of J_k (K_k^T = I - (w_k / 2) J_k^T, ju = J_k^T u).
+template <int NX, bool TRJ, typename P>
 __device__ __forceinline__ void node_lu(P Jp, int64_t js, double wk, double (&K)[NX][NX], double (&rp)[NX],
                                         int* flag, const double* u, double* ju) {
   double jmax = 0.0;
@@ -806,7 +807,7 @@ __device__ __forceinline__ void node_lu(P Jp, int64_t js, double wk, double (&K)
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < NX; ++q) {
-      const double jv = Jp[(int64_t)(r * NX + q) * js];
+      const double jv = Jp[(int64_t)(TRJ ? q * NX + r : r * NX + q) * js];
       if (flag) jmax = fmax(jmax, fabs(jv));
       if (u) acc += jv * u[q];
       K[r][q] = (r == q ? 1.0 : 0.0) - 0.5 * wk * jv;
@@ -821,11 +822,13 @@ __device__ __forceinline__ void node_lu(P Jp, int64_t js, double wk, double (&K)
 // stages 64 consecutive nodes of the wave's 4 * 64 (J entry e of node 64 j + l at
 // lds[e * 64 + l], coalesced global reads), and the 16 lanes whose chunks lie in them
 // (lanes 16 j .. 16 j + 15) then work their nodes from LDS.
-template <int NX>
+// BACK: scan positions run from the last node down (position p is node N_n - 1 - p).
+template <int NX, bool BACK>
 __device__ __forceinline__ void stage_j(double* __restrict__ jw, const double* __restrict__ Jn, int64_t Nn,
                                         int64_t kl, int l) {
+  const int64_t k = BACK ? Nn - 1 - kl : kl;
 #pragma unroll
-  for (int e = 0; e < NX * NX; ++e) jw[e * 64 + l] = (kl < Nn) ? Jn[(int64_t)e * Nn + kl] : 0.0;
+  for (int e = 0; e < NX * NX; ++e) jw[e * 64 + l] = (kl < Nn) ? Jn[(int64_t)e * Nn + k] : 0.0;
 }
 
 // The map of one chunk, composed node by node from A = I, b = 0.  Node k takes
@@ -833,27 +836,32 @@ __device__ __forceinline__ void stage_j(double* __restrict__ jw, const double* _
 // S -> C_k S + (C_k - I) y_k with C_k = 2 K_k^{-1} - I, so with x = K_k^{-1} v
 //     A <- C_k A:  each column a of A becomes a + 2 (K_k^{-1} a - a),
 //     b <- C_k b + (C_k - I) y_k = b + 2 (K_k^{-1} u - u),  u = b + y_k,
-// which needs only the factors of K_k (no J_k and no H_k kept).  Nodes past N_n are
-// identity maps.
-template <int NX, typename P, typename T>
+// which needs only the factors of K_k (no J_k and no H_k kept).  BACK (P^{-T}, backward
+// substitution with P^T from the last node, T the sum of the later x): node k takes
+// T -> T + K_k^{-T} (y_k + w_k J_k^T T) = C'_k T + K_k^{-T} y_k with C'_k = 2 K_k^{-T} - I,
+// so A as above with K_k^T, and b <- K_k^{-T} (2 b + y_k) - b.  Positions p = k0 + j run
+// over the nodes (node p, or N_n - 1 - p with BACK); positions past N_n are identity maps.
+template <int NX, bool BACK, typename P, typename T>
 __device__ __forceinline__ void chunk_map(P Jp, int64_t jstep, int64_t js, const double* __restrict__ w,
                                           const T* __restrict__ yi, int64_t Nn, int64_t k0, Aff<NX>& m, int* flag) {
 #pragma unroll 1
   for (int j = 0; j < kTC; ++j) {
-    const int64_t k = k0 + j;
-    if (k >= Nn) break;
+    const int64_t pos = k0 + j;
+    if (pos >= Nn) break;
+    const int64_t k = BACK ? Nn - 1 - pos : pos;
     const double wk = w[k];
     double K[NX][NX], rp[NX];
-    node_lu<NX>(Jp + j * jstep, js, wk, K, rp, flag, nullptr, nullptr);
+    node_lu<NX, BACK>(Jp + j * jstep, js, wk, K, rp, flag, nullptr, nullptr);
     double u[NX], x[NX];
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
-      u[r] = m.b[r] + (double)yi[(int64_t)r * Nn + k];
+      const double yv = (double)yi[(int64_t)r * Nn + k];
+      u[r] = BACK ? 2.0 * m.b[r] + yv : m.b[r] + yv;
       x[r] = u[r];
     }
     lu_solve<NX>(K, rp, x);
 #pragma unroll
-    for (int r = 0; r < NX; ++r) m.b[r] += 2.0 * (x[r] - u[r]);
+    for (int r = 0; r < NX; ++r) m.b[r] = BACK ? x[r] - m.b[r] : m.b[r] + 2.0 * (x[r] - u[r]);
 #pragma unroll
     for (int c = 0; c < NX; ++c) {
 #pragma unroll
@@ -867,27 +875,41 @@ __device__ __forceinline__ void chunk_map(P Jp, int64_t jstep, int64_t js, const
 
 // Replay of a chunk from state s (FastPinvY box): per node u = y_k + S,
 // xi_k = K_k^{-1} u, (J xi)_k = K_k^{-1} (J_k u) (J_k commutes with K_k^{-1}),
-// S <- S + w_k (J xi)_k.
-template <int NX, typename P, typename T>
+// S <- S + w_k (J xi)_k.  BACK (P^{-T}, from the last node): x_k = K_k^{-T} (y_k +
+// w_k J_k^T T), T <- T + x_k; ji is not written.
+template <int NX, bool BACK, typename P, typename T>
 __device__ __forceinline__ void chunk_replay(P Jp, int64_t jstep, int64_t js, const double* __restrict__ w,
                                              const T* __restrict__ yi, T* __restrict__ oi, T* __restrict__ ji,
                                              int64_t Nn, int64_t k0, double (&s)[NX]) {
 #pragma unroll 1
   for (int j = 0; j < kTC; ++j) {
-    const int64_t k = k0 + j;
-    if (k >= Nn) break;
+    const int64_t pos = k0 + j;
+    if (pos >= Nn) break;
+    const int64_t k = BACK ? Nn - 1 - pos : pos;
     const double wk = w[k];
     double u[NX], ju[NX], K[NX][NX], rp[NX];
+    if constexpr (BACK) {
+      node_lu<NX, true>(Jp + j * jstep, js, wk, K, rp, nullptr, s, ju);
 #pragma unroll
-    for (int r = 0; r < NX; ++r) u[r] = s[r] + (double)yi[(int64_t)r * Nn + k];
-    node_lu<NX>(Jp + j * jstep, js, wk, K, rp, nullptr, u, ju);
-    lu_solve<NX>(K, rp, u);
-    lu_solve<NX>(K, rp, ju);
+      for (int r = 0; r < NX; ++r) u[r] = (double)yi[(int64_t)r * Nn + k] + wk * ju[r];
+      lu_solve<NX>(K, rp, u);
 #pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      s[r] += wk * ju[r];
-      oi[(int64_t)r * Nn + k] = (T)u[r];
-      if (ji) ji[(int64_t)r * Nn + k] = (T)ju[r];
+      for (int r = 0; r < NX; ++r) {
+        s[r] += u[r];
+        oi[(int64_t)r * Nn + k] = (T)u[r];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < NX; ++r) u[r] = s[r] + (double)yi[(int64_t)r * Nn + k];
+      node_lu<NX, false>(Jp + j * jstep, js, wk, K, rp, nullptr, u, ju);
+      lu_solve<NX>(K, rp, u);
+      lu_solve<NX>(K, rp, ju);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        s[r] += wk * ju[r];
+        oi[(int64_t)r * Nn + k] = (T)u[r];
+        if (ji) ji[(int64_t)r * Nn + k] = (T)ju[r];
+      }
     }
   }
 }
@@ -1027,7 +1049,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tmake_h(JT* __restrict__ js
 // totals gives their prefixes), so chunk t holds the map of nodes 0 .. 4t + 3 of its tile.
 // These inclusive maps are stored as [g][field][t] (scan[tmap + g F 256 + f 256 + t]) and
 // the last one is the tile aggregate (scan[tagg + g F]).  tile = (k, g).
-template <int NX, int MODE, typename T>
+template <int NX, int MODE, bool BACK, typename T>
 __global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const double* __restrict__ J, const T* __restrict__ jsw,
                                                              const T* __restrict__ y,
                                                              const PinvDesc* __restrict__ pd,
@@ -1050,14 +1072,16 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const double* 
       double* jw = jl + w * 64 * NX * NX;
       const int64_t kw = g * kTileNodes + (int64_t)w * 64 * kTC;
       for (int j = 0; j < kTC; ++j) {
-        stage_j<NX>(jw, J + d.joff, d.Nn, kw + 64 * j + l, l);
+        stage_j<NX, BACK>(jw, J + d.joff, d.Nn, kw + 64 * j + l, l);
         __syncthreads();
-        if ((l >> 4) == j) chunk_map<NX>(jw + (4 * l - 64 * j), int64_t(1), int64_t(64), d.w, y + d.off, d.Nn, k0, m, flag);
+        if ((l >> 4) == j)
+          chunk_map<NX, BACK>(jw + (4 * l - 64 * j), int64_t(1), int64_t(64), d.w, y + d.off, d.Nn, k0, m, flag);
         __syncthreads();
       }
     } else if constexpr (MODE == kFlyConst) {
-      chunk_map<NX>(J + d.jcoff, int64_t(0), int64_t(1), d.w, y + d.off, d.Nn, k0, m, flag);
+      chunk_map<NX, BACK>(J + d.jcoff, int64_t(0), int64_t(1), d.w, y + d.off, d.Nn, k0, m, flag);
     } else {
+      static_assert(!BACK, "the cached H_k serve P^{-1} only");
       constexpr int E = NX * NX + 1;
       chunk_map_h<NX, T>(jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x, y + d.off, d.Nn, k0, m);
     }
@@ -1156,7 +1180,7 @@ __global__ __launch_bounds__(256) void k_tscan_tiles(double* __restrict__ scan, 
 // Replay of one tile: chunk t starts from the tile start state advanced by the inclusive
 // map of chunk t - 1 (k_tscan_reduce), then replays its nodes (chunk_replay); K_k is
 // formed and factored here again from J_k and w_k.  tile = (k, g).
-template <int NX, int MODE, typename T>
+template <int NX, int MODE, bool BACK, typename T>
 __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const double* __restrict__ J, const T* __restrict__ jsw,
                                                             const T* __restrict__ y,
                                                             const PinvDesc* __restrict__ pd,
@@ -1196,15 +1220,17 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const double* __re
     double* jw = jl + w * 64 * NX * NX;
     const int64_t kw = g * kTileNodes + (int64_t)w * 64 * kTC;
     for (int j = 0; j < kTC; ++j) {
-      stage_j<NX>(jw, J + d.joff, Nn, kw + 64 * j + l, l);
+      stage_j<NX, BACK>(jw, J + d.joff, Nn, kw + 64 * j + l, l);
       __syncthreads();
-      if ((l >> 4) == j) chunk_replay<NX>(jw + (4 * l - 64 * j), int64_t(1), int64_t(64), d.w, yi, oi, ji, Nn, k0, s);
+      if ((l >> 4) == j)
+        chunk_replay<NX, BACK>(jw + (4 * l - 64 * j), int64_t(1), int64_t(64), d.w, yi, oi, ji, Nn, k0, s);
       __syncthreads();
     }
   } else if constexpr (MODE == kFlyConst) {
-    chunk_replay<NX>(J + d.jcoff, int64_t(0), int64_t(1), d.w, yi, oi, ji, Nn, k0, s);
+    chunk_replay<NX, BACK>(J + d.jcoff, int64_t(0), int64_t(1), d.w, yi, oi, ji, Nn, k0, s);
   } else {
     // H_k from precond_prepare: v = H_k u, xi_k = u + v / 2, (J xi)_k = v / w_k, S <- S + v
+    static_assert(!BACK, "the cached H_k serve P^{-1} only");
     constexpr int E = NX * NX + 1;
     const T* hs = jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x;
 #pragma unroll 1
@@ -1549,24 +1575,24 @@ static void pinv_class(birk_plan* p, const PinvClass& pc, const double* J, int p
   if constexpr (NX <= kWaveNx) {
     const dim3 grid(pc.n_tile), block(kTileThreads);
     if (!pn) {
-      hipLaunchKernelGGL((k_tscan_reduce<NX, kFlyConst, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan,
+      hipLaunchKernelGGL((k_tscan_reduce<NX, kFlyConst, false, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan,
                          p->flag);
     } else if (cached) {
-      hipLaunchKernelGGL((k_tscan_reduce<NX, kCachedH, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan,
+      hipLaunchKernelGGL((k_tscan_reduce<NX, kCachedH, false, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan,
                          p->flag);
     } else {
-      hipLaunchKernelGGL((k_tscan_reduce<NX, kFlyPerNode, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan,
+      hipLaunchKernelGGL((k_tscan_reduce<NX, kFlyPerNode, false, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan,
                          p->flag);
     }
     hipLaunchKernelGGL((k_tscan_tiles<NX>), dim3(pc.ninst), dim3(256), 0, s, scan, pc.dev);
     if (!pn) {
-      hipLaunchKernelGGL((k_tscan_apply<NX, kFlyConst, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan, out,
+      hipLaunchKernelGGL((k_tscan_apply<NX, kFlyConst, false, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan, out,
                          jout);
     } else if (cached) {
-      hipLaunchKernelGGL((k_tscan_apply<NX, kCachedH, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan, out,
+      hipLaunchKernelGGL((k_tscan_apply<NX, kCachedH, false, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan, out,
                          jout);
     } else {
-      hipLaunchKernelGGL((k_tscan_apply<NX, kFlyPerNode, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan,
+      hipLaunchKernelGGL((k_tscan_apply<NX, kFlyPerNode, false, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan,
                          out, jout);
     }
   } else {
@@ -1602,6 +1628,44 @@ hipError_t precond_inverse(birk_plan* p, int jac_kind, const double* J, const T*
   const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
   for (const PinvClass& pc : p->pclass) {
     BIRK_NX_SWITCH(pc.nx, (pinv_class<NXC, T>(p, pc, J, pn, cached, y, out, jout, s)))
+  }
+  return hipGetLastError();
+}
+
+// P^{-T} y for the classes with n_x <= kWaveNx: the same three launches run backwards over
+// the nodes with K_k^T (double only; the classes above are left to the caller).
+template <int NX>
+static void pinv_t_class(birk_plan* p, const PinvClass& pc, const double* J, int pn, const double* y, double* out,
+                         hipStream_t s) {
+  if constexpr (NX <= kWaveNx) {
+    const dim3 grid(pc.n_tile), block(kTileThreads);
+    const double* jsw = (const double*)p->jsw;
+    if (pn) {
+      hipLaunchKernelGGL((k_tscan_reduce<NX, kFlyPerNode, true, double>), grid, block, 0, s, J, jsw, y, pc.dev,
+                         pc.t_tile, p->scan, p->flag);
+    } else {
+      hipLaunchKernelGGL((k_tscan_reduce<NX, kFlyConst, true, double>), grid, block, 0, s, J, jsw, y, pc.dev,
+                         pc.t_tile, p->scan, p->flag);
+    }
+    hipLaunchKernelGGL((k_tscan_tiles<NX>), dim3(pc.ninst), dim3(256), 0, s, p->scan, pc.dev);
+    if (pn) {
+      hipLaunchKernelGGL((k_tscan_apply<NX, kFlyPerNode, true, double>), grid, block, 0, s, J, jsw, y, pc.dev,
+                         pc.t_tile, p->scan, out, nullptr);
+    } else {
+      hipLaunchKernelGGL((k_tscan_apply<NX, kFlyConst, true, double>), grid, block, 0, s, J, jsw, y, pc.dev,
+                         pc.t_tile, p->scan, out, nullptr);
+    }
+  } else {
+    (void)p, (void)pc, (void)J, (void)pn, (void)y, (void)out, (void)s;
+  }
+}
+
+hipError_t precond_inverse_t_wave(birk_plan* p, int jac_kind, const double* J, const double* y, double* out,
+                                  hipStream_t s) {
+  const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
+  for (const PinvClass& pc : p->pclass) {
+    if (pc.nx > kWaveNx) continue;
+    BIRK_NX_SWITCH(pc.nx, (pinv_t_class<NXC>(p, pc, J, pn, y, out, s)))
   }
   return hipGetLastError();
 }
