@@ -138,10 +138,11 @@ birk_status birk_plan_tune(birk_plan* plan, char* report, int64_t report_len);
  * same pointers may carry new data; buffers must stay allocated while their triple is in
  * use.  In graph mode birk_krylov_solve also records each chunk of Arnoldi steps it runs
  * (the steps between two host reads of the convergence flags: single steps at first, then
- * 2 and 4 steps on plans shorter than 2^20 elements) the
- * first time a (precision, first step, chunk length, restart, Jacobian pointer and kind,
- * preconditioner) chunk occurs, and replays it afterwards; the Jacobian must stay
- * allocated while such graphs exist (at most 48, all dropped beyond that).  enable = 0
+ * 2 and 4 steps on plans shorter than 2^20 elements) the first time a (precision, first
+ * step, chunk length, restart, Jacobian pointer and kind, preconditioner, P^{-1} formed on
+ * the fly or from the per-node tables cached after the first application) chunk occurs,
+ * and replays it afterwards; the Jacobian must stay allocated while such graphs exist
+ * (at most 48, all dropped beyond that).  enable = 0
  * (the default) drops every recorded graph.  birk_plan_tune drops them too (they hold the
  * old schedule).  Requires a plan created on a non-null stream.  Other entry points are
  * unaffected.  Errors: BIRK_ERR_ARG, BIRK_ERR_UNSUPPORTED (plan on the legacy null
@@ -287,8 +288,8 @@ birk_status birk_krylov_solve(birk_plan* plan, birk_jac_kind jac_kind, const dou
  * by M = blockdiag(H, P H^{-1} P^T) with the Birkhoff preconditioner P = I - B~^a J
  * (B~^a section; P^{-T} by backward substitution), restarted on the true residual in
  * double until ||[f; g] - K [chi; lambda]||_2 <= rtol ||[f; g]||_2 per instance.  The
- * Lanczos, rotation and step scalars stay on the device; the host reads them once per
- * eight iterations.
+ * Lanczos, rotation and step scalars stay on the device; the host reads them after 2, 2
+ * and 4 iterations of a cycle, then once per 8.
  * J: as for birk_krylov_solve.  h: device double, birk_plan_length entries, positive, or
  * NULL for H = I.  f: device double (length as h) or NULL for f = 0.  g: device double.
  * chi (and lam, if not NULL): device double outputs (and the starting point when

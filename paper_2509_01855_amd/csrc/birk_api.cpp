@@ -512,7 +512,7 @@ birk_status birk_precond(birk_plan* p, birk_jac_kind jk, const double* J, const 
     return e == hipSuccess ? BIRK_OK : BIRK_ERR_DEVICE;
   }
   if (inverse) {
-    e = precond_prepare(p, jk, J, p->prec == BIRK_F64 ? 0 : 1, p->stream, 0);
+    e = precond_prepare(p, jk, J, p->prec == BIRK_F64 ? 0 : 1, p->stream, kPrepLarge);
     if (e != hipSuccess) return BIRK_ERR_DEVICE;
   }
   if (p->prec == BIRK_F64) {
@@ -626,7 +626,8 @@ hipError_t seg_norms(birk_plan* p, const double* v, std::vector<double>& out) {
 // preconditioner), t = B^a y, u = z - t, CGS2 against q_0..q_j, q_{j+1} = u / ||u||, and
 // the device update of the Hessenberg column, rotations and g.
 template <typename TK>
-static hipError_t arnoldi_step(birk_plan* p, int jk, const double* J, int j, int m, int use_precond, bool keep_jz) {
+static hipError_t arnoldi_step(birk_plan* p, int jk, const double* J, int j, int m, int use_precond, bool keep_jz,
+                               int cached) {
   const int64_t n = p->total_len;
   hipStream_t s = p->stream;
   TK* Q = (TK*)p->krylov_Q;
@@ -639,7 +640,7 @@ static hipError_t arnoldi_step(birk_plan* p, int jk, const double* J, int j, int
   const TK* uz = qj;
   hipError_t e;
   if (use_precond) {
-    e = precond_inverse<TK>(p, jk, J, qj, z, y, s, p->flag, 1);
+    e = precond_inverse<TK>(p, jk, J, qj, z, y, s, p->flag, cached);
     uz = z;
   } else {
     e = jac_times<TK>(p, jk, J, qj, y, s);
@@ -663,10 +664,10 @@ constexpr size_t kMaxKryGraphs = 48;
 // from a HIP graph recorded the first time this (precision, steps, Jacobian) chunk runs.
 template <typename TK>
 static hipError_t arnoldi_chunk(birk_plan* p, int jk, const double* J, int j0, int k, int m, int use_precond,
-                                bool keep_jz) {
+                                bool keep_jz, int cached) {
   if (!p->use_graphs) {
     for (int j = j0; j < j0 + k; ++j) {
-      const hipError_t e = arnoldi_step<TK>(p, jk, J, j, m, use_precond, keep_jz);
+      const hipError_t e = arnoldi_step<TK>(p, jk, J, j, m, use_precond, keep_jz, cached);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -674,7 +675,7 @@ static hipError_t arnoldi_chunk(birk_plan* p, int jk, const double* J, int j0, i
   const int prec = sizeof(TK) == 8 ? 0 : 1;
   for (const auto& g : p->kgraphs)
     if (g.prec == prec && g.j0 == j0 && g.k == k && g.m == m && g.J == J && g.jk == jk &&
-        g.use_precond == use_precond && g.keep_jz == (int)keep_jz)
+        g.use_precond == use_precond && g.keep_jz == (int)keep_jz && g.cached == cached)
       return hipGraphLaunch(g.exec, p->stream);
   if (p->kgraphs.size() >= kMaxKryGraphs) {
     for (auto& g : p->kgraphs) (void)hipGraphExecDestroy(g.exec);
@@ -683,10 +684,11 @@ static hipError_t arnoldi_chunk(birk_plan* p, int jk, const double* J, int j0, i
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
-  for (int j = j0; j < j0 + k && e == hipSuccess; ++j) e = arnoldi_step<TK>(p, jk, J, j, m, use_precond, keep_jz);
+  for (int j = j0; j < j0 + k && e == hipSuccess; ++j)
+    e = arnoldi_step<TK>(p, jk, J, j, m, use_precond, keep_jz, cached);
   const hipError_t e2 = hipStreamEndCapture(p->stream, &graph);
   if (e == hipSuccess) e = e2;
-  birk_plan::KryGraph kg{prec, j0, k, m, J, jk, use_precond, (int)keep_jz, nullptr};
+  birk_plan::KryGraph kg{prec, j0, k, m, J, jk, use_precond, (int)keep_jz, cached, nullptr};
   if (e == hipSuccess) e = hipGraphInstantiate(&kg.exec, graph, nullptr, nullptr, 0);
   if (graph) (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return e;
@@ -703,7 +705,7 @@ static hipError_t arnoldi_chunk(birk_plan* p, int jk, const double* J, int j0, i
 template <typename TK>
 birk_status gmres_cycle(birk_plan* p, int jk, const double* J, const double* r, double* chi, double* jchi,
                         std::vector<InstState>& st, const std::vector<double>& tol_inner, int m, int use_precond,
-                        int& budget) {
+                        int& budget, int& pinv_state) {
   const int B = (int)p->inst.size();
   const int64_t n = p->total_len;
   hipStream_t s = p->stream;
@@ -742,8 +744,15 @@ birk_status gmres_cycle(birk_plan* p, int jk, const double* J, const double* r, 
   while (j < m && budget > 0) {
     const int want = (!small || checks < 3) ? 1 : checks < 4 ? 2 : 4;
     const int k = std::min(want, std::min(m - j, budget));
-    e = arnoldi_chunk<TK>(p, jk, J, j, k, m, use_precond, Yb != nullptr);
+    // the first P^{-1} of the solve forms K_k on the fly; per-node H_k are cached (one
+    // preparation pass, outside any recorded chunk) before the second
+    if (use_precond && pinv_state == 1) {
+      if (precond_prepare(p, jk, J, sizeof(TK) == 4 ? 1 : 0, s, kPrepCache) != hipSuccess) return BIRK_ERR_DEVICE;
+      pinv_state = 2;
+    }
+    e = arnoldi_chunk<TK>(p, jk, J, j, k, m, use_precond, Yb != nullptr, pinv_state == 2 ? 1 : 0);
     if (e != hipSuccess) return BIRK_ERR_DEVICE;
+    if (pinv_state == 0) pinv_state = 1;
     j += k;
     budget -= k;
     ++checks;
@@ -815,7 +824,12 @@ extern "C" birk_status birk_krylov_solve(birk_plan* p, birk_jac_kind jk, const d
   hipError_t e = ensure_krylov(p, o.restart, mixed ? sizeof(float) : sizeof(double));
   if (e != hipSuccess) return dev_err(e);
   if (hipMemsetAsync(p->flag, 0, sizeof(int), s) != hipSuccess) return BIRK_ERR_DEVICE;
-  if (o.use_precond && precond_prepare(p, jk, J, mixed ? 1 : 0, s, 1) != hipSuccess) return BIRK_ERR_DEVICE;
+  // P^{-1} applications so far: 0, 1, or 2 = several (per-node H_k cached).  Mixed plans
+  // cache the float H_k at once: their staged double J reads cost more than a float table.
+  int pinv_state = mixed ? 2 : 0;
+  if (o.use_precond && precond_prepare(p, jk, J, mixed ? 1 : 0, s, mixed ? kPrepLarge | kPrepCache : kPrepLarge) !=
+                           hipSuccess)
+    return BIRK_ERR_DEVICE;
   if (!o.use_x0 && hipMemsetAsync(chi, 0, n * sizeof(double), s) != hipSuccess) return BIRK_ERR_DEVICE;
 
   std::vector<InstState> st(B);
@@ -887,8 +901,10 @@ extern "C" birk_status birk_krylov_solve(birk_plan* p, birk_jac_kind jk, const d
       st[i].breakdown_last = st[i].status == BIRK_ERR_BREAKDOWN;
       if (st[i].status == BIRK_ERR_BREAKDOWN) st[i].status = BIRK_OK;
     }
-    birk_status cs = mixed ? gmres_cycle<float>(p, jk, J, rcur, chi, nullptr, st, tol, o.restart, o.use_precond, budget)
-                           : gmres_cycle<double>(p, jk, J, rcur, chi, jchi, st, tol, o.restart, o.use_precond, budget);
+    birk_status cs = mixed ? gmres_cycle<float>(p, jk, J, rcur, chi, nullptr, st, tol, o.restart, o.use_precond, budget,
+                                                pinv_state)
+                           : gmres_cycle<double>(p, jk, J, rcur, chi, jchi, st, tol, o.restart, o.use_precond, budget,
+                                                 pinv_state);
     if (cs == BIRK_ERR_SINGULAR || cs == BIRK_ERR_DEVICE) {
       result = cs;
       for (int i = 0; i < B; ++i) st[i].done = true;

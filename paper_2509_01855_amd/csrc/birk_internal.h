@@ -268,7 +268,7 @@ struct birk_plan {
   struct KryGraph {
     int prec, j0, k, m;
     const double* J;
-    int jk, use_precond, keep_jz;
+    int jk, use_precond, keep_jz, cached;
     hipGraphExec_t exec;
   };
   std::vector<KryGraph> kgraphs;
@@ -332,7 +332,7 @@ hipError_t jac_times(birk_plan* p, int jac_kind, const double* J, const T* x, T*
 template <typename T>
 hipError_t precond_forward(birk_plan* p, int jac_kind, const double* J, const T* y, T* out,
                            hipStream_t s);
-// cached = 1: per-node H_k laid out by precond_prepare(..., repeated = 1) for this J.
+// cached = 1: per-node H_k laid out by precond_prepare(..., kPrepCache) for this J.
 template <typename T>
 hipError_t precond_inverse(birk_plan* p, int jac_kind, const double* J, const T* y, T* out,
                            T* jout, hipStream_t s, int* flag, int cached);
@@ -346,11 +346,13 @@ int64_t pinv_jsw_size(int64_t Nn, int nx);
 // and the weights exist); allocations are recorded in p->allocs.
 hipError_t plan_solve(birk_plan* p);
 // Per-J preparation of the inverse scan; must precede precond_inverse whenever J changes.
-// n_x > 8: H_k in the level-0 slots, always.  n_x <= 8: with repeated = 1 and per-node J,
-// H_k in the tile layout (read by precond_inverse with cached = 1); nothing otherwise.
+// kPrepLarge: n_x > 8 lay H_k out in the level-0 slots (always needed there).
+// kPrepCache: n_x <= 8 with per-node J lay H_k out in the tile layout, read by
+// precond_inverse with cached = 1 (worth it from the second application with one J).
 // single = 1 lays the data out in float (for precond_inverse<float>), else in double.
+constexpr int kPrepLarge = 1, kPrepCache = 2;
 hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s,
-                           int repeated);
+                           int what);
 
 // Krylov BLAS-1 launchers (birk_solve.hip).  Reductions accumulate in double.
 constexpr int kKryMaxDots = 32;

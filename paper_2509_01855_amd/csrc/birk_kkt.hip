@@ -717,12 +717,12 @@ static hipError_t kkt_apply(birk_plan* p, int jk, const double* J, const double*
 
 // M^{-1} [r1; r2] = [r1 / h; P^{-T}(h * P^{-1} r2)] (P^{-1} prepared for J)
 static hipError_t kkt_prec(birk_plan* p, int jk, const double* J, const double* h, const double* r, double* z,
-                           double* scr, int use_precond, hipStream_t s) {
+                           double* scr, int use_precond, int cached, hipStream_t s) {
   const int64_t n = p->total_len;
   if (!use_precond) return hipMemcpyAsync(z, r, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s);
   hipLaunchKernelGGL(k_hscale, dim3(nb256(n)), dim3(256), 0, s, r, h, z, n, 1);
   double* t0 = (double*)p->tmp_vec[0];
-  hipError_t e = precond_inverse<double>(p, jk, J, r + n, t0, nullptr, s, nullptr, 1);
+  hipError_t e = precond_inverse<double>(p, jk, J, r + n, t0, nullptr, s, nullptr, cached);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_hscale, dim3(nb256(n)), dim3(256), 0, s, t0, h, t0, n, 0);
   return precond_inverse_t(p, jk, J, t0, z + n, scr, s);
@@ -754,8 +754,20 @@ birk_status kkt_solve(birk_plan* p, int jk, const double* J, const double* h, co
   } else if (e == hipSuccess) {
     e = hipMemsetAsync(b.x, 0, 2 * n * sizeof(double), s);
   }
-  if (e == hipSuccess && o->use_precond) e = precond_prepare(p, jk, J, 0, s, 1);
+  if (e == hipSuccess && o->use_precond) e = precond_prepare(p, jk, J, 0, s, kPrepLarge);
   if (e != hipSuccess) return BIRK_ERR_DEVICE;
+  // the first preconditioner application forms K_k on the fly; per-node H_k are cached
+  // before the second
+  int napp = 0;
+  auto prec = [&](const double* r, double* z) -> hipError_t {
+    if (o->use_precond && napp == 1) {
+      const hipError_t ee = precond_prepare(p, jk, J, 0, s, kPrepCache);
+      if (ee != hipSuccess) return ee;
+    }
+    const int cached = napp >= 1 ? 1 : 0;
+    ++napp;
+    return kkt_prec(p, jk, J, h, r, z, p->bt_scr, o->use_precond, cached, s);
+  };
   std::vector<double> hst((size_t)B * kSt), bn(B), rn(B), tolv(B);
   std::vector<int> run(B, 1), status(B, BIRK_OK), inner(B, 0), outer(B, 0);
   std::vector<char> done(B, 0);
@@ -769,6 +781,9 @@ birk_status kkt_solve(birk_plan* p, int jk, const double* J, const double* h, co
   };
   if (norms(b.rhs, bn) != hipSuccess) return BIRK_ERR_DEVICE;
   int budget = o->max_iter;
+  // iterations between host reads of the convergence state: 2, 2, 4, then 8 per cycle
+  // (the preconditioned counts are small, and an iteration past convergence costs a
+  // whole operator and preconditioner application)
   constexpr int kChunkIts = 8;
   birk_status result = BIRK_OK;
   for (int cycle = 0;; ++cycle) {
@@ -804,7 +819,7 @@ birk_status kkt_solve(birk_plan* p, int jk, const double* J, const double* h, co
     if (e == hipSuccess) e = hipMemsetAsync(b.w1, 0, 2 * n * sizeof(double), s);
     if (e == hipSuccess) e = hipMemcpyAsync(b.tol, tolv.data(), B * sizeof(double), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(b.run, run.data(), B * sizeof(int), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = kkt_prec(p, jk, J, h, b.r1, b.y, p->bt_scr, o->use_precond, s);
+    if (e == hipSuccess) e = prec(b.r1, b.y);
     if (e != hipSuccess) return BIRK_ERR_DEVICE;
     hipLaunchKernelGGL(k_kv_dot, dim3(nt2), dim3(256), 0, s, b.r1, b.y, b.part, sg);
     hipLaunchKernelGGL(k_kv_reduce, dim3(B), dim3(64), 0, s, b.part, p->seg.ranges, sg.ntiles, b.dot);
@@ -812,8 +827,11 @@ birk_status kkt_solve(birk_plan* p, int jk, const double* J, const double* h, co
     // w: w_{k-1}, w1: w_{k-2}
     double *r1 = b.r1, *r2 = b.r2, *y = b.y, *w = b.w, *w1 = b.w1;
     bool cycle_done = false;
+    int chunk_no = 0;
     while (!cycle_done && budget > 0) {
-      const int its = std::min(kChunkIts, budget);
+      const int want = chunk_no < 2 ? 2 : chunk_no < 3 ? 4 : kChunkIts;
+      ++chunk_no;
+      const int its = std::min(want, budget);
       for (int k = 0; k < its; ++k) {
         hipLaunchKernelGGL(k_mr_pre, dim3(ib), dim3(64), 0, s, b.st, B);
         // v = y / beta
@@ -833,7 +851,7 @@ birk_status kkt_solve(birk_plan* p, int jk, const double* J, const double* h, co
         r2 = y;
         y = t;
         // y = M^{-1} r2; beta = sqrt(r2 . y)
-        if (kkt_prec(p, jk, J, h, r2, y, p->bt_scr, o->use_precond, s) != hipSuccess) return BIRK_ERR_DEVICE;
+        if (prec(r2, y) != hipSuccess) return BIRK_ERR_DEVICE;
         hipLaunchKernelGGL(k_kv_dot, dim3(nt2), dim3(256), 0, s, r2, y, b.part, sg);
         hipLaunchKernelGGL(k_kv_reduce, dim3(B), dim3(64), 0, s, b.part, p->seg.ranges, sg.ntiles, b.dot);
         hipLaunchKernelGGL(k_mr_givens, dim3(ib), dim3(64), 0, s, b.st, b.dot, B);

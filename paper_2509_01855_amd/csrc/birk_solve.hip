@@ -1516,15 +1516,15 @@ hipError_t plan_solve(birk_plan* p) {
 }
 
 template <int NX, typename JT>
-static void make_h_class(birk_plan* p, const PinvClass& pc, const double* J, int pn, int repeated, hipStream_t s) {
+static void make_h_class(birk_plan* p, const PinvClass& pc, const double* J, int pn, int what, hipStream_t s) {
   if constexpr (NX <= kWaveNx) {
     // per-node J applied repeatedly: H_k cached in the tile layout; otherwise the scan
     // kernels form K_k from J and w_k themselves
-    if (pn && repeated)
+    if (pn && (what & kPrepCache))
       hipLaunchKernelGGL((k_tmake_h<NX, JT>), dim3(pc.n_tile), dim3(kTileThreads), 0, s, (JT*)p->jsw, J, pn, pc.dev,
                          pc.t_tile, p->flag);
   } else {
-    (void)repeated;
+    if (!(what & kPrepLarge)) return;
     if (pc.n_swz[pn] == 0) return;
     hipLaunchKernelGGL(k_swizzle_nodes<JT>, dim3(pc.n_swz[pn]), dim3(256), 0, s, J, pn, pc.nx, pc.dev, pc.t_swz[pn],
                        (JT*)p->jsw);
@@ -1552,16 +1552,17 @@ static void make_h_class(birk_plan* p, const PinvClass& pc, const double* J, int
 
 // Per-Jacobian preparation of the scan: n_x > kWaveNx lay J and w out in the level-0
 // slots and replace the J fields by H_k (k_make_h_rows), which their scan kernels read.
-// n_x <= kWaveNx with per-node J and repeated = 1 (a solve) cache H_k in the tile layout
-// (k_tmake_h: one pass that turns the later applications' strided J reads and per-node
-// factorisations into coalesced H_k reads); otherwise they need nothing.
-hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s, int repeated) {
+// n_x <= kWaveNx with per-node J and kPrepCache (a solve, before its second application)
+// cache H_k in the tile layout (k_tmake_h: one pass that turns the later applications'
+// staged J reads and per-node factorisations into coalesced H_k reads); otherwise they
+// need nothing.  what: kPrepLarge, kPrepCache or both.
+hipError_t precond_prepare(birk_plan* p, int jac_kind, const double* J, int single, hipStream_t s, int what) {
   const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
   for (const PinvClass& pc : p->pclass) {
     if (single) {
-      BIRK_NX_SWITCH(pc.nx, (make_h_class<NXC, float>(p, pc, J, pn, repeated, s)))
+      BIRK_NX_SWITCH(pc.nx, (make_h_class<NXC, float>(p, pc, J, pn, what, s)))
     } else {
-      BIRK_NX_SWITCH(pc.nx, (make_h_class<NXC, double>(p, pc, J, pn, repeated, s)))
+      BIRK_NX_SWITCH(pc.nx, (make_h_class<NXC, double>(p, pc, J, pn, what, s)))
     }
   }
   return hipGetLastError();
@@ -1622,8 +1623,8 @@ hipError_t precond_inverse(birk_plan* p, int jac_kind, const double* J, const T*
                            hipStream_t s, int* flag, int cached) {
   // n_x <= 8: K_k formed from J and factored inside the scan kernels (pivot checks into
   // the plan's flag), or, per-node J with cached = 1, the H_k that precond_prepare laid
-  // out with repeated = 1; larger n_x read the H_k that precond_prepare laid out for this
-  // J (checking the pivots there)
+  // out with kPrepCache; larger n_x read the H_k that precond_prepare laid out for this
+  // J with kPrepLarge (checking the pivots there)
   (void)flag;
   const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
   for (const PinvClass& pc : p->pclass) {
