@@ -1286,21 +1286,35 @@ __global__ __launch_bounds__(256) void k_pinv_final_lanes(const T* __restrict__ 
   double s = act ? scan[d.st[0] + swz(B, i, rr, NX, l)] : 0.0;
   const int64_t k0 = c * kChunk;
   const int jn = (int)min((int64_t)kChunk, Nn - k0);
+  // row r of H_k, w_k and y_k of the next node are loaded while the current node is
+  // replayed (the replay itself waits on the carried state)
+  double hn[NX], wn = 1.0, yn = 0.0;
+  auto fetch = [&](int j) {
+    const T* base = js + (int64_t)j * E * 64;
+#pragma unroll
+    for (int q = 0; q < NX; ++q) hn[q] = act ? (double)base[(rr * NX + q) * 64] : 0.0;
+    wn = (double)base[(E - 1) * 64];
+    yn = act ? (double)yi[(int64_t)rr * Nn + k0 + j] : 0.0;
+  };
+  if (jn > 0) fetch(0);
 #pragma unroll 1
   for (int j = 0; j < jn; ++j) {
     const int64_t k = k0 + j;
-    const T* base = js + (int64_t)j * E * 64;
-    const double inv_w = 1.0 / (double)base[(E - 1) * 64];
-    const double u = s + (act ? (double)yi[(int64_t)rr * Nn + k] : 0.0);
+    double h[NX];
+#pragma unroll
+    for (int q = 0; q < NX; ++q) h[q] = hn[q];
+    const double wk = wn;
+    const double u = s + yn;
+    if (j + 1 < jn) fetch(j + 1);
     double v = 0.0;
     static_for<0, NX>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      v += (act ? (double)base[(rr * NX + q) * 64] : 0.0) * row_bcast<q>(u);
+      v += h[q] * row_bcast<q>(u);
     });
     s += v;
     if (act) {
       oi[(int64_t)r * Nn + k] = (T)(u + 0.5 * v);
-      if (ji) ji[(int64_t)r * Nn + k] = (T)(v * inv_w);
+      if (ji) ji[(int64_t)r * Nn + k] = (T)(v * recip(wk));
     }
   }
 }
