@@ -162,9 +162,6 @@ struct PinvClass {
   int n_up[kPinvMaxLevels] = {};
   int2* t_upc[kPinvMaxLevels] = {};          // (k, block of 64 parents) of the column-wise up-sweep
   int n_upc[kPinvMaxLevels] = {};
-  int2* t_swz[2] = {nullptr, nullptr};       // (k, block * E + field) of the layout pass [constant J, per node];
-                                             // [0] is also the (k, B kFan + i) list of level-0 slot blocks
-  int n_swz[2] = {0, 0};
   int2* t_nodes = nullptr;                   // (k, block of 256 nodes): J x
   int n_nodes = 0;
   int2* t_tile = nullptr;                    // (k, tile) of the wave-scan path

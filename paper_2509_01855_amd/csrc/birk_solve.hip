@@ -294,41 +294,41 @@ __device__ __forceinline__ int64_t swz(int64_t B, int i, int field, int nfield, 
   return (((B * kFan + i) * nfield) + field) * 64 + l;
 }
 
-// Swizzle per-node data for the level-0 kernels.  E = nx^2 + 1 fields per node: fields
-// e < nx^2 take J entry e at the node (per-node Jacobians only; k_make_h_rows then replaces
-// them by H_k), the last field is w_k.  Node k -> chunk c = k / kChunk, j = k % kChunk;
-// g = c / kFan, i = c % kFan; B = g / 64, l = g % 64; stored at
-// jsw[(((B kFan + i) kChunk + j) E + e) 64 + l].  Nodes past N_n are zero.  One
-// workgroup per (B, i, e): for each of the 64 lanes l it reads the kChunk consecutive
-// nodes of chunk (64 B + l) kFan + i, and writes kChunk rows of 64 consecutive lanes,
-// transposing through LDS.  tile = (k, (B kFan + i) nf + f) with nf = E fields written
-// for per-node J, nf = 1 (the weights) for constant J.
-template <typename JT>
-__global__ __launch_bounds__(256) void k_swizzle_nodes(const double* __restrict__ J, int per_node, int nx,
-                                                       const PinvDesc* __restrict__ pd,
-                                                       const int2* __restrict__ tiles, JT* __restrict__ jsw) {
-  __shared__ double tile[64][kChunk + 1];
-  const int2 t = tiles[blockIdx.x];
-  const PinvDesc& d = pd[t.x];
-  const int E = nx * nx + 1;
-  const int nf = per_node ? E : 1;
-  const int f = t.y % nf;
-  const int e = per_node ? f : E - 1;
-  const int bx = t.y / nf;
-  const int i = bx % kFan;
-  const int64_t B = bx / kFan;
-  const int64_t Nn = d.Nn;
-  const double* src = (e == E - 1) ? d.w : J + d.joff + (int64_t)e * Nn;
-  JT* dst = jsw + d.jsw_off;
-  for (int q = threadIdx.x; q < 64 * kChunk; q += blockDim.x) {
-    const int l = q / kChunk, j = q % kChunk;
-    const int64_t k = (((B * 64 + l) * kFan + i) * kChunk) + j;
-    tile[l][j] = (k < Nn) ? src[k] : 0.0;
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < 64 * kChunk; q += blockDim.x) {
-    const int l = q & 63, j = q >> 6;
-    dst[((((B * kFan + i) * kChunk) + j) * E + e) * 64 + l] = (JT)tile[l][j];
+// Per-node tables of the level-0 kernels: node k -> chunk c = k / kChunk, j = k % kChunk;
+// g = c / kFan, i = c % kFan; B = g / 64, l = g % 64; slot sigma = (B kFan + i) 64 + l.
+// Node j of slot sigma keeps row-major H_k (NX^2 values) then w_k in a record of
+// hrec<NX>() values (a multiple of four, so that the rows start 16-byte aligned for
+// doubles with NX even and for floats with NX a multiple of four) at
+// jsw[(sigma kChunk + j) hrec].  A lane holding row r of a chunk's state reads the NX
+// contiguous values of row r of H_k; the sixteen lanes of a chunk read one record.
+template <int NX>
+__host__ __device__ constexpr int hrec() { return (NX * NX + 1 + 3) & ~3; }
+
+// Row r of H_k (NX values at p) into registers; 16-byte loads where every row is 16-byte
+// aligned (records are multiples of four values).
+template <int NX, typename T>
+__device__ __forceinline__ void load_row(const T* __restrict__ p, double (&h)[NX]) {
+  if constexpr (sizeof(T) == 8 && (NX % 2) == 0) {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int q = 0; q < NX; q += 2) {
+      const v2 v = *reinterpret_cast<const v2*>(p + q);
+      h[q] = v.x;
+      h[q + 1] = v.y;
+    }
+  } else if constexpr (sizeof(T) == 4 && (NX % 4) == 0) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int q = 0; q < NX; q += 4) {
+      const v4 v = *reinterpret_cast<const v4*>(p + q);
+      h[q] = v.x;
+      h[q + 1] = v.y;
+      h[q + 2] = v.z;
+      h[q + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NX; ++q) h[q] = (double)p[q];
   }
 }
 
@@ -336,8 +336,8 @@ __global__ __launch_bounds__(256) void k_swizzle_nodes(const double* __restrict_
 // Everything the scan needs follows from H_k:  K_k^{-1} = I + H_k / 2, so for
 // u = y_k + S_k
 //     xi_k = u + H_k u / 2,   J_k xi_k = H_k u / w_k,   S_{k+1} = S_k + H_k u,
-// and the affine map of the node is S -> (I + H_k) S + H_k y_k.  H_k is written over the
-// J fields of the node's level-0 slot (in place; constant J: into the empty fields).
+// and the affine map of the node is S -> (I + H_k) S + H_k y_k.  H_k and w_k go to the
+// node's record (J, per node or constant, and w are read where they are).
 // Sixteen lanes per chunk: lane r < NX holds row r of [K_k | w_k J_k] and Gauss-Jordan
 // elimination without pivoting, the pivot row broadcast across the sixteen lanes, turns
 // it into [I | K_k^{-1} w_k J_k]; its pivots are those of the unpivoted LU, and one that
@@ -358,21 +358,23 @@ __global__ __launch_bounds__(256) void k_make_h_rows(JT* __restrict__ jsw, const
   const int l = (int)(tau & 63);
   const int64_t c = (B * 64 + l) * kFan + i;
   if (c >= d.cnt[0]) return;  // the whole group leaves together
-  constexpr int E = NX * NX + 1;
+  constexpr int E = hrec<NX>();
   const double* Jc = J + d.jcoff;
-  JT* js = jsw + d.jsw_off + ((B * kFan + i) * kChunk) * E * 64 + l;
+  const double* Jn = J + d.joff;
+  JT* js = jsw + d.jsw_off + (((B * kFan + i) * 64 + l) * kChunk) * E;
   const int jn = (int)min((int64_t)kChunk, d.Nn - c * kChunk);
   const bool act = r < NX;
   const int rr = act ? r : 0;
 #pragma unroll 1
   for (int j = 0; j < jn; ++j) {
-    JT* base = js + (int64_t)j * E * 64;
-    const double wk = (double)base[(E - 1) * 64];
+    JT* base = js + (int64_t)j * E;
+    const int64_t k = c * kChunk + j;
+    const double wk = d.w[k];
     double Kr[NX], Xr[NX];
     double jm = 0.0;
 #pragma unroll
     for (int q = 0; q < NX; ++q) {
-      const double jv = act ? (per_node ? (double)base[(rr * NX + q) * 64] : Jc[rr * NX + q]) : 0.0;
+      const double jv = act ? (per_node ? Jn[(int64_t)(rr * NX + q) * d.Nn + k] : Jc[rr * NX + q]) : 0.0;
       jm = fmax(jm, fabs(jv));
       Xr[q] = wk * jv;
       Kr[q] = (r == q ? 1.0 : 0.0) - 0.5 * wk * jv;
@@ -405,8 +407,9 @@ __global__ __launch_bounds__(256) void k_make_h_rows(JT* __restrict__ jsw, const
     });
     if (act) {
 #pragma unroll
-      for (int q = 0; q < NX; ++q) base[(r * NX + q) * 64] = (JT)Xr[q];
+      for (int q = 0; q < NX; ++q) base[r * NX + q] = (JT)Xr[q];
     }
+    if (r == 0) base[NX * NX] = (JT)wk;
   }
 }
 
@@ -421,75 +424,61 @@ struct ColGroups {
 };
 
 // Level-0 up-sweep: each chunk of kChunk nodes is reduced to (A, b) with
-// S_out = A S_in + b by the node maps S -> (I + H_k) S + H_k y_k: column c < NX of A
-// starts at e_c and takes col <- col + H_k col, b starts at 0 and takes
-// col <- col + H_k (col + y_k).  G = ColGroups<NX>::count neighbouring lanes share a
-// chunk, lane g carrying column group g, so each H_k entry is fetched once for the G
-// lanes.  grid = (tile (k, block of 256 level-0 threads), G): block y of a tile takes
-// slots tau = 256 t + (256 / G) y + threadIdx.x / G.
+// S_out = A S_in + b by the node maps S -> (I + H_k) S + H_k y_k, sixteen lanes per chunk
+// with lane r < NX holding row r of A and b: from A = I, b = 0 each node takes
+//     A <- A + H_k A,   b <- b + H_k (b + y_k),
+// row r of H_k read contiguously from the node's record and the rows of A and of
+// b + y_k broadcast across the sixteen lanes (DPP row_newbcast).
+// grid = (tile (k, block of 256 level-0 threads), 16 groups of 16 chunks).
 template <int NX, typename T>
 __global__ __launch_bounds__(256) void k_pinv_up0(const T* __restrict__ jsw, const T* __restrict__ y,
                                                   const PinvDesc* __restrict__ pd, const int2* __restrict__ tiles,
                                                   double* __restrict__ scan) {
-  constexpr int PER = ColGroups<NX>::per;
-  constexpr int G = ColGroups<NX>::count;
+  static_assert(NX <= 16, "one row per lane of a 16-lane group");
+  constexpr int E = hrec<NX>();
+  constexpr int F = NX * NX + NX;
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
-  const int64_t tau = (int64_t)t.y * 256 + (int64_t)blockIdx.y * (256 / G) + threadIdx.x / G;
+  const int64_t tau = (int64_t)t.y * 256 + blockIdx.y * 16 + (threadIdx.x >> 4);
+  const int r = (int)(threadIdx.x & 15);
   const int64_t B = tau / (64 * kFan);
   const int i = (int)((tau >> 6) % kFan);
   const int l = (int)(tau & 63);
   const int64_t ch = (B * 64 + l) * kFan + i;
-  if (ch >= d.cnt[0]) return;
-  const int c0 = (int)(threadIdx.x % G) * PER;
-  constexpr int E = NX * NX + 1;
-  constexpr int F = NX * NX + NX;
+  if (ch >= d.cnt[0]) return;  // the whole group leaves together
+  const bool act = r < NX;
+  const int rr = act ? r : 0;
   const int64_t Nn = d.Nn;
-  const T* js = jsw + d.jsw_off + ((B * kFan + i) * kChunk) * E * 64 + l;
-  const T* yi = y + d.off;
-  double col[PER][NX];
+  const T* hs = jsw + d.jsw_off + (((B * kFan + i) * 64 + l) * kChunk) * E + rr * NX;
+  const T* yi = y + d.off + (int64_t)rr * Nn;
+  double a[NX], b = 0.0;
 #pragma unroll
-  for (int p = 0; p < PER; ++p)
-#pragma unroll
-    for (int r = 0; r < NX; ++r) col[p][r] = (r == c0 + p) ? 1.0 : 0.0;
+  for (int c = 0; c < NX; ++c) a[c] = (act && c == r) ? 1.0 : 0.0;
   const int64_t k0 = ch * kChunk;
   const int jn = (int)min((int64_t)kChunk, Nn - k0);
 #pragma unroll 1
   for (int j = 0; j < jn; ++j) {
-    const T* base = js + (int64_t)j * E * 64;
-    double u[PER][NX];
+    double h[NX];
+    load_row<NX, T>(hs + (int64_t)j * E, h);  // lanes r >= NX read row 0 (in bounds), unused
+    const double u = b + (act ? (double)yi[k0 + j] : 0.0);
+    double na[NX], nb = b;
 #pragma unroll
-    for (int p = 0; p < PER; ++p)
+    for (int c = 0; c < NX; ++c) na[c] = a[c];
+    static_for<0, NX>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      nb += h[q] * row_bcast<q>(u);
 #pragma unroll
-      for (int r = 0; r < NX; ++r) u[p][r] = col[p][r];
+      for (int c = 0; c < NX; ++c) na[c] += h[q] * row_bcast<q>(a[c]);
+    });
 #pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      if (c0 + p == NX) {
-#pragma unroll
-        for (int r = 0; r < NX; ++r) u[p][r] += (double)yi[(int64_t)r * Nn + k0 + j];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      double h[NX];
-#pragma unroll
-      for (int q = 0; q < NX; ++q) h[q] = (double)base[(r * NX + q) * 64];
-#pragma unroll
-      for (int p = 0; p < PER; ++p) {
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < NX; ++q) acc += h[q] * u[p][q];
-        col[p][r] += acc;
-      }
-    }
+    for (int c = 0; c < NX; ++c) a[c] = na[c];
+    b = nb;
   }
-  double* agg = scan + d.agg[0];
+  if (act) {
+    double* agg = scan + d.agg[0];
 #pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int c = c0 + p;
-    if (c > NX) break;
-#pragma unroll
-    for (int r = 0; r < NX; ++r) agg[swz(B, i, (c < NX) ? r * NX + c : NX * NX + r, F, l)] = col[p][r];
+    for (int c = 0; c < NX; ++c) agg[swz(B, i, r * NX + c, F, l)] = a[c];
+    agg[swz(B, i, NX * NX + r, F, l)] = b;
   }
 }
 
@@ -1275,11 +1264,11 @@ __global__ __launch_bounds__(256) void k_pinv_final_lanes(const T* __restrict__ 
   const int l = (int)(tau & 63);
   const int64_t c = (B * 64 + l) * kFan + i;
   if (c >= d.cnt[0]) return;  // the whole group leaves together
-  constexpr int E = NX * NX + 1;
+  constexpr int E = hrec<NX>();
   const int64_t Nn = d.Nn;
   const bool act = r < NX;
   const int rr = act ? r : 0;
-  const T* js = jsw + d.jsw_off + ((B * kFan + i) * kChunk) * E * 64 + l;
+  const T* js = jsw + d.jsw_off + (((B * kFan + i) * 64 + l) * kChunk) * E;
   const T* yi = y + d.off;
   T* oi = out + d.off;
   T* ji = jout ? jout + d.off : nullptr;
@@ -1290,10 +1279,13 @@ __global__ __launch_bounds__(256) void k_pinv_final_lanes(const T* __restrict__ 
   // replayed (the replay itself waits on the carried state)
   double hn[NX], wn = 1.0, yn = 0.0;
   auto fetch = [&](int j) {
-    const T* base = js + (int64_t)j * E * 64;
+    const T* base = js + (int64_t)j * E;
+    load_row<NX, T>(base + rr * NX, hn);
+    if (!act) {
 #pragma unroll
-    for (int q = 0; q < NX; ++q) hn[q] = act ? (double)base[(rr * NX + q) * 64] : 0.0;
-    wn = (double)base[(E - 1) * 64];
+      for (int q = 0; q < NX; ++q) hn[q] = 0.0;
+    }
+    wn = (double)base[NX * NX];
     yn = act ? (double)yi[(int64_t)rr * Nn + k0 + j] : 0.0;
   };
   if (jn > 0) fetch(0);
@@ -1371,7 +1363,7 @@ int64_t pinv_jsw_size(int64_t Nn, int nx) {
   if (nx <= kWaveNx) return pinv_tiles(Nn) * kTileNodes * ((int64_t)nx * nx + 1);
   int64_t cnt[kPinvMaxLevels];
   pinv_levels(Nn, cnt);
-  return pinv_blocks0(cnt[0]) * 64 * kFan * kChunk * ((int64_t)nx * nx + 1);
+  return pinv_blocks0(cnt[0]) * 64 * kFan * kChunk * (((int64_t)nx * nx + 4) & ~int64_t(3));  // hrec<nx>()
 }
 
 // Scratch (doubles) the inverse scan needs for one instance (level 0 in whole blocks).
@@ -1453,7 +1445,7 @@ hipError_t plan_solve(birk_plan* p) {
     }
     if (pc.host.empty()) continue;
     pc.ninst = (int)pc.host.size();
-    std::vector<int2> t0, tn, tt, tsw[2], tup[kPinvMaxLevels], tupc[kPinvMaxLevels];
+    std::vector<int2> t0, tn, tt, tup[kPinvMaxLevels], tupc[kPinvMaxLevels];
     for (int k = 0; k < pc.ninst; ++k) {
       const PinvDesc& d = pc.host[k];
       if (nx <= kWaveNx) {
@@ -1464,11 +1456,6 @@ hipError_t plan_solve(birk_plan* p) {
       const int64_t thr0 = (int64_t)d.nb0 * 64 * kFan;
       for (unsigned b = 0; b < nblocks(thr0, 256); ++b) t0.push_back(make_int2(k, (int)b));
       for (unsigned b = 0; b < nblocks(d.Nn, 256); ++b) tn.push_back(make_int2(k, (int)b));
-      for (int pn = 0; pn < 2; ++pn) {
-        const int E = pn ? nx * nx + 1 : 1;
-        for (int64_t bx = 0; bx < (int64_t)d.nb0 * kFan; ++bx)
-          for (int f = 0; f < E; ++f) tsw[pn].push_back(make_int2(k, (int)(bx * E + f)));
-      }
       for (int l = 0; l < d.L; ++l) {
         for (unsigned b = 0; b < nblocks(d.cnt[l + 1], 256); ++b) tup[l].push_back(make_int2(k, (int)b));
         for (unsigned b = 0; b < nblocks(d.cnt[l + 1], 64); ++b) tupc[l].push_back(make_int2(k, (int)b));
@@ -1486,10 +1473,6 @@ hipError_t plan_solve(birk_plan* p) {
     pc.n_nodes = (int)tn.size();
     if ((e = upload_tiles(p, tt, &pc.t_tile)) != hipSuccess) return e;
     pc.n_tile = (int)tt.size();
-    for (int pn = 0; pn < 2; ++pn) {
-      if ((e = upload_tiles(p, tsw[pn], &pc.t_swz[pn])) != hipSuccess) return e;
-      pc.n_swz[pn] = (int)tsw[pn].size();
-    }
     for (int l = 0; l < pc.Lmax; ++l) {
       if ((e = upload_tiles(p, tup[l], &pc.t_up[l])) != hipSuccess) return e;
       pc.n_up[l] = (int)tup[l].size();
@@ -1538,10 +1521,7 @@ static void make_h_class(birk_plan* p, const PinvClass& pc, const double* J, int
       hipLaunchKernelGGL((k_tmake_h<NX, JT>), dim3(pc.n_tile), dim3(kTileThreads), 0, s, (JT*)p->jsw, J, pn, pc.dev,
                          pc.t_tile, p->flag);
   } else {
-    if (!(what & kPrepLarge)) return;
-    if (pc.n_swz[pn] == 0) return;
-    hipLaunchKernelGGL(k_swizzle_nodes<JT>, dim3(pc.n_swz[pn]), dim3(256), 0, s, J, pn, pc.nx, pc.dev, pc.t_swz[pn],
-                       (JT*)p->jsw);
+    if (!(what & kPrepLarge) || pc.n_node0 == 0) return;
     hipLaunchKernelGGL((k_make_h_rows<NX, JT>), dim3(pc.n_node0, 16), dim3(256), 0, s, (JT*)p->jsw, J, pn, pc.dev,
                        pc.t_node0, p->flag);
   }
@@ -1615,7 +1595,7 @@ static void pinv_class(birk_plan* p, const PinvClass& pc, const double* J, int p
     (void)pn;
     (void)cached;
     constexpr int ncg = ColGroups<NX>::count;
-    hipLaunchKernelGGL((k_pinv_up0<NX, T>), dim3(pc.n_node0, ncg), dim3(256), 0, s, jsw, y, pc.dev, pc.t_node0, scan);
+    hipLaunchKernelGGL((k_pinv_up0<NX, T>), dim3(pc.n_node0, 16), dim3(256), 0, s, jsw, y, pc.dev, pc.t_node0, scan);
     for (int l = 0; l < pc.Lmax; ++l)
       hipLaunchKernelGGL((k_pinv_up<NX>), dim3(pc.n_up[l], ncg), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
     hipLaunchKernelGGL((k_pinv_top<NX>), dim3(pc.ninst), dim3(64), 0, s, scan, pc.dev);
