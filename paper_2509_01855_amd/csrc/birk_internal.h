@@ -160,8 +160,6 @@ struct PinvClass {
   int n_node0 = 0;
   int2* t_up[kPinvMaxLevels] = {};           // (k, block) over cnt[l + 1] parents of level l
   int n_up[kPinvMaxLevels] = {};
-  int2* t_upc[kPinvMaxLevels] = {};          // (k, block of 64 parents) of the column-wise up-sweep
-  int n_upc[kPinvMaxLevels] = {};
   int2* t_nodes = nullptr;                   // (k, block of 256 nodes): J x
   int n_nodes = 0;
   int2* t_tile = nullptr;                    // (k, tile) of the wave-scan path

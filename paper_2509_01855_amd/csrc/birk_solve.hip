@@ -413,16 +413,6 @@ __global__ __launch_bounds__(256) void k_make_h_rows(JT* __restrict__ jsw, const
   }
 }
 
-// The upper up-sweep levels carry the NX + 1 columns of an aggregate (A, b): a thread
-// holds PER of them, all when NX <= 8 (blockIdx.y = 0), else one of four groups
-// (blockIdx.y picks the group), and streams the rows of the child aggregates it applies, so their
-// entries are read once per group.
-template <int NX>
-struct ColGroups {
-  static constexpr int per = (NX <= 8) ? NX + 1 : (NX + 4) / 4;  // four groups above 8
-  static constexpr int count = (NX + 1 + per - 1) / per;
-};
-
 // Level-0 up-sweep: each chunk of kChunk nodes is reduced to (A, b) with
 // S_out = A S_in + b by the node maps S -> (I + H_k) S + H_k y_k, sixteen lanes per chunk
 // with lane r < NX holding row r of A and b: from A = I, b = 0 each node takes
@@ -527,144 +517,133 @@ __device__ __forceinline__ void advance(const double* __restrict__ a, int64_t fs
   for (int r = 0; r < NX; ++r) s[r] = ns[r];
 }
 
+// Upper levels of the hierarchical scan, sixteen lanes per parent (lane r < NX holds row
+// r of a map or component r of a state; rows and states broadcast with DPP row_newbcast).
+// Child aggregate i of parent g: level 0 in the slot layout (field f at stride 64), upper
+// levels plain (F consecutive fields).  grid = (tile (k, block of 256 parents), 16 groups
+// of 16 parents).
 template <int NX>
-__device__ __forceinline__ void store_agg(double* __restrict__ o, const double (&A)[NX][NX], const double (&b)[NX]) {
-#pragma unroll
-  for (int r = 0; r < NX; ++r)
-#pragma unroll
-    for (int q = 0; q < NX; ++q) o[r * NX + q] = A[r][q];
-#pragma unroll
-  for (int r = 0; r < NX; ++r) o[NX * NX + r] = b[r];
-}
-
-template <int NX>
-__device__ __forceinline__ void identity_agg(double (&A)[NX][NX], double (&b)[NX]) {
-#pragma unroll
-  for (int r = 0; r < NX; ++r) {
-    b[r] = 0.0;
-#pragma unroll
-    for (int q = 0; q < NX; ++q) A[r][q] = (r == q) ? 1.0 : 0.0;
+__device__ __forceinline__ const double* child_agg(const double* __restrict__ child, int lv, int64_t g, int i,
+                                                   int64_t& fs) {
+  constexpr int F = NX * NX + NX;
+  if (lv == 0) {
+    fs = 64;
+    return child + swz(g >> 6, i, 0, F, (int)(g & 63));
   }
+  fs = 1;
+  return child + (g * kFan + i) * F;
 }
 
-// Up-sweep level lv -> lv + 1: thread per parent combines its kFan child aggregates in
-// order, (A, b) <- (a_A A, a_A b + a_b), over its group of columns; level 0 is read
-// swizzled.  tile = (k, block of 256 parents).
+// Up-sweep level lv -> lv + 1: each parent composes its kFan child aggregates in order,
+// (A, b) <- (a_A A, a_A b + a_b).
 template <int NX>
 __global__ __launch_bounds__(256) void k_pinv_up(double* __restrict__ scan, const PinvDesc* __restrict__ pd,
                                                  const int2* __restrict__ tiles, int lv) {
-  constexpr int PER = ColGroups<NX>::per;
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
-  const int64_t g = (int64_t)t.y * blockDim.x + threadIdx.x;
-  if (g >= d.cnt[lv + 1]) return;
-  const int c0 = (int)blockIdx.y * PER;
+  const int64_t g = (int64_t)t.y * 256 + blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (g >= d.cnt[lv + 1]) return;  // the whole group leaves together
+  const int r = (int)(threadIdx.x & 15);
+  const bool act = r < NX;
+  const int rr = act ? r : 0;
   constexpr int F = NX * NX + NX;
   const double* child = scan + d.agg[lv];
-  const int64_t nchild = d.cnt[lv];
-  double col[PER][NX];
+  double a[NX], b = 0.0;
 #pragma unroll
-  for (int p = 0; p < PER; ++p)
-#pragma unroll
-    for (int r = 0; r < NX; ++r) col[p][r] = (r == c0 + p) ? 1.0 : 0.0;
-  const int nc = (int)min((int64_t)kFan, nchild - g * kFan);
+  for (int c = 0; c < NX; ++c) a[c] = (act && c == r) ? 1.0 : 0.0;
+  const int nc = (int)min((int64_t)kFan, d.cnt[lv] - g * kFan);
 #pragma unroll 1
   for (int i = 0; i < nc; ++i) {
-    const double* a;
     int64_t fs;
-    if (lv == 0) {
-      a = child + swz(g >> 6, i, 0, F, (int)(g & 63));
-      fs = 64;
-    } else {
-      a = child + (g * kFan + i) * F;
-      fs = 1;
-    }
-    double u[PER][NX];
+    const double* ca = child_agg<NX>(child, lv, g, i, fs);
+    double row[NX];
 #pragma unroll
-    for (int p = 0; p < PER; ++p)
+    for (int q = 0; q < NX; ++q) row[q] = ca[(rr * NX + q) * fs];
+    double na[NX], nb = ca[(NX * NX + rr) * fs];
 #pragma unroll
-      for (int r = 0; r < NX; ++r) u[p][r] = col[p][r];
+    for (int c = 0; c < NX; ++c) na[c] = 0.0;
+    static_for<0, NX>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      nb += row[q] * row_bcast<q>(b);
 #pragma unroll
-    for (int r = 0; r < NX; ++r) {
-      double h[NX];
+      for (int c = 0; c < NX; ++c) na[c] += row[q] * row_bcast<q>(a[c]);
+    });
 #pragma unroll
-      for (int q = 0; q < NX; ++q) h[q] = a[(r * NX + q) * fs];
-      const double ab = a[(NX * NX + r) * fs];
-#pragma unroll
-      for (int p = 0; p < PER; ++p) {
-        double acc = (c0 + p == NX) ? ab : 0.0;
-#pragma unroll
-        for (int q = 0; q < NX; ++q) acc += h[q] * u[p][q];
-        col[p][r] = acc;
-      }
-    }
+    for (int c = 0; c < NX; ++c) a[c] = na[c];
+    b = nb;
   }
-  double* o = scan + d.agg[lv + 1] + g * F;
+  if (act) {
+    double* o = scan + d.agg[lv + 1] + g * F;
 #pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int c = c0 + p;
-    if (c > NX) break;
-#pragma unroll
-    for (int r = 0; r < NX; ++r) o[(c < NX) ? r * NX + c : NX * NX + r] = col[p][r];
+    for (int c = 0; c < NX; ++c) o[r * NX + c] = a[c];
+    o[NX * NX + r] = b;
   }
 }
 
-// Top: one thread per instance walks the top-level aggregates from S = 0 and writes
-// their start states (level 0 swizzled when the instance has a single group).
+// Top: sixteen lanes per instance (one workgroup of 64 threads, the first row working)
+// walk the top-level aggregates from S = 0 and write their start states (level 0 in the
+// slot layout when the instance has a single group).
 template <int NX>
 __global__ void k_pinv_top(double* __restrict__ scan, const PinvDesc* __restrict__ pd) {
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x >= 16) return;
+  const int r = (int)threadIdx.x;
+  const bool act = r < NX;
+  const int rr = act ? r : 0;
   const PinvDesc& d = pd[blockIdx.x];
   constexpr int F = NX * NX + NX;
   const int L = d.L;
   const double* agg = scan + d.agg[L];
   double* state = scan + d.st[L];
-  double s[NX];
-#pragma unroll
-  for (int r = 0; r < NX; ++r) s[r] = 0.0;
+  double s = 0.0;
   for (int64_t i = 0; i < d.cnt[L]; ++i) {
-    if (L == 0) {
-#pragma unroll
-      for (int r = 0; r < NX; ++r) state[swz(0, (int)i, r, NX, 0)] = s[r];
-      advance<NX>(agg + swz(0, (int)i, 0, F, 0), 64, s);
-    } else {
-#pragma unroll
-      for (int r = 0; r < NX; ++r) state[i * NX + r] = s[r];
-      advance<NX>(agg + i * F, 1, s);
+    const double* ca = (L == 0) ? agg + swz(0, (int)i, 0, F, 0) : agg + i * F;
+    const int64_t fs = (L == 0) ? 64 : 1;
+    if (act) {
+      if (L == 0) state[swz(0, (int)i, r, NX, 0)] = s;
+      else state[i * NX + r] = s;
     }
+    double ns = ca[(NX * NX + rr) * fs];
+    static_for<0, NX>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      ns += ca[(rr * NX + q) * fs] * row_bcast<q>(s);
+    });
+    s = ns;
   }
 }
 
-// Down-sweep level lv + 1 -> lv: thread per parent pushes its start state through its
-// children (level 0 written swizzled).  tile = (k, block over cnt[lv + 1]).
+// Down-sweep level lv + 1 -> lv: each parent pushes its start state through its children
+// (level 0 written in the slot layout).
 template <int NX>
 __global__ __launch_bounds__(256) void k_pinv_down(double* __restrict__ scan, const PinvDesc* __restrict__ pd,
                                                    const int2* __restrict__ tiles, int lv) {
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
-  const int64_t g = (int64_t)t.y * blockDim.x + threadIdx.x;
-  if (g >= d.cnt[lv + 1]) return;
-  constexpr int F = NX * NX + NX;
+  const int64_t g = (int64_t)t.y * 256 + blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (g >= d.cnt[lv + 1]) return;  // the whole group leaves together
+  const int r = (int)(threadIdx.x & 15);
+  const bool act = r < NX;
+  const int rr = act ? r : 0;
   const double* child = scan + d.agg[lv];
   double* cstate = scan + d.st[lv];
-  const double* pstate = scan + d.st[lv + 1];
-  double s[NX];
-#pragma unroll
-  for (int r = 0; r < NX; ++r) s[r] = pstate[g * NX + r];
+  double s = act ? scan[d.st[lv + 1] + g * NX + r] : 0.0;
   const int nc = (int)min((int64_t)kFan, d.cnt[lv] - g * kFan);
+#pragma unroll 1
   for (int i = 0; i < nc; ++i) {
-    if (lv == 0) {
-      const int64_t B = g >> 6;
-      const int l = (int)(g & 63);
-#pragma unroll
-      for (int r = 0; r < NX; ++r) cstate[swz(B, i, r, NX, l)] = s[r];
-      advance<NX>(child + swz(B, i, 0, F, l), 64, s);
-    } else {
-      const int64_t c = g * kFan + i;
-#pragma unroll
-      for (int r = 0; r < NX; ++r) cstate[c * NX + r] = s[r];
-      advance<NX>(child + c * F, 1, s);
+    if (act) {
+      if (lv == 0) cstate[swz(g >> 6, i, r, NX, (int)(g & 63))] = s;
+      else cstate[(g * kFan + i) * NX + r] = s;
     }
+    int64_t fs;
+    const double* ca = child_agg<NX>(child, lv, g, i, fs);
+    double row[NX];
+#pragma unroll
+    for (int q = 0; q < NX; ++q) row[q] = ca[(rr * NX + q) * fs];
+    double ns = ca[(NX * NX + rr) * fs];
+    static_for<0, NX>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      ns += row[q] * row_bcast<q>(s);
+    });
+    s = ns;
   }
 }
 
@@ -1445,7 +1424,7 @@ hipError_t plan_solve(birk_plan* p) {
     }
     if (pc.host.empty()) continue;
     pc.ninst = (int)pc.host.size();
-    std::vector<int2> t0, tn, tt, tup[kPinvMaxLevels], tupc[kPinvMaxLevels];
+    std::vector<int2> t0, tn, tt, tup[kPinvMaxLevels];
     for (int k = 0; k < pc.ninst; ++k) {
       const PinvDesc& d = pc.host[k];
       if (nx <= kWaveNx) {
@@ -1458,7 +1437,6 @@ hipError_t plan_solve(birk_plan* p) {
       for (unsigned b = 0; b < nblocks(d.Nn, 256); ++b) tn.push_back(make_int2(k, (int)b));
       for (int l = 0; l < d.L; ++l) {
         for (unsigned b = 0; b < nblocks(d.cnt[l + 1], 256); ++b) tup[l].push_back(make_int2(k, (int)b));
-        for (unsigned b = 0; b < nblocks(d.cnt[l + 1], 64); ++b) tupc[l].push_back(make_int2(k, (int)b));
       }
     }
     void* dd = nullptr;
@@ -1476,8 +1454,6 @@ hipError_t plan_solve(birk_plan* p) {
     for (int l = 0; l < pc.Lmax; ++l) {
       if ((e = upload_tiles(p, tup[l], &pc.t_up[l])) != hipSuccess) return e;
       pc.n_up[l] = (int)tup[l].size();
-      if ((e = upload_tiles(p, tupc[l], &pc.t_upc[l])) != hipSuccess) return e;
-      pc.n_upc[l] = (int)tupc[l].size();
     }
     p->pclass.push_back(std::move(pc));
   }
@@ -1594,13 +1570,12 @@ static void pinv_class(birk_plan* p, const PinvClass& pc, const double* J, int p
     (void)J;
     (void)pn;
     (void)cached;
-    constexpr int ncg = ColGroups<NX>::count;
     hipLaunchKernelGGL((k_pinv_up0<NX, T>), dim3(pc.n_node0, 16), dim3(256), 0, s, jsw, y, pc.dev, pc.t_node0, scan);
     for (int l = 0; l < pc.Lmax; ++l)
-      hipLaunchKernelGGL((k_pinv_up<NX>), dim3(pc.n_up[l], ncg), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
+      hipLaunchKernelGGL((k_pinv_up<NX>), dim3(pc.n_up[l], 16), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
     hipLaunchKernelGGL((k_pinv_top<NX>), dim3(pc.ninst), dim3(64), 0, s, scan, pc.dev);
     for (int l = pc.Lmax - 1; l >= 0; --l)
-      hipLaunchKernelGGL((k_pinv_down<NX>), dim3(pc.n_up[l]), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
+      hipLaunchKernelGGL((k_pinv_down<NX>), dim3(pc.n_up[l], 16), dim3(256), 0, s, scan, pc.dev, pc.t_up[l], l);
     hipLaunchKernelGGL((k_pinv_final_lanes<NX, T>), dim3(pc.n_node0, 16), dim3(256), 0, s, jsw, y, pc.dev,
                        pc.t_node0, scan, out, jout);
   }
