@@ -446,11 +446,15 @@ __global__ __launch_bounds__(256) void k_pinv_up0(const T* __restrict__ jsw, con
   for (int c = 0; c < NX; ++c) a[c] = (act && c == r) ? 1.0 : 0.0;
   const int64_t k0 = ch * kChunk;
   const int jn = (int)min((int64_t)kChunk, Nn - k0);
-#pragma unroll 1
-  for (int j = 0; j < jn; ++j) {
+  double yv[kChunk];  // the chunk's run of y for component r, loaded together
+#pragma unroll
+  for (int j = 0; j < kChunk; ++j) yv[j] = (act && j < jn) ? (double)yi[k0 + j] : 0.0;
+#pragma unroll
+  for (int j = 0; j < kChunk; ++j) {
+    if (j >= jn) break;
     double h[NX];
     load_row<NX, T>(hs + (int64_t)j * E, h);  // lanes r >= NX read row 0 (in bounds), unused
-    const double u = b + (act ? (double)yi[k0 + j] : 0.0);
+    const double u = b + yv[j];
     double na[NX], nb = b;
 #pragma unroll
     for (int c = 0; c < NX; ++c) na[c] = a[c];
@@ -1254,9 +1258,15 @@ __global__ __launch_bounds__(256) void k_pinv_final_lanes(const T* __restrict__ 
   double s = act ? scan[d.st[0] + swz(B, i, rr, NX, l)] : 0.0;
   const int64_t k0 = c * kChunk;
   const int jn = (int)min((int64_t)kChunk, Nn - k0);
-  // row r of H_k, w_k and y_k of the next node are loaded while the current node is
-  // replayed (the replay itself waits on the carried state)
-  double hn[NX], wn = 1.0, yn = 0.0;
+  // the chunk's kChunk values of y (one 128-byte run per component) are loaded together,
+  // and its outputs kept in registers and stored together at the end, so that each run
+  // is read and written back to back; row r of H_k and w_k of the next node are loaded
+  // while the current node is replayed (the replay itself waits on the carried state)
+  const T* yr = yi + (int64_t)rr * Nn + k0;
+  double yv[kChunk], xo[kChunk], jo[kChunk];
+#pragma unroll
+  for (int j = 0; j < kChunk; ++j) yv[j] = (act && j < jn) ? (double)yr[j] : 0.0;
+  double hn[NX], wn = 1.0;
   auto fetch = [&](int j) {
     const T* base = js + (int64_t)j * E;
     load_row<NX, T>(base + rr * NX, hn);
@@ -1265,27 +1275,37 @@ __global__ __launch_bounds__(256) void k_pinv_final_lanes(const T* __restrict__ 
       for (int q = 0; q < NX; ++q) hn[q] = 0.0;
     }
     wn = (double)base[NX * NX];
-    yn = act ? (double)yi[(int64_t)rr * Nn + k0 + j] : 0.0;
   };
   if (jn > 0) fetch(0);
-#pragma unroll 1
-  for (int j = 0; j < jn; ++j) {
-    const int64_t k = k0 + j;
-    double h[NX];
 #pragma unroll
-    for (int q = 0; q < NX; ++q) h[q] = hn[q];
-    const double wk = wn;
-    const double u = s + yn;
-    if (j + 1 < jn) fetch(j + 1);
-    double v = 0.0;
-    static_for<0, NX>([&](auto qc) {
-      constexpr int q = decltype(qc)::value;
-      v += h[q] * row_bcast<q>(u);
-    });
-    s += v;
-    if (act) {
-      oi[(int64_t)r * Nn + k] = (T)(u + 0.5 * v);
-      if (ji) ji[(int64_t)r * Nn + k] = (T)(v * recip(wk));
+  for (int j = 0; j < kChunk; ++j) {
+    if (j < jn) {
+      double h[NX];
+#pragma unroll
+      for (int q = 0; q < NX; ++q) h[q] = hn[q];
+      const double wk = wn;
+      const double u = s + yv[j];
+      if (j + 1 < jn) fetch(j + 1);
+      double v = 0.0;
+      static_for<0, NX>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        v += h[q] * row_bcast<q>(u);
+      });
+      s += v;
+      xo[j] = u + 0.5 * v;
+      jo[j] = v * recip(wk);
+    }
+  }
+  if (act) {
+    T* orow = oi + (int64_t)r * Nn + k0;
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j)
+      if (j < jn) orow[j] = (T)xo[j];
+    if (ji) {
+      T* jrow = ji + (int64_t)r * Nn + k0;
+#pragma unroll
+      for (int j = 0; j < kChunk; ++j)
+        if (j < jn) jrow[j] = (T)jo[j];
     }
   }
 }
