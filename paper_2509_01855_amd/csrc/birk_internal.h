@@ -332,9 +332,10 @@ template <typename T>
 hipError_t precond_inverse(birk_plan* p, int jac_kind, const double* J, const T* y, T* out,
                            T* jout, hipStream_t s, int* flag, int cached);
 // P^{-T} y for the instances with n_x <= 8 (backward wave scan, double); the instances
-// with larger n_x are left untouched (birk_kkt.hip covers them).
+// with larger n_x are left untouched (birk_kkt.hip covers them).  cached = 1: per-node
+// H_k laid out by precond_prepare(..., kPrepCache) in double for this J (read transposed).
 hipError_t precond_inverse_t_wave(birk_plan* p, int jac_kind, const double* J, const double* y, double* out,
-                                  hipStream_t s);
+                                  hipStream_t s, int cached);
 int64_t pinv_scratch(int64_t Nn, int nx);
 int64_t pinv_jsw_size(int64_t Nn, int nx);
 // Build the per-n_x scan classes and the Krylov segmentation (after scan_off, jsw_off
@@ -399,9 +400,10 @@ void gm_running(const birk_plan* p, const double* st, double* flags, hipStream_t
 // ---- the KKT form and MINRES (birk_kkt.hip) ----
 // Build the P^{-T} scan classes (after the weights exist).
 hipError_t plan_kkt(birk_plan* p);
-// x = P^{-T} y in double (scr: the plan's KKT scan scratch).
+// x = P^{-T} y in double (scr: the plan's KKT scan scratch).  cached = 1: the per-node
+// H_k tables of precond_prepare(..., kPrepCache) (double) hold this J.
 hipError_t precond_inverse_t(birk_plan* p, int jac_kind, const double* J, const double* y, double* x, double* scr,
-                             hipStream_t s);
+                             hipStream_t s, int cached = 0);
 // y_k = J_k^T x_k per node, double.
 hipError_t jac_t_times(birk_plan* p, int jac_kind, const double* J, const double* x, double* y, hipStream_t s);
 // MINRES on [[H, A^T], [A, 0]] [chi; lambda] = [f; g] (h or f null: identity, zero).

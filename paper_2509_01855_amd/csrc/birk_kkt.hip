@@ -621,9 +621,9 @@ hipError_t plan_kkt(birk_plan* p) {
 }
 
 hipError_t precond_inverse_t(birk_plan* p, int jac_kind, const double* J, const double* y, double* x, double* scr,
-                             hipStream_t s) {
+                             hipStream_t s, int cached) {
   // n_x <= 8: the backward wave scan of birk_solve.hip; larger n_x: the chunked scan here
-  hipError_t e = precond_inverse_t_wave(p, jac_kind, J, y, x, s);
+  hipError_t e = precond_inverse_t_wave(p, jac_kind, J, y, x, s, cached);
   if (e != hipSuccess) return e;
   for (const BtClass& bc : p->btclass) {
     if (bc.nx <= 8) continue;
@@ -725,7 +725,7 @@ static hipError_t kkt_prec(birk_plan* p, int jk, const double* J, const double* 
   hipError_t e = precond_inverse<double>(p, jk, J, r + n, t0, nullptr, s, nullptr, cached);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_hscale, dim3(nb256(n)), dim3(256), 0, s, t0, h, t0, n, 0);
-  return precond_inverse_t(p, jk, J, t0, z + n, scr, s);
+  return precond_inverse_t(p, jk, J, t0, z + n, scr, s, cached);
 }
 
 // MINRES on the KKT system for every instance of the batch (arguments checked by the

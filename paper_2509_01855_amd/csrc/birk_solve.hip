@@ -943,6 +943,88 @@ __device__ __forceinline__ void chunk_map_h(const T* __restrict__ hs, const T* _
   }
 }
 
+// Backward (P^{-T}) counterparts reading the same cached tables: position p is node
+// k = N_n - 1 - p, whose H_k sits in its own tile slot (tile k / kTileNodes, thread
+// (k / kTC) mod kTileThreads, node k mod kTC); G_k = H_k^T.  Node map (K_k^{-T} = I + G/2
+// and w_k J_k^T K_k^{-T} = G): T -> (I + G) T + (I + G / 2) y_k, so A <- A + G A and
+// b <- b + y_k + G (b + y_k / 2); replay x_k = y_k + G (T + y_k / 2), T <- T + x_k.
+template <typename T>
+__device__ __forceinline__ const T* node_slot(const T* __restrict__ tab, int64_t k, int E) {
+  return tab + (k / kTileNodes) * kTC * E * kTileThreads + (k % kTC) * E * kTileThreads + (k / kTC) % kTileThreads;
+}
+
+template <int NX, typename T>
+__device__ __forceinline__ void chunk_map_ht(const T* __restrict__ tab, const T* __restrict__ yi, int64_t Nn,
+                                             int64_t k0, Aff<NX>& m) {
+  constexpr int E = NX * NX + 1;
+#pragma unroll 1
+  for (int j = 0; j < kTC; ++j) {
+    const int64_t pos = k0 + j;
+    if (pos >= Nn) break;
+    const int64_t k = Nn - 1 - pos;
+    const T* base = node_slot<T>(tab, k, E);
+    double G[NX][NX], yv[NX], u[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r)
+#pragma unroll
+      for (int q = 0; q < NX; ++q) G[r][q] = (double)base[(q * NX + r) * kTileThreads];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      yv[r] = (double)yi[(int64_t)r * Nn + k];
+      u[r] = m.b[r] + 0.5 * yv[r];
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < NX; ++q) acc += G[r][q] * u[q];
+      m.b[r] += yv[r] + acc;
+    }
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+      double t[NX];
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < NX; ++q) acc += G[r][q] * m.A[q][c];
+        t[r] = acc;
+      }
+#pragma unroll
+      for (int r = 0; r < NX; ++r) m.A[r][c] += t[r];
+    }
+  }
+}
+
+template <int NX, typename T>
+__device__ __forceinline__ void chunk_replay_ht(const T* __restrict__ tab, const T* __restrict__ yi,
+                                                T* __restrict__ oi, int64_t Nn, int64_t k0, double (&s)[NX]) {
+  constexpr int E = NX * NX + 1;
+#pragma unroll 1
+  for (int j = 0; j < kTC; ++j) {
+    const int64_t pos = k0 + j;
+    if (pos >= Nn) break;
+    const int64_t k = Nn - 1 - pos;
+    const T* base = node_slot<T>(tab, k, E);
+    double yv[NX], u[NX], x[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      yv[r] = (double)yi[(int64_t)r * Nn + k];
+      u[r] = s[r] + 0.5 * yv[r];
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < NX; ++q) acc += (double)base[(q * NX + r) * kTileThreads] * u[q];
+      x[r] = yv[r] + acc;
+      oi[(int64_t)r * Nn + k] = (T)x[r];
+    }
+#pragma unroll
+    for (int r = 0; r < NX; ++r) s[r] += x[r];
+  }
+}
+
 template <int NX>
 __device__ __forceinline__ void aff_store(double* __restrict__ o, const Aff<NX>& m) {
 #pragma unroll
@@ -1052,8 +1134,9 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const double* 
       }
     } else if constexpr (MODE == kFlyConst) {
       chunk_map<NX, BACK>(J + d.jcoff, int64_t(0), int64_t(1), d.w, y + d.off, d.Nn, k0, m, flag);
+    } else if constexpr (BACK) {
+      chunk_map_ht<NX, T>(jsw + d.jsw_off, y + d.off, d.Nn, k0, m);
     } else {
-      static_assert(!BACK, "the cached H_k serve P^{-1} only");
       constexpr int E = NX * NX + 1;
       chunk_map_h<NX, T>(jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x, y + d.off, d.Nn, k0, m);
     }
@@ -1202,7 +1285,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const double* __re
     chunk_replay<NX, BACK>(J + d.jcoff, int64_t(0), int64_t(1), d.w, yi, oi, ji, Nn, k0, s);
   } else {
     // H_k from precond_prepare: v = H_k u, xi_k = u + v / 2, (J xi)_k = v / w_k, S <- S + v
-    static_assert(!BACK, "the cached H_k serve P^{-1} only");
+    if constexpr (BACK) {
+      chunk_replay_ht<NX, T>(jsw + d.jsw_off, yi, oi, Nn, k0, s);
+      return;
+    }
     constexpr int E = NX * NX + 1;
     const T* hs = jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x;
 #pragma unroll 1
@@ -1625,12 +1711,15 @@ hipError_t precond_inverse(birk_plan* p, int jac_kind, const double* J, const T*
 // P^{-T} y for the classes with n_x <= kWaveNx: the same three launches run backwards over
 // the nodes with K_k^T (double only; the classes above are left to the caller).
 template <int NX>
-static void pinv_t_class(birk_plan* p, const PinvClass& pc, const double* J, int pn, const double* y, double* out,
-                         hipStream_t s) {
+static void pinv_t_class(birk_plan* p, const PinvClass& pc, const double* J, int pn, int cached, const double* y,
+                         double* out, hipStream_t s) {
   if constexpr (NX <= kWaveNx) {
     const dim3 grid(pc.n_tile), block(kTileThreads);
     const double* jsw = (const double*)p->jsw;
-    if (pn) {
+    if (pn && cached) {
+      hipLaunchKernelGGL((k_tscan_reduce<NX, kCachedH, true, double>), grid, block, 0, s, J, jsw, y, pc.dev,
+                         pc.t_tile, p->scan, p->flag);
+    } else if (pn) {
       hipLaunchKernelGGL((k_tscan_reduce<NX, kFlyPerNode, true, double>), grid, block, 0, s, J, jsw, y, pc.dev,
                          pc.t_tile, p->scan, p->flag);
     } else {
@@ -1638,7 +1727,10 @@ static void pinv_t_class(birk_plan* p, const PinvClass& pc, const double* J, int
                          pc.t_tile, p->scan, p->flag);
     }
     hipLaunchKernelGGL((k_tscan_tiles<NX>), dim3(pc.ninst), dim3(256), 0, s, p->scan, pc.dev);
-    if (pn) {
+    if (pn && cached) {
+      hipLaunchKernelGGL((k_tscan_apply<NX, kCachedH, true, double>), grid, block, 0, s, J, jsw, y, pc.dev,
+                         pc.t_tile, p->scan, out, nullptr);
+    } else if (pn) {
       hipLaunchKernelGGL((k_tscan_apply<NX, kFlyPerNode, true, double>), grid, block, 0, s, J, jsw, y, pc.dev,
                          pc.t_tile, p->scan, out, nullptr);
     } else {
@@ -1646,16 +1738,16 @@ static void pinv_t_class(birk_plan* p, const PinvClass& pc, const double* J, int
                          pc.t_tile, p->scan, out, nullptr);
     }
   } else {
-    (void)p, (void)pc, (void)J, (void)pn, (void)y, (void)out, (void)s;
+    (void)p, (void)pc, (void)J, (void)pn, (void)cached, (void)y, (void)out, (void)s;
   }
 }
 
 hipError_t precond_inverse_t_wave(birk_plan* p, int jac_kind, const double* J, const double* y, double* out,
-                                  hipStream_t s) {
+                                  hipStream_t s, int cached) {
   const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
   for (const PinvClass& pc : p->pclass) {
     if (pc.nx > kWaveNx) continue;
-    BIRK_NX_SWITCH(pc.nx, (pinv_t_class<NXC>(p, pc, J, pn, y, out, s)))
+    BIRK_NX_SWITCH(pc.nx, (pinv_t_class<NXC>(p, pc, J, pn, cached, y, out, s)))
   }
   return hipGetLastError();
 }
