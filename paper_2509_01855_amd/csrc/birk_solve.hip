@@ -795,12 +795,18 @@ __device__ __forceinline__ void node_lu(P Jp, int64_t js, double wk, double (&K)
 // lds[e * 64 + l], coalesced global reads), and the 16 lanes whose chunks lie in them
 // (lanes 16 j .. 16 j + 15) then work their nodes from LDS.
 // BACK: scan positions run from the last node down (position p is node N_n - 1 - p).
+// The loads of a round go to registers first (fetch_j), so that the next round's loads
+// can be in flight while the current round is worked; put_j then writes them to LDS.
 template <int NX, bool BACK>
-__device__ __forceinline__ void stage_j(double* __restrict__ jw, const double* __restrict__ Jn, int64_t Nn,
-                                        int64_t kl, int l) {
+__device__ __forceinline__ void fetch_j(double (&v)[NX * NX], const double* __restrict__ Jn, int64_t Nn, int64_t kl) {
   const int64_t k = BACK ? Nn - 1 - kl : kl;
 #pragma unroll
-  for (int e = 0; e < NX * NX; ++e) jw[e * 64 + l] = (kl < Nn) ? Jn[(int64_t)e * Nn + k] : 0.0;
+  for (int e = 0; e < NX * NX; ++e) v[e] = (kl < Nn) ? Jn[(int64_t)e * Nn + k] : 0.0;
+}
+template <int NX>
+__device__ __forceinline__ void put_j(double* __restrict__ jw, const double (&v)[NX * NX], int l) {
+#pragma unroll
+  for (int e = 0; e < NX * NX; ++e) jw[e * 64 + l] = v[e];
 }
 
 // The map of one chunk, composed node by node from A = I, b = 0.  Node k takes
@@ -1125,9 +1131,12 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const double* 
     if constexpr (MODE == kFlyPerNode) {
       double* jw = jl + w * 64 * NX * NX;
       const int64_t kw = g * kTileNodes + (int64_t)w * 64 * kTC;
+      double pre[NX * NX];
+      fetch_j<NX, BACK>(pre, J + d.joff, d.Nn, kw + l);
       for (int j = 0; j < kTC; ++j) {
-        stage_j<NX, BACK>(jw, J + d.joff, d.Nn, kw + 64 * j + l, l);
+        put_j<NX>(jw, pre, l);
         __syncthreads();
+        if (j + 1 < kTC) fetch_j<NX, BACK>(pre, J + d.joff, d.Nn, kw + 64 * (j + 1) + l);
         if ((l >> 4) == j)
           chunk_map<NX, BACK>(jw + (4 * l - 64 * j), int64_t(1), int64_t(64), d.w, y + d.off, d.Nn, k0, m, flag);
         __syncthreads();
@@ -1274,9 +1283,12 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const double* __re
     const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
     double* jw = jl + w * 64 * NX * NX;
     const int64_t kw = g * kTileNodes + (int64_t)w * 64 * kTC;
+    double pre[NX * NX];
+    fetch_j<NX, BACK>(pre, J + d.joff, Nn, kw + l);
     for (int j = 0; j < kTC; ++j) {
-      stage_j<NX, BACK>(jw, J + d.joff, Nn, kw + 64 * j + l, l);
+      put_j<NX>(jw, pre, l);
       __syncthreads();
+      if (j + 1 < kTC) fetch_j<NX, BACK>(pre, J + d.joff, Nn, kw + 64 * (j + 1) + l);
       if ((l >> 4) == j)
         chunk_replay<NX, BACK>(jw + (4 * l - 64 * j), int64_t(1), int64_t(64), d.w, yi, oi, ji, Nn, k0, s);
       __syncthreads();
