@@ -84,6 +84,30 @@ def test_precond_inverse_roundtrip_large(B, Nn):
     assert rel_err(sy.precond_apply(w, inst.J, xi), y) <= 1e-11
 
 
+@pytest.mark.parametrize("Nn,nx", [(3001, 9), (3001, 10), (20000, 11), (20000, 12), (70001, 12)])
+def test_precond_inverse_per_node_large_nx(B, Nn, nx):
+    """P^{-1} with a per-node Jacobian on the sixteen-lane hierarchical scan (n_x > 8): odd
+    and even n_x (scalar and 16-byte row loads), one to three levels, against the
+    oracle's block forward substitution."""
+    import torch
+    announce(f"precond inverse per-node J Nn={Nn} nx={nx}")
+    rng = np.random.default_rng([nx, Nn])
+    A = wl.lti_matrix(rng, nx)
+    C = rng.standard_normal((nx, nx)) / np.sqrt(nx)
+    tau = -np.cos(np.pi * np.arange(Nn) / (Nn - 1))
+    J = A[:, :, None] + 0.25 * np.sin(3.0 * tau)[None, None, :] * C[:, :, None]
+    w = bk.weights(Nn - 1)
+    y = wl.random_vectors([7, Nn], (nx * Nn,))[0]
+    plan = B.birk_plan_create([Nn], [nx], B.BIRK_F64)
+    yd = dev(y, torch.float64)
+    out = torch.empty_like(yd)
+    B.birk_precond(plan, dev(J.ravel(), torch.float64), yd, out, 1, B.BIRK_J_PER_NODE)
+    torch.cuda.synchronize()
+    got = host(out)
+    plan.destroy()
+    assert rel_err(got, sy.precond_inverse(w, J, y)) <= 1e-12
+
+
 def test_precond_f32_storage(B):
     import torch
     Nn = 1025
