@@ -681,8 +681,8 @@ __device__ __forceinline__ double recip_int<double>(double x) {
   return __builtin_fma(r, e, r);
 }
 
-// stencil_fwd, stencil_tr and c0_coef with one or two reciprocals per element in place of
-// their divisions (same formulas).
+// stencil_fwd and stencil_tr with one or two reciprocals per element in place of their
+// divisions (same formulas).
 template <typename T>
 __device__ __forceinline__ T stencil_fwd_r(int k, int N, T Ym, T Yp, T invN, T inv4N1) {
   if (k == 0) return T(0);
@@ -712,13 +712,6 @@ __device__ __forceinline__ T stencil_tr_r(int j, int N, T Ym, T Yp, T p0, T inv2
   return q;
 }
 
-__device__ __forceinline__ double c0_coef_r(int k, int N) {
-  if (k == 0) return 0.5;
-  if (k == 1) return 0.25;
-  const double ek = (k == N) ? 0.5 : 1.0;
-  return -ek * recip_int<double>((double)(k - 1) * (double)(k + 1));
-}
-
 // Pass B for rows of L2 = 2^LOGL2 (512..2048) points, TB rows per tile (2 or 4), blockDim
 // = L2 / 8, with the row transforms kept in registers at both ends (fft_regs): each thread
 // builds its eight elements m = tid + i blockDim of a Hermitian row pair straight from G
@@ -726,10 +719,22 @@ __device__ __forceinline__ double c0_coef_r(int k, int N) {
 // threads), runs the first butterflies in registers, and receives its outputs
 // m = tid + i blockDim of the last stage in registers, which is the layout the stencil and
 // the second DCT's column transform use.  Only the stages in between, and the mirror
-// reads of the final separation, go through LDS.  The tile's rows are swept in pairs with
-// a rolling window: DCT-1 row pair (t0 + 2q + 1, t0 + 2q + 2) joins the pair before it,
-// the stencil of rows t0 + 2q, t0 + 2q + 1 follows, then their DCT-2 column transform and
-// store; so TB rows cost TB/2 + 1 DCT-1 and TB/2 DCT-2 transforms.
+// reads of the final separation, go through LDS.
+//
+// The stencil of rows k1, k1 + 1 reads Y of rows k1 - 1 .. k1 + 2 at the same m.
+// * Forward: d_k = +-(Y_{k+1} - Y_{k-1}) / (2 k N) for every k in [1, N - 2], so by
+//   linearity one FFT of the row differences G(k1 + 1) - G(k1 - 1), G(k1 + 2) - G(k1)
+//   gives the stencil of both rows.  The three other coefficients lie in the first tile:
+//   d_0 = 0, and d_N, d_{N-1} need Y_{N-2}, Y_{N-1}, Y_N, which are element L2/2 of rows
+//   2, 1, 0, i.e. alternating sums over those rows (block reductions).  c^_0 makes the
+//   integral vanish at the first node, where every T_k is 1 after the sign folding:
+//   c^_0 = -(d_1 + ... + d_{N-1} + d_N / 2) with d_N as stored (already doubled), so the
+//   partial sums add the stencil outputs (each k once: rows 1..L1/2 - 1 in full, rows 0
+//   and L1/2 for K <= N) and are scaled by N, the form pass C divides out.
+// * Transpose (Y_{k-1} and Y_{k+1} weighted differently): the tile's rows are swept in
+//   pairs with a rolling window: DCT-1 row pair (t0 + 2q + 1, t0 + 2q + 2) joins the pair
+//   before it, the stencil of rows t0 + 2q, t0 + 2q + 1 follows, then their DCT-2 column
+//   transform and store; so TB rows cost TB/2 + 1 DCT-1 and TB/2 DCT-2 transforms.
 template <typename T, int TRANS, int LOGL2, int TB>
 __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB3(
     const cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg, cplx<T>* __restrict__ G2, int64_t g2comp, int64_t sg2,
@@ -755,121 +760,21 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB3(
   cplx<T>* G2c = G2 + (int64_t)comp * g2comp;
   const int tmask = (1 << tsh) - 1;
   const int sg2i = (int)sg2;
-  T p0 = T(0);
-  if (TRANS) {
-    double acc = 0.0;
-    for (int n2 = t; n2 <= half2; n2 += NTHR) acc += (double)Gc[n2].x * ((n2 == 0 || n2 == half2) ? 1.0 : 2.0);
-    p0 = (T)(0.5 * block_sum(acc, red));
-  }
-  // one DCT-1 row pair (k1a, k1a + 1) into registers: element m = t + i NTHR
-  auto dct1_pair = [&](int k1a, T (&vr)[kPPT], T (&vi)[kPPT]) {
-    int ma, mb;
-    const int sa = hrow_src(k1a, L1, &ma);
-    const int sb = hrow_src(k1a + 1, L1, &mb);
-    const cplx<T>* ga = Gc + (int64_t)sa * sgi;
-    const cplx<T>* gb = Gc + (int64_t)sb * sgi;
-    cplx<T> a[kPPT], b[kPPT];
-#pragma unroll
-    for (int i = 0; i < kPPT; ++i) {
-      const int m = t + i * NTHR;
-      const int gi = m <= half2 ? m : L2 - m;
-      a[i] = ga[gi];
-      b[i] = gb[gi];
-    }
-#pragma unroll
-    for (int i = 0; i < kPPT; ++i) {
-      const int m = t + i * NTHR;
-      const int gi = m <= half2 ? m : L2 - m;
-      cplx<T> aa = a[i], bb = b[i];
-      if (ma) aa = conjg<T>(aa);
-      if (ma == 2) aa = cmul<T>(aa, tw[gi << twsh]);
-      if (mb) bb = conjg<T>(bb);
-      if (mb == 2) bb = cmul<T>(bb, tw[gi << twsh]);
-      if (m <= half2) {
-        vr[i] = aa.x - bb.y;
-        vi[i] = aa.y + bb.x;
-      } else {
-        vr[i] = aa.x + bb.y;
-        vi[i] = bb.x - aa.y;
-      }
-    }
-    fft_regs<T, LOGL2>(Yre, vr, vi, tw);
-  };
   const int N2 = 2 * N;
   const T invN = T(1) / T(N), inv4N1 = T(1) / T(4 * (int64_t)N + 4), inv2N1 = T(1) / T(2 * (int64_t)N + 2);
-  double c0acc = 0.0;
-  // window: rows k1 - 1, k1 (pa*) and k1 + 1, k1 + 2 (pb*) around the pair k1 = t0 + 2q
-  T par[kPPT], pai[kPPT];
-  dct1_pair(t0 - 1, par, pai);
-#pragma unroll
-  for (int q = 0; q < TB / 2; ++q) {
-    const int k1 = t0 + 2 * q;
-    T pbr[kPPT], pbi[kPPT];
-    dct1_pair(k1 + 1, pbr, pbi);
-    // stencil of rows k1 and k1 + 1; rows k1 - 1, k1, k1 + 1, k1 + 2 = par, pai, pbr, pbi
-    T dr[kPPT], di[kPPT];
-    if (t0 >= 2) {
-      // rows k1 >= 2: every coefficient index k = K or 2N - K lies in [2, N - 2], where the
-      // stencil has no special terms, and K = k1 + L1 m <= N exactly when m < L2 / 2, i.e.
-      // for the thread's elements i < 4
-#pragma unroll
-      for (int i = 0; i < kPPT; ++i) {
-        const int m = t + i * NTHR;
-#pragma unroll
-        for (int rl = 0; rl < 2; ++rl) {
-          const int K = k1 + rl + L1 * m;
-          const int k = i < 4 ? K : N2 - K;
-          const T ylo = rl ? pai[i] : par[i];
-          const T ymid = rl ? pbr[i] : pai[i];
-          const T yhi = rl ? pbi[i] : pbr[i];
-          const T Ym = i < 4 ? ylo : yhi;
-          const T Yp = i < 4 ? yhi : ylo;
-          T d;
-          if (TRANS) {
-            // stencil_tr for 2 <= j < N: -p0 / (j^2 - 1) + (Ym / (j - 1) - Yp / (j + 1)) / 4
-            const T rm = recip_int<T>(T(k - 1)), rp = recip_int<T>(T(k + 1));
-            d = -p0 * rm * rp + T(0.25) * (Ym * rm - Yp * rp);
-          } else {
-            // stencil_fwd for 2 <= k < N - 1: (Yp - Ym) / (2 k N); c0 weight -1 / (k^2 - 1),
-            // from rows up to L1 / 2 (the upper half of row L1 / 2 mirrors its lower half)
-            const double kd = (double)k;
-            const int kr = k1 + rl;
-            d = (Yp - Ym) * recip_int<T>(T(2 * k)) * invN;
-            if (kr < L1 / 2 || (kr == L1 / 2 && i < 4)) c0acc -= (double)ymid * recip_int<double>(kd * kd - 1.0);
-          }
-          if (rl == 0) dr[i] = d;
-          else di[i] = d;
-        }
-      }
+  // a + i b of two Hermitian rows at element m (values aa, bb of the stored half)
+  auto pack = [&](int m, T ax, T ay, T bx, T by, T& vr, T& vi) {
+    if (m <= half2) {
+      vr = ax - by;
+      vi = ay + bx;
     } else {
-#pragma unroll
-    for (int i = 0; i < kPPT; ++i) {
-      const int m = t + i * NTHR;
-#pragma unroll
-      for (int rl = 0; rl < 2; ++rl) {
-        const int kr = k1 + rl;
-        const T ylo = rl ? pai[i] : par[i];
-        const T ymid = rl ? pbr[i] : pai[i];
-        const T yhi = rl ? pbi[i] : pbr[i];
-        const int K = kr + L1 * m;
-        const bool lowhalf = K <= N;
-        const int k = lowhalf ? K : N2 - K;
-        const T Ym = lowhalf ? ylo : yhi;
-        const T Yp = lowhalf ? yhi : ylo;
-        T d;
-        if (TRANS) {
-          d = stencil_tr_r<T>(k, N, Ym, Yp, p0, inv2N1);
-        } else {
-          d = stencil_fwd_r<T>(k, N, Ym, Yp, invN, inv4N1);
-          if (kr <= L1 / 2 && ((kr != 0 && kr != L1 / 2) || lowhalf)) c0acc += c0_coef_r(k, N) * (double)ymid;
-        }
-        if (rl == 0) dr[i] = d;
-        else di[i] = d;
-      }
+      vr = ax + by;
+      vi = bx - ay;
     }
-    }
-    // column transform of DCT 2 on d(k1) + i d(k1 + 1); the separation needs the mirror
-    // element L2 - q, held by another thread, so the outputs go through LDS once
+  };
+  // column transform of DCT 2 on d(k1) + i d(k1 + 1); the separation needs the mirror
+  // element L2 - q, held by another thread, so the outputs go through LDS once
+  auto dct2_store = [&](int k1, T (&dr)[kPPT], T (&di)[kPPT]) {
     fft_regs<T, LOGL2>(Yre, dr, di, tw);
     __syncthreads();
 #pragma unroll
@@ -897,15 +802,182 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB3(
         }
       }
     }
+  };
+  if constexpr (!TRANS) {
+    double c0acc = 0.0;
 #pragma unroll
-    for (int i = 0; i < kPPT; ++i) {
-      par[i] = pbr[i];
-      pai[i] = pbi[i];
+    for (int q = 0; q < TB / 2; ++q) {
+      const int k1 = t0 + 2 * q;
+      const bool first = k1 == 0;
+      // DCT-1 transform of the row differences; rows k1 - 1 .. k1 + 2 read in two halves
+      // of four elements (as many loads in flight as one row pair of eight); the first
+      // tile also sums rows 0, 1, 2 with alternating signs ((-1)^m = (-1)^t)
+      T dr[kPPT], di[kPPT];
+      double alt[3] = {0.0, 0.0, 0.0};
+      {
+        int mo[4];
+        const cplx<T>* g[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g[r] = Gc + (int64_t)hrow_src(k1 - 1 + r, L1, &mo[r]) * sgi;
+#pragma unroll
+        for (int h = 0; h < kPPT; h += 4) {
+          cplx<T> x[4][4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int m = t + (h + u) * NTHR;
+            const int gi = m <= half2 ? m : L2 - m;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) x[r][u] = g[r][gi];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int m = t + (h + u) * NTHR;
+            const int gi = m <= half2 ? m : L2 - m;
+            cplx<T> y[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              y[r] = x[r][u];
+              if (mo[r]) y[r] = conjg<T>(y[r]);
+              if (mo[r] == 2) y[r] = cmul<T>(y[r], tw[gi << twsh]);
+            }
+            if (first) {
+#pragma unroll
+              for (int r = 0; r < 3; ++r) alt[r] += (double)y[r + 1].x;
+            }
+            pack(m, y[2].x - y[0].x, y[2].y - y[0].y, y[3].x - y[1].x, y[3].y - y[1].y, dr[h + u], di[h + u]);
+          }
+        }
+      }
+      fft_regs<T, LOGL2>(Yre, dr, di, tw);
+      T yN = T(0), yN1 = T(0), yN2 = T(0);  // Y_N, Y_{N-1}, Y_{N-2}
+      if (first) {
+        const double sgn = (t & 1) ? -1.0 : 1.0;
+        yN = (T)block_sum(sgn * alt[0], red);
+        yN1 = (T)block_sum(sgn * alt[1], red);
+        yN2 = (T)block_sum(sgn * alt[2], red);
+      }
+      // stencil of rows k1 (dr) and k1 + 1 (di), in place; K = k1 + rl + L1 m <= N exactly
+      // when m < L2 / 2, i.e. for the thread's elements i < 4, except K = N (row 0, m = L2/2)
+#pragma unroll
+      for (int i = 0; i < kPPT; ++i) {
+        const int m = t + i * NTHR;
+#pragma unroll
+        for (int rl = 0; rl < 2; ++rl) {
+          const int kr = k1 + rl;
+          const int K = kr + L1 * m;
+          const int k = i < 4 ? K : N2 - K;
+          const T D = rl ? di[i] : dr[i];
+          T d = (i < 4 ? D : -D) * recip_int<T>(T(2 * k)) * invN;
+          double wc = (kr < L1 / 2 || (kr == L1 / 2 && i < 4)) ? 1.0 : 0.0;  // weight in c^_0
+          if (first && i == 0 && rl == 0 && t == 0) d = T(0);  // k = 0
+          if (first && i >= 4 && rl == 0) wc = 0.0;  // row 0 above K = N mirrors its lower half
+          if (first && i == 4 && t == 0) {
+            if (rl == 0) {  // k = N
+              d = stencil_fwd_r<T>(N, N, yN1, T(0), invN, inv4N1);
+              wc = 0.5;
+            } else {  // k = N - 1
+              d = stencil_fwd_r<T>(N - 1, N, yN2, yN, invN, inv4N1);
+            }
+          }
+          c0acc -= wc * (double)d;
+          if (rl == 0) dr[i] = d;
+          else di[i] = d;
+        }
+      }
+      dct2_store(k1, dr, di);
     }
-  }
-  if (!TRANS) {
     const double tot = block_sum(c0acc, red);
-    if (t == 0) part[(int64_t)comp * nt + tile] = tot;
+    if (t == 0) part[(int64_t)comp * nt + tile] = tot * (double)N;
+  } else {
+    T p0;
+    {
+      double acc = 0.0;
+      for (int n2 = t; n2 <= half2; n2 += NTHR) acc += (double)Gc[n2].x * ((n2 == 0 || n2 == half2) ? 1.0 : 2.0);
+      p0 = (T)(0.5 * block_sum(acc, red));
+    }
+    // one DCT-1 row pair (k1a, k1a + 1) into registers: element m = t + i NTHR
+    auto dct1_pair = [&](int k1a, T (&vr)[kPPT], T (&vi)[kPPT]) {
+      int ma, mb;
+      const int sa = hrow_src(k1a, L1, &ma);
+      const int sb = hrow_src(k1a + 1, L1, &mb);
+      const cplx<T>* ga = Gc + (int64_t)sa * sgi;
+      const cplx<T>* gb = Gc + (int64_t)sb * sgi;
+      cplx<T> a[kPPT], b[kPPT];
+#pragma unroll
+      for (int i = 0; i < kPPT; ++i) {
+        const int m = t + i * NTHR;
+        const int gi = m <= half2 ? m : L2 - m;
+        a[i] = ga[gi];
+        b[i] = gb[gi];
+      }
+#pragma unroll
+      for (int i = 0; i < kPPT; ++i) {
+        const int m = t + i * NTHR;
+        const int gi = m <= half2 ? m : L2 - m;
+        cplx<T> aa = a[i], bb = b[i];
+        if (ma) aa = conjg<T>(aa);
+        if (ma == 2) aa = cmul<T>(aa, tw[gi << twsh]);
+        if (mb) bb = conjg<T>(bb);
+        if (mb == 2) bb = cmul<T>(bb, tw[gi << twsh]);
+        pack(m, aa.x, aa.y, bb.x, bb.y, vr[i], vi[i]);
+      }
+      fft_regs<T, LOGL2>(Yre, vr, vi, tw);
+    };
+    // window: rows k1 - 1, k1 (pa*) and k1 + 1, k1 + 2 (pb*) around the pair k1 = t0 + 2q
+    T par[kPPT], pai[kPPT];
+    dct1_pair(t0 - 1, par, pai);
+#pragma unroll
+    for (int q = 0; q < TB / 2; ++q) {
+      const int k1 = t0 + 2 * q;
+      T pbr[kPPT], pbi[kPPT];
+      dct1_pair(k1 + 1, pbr, pbi);
+      // stencil of rows k1 and k1 + 1; rows k1 - 1, k1, k1 + 1, k1 + 2 = par, pai, pbr, pbi
+      T dr[kPPT], di[kPPT];
+      if (t0 >= 2) {
+        // rows k1 >= 2: every coefficient index k = K or 2N - K lies in [2, N - 2], and
+        // K <= N exactly when m < L2 / 2, i.e. for the thread's elements i < 4; there
+        // stencil_tr is -p0 / (j^2 - 1) + (Ym / (j - 1) - Yp / (j + 1)) / 4
+#pragma unroll
+        for (int i = 0; i < kPPT; ++i) {
+          const int m = t + i * NTHR;
+#pragma unroll
+          for (int rl = 0; rl < 2; ++rl) {
+            const int K = k1 + rl + L1 * m;
+            const int k = i < 4 ? K : N2 - K;
+            const T ylo = rl ? pai[i] : par[i];
+            const T yhi = rl ? pbi[i] : pbr[i];
+            const T Ym = i < 4 ? ylo : yhi;
+            const T Yp = i < 4 ? yhi : ylo;
+            const T rm = recip_int<T>(T(k - 1)), rp = recip_int<T>(T(k + 1));
+            const T d = -p0 * rm * rp + T(0.25) * (Ym * rm - Yp * rp);
+            if (rl == 0) dr[i] = d;
+            else di[i] = d;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < kPPT; ++i) {
+          const int m = t + i * NTHR;
+#pragma unroll
+          for (int rl = 0; rl < 2; ++rl) {
+            const int K = k1 + rl + L1 * m;
+            const T ylo = rl ? pai[i] : par[i];
+            const T yhi = rl ? pbi[i] : pbr[i];
+            const bool lowhalf = K <= N;
+            const int k = lowhalf ? K : N2 - K;
+            const T d = stencil_tr_r<T>(k, N, lowhalf ? ylo : yhi, lowhalf ? yhi : ylo, p0, inv2N1);
+            if (rl == 0) dr[i] = d;
+            else di[i] = d;
+          }
+        }
+      }
+      dct2_store(k1, dr, di);
+#pragma unroll
+      for (int i = 0; i < kPPT; ++i) {
+        par[i] = pbr[i];
+        pai[i] = pbi[i];
+      }
+    }
   }
 }
 
@@ -1005,6 +1077,8 @@ __global__ __launch_bounds__(512) void k_fastC(const cplx<T>* __restrict__ G2, i
 
 // ---- passes A and C at fixed lengths (L1 = 2^LOGL1, W = 2^LOGW columns per tile,
 // blockDim = W L1 / 16: one radix-8 butterfly per thread per stage) ----
+// Pass A: every thread issues all of its loads (PER values) at once, and its NO outputs
+// are one unrolled batch (their twiddle reads in flight together).
 template <typename T, int LOGL1, int LOGW>
 __global__ __launch_bounds__((1 << LOGW) << (LOGL1 - 4)) void k_fastA2(
     const T* __restrict__ x, int64_t Nn, int logL2, cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg,
@@ -1015,6 +1089,9 @@ __global__ __launch_bounds__((1 << LOGW) << (LOGL1 - 4)) void k_fastA2(
   constexpr int LD = padded_ld(L1);
   constexpr int NIN = W * L1;
   constexpr int PER = NIN / NTHR;  // 16 values per thread
+  constexpr int half1 = L1 / 2;
+  constexpr int NOUT = (half1 + 1) * W;
+  constexpr int NO = (NOUT + NTHR - 1) / NTHR;  // outputs per thread (the last one for few threads)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* A = reinterpret_cast<T*>(smem_raw);
   int comp, tile;
@@ -1022,53 +1099,40 @@ __global__ __launch_bounds__((1 << LOGW) << (LOGL1 - 4)) void k_fastA2(
   const T* xc = x + (int64_t)comp * Nn;
   const int N = (int)(Nn - 1), N2 = 2 * N;
   const int c0 = tile * W;
+  const int t = (int)threadIdx.x;
+  T val[PER];
 #pragma unroll
-  for (int h = 0; h < PER; h += 8) {
-    T val[8];
+  for (int u = 0; u < PER; ++u) {
+    const int e = t + u * NTHR;
+    const int w = e & (W - 1), n1 = e >> LOGW;
+    const int m = (n1 << logL2) + c0 + w;
+    const int idx = m <= N ? m : N2 - m;
+    val[u] = xc[idx];
+    if (ends2 && (idx == 0 || idx == N)) val[u] *= T(2);
+  }
+  const int L2h = (1 << logL2) / 2;
+  const int tmask = (1 << tsh) - 1;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = (int)threadIdx.x + (h + u) * NTHR;
-      const int w = e & (W - 1), n1 = e >> LOGW;
-      const int m = (n1 << logL2) + c0 + w;
-      const int idx = m <= N ? m : N2 - m;
-      val[u] = xc[idx];
-      if (ends2 && (idx == 0 || idx == N)) val[u] *= T(2);
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = (int)threadIdx.x + (h + u) * NTHR;
-      const int w = e & (W - 1), n1 = e >> LOGW;
-      A[w * LD + pad(n1)] = val[u];
-    }
+  for (int u = 0; u < PER; ++u) {
+    const int e = t + u * NTHR;
+    const int w = e & (W - 1), n1 = e >> LOGW;
+    A[w * LD + pad(n1)] = val[u];
   }
   __syncthreads();
   fft_ct<T, LOGL1, W / 2>(A, tw);
-  constexpr int half1 = L1 / 2;
   cplx<T>* Gc = G + (int64_t)comp * gcomp;
-  constexpr int NOUT = (half1 + 1) * W;
-  const int L2h = (1 << logL2) / 2;
-  const int tmask = (1 << tsh) - 1;
-  for (int base = threadIdx.x; base < NOUT; base += 4 * NTHR) {
-    cplx<T> v[4];
-    int gi[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = base + u * NTHR;
-      gi[u] = -1;
-      const int w = e & (W - 1), k1 = e >> LOGW;
-      const int n2 = c0 + w;
-      if (e < NOUT && n2 <= L2h) {
-        const int t = n2 * k1;
-        const cplx<T> tws = cmul<T>(thi[t >> tsh], tlo[t & tmask]);
-        const T* re = A + (w & ~1) * LD;
-        const int km = (L1 - k1) & (L1 - 1);
-        v[u] = cmul<T>(separate<T>(re[pad(k1)], re[LD + pad(k1)], re[pad(km)], re[LD + pad(km)], w & 1), tws);
-        gi[u] = k1 * (int)sg + n2;
-      }
+  for (int u = 0; u < NO; ++u) {
+    const int e = t + u * NTHR;
+    const int w = e & (W - 1), k1 = e >> LOGW;
+    const int n2 = c0 + w;
+    if (e < NOUT && n2 <= L2h) {
+      const T* re = A + (w & ~1) * LD;
+      const int km = (L1 - k1) & (L1 - 1);
+      Gc[k1 * (int)sg + n2] =
+          cmul<T>(separate<T>(re[pad(k1)], re[LD + pad(k1)], re[pad(km)], re[LD + pad(km)], w & 1),
+                  cmul<T>(thi[(n2 * k1) >> tsh], tlo[(n2 * k1) & tmask]));
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (gi[u] >= 0) Gc[gi[u]] = v[u];
   }
 }
 
@@ -1091,44 +1155,44 @@ __global__ __launch_bounds__((1 << LOGW) << (LOGL1 - 4)) void k_fastC2(
   const int N = (int)(Nn - 1);
   const int c0 = tile * W;
   const int sg2i = (int)sg2;
+  // all G2 loads of the thread at once (the last one for few threads), then the c^_0
+  // total, whose reads and block sum overlap their latency
+  const cplx<T>* G2c = G2 + (int64_t)comp * g2comp;
+  constexpr int NIN = NP * hp1;
+  constexpr int NI = (NIN + NTHR - 1) / NTHR;
+  const int t = (int)threadIdx.x;
+  cplx<T> ra[NI], rb[NI];
+#pragma unroll
+  for (int u = 0; u < NI; ++u) {
+    const int e = t + u * NTHR;
+    ra[u] = rb[u] = mk<T>(T(0), T(0));
+    if (e < NIN) {
+      // G2 row r holds q = 0..L2/2 contiguously: the W columns of this tile are one
+      // contiguous segment per row
+      const int r = e / NP, pr = e - r * NP;
+      const int qa = c0 + 2 * pr, qb = qa + 1;
+      if (qa <= half2) ra[u] = G2c[r * sg2i + qa];
+      if (qb <= half2) rb[u] = G2c[r * sg2i + qb];
+    }
+  }
   T c0hat = T(0);
   if (!TRANS) {
     double acc = 0.0;
-    for (int i = threadIdx.x; i < ntB; i += NTHR) acc += part[(int64_t)comp * ntB + i];
+    for (int i = t; i < ntB; i += NTHR) acc += part[(int64_t)comp * ntB + i];
     c0hat = (T)(block_sum(acc, red) / (double)N);
   }
-  const cplx<T>* G2c = G2 + (int64_t)comp * g2comp;
-  constexpr int NIN = NP * hp1;
-  for (int base = threadIdx.x; base < NIN; base += 4 * NTHR) {
-    cplx<T> ra[4], rb[4];
-    int pr_[4], r_[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = base + u * NTHR;
-      pr_[u] = -1;
-      if (e < NIN) {
-        // G2 row r holds q = 0..L2/2 contiguously: the W columns of this tile are one
-        // contiguous segment per row
-        const int r = e / NP, pr = e - r * NP;
-        const int qa = c0 + 2 * pr, qb = qa + 1;
-        ra[u] = qa <= half2 ? G2c[r * sg2i + qa] : mk<T>(T(0), T(0));
-        rb[u] = qb <= half2 ? G2c[r * sg2i + qb] : mk<T>(T(0), T(0));
-        pr_[u] = pr;
-        r_[u] = r;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (pr_[u] < 0) continue;
-      const int r = r_[u];
-      T* re = U + (2 * pr_[u]) * LD;
-      T* im = re + LD;
-      re[pad(r)] = ra[u].x - rb[u].y;
-      im[pad(r)] = ra[u].y + rb[u].x;
-      if (r > 0 && r < half1) {
-        re[pad(L1 - r)] = ra[u].x + rb[u].y;
-        im[pad(L1 - r)] = rb[u].x - ra[u].y;
-      }
+  for (int u = 0; u < NI; ++u) {
+    const int e = t + u * NTHR;
+    if (e >= NIN) continue;
+    const int r = e / NP, pr = e - r * NP;
+    T* re = U + (2 * pr) * LD;
+    T* im = re + LD;
+    re[pad(r)] = ra[u].x - rb[u].y;
+    im[pad(r)] = ra[u].y + rb[u].x;
+    if (r > 0 && r < half1) {
+      re[pad(L1 - r)] = ra[u].x + rb[u].y;
+      im[pad(L1 - r)] = rb[u].x - ra[u].y;
     }
   }
   __syncthreads();
@@ -1207,7 +1271,8 @@ static void fast_shape(const FastKnobs& kn, int64_t N, int& logL1, int& logL2, i
 static bool use_b2(const FastKnobs& kn, int logL2) { return kn.b2 && logL2 >= 9 && logL2 <= 11; }
 static int b2_rows(const FastKnobs& kn) { return kn.tb == 4 ? 4 : 2; }
 
-// Pass-B tiles per component (rows 0..L1/2 in tiles of TB, or of 2 for the register kernel).
+// Pass-B tiles per component (rows 0..L1/2 in tiles of TB, or of 2 or 4 for the register
+// kernels).
 template <typename T>
 static int fast_tiles_b(const FastKnobs& kn, int64_t N) {
   int logL1, logL2, WA, TB, WC;
