@@ -683,13 +683,28 @@ __device__ __forceinline__ void blu_rows_body(cplx<T>* __restrict__ tmp, const P
   constexpr int W = 1 << LOGW;
   const int r0 = ty << LOGW;
   cplx<T>* ts = tmp + d.work + ((int64_t)r0 << LOGM2);
-  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) sput<T, LOGM2>(sm, e >> LOGM2, e & (M2 - 1), ts[e]);
+  const cplx<T>* filt = (const cplx<T>*)d.filt[pi] + ((int64_t)r0 << LOGM2);
+  constexpr int PER = kLdsMax / kBluThreads;
+  // the tile and its filter spectrum are read in one batch
+  cplx<T> v[PER], fv[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = (int)threadIdx.x + i * kBluThreads;
+    v[i] = ts[e];
+    fv[i] = filt[e];
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = (int)threadIdx.x + i * kBluThreads;
+    sput<T, LOGM2>(sm, e >> LOGM2, e & (M2 - 1), v[i]);
+  }
   __syncthreads();
   fast::fft_ct<T, LOGM2, W>(sm, tw);
-  const cplx<T>* filt = (const cplx<T>*)d.filt[pi] + ((int64_t)r0 << LOGM2);
-  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = (int)threadIdx.x + i * kBluThreads;
     const int w = e >> LOGM2, k2 = e & (M2 - 1);
-    sput<T, LOGM2>(sm, w, k2, cconj<T>(cmul<T>(sget<T, LOGM2>(sm, w, k2), filt[e])));
+    sput<T, LOGM2>(sm, w, k2, cconj<T>(cmul<T>(sget<T, LOGM2>(sm, w, k2), fv[i])));
   }
   __syncthreads();
   fast::fft_ct<T, LOGM2, W>(sm, tw);
@@ -724,17 +739,31 @@ __device__ __forceinline__ void blu_icols_body(const cplx<T>* __restrict__ tmp, 
   const int logM2 = d.logM2;
   const int c0 = ty << LOGW;
   const cplx<T>* ts = tmp + d.work;
-  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
-    const int w = e & (W - 1), k1 = e >> LOGW;
-    sput<T, LOGM1>(sm, w, k1, cconj<T>(ts[((int64_t)k1 << logM2) + c0 + w]));
+  const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
+  constexpr int PER = kLdsMax / kBluThreads;
+  // the tile and the chirp of its outputs n = M2 n1 + n2 <= N are read in one batch
+  cplx<T> v[PER], cv[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = (int)threadIdx.x + i * kBluThreads;
+    const int w = e & (W - 1), k = e >> LOGW;
+    const int64_t idx = ((int64_t)k << logM2) + c0 + w;
+    v[i] = ts[idx];
+    cv[i] = idx <= d.N ? chirp[idx] : mk<T>(T(0), T(0));
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = (int)threadIdx.x + i * kBluThreads;
+    sput<T, LOGM1>(sm, e & (W - 1), e >> LOGW, cconj<T>(v[i]));
   }
   __syncthreads();
   fast::fft_ct<T, LOGM1, W>(sm, tw);
-  const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
-  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = (int)threadIdx.x + i * kBluThreads;
     const int w = e & (W - 1), n1 = e >> LOGW;
     const int64_t idx = ((int64_t)n1 << logM2) + c0 + w;
-    if (idx <= d.N) Y[d.work + idx] = cmul<T>(cconj<T>(sget<T, LOGM1>(sm, w, n1)), chirp[idx]);
+    if (idx <= d.N) Y[d.work + idx] = cmul<T>(cconj<T>(sget<T, LOGM1>(sm, w, n1)), cv[i]);
   }
 }
 
