@@ -30,6 +30,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -643,19 +645,44 @@ __device__ __forceinline__ void blu_cols_body(const T* __restrict__ x, const cpl
   const int logM2 = d.logM2;
   const int c0 = ty << LOGW;
   const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
-  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
-    const int w = e & (W - 1), n1 = e >> LOGW;
-    sput<T, LOGM1>(sm, w, n1, blu_in<T>(d, x, dz, src_x, ends2, chirp, ((int64_t)n1 << logM2) + c0 + w));
-  }
-  __syncthreads();
-  fast::fft_ct<T, LOGM1, W>(sm, tw);
   const cplx<T>* thi = (const cplx<T>*)d.thi[pi];
   const cplx<T>* tlo = (const cplx<T>*)d.tlo[pi];
   cplx<T>* ts = tmp + d.work;
-  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
-    const int w = e & (W - 1), k1 = e >> LOGW;
-    const int64_t t = (int64_t)(c0 + w) * k1;
-    ts[((int64_t)k1 << logM2) + c0 + w] = cmul<T>(sget<T, LOGM1>(sm, w, k1), tw4<T>(thi, tlo, d.tw_shift, t, 0));
+  if constexpr (sizeof(T) == 8 && std::is_floating_point<T>::value) {
+    // double: a thread's outputs k1 = k1_0 + i s (s = blockDim / W) share the column n2, so
+    // their twiddles W_M^(n2 k1) are W_M^(n2 k1_0) times powers of W_M^(n2 s): two table
+    // reads issued with the inputs, and at most seven rounded products per twiddle
+    constexpr int PER = kLdsMax / kBluThreads;
+    constexpr int S = kBluThreads >> LOGW;
+    const int w = (int)threadIdx.x & (W - 1), k10 = (int)threadIdx.x >> LOGW;
+    const int n2 = c0 + w;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int n1 = k10 + i * S;
+      sput<T, LOGM1>(sm, w, n1, blu_in<T>(d, x, dz, src_x, ends2, chirp, ((int64_t)n1 << logM2) + n2));
+    }
+    cplx<T> wv = tw4<T>(thi, tlo, d.tw_shift, (int64_t)n2 * k10, 0);
+    const cplx<T> ws = tw4<T>(thi, tlo, d.tw_shift, (int64_t)n2 * S, 0);
+    __syncthreads();
+    fast::fft_ct<T, LOGM1, W>(sm, tw);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int k1 = k10 + i * S;
+      ts[((int64_t)k1 << logM2) + n2] = cmul<T>(sget<T, LOGM1>(sm, w, k1), wv);
+      wv = cmul<T>(wv, ws);
+    }
+  } else {
+    for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+      const int w = e & (W - 1), n1 = e >> LOGW;
+      sput<T, LOGM1>(sm, w, n1, blu_in<T>(d, x, dz, src_x, ends2, chirp, ((int64_t)n1 << logM2) + c0 + w));
+    }
+    __syncthreads();
+    fast::fft_ct<T, LOGM1, W>(sm, tw);
+    for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+      const int w = e & (W - 1), k1 = e >> LOGW;
+      const int64_t t = (int64_t)(c0 + w) * k1;
+      ts[((int64_t)k1 << logM2) + c0 + w] = cmul<T>(sget<T, LOGM1>(sm, w, k1), tw4<T>(thi, tlo, d.tw_shift, t, 0));
+    }
   }
 }
 
@@ -707,12 +734,29 @@ __device__ __forceinline__ void blu_rows_body(cplx<T>* __restrict__ tmp, const P
     sput<T, LOGM2>(sm, w, k2, cconj<T>(cmul<T>(sget<T, LOGM2>(sm, w, k2), fv[i])));
   }
   __syncthreads();
-  fast::fft_ct<T, LOGM2, W>(sm, tw);
   const cplx<T>* thi = (const cplx<T>*)d.thi[pi];
   const cplx<T>* tlo = (const cplx<T>*)d.tlo[pi];
-  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
-    const int w = e >> LOGM2, n2 = e & (M2 - 1);
-    ts[e] = cmul<T>(cconj<T>(sget<T, LOGM2>(sm, w, n2)), tw4<T>(thi, tlo, d.tw_shift, (int64_t)n2 * (r0 + w), 1));
+  if constexpr (sizeof(T) == 8 && std::is_floating_point<T>::value && LOGM2 <= 9) {
+    // double, rows of at most blockDim points: a thread's elements share n2 and step
+    // through rows w = w_0 + i s, so their twiddles W_M^(-n2 (r0 + w)) are powers of one
+    // step times a base (read before the second transform)
+    constexpr int S = kBluThreads >> LOGM2;
+    const int n2 = (int)threadIdx.x & (M2 - 1), w0 = (int)threadIdx.x >> LOGM2;
+    cplx<T> wv = tw4<T>(thi, tlo, d.tw_shift, (int64_t)n2 * (r0 + w0), 1);
+    const cplx<T> ws = tw4<T>(thi, tlo, d.tw_shift, (int64_t)n2 * S, 1);
+    fast::fft_ct<T, LOGM2, W>(sm, tw);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int w = w0 + i * S;
+      ts[(w << LOGM2) + n2] = cmul<T>(cconj<T>(sget<T, LOGM2>(sm, w, n2)), wv);
+      wv = cmul<T>(wv, ws);
+    }
+  } else {
+    fast::fft_ct<T, LOGM2, W>(sm, tw);
+    for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+      const int w = e >> LOGM2, n2 = e & (M2 - 1);
+      ts[e] = cmul<T>(cconj<T>(sget<T, LOGM2>(sm, w, n2)), tw4<T>(thi, tlo, d.tw_shift, (int64_t)n2 * (r0 + w), 1));
+    }
   }
 }
 
