@@ -31,6 +31,7 @@
 #include <cmath>
 #include <cstdio>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "birk_fft.h"
@@ -775,6 +776,18 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB3(
   // column transform of DCT 2 on d(k1) + i d(k1 + 1); the separation needs the mirror
   // element L2 - q, held by another thread, so the outputs go through LDS once
   auto dct2_store = [&](int k1, T (&dr)[kPPT], T (&di)[kPPT]) {
+    // double: the twiddles W_2N^(r qq), qq = t + u NTHR, of row r are W_2N^(r t) times
+    // powers of W_2N^(r NTHR); the four table reads are issued before the transform
+    constexpr bool kStep = std::is_same<T, double>::value;
+    cplx<T> wb[2], wst[2];
+    if constexpr (kStep) {
+#pragma unroll
+      for (int rl = 0; rl < 2; ++rl) {
+        const int r = k1 + rl, ta = r * t, tb = r * NTHR;
+        wb[rl] = cmul<T>(thi[ta >> tsh], tlo[ta & tmask]);
+        wst[rl] = cmul<T>(thi[tb >> tsh], tlo[tb & tmask]);
+      }
+    }
     fft_regs<T, LOGL2>(Yre, dr, di, tw);
     __syncthreads();
 #pragma unroll
@@ -796,10 +809,14 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB3(
           const int r = k1 + rl;
           if (r > L1 / 2) continue;
           const int tt = r * qq;
-          const cplx<T> w = cmul<T>(thi[tt >> tsh], tlo[tt & tmask]);
+          const cplx<T> w = kStep ? wb[rl] : cmul<T>(thi[tt >> tsh], tlo[tt & tmask]);
           const cplx<T> v = separate<T>(dr[u], di[u], mr, mi, rl);
           G2c[r * sg2i + qq] = cmul<T>(v, w);
         }
+      }
+      if constexpr (kStep) {
+#pragma unroll
+        for (int rl = 0; rl < 2; ++rl) wb[rl] = cmul<T>(wb[rl], wst[rl]);
       }
     }
   };
@@ -1112,6 +1129,18 @@ __global__ __launch_bounds__((1 << LOGW) << (LOGL1 - 4)) void k_fastA2(
   }
   const int L2h = (1 << logL2) / 2;
   const int tmask = (1 << tsh) - 1;
+  // double: the thread's outputs share n2 and step through k1 = k1_0 + u NTHR / W, so
+  // their twiddles W_2N^(n2 k1) are a base times powers of one step (four table reads,
+  // issued with the inputs)
+  constexpr bool kStep = std::is_same<T, double>::value;
+  constexpr int S = NTHR / W;
+  const int n2t = c0 + (t & (W - 1)), k10 = t >> LOGW;
+  cplx<T> wv, ws;
+  if constexpr (kStep) {
+    const int ta = n2t * k10, tb = n2t * S;
+    wv = cmul<T>(thi[ta >> tsh], tlo[ta & tmask]);
+    ws = cmul<T>(thi[tb >> tsh], tlo[tb & tmask]);
+  }
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int e = t + u * NTHR;
@@ -1129,10 +1158,11 @@ __global__ __launch_bounds__((1 << LOGW) << (LOGL1 - 4)) void k_fastA2(
     if (e < NOUT && n2 <= L2h) {
       const T* re = A + (w & ~1) * LD;
       const int km = (L1 - k1) & (L1 - 1);
+      const cplx<T> tws = kStep ? wv : cmul<T>(thi[(n2 * k1) >> tsh], tlo[(n2 * k1) & tmask]);
       Gc[k1 * (int)sg + n2] =
-          cmul<T>(separate<T>(re[pad(k1)], re[LD + pad(k1)], re[pad(km)], re[LD + pad(km)], w & 1),
-                  cmul<T>(thi[(n2 * k1) >> tsh], tlo[(n2 * k1) & tmask]));
+          cmul<T>(separate<T>(re[pad(k1)], re[LD + pad(k1)], re[pad(km)], re[LD + pad(km)], w & 1), tws);
     }
+    if constexpr (kStep) wv = cmul<T>(wv, ws);
   }
 }
 
