@@ -906,11 +906,13 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB3(
     const double tot = block_sum(c0acc, red);
     if (t == 0) part[(int64_t)comp * nt + tile] = tot * (double)N;
   } else {
-    T p0;
-    {
-      double acc = 0.0;
-      for (int n2 = t; n2 <= half2; n2 += NTHR) acc += (double)Gc[n2].x * ((n2 == 0 || n2 == half2) ? 1.0 : 2.0);
-      p0 = (T)(0.5 * block_sum(acc, red));
+    // p0 = (row 0 summed over n2) / 2: its reads are issued before the first row pair's,
+    // and its block sum follows that pair's transform
+    double p0acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < (hp1 + NTHR - 1) / NTHR; ++u) {
+      const int n2 = t + u * NTHR;
+      if (n2 <= half2) p0acc += (double)Gc[n2].x * ((n2 == 0 || n2 == half2) ? 1.0 : 2.0);
     }
     // one DCT-1 row pair (k1a, k1a + 1) into registers: element m = t + i NTHR
     auto dct1_pair = [&](int k1a, T (&vr)[kPPT], T (&vi)[kPPT]) {
@@ -943,6 +945,7 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB3(
     // window: rows k1 - 1, k1 (pa*) and k1 + 1, k1 + 2 (pb*) around the pair k1 = t0 + 2q
     T par[kPPT], pai[kPPT];
     dct1_pair(t0 - 1, par, pai);
+    const T p0 = (T)(0.5 * block_sum(p0acc, red));
 #pragma unroll
     for (int q = 0; q < TB / 2; ++q) {
       const int k1 = t0 + 2 * q;
