@@ -593,31 +593,44 @@ __device__ __forceinline__ void blu_lds_body(const T* __restrict__ x, const cplx
   constexpr int pi = prec_index<T>();
   constexpr int M = 1 << LOGM;
   constexpr int COUNT = kLdsMax >> LOGM;
-  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+  constexpr int PER = kLdsMax / kBluThreads;
+  // the inputs, the filter spectra and the chirp of the outputs are read in one batch
+  cplx<T> v[PER], fv[PER], cv[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = (int)threadIdx.x + i * kBluThreads;
     const int t = e >> LOGM, n = e & (M - 1);
-    cplx<T> v = mk<T>(T(0), T(0));
+    v[i] = fv[i] = cv[i] = mk<T>(T(0), T(0));
     if (t < tile.y) {
       const PairDesc& d = pd[tile.x + t];
-      v = blu_in<T>(d, x, dz, src_x, ends2, (const cplx<T>*)d.chirp[pi], n);
+      const cplx<T>* chirp = (const cplx<T>*)d.chirp[pi];
+      v[i] = blu_in<T>(d, x, dz, src_x, ends2, chirp, n);
+      fv[i] = ((const cplx<T>*)d.filt[pi])[n];
+      if (n <= d.N) cv[i] = chirp[n];
     }
-    sput<T, LOGM>(sm, t, n, v);
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = (int)threadIdx.x + i * kBluThreads;
+    sput<T, LOGM>(sm, e >> LOGM, e & (M - 1), v[i]);
   }
   __syncthreads();
   fast::fft_ct<T, LOGM, COUNT>(sm, tw);
-  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = (int)threadIdx.x + i * kBluThreads;
     const int t = e >> LOGM, k = e & (M - 1);
-    if (t < tile.y) {
-      const cplx<T>* filt = (const cplx<T>*)pd[tile.x + t].filt[pi];
-      sput<T, LOGM>(sm, t, k, cconj<T>(cmul<T>(sget<T, LOGM>(sm, t, k), filt[k])));
-    }
+    if (t < tile.y) sput<T, LOGM>(sm, t, k, cconj<T>(cmul<T>(sget<T, LOGM>(sm, t, k), fv[i])));
   }
   __syncthreads();
   fast::fft_ct<T, LOGM, COUNT>(sm, tw);
-  for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = (int)threadIdx.x + i * kBluThreads;
     const int t = e >> LOGM, k = e & (M - 1);
     if (t < tile.y) {
       const PairDesc& d = pd[tile.x + t];
-      if (k <= d.N) Y[d.work + k] = cmul<T>(cconj<T>(sget<T, LOGM>(sm, t, k)), ((const cplx<T>*)d.chirp[pi])[k]);
+      if (k <= d.N) Y[d.work + k] = cmul<T>(cconj<T>(sget<T, LOGM>(sm, t, k)), cv[i]);
     }
   }
 }
