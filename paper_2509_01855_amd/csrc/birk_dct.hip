@@ -661,10 +661,11 @@ __device__ __forceinline__ void blu_cols_body(const T* __restrict__ x, const cpl
   const cplx<T>* thi = (const cplx<T>*)d.thi[pi];
   const cplx<T>* tlo = (const cplx<T>*)d.tlo[pi];
   cplx<T>* ts = tmp + d.work;
-  if constexpr (sizeof(T) == 8 && std::is_floating_point<T>::value) {
-    // double: a thread's outputs k1 = k1_0 + i s (s = blockDim / W) share the column n2, so
-    // their twiddles W_M^(n2 k1) are W_M^(n2 k1_0) times powers of W_M^(n2 s): two table
-    // reads issued with the inputs, and at most seven rounded products per twiddle
+  if constexpr (std::is_floating_point<T>::value) {
+    // double and float: a thread's outputs k1 = k1_0 + i s (s = blockDim / W) share the
+    // column n2, so their twiddles W_M^(n2 k1) are W_M^(n2 k1_0) times powers of W_M^(n2 s):
+    // two reads of the double table issued with the inputs, the powers formed in double
+    // (at most seven rounded products per twiddle)
     constexpr int PER = kLdsMax / kBluThreads;
     constexpr int S = kBluThreads >> LOGW;
     const int w = (int)threadIdx.x & (W - 1), k10 = (int)threadIdx.x >> LOGW;
@@ -674,15 +675,17 @@ __device__ __forceinline__ void blu_cols_body(const T* __restrict__ x, const cpl
       const int n1 = k10 + i * S;
       sput<T, LOGM1>(sm, w, n1, blu_in<T>(d, x, dz, src_x, ends2, chirp, ((int64_t)n1 << logM2) + n2));
     }
-    cplx<T> wv = tw4<T>(thi, tlo, d.tw_shift, (int64_t)n2 * k10, 0);
-    const cplx<T> ws = tw4<T>(thi, tlo, d.tw_shift, (int64_t)n2 * S, 0);
+    const cplx<double>* thd = (const cplx<double>*)d.thi[0];
+    const cplx<double>* tld = (const cplx<double>*)d.tlo[0];
+    cplx<double> wv = tw4<double>(thd, tld, d.tw_shift, (int64_t)n2 * k10, 0);
+    const cplx<double> ws = tw4<double>(thd, tld, d.tw_shift, (int64_t)n2 * S, 0);
     __syncthreads();
     fast::fft_ct<T, LOGM1, W>(sm, tw);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int k1 = k10 + i * S;
-      ts[((int64_t)k1 << logM2) + n2] = cmul<T>(sget<T, LOGM1>(sm, w, k1), wv);
-      wv = cmul<T>(wv, ws);
+      ts[((int64_t)k1 << logM2) + n2] = cmul<T>(sget<T, LOGM1>(sm, w, k1), mk<T>((T)wv.x, (T)wv.y));
+      wv = cmul<double>(wv, ws);
     }
   } else {
     for (int e = threadIdx.x; e < kLdsMax; e += kBluThreads) {
@@ -749,20 +752,23 @@ __device__ __forceinline__ void blu_rows_body(cplx<T>* __restrict__ tmp, const P
   __syncthreads();
   const cplx<T>* thi = (const cplx<T>*)d.thi[pi];
   const cplx<T>* tlo = (const cplx<T>*)d.tlo[pi];
-  if constexpr (sizeof(T) == 8 && std::is_floating_point<T>::value && LOGM2 <= 9) {
-    // double, rows of at most blockDim points: a thread's elements share n2 and step
-    // through rows w = w_0 + i s, so their twiddles W_M^(-n2 (r0 + w)) are powers of one
-    // step times a base (read before the second transform)
+  if constexpr (std::is_floating_point<T>::value && LOGM2 <= 9) {
+    // double and float, rows of at most blockDim points: a thread's elements share n2 and
+    // step through rows w = w_0 + i s, so their twiddles W_M^(-n2 (r0 + w)) are powers of
+    // one step times a base (double table, read before the second transform; powers in
+    // double)
     constexpr int S = kBluThreads >> LOGM2;
     const int n2 = (int)threadIdx.x & (M2 - 1), w0 = (int)threadIdx.x >> LOGM2;
-    cplx<T> wv = tw4<T>(thi, tlo, d.tw_shift, (int64_t)n2 * (r0 + w0), 1);
-    const cplx<T> ws = tw4<T>(thi, tlo, d.tw_shift, (int64_t)n2 * S, 1);
+    const cplx<double>* thd = (const cplx<double>*)d.thi[0];
+    const cplx<double>* tld = (const cplx<double>*)d.tlo[0];
+    cplx<double> wv = tw4<double>(thd, tld, d.tw_shift, (int64_t)n2 * (r0 + w0), 1);
+    const cplx<double> ws = tw4<double>(thd, tld, d.tw_shift, (int64_t)n2 * S, 1);
     fast::fft_ct<T, LOGM2, W>(sm, tw);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int w = w0 + i * S;
-      ts[(w << LOGM2) + n2] = cmul<T>(cconj<T>(sget<T, LOGM2>(sm, w, n2)), wv);
-      wv = cmul<T>(wv, ws);
+      ts[(w << LOGM2) + n2] = cmul<T>(cconj<T>(sget<T, LOGM2>(sm, w, n2)), mk<T>((T)wv.x, (T)wv.y));
+      wv = cmul<double>(wv, ws);
     }
   } else {
     fast::fft_ct<T, LOGM2, W>(sm, tw);

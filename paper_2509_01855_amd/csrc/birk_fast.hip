@@ -740,7 +740,8 @@ template <typename T, int TRANS, int LOGL2, int TB>
 __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB3(
     const cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg, cplx<T>* __restrict__ G2, int64_t g2comp, int64_t sg2,
     int64_t N64, int logL1, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ thi,
-    const cplx<T>* __restrict__ tlo, int tsh, double* __restrict__ part, int nt, int nc, int xcd_order) {
+    const cplx<T>* __restrict__ tlo, int tsh, const cplx<double>* __restrict__ thd,
+    const cplx<double>* __restrict__ tld, double* __restrict__ part, int nt, int nc, int xcd_order) {
   constexpr int L2 = 1 << LOGL2;
   constexpr int NTHR = L2 / kPPT;
   constexpr int half2 = L2 / 2, hp1 = half2 + 1;
@@ -776,16 +777,17 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB3(
   // column transform of DCT 2 on d(k1) + i d(k1 + 1); the separation needs the mirror
   // element L2 - q, held by another thread, so the outputs go through LDS once
   auto dct2_store = [&](int k1, T (&dr)[kPPT], T (&di)[kPPT]) {
-    // double: the twiddles W_2N^(r qq), qq = t + u NTHR, of row r are W_2N^(r t) times
-    // powers of W_2N^(r NTHR); the four table reads are issued before the transform
-    constexpr bool kStep = std::is_same<T, double>::value;
-    cplx<T> wb[2], wst[2];
+    // double and float: the twiddles W_2N^(r qq), qq = t + u NTHR, of row r are W_2N^(r t)
+    // times powers of W_2N^(r NTHR); the four reads of the double table are issued before
+    // the transform and the powers are formed in double
+    constexpr bool kStep = std::is_floating_point<T>::value;
+    cplx<double> wb[2], wst[2];
     if constexpr (kStep) {
 #pragma unroll
       for (int rl = 0; rl < 2; ++rl) {
         const int r = k1 + rl, ta = r * t, tb = r * NTHR;
-        wb[rl] = cmul<T>(thi[ta >> tsh], tlo[ta & tmask]);
-        wst[rl] = cmul<T>(thi[tb >> tsh], tlo[tb & tmask]);
+        wb[rl] = cmul<double>(thd[ta >> tsh], tld[ta & tmask]);
+        wst[rl] = cmul<double>(thd[tb >> tsh], tld[tb & tmask]);
       }
     }
     fft_regs<T, LOGL2>(Yre, dr, di, tw);
@@ -809,14 +811,14 @@ __global__ __launch_bounds__(1 << (LOGL2 - 3)) void k_fastB3(
           const int r = k1 + rl;
           if (r > L1 / 2) continue;
           const int tt = r * qq;
-          const cplx<T> w = kStep ? wb[rl] : cmul<T>(thi[tt >> tsh], tlo[tt & tmask]);
+          const cplx<T> w = kStep ? mk<T>((T)wb[rl].x, (T)wb[rl].y) : cmul<T>(thi[tt >> tsh], tlo[tt & tmask]);
           const cplx<T> v = separate<T>(dr[u], di[u], mr, mi, rl);
           G2c[r * sg2i + qq] = cmul<T>(v, w);
         }
       }
       if constexpr (kStep) {
 #pragma unroll
-        for (int rl = 0; rl < 2; ++rl) wb[rl] = cmul<T>(wb[rl], wst[rl]);
+        for (int rl = 0; rl < 2; ++rl) wb[rl] = cmul<double>(wb[rl], wst[rl]);
       }
     }
   };
@@ -1103,7 +1105,7 @@ template <typename T, int LOGL1, int LOGW>
 __global__ __launch_bounds__((1 << LOGW) << (LOGL1 - 4)) void k_fastA2(
     const T* __restrict__ x, int64_t Nn, int logL2, cplx<T>* __restrict__ G, int64_t gcomp, int64_t sg,
     const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ thi, const cplx<T>* __restrict__ tlo, int tsh,
-    int ends2, int nt, int nc, int xcd_order) {
+    const cplx<double>* __restrict__ thd, const cplx<double>* __restrict__ tld, int ends2, int nt, int nc, int xcd_order) {
   constexpr int L1 = 1 << LOGL1, W = 1 << LOGW;
   constexpr int NTHR = W * L1 / 16;
   constexpr int LD = padded_ld(L1);
@@ -1132,17 +1134,17 @@ __global__ __launch_bounds__((1 << LOGW) << (LOGL1 - 4)) void k_fastA2(
   }
   const int L2h = (1 << logL2) / 2;
   const int tmask = (1 << tsh) - 1;
-  // double: the thread's outputs share n2 and step through k1 = k1_0 + u NTHR / W, so
-  // their twiddles W_2N^(n2 k1) are a base times powers of one step (four table reads,
-  // issued with the inputs)
-  constexpr bool kStep = std::is_same<T, double>::value;
+  // double and float: the thread's outputs share n2 and step through k1 = k1_0 + u NTHR / W,
+  // so their twiddles W_2N^(n2 k1) are a base times powers of one step (four reads of the
+  // double table, issued with the inputs; the powers formed in double)
+  constexpr bool kStep = std::is_floating_point<T>::value;
   constexpr int S = NTHR / W;
   const int n2t = c0 + (t & (W - 1)), k10 = t >> LOGW;
-  cplx<T> wv, ws;
+  cplx<double> wv, ws;
   if constexpr (kStep) {
     const int ta = n2t * k10, tb = n2t * S;
-    wv = cmul<T>(thi[ta >> tsh], tlo[ta & tmask]);
-    ws = cmul<T>(thi[tb >> tsh], tlo[tb & tmask]);
+    wv = cmul<double>(thd[ta >> tsh], tld[ta & tmask]);
+    ws = cmul<double>(thd[tb >> tsh], tld[tb & tmask]);
   }
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
@@ -1161,11 +1163,11 @@ __global__ __launch_bounds__((1 << LOGW) << (LOGL1 - 4)) void k_fastA2(
     if (e < NOUT && n2 <= L2h) {
       const T* re = A + (w & ~1) * LD;
       const int km = (L1 - k1) & (L1 - 1);
-      const cplx<T> tws = kStep ? wv : cmul<T>(thi[(n2 * k1) >> tsh], tlo[(n2 * k1) & tmask]);
+      const cplx<T> tws = kStep ? mk<T>((T)wv.x, (T)wv.y) : cmul<T>(thi[(n2 * k1) >> tsh], tlo[(n2 * k1) & tmask]);
       Gc[k1 * (int)sg + n2] =
           cmul<T>(separate<T>(re[pad(k1)], re[LD + pad(k1)], re[pad(km)], re[LD + pad(km)], w & 1), tws);
     }
-    if constexpr (kStep) wv = cmul<T>(wv, ws);
+    if constexpr (kStep) wv = cmul<double>(wv, ws);
   }
 }
 
@@ -1369,6 +1371,8 @@ static hipError_t fast_passes(birk_plan* p, const FastGroup& g, const T* v, T* o
   const cplx<T>* thi = (const cplx<T>*)g.tw.hi[pi];
   const cplx<T>* tlo = (const cplx<T>*)g.tw.lo[pi];
   const int tsh = g.tw.shift;
+  const cplx<double>* thd = (const cplx<double>*)g.tw.hi[0];
+  const cplx<double>* tld = (const cplx<double>*)g.tw.lo[0];
   const int nc = g.nc;
   const int lw = fixed_logw(kn, logL1);
   if (lw > 0) {
@@ -1385,7 +1389,7 @@ static hipError_t fast_passes(birk_plan* p, const FastGroup& g, const T* v, T* o
     }
     lds_attr(f, lds);
     hipLaunchKernelGGL(f, dim3(ntA * nc), dim3(W * L1 / 16), lds, s, v + g.off, g.Nn, logL2, G, gcomp, sg, tw, thi,
-                       tlo, tsh, transpose ? 1 : 0, ntA, nc, kn.xcd);
+                       tlo, tsh, thd, tld, transpose ? 1 : 0, ntA, nc, kn.xcd);
   } else {
     const int ntA = (L2 / 2 + 1 + WA - 1) / WA;
     const int lds = WA * ld1 * (int)sizeof(T);
@@ -1416,7 +1420,7 @@ static hipError_t fast_passes(birk_plan* p, const FastGroup& g, const T* v, T* o
     }
     lds_attr(f, lds);
     hipLaunchKernelGGL(f, dim3(ntB * nc), dim3(thr), lds, s, G, gcomp, sg, G2, g2comp, sg2, g.N, logL1, tw, thi, tlo,
-                       tsh, part, ntB, nc, kn.xcd);
+                       tsh, thd, tld, part, ntB, nc, kn.xcd);
   } else if (use_b2(kn, logL2)) {
     const int lds = 2 * ld2 * (int)sizeof(T);
     const int thr = L2 / fast::kPPT;
