@@ -575,8 +575,10 @@ using namespace kkt;
 
 hipError_t plan_kkt(birk_plan* p) {
   // classes by n_x; descriptors, block and node tile lists; scan scratch offsets
+  // (the KKT preconditioner covers n_x <= 12; instances with more states get no class)
   std::vector<std::vector<int>> by(13);
-  for (int i = 0; i < (int)p->inst.size(); ++i) by[p->inst[i].nx].push_back(i);
+  for (int i = 0; i < (int)p->inst.size(); ++i)
+    if (p->inst[i].nx <= 12) by[p->inst[i].nx].push_back(i);
   int64_t soff = 0;
   hipError_t e = hipSuccess;
   for (int nx = 1; nx <= 12 && e == hipSuccess; ++nx) {
