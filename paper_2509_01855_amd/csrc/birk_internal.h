@@ -238,6 +238,9 @@ struct birk_plan {
   int pfwd_ntiles = 0;
   int2* pfwd_pairs = nullptr;       // P y scans: (instance, component)
   int pfwd_npairs = 0;
+  int2* pfwd_btiles = nullptr;      // P y, all components at once: (instance, tile)
+  int pfwd_nbtiles = 0;
+  int pfwd_maxnx = 0;               // largest n_x of the plan
   void* newton_buf = nullptr;       // Newton workspace, allocated by the first Newton solve
   std::vector<birk::BtClass> btclass;  // P^{-T} scan schedule, one class per n_x
   int64_t total_bt = 0;             // doubles of P^{-T} scan scratch

@@ -85,9 +85,11 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
 // P y = y - B~^a (J y) per component r: an exclusive prefix sum of u_k = w_k (J_k y_k)_r
 // plus half the node's own term (B~^a: w_j below the diagonal, w_k / 2 on it).  Three
 // launches: block sums over tiles of kScanBlock nodes, an exclusive scan of the block sums
-// (one workgroup per component), and the final pass, which rebuilds u and scans inside
-// the tile.  Global accesses are coalesced (node k = tile base + i * 256 + thread); the
-// final pass moves u through LDS to scan it in node order.
+// (one workgroup per component), and the final pass, which scans inside the tile.  Global
+// accesses are coalesced (node k = tile base + i * 256 + thread); the final pass moves u
+// through LDS to scan it in node order.  Double plans with n_x <= 16 form u once for all
+// components (k_pfwd_sums_all, u kept in out); otherwise each component's passes rebuild
+// their u_r from J and y.
 
 // One workgroup per tile of kScanBlock nodes of one component of one instance, over the
 // whole batch: tile = (instance, component * ntiles + tile index); the tile sums of
@@ -200,10 +202,124 @@ __global__ __launch_bounds__(256) void k_pfwd_final(const int2* __restrict__ til
   }
 }
 
+// Double plans with n_x <= 16: one workgroup per tile forms u_k = w_k J_k y_k for all
+// components (J and y read once), stores u in out (which does not overlap y) and sums it
+// per component; the final pass of component r then reads u_r back instead of J and all
+// of y.  Tile = (instance, tile); the sums go where k_pfwd_sums puts them.
+template <int MAXNX>
+__global__ __launch_bounds__(256) void k_pfwd_sums_all(const int2* __restrict__ tiles,
+                                                       const InstDesc* __restrict__ idesc,
+                                                       const double* __restrict__ J, int per_node,
+                                                       const double* __restrict__ y, double* __restrict__ u,
+                                                       double* __restrict__ scan) {
+  __shared__ double sh[4][MAXNX];
+  const int2 t = tiles[blockIdx.x];
+  const InstDesc d = idesc[t.x];
+  const int nt = pfwd_ntiles(d.Nn), b = t.y, nx = (int)d.nx;
+  const int64_t Nn = d.Nn;
+  const double* Ji = J + (per_node ? d.joff : d.jcoff);
+  const double* yi = y + d.off;
+  double* ui = u + d.off;
+  const int64_t base = (int64_t)b * kScanBlock;
+  double acc[MAXNX];
+#pragma unroll
+  for (int r = 0; r < MAXNX; ++r) acc[r] = 0.0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t k = base + i * 256 + threadIdx.x;
+    if (k >= Nn) break;
+    double yv[MAXNX];
+#pragma unroll
+    for (int c = 0; c < MAXNX; ++c) yv[c] = c < nx ? yi[(int64_t)c * Nn + k] : 0.0;
+    const double wk = d.w[k];
+#pragma unroll
+    for (int r = 0; r < MAXNX; ++r) {
+      if (r >= nx) break;
+      double a = 0.0;
+#pragma unroll
+      for (int c = 0; c < MAXNX; ++c) {
+        if (c >= nx) break;
+        a += (per_node ? Ji[(int64_t)(r * nx + c) * Nn + k] : Ji[r * nx + c]) * yv[c];
+      }
+      a *= wk;
+      ui[(int64_t)r * Nn + k] = a;
+      acc[r] += a;
+    }
+  }
+  const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
+#pragma unroll
+  for (int r = 0; r < MAXNX; ++r) {
+    if (r >= nx) break;
+    double v = acc[r];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (l == 0) sh[w][r] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nx) {
+    const int r = (int)threadIdx.x;
+    scan[d.scan_off + (int64_t)r * nt + b] = ((sh[0][r] + sh[1][r]) + sh[2][r]) + sh[3][r];
+  }
+}
+
+// Final pass of component r from u_r held in out (in place: a workgroup reads its tile of
+// u_r before it writes the same elements of out).
+__global__ __launch_bounds__(256) void k_pfwd_final_u(const int2* __restrict__ tiles, const InstDesc* __restrict__ idesc,
+                                                      const double* __restrict__ y, const double* __restrict__ scan,
+                                                      double* __restrict__ out) {
+  __shared__ double su[kScanBlock];
+  __shared__ double sh[256];
+  const int2 t = tiles[blockIdx.x];
+  const InstDesc d = idesc[t.x];
+  const int nt = pfwd_ntiles(d.Nn);
+  const int r = t.y / nt, b = t.y - r * nt;
+  const int64_t base = (int64_t)b * kScanBlock;
+  double* oi = out + d.off + (int64_t)r * d.Nn;
+  const double* yr = y + d.off + (int64_t)r * d.Nn;
+  double yv[kScanItems];
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t k = base + i * 256 + threadIdx.x;
+    su[i * 256 + threadIdx.x] = (k < d.Nn) ? oi[k] : 0.0;
+    yv[i] = (k < d.Nn) ? yr[k] : 0.0;
+  }
+  __syncthreads();
+  // thread t scans nodes base + kScanItems t + j, j < kScanItems, in order
+  double uu[kScanItems];
+  double tsum = 0.0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    uu[j] = su[threadIdx.x * kScanItems + j];
+    tsum += uu[j];
+  }
+  double run = scan[d.scan_off + t.y] + block_scan256(tsum, sh) - tsum;
+  // each thread rewrites only the entries it read itself
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    su[threadIdx.x * kScanItems + j] = run + 0.5 * uu[j];
+    run += uu[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t k = base + i * 256 + threadIdx.x;
+    if (k < d.Nn) oi[k] = yv[i] - su[i * 256 + threadIdx.x];
+  }
+}
+
 template <typename T>
 hipError_t precond_forward(birk_plan* p, int jac_kind, const double* J, const T* y, T* out,
                            hipStream_t s) {
   const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
+  if constexpr (std::is_same<T, double>::value) {
+    if (p->pfwd_maxnx <= 16) {
+      auto f = p->pfwd_maxnx <= 4 ? k_pfwd_sums_all<4> : p->pfwd_maxnx <= 8 ? k_pfwd_sums_all<8> : k_pfwd_sums_all<16>;
+      hipLaunchKernelGGL(f, dim3(p->pfwd_nbtiles), dim3(256), 0, s, p->pfwd_btiles, p->idesc, J, pn, y, out, p->scan);
+      hipLaunchKernelGGL(k_pfwd_scanparts, dim3(p->pfwd_npairs), dim3(256), 0, s, p->pfwd_pairs, p->idesc, p->scan);
+      hipLaunchKernelGGL(k_pfwd_final_u, dim3(p->pfwd_ntiles), dim3(256), 0, s, p->pfwd_tiles, p->idesc, y,
+                         (const double*)p->scan, out);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL(k_pfwd_sums<T>, dim3(p->pfwd_ntiles), dim3(256), 0, s, p->pfwd_tiles, p->idesc, J, pn, y,
                      p->scan);
   hipLaunchKernelGGL(k_pfwd_scanparts, dim3(p->pfwd_npairs), dim3(256), 0, s, p->pfwd_pairs, p->idesc, p->scan);
@@ -1502,6 +1618,16 @@ hipError_t plan_solve(birk_plan* p) {
     p->pfwd_ntiles = (int)tl.size();
     if ((e = upload_tiles(p, pr, &p->pfwd_pairs)) != hipSuccess) return e;
     p->pfwd_npairs = (int)pr.size();
+    std::vector<int2> bt;
+    p->pfwd_maxnx = 0;
+    for (int i = 0; i < (int)p->inst.size(); ++i) {
+      const Instance& in = p->inst[i];
+      const int nt = (int)((in.Nn + kScanBlock - 1) / kScanBlock);
+      for (int b = 0; b < nt; ++b) bt.push_back(make_int2(i, b));
+      p->pfwd_maxnx = std::max(p->pfwd_maxnx, (int)in.nx);
+    }
+    if ((e = upload_tiles(p, bt, &p->pfwd_btiles)) != hipSuccess) return e;
+    p->pfwd_nbtiles = (int)bt.size();
   }
   p->pclass.clear();
   for (int nx = 1; nx <= 12; ++nx) {

@@ -66,6 +66,25 @@ def test_precond_f64(B, kind, Nn, nx, inverse):
     assert rel_err(got, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("Nn,nx", [(300, 17), (5000, 20)])
+def test_precond_forward_many_states(B, Nn, nx):
+    """P y for n_x above 16, where each component's passes form their own u_r from J and y
+    (double plans up to n_x = 16 form u once for all components)."""
+    import torch
+    announce(f"precond forward Nn={Nn} nx={nx}")
+    inst = _inst("lti", Nn, nx, 6)
+    w = bk.weights(Nn - 1)
+    y = wl.random_vectors([6, Nn], (nx * Nn,))[0]
+    plan = B.birk_plan_create([Nn], [nx], B.BIRK_F64)
+    yd = dev(y, torch.float64)
+    out = torch.empty_like(yd)
+    B.birk_precond(plan, _J_dev(inst), yd, out, 0, B.BIRK_J_CONSTANT)
+    torch.cuda.synchronize()
+    got = host(out)
+    plan.destroy()
+    assert rel_err(got, sy.precond_apply(w, inst.J, y)) <= 1e-12
+
+
 @pytest.mark.parametrize("Nn", [(1 << 16) + 1, (1 << 20) + 1])
 def test_precond_inverse_roundtrip_large(B, Nn):
     """P (P^{-1} y) = y with P applied by the oracle (vectorised prefix sums)."""
