@@ -852,11 +852,12 @@ static hipError_t dct_blu(birk_plan* p, const PairSet& ps, const T* x, const cpl
   const cplx<T>* tw = (const cplx<T>*)p->lds_tw[prec_index<T>()];
   cplx<T>* tmp = (cplx<T>*)p->work[0];
   const size_t lds = (size_t)kBluLdsReals * sizeof(T);
-  static const bool attr = [lds] {  // above the default dynamic LDS limit in double
-    (void)hipFuncSetAttribute((const void*)k_blu_lds<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void*)k_blu_cols<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void*)k_blu_rows<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void*)k_blu_icols<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  static const bool attr = [] {  // above the default dynamic LDS limit in double
+    constexpr int b = (int)(kBluLdsReals * sizeof(T));
+    (void)hipFuncSetAttribute((const void*)k_blu_lds<T>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    (void)hipFuncSetAttribute((const void*)k_blu_cols<T>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    (void)hipFuncSetAttribute((const void*)k_blu_rows<T>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    (void)hipFuncSetAttribute((const void*)k_blu_icols<T>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     return true;
   }();
   (void)attr;
