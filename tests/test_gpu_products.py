@@ -267,14 +267,17 @@ def test_autotune_without_power_of_two_groups(B):
 # ---------------------------------------------------------------- the timed configuration
 # The benchmark times B^a and B^aT at N_n = 2^20 + 1, n_x = 6 after birk_plan_tune; the
 # tuner picks among the schedules below (split 0, two rows per pass-B tile, one to three
-# streams, four- or eight-column pass-A/C tiles).  Each is checked here on the same
+# streams, four- or eight-column pass-A/C tiles; also four rows per pass-B tile on both
+# splits, which other plans pick).  Each is checked here on the same
 # inputs: a random dense v at 16 rows (96 outputs) through O(N log N) rows and columns of
 # the oracle, and six exact series (Chebyshev modes for B^a, node-sparse right-hand
 # sides for B^aT) at every output.
 HEAD_NN, HEAD_NX = (1 << 20) + 1, 6
 HEAD_SCHEDULES = [{"BIRK_FAST_SPLIT": "0", "BIRK_FAST_TB": "2", "BIRK_FAST_XCD": "1",
                    "BIRK_FAST_NARROW": nw, "BIRK_FAST_STREAMS": st}
-                  for nw in ("0", "1") for st in ("1", "2", "3")] + ["tuned"]
+                  for nw in ("0", "1") for st in ("1", "2", "3")] + \
+                 [{"BIRK_FAST_SPLIT": sp, "BIRK_FAST_TB": "4", "BIRK_FAST_XCD": "1", "BIRK_FAST_NARROW": "1",
+                   "BIRK_FAST_STREAMS": "1"} for sp in ("0", "1")] + ["tuned"]
 
 
 @pytest.fixture(scope="module")
@@ -304,7 +307,8 @@ def head_refs():
 
 
 @pytest.mark.parametrize("sched", HEAD_SCHEDULES, ids=lambda s: "tuned" if s == "tuned" else
-                         f"narrow{s['BIRK_FAST_NARROW']}-streams{s['BIRK_FAST_STREAMS']}")
+                         f"split{s['BIRK_FAST_SPLIT']}-tb{s['BIRK_FAST_TB']}-narrow{s['BIRK_FAST_NARROW']}"
+                         f"-streams{s['BIRK_FAST_STREAMS']}")
 def test_timed_configuration_schedules(B, head_refs, sched, monkeypatch):
     import torch
     r = head_refs
