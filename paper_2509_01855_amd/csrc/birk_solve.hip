@@ -971,7 +971,10 @@ __device__ __forceinline__ void chunk_map(P Jp, int64_t jstep, int64_t js, const
 // xi_k = K_k^{-1} u, (J xi)_k = K_k^{-1} (J_k u) (J_k commutes with K_k^{-1}),
 // S <- S + w_k (J xi)_k.  BACK (P^{-T}, from the last node): x_k = K_k^{-T} (y_k +
 // w_k J_k^T T), T <- T + x_k; ji is not written.
-template <int NX, bool BACK, typename P, typename T>
+// LOUT (J_k staged in LDS, one column of 64-strided entries per node): xi_k and (J xi)_k
+// go to entries 0..NX-1 and NX..2NX-1 of the node's own column, whose J_k has been read
+// by then, and the caller stores them coalesced after the round.
+template <int NX, bool BACK, bool LOUT = false, typename P, typename T>
 __device__ __forceinline__ void chunk_replay(P Jp, int64_t jstep, int64_t js, const double* __restrict__ w,
                                              const T* __restrict__ yi, T* __restrict__ oi, T* __restrict__ ji,
                                              int64_t Nn, int64_t k0, double (&s)[NX]) {
@@ -990,7 +993,8 @@ __device__ __forceinline__ void chunk_replay(P Jp, int64_t jstep, int64_t js, co
 #pragma unroll
       for (int r = 0; r < NX; ++r) {
         s[r] += u[r];
-        oi[(int64_t)r * Nn + k] = (T)u[r];
+        if constexpr (LOUT) Jp[j * jstep + (int64_t)r * js] = u[r];
+        else oi[(int64_t)r * Nn + k] = (T)u[r];
       }
     } else {
 #pragma unroll
@@ -1001,8 +1005,13 @@ __device__ __forceinline__ void chunk_replay(P Jp, int64_t jstep, int64_t js, co
 #pragma unroll
       for (int r = 0; r < NX; ++r) {
         s[r] += wk * ju[r];
-        oi[(int64_t)r * Nn + k] = (T)u[r];
-        if (ji) ji[(int64_t)r * Nn + k] = (T)ju[r];
+        if constexpr (LOUT) {
+          Jp[j * jstep + (int64_t)r * js] = u[r];
+          Jp[j * jstep + (int64_t)(NX + r) * js] = ju[r];
+        } else {
+          oi[(int64_t)r * Nn + k] = (T)u[r];
+          if (ji) ji[(int64_t)r * Nn + k] = (T)ju[r];
+        }
       }
     }
   }
@@ -1401,13 +1410,29 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const double* __re
     const int64_t kw = g * kTileNodes + (int64_t)w * 64 * kTC;
     double pre[NX * NX];
     fetch_j<NX, BACK>(pre, J + d.joff, Nn, kw + l);
+    // the round's outputs come back through the LDS columns (xi in entries 0..NX-1, J xi in
+    // NX..2NX-1) and are stored coalesced, lane l taking node kw + 64 j + l; each lane then
+    // writes only its own column in the next put_j, so no barrier is needed between
+    constexpr bool kLout = 2 * NX <= NX * NX;
     for (int j = 0; j < kTC; ++j) {
       put_j<NX>(jw, pre, l);
       __syncthreads();
       if (j + 1 < kTC) fetch_j<NX, BACK>(pre, J + d.joff, Nn, kw + 64 * (j + 1) + l);
       if ((l >> 4) == j)
-        chunk_replay<NX, BACK>(jw + (4 * l - 64 * j), int64_t(1), int64_t(64), d.w, yi, oi, ji, Nn, k0, s);
+        chunk_replay<NX, BACK, kLout>(jw + (4 * l - 64 * j), int64_t(1), int64_t(64), d.w, yi, oi, ji, Nn, k0, s);
       __syncthreads();
+      if constexpr (kLout) {
+        const int64_t pos = kw + 64 * j + l;
+        if (pos < Nn) {
+          const int64_t k = BACK ? Nn - 1 - pos : pos;
+#pragma unroll
+          for (int r = 0; r < NX; ++r) oi[(int64_t)r * Nn + k] = (T)jw[r * 64 + l];
+          if (!BACK && ji) {
+#pragma unroll
+            for (int r = 0; r < NX; ++r) ji[(int64_t)r * Nn + k] = (T)jw[(NX + r) * 64 + l];
+          }
+        }
+      }
     }
   } else if constexpr (MODE == kFlyConst) {
     chunk_replay<NX, BACK>(J + d.jcoff, int64_t(0), int64_t(1), d.w, yi, oi, ji, Nn, k0, s);
