@@ -1017,6 +1017,56 @@ __device__ __forceinline__ void chunk_replay(P Jp, int64_t jstep, int64_t js, co
   }
 }
 
+// The same replay from LDS-staged J_k for a whole wave, in round j of the staging
+// (positions kw + 64 j + c, c < 64, of which lane c read y and w coalesced into yc, wc):
+// lanes 16 j .. 16 j + 15 (act) replay their chunks, the node at column
+// c = 4 (l mod 16) + jj taking y and w from lane c by a shuffle, which every lane of the
+// wave executes; the other lanes run the same instructions on column 0 and change
+// nothing.  Outputs as with LOUT.
+template <int NX, bool BACK>
+__device__ __forceinline__ void chunk_replay_wave(double* __restrict__ jcol, bool act, const double (&yc)[NX],
+                                                  double wc, int64_t Nn, int64_t k0, double (&s)[NX]) {
+  const int l = (int)(threadIdx.x & 63);
+#pragma unroll 1
+  for (int j = 0; j < kTC; ++j) {
+    const int src = 4 * (l & 15) + j;
+    double yv[NX];
+#pragma unroll
+    for (int r = 0; r < NX; ++r) yv[r] = __shfl(yc[r], src, 64);
+    const double wk = __shfl(wc, src, 64);
+    const bool live = act && k0 + j < Nn;
+    double* Jp = jcol + j;
+    double u[NX], ju[NX], K[NX][NX], rp[NX];
+    if constexpr (BACK) {
+      node_lu<NX, true>(Jp, int64_t(64), wk, K, rp, nullptr, s, ju);
+#pragma unroll
+      for (int r = 0; r < NX; ++r) u[r] = yv[r] + wk * ju[r];
+      lu_solve<NX>(K, rp, u);
+      if (live) {
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+          s[r] += u[r];
+          Jp[r * 64] = u[r];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < NX; ++r) u[r] = s[r] + yv[r];
+      node_lu<NX, false>(Jp, int64_t(64), wk, K, rp, nullptr, u, ju);
+      lu_solve<NX>(K, rp, u);
+      lu_solve<NX>(K, rp, ju);
+      if (live) {
+#pragma unroll
+        for (int r = 0; r < NX; ++r) {
+          s[r] += wk * ju[r];
+          Jp[r * 64] = u[r];
+          Jp[(NX + r) * 64] = ju[r];
+        }
+      }
+    }
+  }
+}
+
 // The map of one chunk: node k takes S -> (I + H_k) S + H_k y_k, so from A = I, b = 0 the
 // first node gives (I + H, H y) and each further node A <- A + H A, b <- b + H (b + y).
 // hs points at the thread's slot of field 0, node 0 of its tile.
@@ -1413,13 +1463,40 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const double* __re
     // the round's outputs come back through the LDS columns (xi in entries 0..NX-1, J xi in
     // NX..2NX-1) and are stored coalesced, lane l taking node kw + 64 j + l; each lane then
     // writes only its own column in the next put_j, so no barrier is needed between
+    // (n_x >= 2) y and w are read coalesced with the staged J, one round ahead, and handed
+    // to the replaying lanes by shuffles (chunk_replay_wave)
     constexpr bool kLout = 2 * NX <= NX * NX;
+    double ypre[NX], wpre = 0.0;
+    if constexpr (kLout) {
+      const int64_t pos = kw + l;
+      const int64_t k = BACK ? Nn - 1 - pos : pos;
+#pragma unroll
+      for (int r = 0; r < NX; ++r) ypre[r] = pos < Nn ? (double)yi[(int64_t)r * Nn + k] : 0.0;
+      wpre = pos < Nn ? d.w[k] : 0.0;
+    }
     for (int j = 0; j < kTC; ++j) {
       put_j<NX>(jw, pre, l);
+      double ycur[NX];
+#pragma unroll
+      for (int r = 0; r < NX; ++r) ycur[r] = kLout ? ypre[r] : 0.0;
+      const double wcur = wpre;
       __syncthreads();
-      if (j + 1 < kTC) fetch_j<NX, BACK>(pre, J + d.joff, Nn, kw + 64 * (j + 1) + l);
-      if ((l >> 4) == j)
-        chunk_replay<NX, BACK, kLout>(jw + (4 * l - 64 * j), int64_t(1), int64_t(64), d.w, yi, oi, ji, Nn, k0, s);
+      if (j + 1 < kTC) {
+        fetch_j<NX, BACK>(pre, J + d.joff, Nn, kw + 64 * (j + 1) + l);
+        if constexpr (kLout) {
+          const int64_t pos = kw + 64 * (j + 1) + l;
+          const int64_t k = BACK ? Nn - 1 - pos : pos;
+#pragma unroll
+          for (int r = 0; r < NX; ++r) ypre[r] = pos < Nn ? (double)yi[(int64_t)r * Nn + k] : 0.0;
+          wpre = pos < Nn ? d.w[k] : 0.0;
+        }
+      }
+      const bool act = (l >> 4) == j;
+      if constexpr (kLout) {
+        chunk_replay_wave<NX, BACK>(jw + (act ? 4 * l - 64 * j : 0), act, ycur, wcur, Nn, k0, s);
+      } else if (act) {
+        chunk_replay<NX, BACK>(jw + (4 * l - 64 * j), int64_t(1), int64_t(64), d.w, yi, oi, ji, Nn, k0, s);
+      }
       __syncthreads();
       if constexpr (kLout) {
         const int64_t pos = kw + 64 * j + l;
