@@ -1429,6 +1429,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const double* __re
   constexpr int F = NX * NX + NX;
   constexpr int NW = kTileThreads / 64;
   __shared__ double jl[MODE == kFlyPerNode ? NW * 64 * NX * NX : 1];
+  // cached H, forward: the tile's y (component-major, node i of the tile at io[r][i]) and
+  // then its xi, so that both move coalesced
+  __shared__ T io[(MODE == kCachedH && !BACK) ? NX * kTileNodes : 1];
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
   const int64_t g = t.y;
@@ -1521,6 +1524,17 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const double* __re
     }
     constexpr int E = NX * NX + 1;
     const T* hs = jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x;
+    const int64_t tb = g * kTileNodes;  // first node of the tile
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+#pragma unroll
+      for (int q = 0; q < kTC; ++q) {
+        const int i = (int)threadIdx.x + q * kTileThreads;
+        io[r * kTileNodes + i] = (tb + i < Nn) ? yi[(int64_t)r * Nn + tb + i] : T(0);
+      }
+    }
+    __syncthreads();
+    const int i0 = (int)threadIdx.x * kTC;
 #pragma unroll 1
     for (int j = 0; j < kTC; ++j) {
       const int64_t k = k0 + j;
@@ -1529,15 +1543,24 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const double* __re
       const double inv_w = 1.0 / (double)base[(E - 1) * kTileThreads];
       double u[NX];
 #pragma unroll
-      for (int r = 0; r < NX; ++r) u[r] = s[r] + (double)yi[(int64_t)r * Nn + k];
+      for (int r = 0; r < NX; ++r) u[r] = s[r] + (double)io[r * kTileNodes + i0 + j];
 #pragma unroll
       for (int r = 0; r < NX; ++r) {
         double v = 0.0;
 #pragma unroll
         for (int q = 0; q < NX; ++q) v += (double)base[(r * NX + q) * kTileThreads] * u[q];
         s[r] += v;
-        oi[(int64_t)r * Nn + k] = (T)(u[r] + 0.5 * v);
+        io[r * kTileNodes + i0 + j] = (T)(u[r] + 0.5 * v);
         if (ji) ji[(int64_t)r * Nn + k] = (T)(v * inv_w);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NX; ++r) {
+#pragma unroll
+      for (int q = 0; q < kTC; ++q) {
+        const int i = (int)threadIdx.x + q * kTileThreads;
+        if (tb + i < Nn) oi[(int64_t)r * Nn + tb + i] = io[r * kTileNodes + i];
       }
     }
   }
