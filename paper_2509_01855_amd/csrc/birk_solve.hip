@@ -1070,9 +1070,11 @@ __device__ __forceinline__ void chunk_replay_wave(double* __restrict__ jcol, boo
 // The map of one chunk: node k takes S -> (I + H_k) S + H_k y_k, so from A = I, b = 0 the
 // first node gives (I + H, H y) and each further node A <- A + H A, b <- b + H (b + y).
 // hs points at the thread's slot of field 0, node 0 of its tile.
+// y of node j of the chunk, component r, at yb[r ystride + j] (global: yb = y + k0,
+// ystride = N_n; staged in LDS: the tile's y component-major).
 template <int NX, typename T>
-__device__ __forceinline__ void chunk_map_h(const T* __restrict__ hs, const T* __restrict__ yi, int64_t Nn, int64_t k0,
-                                          Aff<NX>& m) {
+__device__ __forceinline__ void chunk_map_h(const T* __restrict__ hs, const T* __restrict__ yb, int64_t ystride,
+                                          int64_t Nn, int64_t k0, Aff<NX>& m) {
   constexpr int E = NX * NX + 1;
 #pragma unroll 1
   for (int j = 0; j < kTC; ++j) {
@@ -1084,7 +1086,7 @@ __device__ __forceinline__ void chunk_map_h(const T* __restrict__ hs, const T* _
 #pragma unroll
       for (int q = 0; q < NX; ++q) H[r][q] = (double)base[(r * NX + q) * kTileThreads];
 #pragma unroll
-    for (int r = 0; r < NX; ++r) yv[r] = (k < Nn) ? (double)yi[(int64_t)r * Nn + k] : 0.0;
+    for (int r = 0; r < NX; ++r) yv[r] = (k < Nn) ? (double)yb[(int64_t)r * ystride + j] : 0.0;
     if (j == 0) {
 #pragma unroll
       for (int r = 0; r < NX; ++r) {
@@ -1294,6 +1296,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const double* 
   constexpr int NW = kTileThreads / 64;
   __shared__ double tot[NW][F];
   __shared__ double jl[MODE == kFlyPerNode ? NW * 64 * NX * NX : 1];
+  __shared__ T yl[(MODE == kCachedH && !BACK) ? NX * kTileNodes : 1];
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
   const int64_t g = t.y;
@@ -1321,8 +1324,21 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const double* 
     } else if constexpr (BACK) {
       chunk_map_ht<NX, T>(jsw + d.jsw_off, y + d.off, d.Nn, k0, m);
     } else {
+      // the tile's y staged coalesced through LDS (component-major)
       constexpr int E = NX * NX + 1;
-      chunk_map_h<NX, T>(jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x, y + d.off, d.Nn, k0, m);
+      const T* yi = y + d.off;
+      const int64_t tb = g * kTileNodes;
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+#pragma unroll
+        for (int q = 0; q < kTC; ++q) {
+          const int i = (int)threadIdx.x + q * kTileThreads;
+          yl[r * kTileNodes + i] = (tb + i < d.Nn) ? yi[(int64_t)r * d.Nn + tb + i] : T(0);
+        }
+      }
+      __syncthreads();
+      chunk_map_h<NX, T>(jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x, yl + (int)threadIdx.x * kTC,
+                         int64_t(kTileNodes), d.Nn, k0, m);
     }
     wave_scan<NX>(m);
     if (l == 63) aff_store<NX>(&tot[w][0], m);
