@@ -1136,8 +1136,10 @@ __device__ __forceinline__ const T* node_slot(const T* __restrict__ tab, int64_t
   return tab + (k / kTileNodes) * kTC * E * kTileThreads + (k % kTC) * E * kTileThreads + (k / kTC) % kTileThreads;
 }
 
+// yp: y of the chunk's positions, component r of position k0 + j at yp[r kTileNodes + j]
+// (the tile's y staged in LDS in position order).
 template <int NX, typename T>
-__device__ __forceinline__ void chunk_map_ht(const T* __restrict__ tab, const T* __restrict__ yi, int64_t Nn,
+__device__ __forceinline__ void chunk_map_ht(const T* __restrict__ tab, const T* __restrict__ yp, int64_t Nn,
                                              int64_t k0, Aff<NX>& m) {
   constexpr int E = NX * NX + 1;
 #pragma unroll 1
@@ -1153,7 +1155,7 @@ __device__ __forceinline__ void chunk_map_ht(const T* __restrict__ tab, const T*
       for (int q = 0; q < NX; ++q) G[r][q] = (double)base[(q * NX + r) * kTileThreads];
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
-      yv[r] = (double)yi[(int64_t)r * Nn + k];
+      yv[r] = (double)yp[r * kTileNodes + j];
       u[r] = m.b[r] + 0.5 * yv[r];
     }
 #pragma unroll
@@ -1179,9 +1181,10 @@ __device__ __forceinline__ void chunk_map_ht(const T* __restrict__ tab, const T*
   }
 }
 
+// yp as in chunk_map_ht; x_k replaces y_k there (the caller stores the tile).
 template <int NX, typename T>
-__device__ __forceinline__ void chunk_replay_ht(const T* __restrict__ tab, const T* __restrict__ yi,
-                                                T* __restrict__ oi, int64_t Nn, int64_t k0, double (&s)[NX]) {
+__device__ __forceinline__ void chunk_replay_ht(const T* __restrict__ tab, T* __restrict__ yp, int64_t Nn, int64_t k0,
+                                                double (&s)[NX]) {
   constexpr int E = NX * NX + 1;
 #pragma unroll 1
   for (int j = 0; j < kTC; ++j) {
@@ -1192,7 +1195,7 @@ __device__ __forceinline__ void chunk_replay_ht(const T* __restrict__ tab, const
     double yv[NX], u[NX], x[NX];
 #pragma unroll
     for (int r = 0; r < NX; ++r) {
-      yv[r] = (double)yi[(int64_t)r * Nn + k];
+      yv[r] = (double)yp[r * kTileNodes + j];
       u[r] = s[r] + 0.5 * yv[r];
     }
 #pragma unroll
@@ -1201,7 +1204,7 @@ __device__ __forceinline__ void chunk_replay_ht(const T* __restrict__ tab, const
 #pragma unroll
       for (int q = 0; q < NX; ++q) acc += (double)base[(q * NX + r) * kTileThreads] * u[q];
       x[r] = yv[r] + acc;
-      oi[(int64_t)r * Nn + k] = (T)x[r];
+      yp[r * kTileNodes + j] = (T)x[r];
     }
 #pragma unroll
     for (int r = 0; r < NX; ++r) s[r] += x[r];
@@ -1281,6 +1284,34 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tmake_h(JT* __restrict__ js
   }
 }
 
+// A tile's y in position order (node k = tb + i, or N_n - 1 - tb - i with BACK) into
+// buf[r kTileNodes + i], coalesced; zeros past the instance.  And the store of buf back
+// to out in the same order.
+template <int NX, bool BACK, typename T>
+__device__ __forceinline__ void stage_tile(T* __restrict__ buf, const T* __restrict__ yi, int64_t Nn, int64_t tb) {
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+#pragma unroll
+    for (int q = 0; q < kTC; ++q) {
+      const int i = (int)threadIdx.x + q * kTileThreads;
+      const int64_t pos = tb + i;
+      buf[r * kTileNodes + i] = pos < Nn ? yi[(int64_t)r * Nn + (BACK ? Nn - 1 - pos : pos)] : T(0);
+    }
+  }
+}
+template <int NX, bool BACK, typename T>
+__device__ __forceinline__ void store_tile(const T* __restrict__ buf, T* __restrict__ oi, int64_t Nn, int64_t tb) {
+#pragma unroll
+  for (int r = 0; r < NX; ++r) {
+#pragma unroll
+    for (int q = 0; q < kTC; ++q) {
+      const int i = (int)threadIdx.x + q * kTileThreads;
+      const int64_t pos = tb + i;
+      if (pos < Nn) oi[(int64_t)r * Nn + (BACK ? Nn - 1 - pos : pos)] = buf[r * kTileNodes + i];
+    }
+  }
+}
+
 // Tile maps: each chunk's map composed from its node maps, scanned across the wave by
 // DPP, then composed with the maps of the tile's earlier waves (a 4-lane scan of the wave
 // totals gives their prefixes), so chunk t holds the map of nodes 0 .. 4t + 3 of its tile.
@@ -1296,7 +1327,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const double* 
   constexpr int NW = kTileThreads / 64;
   __shared__ double tot[NW][F];
   __shared__ double jl[MODE == kFlyPerNode ? NW * 64 * NX * NX : 1];
-  __shared__ T yl[(MODE == kCachedH && !BACK) ? NX * kTileNodes : 1];
+  __shared__ T yl[MODE == kCachedH ? NX * kTileNodes : 1];
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
   const int64_t g = t.y;
@@ -1321,24 +1352,17 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const double* 
       }
     } else if constexpr (MODE == kFlyConst) {
       chunk_map<NX, BACK>(J + d.jcoff, int64_t(0), int64_t(1), d.w, y + d.off, d.Nn, k0, m, flag);
-    } else if constexpr (BACK) {
-      chunk_map_ht<NX, T>(jsw + d.jsw_off, y + d.off, d.Nn, k0, m);
     } else {
-      // the tile's y staged coalesced through LDS (component-major)
-      constexpr int E = NX * NX + 1;
-      const T* yi = y + d.off;
-      const int64_t tb = g * kTileNodes;
-#pragma unroll
-      for (int r = 0; r < NX; ++r) {
-#pragma unroll
-        for (int q = 0; q < kTC; ++q) {
-          const int i = (int)threadIdx.x + q * kTileThreads;
-          yl[r * kTileNodes + i] = (tb + i < d.Nn) ? yi[(int64_t)r * d.Nn + tb + i] : T(0);
-        }
-      }
+      // the tile's y staged coalesced through LDS (component-major, position order)
+      stage_tile<NX, BACK, T>(yl, y + d.off, d.Nn, g * kTileNodes);
       __syncthreads();
-      chunk_map_h<NX, T>(jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x, yl + (int)threadIdx.x * kTC,
-                         int64_t(kTileNodes), d.Nn, k0, m);
+      if constexpr (BACK) {
+        chunk_map_ht<NX, T>(jsw + d.jsw_off, yl + (int)threadIdx.x * kTC, d.Nn, k0, m);
+      } else {
+        constexpr int E = NX * NX + 1;
+        chunk_map_h<NX, T>(jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x, yl + (int)threadIdx.x * kTC,
+                           int64_t(kTileNodes), d.Nn, k0, m);
+      }
     }
     wave_scan<NX>(m);
     if (l == 63) aff_store<NX>(&tot[w][0], m);
@@ -1447,7 +1471,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const double* __re
   __shared__ double jl[MODE == kFlyPerNode ? NW * 64 * NX * NX : 1];
   // cached H, forward: the tile's y (component-major, node i of the tile at io[r][i]) and
   // then its xi, so that both move coalesced
-  __shared__ T io[(MODE == kCachedH && !BACK) ? NX * kTileNodes : 1];
+  __shared__ T io[MODE == kCachedH ? NX * kTileNodes : 1];
   const int2 t = tiles[blockIdx.x];
   const PinvDesc& d = pd[t.x];
   const int64_t g = t.y;
@@ -1534,22 +1558,17 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const double* __re
     chunk_replay<NX, BACK>(J + d.jcoff, int64_t(0), int64_t(1), d.w, yi, oi, ji, Nn, k0, s);
   } else {
     // H_k from precond_prepare: v = H_k u, xi_k = u + v / 2, (J xi)_k = v / w_k, S <- S + v
+    const int64_t tb = g * kTileNodes;  // first position of the tile
+    stage_tile<NX, BACK, T>(io, yi, Nn, tb);
+    __syncthreads();
     if constexpr (BACK) {
-      chunk_replay_ht<NX, T>(jsw + d.jsw_off, yi, oi, Nn, k0, s);
+      chunk_replay_ht<NX, T>(jsw + d.jsw_off, io + (int)threadIdx.x * kTC, Nn, k0, s);
+      __syncthreads();
+      store_tile<NX, true, T>(io, oi, Nn, tb);
       return;
     }
     constexpr int E = NX * NX + 1;
     const T* hs = jsw + d.jsw_off + g * kTC * E * kTileThreads + threadIdx.x;
-    const int64_t tb = g * kTileNodes;  // first node of the tile
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-#pragma unroll
-      for (int q = 0; q < kTC; ++q) {
-        const int i = (int)threadIdx.x + q * kTileThreads;
-        io[r * kTileNodes + i] = (tb + i < Nn) ? yi[(int64_t)r * Nn + tb + i] : T(0);
-      }
-    }
-    __syncthreads();
     const int i0 = (int)threadIdx.x * kTC;
 #pragma unroll 1
     for (int j = 0; j < kTC; ++j) {
@@ -1571,14 +1590,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const double* __re
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < NX; ++r) {
-#pragma unroll
-      for (int q = 0; q < kTC; ++q) {
-        const int i = (int)threadIdx.x + q * kTileThreads;
-        if (tb + i < Nn) oi[(int64_t)r * Nn + tb + i] = io[r * kTileNodes + i];
-      }
-    }
+    store_tile<NX, false, T>(io, oi, Nn, tb);
   }
 }
 
