@@ -1415,16 +1415,23 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const double* 
 }
 
 
-// Tile start states of one instance (S = 0 before node 0), one workgroup per instance:
-// thread t composes the aggregates of tiles [t q, t q + q), the maps are scanned across
-// the workgroup, and each thread then walks its tiles from its start state.
+// Tile start states of one instance (S = 0 before node 0), one workgroup of
+// tiles_threads<NX>() per instance: thread t composes the aggregates of tiles
+// [t q, t q + q), the maps are scanned across the workgroup, and each thread then walks
+// its tiles from its start state.  512 threads (fewer tiles per thread) where a thread's
+// map fits two waves per SIMD, 256 above n_x = 6.
 template <int NX>
-__global__ __launch_bounds__(256) void k_tscan_tiles(double* __restrict__ scan, const PinvDesc* __restrict__ pd) {
+constexpr int tiles_threads() { return NX <= 6 ? 512 : 256; }
+
+template <int NX>
+__global__ __launch_bounds__(tiles_threads<NX>()) void k_tscan_tiles(double* __restrict__ scan,
+                                                                     const PinvDesc* __restrict__ pd) {
   constexpr int F = NX * NX + NX;
-  __shared__ double tot[4][F];
+  constexpr int NT = tiles_threads<NX>();
+  __shared__ double tot[NT / 64][F];
   const PinvDesc& d = pd[blockIdx.x];
   const int64_t nt = d.ntile;
-  const int64_t q = (nt + 255) / 256;
+  const int64_t q = (nt + NT - 1) / NT;
   const int64_t i0 = (int64_t)threadIdx.x * q;
   const int64_t i1 = min(nt, i0 + q);
   const double* agg = scan + d.tagg;
@@ -1952,7 +1959,7 @@ static void pinv_class(birk_plan* p, const PinvClass& pc, const double* J, int p
       hipLaunchKernelGGL((k_tscan_reduce<NX, kFlyPerNode, false, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan,
                          p->flag);
     }
-    hipLaunchKernelGGL((k_tscan_tiles<NX>), dim3(pc.ninst), dim3(256), 0, s, scan, pc.dev);
+    hipLaunchKernelGGL((k_tscan_tiles<NX>), dim3(pc.ninst), dim3(tiles_threads<NX>()), 0, s, scan, pc.dev);
     if (!pn) {
       hipLaunchKernelGGL((k_tscan_apply<NX, kFlyConst, false, T>), grid, block, 0, s, J, jsw, y, pc.dev, pc.t_tile, scan, out,
                          jout);
@@ -2017,7 +2024,7 @@ static void pinv_t_class(birk_plan* p, const PinvClass& pc, const double* J, int
       hipLaunchKernelGGL((k_tscan_reduce<NX, kFlyConst, true, double>), grid, block, 0, s, J, jsw, y, pc.dev,
                          pc.t_tile, p->scan, p->flag);
     }
-    hipLaunchKernelGGL((k_tscan_tiles<NX>), dim3(pc.ninst), dim3(256), 0, s, p->scan, pc.dev);
+    hipLaunchKernelGGL((k_tscan_tiles<NX>), dim3(pc.ninst), dim3(tiles_threads<NX>()), 0, s, p->scan, pc.dev);
     if (pn && cached) {
       hipLaunchKernelGGL((k_tscan_apply<NX, kCachedH, true, double>), grid, block, 0, s, J, jsw, y, pc.dev,
                          pc.t_tile, p->scan, out, nullptr);
