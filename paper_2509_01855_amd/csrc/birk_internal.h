@@ -145,7 +145,7 @@ struct PinvDesc {
   int nb0 = 0;                          // level-0 blocks of 64 groups
   // wave-scan path (n_x <= kWaveNx): tiles of kTileNodes nodes
   int64_t ntile = 0;                    // tiles of the instance
-  int64_t tagg = 0, tst = 0;            // tile aggregates and tile start states (doubles)
+  int64_t tagg = 0, tst = 0;            // tile aggregates and start states, [field][tile] (doubles)
   int64_t tmap = 0;                     // inclusive chunk maps, [tile][field][thread] (doubles)
 };
 

@@ -1316,7 +1316,8 @@ __device__ __forceinline__ void store_tile(const T* __restrict__ buf, T* __restr
 // DPP, then composed with the maps of the tile's earlier waves (a 4-lane scan of the wave
 // totals gives their prefixes), so chunk t holds the map of nodes 0 .. 4t + 3 of its tile.
 // These inclusive maps are stored as [g][field][t] (scan[tmap + g F 256 + f 256 + t]) and
-// the last one is the tile aggregate (scan[tagg + g F]).  tile = (k, g).
+// the last one is the tile aggregate, stored field-major (scan[tagg + f ntile + g]) so
+// that the one-workgroup tile scan reads it coalesced.  tile = (k, g).
 template <int NX, int MODE, bool BACK, typename T>
 __global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const double* __restrict__ J, const T* __restrict__ jsw,
                                                              const T* __restrict__ y,
@@ -1409,7 +1410,7 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const double* 
     }
     if (threadIdx.x == kTileThreads - 1) {
 #pragma unroll
-      for (int f = 0; f < F; ++f) scan[d.tagg + g * F + f] = last[f];
+      for (int f = 0; f < F; ++f) scan[d.tagg + f * d.ntile + g] = last[f];
     }
   }
 }
@@ -1418,8 +1419,11 @@ __global__ __launch_bounds__(kTileThreads, 2) void k_tscan_reduce(const double* 
 // Tile start states of one instance (S = 0 before node 0), one workgroup of
 // tiles_threads<NX>() per instance: thread t composes the aggregates of tiles
 // [t q, t q + q), the maps are scanned across the workgroup, and each thread then walks
-// its tiles from its start state.  512 threads (fewer tiles per thread) where a thread's
-// map fits two waves per SIMD, 256 above n_x = 6.
+// its tiles from its start state.  Aggregates and start states are field-major
+// ([field][tile]), so a wave's loads and stores touch a few cache lines rather than one
+// per lane: the whole scan runs on one CU, whose request rate bounds it.  512 threads
+// (fewer tiles per thread) where a thread's map fits two waves per SIMD, 256 above
+// n_x = 6.
 template <int NX>
 constexpr int tiles_threads() { return NX <= 6 ? 512 : 256; }
 
@@ -1437,7 +1441,7 @@ __global__ __launch_bounds__(tiles_threads<NX>()) void k_tscan_tiles(double* __r
   const double* agg = scan + d.tagg;
   Aff<NX> m;
   aff_identity<NX>(m);
-  for (int64_t i = i0; i < i1; ++i) compose<NX>(agg + i * F, 1, m.A, m.b);
+  for (int64_t i = i0; i < i1; ++i) compose<NX>(agg + i, nt, m.A, m.b);
   wave_scan<NX>(m);
   const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
   if (l == 63) aff_store<NX>(&tot[w][0], m);
@@ -1458,8 +1462,8 @@ __global__ __launch_bounds__(tiles_threads<NX>()) void k_tscan_tiles(double* __r
   double* st = scan + d.tst;
   for (int64_t i = i0; i < i1; ++i) {
 #pragma unroll
-    for (int r = 0; r < NX; ++r) st[i * NX + r] = s[r];
-    advance<NX>(agg + i * F, 1, s);
+    for (int r = 0; r < NX; ++r) st[r * nt + i] = s[r];
+    advance<NX>(agg + i, nt, s);
   }
 }
 
@@ -1486,7 +1490,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tscan_apply(const double* __re
   const int64_t k0 = (g * kTileThreads + threadIdx.x) * kTC;
   double s[NX];
 #pragma unroll
-  for (int r = 0; r < NX; ++r) s[r] = scan[d.tst + g * NX + r];
+  for (int r = 0; r < NX; ++r) s[r] = scan[d.tst + r * d.ntile + g];
   if (threadIdx.x > 0 && k0 < Nn) {
     const double* cm = scan + d.tmap + g * F * kTileThreads + (threadIdx.x - 1);
     double ns[NX];
