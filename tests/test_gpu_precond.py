@@ -127,6 +127,34 @@ def test_precond_inverse_per_node_large_nx(B, Nn, nx):
     assert rel_err(got, sy.precond_inverse(w, J, y)) <= 1e-12
 
 
+@pytest.mark.parametrize("nx,jkind", [(7, "per_node"), (8, "per_node"), (8, "constant"), (5, "constant")])
+def test_precond_inverse_many_tiles(B, nx, jkind):
+    """P^{-1} on the wave-scan path with 293 tiles of 1024 nodes, so that the tile scan
+    gives most of its threads two tiles and one thread a single tile (256 threads above
+    n_x = 6, 512 at n_x = 5, where some threads hold none), against the oracle's forward
+    substitution."""
+    import torch
+    Nn = 300001
+    announce(f"precond inverse many tiles Nn={Nn} nx={nx} J={jkind}")
+    rng = np.random.default_rng([nx, 293])
+    if jkind == "per_node":
+        J = rng.standard_normal((nx, nx, Nn)) / np.sqrt(nx) - 2.0 * np.eye(nx)[:, :, None]
+        jk = B.BIRK_J_PER_NODE
+    else:
+        J = wl.lti_matrix(rng, nx)
+        jk = B.BIRK_J_CONSTANT
+    w = bk.weights(Nn - 1)
+    y = rng.standard_normal(nx * Nn)
+    plan = B.birk_plan_create([Nn], [nx], B.BIRK_F64)
+    yd = dev(y, torch.float64)
+    out = torch.empty_like(yd)
+    B.birk_precond(plan, dev(J.ravel(), torch.float64), yd, out, 1, jk)
+    torch.cuda.synchronize()
+    got = host(out)
+    plan.destroy()
+    assert rel_err(got, sy.precond_inverse(w, J, y)) <= 1e-12
+
+
 def test_precond_f32_storage(B):
     import torch
     Nn = 1025
