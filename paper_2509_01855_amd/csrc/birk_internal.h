@@ -241,6 +241,7 @@ struct birk_plan {
   int2* pfwd_btiles = nullptr;      // P y, all components at once: (instance, tile)
   int pfwd_nbtiles = 0;
   int pfwd_maxnx = 0;               // largest n_x of the plan
+  int pfwd_unx = 0;                 // the n_x every instance shares, else 0
   void* newton_buf = nullptr;       // Newton workspace, allocated by the first Newton solve
   std::vector<birk::BtClass> btclass;  // P^{-T} scan schedule, one class per n_x
   int64_t total_bt = 0;             // doubles of P^{-T} scan scratch

@@ -205,8 +205,10 @@ __global__ __launch_bounds__(256) void k_pfwd_final(const int2* __restrict__ til
 // Double plans with n_x <= 16: one workgroup per tile forms u_k = w_k J_k y_k for all
 // components (J and y read once), stores u in out (which does not overlap y) and sums it
 // per component; the final pass of component r then reads u_r back instead of J and all
-// of y.  Tile = (instance, tile); the sums go where k_pfwd_sums puts them.
-template <int MAXNX>
+// of y.  Tile = (instance, tile); the sums go where k_pfwd_sums puts them.  NXC > 0: every
+// instance has n_x = NXC, so the loops unroll completely and a node's J and y loads issue
+// together.
+template <int MAXNX, int NXC = 0>
 __global__ __launch_bounds__(256) void k_pfwd_sums_all(const int2* __restrict__ tiles,
                                                        const InstDesc* __restrict__ idesc,
                                                        const double* __restrict__ J, int per_node,
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(256) void k_pfwd_sums_all(const int2* __restrict__ 
   __shared__ double sh[4][MAXNX];
   const int2 t = tiles[blockIdx.x];
   const InstDesc d = idesc[t.x];
-  const int nt = pfwd_ntiles(d.Nn), b = t.y, nx = (int)d.nx;
+  const int nt = pfwd_ntiles(d.Nn), b = t.y, nx = NXC > 0 ? NXC : (int)d.nx;
   const int64_t Nn = d.Nn;
   const double* Ji = J + (per_node ? d.joff : d.jcoff);
   const double* yi = y + d.off;
@@ -312,7 +314,20 @@ hipError_t precond_forward(birk_plan* p, int jac_kind, const double* J, const T*
   const int pn = jac_kind == BIRK_J_PER_NODE ? 1 : 0;
   if constexpr (std::is_same<T, double>::value) {
     if (p->pfwd_maxnx <= 16) {
-      auto f = p->pfwd_maxnx <= 4 ? k_pfwd_sums_all<4> : p->pfwd_maxnx <= 8 ? k_pfwd_sums_all<8> : k_pfwd_sums_all<16>;
+      static constexpr decltype(&k_pfwd_sums_all<8>) kUniform[9] = {
+          nullptr,
+          k_pfwd_sums_all<1, 1>,
+          k_pfwd_sums_all<2, 2>,
+          k_pfwd_sums_all<3, 3>,
+          k_pfwd_sums_all<4, 4>,
+          k_pfwd_sums_all<5, 5>,
+          k_pfwd_sums_all<6, 6>,
+          k_pfwd_sums_all<7, 7>,
+          k_pfwd_sums_all<8, 8>};
+      auto f = (p->pfwd_unx >= 1 && p->pfwd_unx <= 8) ? kUniform[p->pfwd_unx]
+               : p->pfwd_maxnx <= 4                   ? k_pfwd_sums_all<4>
+               : p->pfwd_maxnx <= 8                   ? k_pfwd_sums_all<8>
+                                                      : k_pfwd_sums_all<16>;
       hipLaunchKernelGGL(f, dim3(p->pfwd_nbtiles), dim3(256), 0, s, p->pfwd_btiles, p->idesc, J, pn, y, out, p->scan);
       hipLaunchKernelGGL(k_pfwd_scanparts, dim3(p->pfwd_npairs), dim3(256), 0, s, p->pfwd_pairs, p->idesc, p->scan);
       hipLaunchKernelGGL(k_pfwd_final_u, dim3(p->pfwd_ntiles), dim3(256), 0, s, p->pfwd_tiles, p->idesc, y,
@@ -1784,11 +1799,13 @@ hipError_t plan_solve(birk_plan* p) {
     p->pfwd_npairs = (int)pr.size();
     std::vector<int2> bt;
     p->pfwd_maxnx = 0;
+    p->pfwd_unx = p->inst.empty() ? 0 : (int)p->inst[0].nx;
     for (int i = 0; i < (int)p->inst.size(); ++i) {
       const Instance& in = p->inst[i];
       const int nt = (int)((in.Nn + kScanBlock - 1) / kScanBlock);
       for (int b = 0; b < nt; ++b) bt.push_back(make_int2(i, b));
       p->pfwd_maxnx = std::max(p->pfwd_maxnx, (int)in.nx);
+      if ((int)in.nx != p->pfwd_unx) p->pfwd_unx = 0;
     }
     if ((e = upload_tiles(p, bt, &p->pfwd_btiles)) != hipSuccess) return e;
     p->pfwd_nbtiles = (int)bt.size();
