@@ -36,10 +36,11 @@ def _J_dev(inst):
 
 
 # n_x <= 8 runs the wave-scan path (tiles of 1024 nodes: 1024 and 1025 sit on a tile
-# edge), larger n_x the hierarchical scan (20000 nodes at n_x = 9 takes two levels).
+# edge), larger n_x the hierarchical scan (20000 nodes at n_x = 9 takes two levels); P y
+# of every n_x from 1 to 8 runs its own compiled n_x.
 CASES = [("lti", 3, 1), ("lti", 17, 4), ("lti", 256, 6), ("lti", 257, 12), ("kepler", 257, 6),
          ("lti", 1000, 5), ("lti", 1024, 6), ("lti", 1025, 8), ("lti", 3000, 7), ("kepler", 4097, 6),
-         ("lti", 20000, 2), ("lti", 20000, 9), ("kepler", 70001, 6)]
+         ("lti", 5000, 3), ("lti", 20000, 2), ("lti", 20000, 9), ("kepler", 70001, 6)]
 
 
 @pytest.mark.parametrize("kind,Nn,nx", CASES)
